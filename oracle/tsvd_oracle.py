@@ -1,0 +1,572 @@
+"""FP64 CPU oracle for the randomized block Krylov truncated T-SVD.
+
+Paper: M. Nobakht Kooshkghazi, S. Ahmadi-Asl, A. L. F. de Almeida,
+"Randomized block Krylov method for approximation of truncated tensor SVD"
+(arXiv:2504.04989).
+
+TEST INFRASTRUCTURE ONLY.  This module is imported by ``tests/``, by
+``__graft_entry__.smoke()`` and by the ``cpu_baseline`` leg of ``bench.py``;
+nothing in the library package imports, links or executes it, and it shares
+no code with the HIP path.  It is deliberately plain: numpy in float64 /
+complex128, explicit loops where the paper's definitions are loops, numpy's
+matmul / norm as the only library primitives, no blocking and no reordering.
+
+Every function names the passage of the paper it writes out.  The readings
+taken where the paper is silent, ambiguous or garbled are listed at the end of
+this docstring; each one is also recorded in the repository's design notes.
+
+Pins (tests/test_oracle_*.py, all ``-m "not gpu"``):
+  dft_mode3 / idft_mode3   impulse and pure-exponential closed forms, numpy.fft,
+                           Parseval (eq. (eq_fou)), round trip, real DC/Nyquist
+  tprod                    brute force fold(bcirc(X) unfold(Y)) (Def. T-product)
+  ttranspose               (X*Y)^T = Y^T*X^T and bcirc(X^T) = bcirc(X)^T
+  householder_qr           Q^H Q = I, QR = K, triangular R, numpy.linalg.qr
+  jacobi_svd               numpy.linalg.svd singular values, W S Z^H = C
+  rbk_tsvd                 m = n1 gives the exact truncated T-SVD; exact recovery
+                           of a tubal-rank-r tensor (r <= k); n3 = 1 is the matrix
+                           block Krylov method; Eckart-Young; Lemma mn38;
+                           the Frobenius theorem of Sec. 4; monotone in q;
+                           literal == stabilised Krylov form
+  proj / proj_backward     central finite differences, torch CPU autograd,
+                           Euler homogeneity
+
+Readings (where the paper is silent / ambiguous):
+  R1  Omega has n2 rows (Alg. 2 draws randn(n1, ...) but X*Omega needs n2 rows,
+      as in Alg. 1).
+  R2  Omega is a real Gaussian tensor in the spatial domain, transformed like X.
+  R3  Parameters are (k, b, q) with b = R + P (rank plus oversampling), k <= b.
+  R4  DFT: omega = exp(-2 pi i / n), forward unnormalised, inverse carries 1/n3
+      (Sec. 2, Def. of F_n).  Eq. (mn35) omits the 1/n3 of F^{-1}.  The half
+      spectrum has n3//2 + 1 slices (= ceil((n3+1)/2)); the mirror index
+      n3 - i + 2 (1-based) is (n3 - f) mod n3 (0-based).
+  R5  "^T" in the Fourier domain is the per-slice conjugate transpose.
+  R6  Krylov recursion: the parity reference is the stabilised form
+      (orthonormalise each block and re-orthogonalise it against the earlier
+      blocks before the next multiplication), which spans the same space as the
+      literal powers of Alg. 2 in exact arithmetic; the literal form is kept as
+      a cross-check (krylov="lit").
+  R7  Economy T-QR, m = b (q + 1) <= min(n1, n2).
+  R8  Only the top k singular triplets of each Fourier slice of C are kept.
+  R9  Singular vectors carry an arbitrary phase; for comparison each column of
+      U_f and V_f is multiplied by the conjugate phase of the largest-modulus
+      entry of the U_f column (first such entry on ties).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EPS64 = 2.0 ** -53
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2: DFT along mode 3, block diagonalisation, half spectrum
+# ---------------------------------------------------------------------------
+
+def twiddles(n: int) -> np.ndarray:
+    """w[r] = omega^r, omega = exp(-2 pi i / n)  (Sec. 2, Def. of the DFT
+    matrix F_n).  The four quarter points are set to their exact values so the
+    DC and Nyquist rows of F_n are exactly real."""
+    r = np.arange(n, dtype=np.float64)
+    w = np.cos(2.0 * np.pi * r / n) - 1j * np.sin(2.0 * np.pi * r / n)
+    w[0] = 1.0
+    if n % 2 == 0:
+        w[n // 2] = -1.0
+    if n % 4 == 0:
+        w[n // 4] = -1j
+        w[3 * n // 4] = 1j
+    return w
+
+
+def dft_matrix(n: int) -> np.ndarray:
+    """F_n with entries omega^(f t)  (Sec. 2, Def. of F_n)."""
+    t = np.arange(n)
+    return twiddles(n)[np.outer(t, t) % n]
+
+
+def dft_mode3(X: np.ndarray, freqs=None) -> np.ndarray:
+    """X_bar = fft(X, [], 3): the unnormalised DFT of every tube (Sec. 2),
+    taken along the last axis.
+
+    X_bar[i, j, f] = sum_t X[i, j, t] omega^(f t).  ``freqs`` restricts the
+    output to the listed frequencies (same values, fewer of them)."""
+    n3 = X.shape[-1]
+    Fm = dft_matrix(n3)
+    if freqs is not None:
+        Fm = Fm[list(freqs), :]
+    return np.tensordot(np.asarray(X), Fm, axes=([-1], [1]))
+
+
+def idft_mode3(Xbar: np.ndarray) -> np.ndarray:
+    """X = ifft(X_bar, [], 3) with F_n^{-1} = F_n^* / n  (Sec. 2)."""
+    n3 = Xbar.shape[-1]
+    Finv = np.conj(dft_matrix(n3)) / n3
+    return np.tensordot(Xbar, Finv, axes=([-1], [1]))
+
+
+def n_half(n3: int) -> int:
+    """Number of Fourier slices computed, ceil((n3+1)/2) = n3//2 + 1
+    (Alg. TP, first loop)."""
+    return n3 // 2 + 1
+
+
+def mirror(Xh: np.ndarray, n3: int) -> np.ndarray:
+    """Complete a half spectrum by conjugate symmetry: slice n3 - f is
+    conj(slice f)  (Alg. TP, second loop; 0-based index (n3 - f) mod n3)."""
+    F = n_half(n3)
+    full = np.zeros(Xh.shape[:-1] + (n3,), dtype=np.complex128)
+    full[..., :F] = Xh
+    for f in range(F, n3):
+        full[..., f] = np.conj(Xh[..., n3 - f])
+    return full
+
+
+def real_part_checked(X: np.ndarray, rtol: float = 1e-12) -> np.ndarray:
+    """Real part of an inverse transform that must be real; raises if the
+    imaginary part is not at rounding level."""
+    X = np.asarray(X)
+    scale = max(float(np.max(np.abs(X.real))) if X.size else 0.0, 1e-300)
+    im = float(np.max(np.abs(X.imag))) if X.size else 0.0
+    if im > rtol * scale + 1e-300:
+        raise ValueError(f"inverse DFT not real: max|Im| = {im:.3e}, max|Re| = {scale:.3e}")
+    return np.ascontiguousarray(X.real)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2: bcirc / unfold / fold, T-product, T-transpose, identity, norms
+# ---------------------------------------------------------------------------
+
+def bcirc(X: np.ndarray) -> np.ndarray:
+    """Block circulant matrix of X (Sec. 2): block (r, c) = X^{((r - c) mod n3)}."""
+    n1, n2, n3 = X.shape
+    B = np.zeros((n1 * n3, n2 * n3), dtype=X.dtype)
+    for r in range(n3):
+        for c in range(n3):
+            B[r * n1:(r + 1) * n1, c * n2:(c + 1) * n2] = X[:, :, (r - c) % n3]
+    return B
+
+
+def unfold(X: np.ndarray) -> np.ndarray:
+    """Stack the frontal slices vertically (Sec. 2, Def. of unfold)."""
+    n1, n2, n3 = X.shape
+    return np.concatenate([X[:, :, t] for t in range(n3)], axis=0)
+
+
+def fold(M: np.ndarray, n1: int, n3: int) -> np.ndarray:
+    """Inverse of ``unfold``."""
+    return np.stack([M[t * n1:(t + 1) * n1, :] for t in range(n3)], axis=2)
+
+
+def tprod_bcirc(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """T-product by its definition: fold(bcirc(X) . unfold(Y))  (Def. T-product)."""
+    return fold(bcirc(X) @ unfold(Y), X.shape[0], X.shape[2])
+
+
+def tprod(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """T-product in the Fourier domain (Alg. TP): transform both operands,
+    multiply the first n3//2+1 frontal slices, mirror, inverse transform."""
+    n3 = X.shape[2]
+    F = n_half(n3)
+    Xb, Yb = dft_mode3(X), dft_mode3(Y)
+    Ch = np.empty((X.shape[0], Y.shape[1], F), dtype=np.complex128)
+    for f in range(F):
+        Ch[:, :, f] = Xb[:, :, f] @ Yb[:, :, f]
+    return real_part_checked(idft_mode3(mirror(Ch, n3)))
+
+
+def ttranspose(X: np.ndarray) -> np.ndarray:
+    """Tensor transpose (Sec. 2): transpose every frontal slice and reverse the
+    order of slices 2..n3."""
+    n1, n2, n3 = X.shape
+    T = np.empty((n2, n1, n3), dtype=X.dtype)
+    T[:, :, 0] = X[:, :, 0].T
+    for t in range(1, n3):
+        T[:, :, t] = X[:, :, n3 - t].T
+    return T
+
+
+def identity_tensor(n: int, n3: int) -> np.ndarray:
+    """Identity tensor: first frontal slice I_n, the others zero (Sec. 2)."""
+    Id = np.zeros((n, n, n3))
+    Id[:, :, 0] = np.eye(n)
+    return Id
+
+
+def fro(X: np.ndarray) -> float:
+    """Frobenius norm (Def. mn3)."""
+    return float(np.sqrt(np.sum(np.abs(X) ** 2)))
+
+
+def relative_error(X: np.ndarray, Xt: np.ndarray) -> float:
+    """e(X~) = ||X - X~||_F / ||X||_F  (Sec. 5, relative error)."""
+    return fro(X - Xt) / fro(X)
+
+
+def psnr(X: np.ndarray, Y: np.ndarray, peak: float = 255.0) -> float:
+    """PSNR = 10 log10(peak^2 / MSE), MSE = ||X - Y||_F^2 / num(X)  (Sec. 5)."""
+    mse = fro(X - Y) ** 2 / X.size
+    return float(10.0 * np.log10(peak ** 2 / mse))
+
+
+# ---------------------------------------------------------------------------
+# Per-slice dense linear algebra: Householder QR, one-sided Jacobi SVD
+# ---------------------------------------------------------------------------
+
+def householder_qr(K: np.ndarray):
+    """Economy QR, K = Q R with Q n x m orthonormal and R m x m upper
+    triangular: the per-slice ``qr(X, 0)`` of Alg. TQR.
+
+    Column j: x = R[j:, j]; beta = -exp(i arg x0) ||x||; v = x - beta e1 scaled
+    so that v0 = 1; tau = (beta - x0) / beta (real); H_j = I - tau v v^H maps x
+    to beta e1.  A zero column gives tau = 0 (H_j = I).  Q = H_0 ... H_{m-1}
+    applied to the first m columns of the identity."""
+    R = np.array(K, dtype=np.complex128)
+    n, m = R.shape
+    if m > n:
+        raise ValueError("economy QR needs m <= n")
+    vs, taus = [], []
+    for j in range(m):
+        x = R[j:, j].copy()
+        nx = np.linalg.norm(x)
+        if nx == 0.0:
+            vs.append(np.zeros(n - j, dtype=np.complex128))
+            taus.append(0.0)
+            continue
+        x0 = x[0]
+        phase = x0 / abs(x0) if x0 != 0 else 1.0
+        beta = -phase * nx
+        v = x.copy()
+        v[0] = x0 - beta
+        v = v / v[0]
+        tau = ((beta - x0) / beta).real
+        R[j:, j:] -= tau * np.outer(v, v.conj() @ R[j:, j:])
+        R[j, j] = beta
+        R[j + 1:, j] = 0.0
+        vs.append(v)
+        taus.append(tau)
+    Q = np.zeros((n, m), dtype=np.complex128)
+    Q[:m, :m] = np.eye(m)
+    for j in reversed(range(m)):
+        v, tau = vs[j], taus[j]
+        if tau != 0.0:
+            Q[j:, :] -= tau * np.outer(v, v.conj() @ Q[j:, :])
+    return Q, np.triu(R[:m, :m])
+
+
+def jacobi_svd(C: np.ndarray, max_sweeps: int = 60, tol: float | None = None):
+    """Thin SVD C = W diag(s) Z^H of an m x n matrix with m <= n, the per-slice
+    T-SVD of Alg. 2 (Sec. 2: T-SVD by per-slice SVD in the Fourier domain).
+
+    Steps: Householder QR C^H = Qc R (R m x m); one-sided (Hestenes) Jacobi on
+    the columns of R with cyclic row ordering: for each pair (p, q),
+    alpha = ||r_p||^2, beta = ||r_q||^2, gamma = r_p^H r_q = |gamma| e^{i phi};
+    skip if |gamma| <= tol sqrt(alpha beta), otherwise apply the unitary
+    J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] (zeta = (beta - alpha) / (2|gamma|),
+    t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2), s = c t) that
+    makes the two columns orthogonal, to R and to the accumulator (initially I).
+    Stop after a sweep without rotations.  Then s_j = ||r_j||,
+    Zhat = R J diag(1/s), W = J, Z = Qc Zhat, sorted by decreasing s (ties keep
+    the lower original index).  Returns (W, s, Z, sweeps)."""
+    C = np.asarray(C, dtype=np.complex128)
+    m, n = C.shape
+    if m > n:
+        raise ValueError("jacobi_svd expects a wide matrix (m <= n)")
+    if tol is None:
+        tol = m * EPS64
+    Qc, R = householder_qr(C.conj().T)
+    Y = R.copy()
+    J = np.eye(m, dtype=np.complex128)
+    sweeps = 0
+    converged = False
+    for sweep in range(max_sweeps):
+        sweeps = sweep + 1
+        rotated = False
+        for p in range(m - 1):
+            for q in range(p + 1, m):
+                yp, yq = Y[:, p], Y[:, q]
+                alpha = float(np.real(np.vdot(yp, yp)))
+                beta = float(np.real(np.vdot(yq, yq)))
+                gamma = np.vdot(yp, yq)
+                ag = abs(gamma)
+                if ag == 0.0 or ag <= tol * np.sqrt(alpha * beta):
+                    continue
+                rotated = True
+                eph = np.conj(gamma / ag)          # e^{-i phi}
+                zeta = (beta - alpha) / (2.0 * ag)
+                t = (1.0 if zeta >= 0 else -1.0) / (abs(zeta) + np.sqrt(1.0 + zeta * zeta))
+                c = 1.0 / np.sqrt(1.0 + t * t)
+                s = c * t
+                for M in (Y, J):
+                    mp, mq = M[:, p].copy(), M[:, q].copy()
+                    M[:, p] = c * mp - s * eph * mq
+                    M[:, q] = s * mp + c * eph * mq
+        if not rotated:
+            converged = True
+            break
+    if not converged:
+        raise RuntimeError(f"jacobi_svd: no convergence in {max_sweeps} sweeps")
+    s = np.sqrt(np.real(np.sum(Y.conj() * Y, axis=0)))
+    Zhat = np.zeros_like(Y)
+    nz = s > 0
+    Zhat[:, nz] = Y[:, nz] / s[nz]
+    order = np.argsort(-s, kind="stable")
+    W = J[:, order]
+    s = s[order]
+    Z = Qc @ Zhat[:, order]
+    return W, s, Z, sweeps
+
+
+def canonical_phase(Uf: np.ndarray, Vf: np.ndarray):
+    """Reading R9: scale column j of Uf and Vf by the conjugate phase of Uf's
+    largest-modulus entry in column j (first index on ties)."""
+    Uf = Uf.copy()
+    Vf = Vf.copy()
+    for j in range(Uf.shape[1]):
+        i = int(np.argmax(np.abs(Uf[:, j])))
+        a = Uf[i, j]
+        if a != 0:
+            ph = np.conj(a) / abs(a)
+            Uf[:, j] *= ph
+            Vf[:, j] *= ph
+    return Uf, Vf
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2: randomized block Krylov truncated T-SVD, per Fourier slice
+# ---------------------------------------------------------------------------
+
+def krylov_basis(Af: np.ndarray, Of: np.ndarray, q: int, krylov: str = "stab"):
+    """Orthonormal basis Q_f of the block Krylov space of Alg. 2 for one slice:
+    K = [A Om, (A A^H) A Om, ..., (A A^H)^q A Om].
+
+    krylov="lit": the blocks exactly as written (K_i = A (A^H K_{i-1})), then one
+    Householder QR of K (Alg. 2, Krylov loop and T-QR).
+    krylov="stab": Q_0 = qr(A Om); for i >= 1, W = A (A^H Q_{i-1}),
+    W -= Q_<i (Q_<i^H W) twice, Q_i = qr(W); Q = [Q_0 .. Q_q] (reading R6).
+    Returns (Q, blocks) where blocks are the R factors / literal blocks."""
+    if krylov == "lit":
+        blocks = [Af @ Of]
+        for _ in range(q):
+            blocks.append(Af @ (Af.conj().T @ blocks[-1]))
+        Q, R = householder_qr(np.concatenate(blocks, axis=1))
+        return Q, R
+    if krylov != "stab":
+        raise ValueError(krylov)
+    Q0, _ = householder_qr(Af @ Of)
+    Qs = [Q0]
+    for _ in range(q):
+        W = Af @ (Af.conj().T @ Qs[-1])
+        Qp = np.concatenate(Qs, axis=1)
+        for _rep in range(2):
+            W = W - Qp @ (Qp.conj().T @ W)
+        Qi, _ = householder_qr(W)
+        Qs.append(Qi)
+    return np.concatenate(Qs, axis=1), None
+
+
+def _check_params(n1, n2, n3, k, b, q):
+    if min(n1, n2, n3) < 1:
+        raise ValueError("empty tensor")
+    if not (1 <= k <= b) or q < 0:
+        raise ValueError("need 1 <= k <= b and q >= 0")
+    if b * (q + 1) > min(n1, n2):
+        raise ValueError("need m = b (q + 1) <= min(n1, n2)")
+
+
+def rbk_slices(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
+               freqs=None, krylov: str = "stab"):
+    """Alg. 2 in the Fourier domain for the requested slices (default: the
+    n3//2 + 1 slices of the half spectrum).
+
+    Per slice f: Krylov basis Q_f (Alg. 2 Krylov loop + T-QR), C_f = Q_f^H A_f
+    (Alg. 2, projection), SVD of C_f (Alg. 2, T-SVD of C), U_f = Q_f W(:, :k),
+    S_f = s[:k], V_f = Z(:, :k) (Alg. 2, lift and truncation), phases
+    canonicalised (reading R9).  Returns a dict of per-slice arrays indexed like
+    ``freqs``: Uf (n1,k,nf), Sf (k,nf), Vf (n2,k,nf), Q (n1,m,nf), C (m,n2,nf),
+    s_all (m,nf) (all singular values of C_f)."""
+    n1, n2, n3 = A.shape
+    _check_params(n1, n2, n3, k, b, q)
+    if Omega.shape != (n2, b, n3):
+        raise ValueError("Omega must be n2 x b x n3")
+    if freqs is None:
+        freqs = list(range(n_half(n3)))
+    Ab = dft_mode3(A, freqs)
+    Ob = dft_mode3(Omega, freqs)
+    m = b * (q + 1)
+    nf = len(freqs)
+    out = {
+        "freqs": list(freqs),
+        "Uf": np.zeros((n1, k, nf), complex), "Sf": np.zeros((k, nf)),
+        "Vf": np.zeros((n2, k, nf), complex), "Q": np.zeros((n1, m, nf), complex),
+        "C": np.zeros((m, n2, nf), complex), "s_all": np.zeros((m, nf)),
+    }
+    for idx in range(nf):
+        Af, Of = Ab[:, :, idx], Ob[:, :, idx]
+        Q, _ = krylov_basis(Af, Of, q, krylov)
+        C = Q.conj().T @ Af
+        W, s, Z, _ = jacobi_svd(C)
+        Uf = Q @ W[:, :k]
+        Vf = Z[:, :k]
+        Uf, Vf = canonical_phase(Uf, Vf)
+        out["Uf"][:, :, idx] = Uf
+        out["Vf"][:, :, idx] = Vf
+        out["Sf"][:, idx] = s[:k]
+        out["Q"][:, :, idx] = Q
+        out["C"][:, :, idx] = C
+        out["s_all"][:, idx] = s
+    return out
+
+
+def rbk_tsvd(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
+             krylov: str = "stab"):
+    """Alg. 2: U (n1 x k x n3), S (k x n3: the diagonal tubes of the f-diagonal
+    S_R), V (n2 x k x n3) with A ~ U * S * V^T, plus the half-spectrum pieces.
+    The mirror and inverse transform follow Alg. TP."""
+    n1, n2, n3 = A.shape
+    sl = rbk_slices(A, Omega, k, b, q, None, krylov)
+    U = real_part_checked(idft_mode3(mirror(sl["Uf"], n3)))
+    V = real_part_checked(idft_mode3(mirror(sl["Vf"], n3)))
+    S = real_part_checked(idft_mode3(mirror(sl["Sf"].astype(np.complex128), n3)))
+    sl.update(U=U, S=S, V=V)
+    return sl
+
+
+def s_tensor(S: np.ndarray) -> np.ndarray:
+    """f-diagonal k x k x n3 tensor from its k diagonal tubes."""
+    k, n3 = S.shape
+    T = np.zeros((k, k, n3))
+    for j in range(k):
+        T[j, j, :] = S[j, :]
+    return T
+
+
+def approx_from_slices(sl: dict, n1: int, n2: int, n3: int) -> np.ndarray:
+    """X_hat = U * S * V^T assembled per slice as U_f S_f V_f^H (Alg. TP), then
+    mirrored and inverse transformed; equals Q * (Q^T * A)_k (Lemma mn38)."""
+    F = n_half(n3)
+    Xh = np.zeros((n1, n2, F), complex)
+    for f in range(F):
+        Xh[:, :, f] = (sl["Uf"][:, :, f] * sl["Sf"][:, f]) @ sl["Vf"][:, :, f].conj().T
+    return real_part_checked(idft_mode3(mirror(Xh, n3)))
+
+
+def rbk_approx(A, Omega, k, b, q, krylov: str = "stab") -> np.ndarray:
+    """Rank-k approximation X_hat = U_R * S_R * V_R^T returned by Alg. 2."""
+    n1, n2, n3 = A.shape
+    sl = rbk_slices(A, Omega, k, b, q, None, krylov)
+    return approx_from_slices(sl, n1, n2, n3)
+
+
+# ---------------------------------------------------------------------------
+# Projection P(A) = Q * Q^T * A and its adjoint
+# ---------------------------------------------------------------------------
+
+def proj(A: np.ndarray, Omega: np.ndarray, b: int, q: int, krylov: str = "stab"):
+    """P(A) = Q * Q^T * A with Q the T-QR basis of the block Krylov tensor of
+    Alg. 2 (the orthogonal projection of Sec. 4, Thm. mn44 / Lemma mn38):
+    per slice Q_f Q_f^H A_f, mirrored, inverse transformed."""
+    n1, n2, n3 = A.shape
+    _check_params(n1, n2, n3, 1, b, q)
+    F = n_half(n3)
+    Ab, Ob = dft_mode3(A, range(F)), dft_mode3(Omega, range(F))
+    Ph = np.zeros((n1, n2, F), complex)
+    for f in range(F):
+        Q, _ = krylov_basis(Ab[:, :, f], Ob[:, :, f], q, krylov)
+        Ph[:, :, f] = Q @ (Q.conj().T @ Ab[:, :, f])
+    return real_part_checked(idft_mode3(mirror(Ph, n3)))
+
+
+def _proj_slice_adjoint(Af, Of, Yb, q):
+    """Adjoint of the per-slice map A_f -> Q Q^H A_f at A_f, applied to the
+    cotangent Yb, for the real inner product <X, Y> = Re tr(X^H Y).
+
+    Forward (stabilised form, reading R6): Q_0 R_0 = A Om; for i >= 1,
+    T_i = A^H Q_{i-1}, W_i = A T_i, Z_i = (I - Q_<i Q_<i^H) W_i, Q_i R_i = Z_i.
+    Reverse: direct term Q Q^H Yb; Qbar = (Yb A^H + A Yb^H) Q; for i = q..1:
+    Zbar_i = (I - Q_i Q_i^H) Qbar_i R_i^{-H} (the loss depends on Q_i only
+    through its range); Wbar_i = (I - Q_<i Q_<i^H) Zbar_i;
+    Qbar_l -= (Zbar_i W_i^H + W_i Zbar_i^H) Q_l for l < i;
+    Abar += Wbar_i T_i^H; Tbar_i = A^H Wbar_i; Abar += Q_{i-1} Tbar_i^H;
+    Qbar_{i-1} += A Tbar_i.  Finally Zbar_0 = (I - Q_0 Q_0^H) Qbar_0 R_0^{-H}
+    and Abar += Zbar_0 Om^H."""
+    A = Af
+    Q0, R0 = householder_qr(A @ Of)
+    Qs, Rs, Ts, Ws = [Q0], [R0], [None], [None]
+    for i in range(1, q + 1):
+        T = A.conj().T @ Qs[i - 1]
+        W = A @ T
+        Qp = np.concatenate(Qs, axis=1)
+        Z = W - Qp @ (Qp.conj().T @ W)
+        Z = Z - Qp @ (Qp.conj().T @ Z)
+        Qi, Ri = householder_qr(Z)
+        Qs.append(Qi)
+        Rs.append(Ri)
+        Ts.append(T)
+        Ws.append(W)
+    Q = np.concatenate(Qs, axis=1)
+    b = Q0.shape[1]
+    Abar = Q @ (Q.conj().T @ Yb)
+    Qbar_all = (Yb @ A.conj().T + A @ Yb.conj().T) @ Q
+    Qbar = [Qbar_all[:, i * b:(i + 1) * b].copy() for i in range(q + 1)]
+    for i in range(q, 0, -1):
+        Qi, Ri = Qs[i], Rs[i]
+        X = Qbar[i] - Qi @ (Qi.conj().T @ Qbar[i])
+        Zbar = np.linalg.solve(Ri, X.conj().T).conj().T        # X R^{-H}
+        Qp = np.concatenate(Qs[:i], axis=1)
+        Wbar = Zbar - Qp @ (Qp.conj().T @ Zbar)
+        for l in range(i):
+            Qbar[l] -= (Zbar @ (Ws[i].conj().T @ Qs[l]) + Ws[i] @ (Zbar.conj().T @ Qs[l]))
+        Abar += Wbar @ Ts[i].conj().T
+        Tbar = A.conj().T @ Wbar
+        Abar += Qs[i - 1] @ Tbar.conj().T
+        Qbar[i - 1] += A @ Tbar
+    X = Qbar[0] - Q0 @ (Q0.conj().T @ Qbar[0])
+    Zbar0 = np.linalg.solve(R0, X.conj().T).conj().T
+    Abar += Zbar0 @ Of.conj().T
+    return Abar
+
+
+def proj_backward(A: np.ndarray, Omega: np.ndarray, G: np.ndarray, b: int, q: int):
+    """dL/dA for L = <G, P(A)> (G = dL/dP): per-slice adjoint of the Fourier
+    domain map applied to fft(G), mirrored, inverse transformed.  The 1/n3 of
+    the inverse DFT and the conjugate mirror turn the per-slice adjoints into
+    the spatial gradient: dL/dA = ifft(adjoint_f(fft(G)_f))."""
+    n1, n2, n3 = A.shape
+    _check_params(n1, n2, n3, 1, b, q)
+    F = n_half(n3)
+    Ab, Ob, Gb = dft_mode3(A, range(F)), dft_mode3(Omega, range(F)), dft_mode3(G, range(F))
+    Dh = np.zeros((n1, n2, F), complex)
+    for f in range(F):
+        Dh[:, :, f] = _proj_slice_adjoint(Ab[:, :, f], Ob[:, :, f], Gb[:, :, f], q)
+    return real_part_checked(idft_mode3(mirror(Dh, n3)))
+
+
+def masked_loss(T: np.ndarray, M: np.ndarray, P: np.ndarray) -> float:
+    """||M (.) (T - P)||_F^2, the completion data term of Ex. 3."""
+    return float(np.sum((M * (T - P)) ** 2))
+
+
+# ---------------------------------------------------------------------------
+# Reference truncated T-SVD (Sec. 2): per-slice full SVD, used as a pin
+# ---------------------------------------------------------------------------
+
+def exact_truncated_tsvd_slices(A: np.ndarray, k: int):
+    """Truncated T-SVD of tubal rank k by the per-slice SVD in the Fourier
+    domain (Sec. 2, T-SVD): returns (Uf, Sf, Vf, s_all) on the half spectrum."""
+    n1, n2, n3 = A.shape
+    F = n_half(n3)
+    Ab = dft_mode3(A, range(F))
+    r = min(n1, n2)
+    Uf = np.zeros((n1, k, F), complex)
+    Vf = np.zeros((n2, k, F), complex)
+    Sf = np.zeros((k, F))
+    s_all = np.zeros((r, F))
+    for f in range(F):
+        Af = Ab[:, :, f]
+        if n1 <= n2:
+            W, s, Z, _ = jacobi_svd(Af)
+        else:
+            Z, s, W, _ = jacobi_svd(Af.conj().T)
+        u, v = canonical_phase(W[:, :k], Z[:, :k])
+        Uf[:, :, f], Vf[:, :, f], Sf[:, f] = u, v, s[:k]
+        s_all[:, f] = s[:r]
+    return Uf, Sf, Vf, s_all

@@ -1,0 +1,162 @@
+"""Seeded synthetic inputs for the randomized block Krylov T-SVD.
+
+This module only draws random numbers and assembles test tensors; it holds
+none of the method's arithmetic and imports neither the library binding nor
+the oracle.  Both sides (the HIP library and the FP64 oracle) consume exactly
+the arrays produced here.
+
+Workload recipes (real tensors, C-contiguous (n1, n2, n3), tubes contiguous):
+
+  lowrank      A = U * S * V^T (T-product) + noise * N(0, 1).  U (n1 x r x n3) and
+               V (n2 x r x n3) i.i.d. N(0, 1); S f-diagonal with diagonal tubes
+               S(i, i, :) = c_i g_i, g_i ~ N(0, I_n3), c_i the stated decay
+               (i = 1..r).  The T-product is evaluated with numpy's FFT.
+  hyperspectral sum of r separable Gaussian-bump spatial maps times smooth
+               random spectral curves, min-max scaled to [0, 1], plus noise.
+  completion   T = U * V^T of tubal rank r (N(0, 1) factors) and a Bernoulli
+               keep-mask; the starting point X0 = M (.) T.
+
+Draw order inside one seed: factors U, then S tubes, then V, then noise, then
+the mask.  The Gaussian test tensor Omega (n2 x b x n3) comes from a separate
+stream spawned from the same seed, so it does not depend on the data shape.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CONFIGS = {
+    # name: shape, rank/decay recipe, method parameters, precision, seed
+    "c1_fp64_64x64x16": dict(kind="lowrank", n1=64, n2=64, n3=16, r=10,
+                             decay=("geom", 0.8), noise=1e-3, k=5, b=10, q=2,
+                             seed=0, prec="f64"),
+    "c2_fp32_1000x1000x32": dict(kind="lowrank", n1=1000, n2=1000, n3=32, r=200,
+                                 decay=("geom", 0.95), noise=1e-4, k=50, b=60, q=2,
+                                 seed=1, prec="f32"),
+    "c3_hyper_512x512x200": dict(kind="hyperspectral", n1=512, n2=512, n3=200, r=30,
+                                 noise=1e-3, k=30, b=40, q=3, seed=2, prec="bf16"),
+    "c4_completion_2000x2000x16": dict(kind="completion", n1=2000, n2=2000, n3=16,
+                                       r=20, keep=0.3, k=20, b=30, q=2, seed=3,
+                                       prec="f32"),
+    "c5_fp32_4096x4096x64": dict(kind="lowrank", n1=4096, n2=4096, n3=64, r=400,
+                                 decay=("pow", -1.5), noise=1e-5, k=100, b=110, q=3,
+                                 seed=4, prec="f32"),
+}
+
+
+def _streams(seed: int):
+    ss = np.random.SeedSequence(seed)
+    data_ss, omega_ss = ss.spawn(2)
+    return np.random.default_rng(data_ss), np.random.default_rng(omega_ss)
+
+
+def _decay(spec, r: int) -> np.ndarray:
+    i = np.arange(1, r + 1, dtype=np.float64)
+    kind, val = spec
+    if kind == "geom":
+        return val ** i
+    if kind == "pow":
+        return i ** val
+    raise ValueError(spec)
+
+
+def _tprod_usvt(U: np.ndarray, s_tubes: np.ndarray | None, V: np.ndarray) -> np.ndarray:
+    """U * S * V^T for f-diagonal S given by its diagonal tubes (r x n3), or
+    U * V^T when s_tubes is None; evaluated slice-wise in the Fourier domain
+    with numpy's real FFT."""
+    n3 = U.shape[2]
+    Ub = np.fft.rfft(U, axis=2)
+    Vb = np.fft.rfft(V, axis=2)
+    sb = np.fft.rfft(s_tubes, axis=1) if s_tubes is not None else None
+    F = Ub.shape[2]
+    Ab = np.empty((U.shape[0], V.shape[0], F), dtype=np.complex128)
+    for f in range(F):
+        Uf = Ub[:, :, f] if sb is None else Ub[:, :, f] * sb[:, f]
+        Ab[:, :, f] = Uf @ Vb[:, :, f].conj().T
+    return np.fft.irfft(Ab, n=n3, axis=2)
+
+
+def lowrank_tensor(n1, n2, n3, r, decay, noise, seed):
+    """A = U * S * V^T + noise * N(0, 1) (recipe ``lowrank``)."""
+    rng, _ = _streams(seed)
+    U = rng.standard_normal((n1, r, n3))
+    s = _decay(decay, r)[:, None] * rng.standard_normal((r, n3))
+    V = rng.standard_normal((n2, r, n3))
+    A = _tprod_usvt(U, s, V)
+    if noise:
+        A += noise * rng.standard_normal((n1, n2, n3))
+    return np.ascontiguousarray(A)
+
+
+def exact_lowrank_tensor(n1, n2, n3, r, seed, decay=("geom", 0.8)):
+    """Noiseless tensor of tubal rank <= r (recipe ``lowrank`` without noise)."""
+    return lowrank_tensor(n1, n2, n3, r, decay, 0.0, seed)
+
+
+def hyperspectral_tensor(n1, n2, n3, r, noise, seed):
+    """Recipe ``hyperspectral``: A0(i, j, t) = sum_r g_r(i) h_r(j) s_r(t) with
+    g_r, h_r Gaussian bumps (centres U[0, n), widths U[8, 64]) and s_r a sum
+    of 2-3 Gaussian bumps over t (amplitude U[0.2, 1], width U[5, 40]);
+    min-max scaled to [0, 1]; then noise * N(0, 1), no clipping."""
+    rng, _ = _streams(seed)
+    i = np.arange(n1, dtype=np.float64)
+    j = np.arange(n2, dtype=np.float64)
+    t = np.arange(n3, dtype=np.float64)
+    G = np.empty((n1, r))
+    H = np.empty((n2, r))
+    Sp = np.zeros((n3, r))
+    for c in range(r):
+        ci, wi = rng.uniform(0, n1), rng.uniform(8, 64)
+        cj, wj = rng.uniform(0, n2), rng.uniform(8, 64)
+        G[:, c] = np.exp(-(i - ci) ** 2 / (2 * wi * wi))
+        H[:, c] = np.exp(-(j - cj) ** 2 / (2 * wj * wj))
+        for _ in range(int(rng.integers(2, 4))):
+            a, ct, wt = rng.uniform(0.2, 1.0), rng.uniform(0, n3), rng.uniform(5, 40)
+            Sp[:, c] += a * np.exp(-(t - ct) ** 2 / (2 * wt * wt))
+    A = np.einsum("ic,jc,tc->ijt", G, H, Sp, optimize=True)
+    A = (A - A.min()) / (A.max() - A.min())
+    if noise:
+        A += noise * rng.standard_normal((n1, n2, n3))
+    return np.ascontiguousarray(A)
+
+
+def completion_problem(n1, n2, n3, r, keep, seed):
+    """Recipe ``completion``: T = U * V^T (tubal rank r, N(0,1) factors),
+    mask M ~ Bernoulli(keep) per entry, X0 = M (.) T.  Returns (T, M, X0)."""
+    rng, _ = _streams(seed)
+    U = rng.standard_normal((n1, r, n3))
+    V = rng.standard_normal((n2, r, n3))
+    T = _tprod_usvt(U, None, V)
+    M = (rng.random((n1, n2, n3)) < keep).astype(np.float64)
+    return np.ascontiguousarray(T), M, np.ascontiguousarray(M * T)
+
+
+def omega(n2, b, n3, seed):
+    """Gaussian test tensor Omega ~ N(0, 1), n2 x b x n3 (Alg. 2, first line,
+    with n2 rows), from the seed's second stream."""
+    _, rng = _streams(seed)
+    return np.ascontiguousarray(rng.standard_normal((n2, b, n3)))
+
+
+def make_config(name: str):
+    """(A, Omega, params) for a named workload; A and Omega are float64."""
+    c = dict(CONFIGS[name])
+    kind = c["kind"]
+    if kind == "lowrank":
+        A = lowrank_tensor(c["n1"], c["n2"], c["n3"], c["r"], c["decay"], c["noise"], c["seed"])
+    elif kind == "hyperspectral":
+        A = hyperspectral_tensor(c["n1"], c["n2"], c["n3"], c["r"], c["noise"], c["seed"])
+    elif kind == "completion":
+        T, M, A = completion_problem(c["n1"], c["n2"], c["n3"], c["r"], c["keep"], c["seed"])
+        c["T"], c["M"] = T, M
+    else:
+        raise ValueError(kind)
+    Om = omega(c["n2"], c["b"], c["n3"], c["seed"])
+    return A, Om, c
+
+
+def random_tensor(shape, seed, dist="normal"):
+    """Plain i.i.d. tensor for unit tests."""
+    rng, _ = _streams(seed)
+    if dist == "normal":
+        return rng.standard_normal(shape)
+    return rng.uniform(-1, 1, shape)

@@ -1,0 +1,127 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each case applies one textual mutation to a copy of the oracle's source
+(a dropped conjugate, a wrong sign, a missing 1/n3, a wrong index, a dropped
+adjoint term), loads the copy as a separate module and checks that the named
+pin rejects it.  The oracle on disk is never modified.
+"""
+import inspect
+import types
+
+import numpy as np
+import pytest
+
+from oracle import tsvd_oracle
+from paper_2504_04989_amd import inputs
+
+SRC = inspect.getsource(tsvd_oracle)
+
+
+def _mutant(old: str, new: str):
+    assert SRC.count(old) == 1, f"mutation anchor not unique: {old!r}"
+    mod = types.ModuleType("oracle_mutant")
+    exec(compile(SRC.replace(old, new), "oracle_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+# ---- pins, parameterised by the module under test -------------------------
+
+def pin_dft(O):
+    X = inputs.random_tensor((3, 2, 8), 1)
+    assert np.allclose(O.dft_mode3(X), np.fft.fft(X, axis=2), atol=1e-12)
+
+
+def pin_tprod(O):
+    X = inputs.random_tensor((3, 4, 5), 1)
+    Y = inputs.random_tensor((4, 2, 5), 2)
+    assert np.allclose(O.tprod(X, Y), O.tprod_bcirc(X, Y), atol=1e-12)
+
+
+def pin_qr(O):
+    K = inputs.random_tensor((9, 4), 3) + 1j * inputs.random_tensor((9, 4), 4)
+    Q, R = O.householder_qr(K)
+    assert np.allclose(Q.conj().T @ Q, np.eye(4), atol=1e-12)
+    assert np.allclose(Q @ R, K, atol=1e-12)
+
+
+def pin_svd(O):
+    C = inputs.random_tensor((5, 8), 5) + 1j * inputs.random_tensor((5, 8), 6)
+    W, s, Z, _ = O.jacobi_svd(C, max_sweeps=30)
+    assert np.allclose(s, np.linalg.svd(C, compute_uv=False), atol=1e-12)
+    assert np.allclose((W * s) @ Z.conj().T, C, atol=1e-12)
+
+
+def pin_krylov_spatial(O):
+    A = inputs.random_tensor((9, 8, 5), 3)
+    b, q = 2, 2
+    Om = inputs.omega(8, b, 5, 3)
+    Ks = [O.tprod_bcirc(A, Om)]
+    for _ in range(q):
+        Ks.append(O.tprod_bcirc(A, O.tprod_bcirc(O.ttranspose(A), Ks[-1])))
+    Kb = np.fft.fft(np.concatenate(Ks, axis=1), axis=2)
+    sl = O.rbk_slices(A, Om, 1, b, q)
+    for f in range(3):
+        Q = sl["Q"][:, :, f]
+        assert np.allclose(Q.conj().T @ Q, np.eye(b * (q + 1)), atol=1e-12)
+        res = Kb[:, :, f] - Q @ (Q.conj().T @ Kb[:, :, f])
+        assert np.linalg.norm(res) < 1e-10 * np.linalg.norm(Kb[:, :, f])
+
+
+def pin_exact_tsvd(O):
+    # m = n1: Alg. 2 must equal the truncated T-SVD computed with numpy's SVD.
+    n1, n2, n3, k = 20, 24, 4, 5
+    A = inputs.random_tensor((n1, n2, n3), 7)
+    Om = inputs.omega(n2, 10, n3, 7)
+    sl = O.rbk_tsvd(A, Om, k, 10, 1)
+    Xh = O.approx_from_slices(sl, n1, n2, n3)
+    Ab = np.fft.fft(A, axis=2)
+    Xe = np.zeros_like(Ab)
+    for f in range(n3):
+        u, s, vh = np.linalg.svd(Ab[:, :, f])
+        Xe[:, :, f] = (u[:, :k] * s[:k]) @ vh[:k]
+    Xe = np.fft.ifft(Xe, axis=2).real
+    assert np.linalg.norm(Xh - Xe) < 1e-11 * np.linalg.norm(Xe)
+
+
+def pin_adjoint_fd(O):
+    n1, n2, n3, b, q = 6, 5, 3, 2, 1
+    A = inputs.random_tensor((n1, n2, n3), 2)
+    Om = inputs.omega(n2, b, n3, 2)
+    G = inputs.random_tensor((n1, n2, n3), 3)
+    g = O.proj_backward(A, Om, G, b, q)
+    h = 1e-6
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        D = rng.standard_normal(A.shape)
+        fd = (np.sum(G * O.proj(A + h * D, Om, b, q)) - np.sum(G * O.proj(A - h * D, Om, b, q))) / (2 * h)
+        assert abs(fd - np.sum(g * D)) <= 1e-6 * abs(fd) + 1e-9
+
+
+MUTATIONS = [
+    ("dft sign", "- 1j * np.sin(2.0 * np.pi * r / n)", "+ 1j * np.sin(2.0 * np.pi * r / n)", pin_dft),
+    ("mirror without conj", "full[..., f] = np.conj(Xh[..., n3 - f])", "full[..., f] = Xh[..., n3 - f]", pin_tprod),
+    ("idft missing 1/n3", "Finv = np.conj(dft_matrix(n3)) / n3", "Finv = np.conj(dft_matrix(n3))", pin_tprod),
+    ("householder tau", "tau = ((beta - x0) / beta).real", "tau = 0.5 * ((beta - x0) / beta).real", pin_qr),
+    ("householder reflector without conj", "R[j:, j:] -= tau * np.outer(v, v.conj() @ R[j:, j:])",
+     "R[j:, j:] -= tau * np.outer(v, v @ R[j:, j:])", pin_qr),
+    ("jacobi rotation sign", "M[:, p] = c * mp - s * eph * mq", "M[:, p] = c * mp + s * eph * mq", pin_svd),
+    ("jacobi phase", "eph = np.conj(gamma / ag)", "eph = gamma / ag", pin_svd),
+    ("krylov transpose without conj", "W = Af @ (Af.conj().T @ Qs[-1])", "W = Af @ (Af.T @ Qs[-1])", pin_krylov_spatial),
+    ("reorthogonalisation sign", "W = W - Qp @ (Qp.conj().T @ W)", "W = W + Qp @ (Qp.conj().T @ W)", pin_krylov_spatial),
+    ("projection without conj", "C = Q.conj().T @ Af", "C = Q.T @ Af", pin_exact_tsvd),
+    ("truncation off by one", "Vf = Z[:, :k]", "Vf = Z[:, 1:k + 1]", pin_exact_tsvd),
+    ("lift with conj", "Uf = Q @ W[:, :k]", "Uf = Q @ W[:, :k].conj()", pin_exact_tsvd),
+    ("adjoint direct term dropped", "Abar = Q @ (Q.conj().T @ Yb)", "Abar = 0 * Yb", pin_adjoint_fd),
+    ("adjoint Qbar term dropped", "Qbar_all = (Yb @ A.conj().T + A @ Yb.conj().T) @ Q",
+     "Qbar_all = (Yb @ A.conj().T) @ Q", pin_adjoint_fd),
+    ("adjoint reverse Krylov term dropped", "Abar += Qs[i - 1] @ Tbar.conj().T", "pass", pin_adjoint_fd),
+    ("adjoint R^-H dropped", "Zbar0 = np.linalg.solve(R0, X.conj().T).conj().T", "Zbar0 = X", pin_adjoint_fd),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_rejects_planted_mistake(name, old, new, pin):
+    pin(tsvd_oracle)                  # the real oracle passes the pin ...
+    mutant = _mutant(old, new)
+    with pytest.raises((AssertionError, ValueError, RuntimeError, np.linalg.LinAlgError)):
+        pin(mutant)                   # ... and the planted mistake does not
