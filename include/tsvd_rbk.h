@@ -1,0 +1,153 @@
+/*
+ * tsvd_rbk.h -- C ABI of the MI355X (gfx950) randomized block Krylov
+ * truncated T-SVD library (libtsvd_rbk.so).
+ *
+ * Method: M. Nobakht Kooshkghazi, S. Ahmadi-Asl, A. L. F. de Almeida,
+ * "Randomized block Krylov method for approximation of truncated tensor SVD",
+ * arXiv:2504.04989, Alg. 2 (proposed method), with the T-product / T-QR /
+ * T-SVD machinery of Sec. 2 (Alg. TP, Alg. TQR).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Tensors are real, C-contiguous (n1, n2, n3): element (i, j, t) sits at
+ * (i * n2 + j) * n3 + t, so every tube X(i, j, :) is contiguous.  A tensor
+ * written "p x r x n3" uses the same rule with (p, r, n3).
+ *
+ * Pointers named A, Omega, G, U, S, V, Xhat, P, dA and ws are DEVICE pointers
+ * on the current HIP device.  The caller owns all of them; the library never
+ * allocates or frees device memory and never keeps a pointer after return.
+ * Inputs are read only.  Outputs may not alias inputs or each other.
+ *
+ * Element type of A, Omega, G and of every output: double for
+ * TSVD_PREC_F64, float for the other precisions.  Every pointer must be
+ * 16-byte aligned; ws must be 256-byte aligned.
+ *
+ * `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ * work is enqueued on it; the call returns without synchronising.  Results
+ * are valid once the stream has reached the point of the call.
+ *
+ * Omega is the Gaussian test tensor of Alg. 2 (n2 x b x n3; the algorithm's
+ * first line reads randn(n1, ...), but the product X * Omega needs n2 rows, as
+ * in Alg. 1).  The random draws are an input: the same (A, Omega) always
+ * gives the same result.
+ *
+ * Parameters: k = target tubal rank (R in the paper), b = block width
+ * (R + P: rank plus oversampling), q = number of Krylov steps.
+ * m = b (q + 1) is the number of basis columns per Fourier slice.
+ * Requirements (else TSVD_EINVAL, nothing enqueued):
+ *   n1, n2, n3 >= 1;  1 <= k <= b;  q >= 0;  m <= min(n1, n2);
+ *   n1 * n2 * n3 < 2^31;  m <= 1024;  n3 <= 4096.
+ *
+ * Errors: every entry point returns a status.  TSVD_EINVAL (bad arguments),
+ * TSVD_ENOMEM (ws_bytes below tsvd_workspace_bytes), TSVD_EHIP (a HIP launch
+ * or runtime call failed; nothing more is enqueued).  Numerical events found
+ * on the device (Cholesky shifts, a breakdown, an eigensolver that did not
+ * converge, non-finite values) are counted in the workspace and read with
+ * tsvd_read_info().  tsvd_last_error() gives a message for the last non-zero
+ * status returned on the calling thread.
+ *
+ * Internal precision: Gram matrices, Cholesky factors, re-orthogonalisation
+ * coefficients and the small Hermitian eigenproblem are always FP64; the
+ * mode-3 transforms and the large products run in the precision named by
+ * `prec`.
+ */
+#ifndef TSVD_RBK_H
+#define TSVD_RBK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define TSVD_OK 0
+#define TSVD_EINVAL 1
+#define TSVD_ENOMEM 2
+#define TSVD_EHIP 3
+#define TSVD_ENUMERIC 4
+
+/* precision of the transforms and of the large products */
+#define TSVD_PREC_F64 0    /* FP64 storage, FP64 MFMA                         */
+#define TSVD_PREC_F32 1    /* FP32 storage, FP32 MFMA                         */
+#define TSVD_PREC_BF16 2   /* FP32 storage, BF16 operands on MFMA, FP32 accum. */
+#define TSVD_PREC_BF16X3 3 /* FP32 storage, split BF16 hi/lo operands, 3 BF16
+                              MFMA products per term, FP32 accumulation       */
+
+/* operations, for tsvd_workspace_bytes */
+#define TSVD_OP_RBK 0
+#define TSVD_OP_APPROX 1
+#define TSVD_OP_PROJ 2
+#define TSVD_OP_PROJ_BWD 3
+
+/* diagnostic counters returned by tsvd_read_info (int32 each) */
+#define TSVD_INFO_CHOL_SHIFTED 0   /* shifted Cholesky passes that were needed */
+#define TSVD_INFO_CHOL_BREAKDOWN 1 /* pivots still non-positive after the shift */
+#define TSVD_INFO_EIG_NOCONV 2     /* eigenvectors that did not converge        */
+#define TSVD_INFO_NONFINITE 3      /* non-finite values met                     */
+#define TSVD_INFO_COUNT 8
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int tsvd_version(void);
+
+/* Message for the last non-zero status returned on this thread ("" if none).
+ * The string is owned by the library and valid until the next call on the
+ * same thread. */
+const char* tsvd_last_error(void);
+
+/* Bytes of device workspace needed by operation `op` (TSVD_OP_*) for these
+ * sizes and precision; 0 if the arguments are invalid.  Pure host function. */
+size_t tsvd_workspace_bytes(int64_t n1, int64_t n2, int64_t n3, int64_t k,
+                            int64_t b, int64_t q, int prec, int op);
+
+/* Alg. 2: randomized block Krylov truncated T-SVD.
+ * In:  A (n1 x n2 x n3), Omega (n2 x b x n3).
+ * Out: U (n1 x k x n3), S (k x n3: the k diagonal tubes of the f-diagonal
+ *      S_R, row j is the tube S(j, j, :)), V (n2 x k x n3), with
+ *      A ~ U * S * V^T (T-product, Sec. 2).
+ * Per Fourier slice f = 0 .. n3/2 (conjugate symmetry gives the others,
+ * Alg. TP): the block Krylov space [A_f Om_f, (A_f A_f^H) A_f Om_f, ...,
+ * (A_f A_f^H)^q A_f Om_f] is built block by block, each block orthonormalised
+ * against the earlier ones (same space as the literal powers in exact
+ * arithmetic); C_f = Q_f^H A_f; top-k SVD of C_f; U_f = Q_f W_k,
+ * V_f = right singular vectors.  Each column pair (U_f(:, j), V_f(:, j)) is
+ * scaled by one unit phase so that the largest-modulus entry of U_f(:, j)
+ * (first on ties) is real and positive. */
+int tsvd_rbk(const void* A, const void* Omega, int64_t n1, int64_t n2,
+             int64_t n3, int64_t k, int64_t b, int64_t q, int prec, void* U,
+             void* S, void* V, void* ws, size_t ws_bytes, void* stream);
+
+/* Alg. 2 followed by the rank-k approximation Xhat = U * S * V^T
+ * (n1 x n2 x n3), which equals Q * (Q^T * A)_k (Lemma mn38).  U, S and V
+ * are written as in tsvd_rbk and may not be NULL. */
+int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2,
+                    int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
+                    void* U, void* S, void* V, void* Xhat, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* Projection P(A) = Q * Q^T * A (n1 x n2 x n3), Q the T-orthonormal basis of
+ * the block Krylov tensor of Alg. 2 (the projector of Thm. mn44 and
+ * Lemma mn38; no truncation). */
+int tsvd_proj(const void* A, const void* Omega, int64_t n1, int64_t n2,
+              int64_t n3, int64_t b, int64_t q, int prec, void* P, void* ws,
+              size_t ws_bytes, void* stream);
+
+/* Adjoint of the projection: given G = dL/dP (n1 x n2 x n3), writes
+ * dA = dL/dA (n1 x n2 x n3) for L(P(A)).  The Krylov blocks are recomputed
+ * from A and Omega, not stored.  Derivative of the map defined by tsvd_proj;
+ * for the real inner product sum_ijt x_ijt y_ijt (Sec. 2). */
+int tsvd_proj_backward(const void* A, const void* Omega, const void* G,
+                       int64_t n1, int64_t n2, int64_t n3, int64_t b,
+                       int64_t q, int prec, void* dA, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* Copy the TSVD_INFO_COUNT diagnostic counters of the last call that used
+ * workspace `ws` into info_host (host memory).  Synchronises `stream`. */
+int tsvd_read_info(const void* ws, int32_t* info_host, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSVD_RBK_H */

@@ -1,0 +1,40 @@
+/*
+ * tsvd_rbk_diag.h -- kernel-level entry points of libtsvd_rbk.so, exported so
+ * that each building block of Alg. 2 can be checked on its own.  Same
+ * conventions as tsvd_rbk.h (device pointers, caller-owned memory, stream
+ * ordered, status codes, tsvd_last_error()).
+ */
+#ifndef TSVD_RBK_DIAG_H
+#define TSVD_RBK_DIAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Mode-3 DFT of real tubes (Sec. 2: fft(X, [], 3), unnormalised, omega =
+ * exp(-2 pi i / n3)), first n3/2 + 1 frequencies only (Alg. TP).
+ * X: ntubes x n3 real (tube-contiguous).  Xb: (n3/2 + 1) x ntubes complex,
+ * interleaved (re, im), slice-major.  dtype: 0 = double, 1 = float. */
+int tsvd_diag_fft_r2c(const void* X, void* Xb, int64_t ntubes, int64_t n3, int dtype, void* stream);
+
+/* Inverse (ifft(., [], 3) with the 1/n3, Sec. 2) of a half spectrum completed
+ * by conjugate symmetry (Alg. TP); imaginary parts of the DC and Nyquist
+ * slices are ignored.  Xb: (n3/2 + 1) x ntubes complex; X: ntubes x n3 real. */
+int tsvd_diag_fft_c2r(const void* Xb, void* X, int64_t ntubes, int64_t n3, int dtype, void* stream);
+
+/* Batched complex product C[f] = alpha opA(A[f]) opB(B[f]) + beta C[f]
+ * (the per-slice T-product of Sec. 2 / Alg. TP), all operands interleaved
+ * complex row-major in the same dtype (0 = double, 1 = float).
+ * a_conj = 0: A is M x K; 1: A is stored K x M and opA = A^H.
+ * b_conj = 0: B is K x N; 1: B is stored N x K and opB = B^H.
+ * Leading dimensions are the row lengths of the stored matrices. */
+int tsvd_diag_zgemm(const void* A, int a_conj, const void* B, int b_conj, void* C, int64_t M, int64_t N, int64_t K,
+                    int64_t batch, double alpha, double beta, int dtype, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

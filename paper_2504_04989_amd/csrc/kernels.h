@@ -1,0 +1,67 @@
+// Host-side launch interface of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsvd {
+
+enum DType { DT_F32 = 0, DT_F64 = 1 };
+
+// Batched complex GEMM on interleaved complex storage:
+//   C[f] = alpha * opA(A[f]) * opB(B[f]) + beta * C[f]      (f < batch)
+// opA: a_conj == false -> A is M x K (row m at A + m * lda);
+//      a_conj == true  -> A is stored K x M and opA = A^H.
+// opB: b_conj == false -> B is K x N; b_conj == true -> B stored N x K, opB = B^H.
+// b_nsum > 1: B is the sum of b_nsum matrices spaced b_sum_stride elements.
+// nsplit > 1: the K range is cut into nsplit chunks of kchunk; chunk s writes
+//   alpha * partial product to C + s * c_split_stride (beta must be 0).
+// Element counts (lda, strides, ...) are in complex elements.
+struct GemmDesc {
+  const void* A; int64_t lda, strideA; DType ta; bool a_conj;
+  const void* B; int64_t ldb, strideB; DType tb; bool b_conj; int b_nsum; int64_t b_sum_stride;
+  void* C; int64_t ldc, strideC; DType tc;
+  int M, N, K, batch;
+  int nsplit, kchunk; int64_t c_split_stride;
+  double alpha, beta;
+  DType compute;
+};
+hipError_t zgemm(const GemmDesc& d, hipStream_t s);
+
+// Mode-3 real-to-half-spectrum DFT: X (ntubes x n3, tube-contiguous) ->
+// Xb (F x ntubes complex, F = n3/2 + 1), slice-major.
+hipError_t fft_r2c(const void* X, void* Xb, int64_t ntubes, int n3, DType t, hipStream_t s);
+// Inverse: Xb (F x ntubes, slice stride `slice_stride` elements) -> X
+// (ntubes x n3 real).  Imaginary parts of DC / Nyquist are ignored.
+hipError_t fft_c2r(const void* Xb, int64_t slice_stride, void* X, int64_t ntubes, int n3, DType t, hipStream_t s);
+
+// Per-slice b x b Hermitian Gram (sum of nsum FP64 partials, partial s at
+// Gpart + s * part_stride complex elements, slice f at + f * b * b) -> inverse
+// of its shifted Cholesky factor R (G + shift_coef * trace(G) I = R^H R),
+// upper triangular, FP64, b x b row-major per slice.  gscratch: b(b+1)/2
+// complex doubles per slice, used when !chol_uses_lds(b).
+inline bool chol_uses_lds(int64_t b) { return b * (b + 1) / 2 * 16 <= 46 * 1024; }
+hipError_t chol_inv_ex(const double* Gpart, int nsum, int64_t part_stride, double* Rinv, void* gscratch, int b,
+                       int batch, double shift_coef, int* info, hipStream_t s);
+
+// Per-slice m x m Hermitian PSD matrix (sum of nsum FP64 partials): top-k
+// eigenpairs.  lambda (batch x k, descending), W (batch x m x k complex FP64).
+size_t heig_scratch_bytes(int m, int k);
+hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, int k, int batch, double* lambda,
+                     double* W, void* scratch, int* info, hipStream_t s);
+
+// Lift helpers.
+// Wout (batch x m x k, dtype t) = W * diag(scale) where scale = sqrt(lambda)
+// (scale_mode 0), 1/sqrt(lambda) (mode 1, 0 where lambda <= 0) or 1 (mode 2).
+hipError_t scale_cols(const double* W, const double* lambda, void* Wout, int m, int k, int batch, int scale_mode,
+                      DType t, hipStream_t s);
+// Phase canonicalisation of (U_f, V_f) column pairs and sigma = sqrt(lambda).
+hipError_t canon_phase(void* U, int64_t n1, void* V, int64_t n2, int k, int batch, DType t, hipStream_t s);
+// sigma = sqrt(max(lambda, 0)) (FP64) and (sigma, 0) as complex in dtype t.
+hipError_t sigma_from_lambda(const double* lambda, double* sigma, void* scx, int64_t n, DType t, hipStream_t s);
+// U * diag(sigma): Uout (batch x n1 x k) = Uin * sigma (per slice).
+hipError_t scale_cols_by(const void* Uin, const double* sigma, void* Uout, int64_t n1, int k, int batch, DType t,
+                         hipStream_t s);
+hipError_t zero_info(int* info, hipStream_t s);
+
+}  // namespace tsvd

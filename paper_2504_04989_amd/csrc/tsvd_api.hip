@@ -1,0 +1,593 @@
+// C ABI of the randomized block Krylov truncated T-SVD (Alg. 2 of the paper;
+// see include/tsvd_rbk.h for the contract of every entry point).
+//
+// Host side: validates arguments, carves the caller's workspace and enqueues
+// the kernels on the caller's stream.  Per call, for all Fourier slices at
+// once (each launch is batched over the n3/2 + 1 slices):
+//   mode-3 DFT of A and Omega                       (Sec. 2, Alg. TP)
+//   K_0 = A_f Om_f; block orthonormalisation         (Alg. 2 Krylov loop, T-QR)
+//   for i = 1..q: T_i = A_f^H Q_{i-1}; W = A_f T_i;  re-orthogonalise W
+//                 against Q_<i (two block Gram-Schmidt passes) and
+//                 orthonormalise it (shifted CholeskyQR, three passes)
+//   T_{q+1} = A_f^H Q_q, so that [T_1 .. T_{q+1}] = A_f^H Q_f = C_f^H
+//   G_f = C_f C_f^H (FP64); top-k eigenpairs -> sigma, W_k  (T-SVD of C)
+//   U_f = Q_f W_k; V_f = C_f^H W_k diag(1/sigma)      (lift and truncation)
+//   phase convention; inverse DFT of U, S, V          (Alg. TP mirror)
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "../../include/tsvd_rbk.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace tsvd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+  int64_t n1, n2, n3, k, b, q, m, F;
+  int prec;
+  DType dt;
+  size_t cs;  // bytes of one complex element in the working precision
+  int nsplit_blk, kchunk_blk;   // split-K for K = n1 products (block Grams, projections)
+  int nsplit_g, kchunk_g;       // split-K for G = T^H T (K = n2)
+  // workspace offsets (bytes)
+  size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
+      o_uf, o_vf, o_scx, o_us, total;
+};
+
+int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
+  int64_t ns = (K + 255) / 256;
+  int64_t cap = std::max<int64_t>(1, 1024 / std::max<int64_t>(1, tiles * batch));
+  ns = std::min(ns, cap);
+  if (ns < 1) ns = 1;
+  int64_t kc = (K + ns - 1) / ns;
+  kc = (kc + 15) / 16 * 16;
+  ns = (K + kc - 1) / kc;
+  if (ns < 1) ns = 1;
+  *kchunk = (int)std::max<int64_t>(kc, 16);
+  return (int)ns;
+}
+
+int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, int prec, int op, Plan* p) {
+  if (n1 < 1 || n2 < 1 || n3 < 1) return fail(TSVD_EINVAL, "n1, n2, n3 must be >= 1");
+  if (b < 1 || q < 0) return fail(TSVD_EINVAL, "need b >= 1 and q >= 0");
+  if (op == TSVD_OP_RBK || op == TSVD_OP_APPROX) {
+    if (k < 1 || k > b) return fail(TSVD_EINVAL, "need 1 <= k <= b");
+  } else {
+    k = 1;
+  }
+  const int64_t m = b * (q + 1);
+  if (m > std::min(n1, n2)) return fail(TSVD_EINVAL, "need m = b (q + 1) <= min(n1, n2)");
+  if (m > 1024) return fail(TSVD_EINVAL, "m = b (q + 1) must be <= 1024");
+  if (n3 > 4096) return fail(TSVD_EINVAL, "n3 must be <= 4096");
+  if (n1 * n2 * n3 >= (int64_t)1 << 31 || n1 * n2 >= (int64_t)1 << 31)
+    return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
+  if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32)
+    return fail(TSVD_EINVAL, "precision mode not supported by this build");
+  if (op < TSVD_OP_RBK || op > TSVD_OP_PROJ) return fail(TSVD_EINVAL, "unsupported operation");
+  p->n1 = n1;
+  p->n2 = n2;
+  p->n3 = n3;
+  p->k = k;
+  p->b = b;
+  p->q = q;
+  p->m = m;
+  p->F = n3 / 2 + 1;
+  p->prec = prec;
+  p->dt = prec == TSVD_PREC_F64 ? DT_F64 : DT_F32;
+  p->cs = prec == TSVD_PREC_F64 ? 16 : 8;
+  const int64_t F = p->F;
+  const int64_t tb = (b + 63) / 64;
+  p->nsplit_blk = split_for(n1, tb * ((m + 63) / 64), F, &p->kchunk_blk);
+  const int64_t tm = (m + 63) / 64;
+  p->nsplit_g = split_for(n2, tm * tm, F, &p->kchunk_g);
+
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  const size_t cs = p->cs;
+  p->o_info = take(256);
+  p->o_abar = take((size_t)F * n1 * n2 * cs);
+  p->o_obar = take((size_t)F * n2 * b * cs);
+  p->o_q = take((size_t)F * n1 * m * cs);
+  p->o_t = take((size_t)F * n2 * m * cs);
+  p->o_s0 = take((size_t)F * n1 * b * cs);
+  p->o_s1 = take((size_t)F * n1 * b * cs);
+  size_t part = (size_t)p->nsplit_blk * F * m * b * 16;
+  part = std::max(part, (size_t)p->nsplit_g * F * m * m * 16);
+  p->o_part = take(part);
+  p->o_rinv = take((size_t)F * b * b * 16);
+  p->o_chol = take(chol_uses_lds(b) ? 0 : (size_t)F * b * (b + 1) / 2 * 16);
+  const bool need_svd = (op == TSVD_OP_RBK || op == TSVD_OP_APPROX);
+  p->o_lam = take(need_svd ? (size_t)F * k * 8 : 0);
+  p->o_sig = take(need_svd ? (size_t)F * k * 8 : 0);
+  p->o_wd = take(need_svd ? (size_t)F * m * k * 16 : 0);
+  p->o_wds = take(need_svd ? (size_t)F * m * k * 16 : 0);
+  p->o_heig = take(need_svd ? (size_t)F * heig_scratch_bytes((int)m, (int)k) : 0);
+  p->o_uf = take(need_svd ? (size_t)F * n1 * k * cs : 0);
+  p->o_vf = take(need_svd ? (size_t)F * n2 * k * cs : 0);
+  p->o_scx = take(need_svd ? (size_t)F * k * cs : 0);
+  p->o_us = take(op == TSVD_OP_APPROX ? (size_t)F * n1 * k * cs : 0);
+  p->total = o;
+  return TSVD_OK;
+}
+
+struct Ctx {
+  const Plan& p;
+  unsigned char* ws;
+  hipStream_t s;
+  template <typename T = void>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(ws + off);
+  }
+  int* info() const { return at<int>(p.o_info); }
+};
+
+#define HIPCHK(x)                                                            \
+  do {                                                                       \
+    hipError_t e_ = (x);                                                     \
+    if (e_ != hipSuccess) {                                                  \
+      char b_[256];                                                          \
+      snprintf(b_, sizeof b_, "HIP error %d (%s) at %s:%d", (int)e_,         \
+               hipGetErrorString(e_), __FILE__, __LINE__);                   \
+      return fail(TSVD_EHIP, b_);                                            \
+    }                                                                        \
+  } while (0)
+
+GemmDesc gd() {
+  GemmDesc d{};
+  d.b_nsum = 1;
+  d.nsplit = 1;
+  d.alpha = 1.0;
+  d.beta = 0.0;
+  return d;
+}
+
+// part[s][f] (M x N, FP64) = opA^H-style inner products over K = n1 rows:
+// X^H Y with X (n1 x M, ld lx), Y (n1 x N, ld ly), both in the working dtype.
+int inner_products(const Ctx& c, const void* X, int64_t lx, int M, const void* Y, int64_t ly, int N, int64_t K,
+                   int64_t strideX, int64_t strideY, int nsplit, int kchunk, double* part) {
+  const Plan& p = c.p;
+  GemmDesc d = gd();
+  d.A = X;
+  d.lda = lx;
+  d.strideA = strideX;
+  d.ta = p.dt;
+  d.a_conj = true;
+  d.B = Y;
+  d.ldb = ly;
+  d.strideB = strideY;
+  d.tb = p.dt;
+  d.C = part;
+  d.ldc = N;
+  d.strideC = (int64_t)M * N;
+  d.tc = DT_F64;
+  d.M = M;
+  d.N = N;
+  d.K = (int)K;
+  d.batch = (int)p.F;
+  d.nsplit = nsplit;
+  d.kchunk = kchunk;
+  d.c_split_stride = p.F * M * N;
+  d.compute = DT_F64;
+  HIPCHK(zgemm(d, c.s));
+  return TSVD_OK;
+}
+
+// dst (n1 x b, ld ldd) = src (n1 x b, ld lds) * Rinv   (FP64 arithmetic)
+int apply_rinv(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ldd) {
+  const Plan& p = c.p;
+  GemmDesc d = gd();
+  d.A = src;
+  d.lda = lds;
+  d.strideA = p.n1 * lds;
+  d.ta = p.dt;
+  d.B = c.at(p.o_rinv);
+  d.ldb = p.b;
+  d.strideB = p.b * p.b;
+  d.tb = DT_F64;
+  d.C = dst;
+  d.ldc = ldd;
+  d.strideC = p.n1 * ldd;
+  d.tc = p.dt;
+  d.M = (int)p.n1;
+  d.N = (int)p.b;
+  d.K = (int)p.b;
+  d.batch = (int)p.F;
+  d.compute = DT_F64;
+  HIPCHK(zgemm(d, c.s));
+  return TSVD_OK;
+}
+
+// One CholeskyQR pass: dst = src R^{-1}, G = src^H src (+ shift).
+int cholqr_pass(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ldd, bool shifted) {
+  const Plan& p = c.p;
+  double* part = c.at<double>(p.o_part);
+  int r = inner_products(c, src, lds, (int)p.b, src, lds, (int)p.b, p.n1, p.n1 * lds, p.n1 * lds, p.nsplit_blk,
+                         p.kchunk_blk, part);
+  if (r) return r;
+  const double u = 1.1102230246251565e-16;
+  const double shift = shifted ? 11.0 * ((double)p.n1 * p.b + (double)p.b * (p.b + 1)) * u : 0.0;
+  HIPCHK(chol_inv_ex(part, p.nsplit_blk, p.F * p.b * p.b, c.at<double>(p.o_rinv), c.at(p.o_chol), (int)p.b,
+                     (int)p.F, shift, c.info(), c.s));
+  return apply_rinv(c, src, lds, dst, ldd);
+}
+
+// W (n1 x b, ld b) -= Q_<i (Q_<i^H W), Q_<i = first i*b columns of Q.
+int project_out(const Ctx& c, void* W, int i) {
+  const Plan& p = c.p;
+  if (i == 0) return TSVD_OK;
+  const int ib = (int)(i * p.b);
+  double* part = c.at<double>(p.o_part);
+  void* Q = c.at(p.o_q);
+  int r = inner_products(c, Q, p.m, ib, W, p.b, (int)p.b, p.n1, p.n1 * p.m, p.n1 * p.b, p.nsplit_blk, p.kchunk_blk,
+                         part);
+  if (r) return r;
+  GemmDesc d = gd();
+  d.A = Q;
+  d.lda = p.m;
+  d.strideA = p.n1 * p.m;
+  d.ta = p.dt;
+  d.B = part;
+  d.ldb = p.b;
+  d.strideB = (int64_t)ib * p.b;
+  d.tb = DT_F64;
+  d.b_nsum = p.nsplit_blk;
+  d.b_sum_stride = p.F * ib * p.b;
+  d.C = W;
+  d.ldc = p.b;
+  d.strideC = p.n1 * p.b;
+  d.tc = p.dt;
+  d.M = (int)p.n1;
+  d.N = (int)p.b;
+  d.K = ib;
+  d.batch = (int)p.F;
+  d.alpha = -1.0;
+  d.beta = 1.0;
+  d.compute = DT_F64;
+  HIPCHK(zgemm(d, c.s));
+  return TSVD_OK;
+}
+
+// Orthonormalise the block in S0 against Q_<i and write it to Q(:, i b : (i+1) b).
+int orth_block(const Ctx& c, int i) {
+  const Plan& p = c.p;
+  void* S0 = c.at(p.o_s0);
+  void* S1 = c.at(p.o_s1);
+  void* dst = c.at<unsigned char>(p.o_q) + (size_t)i * p.b * p.cs;
+  int r;
+  if ((r = project_out(c, S0, i))) return r;
+  if ((r = cholqr_pass(c, S0, p.b, S1, p.b, true))) return r;
+  if ((r = project_out(c, S1, i))) return r;
+  if ((r = cholqr_pass(c, S1, p.b, S0, p.b, false))) return r;
+  return cholqr_pass(c, S0, p.b, dst, p.m, false);
+}
+
+// Out (M x N, ld ldc) = A_f (n1 x n2) * X (n2 x N, ld ldx): the big products.
+int big_AX(const Ctx& c, const void* X, int64_t ldx, int64_t strideX, void* Out, int64_t ldo, int64_t strideO, int N) {
+  const Plan& p = c.p;
+  GemmDesc d = gd();
+  d.A = c.at(p.o_abar);
+  d.lda = p.n2;
+  d.strideA = p.n1 * p.n2;
+  d.ta = p.dt;
+  d.B = X;
+  d.ldb = ldx;
+  d.strideB = strideX;
+  d.tb = p.dt;
+  d.C = Out;
+  d.ldc = ldo;
+  d.strideC = strideO;
+  d.tc = p.dt;
+  d.M = (int)p.n1;
+  d.N = N;
+  d.K = (int)p.n2;
+  d.batch = (int)p.F;
+  d.compute = p.dt;
+  HIPCHK(zgemm(d, c.s));
+  return TSVD_OK;
+}
+
+// Out (n2 x N) = A_f^H * Y (n1 x N)
+int big_AhY(const Ctx& c, const void* Y, int64_t ldy, int64_t strideY, void* Out, int64_t ldo, int64_t strideO,
+            int N) {
+  const Plan& p = c.p;
+  GemmDesc d = gd();
+  d.A = c.at(p.o_abar);
+  d.lda = p.n2;
+  d.strideA = p.n1 * p.n2;
+  d.ta = p.dt;
+  d.a_conj = true;
+  d.B = Y;
+  d.ldb = ldy;
+  d.strideB = strideY;
+  d.tb = p.dt;
+  d.C = Out;
+  d.ldc = ldo;
+  d.strideC = strideO;
+  d.tc = p.dt;
+  d.M = (int)p.n2;
+  d.N = N;
+  d.K = (int)p.n1;
+  d.batch = (int)p.F;
+  d.compute = p.dt;
+  HIPCHK(zgemm(d, c.s));
+  return TSVD_OK;
+}
+
+// Everything up to Q and T = C^H.
+int krylov(const Ctx& c, const void* A, const void* Omega) {
+  const Plan& p = c.p;
+  const DType dt = p.dt;
+  HIPCHK(zero_info(c.info(), c.s));
+  HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, dt, c.s));
+  HIPCHK(fft_r2c(Omega, c.at(p.o_obar), p.n2 * p.b, (int)p.n3, dt, c.s));
+  unsigned char* Q = c.at<unsigned char>(p.o_q);
+  unsigned char* T = c.at<unsigned char>(p.o_t);
+  int r;
+  if ((r = big_AX(c, c.at(p.o_obar), p.b, p.n2 * p.b, c.at(p.o_s0), p.b, p.n1 * p.b, (int)p.b))) return r;
+  if ((r = orth_block(c, 0))) return r;
+  for (int i = 1; i <= p.q; ++i) {
+    const size_t col = (size_t)(i - 1) * p.b * p.cs;
+    if ((r = big_AhY(c, Q + col, p.m, p.n1 * p.m, T + col, p.m, p.n2 * p.m, (int)p.b))) return r;
+    if ((r = big_AX(c, T + col, p.m, p.n2 * p.m, c.at(p.o_s0), p.b, p.n1 * p.b, (int)p.b))) return r;
+    if ((r = orth_block(c, i))) return r;
+  }
+  const size_t col = (size_t)p.q * p.b * p.cs;
+  return big_AhY(c, Q + col, p.m, p.n1 * p.m, T + col, p.m, p.n2 * p.m, (int)p.b);
+}
+
+// Small SVD of C_f = T_f^H via G = T^H T, lift, phase, inverse DFT.
+int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
+  const Plan& p = c.p;
+  const DType dt = p.dt;
+  double* part = c.at<double>(p.o_part);
+  void* T = c.at(p.o_t);
+  int r = inner_products(c, T, p.m, (int)p.m, T, p.m, (int)p.m, p.n2, p.n2 * p.m, p.n2 * p.m, p.nsplit_g,
+                         p.kchunk_g, part);
+  if (r) return r;
+  double* lam = c.at<double>(p.o_lam);
+  double* Wd = c.at<double>(p.o_wd);
+  HIPCHK(heig_topk(part, p.nsplit_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
+                   c.info(), c.s));
+  // U_f = Q_f W_k
+  GemmDesc d = gd();
+  d.A = c.at(p.o_q);
+  d.lda = p.m;
+  d.strideA = p.n1 * p.m;
+  d.ta = dt;
+  d.B = Wd;
+  d.ldb = p.k;
+  d.strideB = p.m * p.k;
+  d.tb = DT_F64;
+  d.C = c.at(p.o_uf);
+  d.ldc = p.k;
+  d.strideC = p.n1 * p.k;
+  d.tc = dt;
+  d.M = (int)p.n1;
+  d.N = (int)p.k;
+  d.K = (int)p.m;
+  d.batch = (int)p.F;
+  d.compute = dt;
+  HIPCHK(zgemm(d, c.s));
+  // V_f = T_f W_k diag(1/sigma)
+  HIPCHK(scale_cols(Wd, lam, c.at(p.o_wds), (int)p.m, (int)p.k, (int)p.F, 1, DT_F64, c.s));
+  d.A = T;
+  d.strideA = p.n2 * p.m;
+  d.B = c.at(p.o_wds);
+  d.C = c.at(p.o_vf);
+  d.strideC = p.n2 * p.k;
+  d.M = (int)p.n2;
+  HIPCHK(zgemm(d, c.s));
+  HIPCHK(canon_phase(c.at(p.o_uf), p.n1, c.at(p.o_vf), p.n2, (int)p.k, (int)p.F, dt, c.s));
+  HIPCHK(sigma_from_lambda(lam, c.at<double>(p.o_sig), c.at(p.o_scx), p.F * p.k, dt, c.s));
+  HIPCHK(fft_c2r(c.at(p.o_uf), p.n1 * p.k, U, p.n1 * p.k, (int)p.n3, dt, c.s));
+  HIPCHK(fft_c2r(c.at(p.o_vf), p.n2 * p.k, V, p.n2 * p.k, (int)p.n3, dt, c.s));
+  HIPCHK(fft_c2r(c.at(p.o_scx), p.k, S, p.k, (int)p.n3, dt, c.s));
+  return TSVD_OK;
+}
+
+bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+int check_ptrs(std::initializer_list<const void*> ptrs, const void* ws, size_t ws_bytes, const Plan& p) {
+  for (const void* q : ptrs)
+    if (!q || !aligned(q, 16)) return fail(TSVD_EINVAL, "null or misaligned (16 B) tensor pointer");
+  if (!ws || !aligned(ws, 256)) return fail(TSVD_EINVAL, "null or misaligned (256 B) workspace");
+  if (ws_bytes < p.total) return fail(TSVD_ENOMEM, "workspace smaller than tsvd_workspace_bytes()");
+  return TSVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tsvd_version(void) { return 100; }
+
+const char* tsvd_last_error(void) { return g_err.c_str(); }
+
+size_t tsvd_workspace_bytes(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, int prec, int op) {
+  Plan p;
+  if (make_plan(n1, n2, n3, k, b, q, prec, op, &p)) return 0;
+  return p.total;
+}
+
+int tsvd_rbk(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q,
+             int prec, void* U, void* S, void* V, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_RBK, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, Omega, U, S, V}, ws, ws_bytes, p))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = krylov(c, A, Omega))) return r;
+  if ((r = svd_and_lift(c, U, S, V))) return r;
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                    int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
+                    void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_APPROX, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, Omega, U, S, V, Xhat}, ws, ws_bytes, p))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = krylov(c, A, Omega))) return r;
+  if ((r = svd_and_lift(c, U, S, V))) return r;
+  // X_f = (U_f diag(sigma)) V_f^H, then the inverse DFT.
+  HIPCHK(scale_cols_by(c.at(p.o_uf), c.at<double>(p.o_sig), c.at(p.o_us), p.n1, (int)p.k, (int)p.F, p.dt, c.s));
+  GemmDesc d = gd();
+  d.A = c.at(p.o_us);
+  d.lda = p.k;
+  d.strideA = p.n1 * p.k;
+  d.ta = p.dt;
+  d.B = c.at(p.o_vf);
+  d.ldb = p.k;
+  d.strideB = p.n2 * p.k;
+  d.tb = p.dt;
+  d.b_conj = true;
+  d.C = c.at(p.o_abar);
+  d.ldc = p.n2;
+  d.strideC = p.n1 * p.n2;
+  d.tc = p.dt;
+  d.M = (int)p.n1;
+  d.N = (int)p.n2;
+  d.K = (int)p.k;
+  d.batch = (int)p.F;
+  d.compute = p.dt;
+  HIPCHK(zgemm(d, c.s));
+  HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, Xhat, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_proj(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t b, int64_t q, int prec,
+              void* P, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, 1, b, q, prec, TSVD_OP_PROJ, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, Omega, P}, ws, ws_bytes, p))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = krylov(c, A, Omega))) return r;
+  // P_f = Q_f C_f = Q_f T_f^H, written over A_f (no longer needed).
+  GemmDesc d = gd();
+  d.A = c.at(p.o_q);
+  d.lda = p.m;
+  d.strideA = p.n1 * p.m;
+  d.ta = p.dt;
+  d.B = c.at(p.o_t);
+  d.ldb = p.m;
+  d.strideB = p.n2 * p.m;
+  d.tb = p.dt;
+  d.b_conj = true;
+  d.C = c.at(p.o_abar);
+  d.ldc = p.n2;
+  d.strideC = p.n1 * p.n2;
+  d.tc = p.dt;
+  d.M = (int)p.n1;
+  d.N = (int)p.n2;
+  d.K = (int)p.m;
+  d.batch = (int)p.F;
+  d.compute = p.dt;
+  HIPCHK(zgemm(d, c.s));
+  HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, P, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_proj_backward(const void* A, const void* Omega, const void* G, int64_t n1, int64_t n2, int64_t n3, int64_t b,
+                       int64_t q, int prec, void* dA, void* ws, size_t ws_bytes, void* stream) {
+  (void)A;
+  (void)Omega;
+  (void)G;
+  (void)n1;
+  (void)n2;
+  (void)n3;
+  (void)b;
+  (void)q;
+  (void)prec;
+  (void)dA;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  return fail(TSVD_EINVAL, "tsvd_proj_backward: not available in this build");
+}
+
+int tsvd_read_info(const void* ws, int32_t* info_host, void* stream) {
+  if (!ws || !info_host) return fail(TSVD_EINVAL, "null pointer");
+  hipError_t e = hipMemcpyAsync(info_host, ws, TSVD_INFO_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return fail(TSVD_EHIP, hipGetErrorString(e));
+  return TSVD_OK;
+}
+
+}  // extern "C"
+
+#include "../../include/tsvd_rbk_diag.h"
+
+extern "C" {
+
+int tsvd_diag_fft_r2c(const void* X, void* Xb, int64_t ntubes, int64_t n3, int dtype, void* stream) {
+  if (!X || !Xb || ntubes < 0 || n3 < 1 || n3 > 4096 || (dtype != 0 && dtype != 1))
+    return fail(TSVD_EINVAL, "bad arguments");
+  HIPCHK(fft_r2c(X, Xb, ntubes, (int)n3, dtype == 0 ? DT_F64 : DT_F32, (hipStream_t)stream));
+  return TSVD_OK;
+}
+
+int tsvd_diag_fft_c2r(const void* Xb, void* X, int64_t ntubes, int64_t n3, int dtype, void* stream) {
+  if (!X || !Xb || ntubes < 0 || n3 < 1 || n3 > 4096 || (dtype != 0 && dtype != 1))
+    return fail(TSVD_EINVAL, "bad arguments");
+  HIPCHK(fft_c2r(Xb, ntubes, X, ntubes, (int)n3, dtype == 0 ? DT_F64 : DT_F32, (hipStream_t)stream));
+  return TSVD_OK;
+}
+
+int tsvd_diag_zgemm(const void* A, int a_conj, const void* B, int b_conj, void* C, int64_t M, int64_t N, int64_t K,
+                    int64_t batch, double alpha, double beta, int dtype, void* stream) {
+  if (!A || !B || !C || M < 0 || N < 0 || K < 0 || batch < 0 || (dtype != 0 && dtype != 1) || (a_conj && b_conj) ||
+      M >= (1 << 30) || N >= (1 << 30) || K >= (1 << 30) || batch > 65535)
+    return fail(TSVD_EINVAL, "bad arguments");
+  GemmDesc d = gd();
+  const DType t = dtype == 0 ? DT_F64 : DT_F32;
+  d.A = A;
+  d.a_conj = a_conj != 0;
+  d.lda = a_conj ? M : K;
+  d.strideA = M * K;
+  d.ta = t;
+  d.B = B;
+  d.b_conj = b_conj != 0;
+  d.ldb = b_conj ? K : N;
+  d.strideB = K * N;
+  d.tb = t;
+  d.C = C;
+  d.ldc = N;
+  d.strideC = M * N;
+  d.tc = t;
+  d.M = (int)M;
+  d.N = (int)N;
+  d.K = (int)K;
+  d.batch = (int)batch;
+  d.alpha = alpha;
+  d.beta = beta;
+  d.compute = t;
+  HIPCHK(zgemm(d, (hipStream_t)stream));
+  return TSVD_OK;
+}
+
+}  // extern "C"

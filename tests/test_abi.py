@@ -1,0 +1,82 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/*.h, sizes workspaces and rejects bad arguments on the
+host before anything is enqueued."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2504_04989_amd", "lib", "libtsvd_rbk.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+\*?\s*(tsvd_[a-z0-9_]+)\s*\(", src,
+                             flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIB)
+    names = _declared()
+    assert "tsvd_rbk" in names and "tsvd_proj_backward" in names and "tsvd_diag_zgemm" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_loads_and_names_match():
+    from paper_2504_04989_amd import api
+    for n in api.EXPORTS:
+        assert hasattr(api.lib, n)
+    assert api.lib.tsvd_version() >= 100
+
+
+def test_workspace_sizes():
+    from paper_2504_04989_amd import api
+    ws = api.workspace_bytes(1000, 1000, 32, 50, 60, 2, "f32", "rbk")
+    F = 17
+    # at least the half spectrum of A plus Q and T = C^H
+    assert ws >= F * 1000 * 1000 * 8 + 2 * F * 1000 * 180 * 8
+    assert ws % 256 == 0
+    assert api.workspace_bytes(64, 64, 16, 5, 10, 2, "f64", "rbk") > 0
+    assert api.workspace_bytes(1000, 1000, 32, 50, 60, 2, "f32", "approx") >= ws
+
+
+@pytest.mark.parametrize("args", [
+    (0, 10, 4, 2, 3, 1),      # empty
+    (10, 10, 4, 4, 3, 1),     # k > b
+    (10, 10, 4, 2, 4, 2),     # m = 12 > 10
+    (10, 10, 4, 2, 3, -1),    # q < 0
+    (40, 40, 5000, 2, 3, 1),  # n3 too large
+])
+def test_invalid_sizes_rejected(args):
+    from paper_2504_04989_amd import api
+    assert api.workspace_bytes(*args, "f32", "rbk") == 0
+    assert api.lib.tsvd_last_error().decode() != ""
+
+
+def test_entry_points_reject_bad_pointers_without_touching_the_gpu():
+    from paper_2504_04989_amd import api
+    L = api.lib
+    nul = ctypes.c_void_p(0)
+    r = L.tsvd_rbk(nul, nul, 10, 10, 4, 2, 3, 1, 1, nul, nul, nul, nul, 0, nul)
+    assert r == api.TSVD_EINVAL
+    r = L.tsvd_rbk(nul, nul, 10, 10, 4, 5, 3, 1, 1, nul, nul, nul, nul, 0, nul)   # k > b
+    assert r == api.TSVD_EINVAL and "k <= b" in L.tsvd_last_error().decode()
+    r = L.tsvd_proj(nul, nul, 10, 10, 4, 3, 1, 7, nul, nul, 0, nul)               # bad precision
+    assert r == api.TSVD_EINVAL
+    # aligned fake pointers but a workspace that is too small -> ENOMEM, nothing launched
+    fake = ctypes.c_void_p(1 << 20)
+    r = L.tsvd_rbk(fake, fake, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, fake, 16, nul)
+    assert r == api.TSVD_ENOMEM
+    r = L.tsvd_diag_zgemm(nul, 0, nul, 0, nul, 4, 4, 4, 1, 1.0, 0.0, 1, nul)
+    assert r == api.TSVD_EINVAL

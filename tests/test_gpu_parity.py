@@ -1,0 +1,139 @@
+"""End-to-end parity of the HIP path with the FP64 oracle (GPU).
+
+Both sides consume the same seeded inputs (for FP32 runs, the oracle reads the
+FP32-rounded values widened back to FP64).  Primary metric: the relative
+Frobenius error of X_hat = U * S * V^T; singular values are compared per
+Fourier slice; factors are compared after the shared phase convention where
+that convention is unambiguous.  Tolerances: 1e-10 (FP64), 1e-5 (FP32).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import tsvd_oracle as O
+from paper_2504_04989_amd import inputs
+from tests.gpu_util import load_api, dev, fourier_factors, host, rel_f, unambiguous_phase_columns
+
+pytestmark = pytest.mark.gpu
+api = load_api()
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+def _cast(x, prec):
+    return x.astype(np.float32).astype(np.float64) if prec == "f32" else x
+
+
+def _run_gpu(A, Om, k, b, q, prec):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    U, S, V, X = api.tsvd_rbk_approx(dev(A, dt), dev(Om, dt), k, b, q, prec)
+    torch.cuda.synchronize()
+    return host(U).astype(np.float64), host(S).astype(np.float64), host(V).astype(np.float64), host(X).astype(
+        np.float64)
+
+
+def _compare(A, Om, k, b, q, prec, factors=True, sv_tol=None):
+    print(f"[parity] shape={A.shape} k={k} b={b} q={q} prec={prec}", flush=True)
+    A, Om = _cast(A, prec), _cast(Om, prec)
+    U, S, V, X = _run_gpu(A, Om, k, b, q, prec)
+    n1, n2, n3 = A.shape
+    sl = O.rbk_tsvd(A, Om, k, b, q)
+    Xo = O.approx_from_slices(sl, n1, n2, n3)
+    tol = TOL[prec]
+    e = rel_f(X, Xo)
+    assert e <= tol, f"X_hat rel err {e:.3e}"
+    # U * S * V^T assembled by the oracle's T-product from the GPU factors
+    Xf = O.tprod(O.tprod(U, O.s_tensor(S)), O.ttranspose(V))
+    assert rel_f(Xf, Xo) <= tol
+    F = n3 // 2 + 1
+    Ub, Sb, Vb = fourier_factors(U, S, V, list(range(F)))
+    assert np.max(np.abs(Sb.imag)) <= 1e-6 * np.max(np.abs(Sb)) + 1e-300
+    s_err = np.max(np.abs(Sb.real - sl["Sf"]) / np.maximum(sl["Sf"], 1e-300))
+    assert s_err <= (sv_tol or tol), f"sigma rel err {s_err:.3e}"
+    if factors:
+        for f in range(F):
+            ok = unambiguous_phase_columns(sl["Uf"][:, :, f])
+            s_ext = np.r_[sl["s_all"][:, f], 0.0]
+            gap = np.abs(np.diff(s_ext[: k + 1])) / s_ext[0]
+            ok &= np.minimum(gap[:k], np.r_[1.0, gap[: k - 1]]) > 1e-3
+            if ok.any():
+                assert rel_f(Ub[:, ok, f], sl["Uf"][:, ok, f]) <= 1e3 * tol
+                assert rel_f(Vb[:, ok, f], sl["Vf"][:, ok, f]) <= 1e3 * tol
+    return e
+
+
+def test_config1_fp64():
+    A, Om, c = inputs.make_config("c1_fp64_64x64x16")
+    _compare(A, Om, c["k"], c["b"], c["q"], "f64")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape,k,b,q", [
+    ((70, 90, 10), 8, 12, 2),     # ragged tiles, n1 < n2, even n3
+    ((150, 97, 7), 6, 9, 3),      # n1 > n2, odd n3
+    ((40, 33, 1), 3, 5, 1),       # n3 = 1: the matrix case
+    ((30, 40, 2), 4, 4, 0),       # DC + Nyquist only, q = 0, k = b
+    ((65, 66, 17), 5, 8, 1),      # prime n3 > 13: direct DFT path
+    ((30, 40, 5), 6, 10, 2),      # m = n1: exact truncated T-SVD
+    ((130, 140, 4), 1, 1, 3),     # b = 1
+])
+def test_small_shapes(shape, k, b, q, prec):
+    n1, n2, n3 = shape
+    A = inputs.lowrank_tensor(n1, n2, n3, min(n1, n2) // 2, ("geom", 0.9), 1e-3, seed=sum(shape))
+    Om = inputs.omega(n2, b, n3, seed=sum(shape))
+    _compare(A, Om, k, b, q, prec, sv_tol=TOL[prec] * (10 if prec == "f32" else 1))
+
+
+def test_exact_recovery_fp64():
+    A = inputs.exact_lowrank_tensor(60, 50, 6, 4, seed=5)
+    Om = inputs.omega(50, 6, 6, 5)
+    U, S, V, X = _run_gpu(A, Om, 4, 6, 2, "f64")
+    assert rel_f(X, A) <= 1e-10
+
+
+def test_proj_fp64_vs_oracle_and_identity():
+    A = inputs.random_tensor((48, 40, 6), 3)
+    Om = inputs.omega(40, 5, 6, 3)
+    P = host(api.tsvd_proj(dev(A), dev(Om), 5, 2))
+    assert rel_f(P, O.proj(A, Om, 5, 2)) <= 1e-10
+    A2 = inputs.random_tensor((30, 40, 5), 4)
+    Om2 = inputs.omega(40, 10, 5, 4)
+    P2 = host(api.tsvd_proj(dev(A2), dev(Om2), 10, 2))
+    assert rel_f(P2, A2) <= 1e-11
+
+
+def test_deterministic_bitwise():
+    A, Om, c = inputs.make_config("c1_fp64_64x64x16")
+    r1 = _run_gpu(A, Om, c["k"], c["b"], c["q"], "f64")
+    r2 = _run_gpu(A, Om, c["k"], c["b"], c["q"], "f64")
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b)
+
+
+def test_info_counters_clean_on_config1():
+    A, Om, c = inputs.make_config("c1_fp64_64x64x16")
+    ws = api.workspace(64, 64, 16, c["k"], c["b"], c["q"], "f64", "rbk", "cuda")
+    api.tsvd_rbk(dev(A), dev(Om), c["k"], c["b"], c["q"], "f64", ws=ws)
+    info = api.read_info(ws)
+    assert info["chol_breakdown"] == 0 and info["eig_noconv"] == 0 and info["nonfinite"] == 0
+
+
+def test_config2_fp32_full_size_sampled_slices():
+    """The 1000 x 1000 x 32 FP32 workload at full size, in the launch
+    configuration the benchmark times; the oracle recomputes three Fourier
+    slices (DC, an interior one and Nyquist) from the same FP32 input."""
+    A, Om, c = inputs.make_config("c2_fp32_1000x1000x32")
+    A, Om = _cast(A, "f32"), _cast(Om, "f32")
+    print("[parity] c2 full size", flush=True)
+    U, S, V, X = _run_gpu(A, Om, c["k"], c["b"], c["q"], "f32")
+    freqs = [0, 5, 16]
+    sl = O.rbk_slices(A, Om, c["k"], c["b"], c["q"], freqs=freqs)
+    Ub, Sb, Vb = fourier_factors(U, S, V, freqs)
+    Xb = np.fft.fft(X, axis=2)[:, :, freqs]
+    for i, f in enumerate(freqs):
+        Xo = (sl["Uf"][:, :, i] * sl["Sf"][:, i]) @ sl["Vf"][:, :, i].conj().T
+        e = rel_f(Xb[:, :, i], Xo)
+        s_err = np.max(np.abs(Sb[:, i].real - sl["Sf"][:, i]) / sl["Sf"][:, i])
+        print(f"[parity] c2 slice {f}: X rel {e:.2e} sigma rel {s_err:.2e}", flush=True)
+        assert e <= 1e-5
+        assert s_err <= 1e-5
