@@ -33,6 +33,18 @@ int tsvd_diag_fft_c2r(const void* Xb, void* X, int64_t ntubes, int64_t n3, int d
 int tsvd_diag_zgemm(const void* A, int a_conj, const void* B, int b_conj, void* C, int64_t M, int64_t N, int64_t K,
                     int64_t batch, double alpha, double beta, int dtype, void* stream);
 
+/* Event timer over the kernels of the entry points in tsvd_rbk.h.
+ * tsvd_diag_timing(1) clears the counters and starts recording a pair of HIP
+ * events on the caller's stream around every launch; (0) stops.
+ * tsvd_diag_timing_read synchronises on the recorded events and returns, per
+ * kernel class, the summed duration in ms and the number of launches.
+ * Classes: 0 mode-3 DFT of A, 1 DFT of Omega, 2 Krylov products
+ * (A_f X and A_f^H Y), 3 orthonormalisation products, 4 Cholesky, 5 small
+ * eigenproblem, 6 Gram of C and lift products, 7 inverse DFTs, 8 other. */
+#define TSVD_DIAG_NCLASS 9
+int tsvd_diag_timing(int enable);
+int tsvd_diag_timing_read(double* ms_out, int64_t* count_out, int nclass);
+
 #ifdef __cplusplus
 }
 #endif

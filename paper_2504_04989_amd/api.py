@@ -22,7 +22,7 @@ INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_rbk", "tsvd_rbk_approx",
            "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
-           "tsvd_diag_zgemm")
+           "tsvd_diag_zgemm", "tsvd_diag_timing", "tsvd_diag_timing_read")
 
 
 class TsvdError(RuntimeError):
@@ -54,6 +54,11 @@ def _load():
     lib.tsvd_diag_fft_r2c.argtypes = [vp, vp, i64, i64, ctypes.c_int, vp]
     lib.tsvd_diag_fft_c2r.restype = ctypes.c_int
     lib.tsvd_diag_fft_c2r.argtypes = [vp, vp, i64, i64, ctypes.c_int, vp]
+    lib.tsvd_diag_timing.restype = ctypes.c_int
+    lib.tsvd_diag_timing.argtypes = [ctypes.c_int]
+    lib.tsvd_diag_timing_read.restype = ctypes.c_int
+    lib.tsvd_diag_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.c_int]
     lib.tsvd_diag_zgemm.restype = ctypes.c_int
     lib.tsvd_diag_zgemm.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, i64, i64, i64, i64, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, vp]
@@ -238,3 +243,18 @@ def diag_zgemm(A, B, a_conj=False, b_conj=False, C=None, alpha=1.0, beta=0.0):
     _check(lib.tsvd_diag_zgemm(_ptr(A), int(a_conj), _ptr(B), int(b_conj), _ptr(C), M, N, K, batch, alpha, beta,
                                _dcode(A), _stream(A.device)))
     return C
+
+
+KERNEL_CLASSES = ("fft_A", "fft_omega", "gemm_krylov", "gemm_orth", "chol", "heig", "gemm_lift", "fft_inv", "misc")
+
+
+def diag_timing(enable: bool):
+    _check(lib.tsvd_diag_timing(int(enable)))
+
+
+def diag_timing_read() -> dict:
+    n = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(lib.tsvd_diag_timing_read(ms, cnt, n))
+    return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(KERNEL_CLASSES)}

@@ -17,7 +17,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/tsvd_rbk.h"
 #include "common.h"
@@ -150,6 +152,49 @@ struct Ctx {
     }                                                                        \
   } while (0)
 
+// ---- opt-in per-kernel-class event timer (tsvd_diag_timing*) -------------
+enum KClass { K_FFT_A = 0, K_FFT_OMEGA, K_GEMM_KRYLOV, K_GEMM_ORTH, K_CHOL, K_HEIG, K_GEMM_LIFT, K_FFT_INV, K_MISC,
+              K_NCLASS };
+struct Timer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[K_NCLASS] = {};
+  long long count[K_NCLASS] = {};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Timer g_timer;
+
+struct Timed {
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Timed(int c, hipStream_t st) : cls(c), s(st) {
+    if (!g_timer.on) return;
+    std::lock_guard<std::mutex> l(g_timer.mu);
+    a = g_timer.get();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~Timed() {
+    if (!a) return;
+    std::lock_guard<std::mutex> l(g_timer.mu);
+    hipEvent_t b = g_timer.get();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    g_timer.pending.push_back({cls, {a, b}});
+  }
+};
+
 GemmDesc gd() {
   GemmDesc d{};
   d.b_nsum = 1;
@@ -162,7 +207,7 @@ GemmDesc gd() {
 // part[s][f] (M x N, FP64) = opA^H-style inner products over K = n1 rows:
 // X^H Y with X (n1 x M, ld lx), Y (n1 x N, ld ly), both in the working dtype.
 int inner_products(const Ctx& c, const void* X, int64_t lx, int M, const void* Y, int64_t ly, int N, int64_t K,
-                   int64_t strideX, int64_t strideY, int nsplit, int kchunk, double* part) {
+                   int64_t strideX, int64_t strideY, int nsplit, int kchunk, double* part, int cls = K_GEMM_ORTH) {
   const Plan& p = c.p;
   GemmDesc d = gd();
   d.A = X;
@@ -186,7 +231,10 @@ int inner_products(const Ctx& c, const void* X, int64_t lx, int M, const void* Y
   d.kchunk = kchunk;
   d.c_split_stride = p.F * M * N;
   d.compute = DT_F64;
-  HIPCHK(zgemm(d, c.s));
+  {
+    Timed tm_(cls, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
   return TSVD_OK;
 }
 
@@ -211,7 +259,10 @@ int apply_rinv(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ld
   d.K = (int)p.b;
   d.batch = (int)p.F;
   d.compute = DT_F64;
-  HIPCHK(zgemm(d, c.s));
+  {
+    Timed tm_(K_GEMM_ORTH, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
   return TSVD_OK;
 }
 
@@ -224,8 +275,11 @@ int cholqr_pass(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t l
   if (r) return r;
   const double u = 1.1102230246251565e-16;
   const double shift = shifted ? 11.0 * ((double)p.n1 * p.b + (double)p.b * (p.b + 1)) * u : 0.0;
-  HIPCHK(chol_inv_ex(part, p.nsplit_blk, p.F * p.b * p.b, c.at<double>(p.o_rinv), c.at(p.o_chol), (int)p.b,
+  {
+    Timed tm_(K_CHOL, c.s);
+    HIPCHK(chol_inv_ex(part, p.nsplit_blk, p.F * p.b * p.b, c.at<double>(p.o_rinv), c.at(p.o_chol), (int)p.b,
                      (int)p.F, shift, c.info(), c.s));
+  }
   return apply_rinv(c, src, lds, dst, ldd);
 }
 
@@ -261,7 +315,10 @@ int project_out(const Ctx& c, void* W, int i) {
   d.alpha = -1.0;
   d.beta = 1.0;
   d.compute = DT_F64;
-  HIPCHK(zgemm(d, c.s));
+  {
+    Timed tm_(K_GEMM_ORTH, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
   return TSVD_OK;
 }
 
@@ -300,7 +357,10 @@ int big_AX(const Ctx& c, const void* X, int64_t ldx, int64_t strideX, void* Out,
   d.K = (int)p.n2;
   d.batch = (int)p.F;
   d.compute = p.dt;
-  HIPCHK(zgemm(d, c.s));
+  {
+    Timed tm_(K_GEMM_KRYLOV, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
   return TSVD_OK;
 }
 
@@ -327,7 +387,10 @@ int big_AhY(const Ctx& c, const void* Y, int64_t ldy, int64_t strideY, void* Out
   d.K = (int)p.n1;
   d.batch = (int)p.F;
   d.compute = p.dt;
-  HIPCHK(zgemm(d, c.s));
+  {
+    Timed tm_(K_GEMM_KRYLOV, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
   return TSVD_OK;
 }
 
@@ -335,9 +398,18 @@ int big_AhY(const Ctx& c, const void* Y, int64_t ldy, int64_t strideY, void* Out
 int krylov(const Ctx& c, const void* A, const void* Omega) {
   const Plan& p = c.p;
   const DType dt = p.dt;
-  HIPCHK(zero_info(c.info(), c.s));
-  HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, dt, c.s));
-  HIPCHK(fft_r2c(Omega, c.at(p.o_obar), p.n2 * p.b, (int)p.n3, dt, c.s));
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(zero_info(c.info(), c.s));
+  }
+  {
+    Timed tm_(K_FFT_A, c.s);
+    HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, dt, c.s));
+  }
+  {
+    Timed tm_(K_FFT_OMEGA, c.s);
+    HIPCHK(fft_r2c(Omega, c.at(p.o_obar), p.n2 * p.b, (int)p.n3, dt, c.s));
+  }
   unsigned char* Q = c.at<unsigned char>(p.o_q);
   unsigned char* T = c.at<unsigned char>(p.o_t);
   int r;
@@ -360,12 +432,15 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   double* part = c.at<double>(p.o_part);
   void* T = c.at(p.o_t);
   int r = inner_products(c, T, p.m, (int)p.m, T, p.m, (int)p.m, p.n2, p.n2 * p.m, p.n2 * p.m, p.nsplit_g,
-                         p.kchunk_g, part);
+                         p.kchunk_g, part, K_GEMM_LIFT);
   if (r) return r;
   double* lam = c.at<double>(p.o_lam);
   double* Wd = c.at<double>(p.o_wd);
-  HIPCHK(heig_topk(part, p.nsplit_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
+  {
+    Timed tm_(K_HEIG, c.s);
+    HIPCHK(heig_topk(part, p.nsplit_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
                    c.info(), c.s));
+  }
   // U_f = Q_f W_k
   GemmDesc d = gd();
   d.A = c.at(p.o_q);
@@ -385,21 +460,45 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   d.K = (int)p.m;
   d.batch = (int)p.F;
   d.compute = dt;
-  HIPCHK(zgemm(d, c.s));
+  {
+    Timed tm_(K_GEMM_LIFT, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
   // V_f = T_f W_k diag(1/sigma)
-  HIPCHK(scale_cols(Wd, lam, c.at(p.o_wds), (int)p.m, (int)p.k, (int)p.F, 1, DT_F64, c.s));
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(scale_cols(Wd, lam, c.at(p.o_wds), (int)p.m, (int)p.k, (int)p.F, 1, DT_F64, c.s));
+  }
   d.A = T;
   d.strideA = p.n2 * p.m;
   d.B = c.at(p.o_wds);
   d.C = c.at(p.o_vf);
   d.strideC = p.n2 * p.k;
   d.M = (int)p.n2;
-  HIPCHK(zgemm(d, c.s));
-  HIPCHK(canon_phase(c.at(p.o_uf), p.n1, c.at(p.o_vf), p.n2, (int)p.k, (int)p.F, dt, c.s));
-  HIPCHK(sigma_from_lambda(lam, c.at<double>(p.o_sig), c.at(p.o_scx), p.F * p.k, dt, c.s));
-  HIPCHK(fft_c2r(c.at(p.o_uf), p.n1 * p.k, U, p.n1 * p.k, (int)p.n3, dt, c.s));
-  HIPCHK(fft_c2r(c.at(p.o_vf), p.n2 * p.k, V, p.n2 * p.k, (int)p.n3, dt, c.s));
-  HIPCHK(fft_c2r(c.at(p.o_scx), p.k, S, p.k, (int)p.n3, dt, c.s));
+  {
+    Timed tm_(K_GEMM_LIFT, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(canon_phase(c.at(p.o_uf), p.n1, c.at(p.o_vf), p.n2, (int)p.k, (int)p.F, dt, c.s));
+  }
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(sigma_from_lambda(lam, c.at<double>(p.o_sig), c.at(p.o_scx), p.F * p.k, dt, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_uf), p.n1 * p.k, U, p.n1 * p.k, (int)p.n3, dt, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_vf), p.n2 * p.k, V, p.n2 * p.k, (int)p.n3, dt, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_scx), p.k, S, p.k, (int)p.n3, dt, c.s));
+  }
   return TSVD_OK;
 }
 
@@ -451,7 +550,10 @@ int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2, in
   if ((r = krylov(c, A, Omega))) return r;
   if ((r = svd_and_lift(c, U, S, V))) return r;
   // X_f = (U_f diag(sigma)) V_f^H, then the inverse DFT.
-  HIPCHK(scale_cols_by(c.at(p.o_uf), c.at<double>(p.o_sig), c.at(p.o_us), p.n1, (int)p.k, (int)p.F, p.dt, c.s));
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(scale_cols_by(c.at(p.o_uf), c.at<double>(p.o_sig), c.at(p.o_us), p.n1, (int)p.k, (int)p.F, p.dt, c.s));
+  }
   GemmDesc d = gd();
   d.A = c.at(p.o_us);
   d.lda = p.k;
@@ -471,8 +573,14 @@ int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2, in
   d.K = (int)p.k;
   d.batch = (int)p.F;
   d.compute = p.dt;
-  HIPCHK(zgemm(d, c.s));
-  HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, Xhat, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  {
+    Timed tm_(K_GEMM_LIFT, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, Xhat, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  }
   g_err.clear();
   return TSVD_OK;
 }
@@ -505,8 +613,14 @@ int tsvd_proj(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t 
   d.K = (int)p.m;
   d.batch = (int)p.F;
   d.compute = p.dt;
-  HIPCHK(zgemm(d, c.s));
-  HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, P, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  {
+    Timed tm_(K_GEMM_LIFT, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, P, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  }
   g_err.clear();
   return TSVD_OK;
 }
@@ -587,6 +701,46 @@ int tsvd_diag_zgemm(const void* A, int a_conj, const void* B, int b_conj, void* 
   d.beta = beta;
   d.compute = t;
   HIPCHK(zgemm(d, (hipStream_t)stream));
+  return TSVD_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int tsvd_diag_timing(int enable) {
+  std::lock_guard<std::mutex> l(g_timer.mu);
+  for (auto& pe : g_timer.pending) {
+    g_timer.pool.push_back(pe.second.first);
+    g_timer.pool.push_back(pe.second.second);
+  }
+  g_timer.pending.clear();
+  for (int i = 0; i < K_NCLASS; ++i) {
+    g_timer.ms[i] = 0;
+    g_timer.count[i] = 0;
+  }
+  g_timer.on = enable != 0;
+  return TSVD_OK;
+}
+
+int tsvd_diag_timing_read(double* ms_out, int64_t* count_out, int nclass) {
+  if (!ms_out || !count_out || nclass < 1) return fail(TSVD_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> l(g_timer.mu);
+  for (auto& pe : g_timer.pending) {
+    float ms = 0;
+    hipError_t e = hipEventSynchronize(pe.second.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, pe.second.first, pe.second.second);
+    if (e != hipSuccess) return fail(TSVD_EHIP, hipGetErrorString(e));
+    g_timer.ms[pe.first] += ms;
+    g_timer.count[pe.first] += 1;
+    g_timer.pool.push_back(pe.second.first);
+    g_timer.pool.push_back(pe.second.second);
+  }
+  g_timer.pending.clear();
+  for (int i = 0; i < nclass; ++i) {
+    ms_out[i] = i < K_NCLASS ? g_timer.ms[i] : 0.0;
+    count_out[i] = i < K_NCLASS ? g_timer.count[i] : 0;
+  }
   return TSVD_OK;
 }
 
