@@ -4,25 +4,45 @@
 // singular vectors of C_f are W, sigma = sqrt(lambda), and the right singular
 // vectors are C_f^H W diag(1/sigma).
 //
-// One 256-thread workgroup per Fourier slice:
-//  1. sum the split-K partials and symmetrise, G = (S + S^H) / 2;
-//  2. Householder reduction to a real symmetric tridiagonal matrix,
-//     G = H T H^H, H = H_0 ... H_{m-2}, H_j = I - tau_j v_j v_j^H
-//     (complex reflectors with real beta, so T is real);
-//  3. the k largest eigenvalues of T by bisection on Sturm counts (each
-//     thread one eigenvalue);
-//  4. their eigenvectors by inverse iteration on the pivoted LU of T - lambda I,
-//     re-orthogonalised within clusters of close eigenvalues;
-//  5. back-transformation W = H Z.
-// The matrix lives in global scratch (L2-resident at these sizes); vectors
-// and the tridiagonal live in LDS.
+// Four kernels, all batched over the Fourier slices:
+//  1. tridiag   one workgroup per slice: symmetrised sum of the split-K
+//               partials, then Householder reduction G = H T H^H,
+//               H = H_0 ... H_{m-2}, H_j = I - tau_j v_j v_j^H (complex
+//               reflectors with real beta, so T is real symmetric).  Each step
+//               touches the trailing matrix once: the rank-2 update of step s
+//               and the matrix-vector product of step s+1 share one pass.  The
+//               trailing matrix moves into LDS as soon as it fits.
+//  2. bisect    one wave per eigenvalue: 64-way multisection on Sturm counts
+//               of T for the k largest eigenvalues.
+//  3. invit     one wave per cluster of close eigenvalues: inverse iteration
+//               on the pivoted LU of T - lambda I (in LDS), members of a
+//               cluster re-orthogonalised against each other.
+//  4. backxf    W = H Z, several workgroups per slice, each owning 8 columns
+//               of W in LDS.
 #include "common.h"
 #include "kernels.h"
+
+#ifdef TSVD_PHASE_PROF
+__device__ unsigned long long g_phase[16];
+#define PHASE_T0() unsigned long long ph_t = clock64()
+#define PHASE(i)                                            \
+  do {                                                      \
+    if (blockIdx.x == 0 && threadIdx.x == 0) {              \
+      const unsigned long long now = clock64();             \
+      atomicAdd(&g_phase[i], now - ph_t);                   \
+      ph_t = now;                                           \
+    }                                                       \
+  } while (0)
+#else
+#define PHASE_T0()
+#define PHASE(i)
+#endif
 
 namespace tsvd {
 
 static inline size_t heig_per_slice(int m, int k) {
-  size_t b = (size_t)16 * m * m + (size_t)16 * m + (size_t)48 * k * m;
+  (void)k;
+  size_t b = (size_t)16 * m * m + (size_t)16 * m + (size_t)16 * m;
   return (b + 255) & ~(size_t)255;
 }
 size_t heig_scratch_bytes(int m, int k) { return heig_per_slice(m, k); }
@@ -35,17 +55,469 @@ __device__ __forceinline__ cx<double> cjmul(cx<double> a, cx<double> b) {
   return cx<double>{a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 
+struct HeigView {
+  cx<double>* A;  // m x m working matrix (global)
+  cx<double>* tau;
+  double* d;
+  double* e;
+};
+__device__ __forceinline__ HeigView heig_view(unsigned char* scratch, size_t per_slice, int f, int m) {
+  HeigView v;
+  v.A = reinterpret_cast<cx<double>*>(scratch + (size_t)f * per_slice);
+  v.tau = v.A + (size_t)m * m;
+  v.d = reinterpret_cast<double*>(v.tau + m);
+  v.e = v.d + m;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// 1. Householder tridiagonalisation
+// ---------------------------------------------------------------------------
+// View of the working matrix: element (r, c) at p[(r - off) * ld + (c - off)].
+// One instantiation per memory space keeps LDS accesses as LDS instructions.
+struct MatView {
+  cx<double>* p;
+  int ld, off;
+  __device__ __forceinline__ cx<double>* at(int r, int c) const { return p + (int64_t)(r - off) * ld + (c - off); }
+};
+
+struct TriShared {
+  double* red;  // 2 * (NT / 64) doubles
+  cx<double>* tau;
+  cx<double>* scale;
+  int* skip;
+  cx<double>* ppart;  // TRI_G x m partial sums of p
+};
+
+constexpr int TRI_NT = 512;  // threads per tridiagonalisation workgroup
+constexpr int TRI_G = 8;     // at most this many thread groups share one column
+
+// Block-wide sum of a complex value (one reduction for both parts).
+__device__ __forceinline__ cx<double> block_sum_cx(cx<double> v, double* red) {
+  v.re = wave_sum(v.re);
+  v.im = wave_sum(v.im);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * w] = v.re;
+    red[2 * w + 1] = v.im;
+  }
+  __syncthreads();
+  cx<double> r{0, 0};
+#pragma unroll
+  for (int i = 0; i < TRI_NT / 64; ++i) {
+    r.re += red[2 * i];
+    r.im += red[2 * i + 1];
+  }
+  return r;
+}
+
+// Reflector of step s from row s (the conjugate of column s below the
+// diagonal), given s2 = the squared norm of its entries after the first:
+// writes v (length m - s - 1, v[0] = 1) to `dst` and to row s of the global
+// matrix, and records d[s], e[s], tau[s].
+__device__ __forceinline__ void tri_reflector_from(const MatView& B, int s, int m, double s2, cx<double>* dst,
+                                                   const HeigView& hv, const TriShared& sh) {
+  const int tid = threadIdx.x;
+  const int L = m - s - 1;
+  const cx<double>* row = B.at(s, s + 1);
+  if (tid == 0) {
+    hv.d[s] = B.at(s, s)->re;
+    const double ar = row[0].re, ai = -row[0].im;
+    if (s2 == 0.0 && ai == 0.0) {
+      *sh.skip = 1;
+      hv.e[s] = ar;
+      *sh.tau = cx<double>{0, 0};
+    } else {
+      *sh.skip = 0;
+      const double beta = -copysign(sqrt(ar * ar + ai * ai + s2), ar);
+      *sh.tau = cx<double>{(beta - ar) / beta, -ai / beta};
+      const double dr = ar - beta, di = ai;
+      const double den = dr * dr + di * di;
+      *sh.scale = cx<double>{dr / den, -di / den};
+      hv.e[s] = beta;
+    }
+    hv.tau[s] = *sh.tau;
+  }
+  __syncthreads();
+  const bool skip = *sh.skip != 0;
+  const cx<double> scale = *sh.scale;
+  cx<double>* grow = hv.A + (int64_t)s * m + (s + 1);
+  for (int i = tid; i < L; i += TRI_NT) {
+    cx<double> v;
+    if (i == 0) {
+      v = cx<double>{1.0, 0.0};
+    } else if (skip) {
+      v = cx<double>{0.0, 0.0};
+    } else {
+      const cx<double> a = row[i];
+      v = cmulc(cx<double>{a.re, -a.im}, scale);
+    }
+    dst[i] = v;
+    grow[i] = v;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void tri_reflector(const MatView& B, int s, int m, cx<double>* dst, const HeigView& hv,
+                                              const TriShared& sh) {
+  const int L = m - s - 1;
+  const cx<double>* row = B.at(s, s + 1);
+  double s2 = 0;
+  for (int i = 1 + threadIdx.x; i < L; i += TRI_NT) {
+    const cx<double> a = row[i];
+    s2 += a.re * a.re + a.im * a.im;
+  }
+  s2 = block_sum_cx(cx<double>{s2, 0.0}, sh.red).re;
+  tri_reflector_from(B, s, m, s2, dst, hv, sh);
+}
+
+// (a) w_s = p_s - (tau_s / 2) (p_s^H v_s) v_s, in place over p_s.
+__device__ __forceinline__ void tri_w(int L, const cx<double>* vb, cx<double>* wb, const TriShared& sh) {
+  const int tid = threadIdx.x;
+  const cx<double> tau = *sh.tau;
+  cx<double> acc{0, 0};
+  for (int i = tid; i < L; i += TRI_NT) {
+    const cx<double> t = cjmul(wb[i], vb[i]);
+    acc.re += t.re;
+    acc.im += t.im;
+  }
+  acc = block_sum_cx(acc, sh.red);
+  const cx<double> a2 = cmulc(cx<double>{-0.5 * tau.re, -0.5 * tau.im}, acc);
+  const bool zero = (tau.re == 0.0 && tau.im == 0.0);
+  for (int i = tid; i < L; i += TRI_NT) {
+    if (zero) {
+      wb[i] = cx<double>{0, 0};
+    } else {
+      const cx<double> t = cmulc(a2, vb[i]);
+      wb[i].re += t.re;
+      wb[i].im += t.im;
+    }
+  }
+  __syncthreads();
+}
+
+// Last step (trailing size 1): d[m-1].
+__device__ __forceinline__ void tri_last(const MatView& B, int m, const cx<double>* vb, const cx<double>* wb,
+                                         const HeigView& hv) {
+  if (threadIdx.x == 0) {
+    const cx<double> v = vb[0], w = wb[0];
+    hv.d[m - 1] = B.at(m - 1, m - 1)->re - 2.0 * (v.re * w.re + v.im * w.im);
+    hv.e[m - 1] = 0.0;
+  }
+}
+
+// (c) row s+1 of the step-s update (and the norm for the next reflector),
+// (d) the reflector of step s+1, (e) the rest of the step-s update of
+// A[s+2:, s+2:] fused with p_{s+1} = tau_{s+1} A' v_{s+1}; the rows of each
+// column are split over up to TRI_G thread groups.
+__device__ __forceinline__ void tri_cde(const MatView& B, int s, int m, const cx<double>* vb, const cx<double>* wb,
+                                        cx<double>* vn, cx<double>* pn, const HeigView& hv, const TriShared& sh) {
+  const int tid = threadIdx.x;
+  const int L = m - s - 1;
+  double s2 = 0;
+  {
+    cx<double>* row = B.at(s + 1, s + 1);
+    const cx<double> v0 = vb[0], w0 = wb[0];
+    for (int c = tid; c < L; c += TRI_NT) {
+      const cx<double> vc = vb[c], wc = wb[c];
+      cx<double> a = row[c];
+      a.re -= (v0.re * wc.re + v0.im * wc.im) + (w0.re * vc.re + w0.im * vc.im);
+      a.im -= (v0.im * wc.re - v0.re * wc.im) + (w0.im * vc.re - w0.re * vc.im);
+      row[c] = a;
+      if (c >= 2) s2 += a.re * a.re + a.im * a.im;  // entries of row s+1 after its first off-diagonal
+    }
+  }
+  s2 = block_sum_cx(cx<double>{s2, 0.0}, sh.red).re;
+  tri_reflector_from(B, s + 1, m, s2, vn, hv, sh);
+  const int Ln = L - 1;
+  if (Ln <= 0) return;
+  const cx<double> taun = *sh.tau;
+  int G = TRI_NT / Ln;
+  if (G > TRI_G) G = TRI_G;
+  if (G < 1) G = 1;
+  constexpr int NB = 8;  // rows per batch; the next batch is loaded while this one is updated
+  const int64_t ld = B.ld;
+  for (int t = tid; t < G * Ln || (G == 1 && t < Ln); t += TRI_NT) {
+    const int g = G > 1 ? t / Ln : 0;
+    const int cc = G > 1 ? t - g * Ln : t;
+    const int c = s + 2 + cc;
+    const cx<double> vc = vb[cc + 1], wc = wb[cc + 1];
+    double ar = 0, ai = 0;
+    cx<double>* colp = B.at(s + 2, c);
+    auto upd = [&](cx<double> x, int r) {
+      const cx<double> vr = vb[r + 1], wr = wb[r + 1];
+      x.re -= (vr.re * wc.re + vr.im * wc.im) + (wr.re * vc.re + wr.im * vc.im);
+      x.im -= (vr.im * wc.re - vr.re * wc.im) + (wr.im * vc.re - wr.re * vc.im);
+      colp[(int64_t)r * ld] = x;
+      const cx<double> tt = cjmul(x, vn[r]);
+      ar += tt.re;
+      ai += tt.im;
+    };
+    // rows g, g + G, g + 2G, ... of this column
+    const int nrows = (Ln - g + G - 1) / G;
+    const int nfull = nrows / NB;
+    int q = 0;
+    if (nfull > 0) {
+      cx<double> a[NB];
+#pragma unroll
+      for (int u = 0; u < NB; ++u) a[u] = colp[(int64_t)(g + u * G) * ld];
+      for (int bt = 0; bt < nfull - 1; ++bt, q += NB) {
+        cx<double> an[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) an[u] = colp[(int64_t)(g + (q + NB + u) * G) * ld];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) upd(a[u], g + (q + u) * G);
+#pragma unroll
+        for (int u = 0; u < NB; ++u) a[u] = an[u];
+      }
+#pragma unroll
+      for (int u = 0; u < NB; ++u) upd(a[u], g + (q + u) * G);
+      q += NB;
+    }
+    for (; q < nrows; ++q) upd(colp[(int64_t)(g + q * G) * ld], g + q * G);
+    if (G > 1)
+      sh.ppart[g * m + cc] = cx<double>{ar, ai};
+    else
+      pn[cc] = cmulc(taun, cx<double>{ar, ai});
+  }
+  __syncthreads();
+  if (G > 1) {
+    for (int cc = tid; cc < Ln; cc += TRI_NT) {
+      cx<double> acc{0, 0};
+      for (int g = 0; g < G; ++g) {
+        acc.re += sh.ppart[g * m + cc].re;
+        acc.im += sh.ppart[g * m + cc].im;
+      }
+      pn[cc] = cmulc(taun, acc);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* __restrict__ Gpart, int nsum,
+                                                           int64_t part_stride, int m, unsigned char* scratch,
+                                                           size_t per_slice, int Lsw) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<double>* vbuf0 = reinterpret_cast<cx<double>*>(smem);
+  cx<double>* vbuf1 = vbuf0 + m;
+  cx<double>* wbuf0 = vbuf1 + m;
+  cx<double>* wbuf1 = wbuf0 + m;
+  cx<double>* ppart = wbuf1 + m;          // TRI_G x m partial sums
+  cx<double>* Tl = ppart + TRI_G * m;     // LDS copy of the trailing matrix
+  __shared__ double red[2 * (TRI_NT / 64)];
+  __shared__ cx<double> s_tau, s_scale;
+  __shared__ int s_skip;
+  const TriShared sh{red, &s_tau, &s_scale, &s_skip, ppart};
+  const int tid = threadIdx.x;
+  const int f = blockIdx.x;
+  const HeigView hv = heig_view(scratch, per_slice, f, m);
+  cx<double>* A = hv.A;
+  const cx<double>* G = Gpart + (int64_t)f * m * m;
+
+  // sum of the partials (partial index outermost: independent loads in flight)
+  const int mm = m * m;
+  for (int s = 0; s < nsum; ++s) {
+    const cx<double>* Gs = G + s * part_stride;
+#pragma unroll 8
+    for (int t = tid; t < mm; t += TRI_NT) {
+      const cx<double> g = Gs[t];
+      if (s == 0) {
+        A[t] = g;
+      } else {
+        cx<double> a = A[t];
+        a.re += g.re;
+        a.im += g.im;
+        A[t] = a;
+      }
+    }
+  }
+  __syncthreads();
+  // Hermitian average (upper triangle from the lower one, diagonal real)
+  for (int t = tid; t < mm; t += TRI_NT) {
+    const int i = t / m, c = t - (t / m) * m;
+    if (c > i) continue;
+    const cx<double> g = A[t], h = A[(int64_t)c * m + i];
+    const cx<double> lo{0.5 * (g.re + h.re), i == c ? 0.0 : 0.5 * (g.im - h.im)};
+    A[t] = lo;
+    A[(int64_t)c * m + i] = cx<double>{lo.re, -lo.im};
+  }
+  __syncthreads();
+  if (m == 1) {
+    if (tid == 0) {
+      hv.d[0] = A[0].re;
+      hv.e[0] = 0.0;
+      hv.tau[0] = cx<double>{0, 0};
+    }
+    return;
+  }
+  PHASE_T0();
+  const MatView Bg{A, m, 0};
+  int cur = 0;  // which of the two vector buffers holds v_s / p_s
+  auto vb = [&](int which) { return which ? vbuf1 : vbuf0; };
+  auto wb = [&](int which) { return which ? wbuf1 : wbuf0; };
+
+  // step 0: reflector and p_0 = tau_0 A[1:, 1:] v_0 (global)
+  tri_reflector(Bg, 0, m, vbuf0, hv, sh);
+  {
+    const int L = m - 1;
+    const cx<double> tau = s_tau;
+    for (int c = tid; c < L; c += TRI_NT) {
+      double ar = 0, ai = 0;
+#pragma unroll 4
+      for (int r = 0; r < L; ++r) {
+        const cx<double> t = cjmul(*Bg.at(r + 1, c + 1), vbuf0[r]);
+        ar += t.re;
+        ai += t.im;
+      }
+      wbuf0[c] = cmulc(tau, cx<double>{ar, ai});
+    }
+    __syncthreads();
+  }
+  PHASE(0);
+  // global phase
+  int s = 0;
+  bool done = false;
+  for (; s < m - 1; ++s) {
+    const int L = m - s - 1;
+    tri_w(L, vb(cur), wb(cur), sh);
+    PHASE(1);
+    if (s == m - 2) {
+      tri_last(Bg, m, vb(cur), wb(cur), hv);
+      done = true;
+      break;
+    }
+    if (L <= Lsw) break;
+    tri_cde(Bg, s, m, vb(cur), wb(cur), vb(cur ^ 1), wb(cur ^ 1), hv, sh);
+    PHASE(2);
+    cur ^= 1;
+  }
+  if (done) return;
+  // LDS phase: the trailing matrix A[s+1:, s+1:] (w_s already formed)
+  const int L0 = m - s - 1;
+  for (int r = tid / 32; r < L0; r += TRI_NT / 32)
+    for (int c = tid % 32; c < L0; c += 32) Tl[r * L0 + c] = A[(int64_t)(s + 1 + r) * m + (s + 1 + c)];
+  __syncthreads();
+  const MatView Bl{Tl, L0, s + 1};
+  PHASE(3);
+  tri_cde(Bl, s, m, vb(cur), wb(cur), vb(cur ^ 1), wb(cur ^ 1), hv, sh);
+  cur ^= 1;
+  for (++s; s < m - 1; ++s) {
+    const int L = m - s - 1;
+    tri_w(L, vb(cur), wb(cur), sh);
+    PHASE(4);
+    if (s == m - 2) {
+      tri_last(Bl, m, vb(cur), wb(cur), hv);
+      break;
+    }
+    tri_cde(Bl, s, m, vb(cur), wb(cur), vb(cur ^ 1), wb(cur ^ 1), hv, sh);
+    PHASE(5);
+    cur ^= 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2. eigenvalues by multisection (one wave per eigenvalue)
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ int sturm_count(const double* d, const double* e2, int m, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0;
   for (int i = 1; i < m; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
+    // e2 / q with the hardware reciprocal refined by one Newton step (a
+    // relative perturbation of e2 at rounding level: the count stays the
+    // exact count of a nearby tridiagonal matrix)
+    double r = __builtin_amdgcn_rcp(q);
+    r = r * fma(-q, r, 2.0);
+    q = (d[i] - x) - e2[i - 1] * r;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0;
   }
   return cnt;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Gershgorin interval of T (widened), pivmin and ||T|| for one wave.
+__device__ void tri_bounds(const double* d, const double* e, int m, double* gl, double* gu, double* pivmin,
+                           double* tnorm) {
+  const int lane = threadIdx.x & 63;
+  double lo = 1e300, hi = -1e300, em = 0;
+  for (int i = lane; i < m; i += 64) {
+    const double r = fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0);
+    lo = fmin(lo, d[i] - r);
+    hi = fmax(hi, d[i] + r);
+    em = fmax(em, e[i] * e[i]);
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  em = wave_max(em);
+  const double eps = 2.220446049250313e-16;
+  const double tn = fmax(fabs(lo), fabs(hi));
+  *pivmin = 2.2250738585072014e-308 * fmax(1.0, em);
+  *tnorm = tn;
+  *gl = lo - 2.0 * eps * tn * m - 2.0 * (*pivmin);
+  *gu = hi + 2.0 * eps * tn * m + 2.0 * (*pivmin);
+}
+
+__global__ __launch_bounds__(256) void heig_bisect_kernel(int m, int k, unsigned char* scratch, size_t per_slice,
+                                                          double* __restrict__ lambda_out, int* info) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* d = reinterpret_cast<double*>(smem);
+  double* e = d + m;
+  double* e2 = e + m;
+  const int f = blockIdx.x;
+  HeigView hv = heig_view(scratch, per_slice, f, m);
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    d[i] = hv.d[i];
+    e[i] = hv.e[i];
+    e2[i] = hv.e[i] * hv.e[i];
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = blockIdx.y * (blockDim.x >> 6) + wave;
+  if (t >= k) return;
+  double lo, hi, pivmin, tnorm;
+  tri_bounds(d, e, m, &lo, &hi, &pivmin, &tnorm);
+  const int idx = m - 1 - t;
+  const double eps = 2.220446049250313e-16;
+  for (int it = 0; it < 64; ++it) {
+    if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin) break;
+    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+    const int cnt = sturm_count(d, e2, m, x, pivmin);
+    const unsigned long long above = __ballot(cnt > idx);  // lanes whose point lies above lambda_idx
+    const int p = above ? __ffsll((long long)above) - 1 : 64;  // first such lane
+    const double xp = __shfl(x, p < 64 ? p : 63, 64);
+    const double xm = __shfl(x, p > 0 ? p - 1 : 0, 64);
+    const double nlo = p > 0 ? xm : lo;
+    const double nhi = p < 64 ? xp : hi;
+    if (nlo == lo && nhi == hi) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) {
+    const double lv = 0.5 * (lo + hi);
+    lambda_out[(int64_t)f * k + t] = lv;
+    if (!isfinite(lv)) atomicAdd(&info[INFO_NONFINITE], 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3. eigenvectors of T by inverse iteration (one wave per cluster)
+// ---------------------------------------------------------------------------
+// Order LDS traffic between the lanes of one wave (the wave runs in lockstep;
+// this keeps the compiler from moving LDS accesses across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ double hash_uniform(uint32_t a, uint32_t b) {
@@ -58,239 +530,43 @@ __device__ __forceinline__ double hash_uniform(uint32_t a, uint32_t b) {
   return (double)h * (2.0 / 4294967296.0) - 1.0;
 }
 
-__global__ __launch_bounds__(256) void heig_kernel(const cx<double>* __restrict__ Gpart, int nsum, int64_t part_stride,
-                                                   int m, int k, double* __restrict__ lambda_out,
-                                                   cx<double>* __restrict__ Wout, unsigned char* scratch,
-                                                   size_t per_slice, int* info) {
+__global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned char* scratch, size_t per_slice,
+                                                         const double* __restrict__ lambda,
+                                                         cx<double>* __restrict__ Wout, int* info) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* d = reinterpret_cast<double*>(smem);
   double* e = d + m;
-  double* e2 = e + m;
-  cx<double>* v = reinterpret_cast<cx<double>*>(e2 + m);
-  cx<double>* p = v + m;
-  int* rank = reinterpret_cast<int*>(p + m);
-  int* cstart = rank + k;
-  __shared__ double red[8];
-  __shared__ cx<double> s_tau, s_scale;
-  __shared__ int s_skip, s_maxrank;
-  __shared__ double s_gl, s_gu, s_pivmin, s_tnorm;
-
   const int f = blockIdx.x;
-  const int tid = threadIdx.x;
-  cx<double>* A = reinterpret_cast<cx<double>*>(scratch + (size_t)f * per_slice);
-  cx<double>* tau_g = A + (size_t)m * m;
-  double* lu = reinterpret_cast<double*>(tau_g + m);
-  const cx<double>* G = Gpart + (int64_t)f * m * m;
-  double* lam = lambda_out + (int64_t)f * k;
+  const int nw = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* wsp = e + m + (size_t)wave * 6 * m;
+  double* mult = wsp;
+  double* swp = mult + m;
+  double* u0 = swp + m;
+  double* u1 = u0 + m;
+  double* u2 = u1 + m;
+  double* z = u2 + m;
+  HeigView hv = heig_view(scratch, per_slice, f, m);
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    d[i] = hv.d[i];
+    e[i] = hv.e[i];
+  }
+  __syncthreads();
+  const int t0 = blockIdx.y * nw + wave;
+  if (t0 >= k) return;
+  const double* lam = lambda + (int64_t)f * k;
   cx<double>* W = Wout + (int64_t)f * m * k;
-
-  // 1. symmetrised sum of the partials
-  for (int64_t t = tid; t < (int64_t)m * m; t += 256) {
-    const int i = (int)(t / m), c = (int)(t % m);
-    double re = 0, im = 0, re2 = 0, im2 = 0;
-    for (int s = 0; s < nsum; ++s) {
-      const cx<double> g = G[s * part_stride + (int64_t)i * m + c];
-      const cx<double> h = G[s * part_stride + (int64_t)c * m + i];
-      re += g.re;
-      im += g.im;
-      re2 += h.re;
-      im2 += h.im;
-    }
-    A[t] = cx<double>{0.5 * (re + re2), i == c ? 0.0 : 0.5 * (im - im2)};
-  }
-  __syncthreads();
-
-  // 2. Householder tridiagonalisation (lower form; row j keeps v_j afterwards).
-  for (int j = 0; j < m - 1; ++j) {
-    const int L = m - j - 1;
-    cx<double>* rowj = A + (int64_t)j * m + (j + 1);  // conj of column j below the diagonal
-    double s2 = 0;
-    for (int r = 1 + tid; r < L; r += 256) {
-      const cx<double> a = rowj[r];
-      s2 += a.re * a.re + a.im * a.im;
-    }
-    s2 = block_sum<256>(s2, red);
-    if (tid == 0) {
-      d[j] = A[(int64_t)j * m + j].re;
-      const double ar = rowj[0].re, ai = -rowj[0].im;  // alpha = conj(row entry)
-      if (s2 == 0.0 && ai == 0.0) {
-        s_skip = 1;
-        e[j] = ar;
-        s_tau = cx<double>{0, 0};
-      } else {
-        s_skip = 0;
-        const double beta = -copysign(sqrt(ar * ar + ai * ai + s2), ar);
-        s_tau = cx<double>{(beta - ar) / beta, -ai / beta};
-        // scale = 1 / (alpha - beta)
-        const double dr = ar - beta, di = ai;
-        const double den = dr * dr + di * di;
-        s_scale = cx<double>{dr / den, -di / den};
-        e[j] = beta;
-      }
-      tau_g[j] = s_tau;
-    }
-    __syncthreads();
-    if (s_skip) {
-      for (int r = tid; r < L; r += 256) rowj[r] = cx<double>{r == 0 ? 1.0 : 0.0, 0.0};
-      __syncthreads();
-      continue;
-    }
-    const cx<double> tau = s_tau, scale = s_scale;
-    for (int r = tid; r < L; r += 256) {
-      cx<double> vr;
-      if (r == 0) {
-        vr = cx<double>{1.0, 0.0};
-      } else {
-        const cx<double> a = rowj[r];
-        vr = cmulc(cx<double>{a.re, -a.im}, scale);
-      }
-      v[r] = vr;
-      rowj[r] = vr;
-    }
-    __syncthreads();
-    // p = tau * A22 v, with A22[c][r] = conj(A22[r][c]) (coalesced row reads)
-    cx<double>* A22 = A + (int64_t)(j + 1) * m + (j + 1);
-    for (int c = tid; c < L; c += 256) {
-      double ar = 0, ai = 0;
-      for (int r = 0; r < L; ++r) {
-        const cx<double> a = A22[(int64_t)r * m + c];
-        const cx<double> t = cjmul(a, v[r]);
-        ar += t.re;
-        ai += t.im;
-      }
-      p[c] = cmulc(tau, cx<double>{ar, ai});
-    }
-    __syncthreads();
-    double pr = 0, pi = 0;
-    for (int c = tid; c < L; c += 256) {
-      const cx<double> t = cjmul(p[c], v[c]);
-      pr += t.re;
-      pi += t.im;
-    }
-    pr = block_sum<256>(pr, red);
-    pi = block_sum<256>(pi, red + 4);
-    const cx<double> alpha2 = cmulc(cx<double>{-0.5 * tau.re, -0.5 * tau.im}, cx<double>{pr, pi});
-    for (int c = tid; c < L; c += 256) {
-      const cx<double> t = cmulc(alpha2, v[c]);
-      p[c].re += t.re;
-      p[c].im += t.im;
-    }
-    __syncthreads();
-    // A22 -= v w^H + w v^H
-    for (int r = 0; r < L; ++r) {
-      const cx<double> vr = v[r], wr = p[r];
-      cx<double>* row = A22 + (int64_t)r * m;
-      for (int c = tid; c < L; c += 256) {
-        const cx<double> wc = p[c], vc = v[c];
-        cx<double> a = row[c];
-        // v_r conj(w_c) + w_r conj(v_c)
-        a.re -= (vr.re * wc.re + vr.im * wc.im) + (wr.re * vc.re + wr.im * vc.im);
-        a.im -= (vr.im * wc.re - vr.re * wc.im) + (wr.im * vc.re - wr.re * vc.im);
-        row[c] = a;
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    d[m - 1] = A[(int64_t)(m - 1) * m + (m - 1)].re;
-    e[m - 1] = 0.0;
-  }
-  __syncthreads();
-  for (int i = tid; i < m; i += 256) e2[i] = e[i] * e[i];
-  __syncthreads();
-
-  // 3. Gershgorin interval and bisection for the k largest eigenvalues.
-  __syncthreads();
-  double lo = 1e300, hi = -1e300, emax = 0;
-  for (int i = tid; i < m; i += 256) {
-    const double r = fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0);
-    lo = fmin(lo, d[i] - r);
-    hi = fmax(hi, d[i] + r);
-    emax = fmax(emax, e2[i]);
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, off, 64));
-    hi = fmax(hi, __shfl_xor(hi, off, 64));
-    emax = fmax(emax, __shfl_xor(emax, off, 64));
-  }
-  if ((tid & 63) == 0) {
-    red[tid >> 6] = lo;
-    red[4 + (tid >> 6)] = hi;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double l = red[0], h = red[4];
-    for (int w = 1; w < 4; ++w) {
-      l = fmin(l, red[w]);
-      h = fmax(h, red[4 + w]);
-    }
-    s_gl = l;
-    s_gu = h;
-  }
-  __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = emax;
-  __syncthreads();
-  if (tid == 0) {
-    const double em = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    const double eps0 = 2.220446049250313e-16;
-    const double tnorm = fmax(fabs(s_gl), fabs(s_gu));
-    s_pivmin = 2.2250738585072014e-308 * fmax(1.0, em);
-    s_tnorm = tnorm;
-    s_gl -= 2.0 * eps0 * tnorm * m + 2.0 * s_pivmin;
-    s_gu += 2.0 * eps0 * tnorm * m + 2.0 * s_pivmin;
-  }
-  __syncthreads();
+  double gl, gu, pivmin, tnorm;
+  tri_bounds(d, e, m, &gl, &gu, &pivmin, &tnorm);
   const double eps = 2.220446049250313e-16;
-  const double pivmin = s_pivmin, tnorm = s_tnorm;
-  for (int t = tid; t < k; t += 256) {
-    const int idx = m - 1 - t;
-    double a = s_gl, b = s_gu;
-    for (int it = 0; it < 256; ++it) {
-      if (b - a <= 2.0 * eps * fmax(fabs(a), fabs(b)) + 4.0 * pivmin) break;
-      const double mid = 0.5 * (a + b);
-      if (mid <= a || mid >= b) break;
-      if (sturm_count(d, e2, m, mid, pivmin) <= idx)
-        a = mid;
-      else
-        b = mid;
-    }
-    const double lv = 0.5 * (a + b);
-    lam[t] = lv;
-    if (!isfinite(lv)) atomicAdd(&info[INFO_NONFINITE], 1);
-  }
-  __syncthreads();
-
-  // 4. clusters (descending order) and inverse iteration.
-  if (tid == 0) {
-    const double ortol = 1e-7 * tnorm;
-    int mr = 0;
-    int start = 0, r = 0;
-    for (int t = 0; t < k; ++t) {
-      if (t > 0 && lam[t - 1] - lam[t] < ortol) {
-        ++r;
-      } else {
-        start = t;
-        r = 0;
-      }
-      rank[t] = r;
-      cstart[t] = start;
-      mr = r > mr ? r : mr;
-    }
-    s_maxrank = mr;
-  }
-  __syncthreads();
-  for (int round = 0; round <= s_maxrank; ++round) {
-    for (int t = tid; t < k; t += 256) {
-      if (rank[t] != round) continue;
-      double* mult = lu + (size_t)t * 6 * m;
-      double* swp = mult + m;
-      double* u0 = swp + m;
-      double* u1 = u0 + m;
-      double* u2 = u1 + m;
-      double* z = u2 + m;
-      const double lv = lam[t];
-      const double tinyp = eps * fmax(tnorm, 1e-300);
-      // pivoted LU of T - lambda I
+  const double ortol = 1e-7 * tnorm;
+  if (t0 > 0 && lam[t0 - 1] - lam[t0] < ortol) return;  // not the head of its cluster
+  int t1 = t0 + 1;
+  while (t1 < k && lam[t1 - 1] - lam[t1] < ortol) ++t1;
+  const double tinyp = eps * fmax(tnorm, 1e-300);
+  for (int t = t0; t < t1; ++t) {
+    const double lv = lam[t];
+    if (lane == 0) {
       double pc = d[0] - lv, qc = (m > 1) ? e[0] : 0.0, rc = 0.0;
       for (int i = 0; i < m - 1; ++i) {
         const double ei = e[i];
@@ -326,85 +602,129 @@ __global__ __launch_bounds__(256) void heig_kernel(const cx<double>* __restrict_
       u0[m - 1] = pc;
       u1[m - 1] = 0.0;
       u2[m - 1] = 0.0;
-      // start vector
-      double nrm = 0;
-      for (int i = 0; i < m; ++i) {
-        z[i] = hash_uniform((uint32_t)t, (uint32_t)i);
-        nrm += z[i] * z[i];
-      }
-      nrm = 1.0 / sqrt(nrm);
-      for (int i = 0; i < m; ++i) z[i] *= nrm;
-      for (int it = 0; it < 5; ++it) {
-        // forward: apply the row operations
+      for (int i = 0; i < m; ++i) u0[i] = 1.0 / u0[i];  // the solves multiply by the reciprocal pivots
+    }
+    for (int i = lane; i < m; i += 64) z[i] = hash_uniform((uint32_t)t, (uint32_t)i);
+    wave_sync();
+    for (int it = 0; it < 4; ++it) {
+      if (lane == 0) {
+        double zc = z[0];
         for (int i = 0; i < m - 1; ++i) {
+          double zn = z[i + 1];
           if (swp[i] != 0.0) {
-            const double tmp = z[i];
-            z[i] = z[i + 1];
-            z[i + 1] = tmp;
+            const double tmp = zc;
+            zc = zn;
+            zn = tmp;
           }
-          z[i + 1] -= mult[i] * z[i];
+          z[i] = zc;
+          zc = zn - mult[i] * zc;
         }
-        // back substitution with the three upper diagonals
+        z[m - 1] = zc;
+        double z1 = 0.0, z2 = 0.0;
         for (int i = m - 1; i >= 0; --i) {
-          double s = z[i];
-          if (i + 1 < m) s -= u1[i] * z[i + 1];
-          if (i + 2 < m) s -= u2[i] * z[i + 2];
-          z[i] = s / u0[i];
+          const double v = (z[i] - u1[i] * z1 - u2[i] * z2) * u0[i];
+          z[i] = v;
+          z2 = z1;
+          z1 = v;
         }
-        // re-orthogonalise against earlier members of the cluster
-        for (int t2 = cstart[t]; t2 < t; ++t2) {
-          const double* z2 = lu + (size_t)t2 * 6 * m + 5 * (size_t)m;
-          double c = 0;
-          for (int i = 0; i < m; ++i) c += z[i] * z2[i];
-          for (int i = 0; i < m; ++i) z[i] -= c * z2[i];
-        }
-        nrm = 0;
-        for (int i = 0; i < m; ++i) nrm += z[i] * z[i];
-        nrm = (nrm > 0) ? 1.0 / sqrt(nrm) : 0.0;
-        for (int i = 0; i < m; ++i) z[i] *= nrm;
       }
-      // residual check ||(T - lambda) z||_inf
-      double res = 0;
-      for (int i = 0; i < m; ++i) {
-        double y = (d[i] - lv) * z[i];
-        if (i > 0) y += e[i - 1] * z[i - 1];
-        if (i + 1 < m) y += e[i] * z[i + 1];
-        res = fmax(res, fabs(y));
+      wave_sync();
+      // re-orthogonalise against the earlier members of the cluster
+      for (int t2 = t0; t2 < t; ++t2) {
+        double c = 0;
+        for (int i = lane; i < m; i += 64) c += z[i] * W[(int64_t)i * k + t2].re;
+        c = wave_sum(c);
+        for (int i = lane; i < m; i += 64) z[i] -= c * W[(int64_t)i * k + t2].re;
       }
-      if (!(res <= 1e3 * m * eps * fmax(tnorm, 1e-300))) atomicAdd(&info[INFO_EIG_NOCONV], 1);
-      for (int i = 0; i < m; ++i) W[(int64_t)i * k + t] = cx<double>{z[i], 0.0};
+      double nrm = 0;
+      for (int i = lane; i < m; i += 64) nrm += z[i] * z[i];
+      nrm = wave_sum(nrm);
+      nrm = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
+      for (int i = lane; i < m; i += 64) z[i] *= nrm;
+      wave_sync();
+    }
+    double res = 0;
+    for (int i = lane; i < m; i += 64) {
+      double y = (d[i] - lv) * z[i];
+      if (i > 0) y += e[i - 1] * z[i - 1];
+      if (i + 1 < m) y += e[i] * z[i + 1];
+      res = fmax(res, fabs(y));
+    }
+    res = wave_max(res);
+    if (lane == 0 && !(res <= 1e3 * m * eps * fmax(tnorm, 1e-300))) atomicAdd(&info[INFO_EIG_NOCONV], 1);
+    for (int i = lane; i < m; i += 64) W[(int64_t)i * k + t] = cx<double>{z[i], 0.0};
+    __threadfence();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4. back-transformation W = H_0 ... H_{m-2} Z (8 columns per workgroup)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void heig_backxf_kernel(int m, int k, unsigned char* scratch, size_t per_slice,
+                                                          cx<double>* __restrict__ Wout) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NC = 8;
+  cx<double>* Wl = reinterpret_cast<cx<double>*>(smem);  // m x NC
+  cx<double>* vl = Wl + (size_t)m * NC;                   // m
+  __shared__ cx<double> sc[NC];
+  const int f = blockIdx.x;
+  const int c0 = blockIdx.y * NC;
+  const int tid = threadIdx.x;
+  HeigView hv = heig_view(scratch, per_slice, f, m);
+  cx<double>* W = Wout + (int64_t)f * m * k;
+  for (int idx = tid; idx < m * NC; idx += 256) {
+    const int r = idx / NC, g = idx % NC;
+    Wl[idx] = (c0 + g < k) ? W[(int64_t)r * k + c0 + g] : cx<double>{0, 0};
+  }
+  __syncthreads();
+  const int g = tid >> 5, l32 = tid & 31;
+  constexpr int PF = 4;  // v elements per thread held in registers (m <= 1024)
+  cx<double> nxt[PF];
+  auto fetch = [&](int j) {
+    const int L = m - j - 1;
+    const cx<double>* vg = hv.A + (int64_t)j * m + (j + 1);
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int i = tid + u * 256;
+      nxt[u] = i < L ? vg[i] : cx<double>{0, 0};
+    }
+  };
+  if (m >= 2) fetch(m - 2);
+  for (int j = m - 2; j >= 0; --j) {
+    const cx<double> tau = hv.tau[j];
+    const int L = m - j - 1;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int i = tid + u * 256;
+      if (i < L) vl[i] = nxt[u];
+    }
+    if (j > 0) fetch(j - 1);
+    if (tau.re == 0.0 && tau.im == 0.0) continue;
+    __syncthreads();
+    double sr = 0, si = 0;
+    for (int i = l32; i < L; i += 32) {
+      const cx<double> t = cjmul(vl[i], Wl[(j + 1 + i) * NC + g]);
+      sr += t.re;
+      si += t.im;
+    }
+    for (int o = 16; o > 0; o >>= 1) {
+      sr += __shfl_xor(sr, o, 64);
+      si += __shfl_xor(si, o, 64);
+    }
+    if (l32 == 0) sc[g] = cmulc(tau, cx<double>{sr, si});
+    __syncthreads();
+    for (int idx = tid; idx < L * NC; idx += 256) {
+      const int i = idx / NC, gg = idx % NC;
+      const cx<double> t = cmulc(vl[i], sc[gg]);
+      cx<double>& w = Wl[(j + 1 + i) * NC + gg];
+      w.re -= t.re;
+      w.im -= t.im;
     }
     __syncthreads();
   }
-
-  // 5. back-transformation W = H_0 ... H_{m-2} Z
-  for (int j = m - 2; j >= 0; --j) {
-    const cx<double> tau = tau_g[j];
-    if (tau.re == 0.0 && tau.im == 0.0) continue;
-    const int L = m - j - 1;
-    const cx<double>* vj = A + (int64_t)j * m + (j + 1);
-    for (int r = tid; r < L; r += 256) v[r] = vj[r];
-    __syncthreads();
-    cx<double>* Wj = W + (int64_t)(j + 1) * k;
-    for (int c = tid; c < k; c += 256) {
-      double sr = 0, si = 0;
-      for (int r = 0; r < L; ++r) {
-        const cx<double> t = cjmul(v[r], Wj[(int64_t)r * k + c]);
-        sr += t.re;
-        si += t.im;
-      }
-      p[c] = cmulc(tau, cx<double>{sr, si});
-    }
-    __syncthreads();
-    for (int64_t idx = tid; idx < (int64_t)L * k; idx += 256) {
-      const int r = (int)(idx / k), c = (int)(idx % k);
-      const cx<double> t = cmulc(v[r], p[c]);
-      cx<double> w = Wj[idx];
-      w.re -= t.re;
-      w.im -= t.im;
-      Wj[idx] = w;
-    }
-    __syncthreads();
+  for (int idx = tid; idx < m * NC; idx += 256) {
+    const int r = idx / NC, gg = idx % NC;
+    if (c0 + gg < k) W[(int64_t)r * k + c0 + gg] = Wl[idx];
   }
 }
 
@@ -412,14 +732,49 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
                      double* W, void* scratch, int* info, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   if (m > 1024 || k > m || k < 1) return hipErrorInvalidValue;
-  const size_t sm = (size_t)7 * m * sizeof(double) + (size_t)2 * k * sizeof(int);
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)heig_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    // dynamic LDS limits, leaving room for each kernel's static LDS
+    (void)hipFuncSetAttribute((const void*)heig_tridiag_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              152 * 1024);
+    (void)hipFuncSetAttribute((const void*)heig_invit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              152 * 1024);
+    (void)hipFuncSetAttribute((const void*)heig_backxf_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              152 * 1024);
+    (void)hipGetLastError();
     attr_set = true;
   }
-  hipLaunchKernelGGL(heig_kernel, dim3(batch), dim3(256), sm, s, (const cx<double>*)Gpart, nsum, part_stride, m, k,
-                     lambda, (cx<double>*)W, (unsigned char*)scratch, heig_per_slice(m, k), info);
+  const size_t per = heig_per_slice(m, k);
+  unsigned char* sc = (unsigned char*)scratch;
+  // 1. tridiagonalisation: vectors (4 m) + trailing matrix in LDS (Lsw^2)
+  const size_t lds_total = 150 * 1024;
+  const size_t vec_bytes = (size_t)(4 + TRI_G) * m * sizeof(cx<double>);
+  int Lsw = 0;
+  if (lds_total > vec_bytes) {
+    Lsw = (int)sqrt((double)(lds_total - vec_bytes) / sizeof(cx<double>));
+    if (Lsw > m - 1) Lsw = m - 1;
+  }
+  const size_t sm1 = vec_bytes + (size_t)Lsw * Lsw * sizeof(cx<double>);
+  hipLaunchKernelGGL(heig_tridiag_kernel, dim3(batch), dim3(TRI_NT), sm1, s, (const cx<double>*)Gpart, nsum,
+                     part_stride, m, sc, per, Lsw);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // 2. eigenvalues: 4 waves (eigenvalues) per workgroup
+  hipLaunchKernelGGL(heig_bisect_kernel, dim3(batch, (k + 3) / 4), dim3(256), (size_t)3 * m * sizeof(double), s, m,
+                     k, sc, per, lambda, info);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 3. eigenvectors: per-wave LU workspace of 6 m doubles in LDS
+  int nw = (int)((140 * 1024 - 16 * (size_t)m) / (48 * (size_t)m));
+  if (nw > 4) nw = 4;
+  if (nw < 1) nw = 1;
+  const size_t sm3 = (size_t)2 * m * sizeof(double) + (size_t)nw * 6 * m * sizeof(double);
+  hipLaunchKernelGGL(heig_invit_kernel, dim3(batch, (k + nw - 1) / nw), dim3(64 * nw), sm3, s, m, k, sc, per,
+                     lambda, (cx<double>*)W, info);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // 4. back-transformation
+  const size_t sm4 = ((size_t)m * 8 + m) * sizeof(cx<double>);
+  hipLaunchKernelGGL(heig_backxf_kernel, dim3(batch, (k + 7) / 8), dim3(256), sm4, s, m, k, sc, per,
+                     (cx<double>*)W);
   return hipGetLastError();
 }
 

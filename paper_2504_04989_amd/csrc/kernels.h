@@ -40,7 +40,7 @@ hipError_t fft_c2r(const void* Xb, int64_t slice_stride, void* X, int64_t ntubes
 // of its shifted Cholesky factor R (G + shift_coef * trace(G) I = R^H R),
 // upper triangular, FP64, b x b row-major per slice.  gscratch: b(b+1)/2
 // complex doubles per slice, used when !chol_uses_lds(b).
-inline bool chol_uses_lds(int64_t b) { return b * (b + 1) / 2 * 16 <= 46 * 1024; }
+inline bool chol_uses_lds(int64_t b) { return b * (b + 1) / 2 * 16 <= 120 * 1024; }
 hipError_t chol_inv_ex(const double* Gpart, int nsum, int64_t part_stride, double* Rinv, void* gscratch, int b,
                        int batch, double shift_coef, int* info, hipStream_t s);
 

@@ -51,7 +51,7 @@ struct Plan {
 };
 
 int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
-  int64_t ns = (K + 255) / 256;
+  int64_t ns = (K + 127) / 128;
   int64_t cap = std::max<int64_t>(1, 1024 / std::max<int64_t>(1, tiles * batch));
   ns = std::min(ns, cap);
   if (ns < 1) ns = 1;
