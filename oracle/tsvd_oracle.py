@@ -505,7 +505,7 @@ def _proj_slice_adjoint(Af, Of, Yb, q):
     Q = np.concatenate(Qs, axis=1)
     b = Q0.shape[1]
     Abar = Q @ (Q.conj().T @ Yb)
-    Qbar_all = (Yb @ A.conj().T + A @ Yb.conj().T) @ Q
+    Qbar_all = Yb @ (A.conj().T @ Q) + A @ (Yb.conj().T @ Q)   # (Yb A^H + A Yb^H) Q
     Qbar = [Qbar_all[:, i * b:(i + 1) * b].copy() for i in range(q + 1)]
     for i in range(q, 0, -1):
         Qi, Ri = Qs[i], Rs[i]

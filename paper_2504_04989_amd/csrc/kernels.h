@@ -41,8 +41,10 @@ hipError_t fft_c2r(const void* Xb, int64_t slice_stride, void* X, int64_t ntubes
 // upper triangular, FP64, b x b row-major per slice.  gscratch: b(b+1)/2
 // complex doubles per slice, used when !chol_uses_lds(b).
 inline bool chol_uses_lds(int64_t b) { return b * (b + 1) / 2 * 16 <= 120 * 1024; }
+// mode 1: the partials sum to an upper triangular R instead; the kernel only
+// inverts it (Rinv = R^{-1}).
 hipError_t chol_inv_ex(const double* Gpart, int nsum, int64_t part_stride, double* Rinv, void* gscratch, int b,
-                       int batch, double shift_coef, int* info, hipStream_t s);
+                       int batch, double shift_coef, int* info, hipStream_t s, int mode = 0);
 
 // Per-slice m x m Hermitian PSD matrix (sum of nsum FP64 partials): top-k
 // eigenpairs.  lambda (batch x k, descending), W (batch x m x k complex FP64).

@@ -47,7 +47,7 @@ struct Plan {
   int nsplit_g, kchunk_g;       // split-K for G = T^H T (K = n2)
   // workspace offsets (bytes)
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
-      o_uf, o_vf, o_scx, o_us, total;
+      o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, total;
 };
 
 int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
@@ -79,7 +79,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
     return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
   if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32)
     return fail(TSVD_EINVAL, "precision mode not supported by this build");
-  if (op < TSVD_OP_RBK || op > TSVD_OP_PROJ) return fail(TSVD_EINVAL, "unsupported operation");
+  if (op < TSVD_OP_RBK || op > TSVD_OP_PROJ_BWD) return fail(TSVD_EINVAL, "unsupported operation");
   p->n1 = n1;
   p->n2 = n2;
   p->n3 = n3;
@@ -126,6 +126,15 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_vf = take(need_svd ? (size_t)F * n2 * k * cs : 0);
   p->o_scx = take(need_svd ? (size_t)F * k * cs : 0);
   p->o_us = take(op == TSVD_OP_APPROX ? (size_t)F * n1 * k * cs : 0);
+  const bool bwd = op == TSVD_OP_PROJ_BWD;
+  p->o_gbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
+  p->o_dbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
+  p->o_wraw = take(bwd ? (size_t)F * n1 * m * cs : 0);
+  p->o_qbar = take(bwd ? (size_t)F * n1 * m * cs : 0);
+  p->o_u2 = take(bwd ? (size_t)F * n2 * m * cs : 0);
+  p->o_zbar = take(bwd ? (size_t)F * n1 * b * cs : 0);
+  p->o_wbar = take(bwd ? (size_t)F * n1 * b * cs : 0);
+  p->o_tbar = take(bwd ? (size_t)F * n2 * b * cs : 0);
   p->total = o;
   return TSVD_OK;
 }
@@ -395,7 +404,15 @@ int big_AhY(const Ctx& c, const void* Y, int64_t ldy, int64_t strideY, void* Out
 }
 
 // Everything up to Q and T = C^H.
-int krylov(const Ctx& c, const void* A, const void* Omega) {
+// Copy the raw block in S0 (n1 x b) to column block i of Wraw (n1 x m).
+int save_raw(const Ctx& c, int i) {
+  const Plan& p = c.p;
+  HIPCHK(hipMemcpy2DAsync(c.at<unsigned char>(p.o_wraw) + (size_t)i * p.b * p.cs, (size_t)p.m * p.cs, c.at(p.o_s0),
+                          (size_t)p.b * p.cs, (size_t)p.b * p.cs, (size_t)(p.F * p.n1), hipMemcpyDeviceToDevice, c.s));
+  return TSVD_OK;
+}
+
+int krylov(const Ctx& c, const void* A, const void* Omega, bool keep_raw = false) {
   const Plan& p = c.p;
   const DType dt = p.dt;
   {
@@ -414,11 +431,13 @@ int krylov(const Ctx& c, const void* A, const void* Omega) {
   unsigned char* T = c.at<unsigned char>(p.o_t);
   int r;
   if ((r = big_AX(c, c.at(p.o_obar), p.b, p.n2 * p.b, c.at(p.o_s0), p.b, p.n1 * p.b, (int)p.b))) return r;
+  if (keep_raw && (r = save_raw(c, 0))) return r;
   if ((r = orth_block(c, 0))) return r;
   for (int i = 1; i <= p.q; ++i) {
     const size_t col = (size_t)(i - 1) * p.b * p.cs;
     if ((r = big_AhY(c, Q + col, p.m, p.n1 * p.m, T + col, p.m, p.n2 * p.m, (int)p.b))) return r;
     if ((r = big_AX(c, T + col, p.m, p.n2 * p.m, c.at(p.o_s0), p.b, p.n1 * p.b, (int)p.b))) return r;
+    if (keep_raw && (r = save_raw(c, i))) return r;
     if ((r = orth_block(c, i))) return r;
   }
   const size_t col = (size_t)p.q * p.b * p.cs;
@@ -498,6 +517,162 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   {
     Timed tm_(K_FFT_INV, c.s);
     HIPCHK(fft_c2r(c.at(p.o_scx), p.k, S, p.k, (int)p.n3, dt, c.s));
+  }
+  return TSVD_OK;
+}
+
+
+// Generic batched product C = alpha opA(A) opB(B) + beta C over the F slices
+// (element strides and leading dimensions in complex elements).
+struct Op {
+  const void* p;
+  int64_t ld, stride;
+  DType t;
+  bool conj;
+};
+int gemm(const Ctx& c, int cls, Op A, Op B, void* C, int64_t ldc, int64_t strideC, DType tc, int M, int N, int K,
+         double alpha, double beta, DType compute, int b_nsum = 1, int64_t b_sum_stride = 0) {
+  GemmDesc d = gd();
+  d.A = A.p;
+  d.lda = A.ld;
+  d.strideA = A.stride;
+  d.ta = A.t;
+  d.a_conj = A.conj;
+  d.B = B.p;
+  d.ldb = B.ld;
+  d.strideB = B.stride;
+  d.tb = B.t;
+  d.b_conj = B.conj;
+  d.b_nsum = b_nsum;
+  d.b_sum_stride = b_sum_stride;
+  d.C = C;
+  d.ldc = ldc;
+  d.strideC = strideC;
+  d.tc = tc;
+  d.M = M;
+  d.N = N;
+  d.K = K;
+  d.batch = (int)c.p.F;
+  d.alpha = alpha;
+  d.beta = beta;
+  d.compute = compute;
+  Timed tm_(cls, c.s);
+  HIPCHK(zgemm(d, c.s));
+  return TSVD_OK;
+}
+
+// Reverse pass of P(A) = Q Q^H A per Fourier slice (stabilised Krylov form):
+//   direct term Q Q^H G; Qbar = (G A^H + A G^H) Q; for i = q..0:
+//   Zbar_i = (I - Q_i Q_i^H) Qbar_i R_i^{-H} with R_i = Q_i^H W_i (the loss
+//   depends on Q_i only through its range); for i >= 1:
+//   Wbar_i = (I - Q_<i Q_<i^H) Zbar_i, Qbar_<i -= (Zbar_i W_i^H + W_i Zbar_i^H) Q_<i,
+//   Abar += Wbar_i T_i^H, Tbar_i = A^H Wbar_i, Abar += Q_{i-1} Tbar_i^H,
+//   Qbar_{i-1} += A Tbar_i; for i = 0: Abar += Zbar_0 Om^H.
+int proj_backward_impl(const Ctx& c, const void* A, const void* Omega, const void* G, void* dA) {
+  const Plan& p = c.p;
+  const DType dt = p.dt;
+  int r = krylov(c, A, Omega, true);
+  if (r) return r;
+  {
+    Timed tm_(K_FFT_A, c.s);
+    HIPCHK(fft_r2c(G, c.at(p.o_gbar), p.n1 * p.n2, (int)p.n3, dt, c.s));
+  }
+  const int n1 = (int)p.n1, n2 = (int)p.n2, m = (int)p.m, b = (int)p.b;
+  const int64_t s12 = p.n1 * p.n2, s1m = p.n1 * p.m, s2m = p.n2 * p.m, s1b = p.n1 * p.b, s2b = p.n2 * p.b;
+  unsigned char* Q = c.at<unsigned char>(p.o_q);
+  unsigned char* T = c.at<unsigned char>(p.o_t);
+  unsigned char* Wr = c.at<unsigned char>(p.o_wraw);
+  unsigned char* Qb = c.at<unsigned char>(p.o_qbar);
+  void* Ab = c.at(p.o_abar);
+  void* Gb = c.at(p.o_gbar);
+  void* Db = c.at(p.o_dbar);
+  void* U2 = c.at(p.o_u2);
+  void* Zb = c.at(p.o_zbar);
+  void* Wb = c.at(p.o_wbar);
+  void* Tb = c.at(p.o_tbar);
+  double* part = c.at<double>(p.o_part);
+  const size_t cs = p.cs;
+  // U2 = Gbar^H Q; Dbar = Q U2^H (= Q Q^H Gbar)
+  if ((r = gemm(c, K_GEMM_KRYLOV, Op{Gb, n2, s12, dt, true}, Op{Q, m, s1m, dt, false}, U2, m, s2m, dt, n2, m, n1, 1.0,
+                0.0, dt)))
+    return r;
+  if ((r = gemm(c, K_GEMM_LIFT, Op{Q, m, s1m, dt, false}, Op{U2, m, s2m, dt, true}, Db, n2, s12, dt, n1, n2, m, 1.0,
+                0.0, dt)))
+    return r;
+  // Qbar = Gbar T + Abar U2   (T = Abar^H Q)
+  if ((r = gemm(c, K_GEMM_KRYLOV, Op{Gb, n2, s12, dt, false}, Op{T, m, s2m, dt, false}, Qb, m, s1m, dt, n1, m, n2,
+                1.0, 0.0, dt)))
+    return r;
+  if ((r = gemm(c, K_GEMM_KRYLOV, Op{Ab, n2, s12, dt, false}, Op{U2, m, s2m, dt, false}, Qb, m, s1m, dt, n1, m, n2,
+                1.0, 1.0, dt)))
+    return r;
+  const int ns = p.nsplit_blk, kc = p.kchunk_blk;
+  for (int i = (int)p.q; i >= 0; --i) {
+    unsigned char* Qi = Q + (size_t)i * b * cs;
+    unsigned char* Qbi = Qb + (size_t)i * b * cs;
+    unsigned char* Wi = Wr + (size_t)i * b * cs;
+    // Qbar_i -= Q_i (Q_i^H Qbar_i)
+    if ((r = inner_products(c, Qi, m, b, Qbi, m, b, p.n1, s1m, s1m, ns, kc, part))) return r;
+    if ((r = gemm(c, K_GEMM_ORTH, Op{Qi, m, s1m, dt, false}, Op{part, b, (int64_t)b * b, DT_F64, false}, Qbi, m, s1m,
+                  dt, n1, b, b, -1.0, 1.0, DT_F64, ns, p.F * b * b)))
+      return r;
+    // R_i = Q_i^H W_i, Rinv = R_i^{-1}
+    if ((r = inner_products(c, Qi, m, b, Wi, m, b, p.n1, s1m, s1m, ns, kc, part))) return r;
+    {
+      Timed tm_(K_CHOL, c.s);
+      HIPCHK(chol_inv_ex(part, ns, p.F * b * b, c.at<double>(p.o_rinv), c.at(p.o_chol), b, (int)p.F, 0.0, c.info(),
+                         c.s, 1));
+    }
+    // Zbar = (I - Q_i Q_i^H) Qbar_i R_i^{-H}
+    if ((r = gemm(c, K_GEMM_ORTH, Op{Qbi, m, s1m, dt, false}, Op{c.at(p.o_rinv), b, (int64_t)b * b, DT_F64, true},
+                  Zb, b, s1b, dt, n1, b, b, 1.0, 0.0, DT_F64)))
+      return r;
+    if (i == 0) {
+      // Dbar += Zbar_0 Om^H
+      if ((r = gemm(c, K_GEMM_LIFT, Op{Zb, b, s1b, dt, false}, Op{c.at(p.o_obar), b, s2b, dt, true}, Db, n2, s12, dt,
+                    n1, n2, b, 1.0, 1.0, dt)))
+        return r;
+      break;
+    }
+    const int ib = i * b;
+    // Wbar = Zbar - Q_<i (Q_<i^H Zbar)
+    HIPCHK(hipMemcpyAsync(Wb, Zb, (size_t)p.F * s1b * cs, hipMemcpyDeviceToDevice, c.s));
+    if ((r = inner_products(c, Q, m, ib, Zb, b, b, p.n1, s1m, s1b, ns, kc, part))) return r;
+    if ((r = gemm(c, K_GEMM_ORTH, Op{Q, m, s1m, dt, false}, Op{part, b, (int64_t)ib * b, DT_F64, false}, Wb, b, s1b,
+                  dt, n1, b, ib, -1.0, 1.0, DT_F64, ns, p.F * ib * b)))
+      return r;
+    // Qbar_<i -= Zbar (W_i^H Q_<i) + W_i (Zbar^H Q_<i)
+    if ((r = inner_products(c, Wi, m, b, Q, m, ib, p.n1, s1m, s1m, ns, kc, part))) return r;
+    if ((r = gemm(c, K_GEMM_ORTH, Op{Zb, b, s1b, dt, false}, Op{part, ib, (int64_t)b * ib, DT_F64, false}, Qb, m, s1m,
+                  dt, n1, ib, b, -1.0, 1.0, DT_F64, ns, p.F * b * ib)))
+      return r;
+    if ((r = inner_products(c, Zb, b, b, Q, m, ib, p.n1, s1b, s1m, ns, kc, part))) return r;
+    if ((r = gemm(c, K_GEMM_ORTH, Op{Wi, m, s1m, dt, false}, Op{part, ib, (int64_t)b * ib, DT_F64, false}, Qb, m, s1m,
+                  dt, n1, ib, b, -1.0, 1.0, DT_F64, ns, p.F * b * ib)))
+      return r;
+    unsigned char* Ti = T + (size_t)(i - 1) * b * cs;
+    unsigned char* Qi1 = Q + (size_t)(i - 1) * b * cs;
+    unsigned char* Qbi1 = Qb + (size_t)(i - 1) * b * cs;
+    // Dbar += Wbar T_i^H
+    if ((r = gemm(c, K_GEMM_LIFT, Op{Wb, b, s1b, dt, false}, Op{Ti, m, s2m, dt, true}, Db, n2, s12, dt, n1, n2, b, 1.0,
+                  1.0, dt)))
+      return r;
+    // Tbar = Abar^H Wbar
+    if ((r = gemm(c, K_GEMM_KRYLOV, Op{Ab, n2, s12, dt, true}, Op{Wb, b, s1b, dt, false}, Tb, b, s2b, dt, n2, b, n1,
+                  1.0, 0.0, dt)))
+      return r;
+    // Dbar += Q_{i-1} Tbar^H
+    if ((r = gemm(c, K_GEMM_LIFT, Op{Qi1, m, s1m, dt, false}, Op{Tb, b, s2b, dt, true}, Db, n2, s12, dt, n1, n2, b, 1.0,
+                  1.0, dt)))
+      return r;
+    // Qbar_{i-1} += Abar Tbar
+    if ((r = gemm(c, K_GEMM_KRYLOV, Op{Ab, n2, s12, dt, false}, Op{Tb, b, s2b, dt, false}, Qbi1, m, s1m, dt, n1, b, n2,
+                  1.0, 1.0, dt)))
+      return r;
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(Db, s12, dA, s12, (int)p.n3, dt, c.s));
   }
   return TSVD_OK;
 }
@@ -627,20 +802,14 @@ int tsvd_proj(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t 
 
 int tsvd_proj_backward(const void* A, const void* Omega, const void* G, int64_t n1, int64_t n2, int64_t n3, int64_t b,
                        int64_t q, int prec, void* dA, void* ws, size_t ws_bytes, void* stream) {
-  (void)A;
-  (void)Omega;
-  (void)G;
-  (void)n1;
-  (void)n2;
-  (void)n3;
-  (void)b;
-  (void)q;
-  (void)prec;
-  (void)dA;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  return fail(TSVD_EINVAL, "tsvd_proj_backward: not available in this build");
+  Plan p;
+  int r = make_plan(n1, n2, n3, 1, b, q, prec, TSVD_OP_PROJ_BWD, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, Omega, G, dA}, ws, ws_bytes, p))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = proj_backward_impl(c, A, Omega, G, dA))) return r;
+  g_err.clear();
+  return TSVD_OK;
 }
 
 int tsvd_read_info(const void* ws, int32_t* info_host, void* stream) {

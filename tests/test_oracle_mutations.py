@@ -112,8 +112,8 @@ MUTATIONS = [
     ("truncation off by one", "Vf = Z[:, :k]", "Vf = Z[:, 1:k + 1]", pin_exact_tsvd),
     ("lift with conj", "Uf = Q @ W[:, :k]", "Uf = Q @ W[:, :k].conj()", pin_exact_tsvd),
     ("adjoint direct term dropped", "Abar = Q @ (Q.conj().T @ Yb)", "Abar = 0 * Yb", pin_adjoint_fd),
-    ("adjoint Qbar term dropped", "Qbar_all = (Yb @ A.conj().T + A @ Yb.conj().T) @ Q",
-     "Qbar_all = (Yb @ A.conj().T) @ Q", pin_adjoint_fd),
+    ("adjoint Qbar term dropped", "Qbar_all = Yb @ (A.conj().T @ Q) + A @ (Yb.conj().T @ Q)",
+     "Qbar_all = Yb @ (A.conj().T @ Q)", pin_adjoint_fd),
     ("adjoint reverse Krylov term dropped", "Abar += Qs[i - 1] @ Tbar.conj().T", "pass", pin_adjoint_fd),
     ("adjoint R^-H dropped", "Zbar0 = np.linalg.solve(R0, X.conj().T).conj().T", "Zbar0 = X", pin_adjoint_fd),
 ]
