@@ -39,13 +39,11 @@ def kernel_work(cls: str, c: dict, prec: str):
         return 8.0 * n1 * n2 * b * F / 1e12, "TFLOP/s", "mfma", PEAK["mfma_tflops"][prec]
     if cls == "fft_A":         # read the real tensor, write the half spectrum
         return (es * n1 * n2 * n3 + 2 * es * n1 * n2 * F) / 1e9, "GB/s", "hbm", PEAK["hbm_gbs"]
-    if cls == "heig":          # Householder tridiagonalisation + back-transform, FP64
-        return F * (16.0 / 3.0 * m ** 3 + 8.0 * m * m * k) / 1e12, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"]
-    if cls == "gemm_lift":     # G = C C^H (half), U = Q W, V = C^H W
-        return F * (4.0 * m * m * n2 + 8.0 * (n1 + n2) * m * k) / 1e12, "TFLOP/s", "mfma", PEAK["mfma_tflops"]["f64"]
-    if cls == "gemm_orth":
-        return None
-    return None
+    if cls == "heig_tri":      # Householder tridiagonalisation of the m x m Hermitian G_f, FP64
+        return F * (16.0 / 3.0 * m ** 3) / 1e12, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"]
+    if cls == "chol":          # b x b complex Cholesky + triangular inverse, FP64, per slice
+        return F * (16.0 / 3.0 * b ** 3) / 1e12, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"]
+    return None   # classes whose launches differ in shape carry no per-launch figure
 
 
 def cpu_baseline(A, Om, c, U, S, V, nslices):
@@ -91,7 +89,19 @@ def main():
     ap.add_argument("--prec", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=2)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * 2**20 // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU (one Fourier-slice batch per device); "

@@ -39,9 +39,11 @@ int tsvd_diag_zgemm(const void* A, int a_conj, const void* B, int b_conj, void* 
  * tsvd_diag_timing_read synchronises on the recorded events and returns, per
  * kernel class, the summed duration in ms and the number of launches.
  * Classes: 0 mode-3 DFT of A, 1 DFT of Omega, 2 Krylov products
- * (A_f X and A_f^H Y), 3 orthonormalisation products, 4 Cholesky, 5 small
- * eigenproblem, 6 Gram of C and lift products, 7 inverse DFTs, 8 other. */
-#define TSVD_DIAG_NCLASS 9
+ * (A_f X and A_f^H Y), 3 orthonormalisation products, 4 Cholesky,
+ * 5 tridiagonalisation of the small Hermitian eigenproblem, 6 Gram of C and
+ * lift products, 7 inverse DFTs, 8 other, 9 eigenvalue bisection,
+ * 10 inverse iteration, 11 eigenvector back-transformation. */
+#define TSVD_DIAG_NCLASS 12
 int tsvd_diag_timing(int enable);
 int tsvd_diag_timing_read(double* ms_out, int64_t* count_out, int nclass);
 

@@ -245,7 +245,8 @@ def diag_zgemm(A, B, a_conj=False, b_conj=False, C=None, alpha=1.0, beta=0.0):
     return C
 
 
-KERNEL_CLASSES = ("fft_A", "fft_omega", "gemm_krylov", "gemm_orth", "chol", "heig", "gemm_lift", "fft_inv", "misc")
+KERNEL_CLASSES = ("fft_A", "fft_omega", "gemm_krylov", "gemm_orth", "chol", "heig_tri", "gemm_lift", "fft_inv", "misc",
+                  "heig_bisect", "heig_invit", "heig_backxf")
 
 
 def diag_timing(enable: bool):

@@ -729,7 +729,7 @@ __global__ __launch_bounds__(256) void heig_backxf_kernel(int m, int k, unsigned
 }
 
 hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, int k, int batch, double* lambda,
-                     double* W, void* scratch, int* info, hipStream_t s) {
+                     double* W, void* scratch, int* info, hipStream_t s, int stages) {
   if (batch <= 0) return hipSuccess;
   if (m > 1024 || k > m || k < 1) return hipErrorInvalidValue;
   static bool attr_set = false;
@@ -755,27 +755,36 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
     if (Lsw > m - 1) Lsw = m - 1;
   }
   const size_t sm1 = vec_bytes + (size_t)Lsw * Lsw * sizeof(cx<double>);
-  hipLaunchKernelGGL(heig_tridiag_kernel, dim3(batch), dim3(TRI_NT), sm1, s, (const cx<double>*)Gpart, nsum,
-                     part_stride, m, sc, per, Lsw);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (stages & HEIG_TRIDIAG) {
+    hipLaunchKernelGGL(heig_tridiag_kernel, dim3(batch), dim3(TRI_NT), sm1, s, (const cx<double>*)Gpart, nsum,
+                       part_stride, m, sc, per, Lsw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   // 2. eigenvalues: 4 waves (eigenvalues) per workgroup
-  hipLaunchKernelGGL(heig_bisect_kernel, dim3(batch, (k + 3) / 4), dim3(256), (size_t)3 * m * sizeof(double), s, m,
-                     k, sc, per, lambda, info);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (stages & HEIG_BISECT) {
+    hipLaunchKernelGGL(heig_bisect_kernel, dim3(batch, (k + 3) / 4), dim3(256), (size_t)3 * m * sizeof(double), s,
+                       m, k, sc, per, lambda, info);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   // 3. eigenvectors: per-wave LU workspace of 6 m doubles in LDS
   int nw = (int)((140 * 1024 - 16 * (size_t)m) / (48 * (size_t)m));
   if (nw > 4) nw = 4;
   if (nw < 1) nw = 1;
   const size_t sm3 = (size_t)2 * m * sizeof(double) + (size_t)nw * 6 * m * sizeof(double);
-  hipLaunchKernelGGL(heig_invit_kernel, dim3(batch, (k + nw - 1) / nw), dim3(64 * nw), sm3, s, m, k, sc, per,
-                     lambda, (cx<double>*)W, info);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (stages & HEIG_INVIT) {
+    hipLaunchKernelGGL(heig_invit_kernel, dim3(batch, (k + nw - 1) / nw), dim3(64 * nw), sm3, s, m, k, sc, per,
+                       lambda, (cx<double>*)W, info);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   // 4. back-transformation
   const size_t sm4 = ((size_t)m * 8 + m) * sizeof(cx<double>);
-  hipLaunchKernelGGL(heig_backxf_kernel, dim3(batch, (k + 7) / 8), dim3(256), sm4, s, m, k, sc, per,
-                     (cx<double>*)W);
-  return hipGetLastError();
+  if (stages & HEIG_BACKXF) {
+    hipLaunchKernelGGL(heig_backxf_kernel, dim3(batch, (k + 7) / 8), dim3(256), sm4, s, m, k, sc, per,
+                       (cx<double>*)W);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace tsvd

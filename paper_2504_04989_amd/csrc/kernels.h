@@ -48,9 +48,12 @@ hipError_t chol_inv_ex(const double* Gpart, int nsum, int64_t part_stride, doubl
 
 // Per-slice m x m Hermitian PSD matrix (sum of nsum FP64 partials): top-k
 // eigenpairs.  lambda (batch x k, descending), W (batch x m x k complex FP64).
+// `stages` selects which of the four launches to enqueue (they must run in
+// this order on one stream, with the same arguments).
+enum HeigStage { HEIG_TRIDIAG = 1, HEIG_BISECT = 2, HEIG_INVIT = 4, HEIG_BACKXF = 8, HEIG_ALL = 15 };
 size_t heig_scratch_bytes(int m, int k);
 hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, int k, int batch, double* lambda,
-                     double* W, void* scratch, int* info, hipStream_t s);
+                     double* W, void* scratch, int* info, hipStream_t s, int stages = HEIG_ALL);
 
 // Lift helpers.
 // Wout (batch x m x k, dtype t) = W * diag(scale) where scale = sqrt(lambda)

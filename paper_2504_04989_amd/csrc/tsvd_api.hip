@@ -162,8 +162,8 @@ struct Ctx {
   } while (0)
 
 // ---- opt-in per-kernel-class event timer (tsvd_diag_timing*) -------------
-enum KClass { K_FFT_A = 0, K_FFT_OMEGA, K_GEMM_KRYLOV, K_GEMM_ORTH, K_CHOL, K_HEIG, K_GEMM_LIFT, K_FFT_INV, K_MISC,
-              K_NCLASS };
+enum KClass { K_FFT_A = 0, K_FFT_OMEGA, K_GEMM_KRYLOV, K_GEMM_ORTH, K_CHOL, K_HEIG_TRI, K_GEMM_LIFT, K_FFT_INV, K_MISC,
+              K_HEIG_BISECT, K_HEIG_INVIT, K_HEIG_BACKXF, K_NCLASS };
 struct Timer {
   std::mutex mu;
   bool on = false;
@@ -455,10 +455,12 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   if (r) return r;
   double* lam = c.at<double>(p.o_lam);
   double* Wd = c.at<double>(p.o_wd);
-  {
-    Timed tm_(K_HEIG, c.s);
+  const int stage_cls[4][2] = {
+      {HEIG_TRIDIAG, K_HEIG_TRI}, {HEIG_BISECT, K_HEIG_BISECT}, {HEIG_INVIT, K_HEIG_INVIT}, {HEIG_BACKXF, K_HEIG_BACKXF}};
+  for (const auto& sc : stage_cls) {
+    Timed tm_(sc[1], c.s);
     HIPCHK(heig_topk(part, p.nsplit_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
-                   c.info(), c.s));
+                     c.info(), c.s, sc[0]));
   }
   // U_f = Q_f W_k
   GemmDesc d = gd();

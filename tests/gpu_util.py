@@ -49,3 +49,24 @@ def unambiguous_phase_columns(Uf, rel_gap=1e-3):
         a = np.sort(np.abs(Uf[:, j]))[::-1]
         ok.append(len(a) < 2 or a[0] - a[1] > rel_gap * a[0])
     return np.array(ok)
+
+
+def fp32_twin_slice(A, Om, k, b, q, f):
+    """The floor of FP32 arithmetic on one Fourier slice: the stabilised block
+    Krylov method of Alg. 2 run entirely in complex64 with numpy / LAPACK
+    primitives (QR, SVD), on the same inputs.  Returns (X_hat_f, sigma_1..k).
+    Test infrastructure: it measures what a plain FP32 computation of the slice
+    reaches, so that a GPU error can be told apart from the FP32 limit."""
+    w = np.exp(-2j * np.pi * f * np.arange(A.shape[2]) / A.shape[2])
+    Af = (A @ w).astype(np.complex64)
+    Of = (Om @ w).astype(np.complex64)
+    Qs = [np.linalg.qr(Af @ Of)[0]]
+    for _ in range(q):
+        W = Af @ (Af.conj().T @ Qs[-1])
+        Qp = np.concatenate(Qs, axis=1)
+        W = W - Qp @ (Qp.conj().T @ W)
+        W = W - Qp @ (Qp.conj().T @ W)
+        Qs.append(np.linalg.qr(W)[0])
+    Q = np.concatenate(Qs, axis=1)
+    W, s, Zh = np.linalg.svd(Q.conj().T @ Af, full_matrices=False)
+    return ((Q @ W[:, :k]) * s[:k]) @ Zh[:k], s[:k].astype(np.float64)
