@@ -47,9 +47,22 @@
  * status returned on the calling thread.
  *
  * Internal precision: Gram matrices, Cholesky factors, re-orthogonalisation
- * coefficients and the small Hermitian eigenproblem are always FP64; the
- * mode-3 transforms and the large products run in the precision named by
- * `prec`.
+ * coefficients and the small Hermitian eigenproblem are always FP64, and the
+ * mode-3 transforms compute in FP64 (rounded once to the storage type).
+ * `prec` names the storage type and the arithmetic of the Krylov products
+ * A_f X and A_f^H Y (Alg. 2: the block Krylov space and C_f = Q_f^H A_f):
+ *   TSVD_PREC_F64     FP64 storage, FP64 MFMA
+ *   TSVD_PREC_F32     FP32 storage, FP32 MFMA
+ *   TSVD_PREC_BF16    FP32 storage, products on BF16 MFMA (one product of the
+ *                     bf16-rounded operands), FP32 accumulation
+ *   TSVD_PREC_BF16X3  FP32 storage, each operand split x = hi + lo into two
+ *                     bf16 numbers, hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32
+ *                     accumulation (about 16 significant bits per product)
+ * The orthonormalisation products (block Grams, projections against the
+ * earlier blocks, application of R^{-1}) and G_f = C_f C_f^H use FP64
+ * arithmetic on the stored values in every mode; the lift (U_f = Q_f W_k,
+ * V_f = C_f^H W_k / sigma) and the adjoint's other products use the storage
+ * type's arithmetic.
  */
 #ifndef TSVD_RBK_H
 #define TSVD_RBK_H
@@ -69,11 +82,10 @@ extern "C" {
 #define TSVD_ENUMERIC 4
 
 /* precision of the transforms and of the large products */
-#define TSVD_PREC_F64 0    /* FP64 storage, FP64 MFMA                         */
-#define TSVD_PREC_F32 1    /* FP32 storage, FP32 MFMA                         */
-#define TSVD_PREC_BF16 2   /* FP32 storage, BF16 operands on MFMA, FP32 accum. */
-#define TSVD_PREC_BF16X3 3 /* FP32 storage, split BF16 hi/lo operands, 3 BF16
-                              MFMA products per term, FP32 accumulation       */
+#define TSVD_PREC_F64 0    /* see "Internal precision" above */
+#define TSVD_PREC_F32 1
+#define TSVD_PREC_BF16 2
+#define TSVD_PREC_BF16X3 3
 
 /* operations, for tsvd_workspace_bytes */
 #define TSVD_OP_RBK 0

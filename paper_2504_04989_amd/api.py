@@ -22,7 +22,7 @@ INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_rbk", "tsvd_rbk_approx",
            "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
-           "tsvd_diag_zgemm", "tsvd_diag_timing", "tsvd_diag_timing_read")
+           "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_timing", "tsvd_diag_timing_read")
 
 
 class TsvdError(RuntimeError):
@@ -62,6 +62,8 @@ def _load():
     lib.tsvd_diag_zgemm.restype = ctypes.c_int
     lib.tsvd_diag_zgemm.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, i64, i64, i64, i64, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, vp]
+    lib.tsvd_diag_kgemm.restype = ctypes.c_int
+    lib.tsvd_diag_kgemm.argtypes = [vp, ctypes.c_int, vp, vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, vp]
     return lib
 
 
@@ -242,6 +244,22 @@ def diag_zgemm(A, B, a_conj=False, b_conj=False, C=None, alpha=1.0, beta=0.0):
         C = torch.zeros((batch, M, N), dtype=A.dtype, device=A.device)
     _check(lib.tsvd_diag_zgemm(_ptr(A), int(a_conj), _ptr(B), int(b_conj), _ptr(C), M, N, K, batch, alpha, beta,
                                _dcode(A), _stream(A.device)))
+    return C
+
+
+KGEMM_MODE = {"f32": 0, "bf16": 1, "bf16x3": 2}
+
+
+def diag_kgemm(A, X, herm=False, mode="f32", nsplit=1):
+    """The Krylov-product kernel alone (see tsvd_diag_kgemm): op(A_f) X_f for
+    complex64 tensors A (batch, rows, cols) and X (batch, K, N)."""
+    batch, rows, cols = A.shape
+    M = cols if herm else rows
+    N = X.shape[2]
+    C = torch.empty((batch, M, N), dtype=torch.complex64, device=A.device)
+    part = torch.empty((nsplit, batch, M, N), dtype=torch.complex64, device=A.device) if nsplit > 1 else None
+    _check(lib.tsvd_diag_kgemm(_ptr(A), int(herm), _ptr(X), _ptr(C), rows, cols, N, batch, KGEMM_MODE[mode], nsplit,
+                               _ptr(part) if part is not None else None, _stream(A.device)))
     return C
 
 

@@ -6,7 +6,8 @@
 // slice-major (F x ntubes, interleaved complex), which is the per-slice
 // row-major matrix layout the GEMMs consume.
 //
-// One workgroup owns 2*NP consecutive tubes.  The tubes are read from HBM
+// Arithmetic is FP64 for both storage types (FP32 data is widened on load and
+// rounded once on store).  One workgroup owns 2*NP consecutive tubes.  The tubes are read from HBM
 // with fully coalesced loads, two real tubes are packed into one complex
 // sequence z = x_a + i x_b in LDS, a self-sorting (Stockham) mixed-radix FFT
 // with radices 2, 3, 4, 5, 7, 11, 13 runs out of LDS, and the two real
@@ -146,14 +147,17 @@ __device__ cx<T>* run_passes(cx<T>* b0, cx<T>* b1, const cx<T>* tw, const FftPla
   return in;
 }
 
-template <typename T>
+// T: storage type of the tensor and its spectrum; C: arithmetic type (FP64
+// for FP32 storage, so that every output is the correctly rounded value of a
+// DFT whose error is far below the FP32 rounding of the result).
+template <typename T, typename C>
 __global__ __launch_bounds__(256) void fft_r2c_kernel(const T* __restrict__ X, cx<T>* __restrict__ Xb, int64_t ntubes,
                                                       FftPlan plan, int NP) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = plan.N;
-  cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  cx<T>* b0 = tw + N;
-  cx<T>* b1 = b0 + NP * N;
+  cx<C>* tw = reinterpret_cast<cx<C>*>(smem);
+  cx<C>* b0 = tw + N;
+  cx<C>* b1 = b0 + NP * N;
   make_twiddles(tw, N);
   const int64_t t0 = (int64_t)blockIdx.x * 2 * NP;
   const int ntw = (int)min((int64_t)2 * NP, ntubes - t0);
@@ -161,39 +165,39 @@ __global__ __launch_bounds__(256) void fft_r2c_kernel(const T* __restrict__ X, c
   const int total = ntw * N;
   for (int g = threadIdx.x; g < 2 * NP * N; g += blockDim.x) {
     const int tube = g / N, t = g - tube * N;
-    const T v = (g < total) ? src[g] : (T)0;
-    T* dst = reinterpret_cast<T*>(&b0[(tube >> 1) * N + t]);
+    const C v = (g < total) ? (C)src[g] : (C)0;
+    C* dst = reinterpret_cast<C*>(&b0[(tube >> 1) * N + t]);
     dst[tube & 1] = v;
   }
   __syncthreads();
-  const cx<T>* Z = run_passes<T, false>(b0, b1, tw, plan, NP);
+  const cx<C>* Z = run_passes<C, false>(b0, b1, tw, plan, NP);
   const int F = N / 2 + 1;
   for (int idx = threadIdx.x; idx < F * 2 * NP; idx += blockDim.x) {
     const int f = idx / (2 * NP), tube = idx - f * 2 * NP;
     if (tube >= ntw) continue;
     const int p = tube >> 1;
-    const cx<T> zf = Z[p * N + f];
-    const cx<T> zm = Z[p * N + (f == 0 ? 0 : N - f)];
+    const cx<C> zf = Z[p * N + f];
+    const cx<C> zm = Z[p * N + (f == 0 ? 0 : N - f)];
     cx<T> o;
     if (!(tube & 1)) {
-      o.re = (zf.re + zm.re) * (T)0.5;
-      o.im = (zf.im - zm.im) * (T)0.5;
+      o.re = (T)((zf.re + zm.re) * (C)0.5);
+      o.im = (T)((zf.im - zm.im) * (C)0.5);
     } else {
-      o.re = (zf.im + zm.im) * (T)0.5;
-      o.im = (zm.re - zf.re) * (T)0.5;
+      o.re = (T)((zf.im + zm.im) * (C)0.5);
+      o.im = (T)((zm.re - zf.re) * (C)0.5);
     }
     Xb[(int64_t)f * ntubes + t0 + tube] = o;
   }
 }
 
-template <typename T>
+template <typename T, typename C>
 __global__ __launch_bounds__(256) void fft_c2r_kernel(const cx<T>* __restrict__ Xb, int64_t slice_stride,
                                                       T* __restrict__ X, int64_t ntubes, FftPlan plan, int NP) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = plan.N;
-  cx<T>* tw = reinterpret_cast<cx<T>*>(smem);
-  cx<T>* b0 = tw + N;
-  cx<T>* b1 = b0 + NP * N;
+  cx<C>* tw = reinterpret_cast<cx<C>*>(smem);
+  cx<C>* b0 = tw + N;
+  cx<C>* b1 = b0 + NP * N;
   make_twiddles(tw, N);
   const int64_t t0 = (int64_t)blockIdx.x * 2 * NP;
   const int ntw = (int)min((int64_t)2 * NP, ntubes - t0);
@@ -201,25 +205,31 @@ __global__ __launch_bounds__(256) void fft_c2r_kernel(const cx<T>* __restrict__ 
   for (int idx = threadIdx.x; idx < F * NP; idx += blockDim.x) {
     const int f = idx / NP, p = idx - f * NP;
     const int ta = 2 * p, tb = 2 * p + 1;
-    cx<T> a{0, 0}, b{0, 0};
-    if (ta < ntw) a = Xb[(int64_t)f * slice_stride + t0 + ta];
-    if (tb < ntw) b = Xb[(int64_t)f * slice_stride + t0 + tb];
+    cx<C> a{0, 0}, b{0, 0};
+    if (ta < ntw) {
+      const cx<T> v = Xb[(int64_t)f * slice_stride + t0 + ta];
+      a = cx<C>{(C)v.re, (C)v.im};
+    }
+    if (tb < ntw) {
+      const cx<T> v = Xb[(int64_t)f * slice_stride + t0 + tb];
+      b = cx<C>{(C)v.re, (C)v.im};
+    }
     if (f == 0 || 2 * f == N) {
       a.im = 0;
       b.im = 0;
     }
-    b0[p * N + f] = cx<T>{a.re - b.im, a.im + b.re};
-    if (f > 0 && 2 * f != N) b0[p * N + (N - f)] = cx<T>{a.re + b.im, b.re - a.im};
+    b0[p * N + f] = cx<C>{a.re - b.im, a.im + b.re};
+    if (f > 0 && 2 * f != N) b0[p * N + (N - f)] = cx<C>{a.re + b.im, b.re - a.im};
   }
   __syncthreads();
-  const cx<T>* Z = run_passes<T, true>(b0, b1, tw, plan, NP);
-  const T invN = (T)1 / (T)N;
+  const cx<C>* Z = run_passes<C, true>(b0, b1, tw, plan, NP);
+  const C invN = (C)1 / (C)N;
   const int total = ntw * N;
   T* dst = X + t0 * N;
   for (int g = threadIdx.x; g < total; g += blockDim.x) {
     const int tube = g / N, t = g - tube * N;
-    const cx<T> z = Z[(tube >> 1) * N + t];
-    dst[g] = ((tube & 1) ? z.im : z.re) * invN;
+    const cx<C> z = Z[(tube >> 1) * N + t];
+    dst[g] = (T)(((tube & 1) ? z.im : z.re) * invN);
   }
 }
 
@@ -261,9 +271,9 @@ __global__ void dft_c2r_direct(const cx<T>* Xb, int64_t slice_stride, T* X, int6
   X[idx] = (T)(acc / N);
 }
 
-template <typename T>
+template <typename C>
 static int pick_np(int N) {
-  const int budget = 64 * 1024 / (int)sizeof(cx<T>);
+  const int budget = 64 * 1024 / (int)sizeof(cx<C>);
   int np = (budget - N) / (2 * N);
   if (np > 64) np = 64;
   return np;
@@ -273,7 +283,7 @@ template <typename T>
 static hipError_t r2c_t(const void* X, void* Xb, int64_t ntubes, int n3, hipStream_t s) {
   if (ntubes <= 0) return hipSuccess;
   FftPlan plan = make_plan(n3);
-  const int NP = pick_np<T>(n3);
+  const int NP = pick_np<double>(n3);
   if (plan.direct || NP < 1) {
     const int64_t total = ntubes * (n3 / 2 + 1);
     hipLaunchKernelGGL(dft_r2c_direct<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (const T*)X,
@@ -281,9 +291,9 @@ static hipError_t r2c_t(const void* X, void* Xb, int64_t ntubes, int n3, hipStre
     return hipGetLastError();
   }
   const int64_t nblk = (ntubes + 2 * NP - 1) / (2 * NP);
-  const size_t sm = (size_t)(n3 + 2 * NP * n3) * sizeof(cx<T>);
-  hipLaunchKernelGGL(fft_r2c_kernel<T>, dim3((unsigned)nblk), dim3(256), sm, s, (const T*)X, (cx<T>*)Xb, ntubes,
-                     plan, NP);
+  const size_t sm = (size_t)(n3 + 2 * NP * n3) * sizeof(cx<double>);
+  hipLaunchKernelGGL((fft_r2c_kernel<T, double>), dim3((unsigned)nblk), dim3(256), sm, s, (const T*)X, (cx<T>*)Xb,
+                     ntubes, plan, NP);
   return hipGetLastError();
 }
 
@@ -291,7 +301,7 @@ template <typename T>
 static hipError_t c2r_t(const void* Xb, int64_t stride, void* X, int64_t ntubes, int n3, hipStream_t s) {
   if (ntubes <= 0) return hipSuccess;
   FftPlan plan = make_plan(n3);
-  const int NP = pick_np<T>(n3);
+  const int NP = pick_np<double>(n3);
   if (plan.direct || NP < 1) {
     const int64_t total = ntubes * n3;
     hipLaunchKernelGGL(dft_c2r_direct<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
@@ -299,9 +309,9 @@ static hipError_t c2r_t(const void* Xb, int64_t stride, void* X, int64_t ntubes,
     return hipGetLastError();
   }
   const int64_t nblk = (ntubes + 2 * NP - 1) / (2 * NP);
-  const size_t sm = (size_t)(n3 + 2 * NP * n3) * sizeof(cx<T>);
-  hipLaunchKernelGGL(fft_c2r_kernel<T>, dim3((unsigned)nblk), dim3(256), sm, s, (const cx<T>*)Xb, stride, (T*)X,
-                     ntubes, plan, NP);
+  const size_t sm = (size_t)(n3 + 2 * NP * n3) * sizeof(cx<double>);
+  hipLaunchKernelGGL((fft_c2r_kernel<T, double>), dim3((unsigned)nblk), dim3(256), sm, s, (const cx<T>*)Xb, stride,
+                     (T*)X, ntubes, plan, NP);
   return hipGetLastError();
 }
 

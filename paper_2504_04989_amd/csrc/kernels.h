@@ -28,6 +28,25 @@ struct GemmDesc {
 };
 hipError_t zgemm(const GemmDesc& d, hipStream_t s);
 
+// Krylov products C_f = op(A_f) X_f with the big FP32 complex slice A_f
+// (rows x cols, row stride lda, slice stride strideA, complex elements) and a
+// thin operand X_f (K x N, row stride ldx); herm: op = ^H (M = cols, K = rows),
+// else identity (M = rows, K = cols).  C_f is M x N (row stride ldc).  Modes:
+// FP32 MFMA, BF16 (one product), BF16x3 (hi/lo split, three products), FP32
+// accumulation.  nsplit > 1 splits K; part must then hold
+// nsplit * batch * M * N complex FP32 values (reduced in a fixed order).
+enum KMode { KM_F32 = 0, KM_BF16 = 1, KM_BF16X3 = 2 };
+struct KGemmDesc {
+  const void* A; int64_t lda, strideA; int rows, cols; bool herm;
+  const void* X; int64_t ldx, strideX;
+  void* C; int64_t ldc, strideC;
+  int N, batch, mode, nsplit;
+  void* part;
+};
+hipError_t kgemm(const KGemmDesc& d, hipStream_t s);
+// K split (and chunk) that gives the product enough workgroups to fill the chip.
+int kgemm_split(int M, int K, int N, int batch, int* kchunk);
+
 // Mode-3 real-to-half-spectrum DFT: X (ntubes x n3, tube-contiguous) ->
 // Xb (F x ntubes complex, F = n3/2 + 1), slice-major.
 hipError_t fft_r2c(const void* X, void* Xb, int64_t ntubes, int n3, DType t, hipStream_t s);

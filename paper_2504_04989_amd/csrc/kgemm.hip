@@ -1,0 +1,412 @@
+// Krylov products of Alg. 2 on gfx950 MFMA: C_f = op(A_f) X_f for every
+// Fourier slice f, with A_f the large n1 x n2 slice of the transformed data
+// (FP32 interleaved complex) and X_f a thin block of N columns.
+//
+// Complex arithmetic as one real GEMM over the interleaved storage.  A row of
+// A_f read as reals is a vector of length 2 n2, so
+//   C = A X   :  C[m][2n+t] = sum_{k,s} A_int[m][2k+s] Xe[2n+t][2k+s]
+//                Xe[2n][2k] = xr, Xe[2n][2k+1] = -xi, Xe[2n+1][2k] = xi, Xe[2n+1][2k+1] = xr
+//   C = A^H Y :  C[j][2n+t] = sum_{i,s} A_int[i][2j+s] Ye[2n+t][2i+s]
+//                Ye[2n][2i] = yr, Ye[2n][2i+1] = yi, Ye[2n+1][2i] = yi, Ye[2n+1][2i+1] = -yr
+// with x = X[k][n], y = Y[i][n].  In both cases the thin, expanded operand
+// (Xe or Ye, 2N rows) is the MFMA A operand and is staged through LDS; the big
+// operand A_f is the MFMA B operand and goes from HBM straight into the
+// registers of one wave, which uses it for all 2N output rows: every element
+// of A_f is read from HBM once per product.  The output tile of a wave is
+// (2N real rows) x (16 TB big-dimension columns), i.e. C rows of the complex
+// result, written as contiguous (re, im) pairs.
+//
+// Precision modes: FP32 (v_mfma_f32_16x16x4_f32), BF16 (one bf16 product,
+// v_mfma_f32_16x16x32_bf16) and BF16x3 (x = hi + lo with hi = bf16(x),
+// lo = bf16(x - hi); hi*hi + hi*lo + lo*hi), all with FP32 accumulation.
+//
+// K step: 16 complex (32 real).  Lane (q4 = lane / 16, r = lane % 16) owns
+// real k' = 8 q4 .. 8 q4 + 7 of each step, i.e. complex k = 4 q4 .. 4 q4 + 3:
+// one bf16 MFMA covers the step; in FP32, MFMA block b (0..7) takes k' = 8 q4 + b.
+//
+// Work decomposition: tiles (slice, K split, thin chunk, big tile) are
+// numbered with the big tile fastest, and workgroup ids are mapped so that
+// consecutive tiles land on the same XCD (ids are dispatched round-robin over
+// the 8 XCDs): the thin block of a slice stays in that XCD's L2.
+#include <algorithm>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tsvd {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int KSTEP = 16;  // complex K per step
+constexpr int NWAVE = 4;
+
+struct KArgs {
+  const float* A;  // big operand (floats), slice f at A + f * strideA
+  int64_t lda, strideA;  // in floats
+  const float* X;  // thin operand (floats)
+  int64_t ldx, strideX;  // in floats
+  float* C;        // output (floats)
+  int64_t ldc, strideC;  // in floats
+  float* part;     // split-K partials: [split][f][M][N] complex
+  int M, K, N, batch;
+  int nsplit, kchunk;
+  int nbig, nthin, total, per;
+  int avec;  // big-operand rows are 16-byte aligned (vector loads allowed)
+};
+
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  __bf16 h = (__bf16)x;
+  return (uint32_t)__builtin_bit_cast(unsigned short, h);
+}
+__device__ __forceinline__ float bf16_val(float x) { return (float)(__bf16)x; }
+__device__ __forceinline__ uint32_t pack2(float a, float b) { return bf16_bits(a) | (bf16_bits(b) << 16); }
+
+template <int MODE>
+struct Lds {
+  static constexpr int WORDS = MODE == KM_F32 ? 2 * KSTEP : KSTEP;  // 32-bit words per row
+  static constexpr int STRIDE = WORDS + 4;
+  static constexpr int PLANES = MODE == KM_BF16X3 ? 2 : 1;
+};
+
+template <int MODE, bool HN, int TT, int TB>
+__global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
+  typedef Lds<MODE> L;
+  constexpr int ROWS = TT * 16;
+  constexpr int PLANE = ROWS * L::STRIDE;
+  constexpr int BUF = PLANE * L::PLANES;
+  constexpr int NCH = TT * 8;                 // complex thin columns per tile
+  constexpr int TEL = KSTEP * NCH / 256;      // thin elements per thread per step
+  static_assert(TEL * 256 == KSTEP * NCH, "thin split");
+  extern __shared__ __align__(16) uint32_t lds[];
+
+  // ---- tile of this workgroup (XCD-aware order) ----
+  const int id = blockIdx.x;
+  const int t = (id & 7) * a.per + (id >> 3);
+  if (t >= a.total) return;
+  int r = t;
+  const int bt = r % a.nbig;
+  r /= a.nbig;
+  const int tc = r % a.nthin;
+  r /= a.nthin;
+  const int sp = r % a.nsplit;
+  const int f = r / a.nsplit;
+  const int kb = sp * a.kchunk;
+  const int ke = min(a.K, kb + a.kchunk);
+  const int n0 = tc * NCH;
+  const int nc = min(NCH, a.N - n0);
+  const int tt = (2 * nc + 15) / 16;  // active thin tiles
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q4 = lane >> 4, r16 = lane & 15;
+  const float* Af = a.A + (int64_t)f * a.strideA;
+  const float* Xf = a.X + (int64_t)f * a.strideX;
+  int col[TB];
+  bool colok[TB];
+#pragma unroll
+  for (int u = 0; u < TB; ++u) {
+    col[u] = bt * (NWAVE * 16 * TB) + wave * 16 * TB + u * 16 + r16;
+    colok[u] = col[u] < a.M;
+  }
+
+  // ---- big operand: 8 reals (4 complex along K) per lane and tile ----
+  auto load_big = [&](int k0, float (&v)[TB][8]) {
+    const bool full = k0 + KSTEP <= ke;
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      if (!HN) {
+        const float* p = Af + (int64_t)col[u] * a.lda + 2 * (k0 + 4 * q4);
+        if (colok[u] && full && a.avec) {
+          const float4 x0 = *reinterpret_cast<const float4*>(p);
+          const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
+          v[u][0] = x0.x; v[u][1] = x0.y; v[u][2] = x0.z; v[u][3] = x0.w;
+          v[u][4] = x1.x; v[u][5] = x1.y; v[u][6] = x1.z; v[u][7] = x1.w;
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            float2 x = make_float2(0.f, 0.f);
+            if (colok[u] && k0 + 4 * q4 + c < ke) x = *reinterpret_cast<const float2*>(p + 2 * c);
+            v[u][2 * c] = x.x;
+            v[u][2 * c + 1] = x.y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = k0 + 4 * q4 + c;
+          float2 x = make_float2(0.f, 0.f);
+          if (colok[u] && (full || i < ke))
+            x = *reinterpret_cast<const float2*>(Af + (int64_t)i * a.lda + 2 * col[u]);
+          v[u][2 * c] = x.x;
+          v[u][2 * c + 1] = x.y;
+        }
+      }
+    }
+  };
+
+  // ---- thin operand: KSTEP x NCH complex per step, k fastest in a thread group ----
+  auto load_thin = [&](int k0, float2 (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % KSTEP, nn = idx / KSTEP;
+      float2 v = make_float2(0.f, 0.f);
+      if (k0 + kk < ke && nn < nc) v = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + kk) * a.ldx + 2 * (n0 + nn));
+      x[e] = v;
+    }
+  };
+  auto store_thin = [&](uint32_t* buf, const float2 (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % KSTEP, nn = idx / KSTEP;
+      const float xr = x[e].x, xi = x[e].y;
+      // rows 2nn (real part of the output) and 2nn + 1 (imaginary part)
+      const float r0a = xr, r0b = HN ? xi : -xi;
+      const float r1a = xi, r1b = HN ? -xr : xr;
+      uint32_t* row0 = buf + (2 * nn) * L::STRIDE;
+      uint32_t* row1 = row0 + L::STRIDE;
+      if (MODE == KM_F32) {
+        *reinterpret_cast<float2*>(row0 + 2 * kk) = make_float2(r0a, r0b);
+        *reinterpret_cast<float2*>(row1 + 2 * kk) = make_float2(r1a, r1b);
+      } else {
+        row0[kk] = pack2(r0a, r0b);
+        row1[kk] = pack2(r1a, r1b);
+        if (MODE == KM_BF16X3) {
+          row0[PLANE + kk] = pack2(r0a - bf16_val(r0a), r0b - bf16_val(r0b));
+          row1[PLANE + kk] = pack2(r1a - bf16_val(r1a), r1b - bf16_val(r1b));
+        }
+      }
+    }
+  };
+
+  f32x4 acc[TT][TB];
+#pragma unroll
+  for (int i = 0; i < TT; ++i)
+#pragma unroll
+    for (int u = 0; u < TB; ++u) acc[i][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto compute = [&](const uint32_t* buf, const float (&v)[TB][8]) {
+    if (MODE == KM_F32) {
+#pragma unroll
+      for (int i = 0; i < TT; ++i) {
+        if (i < tt) {
+          const float* rowp = reinterpret_cast<const float*>(buf + (16 * i + r16) * L::STRIDE + 8 * q4);
+          const float4 w0 = *reinterpret_cast<const float4*>(rowp);
+          const float4 w1 = *reinterpret_cast<const float4*>(rowp + 4);
+          const float w[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+          for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int u = 0; u < TB; ++u) acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[b], v[u][b], acc[i][u], 0, 0, 0);
+        }
+      }
+    } else {
+      bf16x8 bh[TB], bl[TB];
+#pragma unroll
+      for (int u = 0; u < TB; ++u) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const __bf16 h = (__bf16)v[u][j];
+          bh[u][j] = h;
+          if (MODE == KM_BF16X3) bl[u][j] = (__bf16)(v[u][j] - (float)h);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < TT; ++i) {
+        if (i < tt) {
+          const uint32_t* rowp = buf + (16 * i + r16) * L::STRIDE + 4 * q4;
+          const bf16x8 th = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(rowp));
+          if (MODE == KM_BF16X3) {
+            const bf16x8 tl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(rowp + PLANE));
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+              acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tl, bh[u], acc[i][u], 0, 0, 0);
+              acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bl[u], acc[i][u], 0, 0, 0);
+              acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bh[u], acc[i][u], 0, 0, 0);
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < TB; ++u)
+              acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bh[u], acc[i][u], 0, 0, 0);
+          }
+        }
+      }
+    }
+  };
+
+  // ---- main loop: LDS double buffer for the thin operand, register prefetch for A_f ----
+  const int nsteps = (ke - kb + KSTEP - 1) / KSTEP;
+  float cur[TB][8], nxt[TB][8];
+  float2 tx[TEL];
+  if (nsteps > 0) {
+    load_big(kb, cur);
+    load_thin(kb, tx);
+    store_thin(lds, tx);
+  }
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+    const int k0 = kb + s * KSTEP;
+    const bool more = s + 1 < nsteps;
+    if (more) {
+      load_big(k0 + KSTEP, nxt);
+      load_thin(k0 + KSTEP, tx);
+    }
+    compute(lds + (s & 1) * BUF, cur);
+    if (more) store_thin(lds + ((s + 1) & 1) * BUF, tx);
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < TB; ++u)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cur[u][j] = nxt[u][j];
+    }
+  }
+
+  // ---- epilogue: acc[i][u][r] = C_int[col][16 i + 4 q4 + r] -> complex n = n0 + 8 i + 2 q4 + {0, 1} ----
+  float* out;
+  int64_t ldo;
+  if (a.nsplit > 1) {
+    out = a.part + 2 * ((int64_t)sp * a.batch + f) * a.M * a.N;
+    ldo = 2 * (int64_t)a.N;
+  } else {
+    out = a.C + (int64_t)f * a.strideC;
+    ldo = a.ldc;
+  }
+#pragma unroll
+  for (int i = 0; i < TT; ++i) {
+    if (i < tt) {
+      const int n = n0 + 8 * i + 2 * q4;
+#pragma unroll
+      for (int u = 0; u < TB; ++u) {
+        if (!colok[u]) continue;
+        float* p = out + (int64_t)col[u] * ldo + 2 * n;
+        if (n < a.N) *reinterpret_cast<float2*>(p) = make_float2(acc[i][u][0], acc[i][u][1]);
+        if (n + 1 < a.N) *reinterpret_cast<float2*>(p + 2) = make_float2(acc[i][u][2], acc[i][u][3]);
+      }
+    }
+  }
+}
+
+// C[f][row][n] = sum_s part[s][f][row][n] (fixed order), complex FP32.
+__global__ void kgemm_reduce_kernel(const float2* __restrict__ part, int nsplit, int batch, int M, int N,
+                                    float2* __restrict__ C, int64_t ldc, int64_t strideC) {
+  const int64_t per = (int64_t)M * N;
+  const int64_t total = per * batch;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = e / per, rem = e % per;
+    const int row = (int)(rem / N), n = (int)(rem % N);
+    float2 s = part[e];
+    for (int j = 1; j < nsplit; ++j) {
+      const float2 v = part[(int64_t)j * total + e];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    C[f * strideC + (int64_t)row * ldc + n] = s;
+  }
+}
+
+template <int MODE, bool HN, int TT>
+hipError_t launch_tt(const KArgs& a, hipStream_t s) {
+  constexpr int TB = 2;
+  const size_t lds = (size_t)2 * TT * 16 * Lds<MODE>::STRIDE * Lds<MODE>::PLANES * 4;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)kgemm_kernel<MODE, HN, TT, TB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+    attr = true;
+  }
+  hipLaunchKernelGGL((kgemm_kernel<MODE, HN, TT, TB>), dim3(8 * a.per), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int MODE, bool HN>
+hipError_t launch_mode(const KArgs& a, int TT, hipStream_t s) {
+  switch (TT) {
+    case 4: return launch_tt<MODE, HN, 4>(a, s);
+    case 8: return launch_tt<MODE, HN, 8>(a, s);
+    case 14: return launch_tt<MODE, HN, 14>(a, s);
+    default: return launch_tt<MODE, HN, 16>(a, s);
+  }
+}
+
+}  // namespace
+
+int kgemm_thin_tiles(int N) {
+  const int nn = N < 128 ? N : 128;
+  if (nn <= 32) return 4;
+  if (nn <= 64) return 8;
+  if (nn <= 112) return 14;
+  return 16;
+}
+
+int kgemm_split(int M, int K, int N, int batch, int* kchunk) {
+  const int TT = kgemm_thin_tiles(N);
+  const int64_t nthin = (N + 8 * TT - 1) / (8 * TT);
+  const int64_t nbig = (M + NWAVE * 16 * 2 - 1) / (NWAVE * 16 * 2);
+  const int64_t tiles = nthin * nbig * batch;
+  int ns = 1;
+  while (tiles * ns < 512 && ns < 8 && (int64_t)K / (2 * ns) >= 256) ns *= 2;
+  int kc = (K + ns - 1) / ns;
+  kc = (kc + KSTEP - 1) / KSTEP * KSTEP;
+  ns = (K + kc - 1) / kc;
+  if (ns < 1) ns = 1;
+  *kchunk = kc < KSTEP ? KSTEP : kc;
+  return ns;
+}
+
+hipError_t kgemm(const KGemmDesc& d, hipStream_t s) {
+  const int M = d.herm ? d.cols : d.rows;
+  const int K = d.herm ? d.rows : d.cols;
+  if (M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
+  KArgs a;
+  a.A = static_cast<const float*>(d.A);
+  a.lda = 2 * d.lda;
+  a.strideA = 2 * d.strideA;
+  a.X = static_cast<const float*>(d.X);
+  a.ldx = 2 * d.ldx;
+  a.strideX = 2 * d.strideX;
+  a.C = static_cast<float*>(d.C);
+  a.ldc = 2 * d.ldc;
+  a.strideC = 2 * d.strideC;
+  a.part = static_cast<float*>(d.part);
+  a.M = M;
+  a.K = K;
+  a.N = d.N;
+  a.batch = d.batch;
+  int kchunk = K;
+  a.nsplit = d.nsplit > 1 ? d.nsplit : 1;
+  if (a.nsplit > 1) {
+    if (!d.part) return hipErrorInvalidValue;
+    kchunk = (K + a.nsplit - 1) / a.nsplit;
+    kchunk = (kchunk + KSTEP - 1) / KSTEP * KSTEP;
+  }
+  a.kchunk = kchunk;
+  const int TT = kgemm_thin_tiles(d.N);
+  a.nthin = (d.N + 8 * TT - 1) / (8 * TT);
+  a.nbig = (M + NWAVE * 16 * 2 - 1) / (NWAVE * 16 * 2);
+  const int64_t total = (int64_t)a.nbig * a.nthin * a.nsplit * d.batch;
+  if (total >= (int64_t)1 << 30) return hipErrorInvalidValue;
+  a.total = (int)total;
+  a.per = (a.total + 7) / 8;
+  a.avec = ((d.lda & 1) == 0 && (d.strideA & 1) == 0 && ((uintptr_t)d.A & 15) == 0) ? 1 : 0;
+  hipError_t e;
+  switch (d.mode) {
+    case KM_F32: e = d.herm ? launch_mode<KM_F32, true>(a, TT, s) : launch_mode<KM_F32, false>(a, TT, s); break;
+    case KM_BF16: e = d.herm ? launch_mode<KM_BF16, true>(a, TT, s) : launch_mode<KM_BF16, false>(a, TT, s); break;
+    case KM_BF16X3:
+      e = d.herm ? launch_mode<KM_BF16X3, true>(a, TT, s) : launch_mode<KM_BF16X3, false>(a, TT, s);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess || a.nsplit <= 1) return e;
+  const int64_t n = (int64_t)M * d.N * d.batch;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(kgemm_reduce_kernel, dim3(blocks), dim3(256), 0, s, (const float2*)d.part, a.nsplit, d.batch, M,
+                     d.N, (float2*)d.C, d.ldc, d.strideC);
+  return hipGetLastError();
+}
+
+}  // namespace tsvd

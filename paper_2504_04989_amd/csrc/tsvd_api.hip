@@ -45,9 +45,11 @@ struct Plan {
   size_t cs;  // bytes of one complex element in the working precision
   int nsplit_blk, kchunk_blk;   // split-K for K = n1 products (block Grams, projections)
   int nsplit_g, kchunk_g;       // split-K for G = T^H T (K = n2)
+  int kmode;                    // Krylov-product arithmetic (KM_*) when dt == DT_F32
+  int ks_ax, ks_ahy;            // K splits of the Krylov products A X and A^H Y
   // workspace offsets (bytes)
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
-      o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, total;
+      o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, total;
 };
 
 int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
@@ -77,8 +79,8 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   if (n3 > 4096) return fail(TSVD_EINVAL, "n3 must be <= 4096");
   if (n1 * n2 * n3 >= (int64_t)1 << 31 || n1 * n2 >= (int64_t)1 << 31)
     return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
-  if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32)
-    return fail(TSVD_EINVAL, "precision mode not supported by this build");
+  if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32 && prec != TSVD_PREC_BF16 && prec != TSVD_PREC_BF16X3)
+    return fail(TSVD_EINVAL, "unknown precision mode");
   if (op < TSVD_OP_RBK || op > TSVD_OP_PROJ_BWD) return fail(TSVD_EINVAL, "unsupported operation");
   p->n1 = n1;
   p->n2 = n2;
@@ -96,6 +98,10 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->nsplit_blk = split_for(n1, tb * ((m + 63) / 64), F, &p->kchunk_blk);
   const int64_t tm = (m + 63) / 64;
   p->nsplit_g = split_for(n2, tm * tm, F, &p->kchunk_g);
+  p->kmode = prec == TSVD_PREC_BF16 ? KM_BF16 : (prec == TSVD_PREC_BF16X3 ? KM_BF16X3 : KM_F32);
+  int kc_unused;
+  p->ks_ax = p->dt == DT_F32 ? kgemm_split((int)n1, (int)n2, (int)b, (int)F, &kc_unused) : 1;
+  p->ks_ahy = p->dt == DT_F32 ? kgemm_split((int)n2, (int)n1, (int)b, (int)F, &kc_unused) : 1;
 
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -135,6 +141,11 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_zbar = take(bwd ? (size_t)F * n1 * b * cs : 0);
   p->o_wbar = take(bwd ? (size_t)F * n1 * b * cs : 0);
   p->o_tbar = take(bwd ? (size_t)F * n2 * b * cs : 0);
+  {
+    const size_t kp_ax = p->ks_ax > 1 ? (size_t)p->ks_ax * F * n1 * b * 8 : 0;
+    const size_t kp_ahy = p->ks_ahy > 1 ? (size_t)p->ks_ahy * F * n2 * b * 8 : 0;
+    p->o_kpart = take(std::max(kp_ax, kp_ahy));
+  }
   p->total = o;
   return TSVD_OK;
 }
@@ -348,6 +359,29 @@ int orth_block(const Ctx& c, int i) {
 // Out (M x N, ld ldc) = A_f (n1 x n2) * X (n2 x N, ld ldx): the big products.
 int big_AX(const Ctx& c, const void* X, int64_t ldx, int64_t strideX, void* Out, int64_t ldo, int64_t strideO, int N) {
   const Plan& p = c.p;
+  if (p.dt == DT_F32) {
+    KGemmDesc k{};
+    k.A = c.at(p.o_abar);
+    k.lda = p.n2;
+    k.strideA = p.n1 * p.n2;
+    k.rows = (int)p.n1;
+    k.cols = (int)p.n2;
+    k.herm = false;
+    k.X = X;
+    k.ldx = ldx;
+    k.strideX = strideX;
+    k.C = Out;
+    k.ldc = ldo;
+    k.strideC = strideO;
+    k.N = N;
+    k.batch = (int)p.F;
+    k.mode = p.kmode;
+    k.nsplit = N == p.b ? p.ks_ax : 1;
+    k.part = c.at(p.o_kpart);
+    Timed tm_(K_GEMM_KRYLOV, c.s);
+    HIPCHK(kgemm(k, c.s));
+    return TSVD_OK;
+  }
   GemmDesc d = gd();
   d.A = c.at(p.o_abar);
   d.lda = p.n2;
@@ -377,6 +411,29 @@ int big_AX(const Ctx& c, const void* X, int64_t ldx, int64_t strideX, void* Out,
 int big_AhY(const Ctx& c, const void* Y, int64_t ldy, int64_t strideY, void* Out, int64_t ldo, int64_t strideO,
             int N) {
   const Plan& p = c.p;
+  if (p.dt == DT_F32) {
+    KGemmDesc k{};
+    k.A = c.at(p.o_abar);
+    k.lda = p.n2;
+    k.strideA = p.n1 * p.n2;
+    k.rows = (int)p.n1;
+    k.cols = (int)p.n2;
+    k.herm = true;
+    k.X = Y;
+    k.ldx = ldy;
+    k.strideX = strideY;
+    k.C = Out;
+    k.ldc = ldo;
+    k.strideC = strideO;
+    k.N = N;
+    k.batch = (int)p.F;
+    k.mode = p.kmode;
+    k.nsplit = N == p.b ? p.ks_ahy : 1;
+    k.part = c.at(p.o_kpart);
+    Timed tm_(K_GEMM_KRYLOV, c.s);
+    HIPCHK(kgemm(k, c.s));
+    return TSVD_OK;
+  }
   GemmDesc d = gd();
   d.A = c.at(p.o_abar);
   d.lda = p.n2;
@@ -840,6 +897,35 @@ int tsvd_diag_fft_c2r(const void* Xb, void* X, int64_t ntubes, int64_t n3, int d
   if (!X || !Xb || ntubes < 0 || n3 < 1 || n3 > 4096 || (dtype != 0 && dtype != 1))
     return fail(TSVD_EINVAL, "bad arguments");
   HIPCHK(fft_c2r(Xb, ntubes, X, ntubes, (int)n3, dtype == 0 ? DT_F64 : DT_F32, (hipStream_t)stream));
+  return TSVD_OK;
+}
+
+int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t rows, int64_t cols, int64_t N,
+                    int64_t batch, int mode, int nsplit, void* part, void* stream) {
+  if (!A || !X || !C || rows < 1 || cols < 1 || N < 1 || batch < 1 || mode < KM_F32 || mode > KM_BF16X3 ||
+      nsplit < 1 || nsplit > 64 || (nsplit > 1 && !part) || rows * cols >= ((int64_t)1 << 31) ||
+      N >= (1 << 20) || batch > 65535)
+    return fail(TSVD_EINVAL, "bad arguments");
+  const int64_t M = herm ? cols : rows, K = herm ? rows : cols;
+  KGemmDesc d{};
+  d.A = A;
+  d.lda = cols;
+  d.strideA = rows * cols;
+  d.rows = (int)rows;
+  d.cols = (int)cols;
+  d.herm = herm != 0;
+  d.X = X;
+  d.ldx = N;
+  d.strideX = K * N;
+  d.C = C;
+  d.ldc = N;
+  d.strideC = M * N;
+  d.N = (int)N;
+  d.batch = (int)batch;
+  d.mode = mode;
+  d.nsplit = nsplit;
+  d.part = part;
+  HIPCHK(kgemm(d, (hipStream_t)stream));
   return TSVD_OK;
 }
 
