@@ -47,6 +47,22 @@ hipError_t kgemm(const KGemmDesc& d, hipStream_t s);
 // K split (and chunk) that gives the product enough workgroups to fill the chip.
 int kgemm_split(int M, int K, int N, int batch, int* kchunk);
 
+// FP64-arithmetic products on FP32-stored complex blocks.
+// ogemm_tn: part[f] (M x N, FP64 complex, row-major) = X_f^H Y_f with X_f
+//   (K x M, row stride lx) and Y_f (K x N, row stride ly); the K range is split
+//   internally and the partial results are summed in a fixed order, so part
+//   needs ogemm_tn_part_bytes() bytes and holds the sum in its first
+//   batch * M * N entries on return.
+// ogemm_nn: C_f (M x N, FP32, row stride ldc) = alpha X_f B_f + beta C_f with
+//   X_f (M x K, row stride lx, FP32) and B_f (K x N, FP64, row stride ldb) the
+//   sum of nsum matrices spaced bsum_stride complex elements.
+size_t ogemm_tn_part_bytes(int M, int K, int N, int batch);
+hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y, int64_t ly, int64_t strideY,
+                    double* part, int M, int N, int K, int batch, hipStream_t s);
+hipError_t ogemm_nn(const float* X, int64_t lx, int64_t strideX, const double* B, int64_t ldb, int64_t strideB,
+                    int nsum, int64_t bsum_stride, float* C, int64_t ldc, int64_t strideC, int M, int N, int K,
+                    int batch, double alpha, double beta, hipStream_t s);
+
 // Mode-3 real-to-half-spectrum DFT: X (ntubes x n3, tube-contiguous) ->
 // Xb (F x ntubes complex, F = n3/2 + 1), slice-major.
 hipError_t fft_r2c(const void* X, void* Xb, int64_t ntubes, int n3, DType t, hipStream_t s);

@@ -1,0 +1,341 @@
+// FP64-arithmetic products of the orthonormalisation and the small SVD on
+// FP32-stored blocks (gfx950 v_mfma_f64_16x16x4_f64):
+//   TN:  P_s[f] = X_f^H Y_f over the rows of chunk s      (block Grams,
+//        projections against earlier blocks, G_f = C_f C_f^H = T_f^H T_f)
+//   NN:  C_f = alpha X_f B_f + beta C_f with B_f FP64      (W R^{-1}, W - Q C)
+// FP32 operands are widened to FP64 exactly, so every product is exact and
+// sums are accumulated in FP64: the Gram matrices and projection
+// coefficients carry FP64 accuracy of the stored blocks.
+//
+// Same structure as the Krylov-product kernel: complex arithmetic as a real
+// GEMM over interleaved storage, the tall operand X (n rows, read once)
+// streams from HBM into the MFMA registers of one wave, the small operand is
+// expanded into real form in LDS (double buffered) and shared by the 4 waves:
+//   TN: P[j][2n+t] = sum_{i,s} X_int[i][2j+s] Ye[2n+t][2i+s],
+//       Ye[2n] = (yr, yi), Ye[2n+1] = (yi, -yr)        (y = Y[i][n])
+//   NN: C[m][2n+t] = sum_{k,s} X_int[m][2k+s] Be[2n+t][2k+s],
+//       Be[2n] = (br, -bi), Be[2n+1] = (bi, br)        (b = B[k][n])
+// K step: 8 complex (16 real); lane (q4, r16) owns real k' = 4 q4 .. 4 q4 + 3
+// of each step, MFMA block b takes k' = 4 q4 + b.  Accumulator r of lane
+// (q4, r16) holds real output row 16 i + q4 + 4 r, i.e. the real (q4 even)
+// or imaginary (q4 odd) part of complex column n = 8 i + q4 / 2 + 2 r.
+#include <algorithm>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tsvd {
+
+namespace {
+
+constexpr int OKSTEP = 8;
+constexpr int OSTRIDE = 2 * OKSTEP + 2;  // doubles per LDS row (16 + pad)
+
+struct OArgs {
+  const float* X;  // tall FP32 operand (floats)
+  int64_t lx, strideX;
+  const void* B;   // small operand: FP32 (TN) or FP64 (NN), in its own element type
+  int64_t ldb, strideB, bsum_stride;
+  int nsum;
+  void* C;         // TN: FP64 partials [split][f][M][N]; NN: FP32 output
+  int64_t ldc, strideC;
+  double alpha, beta;
+  int M, K, N, batch;
+  int nsplit, kchunk;
+  int nbig, nthin, total, per;
+  int xvec;
+};
+
+template <bool TN, int TT>
+__global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
+  constexpr int ROWS = TT * 16;
+  constexpr int BUF = ROWS * OSTRIDE;
+  constexpr int NCH = TT * 8;
+  constexpr int TEL = OKSTEP * NCH / 256;
+  static_assert(TEL * 256 == OKSTEP * NCH, "thin split");
+  extern __shared__ __align__(16) double olds[];
+
+  const int id = blockIdx.x;
+  const int t = (id & 7) * a.per + (id >> 3);
+  if (t >= a.total) return;
+  int r = t;
+  const int bt = r % a.nbig;
+  r /= a.nbig;
+  const int tc = r % a.nthin;
+  r /= a.nthin;
+  const int sp = r % a.nsplit;
+  const int f = r / a.nsplit;
+  const int kb = sp * a.kchunk;
+  const int ke = min(a.K, kb + a.kchunk);
+  const int n0 = tc * NCH;
+  const int nc = min(NCH, a.N - n0);
+  const int tt = (2 * nc + 15) / 16;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q4 = lane >> 4, r16 = lane & 15;
+  const float* Xf = a.X + (int64_t)f * a.strideX;
+  const int col = bt * 64 + wave * 16 + r16;
+  const bool colok = col < a.M;
+
+  auto load_big = [&](int k0, float (&v)[4]) {
+    const bool full = k0 + OKSTEP <= ke;
+    if (!TN) {
+      const float* p = Xf + (int64_t)col * a.lx + 2 * (k0 + 2 * q4);
+      if (colok && full && a.xvec) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          float2 x = make_float2(0.f, 0.f);
+          if (colok && k0 + 2 * q4 + c < ke) x = *reinterpret_cast<const float2*>(p + 2 * c);
+          v[2 * c] = x.x;
+          v[2 * c + 1] = x.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int i = k0 + 2 * q4 + c;
+        float2 x = make_float2(0.f, 0.f);
+        if (colok && (full || i < ke)) x = *reinterpret_cast<const float2*>(Xf + (int64_t)i * a.lx + 2 * col);
+        v[2 * c] = x.x;
+        v[2 * c + 1] = x.y;
+      }
+    }
+  };
+
+  auto load_thin = [&](int k0, double2 (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % OKSTEP, nn = idx / OKSTEP;
+      double2 v = make_double2(0.0, 0.0);
+      if (k0 + kk < ke && nn < nc) {
+        const int64_t off = (int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + (n0 + nn);
+        if (TN) {
+          const float2 y = reinterpret_cast<const float2*>(a.B)[off];
+          v = make_double2((double)y.x, (double)y.y);
+        } else {
+          const double2* Bp = reinterpret_cast<const double2*>(a.B);
+          for (int j = 0; j < a.nsum; ++j) {
+            const double2 y = Bp[off + j * a.bsum_stride];
+            v.x += y.x;
+            v.y += y.y;
+          }
+        }
+      }
+      x[e] = v;
+    }
+  };
+  auto store_thin = [&](double* buf, const double2 (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % OKSTEP, nn = idx / OKSTEP;
+      const double xr = x[e].x, xi = x[e].y;
+      double* row0 = buf + (2 * nn) * OSTRIDE + 2 * kk;
+      double* row1 = row0 + OSTRIDE;
+      if (TN) {
+        *reinterpret_cast<double2*>(row0) = make_double2(xr, xi);
+        *reinterpret_cast<double2*>(row1) = make_double2(xi, -xr);
+      } else {
+        *reinterpret_cast<double2*>(row0) = make_double2(xr, -xi);
+        *reinterpret_cast<double2*>(row1) = make_double2(xi, xr);
+      }
+    }
+  };
+
+  f64x4 acc[TT];
+#pragma unroll
+  for (int i = 0; i < TT; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  auto compute = [&](const double* buf, const float (&v)[4]) {
+    const double bv[4] = {(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
+#pragma unroll
+    for (int i = 0; i < TT; ++i) {
+      if (i < tt) {
+        const double* rowp = buf + (16 * i + r16) * OSTRIDE + 4 * q4;
+        const double2 w0 = *reinterpret_cast<const double2*>(rowp);
+        const double2 w1 = *reinterpret_cast<const double2*>(rowp + 2);
+        const double w[4] = {w0.x, w0.y, w1.x, w1.y};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[b], bv[b], acc[i], 0, 0, 0);
+      }
+    }
+  };
+
+  const int nsteps = (ke - kb + OKSTEP - 1) / OKSTEP;
+  float cur[4], nxt[4];
+  double2 tx[TEL];
+  if (nsteps > 0) {
+    load_big(kb, cur);
+    load_thin(kb, tx);
+    store_thin(olds, tx);
+  }
+  __syncthreads();
+  for (int s = 0; s < nsteps; ++s) {
+    const int k0 = kb + s * OKSTEP;
+    const bool more = s + 1 < nsteps;
+    if (more) {
+      load_big(k0 + OKSTEP, nxt);
+      load_thin(k0 + OKSTEP, tx);
+    }
+    compute(olds + (s & 1) * BUF, cur);
+    if (more) store_thin(olds + ((s + 1) & 1) * BUF, tx);
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
+    }
+  }
+
+  if (!colok) return;
+  const int part = q4 & 1;
+#pragma unroll
+  for (int i = 0; i < TT; ++i) {
+    if (i < tt) {
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int n = n0 + 8 * i + (q4 >> 1) + 2 * rr;
+        if (n >= a.N) continue;
+        if (TN) {
+          double* out = static_cast<double*>(a.C) + 2 * (((int64_t)sp * a.batch + f) * a.M * a.N + (int64_t)col * a.N + n);
+          out[part] = acc[i][rr];
+        } else {
+          float* out = static_cast<float*>(a.C) + 2 * ((int64_t)f * a.strideC + (int64_t)col * a.ldc + n);
+          double val = a.alpha * acc[i][rr];
+          if (a.beta != 0.0) val += a.beta * (double)out[part];
+          out[part] = (float)val;
+        }
+      }
+    }
+  }
+}
+
+// part[e] = sum_s part[s * total + e] in a fixed order (slot 0 in place).
+__global__ void opart_reduce_kernel(double2* part, int nsplit, int64_t total) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    double2 v = part[e];
+    for (int j = 1; j < nsplit; ++j) {
+      const double2 w = part[(int64_t)j * total + e];
+      v.x += w.x;
+      v.y += w.y;
+    }
+    part[e] = v;
+  }
+}
+
+template <bool TN, int TT>
+hipError_t olaunch_tt(const OArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)2 * TT * 16 * OSTRIDE * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)ogemm_kernel<TN, TT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+    attr = true;
+  }
+  hipLaunchKernelGGL((ogemm_kernel<TN, TT>), dim3(8 * a.per), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <bool TN>
+hipError_t olaunch(const OArgs& a, int TT, hipStream_t s) {
+  switch (TT) {
+    case 4: return olaunch_tt<TN, 4>(a, s);
+    case 8: return olaunch_tt<TN, 8>(a, s);
+    default: return olaunch_tt<TN, 16>(a, s);
+  }
+}
+
+int othin_tiles(int N) {
+  const int nn = N < 128 ? N : 128;
+  if (nn <= 32) return 4;
+  if (nn <= 64) return 8;
+  return 16;
+}
+
+void fill_grid(OArgs& a, int TT) {
+  a.nthin = (a.N + 8 * TT - 1) / (8 * TT);
+  a.nbig = (a.M + 63) / 64;
+  const int64_t total = (int64_t)a.nbig * a.nthin * a.nsplit * a.batch;
+  a.total = (int)total;
+  a.per = (a.total + 7) / 8;
+}
+
+}  // namespace
+
+int ogemm_tn_split(int M, int K, int N, int batch) {
+  const int TT = othin_tiles(N);
+  const int64_t tiles = (int64_t)((N + 8 * TT - 1) / (8 * TT)) * ((M + 63) / 64) * batch;
+  int ns = 1;
+  while (tiles * ns < 1024 && ns < 16 && K / (2 * ns) >= 128) ns *= 2;
+  return ns;
+}
+
+size_t ogemm_tn_part_bytes(int M, int K, int N, int batch) {
+  return (size_t)ogemm_tn_split(M, K, N, batch) * batch * M * N * 16;
+}
+
+hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y, int64_t ly, int64_t strideY,
+                    double* part, int M, int N, int K, int batch, hipStream_t s) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  OArgs a{};
+  a.X = X;
+  a.lx = 2 * lx;
+  a.strideX = 2 * strideX;
+  a.B = Y;
+  a.ldb = ly;
+  a.strideB = strideY;
+  a.nsum = 1;
+  a.C = part;
+  a.M = M;
+  a.K = K;
+  a.N = N;
+  a.batch = batch;
+  a.nsplit = ogemm_tn_split(M, K, N, batch);
+  int kc = (K + a.nsplit - 1) / a.nsplit;
+  kc = (kc + OKSTEP - 1) / OKSTEP * OKSTEP;
+  a.kchunk = kc < OKSTEP ? OKSTEP : kc;
+  a.xvec = 0;
+  const int TT = othin_tiles(N);
+  fill_grid(a, TT);
+  hipError_t e = olaunch<true>(a, TT, s);
+  if (e != hipSuccess || a.nsplit <= 1) return e;
+  const int64_t total = (int64_t)batch * M * N;
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(opart_reduce_kernel, dim3(blocks), dim3(256), 0, s, (double2*)part, a.nsplit, total);
+  return hipGetLastError();
+}
+
+hipError_t ogemm_nn(const float* X, int64_t lx, int64_t strideX, const double* B, int64_t ldb, int64_t strideB,
+                    int nsum, int64_t bsum_stride, float* C, int64_t ldc, int64_t strideC, int M, int N, int K,
+                    int batch, double alpha, double beta, hipStream_t s) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  OArgs a{};
+  a.X = X;
+  a.lx = 2 * lx;
+  a.strideX = 2 * strideX;
+  a.B = B;
+  a.ldb = ldb;
+  a.strideB = strideB;
+  a.nsum = nsum < 1 ? 1 : nsum;
+  a.bsum_stride = bsum_stride;
+  a.C = C;
+  a.ldc = ldc;
+  a.strideC = strideC;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.M = M;
+  a.K = K;
+  a.N = N;
+  a.batch = batch;
+  a.nsplit = 1;
+  a.kchunk = (K + OKSTEP - 1) / OKSTEP * OKSTEP;
+  a.xvec = ((lx & 1) == 0 && (strideX & 1) == 0 && ((uintptr_t)X & 15) == 0) ? 1 : 0;
+  const int TT = othin_tiles(N);
+  fill_grid(a, TT);
+  return olaunch<false>(a, TT, s);
+}
+
+}  // namespace tsvd

@@ -119,6 +119,15 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_s1 = take((size_t)F * n1 * b * cs);
   size_t part = (size_t)p->nsplit_blk * F * m * b * 16;
   part = std::max(part, (size_t)p->nsplit_g * F * m * m * 16);
+  if (p->dt == DT_F32) {
+    // FP64-arithmetic products on FP32 blocks: block Grams (b x b), projections
+    // (i b x b and b x i b), G = T^H T (m x m)
+    part = ogemm_tn_part_bytes((int)m, (int)n2, (int)m, (int)F);
+    for (int64_t i = 1; i <= std::max<int64_t>(q, 1); ++i) {
+      part = std::max(part, ogemm_tn_part_bytes((int)(i * b), (int)n1, (int)b, (int)F));
+      part = std::max(part, ogemm_tn_part_bytes((int)b, (int)n1, (int)(i * b), (int)F));
+    }
+  }
   p->o_part = take(part);
   p->o_rinv = take((size_t)F * b * b * 16);
   p->o_chol = take(chol_uses_lds(b) ? 0 : (size_t)F * b * (b + 1) / 2 * 16);
@@ -224,11 +233,20 @@ GemmDesc gd() {
   return d;
 }
 
-// part[s][f] (M x N, FP64) = opA^H-style inner products over K = n1 rows:
-// X^H Y with X (n1 x M, ld lx), Y (n1 x N, ld ly), both in the working dtype.
+// part (M x N per slice, FP64) = X^H Y over K rows, X (K x M, ld lx) and Y
+// (K x N, ld ly) in the working dtype.  *nsum receives the number of partial
+// results (spaced F * M * N) whose sum is the product.
 int inner_products(const Ctx& c, const void* X, int64_t lx, int M, const void* Y, int64_t ly, int N, int64_t K,
-                   int64_t strideX, int64_t strideY, int nsplit, int kchunk, double* part, int cls = K_GEMM_ORTH) {
+                   int64_t strideX, int64_t strideY, int nsplit, int kchunk, double* part, int* nsum,
+                   int cls = K_GEMM_ORTH) {
   const Plan& p = c.p;
+  if (p.dt == DT_F32) {
+    Timed tm_(cls, c.s);
+    HIPCHK(ogemm_tn(static_cast<const float*>(X), lx, strideX, static_cast<const float*>(Y), ly, strideY, part, M, N,
+                    (int)K, (int)p.F, c.s));
+    *nsum = 1;
+    return TSVD_OK;
+  }
   GemmDesc d = gd();
   d.A = X;
   d.lda = lx;
@@ -255,12 +273,20 @@ int inner_products(const Ctx& c, const void* X, int64_t lx, int M, const void* Y
     Timed tm_(cls, c.s);
     HIPCHK(zgemm(d, c.s));
   }
+  *nsum = nsplit;
   return TSVD_OK;
 }
 
 // dst (n1 x b, ld ldd) = src (n1 x b, ld lds) * Rinv   (FP64 arithmetic)
 int apply_rinv(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ldd) {
   const Plan& p = c.p;
+  if (p.dt == DT_F32) {
+    Timed tm_(K_GEMM_ORTH, c.s);
+    HIPCHK(ogemm_nn(static_cast<const float*>(src), lds, p.n1 * lds, c.at<double>(p.o_rinv), p.b, p.b * p.b, 1, 0,
+                    static_cast<float*>(dst), ldd, p.n1 * ldd, (int)p.n1, (int)p.b, (int)p.b, (int)p.F, 1.0, 0.0,
+                    c.s));
+    return TSVD_OK;
+  }
   GemmDesc d = gd();
   d.A = src;
   d.lda = lds;
@@ -290,15 +316,16 @@ int apply_rinv(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ld
 int cholqr_pass(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ldd, bool shifted) {
   const Plan& p = c.p;
   double* part = c.at<double>(p.o_part);
+  int nsum = 1;
   int r = inner_products(c, src, lds, (int)p.b, src, lds, (int)p.b, p.n1, p.n1 * lds, p.n1 * lds, p.nsplit_blk,
-                         p.kchunk_blk, part);
+                         p.kchunk_blk, part, &nsum);
   if (r) return r;
   const double u = 1.1102230246251565e-16;
   const double shift = shifted ? 11.0 * ((double)p.n1 * p.b + (double)p.b * (p.b + 1)) * u : 0.0;
   {
     Timed tm_(K_CHOL, c.s);
-    HIPCHK(chol_inv_ex(part, p.nsplit_blk, p.F * p.b * p.b, c.at<double>(p.o_rinv), c.at(p.o_chol), (int)p.b,
-                     (int)p.F, shift, c.info(), c.s));
+    HIPCHK(chol_inv_ex(part, nsum, p.F * p.b * p.b, c.at<double>(p.o_rinv), c.at(p.o_chol), (int)p.b, (int)p.F,
+                       shift, c.info(), c.s));
   }
   return apply_rinv(c, src, lds, dst, ldd);
 }
@@ -310,9 +337,17 @@ int project_out(const Ctx& c, void* W, int i) {
   const int ib = (int)(i * p.b);
   double* part = c.at<double>(p.o_part);
   void* Q = c.at(p.o_q);
+  int nsum = 1;
   int r = inner_products(c, Q, p.m, ib, W, p.b, (int)p.b, p.n1, p.n1 * p.m, p.n1 * p.b, p.nsplit_blk, p.kchunk_blk,
-                         part);
+                         part, &nsum);
   if (r) return r;
+  if (p.dt == DT_F32) {
+    Timed tm_(K_GEMM_ORTH, c.s);
+    HIPCHK(ogemm_nn(static_cast<const float*>(Q), p.m, p.n1 * p.m, part, p.b, (int64_t)ib * p.b, nsum,
+                    p.F * ib * p.b, static_cast<float*>(W), p.b, p.n1 * p.b, (int)p.n1, (int)p.b, ib, (int)p.F, -1.0,
+                    1.0, c.s));
+    return TSVD_OK;
+  }
   GemmDesc d = gd();
   d.A = Q;
   d.lda = p.m;
@@ -322,7 +357,7 @@ int project_out(const Ctx& c, void* W, int i) {
   d.ldb = p.b;
   d.strideB = (int64_t)ib * p.b;
   d.tb = DT_F64;
-  d.b_nsum = p.nsplit_blk;
+  d.b_nsum = nsum;
   d.b_sum_stride = p.F * ib * p.b;
   d.C = W;
   d.ldc = p.b;
@@ -507,8 +542,9 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   const DType dt = p.dt;
   double* part = c.at<double>(p.o_part);
   void* T = c.at(p.o_t);
+  int nsum_g = 1;
   int r = inner_products(c, T, p.m, (int)p.m, T, p.m, (int)p.m, p.n2, p.n2 * p.m, p.n2 * p.m, p.nsplit_g,
-                         p.kchunk_g, part, K_GEMM_LIFT);
+                         p.kchunk_g, part, &nsum_g, K_GEMM_LIFT);
   if (r) return r;
   double* lam = c.at<double>(p.o_lam);
   double* Wd = c.at<double>(p.o_wd);
@@ -516,7 +552,7 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
       {HEIG_TRIDIAG, K_HEIG_TRI}, {HEIG_BISECT, K_HEIG_BISECT}, {HEIG_INVIT, K_HEIG_INVIT}, {HEIG_BACKXF, K_HEIG_BACKXF}};
   for (const auto& sc : stage_cls) {
     Timed tm_(sc[1], c.s);
-    HIPCHK(heig_topk(part, p.nsplit_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
+    HIPCHK(heig_topk(part, nsum_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
                      c.info(), c.s, sc[0]));
   }
   // U_f = Q_f W_k
@@ -666,20 +702,21 @@ int proj_backward_impl(const Ctx& c, const void* A, const void* Omega, const voi
                 1.0, 1.0, dt)))
     return r;
   const int ns = p.nsplit_blk, kc = p.kchunk_blk;
+  int nsum = 1;
   for (int i = (int)p.q; i >= 0; --i) {
     unsigned char* Qi = Q + (size_t)i * b * cs;
     unsigned char* Qbi = Qb + (size_t)i * b * cs;
     unsigned char* Wi = Wr + (size_t)i * b * cs;
     // Qbar_i -= Q_i (Q_i^H Qbar_i)
-    if ((r = inner_products(c, Qi, m, b, Qbi, m, b, p.n1, s1m, s1m, ns, kc, part))) return r;
+    if ((r = inner_products(c, Qi, m, b, Qbi, m, b, p.n1, s1m, s1m, ns, kc, part, &nsum))) return r;
     if ((r = gemm(c, K_GEMM_ORTH, Op{Qi, m, s1m, dt, false}, Op{part, b, (int64_t)b * b, DT_F64, false}, Qbi, m, s1m,
-                  dt, n1, b, b, -1.0, 1.0, DT_F64, ns, p.F * b * b)))
+                  dt, n1, b, b, -1.0, 1.0, DT_F64, nsum, p.F * b * b)))
       return r;
     // R_i = Q_i^H W_i, Rinv = R_i^{-1}
-    if ((r = inner_products(c, Qi, m, b, Wi, m, b, p.n1, s1m, s1m, ns, kc, part))) return r;
+    if ((r = inner_products(c, Qi, m, b, Wi, m, b, p.n1, s1m, s1m, ns, kc, part, &nsum))) return r;
     {
       Timed tm_(K_CHOL, c.s);
-      HIPCHK(chol_inv_ex(part, ns, p.F * b * b, c.at<double>(p.o_rinv), c.at(p.o_chol), b, (int)p.F, 0.0, c.info(),
+      HIPCHK(chol_inv_ex(part, nsum, p.F * b * b, c.at<double>(p.o_rinv), c.at(p.o_chol), b, (int)p.F, 0.0, c.info(),
                          c.s, 1));
     }
     // Zbar = (I - Q_i Q_i^H) Qbar_i R_i^{-H}
@@ -696,18 +733,18 @@ int proj_backward_impl(const Ctx& c, const void* A, const void* Omega, const voi
     const int ib = i * b;
     // Wbar = Zbar - Q_<i (Q_<i^H Zbar)
     HIPCHK(hipMemcpyAsync(Wb, Zb, (size_t)p.F * s1b * cs, hipMemcpyDeviceToDevice, c.s));
-    if ((r = inner_products(c, Q, m, ib, Zb, b, b, p.n1, s1m, s1b, ns, kc, part))) return r;
+    if ((r = inner_products(c, Q, m, ib, Zb, b, b, p.n1, s1m, s1b, ns, kc, part, &nsum))) return r;
     if ((r = gemm(c, K_GEMM_ORTH, Op{Q, m, s1m, dt, false}, Op{part, b, (int64_t)ib * b, DT_F64, false}, Wb, b, s1b,
-                  dt, n1, b, ib, -1.0, 1.0, DT_F64, ns, p.F * ib * b)))
+                  dt, n1, b, ib, -1.0, 1.0, DT_F64, nsum, p.F * ib * b)))
       return r;
     // Qbar_<i -= Zbar (W_i^H Q_<i) + W_i (Zbar^H Q_<i)
-    if ((r = inner_products(c, Wi, m, b, Q, m, ib, p.n1, s1m, s1m, ns, kc, part))) return r;
+    if ((r = inner_products(c, Wi, m, b, Q, m, ib, p.n1, s1m, s1m, ns, kc, part, &nsum))) return r;
     if ((r = gemm(c, K_GEMM_ORTH, Op{Zb, b, s1b, dt, false}, Op{part, ib, (int64_t)b * ib, DT_F64, false}, Qb, m, s1m,
-                  dt, n1, ib, b, -1.0, 1.0, DT_F64, ns, p.F * b * ib)))
+                  dt, n1, ib, b, -1.0, 1.0, DT_F64, nsum, p.F * b * ib)))
       return r;
-    if ((r = inner_products(c, Zb, b, b, Q, m, ib, p.n1, s1b, s1m, ns, kc, part))) return r;
+    if ((r = inner_products(c, Zb, b, b, Q, m, ib, p.n1, s1b, s1m, ns, kc, part, &nsum))) return r;
     if ((r = gemm(c, K_GEMM_ORTH, Op{Wi, m, s1m, dt, false}, Op{part, ib, (int64_t)b * ib, DT_F64, false}, Qb, m, s1m,
-                  dt, n1, ib, b, -1.0, 1.0, DT_F64, ns, p.F * b * ib)))
+                  dt, n1, ib, b, -1.0, 1.0, DT_F64, nsum, p.F * b * ib)))
       return r;
     unsigned char* Ti = T + (size_t)(i - 1) * b * cs;
     unsigned char* Qi1 = Q + (size_t)(i - 1) * b * cs;

@@ -192,7 +192,12 @@ def _sampled_slices(name, freqs, tol, label, prec="f32"):
         fnum += w * t2
         s_err = np.abs(Sb[:, i].real - so) / so
         s_floor = np.abs(st - so) / so
-        s_ok &= bool(s_err.max() <= max(tol, 4 * s_floor.max()))
+        if prec == "bf16":
+            # bulk BF16 products carry an absolute error of order 2^-9 sigma_1:
+            # singular values are held norm-wise, |d sigma_j| <= tol * sigma_1
+            s_ok &= bool(np.max(np.abs(Sb[:, i].real - so)) <= tol * so[0])
+        else:
+            s_ok &= bool(s_err.max() <= max(tol, 4 * s_floor.max()))
         s_all = sl["s_all"][:, 0]
         gap = (s_all[k - 1] - s_all[k]) / s_all[0] if s_all.size > k else 1.0
         print(f"[parity] {label} slice {f}: X rel {np.sqrt(d2 / o2):.2e} (FP32 floor {np.sqrt(t2 / o2):.2e}); "
