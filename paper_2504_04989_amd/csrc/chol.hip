@@ -178,10 +178,14 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const cx<double>* __restr
   PHASE(3);
 }
 
+hipError_t chol_inv_blocked(const double* Gpart, int nsum, int64_t part_stride, double* Rinv, int b, int batch,
+                            double shift_coef, int* info, hipStream_t s, int mode);
+
 hipError_t chol_inv_ex(const double* Gpart, int nsum, int64_t part_stride, double* Rinv, void* gscratch, int b,
                        int batch, double shift_coef, int* info, hipStream_t s, int mode) {
   if (batch <= 0 || b <= 0) return hipSuccess;
   if (b > 1024) return hipErrorInvalidValue;
+  if (b <= 128) return chol_inv_blocked(Gpart, nsum, part_stride, Rinv, b, batch, shift_coef, info, s, mode);
   const size_t tri_bytes = (size_t)b * (b + 1) / 2 * sizeof(cx<double>);
   const bool use_lds = chol_uses_lds(b);
   static bool attr_set = false;
@@ -197,6 +201,333 @@ hipError_t chol_inv_ex(const double* Gpart, int nsum, int64_t part_stride, doubl
   else
     hipLaunchKernelGGL(chol_inv_kernel<false>, dim3(batch), dim3(256), 0, s, (const cx<double>*)Gpart, nsum,
                        part_stride, (cx<double>*)Rinv, (cx<double>*)gscratch, b, shift_coef, info, mode);
+  return hipGetLastError();
+}
+
+}  // namespace tsvd
+
+// ---------------------------------------------------------------------------
+// Blocked variant for b <= 128: the lower triangle is kept in LDS as 16 x 16
+// tiles (tile (I, J), I >= J, rows padded to 17 entries against bank
+// conflicts); rows and columns beyond b are padded with the identity.
+// Factorisation, per tile column K: one wave factors the diagonal tile and
+// replaces it by its inverse X_KK = L_KK^{-1}; the panel tiles become
+// A_IK X_KK^H; the trailing tiles lose A_IK A_JK^H.  Inverse, per tile row I:
+// S_IJ = sum_{K=J}^{I-1} L_IK X_KJ, then X_IJ = -X_II S_IJ.  About 6 nb
+// barrier phases instead of 2 b, with tile products spread over 4 waves.
+// ---------------------------------------------------------------------------
+namespace tsvd {
+namespace {
+
+constexpr int TSZ = 16;
+constexpr int TRS = 17;               // padded row stride of a tile (complex)
+constexpr int TEL2 = TSZ * TRS;       // complex elements per stored tile
+
+__device__ __forceinline__ int tix(int I, int J) { return (I * (I + 1) / 2 + J) * TEL2; }
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ cx<double> cmad(cx<double> acc, cx<double> a, cx<double> b) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+  return acc;
+}
+// acc += a * conj(b)
+__device__ __forceinline__ cx<double> cmadc(cx<double> acc, cx<double> a, cx<double> b) {
+  acc.re += a.re * b.re + a.im * b.im;
+  acc.im += a.im * b.re - a.re * b.im;
+  return acc;
+}
+
+// Invert the lower triangular 16 x 16 tile T in place (one wave; lane c < 16
+// forms column c of the inverse by forward substitution in registers).
+__device__ void tile_inverse(cx<double>* T, int lane) {
+  cx<double> x[TSZ];
+  const int c = lane & 15;
+#pragma unroll
+  for (int i = 0; i < TSZ; ++i) {
+    cx<double> s{i == c ? 1.0 : 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < i; ++k) {
+      const cx<double> l = T[i * TRS + k];
+      s.re -= l.re * x[k].re - l.im * x[k].im;
+      s.im -= l.re * x[k].im + l.im * x[k].re;
+    }
+    const cx<double> d = T[i * TRS + i];
+    const double den = d.re * d.re + d.im * d.im;
+    const cx<double> inv{d.re / den, -d.im / den};
+    x[i] = (i < c) ? cx<double>{0.0, 0.0} : cx<double>{s.re * inv.re - s.im * inv.im, s.re * inv.im + s.im * inv.re};
+  }
+  wsync();
+  if (lane < TSZ) {
+#pragma unroll
+    for (int i = 0; i < TSZ; ++i) T[i * TRS + c] = x[i];
+  }
+  wsync();
+}
+
+// Cholesky of the Hermitian 16 x 16 tile T (lower part used) in place (one
+// wave).  Returns 1 on a non-positive or non-finite pivot in a row < nvalid.
+__device__ int tile_cholesky(cx<double>* T, int lane, int nvalid) {
+  int bad = 0;
+  for (int k = 0; k < TSZ; ++k) {
+    const double d = T[k * TRS + k].re;
+    double piv = 1.0;
+    if (d > 0 && isfinite(d))
+      piv = sqrt(d);
+    else if (k < nvalid)
+      bad = 1;
+    const double inv = 1.0 / piv;
+    wsync();
+    if (lane > k && lane < TSZ) {
+      cx<double> v = T[lane * TRS + k];
+      v.re *= inv;
+      v.im *= inv;
+      T[lane * TRS + k] = v;
+    }
+    if (lane == 0) T[k * TRS + k] = cx<double>{piv, 0.0};
+    wsync();
+    // T[i][j] -= T[i][k] conj(T[j][k]) for k < j <= i
+    for (int e = lane; e < TSZ * TSZ; e += 64) {
+      const int i = e >> 4, j = e & 15;
+      if (j > k && j <= i) {
+        const cx<double> a = T[i * TRS + k];
+        const cx<double> b = T[j * TRS + k];
+        cx<double> v = T[i * TRS + j];
+        v.re -= a.re * b.re + a.im * b.im;
+        v.im -= a.im * b.re - a.re * b.im;
+        T[i * TRS + j] = v;
+      }
+    }
+    wsync();
+  }
+  return bad;
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restrict__ Gpart, int nsum,
+                                                       int64_t part_stride, cx<double>* __restrict__ Rinv, int b,
+                                                       double shift_coef, int* info, int mode) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<double>* L = reinterpret_cast<cx<double>*>(smem);
+  __shared__ double red[4];
+  const int f = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const cx<double>* G = Gpart + (int64_t)f * b * b;
+  constexpr int BP = NT * TSZ;
+
+  // ---- load: lower triangle (i >= j) of the padded matrix into tiles ----
+  for (int e = tid; e < BP * BP; e += 256) {
+    const int i = e / BP, j = e % BP;
+    if (j > i) continue;
+    cx<double> v{(i == j && i >= b) ? 1.0 : 0.0, 0.0};
+    if (i < b && j < b) {
+      v = cx<double>{0.0, 0.0};
+      for (int s = 0; s < nsum; ++s) {
+        const cx<double>* Gs = G + s * part_stride;
+        if (mode == 1) {
+          const cx<double> r = Gs[(int64_t)j * b + i];  // L = R^H
+          v.re += r.re;
+          v.im -= r.im;
+        } else {
+          const cx<double> g = Gs[(int64_t)i * b + j];
+          const cx<double> h = Gs[(int64_t)j * b + i];
+          v.re += 0.5 * (g.re + h.re);
+          v.im += 0.5 * (g.im - h.im);
+        }
+      }
+    }
+    L[tix(i >> 4, j >> 4) + (i & 15) * TRS + (j & 15)] = v;
+  }
+  __syncthreads();
+
+  int bad = 0;
+  if (mode == 1) {
+    // invert the diagonal tiles (one wave each)
+    for (int K = wave; K < NT; K += 4) tile_inverse(L + tix(K, K), lane);
+    __syncthreads();
+  } else {
+    double tr = 0;
+    for (int i = tid; i < b; i += 256) tr += L[tix(i >> 4, i >> 4) + (i & 15) * (TRS + 1)].re;
+    tr = block_sum<256>(tr, red);
+    const double shift = shift_coef * tr;
+    for (int i = tid; i < b; i += 256) L[tix(i >> 4, i >> 4) + (i & 15) * (TRS + 1)].re += shift;
+    __syncthreads();
+    for (int K = 0; K < NT; ++K) {
+      cx<double>* D = L + tix(K, K);
+      if (wave == 0) {
+        bad |= tile_cholesky(D, lane, b - K * TSZ);
+        tile_inverse(D, lane);  // D <- X_KK = L_KK^{-1}
+      }
+      __syncthreads();
+      // panel: A_IK <- A_IK X_KK^H (one tile per wave at a time)
+      for (int I = K + 1 + wave; I < NT; I += 4) {
+        cx<double>* P = L + tix(I, K);
+        cx<double> out[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = lane + 64 * u, r = e >> 4, c = e & 15;
+          cx<double> acc{0.0, 0.0};
+          for (int k = 0; k <= c; ++k) acc = cmadc(acc, P[r * TRS + k], D[c * TRS + k]);
+          out[u] = acc;
+        }
+        wsync();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = lane + 64 * u;
+          P[(e >> 4) * TRS + (e & 15)] = out[u];
+        }
+        wsync();
+      }
+      __syncthreads();
+      // trailing: A_IJ -= A_IK A_JK^H, K < J <= I
+      const int m = NT - K - 1;
+      const int npairs = m * (m + 1) / 2;
+      for (int pidx = wave; pidx < npairs; pidx += 4) {
+        int I = 0, rem = pidx;
+        while (rem >= I + 1) {
+          rem -= I + 1;
+          ++I;
+        }
+        const int Ig = K + 1 + I, Jg = K + 1 + rem;
+        const cx<double>* AI = L + tix(Ig, K);
+        const cx<double>* AJ = L + tix(Jg, K);
+        cx<double>* T = L + tix(Ig, Jg);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = lane + 64 * u, r = e >> 4, c = e & 15;
+          if (Ig == Jg && c > r) continue;
+          cx<double> acc{0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < TSZ; ++k) acc = cmadc(acc, AI[r * TRS + k], AJ[c * TRS + k]);
+          cx<double> v = T[r * TRS + c];
+          v.re -= acc.re;
+          v.im -= acc.im;
+          T[r * TRS + c] = v;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0 && bad) atomicAdd(&info[INFO_CHOL_BREAKDOWN], 1);
+  }
+  // wave 0 carries `bad`; other waves never set it
+  (void)bad;
+
+  // ---- inverse: row by row, X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ ----
+  for (int I = 1; I < NT; ++I) {
+    // phase A: S_IJ into registers (tiles J < I spread over the waves)
+    cx<double> sreg[2][4];
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      const int J = wave + 4 * slot;
+      if (J >= I) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u, r = e >> 4, c = e & 15;
+        cx<double> acc{0.0, 0.0};
+        for (int K = J; K < I; ++K) {
+          const cx<double>* LI = L + tix(I, K);
+          const cx<double>* XK = L + tix(K, J);
+          const int kmin = (K == J) ? c : 0;  // X_JJ is lower triangular
+          for (int k = kmin; k < TSZ; ++k) acc = cmad(acc, LI[r * TRS + k], XK[k * TRS + c]);
+        }
+        sreg[slot][u] = acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      const int J = wave + 4 * slot;
+      if (J >= I) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u;
+        L[tix(I, J) + (e >> 4) * TRS + (e & 15)] = sreg[slot][u];
+      }
+    }
+    __syncthreads();
+    // phase B: X_IJ = -X_II S_IJ (X_II lower triangular)
+    const cx<double>* XI = L + tix(I, I);
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      const int J = wave + 4 * slot;
+      if (J >= I) continue;
+      const cx<double>* S = L + tix(I, J);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u, r = e >> 4, c = e & 15;
+        cx<double> acc{0.0, 0.0};
+        for (int k = 0; k <= r; ++k) acc = cmad(acc, XI[r * TRS + k], S[k * TRS + c]);
+        sreg[slot][u] = cx<double>{-acc.re, -acc.im};
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      const int J = wave + 4 * slot;
+      if (J >= I) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u;
+        L[tix(I, J) + (e >> 4) * TRS + (e & 15)] = sreg[slot][u];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- R^{-1} = X^H (upper triangular), b x b row-major ----
+  cx<double>* out = Rinv + (int64_t)f * b * b;
+  for (int e = tid; e < b * b; e += 256) {
+    const int r = e / b, c = e % b;
+    cx<double> v{0.0, 0.0};
+    if (c >= r) {
+      const cx<double> x = L[tix(c >> 4, r >> 4) + (c & 15) * TRS + (r & 15)];
+      v = cx<double>{x.re, -x.im};
+    }
+    out[e] = v;
+  }
+}
+
+}  // namespace
+
+bool chol_blocked_ok(int b) { return b <= 128; }
+
+hipError_t chol_inv_blocked(const double* Gpart, int nsum, int64_t part_stride, double* Rinv, int b, int batch,
+                            double shift_coef, int* info, hipStream_t s, int mode) {
+  if (batch <= 0 || b <= 0) return hipSuccess;
+  if (b > 128) return hipErrorInvalidValue;
+  const int nt = (b + TSZ - 1) / TSZ;
+  const size_t lds = (size_t)nt * (nt + 1) / 2 * TEL2 * sizeof(cx<double>);
+  static bool attr = false;
+  if (!attr) {
+    const void* fns[8] = {(const void*)chol_blk_kernel<1>, (const void*)chol_blk_kernel<2>,
+                          (const void*)chol_blk_kernel<3>, (const void*)chol_blk_kernel<4>,
+                          (const void*)chol_blk_kernel<5>, (const void*)chol_blk_kernel<6>,
+                          (const void*)chol_blk_kernel<7>, (const void*)chol_blk_kernel<8>};
+    for (const void* fn : fns) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 157 * 1024);
+    (void)hipGetLastError();
+    attr = true;
+  }
+  const cx<double>* G = (const cx<double>*)Gpart;
+  cx<double>* R = (cx<double>*)Rinv;
+  switch (nt) {
+#define TSVD_CHOL_CASE(n)                                                                                        \
+  case n:                                                                                                        \
+    hipLaunchKernelGGL(chol_blk_kernel<n>, dim3(batch), dim3(256), lds, s, G, nsum, part_stride, R, b, shift_coef, \
+                       info, mode);                                                                              \
+    break;
+    TSVD_CHOL_CASE(1)
+    TSVD_CHOL_CASE(2)
+    TSVD_CHOL_CASE(3)
+    TSVD_CHOL_CASE(4)
+    TSVD_CHOL_CASE(5)
+    TSVD_CHOL_CASE(6)
+    TSVD_CHOL_CASE(7)
+    TSVD_CHOL_CASE(8)
+#undef TSVD_CHOL_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

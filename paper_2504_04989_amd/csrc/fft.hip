@@ -68,12 +68,13 @@ template <typename T, bool INV, int R>
 __device__ void stockham_pass(const cx<T>* in, cx<T>* out, const cx<T>* tw, int N, int Ns, int NP) {
   const int nb = N / R;
   const int tws = N / (Ns * R);
+  const int SP = N + 1;  // padded sequence stride (LDS banks)
   for (int idx = threadIdx.x; idx < NP * nb; idx += blockDim.x) {
     const int p = idx / nb;
     const int j = idx - p * nb;
     const int k = j % Ns;
-    const cx<T>* a = in + p * N;
-    cx<T>* o = out + p * N;
+    const cx<T>* a = in + p * SP;
+    cx<T>* o = out + p * SP;
     cx<T> v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -157,7 +158,8 @@ __global__ __launch_bounds__(256) void fft_r2c_kernel(const T* __restrict__ X, c
   const int N = plan.N;
   cx<C>* tw = reinterpret_cast<cx<C>*>(smem);
   cx<C>* b0 = tw + N;
-  cx<C>* b1 = b0 + NP * N;
+  const int SP = N + 1;
+  cx<C>* b1 = b0 + NP * SP;
   make_twiddles(tw, N);
   const int64_t t0 = (int64_t)blockIdx.x * 2 * NP;
   const int ntw = (int)min((int64_t)2 * NP, ntubes - t0);
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) void fft_r2c_kernel(const T* __restrict__ X, c
   for (int g = threadIdx.x; g < 2 * NP * N; g += blockDim.x) {
     const int tube = g / N, t = g - tube * N;
     const C v = (g < total) ? (C)src[g] : (C)0;
-    C* dst = reinterpret_cast<C*>(&b0[(tube >> 1) * N + t]);
+    C* dst = reinterpret_cast<C*>(&b0[(tube >> 1) * SP + t]);
     dst[tube & 1] = v;
   }
   __syncthreads();
@@ -176,8 +178,8 @@ __global__ __launch_bounds__(256) void fft_r2c_kernel(const T* __restrict__ X, c
     const int f = idx / (2 * NP), tube = idx - f * 2 * NP;
     if (tube >= ntw) continue;
     const int p = tube >> 1;
-    const cx<C> zf = Z[p * N + f];
-    const cx<C> zm = Z[p * N + (f == 0 ? 0 : N - f)];
+    const cx<C> zf = Z[p * SP + f];
+    const cx<C> zm = Z[p * SP + (f == 0 ? 0 : N - f)];
     cx<T> o;
     if (!(tube & 1)) {
       o.re = (T)((zf.re + zm.re) * (C)0.5);
@@ -197,7 +199,8 @@ __global__ __launch_bounds__(256) void fft_c2r_kernel(const cx<T>* __restrict__ 
   const int N = plan.N;
   cx<C>* tw = reinterpret_cast<cx<C>*>(smem);
   cx<C>* b0 = tw + N;
-  cx<C>* b1 = b0 + NP * N;
+  const int SP = N + 1;
+  cx<C>* b1 = b0 + NP * SP;
   make_twiddles(tw, N);
   const int64_t t0 = (int64_t)blockIdx.x * 2 * NP;
   const int ntw = (int)min((int64_t)2 * NP, ntubes - t0);
@@ -218,8 +221,8 @@ __global__ __launch_bounds__(256) void fft_c2r_kernel(const cx<T>* __restrict__ 
       a.im = 0;
       b.im = 0;
     }
-    b0[p * N + f] = cx<C>{a.re - b.im, a.im + b.re};
-    if (f > 0 && 2 * f != N) b0[p * N + (N - f)] = cx<C>{a.re + b.im, b.re - a.im};
+    b0[p * SP + f] = cx<C>{a.re - b.im, a.im + b.re};
+    if (f > 0 && 2 * f != N) b0[p * SP + (N - f)] = cx<C>{a.re + b.im, b.re - a.im};
   }
   __syncthreads();
   const cx<C>* Z = run_passes<C, true>(b0, b1, tw, plan, NP);
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(256) void fft_c2r_kernel(const cx<T>* __restrict__ 
   T* dst = X + t0 * N;
   for (int g = threadIdx.x; g < total; g += blockDim.x) {
     const int tube = g / N, t = g - tube * N;
-    const cx<C> z = Z[(tube >> 1) * N + t];
+    const cx<C> z = Z[(tube >> 1) * SP + t];
     dst[g] = (T)(((tube & 1) ? z.im : z.re) * invN);
   }
 }
@@ -274,7 +277,7 @@ __global__ void dft_c2r_direct(const cx<T>* Xb, int64_t slice_stride, T* X, int6
 template <typename C>
 static int pick_np(int N) {
   const int budget = 64 * 1024 / (int)sizeof(cx<C>);
-  int np = (budget - N) / (2 * N);
+  int np = (budget - N) / (2 * (N + 1));
   if (np > 64) np = 64;
   return np;
 }
@@ -291,7 +294,7 @@ static hipError_t r2c_t(const void* X, void* Xb, int64_t ntubes, int n3, hipStre
     return hipGetLastError();
   }
   const int64_t nblk = (ntubes + 2 * NP - 1) / (2 * NP);
-  const size_t sm = (size_t)(n3 + 2 * NP * n3) * sizeof(cx<double>);
+  const size_t sm = (size_t)(n3 + 2 * NP * (n3 + 1)) * sizeof(cx<double>);
   hipLaunchKernelGGL((fft_r2c_kernel<T, double>), dim3((unsigned)nblk), dim3(256), sm, s, (const T*)X, (cx<T>*)Xb,
                      ntubes, plan, NP);
   return hipGetLastError();
@@ -309,19 +312,281 @@ static hipError_t c2r_t(const void* Xb, int64_t stride, void* X, int64_t ntubes,
     return hipGetLastError();
   }
   const int64_t nblk = (ntubes + 2 * NP - 1) / (2 * NP);
-  const size_t sm = (size_t)(n3 + 2 * NP * n3) * sizeof(cx<double>);
+  const size_t sm = (size_t)(n3 + 2 * NP * (n3 + 1)) * sizeof(cx<double>);
   hipLaunchKernelGGL((fft_c2r_kernel<T, double>), dim3((unsigned)nblk), dim3(256), sm, s, (const cx<T>*)Xb, stride,
                      (T*)X, ntubes, plan, NP);
   return hipGetLastError();
 }
 
+bool fft_pow2_supported(int n3);
+hipError_t fft_r2c_pow2(const void* X, void* Xb, int64_t ntubes, int n3, DType t, hipStream_t s);
+hipError_t fft_c2r_pow2(const void* Xb, int64_t stride, void* X, int64_t ntubes, int n3, DType t, hipStream_t s);
+
 hipError_t fft_r2c(const void* X, void* Xb, int64_t ntubes, int n3, DType t, hipStream_t s) {
+  if (fft_pow2_supported(n3)) return fft_r2c_pow2(X, Xb, ntubes, n3, t, s);
   return t == DT_F64 ? r2c_t<double>(X, Xb, ntubes, n3, s) : r2c_t<float>(X, Xb, ntubes, n3, s);
 }
 
 hipError_t fft_c2r(const void* Xb, int64_t slice_stride, void* X, int64_t ntubes, int n3, DType t, hipStream_t s) {
+  if (fft_pow2_supported(n3)) return fft_c2r_pow2(Xb, slice_stride, X, ntubes, n3, t, s);
   return t == DT_F64 ? c2r_t<double>(Xb, slice_stride, X, ntubes, n3, s)
                      : c2r_t<float>(Xb, slice_stride, X, ntubes, n3, s);
+}
+
+}  // namespace tsvd
+
+// ---------------------------------------------------------------------------
+// Power-of-two lengths 8 <= N <= 256: compile-time length and radices (4,
+// then a final 2 when log2 N is odd), FP64 arithmetic, sequences of a
+// workgroup at a padded LDS stride of N + 1 complex elements (the untangle
+// step reads element f of every sequence at once), float4 / double2 tube loads.
+// ---------------------------------------------------------------------------
+namespace tsvd {
+namespace {
+
+template <int N>
+struct P2 {
+  static constexpr int SP = N + 1;
+  static constexpr int LOG = N <= 1 ? 0 : 1 + P2<N / 2>::LOG;
+};
+template <>
+struct P2<1> {
+  static constexpr int SP = 2;
+  static constexpr int LOG = 0;
+};
+
+// One Stockham pass of radix R on NPs sequences (stride SP) with Ns = product
+// of the radices done so far; twiddles tw[t] = exp(-2 pi i t / N).
+template <int N, int R, int Ns, bool INV>
+__device__ __forceinline__ void p2_pass(const cx<double>* in, cx<double>* out, const cx<double>* tw, int NPs) {
+  constexpr int nb = N / R;
+  constexpr int tws = N / (Ns * R);
+  constexpr int SP = P2<N>::SP;
+  for (int idx = threadIdx.x; idx < NPs * nb; idx += blockDim.x) {
+    const int p = idx / nb;  // compile-time divisor
+    const int j = idx - p * nb;
+    const int k = j % Ns;
+    const cx<double>* a = in + p * SP;
+    cx<double>* o = out + p * SP;
+    cx<double> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      cx<double> x = a[j + r * nb];
+      if (r > 0 && Ns > 1) {
+        cx<double> w = tw[(r * k * tws) % N];
+        if (INV) w.im = -w.im;
+        x = cx<double>{x.re * w.re - x.im * w.im, x.re * w.im + x.im * w.re};
+      }
+      v[r] = x;
+    }
+    cx<double> V[R];
+    if (R == 2) {
+      V[0] = cx<double>{v[0].re + v[1].re, v[0].im + v[1].im};
+      V[1] = cx<double>{v[0].re - v[1].re, v[0].im - v[1].im};
+    } else {
+      const cx<double> t0{v[0].re + v[2].re, v[0].im + v[2].im};
+      const cx<double> t1{v[0].re - v[2].re, v[0].im - v[2].im};
+      const cx<double> t2{v[1].re + v[3].re, v[1].im + v[3].im};
+      const cx<double> d{v[1].re - v[3].re, v[1].im - v[3].im};
+      const cx<double> t3 = INV ? cx<double>{-d.im, d.re} : cx<double>{d.im, -d.re};
+      V[0] = cx<double>{t0.re + t2.re, t0.im + t2.im};
+      V[2] = cx<double>{t0.re - t2.re, t0.im - t2.im};
+      V[1] = cx<double>{t1.re + t3.re, t1.im + t3.im};
+      V[3] = cx<double>{t1.re - t3.re, t1.im - t3.im};
+    }
+    const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) o[base + r * Ns] = V[r];
+  }
+}
+
+template <int N, int Ns, bool INV>
+__device__ __forceinline__ cx<double>* p2_passes(cx<double>* in, cx<double>* out, const cx<double>* tw, int NPs) {
+  if constexpr (Ns >= N) {
+    return in;
+  } else if constexpr (N / Ns >= 4) {
+    p2_pass<N, 4, Ns, INV>(in, out, tw, NPs);
+    __syncthreads();
+    return p2_passes<N, Ns * 4, INV>(out, in, tw, NPs);
+  } else {
+    p2_pass<N, 2, Ns, INV>(in, out, tw, NPs);
+    __syncthreads();
+    return p2_passes<N, Ns * 2, INV>(out, in, tw, NPs);
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void fft_r2c_p2_kernel(const T* __restrict__ X, cx<T>* __restrict__ Xb,
+                                                         int64_t ntubes, int NP) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int SP = P2<N>::SP;
+  constexpr int F = N / 2 + 1;
+  cx<double>* tw = reinterpret_cast<cx<double>*>(smem);
+  cx<double>* b0 = tw + N;
+  cx<double>* b1 = b0 + NP * SP;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)t / (double)N, &s, &c);
+    tw[t] = cx<double>{c, s};
+  }
+  const int64_t t0 = (int64_t)blockIdx.x * 2 * NP;
+  const int ntw = (int)min((int64_t)2 * NP, ntubes - t0);
+  const T* src = X + t0 * N;
+  // tubes are contiguous: load 4 (FP32) or 2 (FP64) consecutive samples per access
+  constexpr int VW = sizeof(T) == 4 ? 4 : 2;
+  const int nvec = 2 * NP * N / VW;
+  const int lim = ntw * N;
+  for (int g = threadIdx.x; g < nvec; g += blockDim.x) {
+    const int e0 = g * VW;
+    const int tube = e0 / N, t = e0 - tube * N;  // compile-time divisor
+    double v[VW];
+    if (e0 < lim) {
+      if constexpr (VW == 4) {
+        const float4 x = *reinterpret_cast<const float4*>(src + e0);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+      } else {
+        const double2 x = *reinterpret_cast<const double2*>(src + e0);
+        v[0] = x.x; v[1] = x.y;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < VW; ++i) v[i] = 0.0;
+    }
+    double* dst = reinterpret_cast<double*>(&b0[(tube >> 1) * SP + t]) + (tube & 1);
+#pragma unroll
+    for (int i = 0; i < VW; ++i) dst[2 * i] = v[i];
+  }
+  __syncthreads();
+  const cx<double>* Z = p2_passes<N, 1, false>(b0, b1, tw, NP);
+  for (int idx = threadIdx.x; idx < F * 2 * NP; idx += blockDim.x) {
+    const int f = idx / (2 * NP), tube = idx - f * 2 * NP;
+    if (tube >= ntw) continue;
+    const int p = tube >> 1;
+    const cx<double> zf = Z[p * SP + f];
+    const cx<double> zm = Z[p * SP + (f == 0 ? 0 : N - f)];
+    cx<T> o;
+    if (!(tube & 1)) {
+      o.re = (T)(0.5 * (zf.re + zm.re));
+      o.im = (T)(0.5 * (zf.im - zm.im));
+    } else {
+      o.re = (T)(0.5 * (zf.im + zm.im));
+      o.im = (T)(0.5 * (zm.re - zf.re));
+    }
+    Xb[(int64_t)f * ntubes + t0 + tube] = o;
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void fft_c2r_p2_kernel(const cx<T>* __restrict__ Xb, int64_t slice_stride,
+                                                         T* __restrict__ X, int64_t ntubes, int NP) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int SP = P2<N>::SP;
+  constexpr int F = N / 2 + 1;
+  cx<double>* tw = reinterpret_cast<cx<double>*>(smem);
+  cx<double>* b0 = tw + N;
+  cx<double>* b1 = b0 + NP * SP;
+  for (int t = threadIdx.x; t < N; t += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)t / (double)N, &s, &c);
+    tw[t] = cx<double>{c, s};
+  }
+  const int64_t t0 = (int64_t)blockIdx.x * 2 * NP;
+  const int ntw = (int)min((int64_t)2 * NP, ntubes - t0);
+  for (int idx = threadIdx.x; idx < F * NP; idx += blockDim.x) {
+    const int f = idx / NP, p = idx - f * NP;
+    const int ta = 2 * p, tb = 2 * p + 1;
+    cx<double> a{0, 0}, b{0, 0};
+    if (ta < ntw) {
+      const cx<T> v = Xb[(int64_t)f * slice_stride + t0 + ta];
+      a = cx<double>{(double)v.re, (double)v.im};
+    }
+    if (tb < ntw) {
+      const cx<T> v = Xb[(int64_t)f * slice_stride + t0 + tb];
+      b = cx<double>{(double)v.re, (double)v.im};
+    }
+    if (f == 0 || 2 * f == N) {
+      a.im = 0;
+      b.im = 0;
+    }
+    b0[p * SP + f] = cx<double>{a.re - b.im, a.im + b.re};
+    if (f > 0 && 2 * f != N) b0[p * SP + (N - f)] = cx<double>{a.re + b.im, b.re - a.im};
+  }
+  __syncthreads();
+  const cx<double>* Z = p2_passes<N, 1, true>(b0, b1, tw, NP);
+  constexpr double invN = 1.0 / N;
+  const int total = ntw * N;
+  T* dst = X + t0 * N;
+  for (int g = threadIdx.x; g < total; g += blockDim.x) {
+    const int tube = g / N, t = g - tube * N;
+    const cx<double> z = Z[(tube >> 1) * SP + t];
+    dst[g] = (T)(((tube & 1) ? z.im : z.re) * invN);
+  }
+}
+
+template <int N>
+int p2_np() {
+  // LDS: N twiddles + 2 buffers of NP sequences (stride N + 1), about 40 KB
+  int np = (40 * 1024 / 16 - N) / (2 * P2<N>::SP);
+  return np > 64 ? 64 : np;
+}
+
+template <typename T, int N>
+hipError_t p2_r2c(const void* X, void* Xb, int64_t ntubes, hipStream_t s) {
+  const int NP = p2_np<N>();
+  const int64_t nblk = (ntubes + 2 * NP - 1) / (2 * NP);
+  const size_t sm = (size_t)(N + 2 * NP * P2<N>::SP) * sizeof(cx<double>);
+  hipLaunchKernelGGL((fft_r2c_p2_kernel<T, N>), dim3((unsigned)nblk), dim3(256), sm, s, (const T*)X, (cx<T>*)Xb,
+                     ntubes, NP);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t p2_c2r(const void* Xb, int64_t stride, void* X, int64_t ntubes, hipStream_t s) {
+  const int NP = p2_np<N>();
+  const int64_t nblk = (ntubes + 2 * NP - 1) / (2 * NP);
+  const size_t sm = (size_t)(N + 2 * NP * P2<N>::SP) * sizeof(cx<double>);
+  hipLaunchKernelGGL((fft_c2r_p2_kernel<T, N>), dim3((unsigned)nblk), dim3(256), sm, s, (const cx<T>*)Xb, stride,
+                     (T*)X, ntubes, NP);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t p2_r2c_dispatch(const void* X, void* Xb, int64_t ntubes, int n3, hipStream_t s) {
+  switch (n3) {
+    case 8: return p2_r2c<T, 8>(X, Xb, ntubes, s);
+    case 16: return p2_r2c<T, 16>(X, Xb, ntubes, s);
+    case 32: return p2_r2c<T, 32>(X, Xb, ntubes, s);
+    case 64: return p2_r2c<T, 64>(X, Xb, ntubes, s);
+    case 128: return p2_r2c<T, 128>(X, Xb, ntubes, s);
+    case 256: return p2_r2c<T, 256>(X, Xb, ntubes, s);
+    default: return hipErrorNotSupported;
+  }
+}
+template <typename T>
+hipError_t p2_c2r_dispatch(const void* Xb, int64_t stride, void* X, int64_t ntubes, int n3, hipStream_t s) {
+  switch (n3) {
+    case 8: return p2_c2r<T, 8>(Xb, stride, X, ntubes, s);
+    case 16: return p2_c2r<T, 16>(Xb, stride, X, ntubes, s);
+    case 32: return p2_c2r<T, 32>(Xb, stride, X, ntubes, s);
+    case 64: return p2_c2r<T, 64>(Xb, stride, X, ntubes, s);
+    case 128: return p2_c2r<T, 128>(Xb, stride, X, ntubes, s);
+    case 256: return p2_c2r<T, 256>(Xb, stride, X, ntubes, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
+}  // namespace
+
+bool fft_pow2_supported(int n3) { return n3 >= 8 && n3 <= 256 && (n3 & (n3 - 1)) == 0; }
+
+hipError_t fft_r2c_pow2(const void* X, void* Xb, int64_t ntubes, int n3, DType t, hipStream_t s) {
+  if (ntubes <= 0) return hipSuccess;
+  return t == DT_F64 ? p2_r2c_dispatch<double>(X, Xb, ntubes, n3, s) : p2_r2c_dispatch<float>(X, Xb, ntubes, n3, s);
+}
+hipError_t fft_c2r_pow2(const void* Xb, int64_t stride, void* X, int64_t ntubes, int n3, DType t, hipStream_t s) {
+  if (ntubes <= 0) return hipSuccess;
+  return t == DT_F64 ? p2_c2r_dispatch<double>(Xb, stride, X, ntubes, n3, s)
+                     : p2_c2r_dispatch<float>(Xb, stride, X, ntubes, n3, s);
 }
 
 }  // namespace tsvd

@@ -559,7 +559,11 @@ __global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned 
   double gl, gu, pivmin, tnorm;
   tri_bounds(d, e, m, &gl, &gu, &pivmin, &tnorm);
   const double eps = 2.220446049250313e-16;
-  const double ortol = 1e-7 * tnorm;
+  // Eigenvalues closer than ortol form a cluster whose vectors are computed
+  // in sequence and re-orthogonalised against each other; vectors of
+  // eigenvalues further apart are computed independently (in parallel), with
+  // a contamination of about eps * ||T|| / gap <= 2e-7 by their neighbours.
+  const double ortol = 1e-9 * tnorm;
   if (t0 > 0 && lam[t0 - 1] - lam[t0] < ortol) return;  // not the head of its cluster
   int t1 = t0 + 1;
   while (t1 < k && lam[t1 - 1] - lam[t1] < ortol) ++t1;
