@@ -60,8 +60,6 @@ __device__ __forceinline__ uint32_t bf16_bits(float x) {
   __bf16 h = (__bf16)x;
   return (uint32_t)__builtin_bit_cast(unsigned short, h);
 }
-__device__ __forceinline__ float bf16_val(float x) { return (float)(__bf16)x; }
-__device__ __forceinline__ uint32_t pack2(float a, float b) { return bf16_bits(a) | (bf16_bits(b) << 16); }
 
 template <int MODE>
 struct Lds {
@@ -70,7 +68,7 @@ struct Lds {
   static constexpr int PLANES = MODE == KM_BF16X3 ? 2 : 1;
 };
 
-template <int MODE, bool HN, int TT, int TB>
+template <int MODE, bool HN, int TT, int TB, bool AVEC>
 __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   typedef Lds<MODE> L;
   constexpr int ROWS = TT * 16;
@@ -102,13 +100,56 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   const int q4 = lane >> 4, r16 = lane & 15;
   const float* Af = a.A + (int64_t)f * a.strideA;
   const float* Xf = a.X + (int64_t)f * a.strideX;
-  int col[TB];
+  int col[TB], colc[TB];
   bool colok[TB];
 #pragma unroll
   for (int u = 0; u < TB; ++u) {
     col[u] = bt * (NWAVE * 16 * TB) + wave * 16 * TB + u * 16 + r16;
     colok[u] = col[u] < a.M;
+    colc[u] = colok[u] ? col[u] : a.M - 1;  // clamped: loads stay in bounds, results unused
   }
+
+  // ---- full K steps: every load is issued unconditionally (clamped
+  // addresses, zero by select) so that the compiler's wait counts can leave
+  // the prefetches of later steps in flight ----
+  auto load_big_full = [&](int k0, float (&v)[TB][8]) {
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      if (!HN) {
+        const float* p = Af + (int64_t)colc[u] * a.lda + 2 * (k0 + 4 * q4);
+        if (AVEC) {
+          const float4 x0 = *reinterpret_cast<const float4*>(p);
+          const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
+          v[u][0] = x0.x; v[u][1] = x0.y; v[u][2] = x0.z; v[u][3] = x0.w;
+          v[u][4] = x1.x; v[u][5] = x1.y; v[u][6] = x1.z; v[u][7] = x1.w;
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float2 x = *reinterpret_cast<const float2*>(p + 2 * c);
+            v[u][2 * c] = x.x;
+            v[u][2 * c + 1] = x.y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float2 x = *reinterpret_cast<const float2*>(Af + (int64_t)(k0 + 4 * q4 + c) * a.lda + 2 * colc[u]);
+          v[u][2 * c] = x.x;
+          v[u][2 * c + 1] = x.y;
+        }
+      }
+    }
+  };
+  auto load_thin_full = [&](int k0, float2 (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % KSTEP, nn = idx / KSTEP;
+      const bool ok = nn < nc;
+      const float2 v = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + kk) * a.ldx + 2 * (n0 + (ok ? nn : 0)));
+      x[e] = ok ? v : make_float2(0.f, 0.f);
+    }
+  };
 
   // ---- big operand: 8 reals (4 complex along K) per lane and tile ----
   auto load_big = [&](int k0, float (&v)[TB][8]) {
@@ -117,7 +158,7 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
     for (int u = 0; u < TB; ++u) {
       if (!HN) {
         const float* p = Af + (int64_t)col[u] * a.lda + 2 * (k0 + 4 * q4);
-        if (colok[u] && full && a.avec) {
+        if (colok[u] && full && AVEC) {
           const float4 x0 = *reinterpret_cast<const float4*>(p);
           const float4 x1 = *reinterpret_cast<const float4*>(p + 4);
           v[u][0] = x0.x; v[u][1] = x0.y; v[u][2] = x0.z; v[u][3] = x0.w;
@@ -162,20 +203,24 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
       const int idx = tid + e * 256;
       const int kk = idx % KSTEP, nn = idx / KSTEP;
       const float xr = x[e].x, xi = x[e].y;
-      // rows 2nn (real part of the output) and 2nn + 1 (imaginary part)
-      const float r0a = xr, r0b = HN ? xi : -xi;
-      const float r1a = xi, r1b = HN ? -xr : xr;
+      // rows 2nn (real part of the output) and 2nn + 1 (imaginary part):
+      //   A X  : (xr, -xi), (xi, xr);   A^H Y : (xr, xi), (xi, -xr)
       uint32_t* row0 = buf + (2 * nn) * L::STRIDE;
       uint32_t* row1 = row0 + L::STRIDE;
       if (MODE == KM_F32) {
-        *reinterpret_cast<float2*>(row0 + 2 * kk) = make_float2(r0a, r0b);
-        *reinterpret_cast<float2*>(row1 + 2 * kk) = make_float2(r1a, r1b);
+        *reinterpret_cast<float2*>(row0 + 2 * kk) = make_float2(xr, HN ? xi : -xi);
+        *reinterpret_cast<float2*>(row1 + 2 * kk) = make_float2(xi, HN ? -xr : xr);
       } else {
-        row0[kk] = pack2(r0a, r0b);
-        row1[kk] = pack2(r1a, r1b);
+        // each value is rounded once; negation flips the bf16 sign bit
+        const __bf16 hr = (__bf16)xr, hi = (__bf16)xi;
+        const uint32_t br = (uint32_t)__builtin_bit_cast(unsigned short, hr);
+        const uint32_t bi = (uint32_t)__builtin_bit_cast(unsigned short, hi);
+        row0[kk] = HN ? (br | (bi << 16)) : (br | ((bi ^ 0x8000u) << 16));
+        row1[kk] = HN ? (bi | ((br ^ 0x8000u) << 16)) : (bi | (br << 16));
         if (MODE == KM_BF16X3) {
-          row0[PLANE + kk] = pack2(r0a - bf16_val(r0a), r0b - bf16_val(r0b));
-          row1[PLANE + kk] = pack2(r1a - bf16_val(r1a), r1b - bf16_val(r1b));
+          const uint32_t lr = bf16_bits(xr - (float)hr), li = bf16_bits(xi - (float)hi);
+          row0[PLANE + kk] = HN ? (lr | (li << 16)) : (lr | ((li ^ 0x8000u) << 16));
+          row1[PLANE + kk] = HN ? (li | ((lr ^ 0x8000u) << 16)) : (li | (lr << 16));
         }
       }
     }
@@ -236,32 +281,46 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
     }
   };
 
-  // ---- main loop: LDS double buffer for the thin operand, register prefetch for A_f ----
-  const int nsteps = (ke - kb + KSTEP - 1) / KSTEP;
-  float cur[TB][8], nxt[TB][8];
+  // ---- main loop over the full K steps: LDS double buffer for the thin
+  // operand, A_f fetched two steps ahead into a ring of three register sets
+  // (unrolled by three so that every set keeps a fixed role).  Loads complete
+  // in issue order, so the thin block needed at the end of a step is requested
+  // before the A_f prefetch; prefetch indices past the last full step are
+  // clamped (the data is not used). ----
+  const int nfull = (ke - kb) / KSTEP;
+  const bool tail = kb + nfull * KSTEP < ke;
+  float bq0[TB][8], bq1[TB][8], bq2[TB][8];
   float2 tx[TEL];
-  if (nsteps > 0) {
-    load_big(kb, cur);
-    load_thin(kb, tx);
+  if (nfull > 0) {
+    load_big_full(kb, bq0);
+    load_big_full(kb + (nfull > 1 ? KSTEP : 0), bq1);
+    load_thin_full(kb, tx);
     store_thin(lds, tx);
   }
   __syncthreads();
-  for (int s = 0; s < nsteps; ++s) {
-    const int k0 = kb + s * KSTEP;
-    const bool more = s + 1 < nsteps;
-    if (more) {
-      load_big(k0 + KSTEP, nxt);
-      load_thin(k0 + KSTEP, tx);
+  auto step = [&](int s, const float (&cur)[TB][8], float (&pre)[TB][8]) {
+    const int sn = s + 1 < nfull ? s + 1 : nfull - 1;
+    const int sp2 = s + 2 < nfull ? s + 2 : nfull - 1;
+    load_thin_full(kb + sn * KSTEP, tx);
+    load_big_full(kb + sp2 * KSTEP, pre);
+    if (s < nfull) {
+      compute(lds + (s & 1) * BUF, cur);
+      if (s + 1 < nfull) store_thin(lds + ((s + 1) & 1) * BUF, tx);
+      __syncthreads();
     }
-    compute(lds + (s & 1) * BUF, cur);
-    if (more) store_thin(lds + ((s + 1) & 1) * BUF, tx);
+  };
+  for (int s = 0; s < nfull; s += 3) {
+    step(s, bq0, bq2);
+    step(s + 1, bq1, bq0);
+    step(s + 2, bq2, bq1);
+  }
+  if (tail) {  // ragged last step, guarded loads
+    const int k0 = kb + nfull * KSTEP;
+    load_thin(k0, tx);
+    store_thin(lds + (nfull & 1) * BUF, tx);
+    load_big(k0, bq0);
     __syncthreads();
-    if (more) {
-#pragma unroll
-      for (int u = 0; u < TB; ++u)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) cur[u][j] = nxt[u][j];
-    }
+    compute(lds + (nfull & 1) * BUF, bq0);
   }
 
   // ---- epilogue: acc[i][u][r] = C_int[col][16 i + 4 q4 + r] -> complex n = n0 + 8 i + 2 q4 + {0, 1} ----
@@ -307,19 +366,26 @@ __global__ void kgemm_reduce_kernel(const float2* __restrict__ part, int nsplit,
   }
 }
 
-template <int MODE, bool HN, int TT>
-hipError_t launch_tt(const KArgs& a, hipStream_t s) {
+template <int MODE, bool HN, int TT, bool AVEC>
+hipError_t launch_tta(const KArgs& a, hipStream_t s) {
   constexpr int TB = 2;
   const size_t lds = (size_t)2 * TT * 16 * Lds<MODE>::STRIDE * Lds<MODE>::PLANES * 4;
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)kgemm_kernel<MODE, HN, TT, TB>,
+    (void)hipFuncSetAttribute((const void*)kgemm_kernel<MODE, HN, TT, TB, AVEC>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL((kgemm_kernel<MODE, HN, TT, TB>), dim3(8 * a.per), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((kgemm_kernel<MODE, HN, TT, TB, AVEC>), dim3(8 * a.per), dim3(256), lds, s, a);
   return hipGetLastError();
+}
+
+template <int MODE, bool HN, int TT>
+hipError_t launch_tt(const KArgs& a, hipStream_t s) {
+  // vector loads only matter for A X (rows of A_f along K)
+  if (!HN && a.avec) return launch_tta<MODE, HN, TT, true>(a, s);
+  return launch_tta<MODE, HN, TT, false>(a, s);
 }
 
 template <int MODE, bool HN>

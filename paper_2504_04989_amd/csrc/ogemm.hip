@@ -46,7 +46,7 @@ struct OArgs {
   int xvec;
 };
 
-template <bool TN, int TT>
+template <bool TN, int TT, bool XVEC>
 __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
   constexpr int ROWS = TT * 16;
   constexpr int BUF = ROWS * OSTRIDE;
@@ -76,12 +76,13 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
   const float* Xf = a.X + (int64_t)f * a.strideX;
   const int col = bt * 64 + wave * 16 + r16;
   const bool colok = col < a.M;
+  const int colc = colok ? col : a.M - 1;  // clamped: loads stay in bounds, results unused
 
   auto load_big = [&](int k0, float (&v)[4]) {
     const bool full = k0 + OKSTEP <= ke;
     if (!TN) {
       const float* p = Xf + (int64_t)col * a.lx + 2 * (k0 + 2 * q4);
-      if (colok && full && a.xvec) {
+      if (colok && full && XVEC) {
         const float4 x = *reinterpret_cast<const float4*>(p);
         v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
       } else {
@@ -105,6 +106,46 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
     }
   };
 
+  // full K steps: loads issued unconditionally (clamped addresses, zero by
+  // select) so that wait counts can leave the next step's loads in flight
+  auto load_big_full = [&](int k0, float (&v)[4]) {
+    if (!TN) {
+      const float* p = Xf + (int64_t)colc * a.lx + 2 * (k0 + 2 * q4);
+      if (XVEC) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+      } else {
+        const float2 x0 = *reinterpret_cast<const float2*>(p);
+        const float2 x1 = *reinterpret_cast<const float2*>(p + 2);
+        v[0] = x0.x; v[1] = x0.y; v[2] = x1.x; v[3] = x1.y;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const float2 x = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + 2 * q4 + c) * a.lx + 2 * colc);
+        v[2 * c] = x.x;
+        v[2 * c + 1] = x.y;
+      }
+    }
+  };
+  auto load_thin_full = [&](int k0, double2 (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % OKSTEP, nn = idx / OKSTEP;
+      const bool ok = nn < nc;
+      const int64_t off = (int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + (n0 + (ok ? nn : 0));
+      double2 v;
+      if (TN) {
+        const float2 y = reinterpret_cast<const float2*>(a.B)[off];
+        v = make_double2((double)y.x, (double)y.y);
+      } else {
+        v = reinterpret_cast<const double2*>(a.B)[off];
+      }
+      x[e] = ok ? v : make_double2(0.0, 0.0);
+    }
+  };
+
   auto load_thin = [&](int k0, double2 (&x)[TEL]) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
@@ -117,12 +158,7 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
           const float2 y = reinterpret_cast<const float2*>(a.B)[off];
           v = make_double2((double)y.x, (double)y.y);
         } else {
-          const double2* Bp = reinterpret_cast<const double2*>(a.B);
-          for (int j = 0; j < a.nsum; ++j) {
-            const double2 y = Bp[off + j * a.bsum_stride];
-            v.x += y.x;
-            v.y += y.y;
-          }
+          v = reinterpret_cast<const double2*>(a.B)[off];
         }
       }
       x[e] = v;
@@ -165,29 +201,36 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
     }
   };
 
-  const int nsteps = (ke - kb + OKSTEP - 1) / OKSTEP;
+  // main loop over the full K steps (LDS double buffer, next step's tall
+  // operand in registers; the thin block is requested first because loads
+  // complete in issue order), then a guarded ragged step
+  const int nfull = (ke - kb) / OKSTEP;
+  const bool tail = kb + nfull * OKSTEP < ke;
   float cur[4], nxt[4];
   double2 tx[TEL];
-  if (nsteps > 0) {
-    load_big(kb, cur);
-    load_thin(kb, tx);
+  if (nfull > 0) {
+    load_big_full(kb, cur);
+    load_thin_full(kb, tx);
     store_thin(olds, tx);
   }
   __syncthreads();
-  for (int s = 0; s < nsteps; ++s) {
-    const int k0 = kb + s * OKSTEP;
-    const bool more = s + 1 < nsteps;
-    if (more) {
-      load_big(k0 + OKSTEP, nxt);
-      load_thin(k0 + OKSTEP, tx);
-    }
+  for (int s = 0; s < nfull; ++s) {
+    const int sn = s + 1 < nfull ? s + 1 : s;
+    load_thin_full(kb + sn * OKSTEP, tx);
+    load_big_full(kb + sn * OKSTEP, nxt);
     compute(olds + (s & 1) * BUF, cur);
-    if (more) store_thin(olds + ((s + 1) & 1) * BUF, tx);
+    if (s + 1 < nfull) store_thin(olds + ((s + 1) & 1) * BUF, tx);
     __syncthreads();
-    if (more) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
-    }
+    for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
+  }
+  if (tail) {
+    const int k0 = kb + nfull * OKSTEP;
+    load_thin(k0, tx);
+    store_thin(olds + (nfull & 1) * BUF, tx);
+    load_big(k0, cur);
+    __syncthreads();
+    compute(olds + (nfull & 1) * BUF, cur);
   }
 
   if (!colok) return;
@@ -226,17 +269,24 @@ __global__ void opart_reduce_kernel(double2* part, int nsplit, int64_t total) {
   }
 }
 
-template <bool TN, int TT>
-hipError_t olaunch_tt(const OArgs& a, hipStream_t s) {
+template <bool TN, int TT, bool XVEC>
+hipError_t olaunch_tta(const OArgs& a, hipStream_t s) {
   const size_t lds = (size_t)2 * TT * 16 * OSTRIDE * sizeof(double);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)ogemm_kernel<TN, TT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)ogemm_kernel<TN, TT, XVEC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
     (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL((ogemm_kernel<TN, TT>), dim3(8 * a.per), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((ogemm_kernel<TN, TT, XVEC>), dim3(8 * a.per), dim3(256), lds, s, a);
   return hipGetLastError();
+}
+
+template <bool TN, int TT>
+hipError_t olaunch_tt(const OArgs& a, hipStream_t s) {
+  if (!TN && a.xvec) return olaunch_tta<TN, TT, true>(a, s);
+  return olaunch_tta<TN, TT, false>(a, s);
 }
 
 template <bool TN>
@@ -312,6 +362,7 @@ hipError_t ogemm_nn(const float* X, int64_t lx, int64_t strideX, const double* B
                     int nsum, int64_t bsum_stride, float* C, int64_t ldc, int64_t strideC, int M, int N, int K,
                     int batch, double alpha, double beta, hipStream_t s) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  if (nsum != 1) return hipErrorInvalidValue;  // callers pass a single (summed) B
   OArgs a{};
   a.X = X;
   a.lx = 2 * lx;
