@@ -33,15 +33,18 @@ int tsvd_diag_fft_c2r(const void* Xb, void* X, int64_t ntubes, int64_t n3, int d
 int tsvd_diag_zgemm(const void* A, int a_conj, const void* B, int b_conj, void* C, int64_t M, int64_t N, int64_t K,
                     int64_t batch, double alpha, double beta, int dtype, void* stream);
 
-/* The Krylov-product kernel alone: C_f = op(A_f) X_f, FP32 complex, batch
+/* The Krylov-product kernels alone: C_f = op(A_f) X_f, FP32 complex, batch
  * slices.  A_f: rows x cols (contiguous slices); herm = 0: op = identity,
  * X_f is cols x N, C_f rows x N; herm = 1: op = ^H, X_f is rows x N, C_f
  * cols x N.  mode: 0 FP32 MFMA, 1 BF16 (one product), 2 BF16x3 (split
  * operands, three products); FP32 accumulation.  nsplit > 1 splits the
- * contraction; part must then hold nsplit * batch * M * N complex floats
- * (M = rows of C_f), reduced in a fixed order. */
+ * contraction (partials reduced in a fixed order).  ws: device workspace of
+ * tsvd_diag_kgemm_ws_bytes() bytes (256-byte aligned; may be NULL when that
+ * is 0). */
+size_t tsvd_diag_kgemm_ws_bytes(int herm, int64_t rows, int64_t cols, int64_t N, int64_t batch, int mode,
+                                int nsplit);
 int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t rows, int64_t cols, int64_t N,
-                    int64_t batch, int mode, int nsplit, void* part, void* stream);
+                    int64_t batch, int mode, int nsplit, void* ws, size_t ws_bytes, void* stream);
 
 /* Event timer over the kernels of the entry points in tsvd_rbk.h.
  * tsvd_diag_timing(1) clears the counters and starts recording a pair of HIP

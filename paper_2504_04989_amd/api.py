@@ -22,7 +22,8 @@ INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_rbk", "tsvd_rbk_approx",
            "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
-           "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_timing", "tsvd_diag_timing_read")
+           "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_timing",
+           "tsvd_diag_timing_read")
 
 
 class TsvdError(RuntimeError):
@@ -62,8 +63,11 @@ def _load():
     lib.tsvd_diag_zgemm.restype = ctypes.c_int
     lib.tsvd_diag_zgemm.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, i64, i64, i64, i64, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, vp]
+    lib.tsvd_diag_kgemm_ws_bytes.restype = sz
+    lib.tsvd_diag_kgemm_ws_bytes.argtypes = [ctypes.c_int, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int]
     lib.tsvd_diag_kgemm.restype = ctypes.c_int
-    lib.tsvd_diag_kgemm.argtypes = [vp, ctypes.c_int, vp, vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, vp]
+    lib.tsvd_diag_kgemm.argtypes = [vp, ctypes.c_int, vp, vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, sz,
+                                    vp]
     return lib
 
 
@@ -257,9 +261,10 @@ def diag_kgemm(A, X, herm=False, mode="f32", nsplit=1):
     M = cols if herm else rows
     N = X.shape[2]
     C = torch.empty((batch, M, N), dtype=torch.complex64, device=A.device)
-    part = torch.empty((nsplit, batch, M, N), dtype=torch.complex64, device=A.device) if nsplit > 1 else None
+    nb = int(lib.tsvd_diag_kgemm_ws_bytes(int(herm), rows, cols, N, batch, KGEMM_MODE[mode], nsplit))
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=A.device)
     _check(lib.tsvd_diag_kgemm(_ptr(A), int(herm), _ptr(X), _ptr(C), rows, cols, N, batch, KGEMM_MODE[mode], nsplit,
-                               _ptr(part) if part is not None else None, _stream(A.device)))
+                               _ptr(ws), ws.numel(), _stream(A.device)))
     return C
 
 

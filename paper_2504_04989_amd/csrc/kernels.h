@@ -46,6 +46,11 @@ struct KGemmDesc {
 hipError_t kgemm(const KGemmDesc& d, hipStream_t s);
 // K split (and chunk) that gives the product enough workgroups to fill the chip.
 int kgemm_split(int M, int K, int N, int batch, int* kchunk);
+// BF16 / BF16x3 modes on planar data: the thin operand is first packed into
+// `pack` (kgemm_bf16_pack_bytes), partials (nsplit > 1) go to d.part.
+hipError_t kgemm_bf16(const KGemmDesc& d, void* pack, hipStream_t s);
+size_t kgemm_bf16_pack_bytes(int mode, int K, int N, int batch);
+int kgemm_bf16_split(int M, int K, int N, int batch);
 
 // FP64-arithmetic products on FP32-stored complex blocks.
 // ogemm_tn: part[f] (M x N, FP64 complex, row-major) = X_f^H Y_f with X_f

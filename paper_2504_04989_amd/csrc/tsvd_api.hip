@@ -49,7 +49,8 @@ struct Plan {
   int ks_ax, ks_ahy;            // K splits of the Krylov products A X and A^H Y
   // workspace offsets (bytes)
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
-      o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, total;
+      o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, o_kpack,
+      total;
 };
 
 int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
@@ -100,8 +101,13 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->nsplit_g = split_for(n2, tm * tm, F, &p->kchunk_g);
   p->kmode = prec == TSVD_PREC_BF16 ? KM_BF16 : (prec == TSVD_PREC_BF16X3 ? KM_BF16X3 : KM_F32);
   int kc_unused;
-  p->ks_ax = p->dt == DT_F32 ? kgemm_split((int)n1, (int)n2, (int)b, (int)F, &kc_unused) : 1;
-  p->ks_ahy = p->dt == DT_F32 ? kgemm_split((int)n2, (int)n1, (int)b, (int)F, &kc_unused) : 1;
+  if (p->kmode != KM_BF16) {
+    p->ks_ax = p->dt == DT_F32 ? kgemm_split((int)n1, (int)n2, (int)b, (int)F, &kc_unused) : 1;
+    p->ks_ahy = p->dt == DT_F32 ? kgemm_split((int)n2, (int)n1, (int)b, (int)F, &kc_unused) : 1;
+  } else {
+    p->ks_ax = kgemm_bf16_split((int)n1, (int)n2, (int)b, (int)F);
+    p->ks_ahy = kgemm_bf16_split((int)n2, (int)n1, (int)b, (int)F);
+  }
 
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -154,6 +160,10 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
     const size_t kp_ax = p->ks_ax > 1 ? (size_t)p->ks_ax * F * n1 * b * 8 : 0;
     const size_t kp_ahy = p->ks_ahy > 1 ? (size_t)p->ks_ahy * F * n2 * b * 8 : 0;
     p->o_kpart = take(std::max(kp_ax, kp_ahy));
+    const bool bfm = p->dt == DT_F32 && p->kmode == KM_BF16;
+    p->o_kpack = take(bfm ? std::max(kgemm_bf16_pack_bytes(p->kmode, (int)n2, (int)b, (int)F),
+                                     kgemm_bf16_pack_bytes(p->kmode, (int)n1, (int)b, (int)F))
+                          : 0);
   }
   p->total = o;
   return TSVD_OK;
@@ -414,7 +424,10 @@ int big_AX(const Ctx& c, const void* X, int64_t ldx, int64_t strideX, void* Out,
     k.nsplit = N == p.b ? p.ks_ax : 1;
     k.part = c.at(p.o_kpart);
     Timed tm_(K_GEMM_KRYLOV, c.s);
-    HIPCHK(kgemm(k, c.s));
+    if (p.kmode != KM_BF16 || N != p.b)
+      HIPCHK(kgemm(k, c.s));
+    else
+      HIPCHK(kgemm_bf16(k, c.at(p.o_kpack), c.s));
     return TSVD_OK;
   }
   GemmDesc d = gd();
@@ -466,7 +479,10 @@ int big_AhY(const Ctx& c, const void* Y, int64_t ldy, int64_t strideY, void* Out
     k.nsplit = N == p.b ? p.ks_ahy : 1;
     k.part = c.at(p.o_kpart);
     Timed tm_(K_GEMM_KRYLOV, c.s);
-    HIPCHK(kgemm(k, c.s));
+    if (p.kmode != KM_BF16 || N != p.b)
+      HIPCHK(kgemm(k, c.s));
+    else
+      HIPCHK(kgemm_bf16(k, c.at(p.o_kpack), c.s));
     return TSVD_OK;
   }
   GemmDesc d = gd();
@@ -937,12 +953,24 @@ int tsvd_diag_fft_c2r(const void* Xb, void* X, int64_t ntubes, int64_t n3, int d
   return TSVD_OK;
 }
 
+size_t tsvd_diag_kgemm_ws_bytes(int herm, int64_t rows, int64_t cols, int64_t N, int64_t batch, int mode,
+                                int nsplit) {
+  if (rows < 1 || cols < 1 || N < 1 || batch < 1 || mode < KM_F32 || mode > KM_BF16X3 || nsplit < 1 ||
+      rows * cols >= ((int64_t)1 << 31) || N >= (1 << 20) || batch > 65535)
+    return 0;
+  const int64_t M = herm ? cols : rows, K = herm ? rows : cols;
+  size_t bytes = nsplit > 1 ? align256((size_t)nsplit * batch * M * N * 8) : 0;
+  if (mode == KM_BF16) bytes += align256(kgemm_bf16_pack_bytes(mode, (int)K, (int)N, (int)batch));
+  return bytes;
+}
+
 int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t rows, int64_t cols, int64_t N,
-                    int64_t batch, int mode, int nsplit, void* part, void* stream) {
+                    int64_t batch, int mode, int nsplit, void* ws, size_t ws_bytes, void* stream) {
+  const size_t need = tsvd_diag_kgemm_ws_bytes(herm, rows, cols, N, batch, mode, nsplit);
   if (!A || !X || !C || rows < 1 || cols < 1 || N < 1 || batch < 1 || mode < KM_F32 || mode > KM_BF16X3 ||
-      nsplit < 1 || nsplit > 64 || (nsplit > 1 && !part) || rows * cols >= ((int64_t)1 << 31) ||
-      N >= (1 << 20) || batch > 65535)
+      nsplit < 1 || nsplit > 64 || rows * cols >= ((int64_t)1 << 31) || N >= (1 << 20) || batch > 65535)
     return fail(TSVD_EINVAL, "bad arguments");
+  if (need > 0 && (!ws || ws_bytes < need || !aligned(ws, 256))) return fail(TSVD_ENOMEM, "workspace too small");
   const int64_t M = herm ? cols : rows, K = herm ? rows : cols;
   KGemmDesc d{};
   d.A = A;
@@ -961,8 +989,13 @@ int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t row
   d.batch = (int)batch;
   d.mode = mode;
   d.nsplit = nsplit;
-  d.part = part;
-  HIPCHK(kgemm(d, (hipStream_t)stream));
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  d.part = nsplit > 1 ? w : nullptr;
+  void* pack = w + (nsplit > 1 ? align256((size_t)nsplit * batch * M * N * 8) : 0);
+  if (mode == KM_BF16)
+    HIPCHK(kgemm_bf16(d, pack, (hipStream_t)stream));
+  else
+    HIPCHK(kgemm(d, (hipStream_t)stream));
   return TSVD_OK;
 }
 
