@@ -347,12 +347,9 @@ namespace {
 template <int N>
 struct P2 {
   static constexpr int SP = N + 1;
-  static constexpr int LOG = N <= 1 ? 0 : 1 + P2<N / 2>::LOG;
-};
-template <>
-struct P2<1> {
-  static constexpr int SP = 2;
-  static constexpr int LOG = 0;
+  // tube pairs per workgroup: N twiddles + 2 buffers of NP sequences in ~40 KB
+  static constexpr int NP0 = (40 * 1024 / 16 - N) / (2 * SP);
+  static constexpr int NP = NP0 > 64 ? 64 : NP0;
 };
 
 // One Stockham pass of radix R on NPs sequences (stride SP) with Ns = product
@@ -417,7 +414,8 @@ __device__ __forceinline__ cx<double>* p2_passes(cx<double>* in, cx<double>* out
 
 template <typename T, int N>
 __global__ __launch_bounds__(256) void fft_r2c_p2_kernel(const T* __restrict__ X, cx<T>* __restrict__ Xb,
-                                                         int64_t ntubes, int NP) {
+                                                         int64_t ntubes) {
+  constexpr int NP = P2<N>::NP;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int SP = P2<N>::SP;
   constexpr int F = N / 2 + 1;
@@ -432,29 +430,39 @@ __global__ __launch_bounds__(256) void fft_r2c_p2_kernel(const T* __restrict__ X
   const int64_t t0 = (int64_t)blockIdx.x * 2 * NP;
   const int ntw = (int)min((int64_t)2 * NP, ntubes - t0);
   const T* src = X + t0 * N;
-  // tubes are contiguous: load 4 (FP32) or 2 (FP64) consecutive samples per access
+  // tubes are contiguous: 4 (FP32) or 2 (FP64) consecutive samples per
+  // access; all of a thread's loads are issued before any is used
   constexpr int VW = sizeof(T) == 4 ? 4 : 2;
-  const int nvec = 2 * NP * N / VW;
+  constexpr int NVEC = 2 * NP * N / VW;
+  constexpr int PERT = (NVEC + 255) / 256;
   const int lim = ntw * N;
-  for (int g = threadIdx.x; g < nvec; g += blockDim.x) {
-    const int e0 = g * VW;
-    const int tube = e0 / N, t = e0 - tube * N;  // compile-time divisor
-    double v[VW];
+  double v[PERT][VW];
+#pragma unroll
+  for (int it = 0; it < PERT; ++it) {
+    const int e0 = (threadIdx.x + 256 * it) * VW;
     if (e0 < lim) {
       if constexpr (VW == 4) {
         const float4 x = *reinterpret_cast<const float4*>(src + e0);
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        v[it][0] = x.x; v[it][1] = x.y; v[it][2] = x.z; v[it][3] = x.w;
       } else {
         const double2 x = *reinterpret_cast<const double2*>(src + e0);
-        v[0] = x.x; v[1] = x.y;
+        v[it][0] = x.x; v[it][1] = x.y;
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < VW; ++i) v[i] = 0.0;
+      for (int i = 0; i < VW; ++i) v[it][i] = 0.0;
     }
-    double* dst = reinterpret_cast<double*>(&b0[(tube >> 1) * SP + t]) + (tube & 1);
+  }
 #pragma unroll
-    for (int i = 0; i < VW; ++i) dst[2 * i] = v[i];
+  for (int it = 0; it < PERT; ++it) {
+    const int g = threadIdx.x + 256 * it;
+    if (g < NVEC) {
+      const int e0 = g * VW;
+      const int tube = e0 / N, t = e0 - tube * N;  // compile-time divisor
+      double* dst = reinterpret_cast<double*>(&b0[(tube >> 1) * SP + t]) + (tube & 1);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) dst[2 * i] = v[it][i];
+    }
   }
   __syncthreads();
   const cx<double>* Z = p2_passes<N, 1, false>(b0, b1, tw, NP);
@@ -478,7 +486,8 @@ __global__ __launch_bounds__(256) void fft_r2c_p2_kernel(const T* __restrict__ X
 
 template <typename T, int N>
 __global__ __launch_bounds__(256) void fft_c2r_p2_kernel(const cx<T>* __restrict__ Xb, int64_t slice_stride,
-                                                         T* __restrict__ X, int64_t ntubes, int NP) {
+                                                         T* __restrict__ X, int64_t ntubes) {
+  constexpr int NP = P2<N>::NP;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int SP = P2<N>::SP;
   constexpr int F = N / 2 + 1;
@@ -523,30 +532,24 @@ __global__ __launch_bounds__(256) void fft_c2r_p2_kernel(const cx<T>* __restrict
   }
 }
 
-template <int N>
-int p2_np() {
-  // LDS: N twiddles + 2 buffers of NP sequences (stride N + 1), about 40 KB
-  int np = (40 * 1024 / 16 - N) / (2 * P2<N>::SP);
-  return np > 64 ? 64 : np;
-}
 
 template <typename T, int N>
 hipError_t p2_r2c(const void* X, void* Xb, int64_t ntubes, hipStream_t s) {
-  const int NP = p2_np<N>();
+  constexpr int NP = P2<N>::NP;
   const int64_t nblk = (ntubes + 2 * NP - 1) / (2 * NP);
   const size_t sm = (size_t)(N + 2 * NP * P2<N>::SP) * sizeof(cx<double>);
   hipLaunchKernelGGL((fft_r2c_p2_kernel<T, N>), dim3((unsigned)nblk), dim3(256), sm, s, (const T*)X, (cx<T>*)Xb,
-                     ntubes, NP);
+                     ntubes);
   return hipGetLastError();
 }
 
 template <typename T, int N>
 hipError_t p2_c2r(const void* Xb, int64_t stride, void* X, int64_t ntubes, hipStream_t s) {
-  const int NP = p2_np<N>();
+  constexpr int NP = P2<N>::NP;
   const int64_t nblk = (ntubes + 2 * NP - 1) / (2 * NP);
   const size_t sm = (size_t)(N + 2 * NP * P2<N>::SP) * sizeof(cx<double>);
   hipLaunchKernelGGL((fft_c2r_p2_kernel<T, N>), dim3((unsigned)nblk), dim3(256), sm, s, (const cx<T>*)Xb, stride,
-                     (T*)X, ntubes, NP);
+                     (T*)X, ntubes);
   return hipGetLastError();
 }
 

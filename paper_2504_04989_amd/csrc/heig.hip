@@ -297,7 +297,7 @@ __device__ __forceinline__ void tri_cde(const MatView& B, int s, int m, const cx
 
 __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* __restrict__ Gpart, int nsum,
                                                            int64_t part_stride, int m, unsigned char* scratch,
-                                                           size_t per_slice, int Lsw) {
+                                                           size_t per_slice, int Lsw, int upper_only) {
   extern __shared__ __align__(16) unsigned char smem[];
   cx<double>* vbuf0 = reinterpret_cast<cx<double>*>(smem);
   cx<double>* vbuf1 = vbuf0 + m;
@@ -333,12 +333,14 @@ __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* 
     }
   }
   __syncthreads();
-  // Hermitian average (upper triangle from the lower one, diagonal real)
+  // Hermitian average (upper triangle from the lower one, diagonal real), or
+  // the Hermitian extension of the upper triangle when only that is valid
   for (int t = tid; t < mm; t += TRI_NT) {
     const int i = t / m, c = t - (t / m) * m;
     if (c > i) continue;
     const cx<double> g = A[t], h = A[(int64_t)c * m + i];
-    const cx<double> lo{0.5 * (g.re + h.re), i == c ? 0.0 : 0.5 * (g.im - h.im)};
+    const cx<double> lo = upper_only ? cx<double>{h.re, i == c ? 0.0 : -h.im}
+                                     : cx<double>{0.5 * (g.re + h.re), i == c ? 0.0 : 0.5 * (g.im - h.im)};
     A[t] = lo;
     A[(int64_t)c * m + i] = cx<double>{lo.re, -lo.im};
   }
@@ -733,7 +735,7 @@ __global__ __launch_bounds__(256) void heig_backxf_kernel(int m, int k, unsigned
 }
 
 hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, int k, int batch, double* lambda,
-                     double* W, void* scratch, int* info, hipStream_t s, int stages) {
+                     double* W, void* scratch, int* info, hipStream_t s, int stages, bool upper_only) {
   if (batch <= 0) return hipSuccess;
   if (m > 1024 || k > m || k < 1) return hipErrorInvalidValue;
   static bool attr_set = false;
@@ -762,7 +764,7 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
   hipError_t e = hipSuccess;
   if (stages & HEIG_TRIDIAG) {
     hipLaunchKernelGGL(heig_tridiag_kernel, dim3(batch), dim3(TRI_NT), sm1, s, (const cx<double>*)Gpart, nsum,
-                       part_stride, m, sc, per, Lsw);
+                       part_stride, m, sc, per, Lsw, upper_only ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // 2. eigenvalues: 4 waves (eigenvalues) per workgroup

@@ -62,8 +62,10 @@ int kgemm_bf16_split(int M, int K, int N, int batch);
 //   X_f (M x K, row stride lx, FP32) and B_f (K x N, FP64, row stride ldb) the
 //   sum of nsum matrices spaced bsum_stride complex elements.
 size_t ogemm_tn_part_bytes(int M, int K, int N, int batch);
+// upper = true (square products): only the entries on and above the
+// diagonal are guaranteed; whole tiles below it are skipped.
 hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y, int64_t ly, int64_t strideY,
-                    double* part, int M, int N, int K, int batch, hipStream_t s);
+                    double* part, int M, int N, int K, int batch, hipStream_t s, bool upper = false);
 hipError_t ogemm_nn(const float* X, int64_t lx, int64_t strideX, const double* B, int64_t ldb, int64_t strideB,
                     int nsum, int64_t bsum_stride, float* C, int64_t ldc, int64_t strideC, int M, int N, int K,
                     int batch, double alpha, double beta, hipStream_t s);
@@ -92,8 +94,11 @@ hipError_t chol_inv_ex(const double* Gpart, int nsum, int64_t part_stride, doubl
 // this order on one stream, with the same arguments).
 enum HeigStage { HEIG_TRIDIAG = 1, HEIG_BISECT = 2, HEIG_INVIT = 4, HEIG_BACKXF = 8, HEIG_ALL = 15 };
 size_t heig_scratch_bytes(int m, int k);
+// upper_only: only the entries on and above the diagonal of the summed
+// partials are valid (the matrix is taken as their Hermitian extension).
 hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, int k, int batch, double* lambda,
-                     double* W, void* scratch, int* info, hipStream_t s, int stages = HEIG_ALL);
+                     double* W, void* scratch, int* info, hipStream_t s, int stages = HEIG_ALL,
+                     bool upper_only = false);
 
 // Lift helpers.
 // Wout (batch x m x k, dtype t) = W * diag(scale) where scale = sqrt(lambda)

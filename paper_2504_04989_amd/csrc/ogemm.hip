@@ -44,6 +44,7 @@ struct OArgs {
   int nsplit, kchunk;
   int nbig, nthin, total, per;
   int xvec;
+  int upper;  // TN: skip tiles strictly below the diagonal of a square product
 };
 
 template <bool TN, int TT, bool XVEC>
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
   const int n0 = tc * NCH;
   const int nc = min(NCH, a.N - n0);
   const int tt = (2 * nc + 15) / 16;
+  if (TN && a.upper && bt * 64 > n0 + NCH - 1) return;  // every entry of this tile has row > column
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q4 = lane >> 4, r16 = lane & 15;
@@ -233,23 +235,36 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
     compute(olds + (nfull & 1) * BUF, cur);
   }
 
-  if (!colok) return;
-  const int part = q4 & 1;
+  // Lanes q4 and q4 ^ 1 hold the real and the imaginary parts of the same
+  // four columns n = n0 + 8 i + q4 / 2 + 2 r; after one exchange the even lane
+  // stores r = 0, 1 and the odd lane r = 2, 3 as whole complex numbers.
+  if (!colok) return;  // the partner lane (same column) returns too
+  const bool odd = q4 & 1;
 #pragma unroll
   for (int i = 0; i < TT; ++i) {
     if (i < tt) {
+      double other[4];
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
+      for (int rr = 0; rr < 4; ++rr) other[rr] = __shfl_xor(acc[i][rr], 16, 64);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int rr = odd ? 2 + h : h;
+        const double re = odd ? other[rr] : acc[i][rr];
+        const double im = odd ? acc[i][rr] : other[rr];
         const int n = n0 + 8 * i + (q4 >> 1) + 2 * rr;
         if (n >= a.N) continue;
         if (TN) {
-          double* out = static_cast<double*>(a.C) + 2 * (((int64_t)sp * a.batch + f) * a.M * a.N + (int64_t)col * a.N + n);
-          out[part] = acc[i][rr];
+          double2* out = static_cast<double2*>(a.C) + (((int64_t)sp * a.batch + f) * a.M * a.N + (int64_t)col * a.N + n);
+          *out = make_double2(re, im);
         } else {
-          float* out = static_cast<float*>(a.C) + 2 * ((int64_t)f * a.strideC + (int64_t)col * a.ldc + n);
-          double val = a.alpha * acc[i][rr];
-          if (a.beta != 0.0) val += a.beta * (double)out[part];
-          out[part] = (float)val;
+          float2* out = static_cast<float2*>(a.C) + ((int64_t)f * a.strideC + (int64_t)col * a.ldc + n);
+          double vr = a.alpha * re, vi = a.alpha * im;
+          if (a.beta != 0.0) {
+            const float2 o = *out;
+            vr += a.beta * (double)o.x;
+            vi += a.beta * (double)o.y;
+          }
+          *out = make_float2((float)vr, (float)vi);
         }
       }
     }
@@ -328,7 +343,7 @@ size_t ogemm_tn_part_bytes(int M, int K, int N, int batch) {
 }
 
 hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y, int64_t ly, int64_t strideY,
-                    double* part, int M, int N, int K, int batch, hipStream_t s) {
+                    double* part, int M, int N, int K, int batch, hipStream_t s, bool upper) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   OArgs a{};
   a.X = X;
@@ -348,6 +363,7 @@ hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y,
   kc = (kc + OKSTEP - 1) / OKSTEP * OKSTEP;
   a.kchunk = kc < OKSTEP ? OKSTEP : kc;
   a.xvec = 0;
+  a.upper = (upper && M == N) ? 1 : 0;
   const int TT = othin_tiles(N);
   fill_grid(a, TT);
   hipError_t e = olaunch<true>(a, TT, s);

@@ -248,12 +248,12 @@ GemmDesc gd() {
 // results (spaced F * M * N) whose sum is the product.
 int inner_products(const Ctx& c, const void* X, int64_t lx, int M, const void* Y, int64_t ly, int N, int64_t K,
                    int64_t strideX, int64_t strideY, int nsplit, int kchunk, double* part, int* nsum,
-                   int cls = K_GEMM_ORTH) {
+                   int cls = K_GEMM_ORTH, bool upper = false) {
   const Plan& p = c.p;
   if (p.dt == DT_F32) {
     Timed tm_(cls, c.s);
     HIPCHK(ogemm_tn(static_cast<const float*>(X), lx, strideX, static_cast<const float*>(Y), ly, strideY, part, M, N,
-                    (int)K, (int)p.F, c.s));
+                    (int)K, (int)p.F, c.s, upper));
     *nsum = 1;
     return TSVD_OK;
   }
@@ -559,8 +559,10 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   double* part = c.at<double>(p.o_part);
   void* T = c.at(p.o_t);
   int nsum_g = 1;
+  // G_f = T^H T is Hermitian: on the FP32 path only its upper triangle is formed
+  const bool upper = p.dt == DT_F32;
   int r = inner_products(c, T, p.m, (int)p.m, T, p.m, (int)p.m, p.n2, p.n2 * p.m, p.n2 * p.m, p.nsplit_g,
-                         p.kchunk_g, part, &nsum_g, K_GEMM_LIFT);
+                         p.kchunk_g, part, &nsum_g, K_GEMM_LIFT, upper);
   if (r) return r;
   double* lam = c.at<double>(p.o_lam);
   double* Wd = c.at<double>(p.o_wd);
@@ -569,7 +571,7 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   for (const auto& sc : stage_cls) {
     Timed tm_(sc[1], c.s);
     HIPCHK(heig_topk(part, nsum_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
-                     c.info(), c.s, sc[0]));
+                     c.info(), c.s, sc[0], upper));
   }
   // U_f = Q_f W_k
   GemmDesc d = gd();
