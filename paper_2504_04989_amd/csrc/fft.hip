@@ -322,12 +322,18 @@ bool fft_pow2_supported(int n3);
 hipError_t fft_r2c_pow2(const void* X, void* Xb, int64_t ntubes, int n3, DType t, hipStream_t s);
 hipError_t fft_c2r_pow2(const void* Xb, int64_t stride, void* X, int64_t ntubes, int n3, DType t, hipStream_t s);
 
+bool fft_reg_supported(int n3, DType t);
+hipError_t fft_r2c_reg(const void* X, void* Xb, int64_t ntubes, int n3, hipStream_t s);
+hipError_t fft_c2r_reg(const void* Xb, int64_t stride, void* X, int64_t ntubes, int n3, hipStream_t s);
+
 hipError_t fft_r2c(const void* X, void* Xb, int64_t ntubes, int n3, DType t, hipStream_t s) {
+  if (fft_reg_supported(n3, t)) return fft_r2c_reg(X, Xb, ntubes, n3, s);
   if (fft_pow2_supported(n3)) return fft_r2c_pow2(X, Xb, ntubes, n3, t, s);
   return t == DT_F64 ? r2c_t<double>(X, Xb, ntubes, n3, s) : r2c_t<float>(X, Xb, ntubes, n3, s);
 }
 
 hipError_t fft_c2r(const void* Xb, int64_t slice_stride, void* X, int64_t ntubes, int n3, DType t, hipStream_t s) {
+  if (fft_reg_supported(n3, t)) return fft_c2r_reg(Xb, slice_stride, X, ntubes, n3, s);
   if (fft_pow2_supported(n3)) return fft_c2r_pow2(Xb, slice_stride, X, ntubes, n3, t, s);
   return t == DT_F64 ? c2r_t<double>(Xb, slice_stride, X, ntubes, n3, s)
                      : c2r_t<float>(Xb, slice_stride, X, ntubes, n3, s);
@@ -590,6 +596,326 @@ hipError_t fft_c2r_pow2(const void* Xb, int64_t stride, void* X, int64_t ntubes,
   if (ntubes <= 0) return hipSuccess;
   return t == DT_F64 ? p2_c2r_dispatch<double>(Xb, stride, X, ntubes, n3, s)
                      : p2_c2r_dispatch<float>(Xb, stride, X, ntubes, n3, s);
+}
+
+}  // namespace tsvd
+
+// ---------------------------------------------------------------------------
+// FP32 tubes of length N in {8, 16, 32, 64}: one thread per tube, the whole
+// transform in registers.  A workgroup moves 256 consecutive tubes between HBM
+// and LDS with coalesced 16-byte accesses (FP32, padded row stride N + 4, so
+// that the 16-byte per-thread row accesses are bank-conflict free); each thread
+// then widens its own tube to FP64, packs it into the N/2-point complex sequence
+// z[n] = x[2n] + i x[2n+1], runs an unrolled radix-2 decimation-in-frequency FFT
+// with compile-time twiddles, separates the spectrum of the real tube
+// X[f] = E[f] + w^f O[f] (E, O the spectra of the even and odd samples,
+// w = exp(-2 pi i / N)) and writes X[0..N/2] slice-major, coalesced across the
+// threads.  The inverse runs the same steps backwards.  LDS is touched once per
+// sample in each direction, which keeps the kernel on the HBM roofline.
+// ---------------------------------------------------------------------------
+namespace tsvd {
+namespace {
+
+// cos and sin of 2 pi k / n at compile time: the angle is reduced to the first
+// octant by exact integer arithmetic and the Taylor series is summed in FP64.
+constexpr double ct_sin_poly(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int i = 1; i < 14; ++i) {
+    term = -term * x2 / (double)((2 * i) * (2 * i + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ct_cos_poly(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int i = 1; i < 14; ++i) {
+    term = -term * x2 / (double)((2 * i - 1) * (2 * i));
+    sum += term;
+  }
+  return sum;
+}
+struct CtCS {
+  double c, s;
+};
+constexpr CtCS ct_turn(int k, int n) {
+  k %= n;
+  if (k < 0) k += n;
+  const int q = (4 * k) / n;      // quadrant
+  const int rn = 4 * k - q * n;   // remainder, in units of (pi / 2) / n
+  double cq = 1.0, sq = 0.0;
+  if (rn != 0) {
+    constexpr double half_pi = 1.57079632679489661923;
+    if (2 * rn <= n) {
+      const double phi = half_pi * (double)rn / (double)n;
+      cq = ct_cos_poly(phi);
+      sq = ct_sin_poly(phi);
+    } else {
+      const double psi = half_pi * (double)(n - rn) / (double)n;
+      cq = ct_sin_poly(psi);
+      sq = ct_cos_poly(psi);
+    }
+  }
+  switch (q) {
+    case 0: return CtCS{cq, sq};
+    case 1: return CtCS{-sq, cq};
+    case 2: return CtCS{-cq, -sq};
+    default: return CtCS{sq, -cq};
+  }
+}
+
+// cos / sin of 2 pi k / N for k < N, evaluated by the compiler
+template <int N>
+struct CtTab {
+  double c[N], s[N];
+  constexpr CtTab() : c(), s() {
+    for (int k = 0; k < N; ++k) {
+      const CtCS w = ct_turn(k, N);
+      c[k] = w.c;
+      s[k] = w.s;
+    }
+  }
+};
+
+constexpr int ct_bitrev(int v, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+constexpr int ct_log2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// In-place M-point complex DFT (sign -1, or +1 when INV, unnormalised) of
+// (re, im); the result is left in bit-reversed order.
+template <int M, bool INV>
+__device__ __forceinline__ void reg_dif(double (&re)[M], double (&im)[M]) {
+  constexpr CtTab<M> tw{};
+#pragma unroll
+  for (int len = M; len >= 2; len >>= 1) {
+    const int half = len >> 1;
+#pragma unroll
+    for (int i0 = 0; i0 < M; i0 += len) {
+#pragma unroll
+      for (int j = 0; j < half; ++j) {
+        const int a = i0 + j, b = a + half;
+        const double ur = re[a], ui = im[a], vr = re[b], vi = im[b];
+        re[a] = ur + vr;
+        im[a] = ui + vi;
+        const double dr = ur - vr, di = ui - vi;
+        const int e = j * (M / len);  // twiddle exp(-+2 pi i e / M)
+        if (e == 0) {
+          re[b] = dr;
+          im[b] = di;
+        } else if (4 * e == M) {  // -i (forward) or +i (inverse)
+          re[b] = INV ? -di : di;
+          im[b] = INV ? dr : -dr;
+        } else {
+          const double wr = tw.c[e], wi = INV ? tw.s[e] : -tw.s[e];
+          re[b] = fma(dr, wr, -di * wi);
+          im[b] = fma(dr, wi, di * wr);
+        }
+      }
+    }
+  }
+}
+
+#ifndef TSVD_FFT_REG_TUBES
+#define TSVD_FFT_REG_TUBES 256
+#endif
+constexpr int REG_TUBES = TSVD_FFT_REG_TUBES;  // tubes (threads) per workgroup
+#ifndef TSVD_FFT_NT
+#define TSVD_FFT_NT 3
+#endif
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// streaming accesses: every sample and every spectrum entry is touched once
+__device__ __forceinline__ float4 ld_stream4(const float4* p) {
+#if TSVD_FFT_NT & 1
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+#else
+  return *p;
+#endif
+}
+__device__ __forceinline__ float2 ld_stream2(const float2* p) {
+#if TSVD_FFT_NT & 1
+  const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+  return make_float2(v.x, v.y);
+#else
+  return *p;
+#endif
+}
+__device__ __forceinline__ void st_stream2(float2* p, float a, float b) {
+#if TSVD_FFT_NT & 2
+  f32x2 v;
+  v.x = a;
+  v.y = b;
+  __builtin_nontemporal_store(v, reinterpret_cast<f32x2*>(p));
+#else
+  *p = make_float2(a, b);
+#endif
+}
+__device__ __forceinline__ void st_stream4(float4* p, float4 x) {
+#if TSVD_FFT_NT & 2
+  f32x4 v;
+  v.x = x.x;
+  v.y = x.y;
+  v.z = x.z;
+  v.w = x.w;
+  __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p));
+#else
+  *p = x;
+#endif
+}
+
+template <int N>
+__global__ __launch_bounds__(REG_TUBES) void fft_r2c_reg_kernel(const float* __restrict__ X,
+                                                                 float2* __restrict__ Xb, int64_t ntubes) {
+  constexpr int M = N / 2, LB = ct_log2(M), SPF = N + 4;
+  constexpr int NV = REG_TUBES * N / 4;  // float4 per workgroup
+  __shared__ __align__(16) float buf[REG_TUBES * SPF];
+  const int tid = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * REG_TUBES;
+  const int ntw = (int)min((int64_t)REG_TUBES, ntubes - t0);
+  const int lim = ntw * (N / 4);
+  const float4* src = reinterpret_cast<const float4*>(X + t0 * N);
+  float4 v[NV / REG_TUBES];
+#pragma unroll
+  for (int it = 0; it < NV / REG_TUBES; ++it) {
+    const int g = tid + REG_TUBES * it;
+    v[it] = g < lim ? ld_stream4(src + g) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int it = 0; it < NV / REG_TUBES; ++it) {
+    const int g = tid + REG_TUBES * it;
+    const int tube = g / (N / 4), c = g - tube * (N / 4);
+    *reinterpret_cast<float4*>(&buf[tube * SPF + 4 * c]) = v[it];
+  }
+  __syncthreads();
+  double re[M], im[M];
+#pragma unroll
+  for (int c = 0; c < N / 4; ++c) {
+    const float4 x = *reinterpret_cast<const float4*>(&buf[tid * SPF + 4 * c]);
+    re[2 * c] = x.x;
+    im[2 * c] = x.y;
+    re[2 * c + 1] = x.z;
+    im[2 * c + 1] = x.w;
+  }
+  reg_dif<M, false>(re, im);
+  if (tid >= ntw) return;
+  constexpr CtTab<N> tw{};
+  float2* out = Xb + t0 + tid;
+  // Z[k] sits at register bitrev(k); Z[M] = Z[0]
+#pragma unroll
+  for (int f = 0; f <= M / 2; ++f) {
+    const int g = M - f;  // partner frequency
+    const int pf = ct_bitrev(f % M, LB), pg = ct_bitrev(g % M, LB);
+    const double zfr = re[pf], zfi = im[pf], zgr = re[pg], zgi = im[pg];
+    // X[f] = E + w^f O with E = (Z[f] + conj Z[g]) / 2, O = -i (Z[f] - conj Z[g]) / 2
+    // X[g] = conj(E) - w^f conj(O)  (E[g] = conj E[f], O[g] = conj O[f], w^g = -conj w^f)
+    const double er = 0.5 * (zfr + zgr), ei = 0.5 * (zfi - zgi);
+    const double orr = 0.5 * (zfi + zgi), oi = -0.5 * (zfr - zgr);
+    const double wr = tw.c[f], wi = -tw.s[f];
+    const double tr = fma(wr, orr, -wi * oi), ti = fma(wr, oi, wi * orr);
+    st_stream2(out + (int64_t)f * ntubes, (float)(er + tr), (float)(ei + ti));
+    if (g != f) st_stream2(out + (int64_t)g * ntubes, (float)(er - tr), (float)(ti - ei));
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(REG_TUBES) void fft_c2r_reg_kernel(const float2* __restrict__ Xb, int64_t slice_stride,
+                                                                 float* __restrict__ X, int64_t ntubes) {
+  constexpr int M = N / 2, LB = ct_log2(M), SPF = N + 4;
+  constexpr int NV = REG_TUBES * N / 4;
+  __shared__ __align__(16) float buf[REG_TUBES * SPF];
+  const int tid = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * REG_TUBES;
+  const int ntw = (int)min((int64_t)REG_TUBES, ntubes - t0);
+  double re[M], im[M];
+  {
+    constexpr CtTab<N> tw{};
+    const int tt = tid < ntw ? tid : 0;  // threads past the end read tube 0 and store nothing
+    const float2* in = Xb + t0 + tt;
+    float2 x[M + 1];
+#pragma unroll
+    for (int f = 0; f <= M; ++f) x[f] = ld_stream2(in + (int64_t)f * slice_stride);
+    x[0].y = 0.f;
+    x[M].y = 0.f;
+    // Z'[f] = (X[f] + conj X[M-f]) + i w^{-f} (X[f] - conj X[M-f]), f < M
+#pragma unroll
+    for (int f = 0; f < M; ++f) {
+      const double ar = x[f].x, ai = x[f].y, br = x[M - f].x, bi = -(double)x[M - f].y;
+      const double sr = ar + br, si = ai + bi, dr = ar - br, di = ai - bi;
+      const double wr = tw.c[f], wi = tw.s[f];  // w^{-f}
+      const double orr = fma(dr, wr, -di * wi), oi = fma(dr, wi, di * wr);
+      re[f] = sr - oi;
+      im[f] = si + orr;
+    }
+  }
+  // unnormalised inverse DFT; z[n] = x[2n] + i x[2n+1] (times N) lands at register bitrev(n)
+  reg_dif<M, true>(re, im);
+  constexpr double invN = 1.0 / N;
+#pragma unroll
+  for (int c = 0; c < N / 4; ++c) {
+    const int p0 = ct_bitrev(2 * c, LB), p1 = ct_bitrev(2 * c + 1, LB);
+    float4 o;
+    o.x = (float)(re[p0] * invN);
+    o.y = (float)(im[p0] * invN);
+    o.z = (float)(re[p1] * invN);
+    o.w = (float)(im[p1] * invN);
+    *reinterpret_cast<float4*>(&buf[tid * SPF + 4 * c]) = o;
+  }
+  __syncthreads();
+  const int lim = ntw * (N / 4);
+  float4* dst = reinterpret_cast<float4*>(X + t0 * N);
+#pragma unroll
+  for (int it = 0; it < NV / REG_TUBES; ++it) {
+    const int g = tid + REG_TUBES * it;
+    const int tube = g / (N / 4), c = g - tube * (N / 4);
+    if (g < lim) st_stream4(dst + g, *reinterpret_cast<const float4*>(&buf[tube * SPF + 4 * c]));
+  }
+}
+
+template <int N>
+hipError_t reg_r2c(const void* X, void* Xb, int64_t ntubes, hipStream_t s) {
+  const int64_t nblk = (ntubes + REG_TUBES - 1) / REG_TUBES;
+  hipLaunchKernelGGL((fft_r2c_reg_kernel<N>), dim3((unsigned)nblk), dim3(REG_TUBES), 0, s, (const float*)X,
+                     (float2*)Xb, ntubes);
+  return hipGetLastError();
+}
+template <int N>
+hipError_t reg_c2r(const void* Xb, int64_t stride, void* X, int64_t ntubes, hipStream_t s) {
+  const int64_t nblk = (ntubes + REG_TUBES - 1) / REG_TUBES;
+  hipLaunchKernelGGL((fft_c2r_reg_kernel<N>), dim3((unsigned)nblk), dim3(REG_TUBES), 0, s, (const float2*)Xb,
+                     stride, (float*)X, ntubes);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool fft_reg_supported(int n3, DType t) { return t == DT_F32 && (n3 == 8 || n3 == 16 || n3 == 32 || n3 == 64); }
+
+hipError_t fft_r2c_reg(const void* X, void* Xb, int64_t ntubes, int n3, hipStream_t s) {
+  if (ntubes <= 0) return hipSuccess;
+  switch (n3) {
+    case 8: return reg_r2c<8>(X, Xb, ntubes, s);
+    case 16: return reg_r2c<16>(X, Xb, ntubes, s);
+    case 32: return reg_r2c<32>(X, Xb, ntubes, s);
+    case 64: return reg_r2c<64>(X, Xb, ntubes, s);
+    default: return hipErrorNotSupported;
+  }
+}
+hipError_t fft_c2r_reg(const void* Xb, int64_t stride, void* X, int64_t ntubes, int n3, hipStream_t s) {
+  if (ntubes <= 0) return hipSuccess;
+  switch (n3) {
+    case 8: return reg_c2r<8>(Xb, stride, X, ntubes, s);
+    case 16: return reg_c2r<16>(Xb, stride, X, ntubes, s);
+    case 32: return reg_c2r<32>(Xb, stride, X, ntubes, s);
+    case 64: return reg_c2r<64>(Xb, stride, X, ntubes, s);
+    default: return hipErrorNotSupported;
+  }
 }
 
 }  // namespace tsvd
