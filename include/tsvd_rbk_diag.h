@@ -46,6 +46,18 @@ size_t tsvd_diag_kgemm_ws_bytes(int herm, int64_t rows, int64_t cols, int64_t N,
 int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t rows, int64_t cols, int64_t N,
                     int64_t batch, int mode, int nsplit, void* ws, size_t ws_bytes, void* stream);
 
+/* The small Hermitian eigensolver alone (the per-slice SVD of C_f in Alg. 2
+ * taken through C_f C_f^H, FP64): the k largest eigenvalues (descending) and
+ * their eigenvectors of batch Hermitian m x m matrices G (interleaved
+ * complex double, row-major, contiguous; the kernel uses the Hermitian part
+ * (G + G^H) / 2).  lambda: batch x k doubles; W: batch x m x k complex
+ * double, row-major.  ws: device workspace of tsvd_diag_heig_ws_bytes()
+ * bytes, 256-byte aligned; its first TSVD_INFO_COUNT ints hold the
+ * diagnostic counters (tsvd_read_info). */
+size_t tsvd_diag_heig_ws_bytes(int64_t m, int64_t k, int64_t batch);
+int tsvd_diag_heig(const void* G, int64_t m, int64_t k, int64_t batch, void* lambda, void* W, void* ws,
+                   size_t ws_bytes, void* stream);
+
 /* Event timer over the kernels of the entry points in tsvd_rbk.h.
  * tsvd_diag_timing(1) clears the counters and starts recording a pair of HIP
  * events on the caller's stream around every launch; (0) stops.

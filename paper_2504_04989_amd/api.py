@@ -22,8 +22,8 @@ INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_rbk", "tsvd_rbk_approx",
            "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
-           "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_timing",
-           "tsvd_diag_timing_read")
+           "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_heig",
+           "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read")
 
 
 class TsvdError(RuntimeError):
@@ -68,6 +68,10 @@ def _load():
     lib.tsvd_diag_kgemm.restype = ctypes.c_int
     lib.tsvd_diag_kgemm.argtypes = [vp, ctypes.c_int, vp, vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, sz,
                                     vp]
+    lib.tsvd_diag_heig_ws_bytes.restype = sz
+    lib.tsvd_diag_heig_ws_bytes.argtypes = [i64, i64, i64]
+    lib.tsvd_diag_heig.restype = ctypes.c_int
+    lib.tsvd_diag_heig.argtypes = [vp, i64, i64, i64, vp, vp, vp, sz, vp]
     return lib
 
 
@@ -266,6 +270,21 @@ def diag_kgemm(A, X, herm=False, mode="f32", nsplit=1):
     _check(lib.tsvd_diag_kgemm(_ptr(A), int(herm), _ptr(X), _ptr(C), rows, cols, N, batch, KGEMM_MODE[mode], nsplit,
                                _ptr(ws), ws.numel(), _stream(A.device)))
     return C
+
+
+def diag_heig(G, k):
+    """The small Hermitian eigensolver alone (see tsvd_diag_heig): the k
+    largest eigenpairs of each complex128 matrix G (batch, m, m).  Returns
+    (lambda (batch, k) descending, W (batch, m, k), info dict)."""
+    batch, m, _ = G.shape
+    lam = torch.empty((batch, k), dtype=torch.float64, device=G.device)
+    W = torch.empty((batch, m, k), dtype=torch.complex128, device=G.device)
+    nb = int(lib.tsvd_diag_heig_ws_bytes(m, k, batch))
+    if nb == 0:
+        raise TsvdError(TSVD_EINVAL, "bad eigensolver shape")
+    ws = torch.empty(nb, dtype=torch.uint8, device=G.device)
+    _check(lib.tsvd_diag_heig(_ptr(G), m, k, batch, _ptr(lam), _ptr(W), _ptr(ws), ws.numel(), _stream(G.device)))
+    return lam, W, read_info(ws)
 
 
 KERNEL_CLASSES = ("fft_A", "fft_omega", "gemm_krylov", "gemm_orth", "chol", "heig_tri", "gemm_lift", "fft_inv", "misc",

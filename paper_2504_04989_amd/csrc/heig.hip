@@ -37,6 +37,16 @@ __device__ unsigned long long g_phase[16];
 #define PHASE_T0()
 #define PHASE(i)
 #endif
+#ifdef TSVD_PHASE_PROF
+extern "C" int tsvd_phase_read(unsigned long long* out, int reset) {
+  if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase)) != hipSuccess) return 1;
+  if (reset) {
+    unsigned long long z[16] = {};
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z)) != hipSuccess) return 1;
+  }
+  return 0;
+}
+#endif
 
 namespace tsvd {
 
@@ -89,7 +99,13 @@ struct TriShared {
   cx<double>* ppart;  // TRI_G x m partial sums of p
 };
 
-constexpr int TRI_NT = 512;  // threads per tridiagonalisation workgroup
+#ifndef TSVD_TRI_NT
+#define TSVD_TRI_NT 512
+#endif
+#ifndef TSVD_TRI_NB
+#define TSVD_TRI_NB 8
+#endif
+constexpr int TRI_NT = TSVD_TRI_NT;  // threads per tridiagonalisation workgroup
 constexpr int TRI_G = 8;     // at most this many thread groups share one column
 
 // Block-wide sum of a complex value (one reduction for both parts).
@@ -236,7 +252,7 @@ __device__ __forceinline__ void tri_cde(const MatView& B, int s, int m, const cx
   int G = TRI_NT / Ln;
   if (G > TRI_G) G = TRI_G;
   if (G < 1) G = 1;
-  constexpr int NB = 8;  // rows per batch; the next batch is loaded while this one is updated
+  constexpr int NB = TSVD_TRI_NB;  // rows per batch; the next batch is loaded while this one is updated
   const int64_t ld = B.ld;
   for (int t = tid; t < G * Ln || (G == 1 && t < Ln); t += TRI_NT) {
     const int g = G > 1 ? t / Ln : 0;
@@ -295,6 +311,44 @@ __device__ __forceinline__ void tri_cde(const MatView& B, int s, int m, const cx
   }
 }
 
+// A = Hermitian part of the sum of the nsum partials (or the Hermitian
+// extension of their upper triangle), written to the slice's working matrix.
+template <int NT>
+__device__ __forceinline__ void tri_load_hermitian(const cx<double>* __restrict__ G, int nsum, int64_t part_stride,
+                                                   int m, int upper_only, cx<double>* A) {
+  const int tid = threadIdx.x;
+  // sum of the partials (partial index outermost: independent loads in flight)
+  const int mm = m * m;
+  for (int s = 0; s < nsum; ++s) {
+    const cx<double>* Gs = G + s * part_stride;
+#pragma unroll 8
+    for (int t = tid; t < mm; t += NT) {
+      const cx<double> g = Gs[t];
+      if (s == 0) {
+        A[t] = g;
+      } else {
+        cx<double> a = A[t];
+        a.re += g.re;
+        a.im += g.im;
+        A[t] = a;
+      }
+    }
+  }
+  __syncthreads();
+  // Hermitian average (upper triangle from the lower one, diagonal real), or
+  // the Hermitian extension of the upper triangle when only that is valid
+  for (int t = tid; t < mm; t += NT) {
+    const int i = t / m, c = t - (t / m) * m;
+    if (c > i) continue;
+    const cx<double> g = A[t], h = A[(int64_t)c * m + i];
+    const cx<double> lo = upper_only ? cx<double>{h.re, i == c ? 0.0 : -h.im}
+                                     : cx<double>{0.5 * (g.re + h.re), i == c ? 0.0 : 0.5 * (g.im - h.im)};
+    A[t] = lo;
+    A[(int64_t)c * m + i] = cx<double>{lo.re, -lo.im};
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* __restrict__ Gpart, int nsum,
                                                            int64_t part_stride, int m, unsigned char* scratch,
                                                            size_t per_slice, int Lsw, int upper_only) {
@@ -315,36 +369,7 @@ __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* 
   cx<double>* A = hv.A;
   const cx<double>* G = Gpart + (int64_t)f * m * m;
 
-  // sum of the partials (partial index outermost: independent loads in flight)
-  const int mm = m * m;
-  for (int s = 0; s < nsum; ++s) {
-    const cx<double>* Gs = G + s * part_stride;
-#pragma unroll 8
-    for (int t = tid; t < mm; t += TRI_NT) {
-      const cx<double> g = Gs[t];
-      if (s == 0) {
-        A[t] = g;
-      } else {
-        cx<double> a = A[t];
-        a.re += g.re;
-        a.im += g.im;
-        A[t] = a;
-      }
-    }
-  }
-  __syncthreads();
-  // Hermitian average (upper triangle from the lower one, diagonal real), or
-  // the Hermitian extension of the upper triangle when only that is valid
-  for (int t = tid; t < mm; t += TRI_NT) {
-    const int i = t / m, c = t - (t / m) * m;
-    if (c > i) continue;
-    const cx<double> g = A[t], h = A[(int64_t)c * m + i];
-    const cx<double> lo = upper_only ? cx<double>{h.re, i == c ? 0.0 : -h.im}
-                                     : cx<double>{0.5 * (g.re + h.re), i == c ? 0.0 : 0.5 * (g.im - h.im)};
-    A[t] = lo;
-    A[(int64_t)c * m + i] = cx<double>{lo.re, -lo.im};
-  }
-  __syncthreads();
+  tri_load_hermitian<TRI_NT>(G, nsum, part_stride, m, upper_only, A);
   if (m == 1) {
     if (tid == 0) {
       hv.d[0] = A[0].re;
@@ -415,6 +440,413 @@ __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* 
     tri_cde(Bl, s, m, vb(cur), wb(cur), vb(cur ^ 1), wb(cur ^ 1), hv, sh);
     PHASE(5);
     cur ^= 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1b. Blocked tridiagonalisation for larger m (panels of NB reflectors).
+// The same reflectors as the unblocked kernel, but within a panel the trailing
+// matrix is only read: step i forms y = A_tr v_i from the matrix as it stood
+// at the start of the panel and corrects it with the panel's earlier
+// reflectors, y -= V (W^H v) + W (V^H v); the panel's 2 NB rank-one terms
+// A -= V W^H + W V^H are applied once at its end.  Only the lower triangle is
+// read or written: a 32 x 32 tile below the diagonal feeds both y_R += A v_C
+// and y_C += A^H v_R.  Each wave takes whole tiles (the next one is loaded
+// while the current one is used), each lane a 4 x 4 block (rows
+// 4 (lane / 8) + q, columns lane % 8 + 8 p); row and column sums are
+// finished with three lane exchanges each and added into y in LDS.  The
+// panel's V and W stay in LDS.  The trailing matrix is read about once per
+// step at half size, against a read and a write of the full matrix per step in
+// the unblocked form.  The LDS additions into y from different waves land in
+// an order that depends on timing, so results can differ between runs in the
+// last bits.
+// ---------------------------------------------------------------------------
+constexpr int T2_NT = 512;
+constexpr int T2_W = T2_NT / 64;
+
+__device__ __forceinline__ cx<double> cadd(cx<double> a, cx<double> b) { return cx<double>{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cx<double> shfl_xor_cx(cx<double> v, int mask) {
+  return cx<double>{__shfl_xor(v.re, mask, 64), __shfl_xor(v.im, mask, 64)};
+}
+// a += x * y
+__device__ __forceinline__ void cfma(cx<double>& a, cx<double> x, cx<double> y) {
+  a.re = fma(x.re, y.re, fma(-x.im, y.im, a.re));
+  a.im = fma(x.re, y.im, fma(x.im, y.re, a.im));
+}
+// a += conj(x) * y
+__device__ __forceinline__ void cfmac(cx<double>& a, cx<double> x, cx<double> y) {
+  a.re = fma(x.re, y.re, fma(x.im, y.im, a.re));
+  a.im = fma(x.re, y.im, fma(-x.im, y.re, a.im));
+}
+
+__device__ __forceinline__ cx<double> block_sum2(cx<double> v, double* red) {
+  v.re = wave_sum(v.re);
+  v.im = wave_sum(v.im);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * w] = v.re;
+    red[2 * w + 1] = v.im;
+  }
+  __syncthreads();
+  cx<double> r{0, 0};
+#pragma unroll
+  for (int i = 0; i < T2_W; ++i) {
+    r.re += red[2 * i];
+    r.im += red[2 * i + 1];
+  }
+  return r;
+}
+
+// Sum of a 4-vector over the eight lanes that differ only in lane bits X0, X1,
+// X2 (three exchanges, halving the vector each time): the result is the total
+// of element 2 [lane & X0] + [lane & X1]; the two lanes differing in X2 hold
+// the same total.
+template <int X0, int X1, int X2>
+__device__ __forceinline__ cx<double> reduce4(const cx<double> (&y)[4], int lane) {
+  const bool h0 = lane & X0, h1 = lane & X1;
+  const cx<double> k0 = h0 ? y[2] : y[0], k1 = h0 ? y[3] : y[1];
+  const cx<double> s0 = h0 ? y[0] : y[2], s1 = h0 ? y[1] : y[3];
+  const cx<double> t0 = cadd(k0, shfl_xor_cx(s0, X0)), t1 = cadd(k1, shfl_xor_cx(s1, X0));
+  const cx<double> kk = h1 ? t1 : t0, ss = h1 ? t0 : t1;
+  const cx<double> u = cadd(kk, shfl_xor_cx(ss, X1));
+  return cadd(u, shfl_xor_cx(u, X2));
+}
+
+// tile t of the lower triangle of tiles with first tile row / column J0 (row-major order)
+__device__ __forceinline__ void tri_tile(int t, int J0, int& I, int& J) {
+  int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= t) ++a;
+  while (a * (a + 1) / 2 > t) --a;
+  J = t - a * (a + 1) / 2 + J0;
+  I = a + J0;
+}
+
+// The lane's 4 x 4 block: rows r0 + q, columns c0 + 8 p (eight lanes of a row
+// group read one contiguous 128-byte segment per access).  Rows are clamped
+// into the matrix; columns past m - 1 (last tile column only) read the next
+// row, or for the last row the vectors stored after the matrix, and are masked.
+__device__ __forceinline__ void load_block(const cx<double>* A, int m, int r0, int c0, cx<double> (&a)[4][4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const cx<double>* rp = A + (int64_t)min(r0 + q, m - 1) * m + c0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) a[q][p] = rp[8 * p];
+  }
+}
+
+// y_R += A_blk v_C and y_C += A_blk^H v_R for the lane's block; MASK handles
+// the tiles on the diagonal, at the first trailing column or past row m - 1.
+template <bool MASK>
+__device__ __forceinline__ void symv_block(const cx<double> (&a)[4][4], const cx<double>* vcur, int r0, int c0,
+                                           int m, int cmin, cx<double> (&yR)[4], cx<double> (&yC)[4]) {
+  cx<double> vr[4], vc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    vr[q] = vcur[r0 + q];
+    vc[q] = vcur[c0 + 8 * q];
+    yR[q] = yC[q] = cx<double>{0, 0};
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      cx<double> x = a[q][p];
+      if (MASK) {
+        const int r = r0 + q, c = c0 + 8 * p;
+        const bool ok = r < m && c >= cmin && r >= c;
+        if (!ok) x = cx<double>{0, 0};
+        if (r == c) x.im = 0.0;
+        cfma(yR[q], x, vc[p]);
+        if (r == c) x = cx<double>{0, 0};
+        cfmac(yC[p], x, vr[q]);
+      } else {
+        cfma(yR[q], x, vc[p]);
+        cfmac(yC[p], x, vr[q]);
+      }
+    }
+  }
+}
+
+// A_blk -= V_R W_C^H + W_R V_C^H over the panel's k < pw terms
+__device__ __forceinline__ void rank_block(cx<double> (&a)[4][4], const cx<double>* Vl, const cx<double>* Wl, int MP,
+                                           int pw, int r0, int c0) {
+  for (int k = 0; k < pw; ++k) {
+    cx<double> vr[4], wr[4], vc[4], wc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      vr[q] = Vl[k * MP + r0 + q];
+      wr[q] = Wl[k * MP + r0 + q];
+      vc[q] = Vl[k * MP + c0 + 8 * q];
+      wc[q] = Wl[k * MP + c0 + 8 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const cx<double> nv{-vr[q].re, -vr[q].im}, nw{-wr[q].re, -wr[q].im};
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        // a -= v_r conj(w_c) + w_r conj(v_c)  ==  a += conj(w_c) (-v_r) + conj(v_c) (-w_r)
+        cfmac(a[q][p], wc[p], nv);
+        cfmac(a[q][p], vc[p], nw);
+      }
+    }
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __restrict__ Gpart, int nsum,
+                                                          int64_t part_stride, int m, int MP, unsigned char* scratch,
+                                                          size_t per_slice, int upper_only) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cx<double>* vcur = reinterpret_cast<cx<double>*>(smem);  // MP: v of the current step (0 outside its range)
+  cx<double>* y = vcur + MP;                                // MP: A_tr v
+  cx<double>* col = y + MP;                                 // MP: the updated column of the step
+  cx<double>* Vl = col + MP;                                // NB x MP: the panel's reflectors
+  cx<double>* Wl = Vl + NB * MP;                            // NB x MP: their update vectors
+  cx<double>* xs = Wl + NB * MP;                            // 2 NB: W^H v and V^H v
+  __shared__ double red[2 * T2_W];
+  __shared__ cx<double> s_tau, s_scale;
+  __shared__ int s_skip;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int f = blockIdx.x;
+  const HeigView hv = heig_view(scratch, per_slice, f, m);
+  cx<double>* A = hv.A;
+  PHASE_T0();
+  tri_load_hermitian<T2_NT>(Gpart + (int64_t)f * m * m, nsum, part_stride, m, upper_only, A);
+  for (int r = tid; r < (2 * NB + 3) * MP; r += T2_NT) vcur[r] = cx<double>{0, 0};
+  const int la = lane >> 3, lb = lane & 7;
+  const int T = MP / 32;
+  __syncthreads();
+  PHASE(8);
+
+  // The trailing matrix is only read within a panel, so a step's column and
+  // its first symv tiles are requested early: the column one step ahead, the
+  // tiles before the column update.  Row indices are clamped into the matrix.
+  cx<double> colnext[2];
+  for (int j0 = 0; j0 < m - 1; j0 += NB) {
+    const int pw = min(NB, m - 1 - j0);
+    for (int ii = 0; ii < pw; ++ii) {
+      const int i = j0 + ii;
+      cx<double> colv[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (ii == 0) colv[u] = A[(int64_t)min(i + tid + u * T2_NT, m - 1) * m + i];
+        else colv[u] = colnext[u];
+      }
+      if (ii + 1 < pw) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) colnext[u] = A[(int64_t)min(i + 1 + tid + u * T2_NT, m - 1) * m + i + 1];
+      }
+      const int sJ0 = (i + 1) >> 5, snT = T - sJ0;
+      const int sntile = snT * (snT + 1) / 2;
+      auto stile_rc = [&](int t, int& r0, int& c0) {
+        int I, J;
+        tri_tile(min(t, sntile - 1), sJ0, I, J);
+        r0 = 32 * I + 4 * la;
+        c0 = 32 * J + lb;
+      };
+      cx<double> a0[4][4], a1[4][4];
+      {
+        int r0, c0;
+        stile_rc(wv, r0, c0);
+        load_block(A, m, r0, c0, a0);
+      }
+      // (1) column i (rows i..m-1) brought up to date with the panel's earlier terms
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int r = i + tid + u * T2_NT;
+        if (r >= m) continue;
+        cx<double> a = colv[u];
+        for (int k = 0; k < ii; ++k) {
+          const cx<double> vr = Vl[k * MP + r], wr = Wl[k * MP + r];
+          const cx<double> vi = Vl[k * MP + i], wi = Wl[k * MP + i];
+          // a -= v_r conj(w_i) + w_r conj(v_i)
+          a.re -= (vr.re * wi.re + vr.im * wi.im) + (wr.re * vi.re + wr.im * vi.im);
+          a.im -= (vr.im * wi.re - vr.re * wi.im) + (wr.im * vi.re - wr.re * vi.im);
+        }
+        col[r] = a;
+      }
+      __syncthreads();
+      PHASE(9);
+      // (2) reflector from alpha = col[i+1], x = col[i+2..m-1]
+      double s2 = 0;
+      for (int r = i + 2 + tid; r < m; r += T2_NT) s2 += col[r].re * col[r].re + col[r].im * col[r].im;
+      s2 = block_sum2(cx<double>{s2, 0.0}, red).re;
+      if (tid == 0) {
+        hv.d[i] = col[i].re;
+        const double ar = col[i + 1].re, ai = col[i + 1].im;
+        if (s2 == 0.0 && ai == 0.0) {
+          s_skip = 1;
+          hv.e[i] = ar;
+          s_tau = cx<double>{0, 0};
+        } else {
+          s_skip = 0;
+          const double beta = -copysign(sqrt(ar * ar + ai * ai + s2), ar);
+          s_tau = cx<double>{(beta - ar) / beta, -ai / beta};
+          const double dr = ar - beta, di = ai;
+          const double den = dr * dr + di * di;
+          s_scale = cx<double>{dr / den, -di / den};
+          hv.e[i] = beta;
+        }
+        hv.tau[i] = s_tau;
+      }
+      __syncthreads();
+      const bool skip = s_skip != 0;
+      const cx<double> tau = s_tau, scale = s_scale;
+      // v (v[i+1] = 1) into LDS, into the panel and into row i of A; y = 0
+      for (int r = i + 1 + tid; r < m; r += T2_NT) {
+        cx<double> v;
+        if (r == i + 1)
+          v = cx<double>{1.0, 0.0};
+        else if (skip)
+          v = cx<double>{0.0, 0.0};
+        else
+          v = cmulc(col[r], scale);
+        vcur[r] = v;
+        Vl[ii * MP + r] = v;
+        A[(int64_t)i * m + r] = v;
+        y[r] = cx<double>{0, 0};
+      }
+      if (tid == 0) vcur[i] = cx<double>{0, 0};
+      __syncthreads();
+      PHASE(10);
+      // (3a) x1 = W^H v, x2 = V^H v over rows i+1..m-1 (one wave per product)
+      for (int dd = wv; dd < 2 * ii; dd += T2_W) {
+        const cx<double>* X = (dd < ii ? Wl + dd * MP : Vl + (dd - ii) * MP);
+        cx<double> acc{0, 0};
+        for (int r = i + 1 + lane; r < m; r += 64) cfmac(acc, X[r], vcur[r]);
+        acc.re = wave_sum(acc.re);
+        acc.im = wave_sum(acc.im);
+        if (lane == 0) xs[dd] = acc;
+      }
+      // (3b) y = A_tr v over the lower triangle of rows / columns >= i+1
+      {
+        const int J0 = sJ0, ntile = sntile;
+        auto process = [&](const cx<double>(&a)[4][4], int t) {
+          int I, J;
+          tri_tile(t, J0, I, J);
+          const int r0 = 32 * I + 4 * la, c0 = 32 * J + lb;
+          cx<double> yR[4], yC[4];
+          if (I > J && 32 * J >= i + 1 && 32 * I + 32 <= m)
+            symv_block<false>(a, vcur, r0, c0, m, i + 1, yR, yC);
+          else
+            symv_block<true>(a, vcur, r0, c0, m, i + 1, yR, yC);
+          const cx<double> sr = reduce4<4, 2, 1>(yR, lane);
+          const cx<double> sc = reduce4<32, 16, 8>(yC, lane);
+          if (!(lane & 1)) {
+            const int q = ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+            atomicAdd(&y[r0 + q].re, sr.re);
+            atomicAdd(&y[r0 + q].im, sr.im);
+          }
+          if (!(la & 1)) {
+            const int p = ((la >> 2) & 1) * 2 + ((la >> 1) & 1);
+            atomicAdd(&y[c0 + 8 * p].re, sc.re);
+            atomicAdd(&y[c0 + 8 * p].im, sc.im);
+          }
+        };
+        // two tile buffers (the first requested at the start of the step);
+        // the next tile is in flight while one is used
+        int r0, c0;
+        for (int t = wv; t < ntile; t += 2 * T2_W) {
+          stile_rc(t + T2_W, r0, c0);
+          load_block(A, m, r0, c0, a1);
+          process(a0, t);
+          if (t + T2_W >= ntile) break;
+          stile_rc(t + 2 * T2_W, r0, c0);
+          load_block(A, m, r0, c0, a0);
+          process(a1, t + T2_W);
+        }
+      }
+      __syncthreads();
+      PHASE(11);
+      // (4) y -= V x1 + W x2; w = tau y; w += alpha v with alpha = -tau (w^H v) / 2
+      //     (rows i+1..m-1, at most two per thread)
+      cx<double> wl[2];
+      cx<double> dot{0, 0};
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int r = i + 1 + tid + u * T2_NT;
+        wl[u] = cx<double>{0, 0};
+        if (r < m) {
+          cx<double> yy = y[r];
+          for (int k = 0; k < ii; ++k) {
+            const cx<double> nx1{-xs[k].re, -xs[k].im}, nx2{-xs[ii + k].re, -xs[ii + k].im};
+            cfma(yy, Vl[k * MP + r], nx1);
+            cfma(yy, Wl[k * MP + r], nx2);
+          }
+          wl[u] = cmulc(tau, yy);
+          cfmac(dot, wl[u], vcur[r]);
+        }
+      }
+      dot = block_sum2(dot, red);
+      const cx<double> alpha = cmulc(cx<double>{-0.5 * tau.re, -0.5 * tau.im}, dot);
+      const bool zero = tau.re == 0.0 && tau.im == 0.0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int r = i + 1 + tid + u * T2_NT;
+        if (r < m) {
+          cx<double> w = wl[u];
+          cfma(w, alpha, vcur[r]);
+          Wl[ii * MP + r] = zero ? cx<double>{0, 0} : w;
+        }
+      }
+      __syncthreads();
+      PHASE(12);
+    }
+    // (5) A -= V W^H + W V^H on the lower triangle of rows / columns >= j0 + pw
+    const int rs = j0 + pw;
+    if (rs < m) {
+      const int J0 = rs >> 5, nT = T - J0;
+      const int ntile = nT * (nT + 1) / 2;
+      auto tile_rc = [&](int t, int& r0, int& c0) {
+        int I, J;
+        tri_tile(min(t, ntile - 1), J0, I, J);
+        r0 = 32 * I + 4 * la;
+        c0 = 32 * J + lb;
+      };
+      auto process = [&](cx<double>(&a)[4][4], int t) {
+        int I, J;
+        tri_tile(t, J0, I, J);
+        const int r0 = 32 * I + 4 * la, c0 = 32 * J + lb;
+        rank_block(a, Vl, Wl, MP, pw, r0, c0);
+        if (I > J && 32 * J >= rs && 32 * I + 32 <= m) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            cx<double>* rp = A + (int64_t)(r0 + q) * m + c0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) rp[8 * p] = a[q][p];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+              const int r = r0 + q, c = c0 + 8 * p;
+              if (r < m && c >= rs && r >= c) A[(int64_t)r * m + c] = a[q][p];
+            }
+          }
+        }
+      };
+      cx<double> a0[4][4], a1[4][4];
+      int r0, c0;
+      tile_rc(wv, r0, c0);
+      load_block(A, m, r0, c0, a0);
+      for (int t = wv; t < ntile; t += 2 * T2_W) {
+        tile_rc(t + T2_W, r0, c0);
+        load_block(A, m, r0, c0, a1);
+        process(a0, t);
+        if (t + T2_W >= ntile) break;
+        tile_rc(t + 2 * T2_W, r0, c0);
+        load_block(A, m, r0, c0, a0);
+        process(a1, t + T2_W);
+      }
+    }
+    __syncthreads();
+    PHASE(13);
+  }
+  if (tid == 0) {
+    hv.d[m - 1] = A[(int64_t)(m - 1) * m + (m - 1)].re;
+    hv.e[m - 1] = 0.0;
   }
 }
 
@@ -743,6 +1175,10 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
     // dynamic LDS limits, leaving room for each kernel's static LDS
     (void)hipFuncSetAttribute((const void*)heig_tridiag_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               152 * 1024);
+    (void)hipFuncSetAttribute((const void*)heig_tri2_kernel<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              152 * 1024);
+    (void)hipFuncSetAttribute((const void*)heig_tri2_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              152 * 1024);
     (void)hipFuncSetAttribute((const void*)heig_invit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               152 * 1024);
     (void)hipFuncSetAttribute((const void*)heig_backxf_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -762,7 +1198,19 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
   }
   const size_t sm1 = vec_bytes + (size_t)Lsw * Lsw * sizeof(cx<double>);
   hipError_t e = hipSuccess;
-  if (stages & HEIG_TRIDIAG) {
+  // blocked form when the matrix spans a few tiles and its panel fits in LDS
+  const int MP = (m + 31) / 32 * 32;
+  auto sm2 = [&](int nb) { return ((size_t)(2 * nb + 3) * MP + 2 * nb) * sizeof(cx<double>); };
+  const bool blocked = m >= 64 && m <= 2 * T2_NT + 1;
+  if ((stages & HEIG_TRIDIAG) && blocked && sm2(8) <= lds_total) {
+    hipLaunchKernelGGL(heig_tri2_kernel<8>, dim3(batch), dim3(T2_NT), sm2(8), s, (const cx<double>*)Gpart, nsum,
+                       part_stride, m, MP, sc, per, upper_only ? 1 : 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else if ((stages & HEIG_TRIDIAG) && blocked && sm2(4) <= lds_total) {
+    hipLaunchKernelGGL(heig_tri2_kernel<4>, dim3(batch), dim3(T2_NT), sm2(4), s, (const cx<double>*)Gpart, nsum,
+                       part_stride, m, MP, sc, per, upper_only ? 1 : 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else if (stages & HEIG_TRIDIAG) {
     hipLaunchKernelGGL(heig_tridiag_kernel, dim3(batch), dim3(TRI_NT), sm1, s, (const cx<double>*)Gpart, nsum,
                        part_stride, m, sc, per, Lsw, upper_only ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;

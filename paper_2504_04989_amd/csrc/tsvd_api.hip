@@ -1001,6 +1001,26 @@ int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t row
   return TSVD_OK;
 }
 
+size_t tsvd_diag_heig_ws_bytes(int64_t m, int64_t k, int64_t batch) {
+  if (m < 1 || m > 1024 || k < 1 || k > m || batch < 1 || batch > 65535) return 0;
+  return 256 + align256((size_t)batch * heig_scratch_bytes((int)m, (int)k));
+}
+
+int tsvd_diag_heig(const void* G, int64_t m, int64_t k, int64_t batch, void* lambda, void* W, void* ws,
+                   size_t ws_bytes, void* stream) {
+  const size_t need = tsvd_diag_heig_ws_bytes(m, k, batch);
+  if (!G || !lambda || !W || need == 0) return fail(TSVD_EINVAL, "bad arguments");
+  if (!ws || ws_bytes < need || !aligned(ws, 256)) return fail(TSVD_ENOMEM, "workspace too small");
+  const hipStream_t s = (hipStream_t)stream;
+  unsigned char* w = static_cast<unsigned char*>(ws);
+  int* info = reinterpret_cast<int*>(w);
+  HIPCHK(zero_info(info, s));
+  HIPCHK(heig_topk(static_cast<const double*>(G), 1, 0, (int)m, (int)k, (int)batch, static_cast<double*>(lambda),
+                   static_cast<double*>(W), w + 256, info, s, HEIG_TRIDIAG | HEIG_BISECT | HEIG_INVIT | HEIG_BACKXF,
+                   false));
+  return TSVD_OK;
+}
+
 int tsvd_diag_zgemm(const void* A, int a_conj, const void* B, int b_conj, void* C, int64_t M, int64_t N, int64_t K,
                     int64_t batch, double alpha, double beta, int dtype, void* stream) {
   if (!A || !B || !C || M < 0 || N < 0 || K < 0 || batch < 0 || (dtype != 0 && dtype != 1) || (a_conj && b_conj) ||
