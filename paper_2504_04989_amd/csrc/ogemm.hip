@@ -330,16 +330,61 @@ void fill_grid(OArgs& a, int TT) {
 
 }  // namespace
 
-int ogemm_tn_split(int M, int K, int N, int batch) {
-  const int TT = othin_tiles(N);
-  const int64_t tiles = (int64_t)((N + 8 * TT - 1) / (8 * TT)) * ((M + 63) / 64) * batch;
-  int ns = 1;
-  while (tiles * ns < 1024 && ns < 16 && K / (2 * ns) >= 128) ns *= 2;
-  return ns;
+namespace {
+
+// Concurrent workgroup slots: two 256-thread workgroups per CU (the kernel's
+// occupancy), times the device's CU count.
+int ogemm_slots() {
+  static int slots = 0;
+  if (!slots) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cus <= 0)
+      cus = 256;
+    slots = 2 * cus;
+  }
+  return slots;
+}
+
+// Workgroups of a TN launch that do work (the others skip tiles strictly
+// below the diagonal of a square upper-only product).
+int64_t tn_live_tiles(int M, int N, int batch, bool upper) {
+  const int TT = othin_tiles(N), NCH = 8 * TT;
+  const int nthin = (N + NCH - 1) / NCH, nbig = (M + 63) / 64;
+  int64_t live = 0;
+  for (int bt = 0; bt < nbig; ++bt)
+    for (int tc = 0; tc < nthin; ++tc) live += (upper && M == N && bt * 64 > tc * NCH + NCH - 1) ? 0 : 1;
+  return live * batch;
+}
+
+}  // namespace
+
+// Split of the contraction for a TN product: the smallest makespan in K steps
+// over the device's workgroup slots, rounds x (steps per split + a fixed
+// per-workgroup cost), plus the reduction of the partials.
+int ogemm_tn_split(int M, int K, int N, int batch, bool upper) {
+  const int64_t live = tn_live_tiles(M, N, batch, upper);
+  const int64_t slots = ogemm_slots();
+  int best = 1;
+  double bcost = 1e300;
+  for (int ns = 1; ns <= 16; ++ns) {
+    int kc = (K + ns - 1) / ns;
+    kc = (kc + OKSTEP - 1) / OKSTEP * OKSTEP;
+    if (ns > 1 && kc < 16 * OKSTEP) break;  // keep at least 16 steps per split
+    const int nsx = (K + kc - 1) / kc;
+    const int64_t rounds = (live * nsx + slots - 1) / slots;
+    const double cost = (double)rounds * (kc / OKSTEP + 6) + (nsx > 1 ? 0.5 * nsx : 0.0);
+    if (cost < bcost - 1e-9) {
+      bcost = cost;
+      best = nsx;
+    }
+  }
+  return best;
 }
 
 size_t ogemm_tn_part_bytes(int M, int K, int N, int batch) {
-  return (size_t)ogemm_tn_split(M, K, N, batch) * batch * M * N * 16;
+  const int ns = std::max(ogemm_tn_split(M, K, N, batch, false), ogemm_tn_split(M, K, N, batch, true));
+  return (size_t)ns * batch * M * N * 16;
 }
 
 hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y, int64_t ly, int64_t strideY,
@@ -358,7 +403,7 @@ hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y,
   a.K = K;
   a.N = N;
   a.batch = batch;
-  a.nsplit = ogemm_tn_split(M, K, N, batch);
+  a.nsplit = ogemm_tn_split(M, K, N, batch, upper && M == N);
   int kc = (K + a.nsplit - 1) / a.nsplit;
   kc = (kc + OKSTEP - 1) / OKSTEP * OKSTEP;
   a.kchunk = kc < OKSTEP ? OKSTEP : kc;
