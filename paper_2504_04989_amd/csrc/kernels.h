@@ -42,8 +42,12 @@ struct KGemmDesc {
   void* C; int64_t ldc, strideC;
   int N, batch, mode, nsplit;
   void* part;
+  size_t part_bytes;  // size of part; a tail split is used only when it fits
 };
 hipError_t kgemm(const KGemmDesc& d, hipStream_t s);
+// Bytes of d.part that kgemm uses: nsplit > 1 partials, or (nsplit == 1) the
+// partials of the split remainder tiles (0 when there is no tail split).
+size_t kgemm_part_bytes(int M, int K, int N, int batch, int nsplit);
 // K split (and chunk) that gives the product enough workgroups to fill the chip.
 int kgemm_split(int M, int K, int N, int batch, int* kchunk);
 // BF16 / BF16x3 modes on planar data: the thin operand is first packed into

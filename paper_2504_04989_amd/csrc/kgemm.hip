@@ -54,6 +54,11 @@ struct KArgs {
   int nsplit, kchunk;
   int nbig, nthin, total, per;
   int avec;  // big-operand rows are 16-byte aligned (vector loads allowed)
+  // Tail split (nsplit == 1): tiles [0, nfull) run whole, nfull / 8 per XCD;
+  // the rem tiles after them are split rsplit ways along K (chunks of
+  // rkchunk) and write their partials to part, one 128 x NCH block per
+  // (tile, split).  rsplit == 0: no tail split.
+  int nfull, nrem, rsplit, rkchunk;
 };
 
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
@@ -68,7 +73,7 @@ struct Lds {
   static constexpr int PLANES = MODE == KM_BF16X3 ? 2 : 1;
 };
 
-template <int MODE, bool HN, int TT, int TB, bool AVEC>
+template <int MODE, bool HN, int TT, int TB, bool AVEC, bool FULL>
 __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   typedef Lds<MODE> L;
   constexpr int ROWS = TT * 16;
@@ -81,20 +86,46 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
 
   // ---- tile of this workgroup (XCD-aware order) ----
   const int id = blockIdx.x;
-  const int t = (id & 7) * a.per + (id >> 3);
-  if (t >= a.total) return;
-  int r = t;
-  const int bt = r % a.nbig;
-  r /= a.nbig;
-  const int tc = r % a.nthin;
-  r /= a.nthin;
-  const int sp = r % a.nsplit;
-  const int f = r / a.nsplit;
-  const int kb = sp * a.kchunk;
-  const int ke = min(a.K, kb + a.kchunk);
+  int bt, tc, sp, f, kb, ke, rt = -1;
+  if (a.rsplit == 0) {
+    const int t = (id & 7) * a.per + (id >> 3);
+    if (t >= a.total) return;
+    int r = t;
+    bt = r % a.nbig;
+    r /= a.nbig;
+    tc = r % a.nthin;
+    r /= a.nthin;
+    sp = r % a.nsplit;
+    f = r / a.nsplit;
+    kb = sp * a.kchunk;
+    ke = min(a.K, kb + a.kchunk);
+  } else {
+    // each XCD first runs nfull / 8 whole tiles, then its share of the split
+    // remainder (so that every XCD gets the same work)
+    const int x = id & 7, l = id >> 3, fper = a.nfull / 8;
+    int u;
+    if (l < fper) {
+      u = x * fper + l;
+      sp = 0;
+      kb = 0;
+      ke = a.K;
+    } else {
+      const int w = (l - fper) * 8 + x;
+      if (w >= a.nrem * a.rsplit) return;
+      rt = w / a.rsplit;
+      sp = w - rt * a.rsplit;
+      u = a.nfull + rt;
+      kb = sp * a.rkchunk;
+      ke = min(a.K, kb + a.rkchunk);
+    }
+    bt = u % a.nbig;
+    u /= a.nbig;
+    tc = u % a.nthin;
+    f = u / a.nthin;
+  }
   const int n0 = tc * NCH;
   const int nc = min(NCH, a.N - n0);
-  const int tt = (2 * nc + 15) / 16;  // active thin tiles
+  const int tt = FULL ? TT : (2 * nc + 15) / 16;  // active thin tiles (all of them when FULL)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q4 = lane >> 4, r16 = lane & 15;
@@ -326,7 +357,13 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   // ---- epilogue: acc[i][u][r] = C_int[col][16 i + 4 q4 + r] -> complex n = n0 + 8 i + 2 q4 + {0, 1} ----
   float* out;
   int64_t ldo;
-  if (a.nsplit > 1) {
+  if (rt >= 0) {
+    // tail split: the (tile, split) block of 128 big rows x NCH columns,
+    // indexed from the tile's first row and column
+    constexpr int BROWS = NWAVE * 16 * TB;
+    out = a.part + 2 * (((int64_t)rt * a.rsplit + sp) * BROWS * NCH) - 2 * ((int64_t)bt * BROWS * NCH + n0);
+    ldo = 2 * NCH;
+  } else if (a.nsplit > 1) {
     out = a.part + 2 * ((int64_t)sp * a.batch + f) * a.M * a.N;
     ldo = 2 * (int64_t)a.N;
   } else {
@@ -366,19 +403,57 @@ __global__ void kgemm_reduce_kernel(const float2* __restrict__ part, int nsplit,
   }
 }
 
-template <int MODE, bool HN, int TT, bool AVEC>
-hipError_t launch_tta(const KArgs& a, hipStream_t s) {
+// C of the split remainder tiles: sum of the rsplit partial blocks of each
+// (fixed order), written where the tile lies in C.
+__global__ void kgemm_tail_reduce_kernel(const float2* __restrict__ part, int nfull, int nrem, int rsplit, int nbig,
+                                         int nthin, int brows, int nch, int M, int N, float2* __restrict__ C,
+                                         int64_t ldc, int64_t strideC) {
+  const int64_t per = (int64_t)brows * nch;
+  const int64_t total = per * nrem;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int rt = (int)(e / per);
+    const int rem = (int)(e - (int64_t)rt * per);
+    const int rl = rem / nch, nl = rem - (rem / nch) * nch;
+    int u = nfull + rt;
+    const int bt = u % nbig;
+    u /= nbig;
+    const int tc = u % nthin, f = u / nthin;
+    const int row = bt * brows + rl, n = tc * nch + nl;
+    if (row >= M || n >= N) continue;
+    const float2* p = part + (int64_t)rt * rsplit * per + rem;
+    float2 sum = p[0];
+    for (int j = 1; j < rsplit; ++j) {
+      const float2 v = p[(int64_t)j * per];
+      sum.x += v.x;
+      sum.y += v.y;
+    }
+    C[f * strideC + (int64_t)row * ldc + n] = sum;
+  }
+}
+
+template <int MODE, bool HN, int TT, bool AVEC, bool FULL>
+hipError_t launch_ttaf(const KArgs& a, hipStream_t s) {
   constexpr int TB = 2;
   const size_t lds = (size_t)2 * TT * 16 * Lds<MODE>::STRIDE * Lds<MODE>::PLANES * 4;
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)kgemm_kernel<MODE, HN, TT, TB, AVEC>,
+    (void)hipFuncSetAttribute((const void*)kgemm_kernel<MODE, HN, TT, TB, AVEC, FULL>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
     attr = true;
   }
-  hipLaunchKernelGGL((kgemm_kernel<MODE, HN, TT, TB, AVEC>), dim3(8 * a.per), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((kgemm_kernel<MODE, HN, TT, TB, AVEC, FULL>), dim3(8 * a.per), dim3(256), lds, s, a);
   return hipGetLastError();
+}
+
+// FULL: every thin chunk, the last one included, fills all TT tiles, so the
+// per-tile guards are compile-time and the tile loop is straight-line code.
+template <int MODE, bool HN, int TT, bool AVEC>
+hipError_t launch_tta(const KArgs& a, hipStream_t s) {
+  constexpr int NCH = TT * 8;
+  const int nlast = a.N - (a.nthin - 1) * NCH;
+  if ((2 * nlast + 15) / 16 == TT) return launch_ttaf<MODE, HN, TT, AVEC, true>(a, s);
+  return launch_ttaf<MODE, HN, TT, AVEC, false>(a, s);
 }
 
 template <int MODE, bool HN, int TT>
@@ -406,6 +481,58 @@ int kgemm_thin_tiles(int N) {
   if (nn <= 64) return 8;
   if (nn <= 112) return 14;
   return 16;
+}
+
+namespace {
+
+// Concurrent workgroup slots of the product kernel: two per CU.
+int kgemm_slots() {
+  static int slots = 0;
+  if (!slots) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cus <= 0)
+      cus = 256;
+    slots = 2 * cus;
+  }
+  return slots;
+}
+
+// Tail split of an unsplit product: with T tiles over S slots, the last
+// T mod S tiles would run as a nearly empty extra round; they are split
+// along K instead so that the round takes a fraction of a tile's time.
+struct TailPlan {
+  int nfull, nrem, rsplit, rkchunk;
+  size_t bytes;
+};
+TailPlan kgemm_tail_plan(int M, int K, int N, int batch) {
+  TailPlan t{0, 0, 0, 0, 0};
+  const int TT = kgemm_thin_tiles(N);
+  const int64_t nthin = (N + 8 * TT - 1) / (8 * TT);
+  const int64_t nbig = (M + NWAVE * 16 * 2 - 1) / (NWAVE * 16 * 2);
+  const int64_t tiles = nthin * nbig * batch;
+  const int64_t S = kgemm_slots();
+  const int64_t nfull = tiles / S * S / 8 * 8;
+  const int64_t nrem = tiles - nfull;
+  if (nfull == 0 || nrem == 0) return t;
+  int rs = (int)std::min<int64_t>(16, S / nrem);
+  rs = std::min(rs, K / (8 * KSTEP));  // at least 8 K steps per split
+  if (rs < 2) return t;
+  int kc = (K + rs - 1) / rs;
+  kc = (kc + KSTEP - 1) / KSTEP * KSTEP;
+  t.nfull = (int)nfull;
+  t.nrem = (int)nrem;
+  t.rsplit = (K + kc - 1) / kc;
+  t.rkchunk = kc;
+  t.bytes = (size_t)nrem * t.rsplit * (NWAVE * 16 * 2) * (8 * TT) * 8;
+  return t;
+}
+
+}  // namespace
+
+size_t kgemm_part_bytes(int M, int K, int N, int batch, int nsplit) {
+  if (nsplit > 1) return (size_t)nsplit * batch * M * N * 8;
+  return kgemm_tail_plan(M, K, N, batch).bytes;
 }
 
 int kgemm_split(int M, int K, int N, int batch, int* kchunk) {
@@ -458,6 +585,20 @@ hipError_t kgemm(const KGemmDesc& d, hipStream_t s) {
   a.total = (int)total;
   a.per = (a.total + 7) / 8;
   a.avec = ((d.lda & 1) == 0 && (d.strideA & 1) == 0 && ((uintptr_t)d.A & 15) == 0) ? 1 : 0;
+  a.nfull = a.nrem = a.rsplit = a.rkchunk = 0;
+  TailPlan tp{0, 0, 0, 0, 0};
+  if (a.nsplit == 1 && d.part) {
+    tp = kgemm_tail_plan(M, K, d.N, d.batch);
+    if (tp.rsplit > 1 && d.part_bytes >= tp.bytes) {
+      a.nfull = tp.nfull;
+      a.nrem = tp.nrem;
+      a.rsplit = tp.rsplit;
+      a.rkchunk = tp.rkchunk;
+      a.per = tp.nfull / 8 + (tp.nrem * tp.rsplit + 7) / 8;
+    } else {
+      tp.rsplit = 0;
+    }
+  }
   hipError_t e;
   switch (d.mode) {
     case KM_F32: e = d.herm ? launch_mode<KM_F32, true>(a, TT, s) : launch_mode<KM_F32, false>(a, TT, s); break;
@@ -467,7 +608,16 @@ hipError_t kgemm(const KGemmDesc& d, hipStream_t s) {
       break;
     default: return hipErrorInvalidValue;
   }
-  if (e != hipSuccess || a.nsplit <= 1) return e;
+  if (e != hipSuccess) return e;
+  if (a.rsplit > 1) {
+    const int TT = kgemm_thin_tiles(d.N);
+    const int64_t n = (int64_t)a.nrem * (NWAVE * 16 * 2) * (8 * TT);
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(kgemm_tail_reduce_kernel, dim3(blocks), dim3(256), 0, s, (const float2*)d.part, a.nfull, a.nrem,
+                       a.rsplit, a.nbig, a.nthin, NWAVE * 16 * 2, 8 * TT, M, d.N, (float2*)d.C, d.ldc, d.strideC);
+    return hipGetLastError();
+  }
+  if (a.nsplit <= 1) return e;
   const int64_t n = (int64_t)M * d.N * d.batch;
   const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(kgemm_reduce_kernel, dim3(blocks), dim3(256), 0, s, (const float2*)d.part, a.nsplit, d.batch, M,

@@ -47,6 +47,7 @@ struct Plan {
   int nsplit_g, kchunk_g;       // split-K for G = T^H T (K = n2)
   int kmode;                    // Krylov-product arithmetic (KM_*) when dt == DT_F32
   int ks_ax, ks_ahy;            // K splits of the Krylov products A X and A^H Y
+  size_t kpart_bytes;           // their partials (K splits or tail splits)
   // workspace offsets (bytes)
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
       o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, o_kpack,
@@ -157,9 +158,15 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_wbar = take(bwd ? (size_t)F * n1 * b * cs : 0);
   p->o_tbar = take(bwd ? (size_t)F * n2 * b * cs : 0);
   {
-    const size_t kp_ax = p->ks_ax > 1 ? (size_t)p->ks_ax * F * n1 * b * 8 : 0;
-    const size_t kp_ahy = p->ks_ahy > 1 ? (size_t)p->ks_ahy * F * n2 * b * 8 : 0;
-    p->o_kpart = take(std::max(kp_ax, kp_ahy));
+    size_t kp = std::max(p->ks_ax > 1 ? (size_t)p->ks_ax * F * n1 * b * 8 : 0,
+                         p->ks_ahy > 1 ? (size_t)p->ks_ahy * F * n2 * b * 8 : 0);
+    if (p->dt == DT_F32 && p->kmode != KM_BF16) {
+      // unsplit products split their last, partial round of tiles along K
+      if (p->ks_ax == 1) kp = std::max(kp, kgemm_part_bytes((int)n1, (int)n2, (int)b, (int)F, 1));
+      if (p->ks_ahy == 1) kp = std::max(kp, kgemm_part_bytes((int)n2, (int)n1, (int)b, (int)F, 1));
+    }
+    p->kpart_bytes = kp;
+    p->o_kpart = take(kp);
     const bool bfm = p->dt == DT_F32 && p->kmode == KM_BF16;
     p->o_kpack = take(bfm ? std::max(kgemm_bf16_pack_bytes(p->kmode, (int)n2, (int)b, (int)F),
                                      kgemm_bf16_pack_bytes(p->kmode, (int)n1, (int)b, (int)F))
@@ -423,6 +430,7 @@ int big_AX(const Ctx& c, const void* X, int64_t ldx, int64_t strideX, void* Out,
     k.mode = p.kmode;
     k.nsplit = N == p.b ? p.ks_ax : 1;
     k.part = c.at(p.o_kpart);
+    k.part_bytes = p.kpart_bytes;
     Timed tm_(K_GEMM_KRYLOV, c.s);
     if (p.kmode != KM_BF16 || N != p.b)
       HIPCHK(kgemm(k, c.s));
@@ -478,6 +486,7 @@ int big_AhY(const Ctx& c, const void* Y, int64_t ldy, int64_t strideY, void* Out
     k.mode = p.kmode;
     k.nsplit = N == p.b ? p.ks_ahy : 1;
     k.part = c.at(p.o_kpart);
+    k.part_bytes = p.kpart_bytes;
     Timed tm_(K_GEMM_KRYLOV, c.s);
     if (p.kmode != KM_BF16 || N != p.b)
       HIPCHK(kgemm(k, c.s));
@@ -963,6 +972,7 @@ size_t tsvd_diag_kgemm_ws_bytes(int herm, int64_t rows, int64_t cols, int64_t N,
   const int64_t M = herm ? cols : rows, K = herm ? rows : cols;
   size_t bytes = nsplit > 1 ? align256((size_t)nsplit * batch * M * N * 8) : 0;
   if (mode == KM_BF16) bytes += align256(kgemm_bf16_pack_bytes(mode, (int)K, (int)N, (int)batch));
+  else if (nsplit == 1) bytes += align256(kgemm_part_bytes((int)M, (int)K, (int)N, (int)batch, 1));
   return bytes;
 }
 
@@ -993,6 +1003,11 @@ int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t row
   d.nsplit = nsplit;
   unsigned char* w = static_cast<unsigned char*>(ws);
   d.part = nsplit > 1 ? w : nullptr;
+  d.part_bytes = nsplit > 1 ? (size_t)nsplit * batch * M * N * 8 : 0;
+  if (nsplit == 1 && mode != KM_BF16 && need > 0) {
+    d.part = w;
+    d.part_bytes = need;
+  }
   void* pack = w + (nsplit > 1 ? align256((size_t)nsplit * batch * M * N * 8) : 0);
   if (mode == KM_BF16)
     HIPCHK(kgemm_bf16(d, pack, (hipStream_t)stream));

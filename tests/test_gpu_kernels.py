@@ -117,3 +117,29 @@ def test_kgemm_split_is_deterministic_and_matches_unsplit():
     c0 = host(api.diag_kgemm(Ad, Xd, nsplit=1))
     assert np.array_equal(c1, c2)
     assert np.linalg.norm((c1 - c0).ravel()) <= 1e-6 * np.linalg.norm(c0.ravel())
+
+
+@pytest.mark.parametrize("herm", [False, True])
+@pytest.mark.parametrize("mode", ["f32", "bf16x3"])
+def test_kgemm_tail_split_vs_float64(herm, mode):
+    """Enough tiles for two full rounds of the device's workgroup slots plus a
+    remainder (1024 x 2048 slices, two thin chunks, 33 slices: 528 or 1056
+    tiles on 256 CUs), which the kernel splits along K; checked against a
+    float64 product and for run-to-run equality."""
+    batch, rows, cols, N = 33, 1024, 2048, 224
+    K = rows if herm else cols
+    rng = np.random.default_rng(5)
+    Ad = torch.complex(torch.tensor(rng.standard_normal((batch, rows, cols), dtype=np.float32)),
+                       torch.tensor(rng.standard_normal((batch, rows, cols), dtype=np.float32))).cuda()
+    Xd = torch.complex(torch.tensor(rng.standard_normal((batch, K, N), dtype=np.float32)),
+                       torch.tensor(rng.standard_normal((batch, K, N), dtype=np.float32))).cuda()
+    C1 = api.diag_kgemm(Ad, Xd, herm=herm, mode=mode)
+    C2 = api.diag_kgemm(Ad, Xd, herm=herm, mode=mode)
+    assert torch.equal(C1, C2)
+    A64 = Ad.to(torch.complex128)
+    opA = A64.transpose(1, 2).conj().contiguous() if herm else A64
+    ref = torch.matmul(opA, Xd.to(torch.complex128).contiguous())
+    err = (torch.linalg.norm((C1.to(torch.complex128) - ref).flatten()) / torch.linalg.norm(ref.flatten())).item()
+    # FP32 accumulation over K = 1024 or 2048 complex terms: a few 1e-6
+    tol = {"f32": 3e-6, "bf16x3": 3e-5}[mode]
+    assert err <= tol, f"rel err {err:.2e}"
