@@ -19,6 +19,8 @@
 //               cluster re-orthogonalised against each other.
 //  4. backxf    W = H Z, several workgroups per slice, each owning 8 columns
 //               of W in LDS.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -50,9 +52,16 @@ extern "C" int tsvd_phase_read(unsigned long long* out, int reset) {
 
 namespace tsvd {
 
+constexpr int TRI_PMAX = 8;  // workgroups per slice of the blocked tridiagonalisation, at most
+
 static inline size_t heig_per_slice(int m, int k) {
   (void)k;
+  const size_t mp = (size_t)(m + 31) / 32 * 32;
+  // A (m x m), tau (m), d and e (m each), the partial products exchanged by the
+  // workgroups of a slice (2 x TRI_PMAX x mp) and their barrier counters
   size_t b = (size_t)16 * m * m + (size_t)16 * m + (size_t)16 * m;
+  b = (b + 255) & ~(size_t)255;
+  b += (size_t)2 * TRI_PMAX * mp * 16 + 256;
   return (b + 255) & ~(size_t)255;
 }
 size_t heig_scratch_bytes(int m, int k) { return heig_per_slice(m, k); }
@@ -70,13 +79,20 @@ struct HeigView {
   cx<double>* tau;
   double* d;
   double* e;
+  cx<double>* ypg;  // 2 x TRI_PMAX x mp partial products of the slice's workgroups
+  unsigned* sync;   // barrier counter and abort flag of the slice's workgroups
 };
 __device__ __forceinline__ HeigView heig_view(unsigned char* scratch, size_t per_slice, int f, int m) {
   HeigView v;
-  v.A = reinterpret_cast<cx<double>*>(scratch + (size_t)f * per_slice);
+  unsigned char* base = scratch + (size_t)f * per_slice;
+  v.A = reinterpret_cast<cx<double>*>(base);
   v.tau = v.A + (size_t)m * m;
   v.d = reinterpret_cast<double*>(v.tau + m);
   v.e = v.d + m;
+  const size_t off = (((size_t)16 * m * m + (size_t)32 * m) + 255) & ~(size_t)255;
+  v.ypg = reinterpret_cast<cx<double>*>(base + off);
+  const size_t mp = (size_t)(m + 31) / 32 * 32;
+  v.sync = reinterpret_cast<unsigned*>(base + off + (size_t)2 * TRI_PMAX * mp * 16);
   return v;
 }
 
@@ -593,10 +609,101 @@ __device__ __forceinline__ void rank_block(cx<double> (&a)[4][4], const cx<doubl
   }
 }
 
+// The slice's matrix, lower triangle only: A = Hermitian part of the sum of
+// the nsum partials (or the Hermitian extension of their upper triangle),
+// rows p, p + P, ... of it (the workgroup's share).
+__device__ __forceinline__ void tri_load_lower(const cx<double>* __restrict__ G, int nsum, int64_t part_stride,
+                                               int m, int upper_only, cx<double>* A, int p, int P) {
+  for (int i = p; i < m; i += P) {
+    for (int c = threadIdx.x; c <= i; c += T2_NT) {
+      cx<double> g{0, 0}, h{0, 0};
+      for (int s = 0; s < nsum; ++s) {
+        const cx<double>* Gs = G + s * part_stride;
+        const cx<double> x = Gs[(int64_t)i * m + c], y = Gs[(int64_t)c * m + i];
+        g.re += x.re;
+        g.im += x.im;
+        h.re += y.re;
+        h.im += y.im;
+      }
+      const cx<double> lo = upper_only ? cx<double>{h.re, i == c ? 0.0 : -h.im}
+                                       : cx<double>{0.5 * (g.re + h.re), i == c ? 0.0 : 0.5 * (g.im - h.im)};
+      A[(int64_t)i * m + c] = lo;
+    }
+  }
+}
+
+// Barrier over the P workgroups of one slice (P > 1; they are co-resident by
+// cooperative launch).  ctr[0] counts arrivals, ctr[1] is set once a wait
+// runs past its bound: every later wait of the slice then returns at once,
+// the kernel finishes with wrong values and the nonfinite counter says so.
+__device__ __forceinline__ void group_sync(unsigned* ctr, unsigned& gen, int P, int* info) {
+  // every wave waits until its own global stores have reached the L2 (s_waitcnt
+  // vmcnt(0)); the one release below then writes the L2 back for the group
+  if (P > 1) __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  if (P > 1) {
+    ++gen;
+    if (threadIdx.x == 0) {
+      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned target = gen * (unsigned)P;
+      unsigned spins = 0;
+      while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins == (1u << 22)) {  // about a second: only reachable if the group is not co-resident
+          __hip_atomic_store(ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          atomicAdd(&info[INFO_NONFINITE], 1);
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // after the relaxed polls
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void heig_sync_zero_kernel(unsigned char* scratch, size_t per_slice, int m, int batch) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= batch) return;
+  unsigned* c = heig_view(scratch, per_slice, f, m).sync;
+  c[0] = 0;
+  c[1] = 0;
+}
+
+// Lighter barrier for data exchanged only through device-coherent accesses
+// (agent-scope atomic loads and stores, which bypass the XCD's L2): each wave
+// waits for its own accesses to complete, then the arrival count is bumped
+// and polled without any cache writeback or invalidation.
+__device__ __forceinline__ void group_sync_coherent(unsigned* ctr, unsigned& gen, int P, int* info) {
+  if (P <= 1) {
+    __syncthreads();
+    return;
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's coherent stores are complete
+  __syncthreads();
+  ++gen;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = gen * (unsigned)P;
+    unsigned spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins == (1u << 22)) {
+        __hip_atomic_store(ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicAdd(&info[INFO_NONFINITE], 1);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 template <int NB>
 __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __restrict__ Gpart, int nsum,
                                                           int64_t part_stride, int m, int MP, unsigned char* scratch,
-                                                          size_t per_slice, int upper_only) {
+                                                          size_t per_slice, int upper_only, int P,
+                                                          int* __restrict__ info) {
   extern __shared__ __align__(16) unsigned char smem[];
   cx<double>* vcur = reinterpret_cast<cx<double>*>(smem);  // MP: v of the current step (0 outside its range)
   cx<double>* y = vcur + MP;                                // MP: A_tr v
@@ -608,15 +715,19 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
   __shared__ cx<double> s_tau, s_scale;
   __shared__ int s_skip;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int f = blockIdx.x;
+  const int f = blockIdx.x / P, pg = blockIdx.x - f * P;  // slice, workgroup within the slice
+  const bool lead = pg == 0;                             // writes the slice's outputs
   const HeigView hv = heig_view(scratch, per_slice, f, m);
   cx<double>* A = hv.A;
+  unsigned* ctr = hv.sync;
+  unsigned gen = 0;
   PHASE_T0();
-  tri_load_hermitian<T2_NT>(Gpart + (int64_t)f * m * m, nsum, part_stride, m, upper_only, A);
+  tri_load_lower(Gpart + (int64_t)f * m * m, nsum, part_stride, m, upper_only, A, pg, P);
   for (int r = tid; r < (2 * NB + 3) * MP; r += T2_NT) vcur[r] = cx<double>{0, 0};
   const int la = lane >> 3, lb = lane & 7;
   const int T = MP / 32;
-  __syncthreads();
+  const int w0 = pg * T2_W + wv, wstep = P * T2_W;  // this wave's first tile and tile stride
+  group_sync(ctr, gen, P, info);
   PHASE(8);
 
   // The trailing matrix is only read within a panel, so a step's column and
@@ -648,7 +759,7 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
       cx<double> a0[4][4], a1[4][4];
       {
         int r0, c0;
-        stile_rc(wv, r0, c0);
+        stile_rc(w0, r0, c0);
         load_block(A, m, r0, c0, a0);
       }
       // (1) column i (rows i..m-1) brought up to date with the panel's earlier terms
@@ -673,11 +784,11 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
       for (int r = i + 2 + tid; r < m; r += T2_NT) s2 += col[r].re * col[r].re + col[r].im * col[r].im;
       s2 = block_sum2(cx<double>{s2, 0.0}, red).re;
       if (tid == 0) {
-        hv.d[i] = col[i].re;
         const double ar = col[i + 1].re, ai = col[i + 1].im;
+        double ei;
         if (s2 == 0.0 && ai == 0.0) {
           s_skip = 1;
-          hv.e[i] = ar;
+          ei = ar;
           s_tau = cx<double>{0, 0};
         } else {
           s_skip = 0;
@@ -686,9 +797,13 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
           const double dr = ar - beta, di = ai;
           const double den = dr * dr + di * di;
           s_scale = cx<double>{dr / den, -di / den};
-          hv.e[i] = beta;
+          ei = beta;
         }
-        hv.tau[i] = s_tau;
+        if (lead) {
+          hv.d[i] = col[i].re;
+          hv.e[i] = ei;
+          hv.tau[i] = s_tau;
+        }
       }
       __syncthreads();
       const bool skip = s_skip != 0;
@@ -704,7 +819,7 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
           v = cmulc(col[r], scale);
         vcur[r] = v;
         Vl[ii * MP + r] = v;
-        A[(int64_t)i * m + r] = v;
+        if (lead) A[(int64_t)i * m + r] = v;
         y[r] = cx<double>{0, 0};
       }
       if (tid == 0) vcur[i] = cx<double>{0, 0};
@@ -747,17 +862,38 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
         // two tile buffers (the first requested at the start of the step);
         // the next tile is in flight while one is used
         int r0, c0;
-        for (int t = wv; t < ntile; t += 2 * T2_W) {
-          stile_rc(t + T2_W, r0, c0);
+        for (int t = w0; t < ntile; t += 2 * wstep) {
+          stile_rc(t + wstep, r0, c0);
           load_block(A, m, r0, c0, a1);
           process(a0, t);
-          if (t + T2_W >= ntile) break;
-          stile_rc(t + 2 * T2_W, r0, c0);
+          if (t + wstep >= ntile) break;
+          stile_rc(t + 2 * wstep, r0, c0);
           load_block(A, m, r0, c0, a0);
-          process(a1, t + T2_W);
+          process(a1, t + wstep);
         }
       }
       __syncthreads();
+      if (P > 1) {
+        // partial products of the slice's workgroups, summed in workgroup order
+        // (double buffered by step parity: a workgroup is at most one exchange ahead)
+        double* yb = reinterpret_cast<double*>(hv.ypg + (int64_t)((i & 1) * P) * MP);
+        for (int r = i + 1 + tid; r < m; r += T2_NT) {
+          double* d = yb + 2 * ((int64_t)pg * MP + r);
+          __hip_atomic_store(d, y[r].re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(d + 1, y[r].im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        group_sync_coherent(ctr, gen, P, info);
+        for (int r = i + 1 + tid; r < m; r += T2_NT) {
+          cx<double> acc{0, 0};
+          for (int q = 0; q < P; ++q) {
+            const double* d = yb + 2 * ((int64_t)q * MP + r);
+            acc.re += __hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            acc.im += __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          y[r] = acc;
+        }
+        __syncthreads();
+      }
       PHASE(11);
       // (4) y -= V x1 + W x2; w = tau y; w += alpha v with alpha = -tau (w^H v) / 2
       //     (rows i+1..m-1, at most two per thread)
@@ -829,22 +965,22 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
       };
       cx<double> a0[4][4], a1[4][4];
       int r0, c0;
-      tile_rc(wv, r0, c0);
+      tile_rc(w0, r0, c0);
       load_block(A, m, r0, c0, a0);
-      for (int t = wv; t < ntile; t += 2 * T2_W) {
-        tile_rc(t + T2_W, r0, c0);
+      for (int t = w0; t < ntile; t += 2 * wstep) {
+        tile_rc(t + wstep, r0, c0);
         load_block(A, m, r0, c0, a1);
         process(a0, t);
-        if (t + T2_W >= ntile) break;
-        tile_rc(t + 2 * T2_W, r0, c0);
+        if (t + wstep >= ntile) break;
+        tile_rc(t + 2 * wstep, r0, c0);
         load_block(A, m, r0, c0, a0);
-        process(a1, t + T2_W);
+        process(a1, t + wstep);
       }
     }
-    __syncthreads();
+    group_sync(ctr, gen, P, info);
     PHASE(13);
   }
-  if (tid == 0) {
+  if (tid == 0 && lead) {
     hv.d[m - 1] = A[(int64_t)(m - 1) * m + (m - 1)].re;
     hv.e[m - 1] = 0.0;
   }
@@ -1202,13 +1338,51 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
   const int MP = (m + 31) / 32 * 32;
   auto sm2 = [&](int nb) { return ((size_t)(2 * nb + 3) * MP + 2 * nb) * sizeof(cx<double>); };
   const bool blocked = m >= 64 && m <= 2 * T2_NT + 1;
-  if ((stages & HEIG_TRIDIAG) && blocked && sm2(8) <= lds_total) {
-    hipLaunchKernelGGL(heig_tri2_kernel<8>, dim3(batch), dim3(T2_NT), sm2(8), s, (const cx<double>*)Gpart, nsum,
-                       part_stride, m, MP, sc, per, upper_only ? 1 : 0);
+  if ((stages & HEIG_TRIDIAG) && blocked && sm2(4) <= lds_total) {
+    const int nb = sm2(8) <= lds_total ? 8 : 4;
+    const size_t sm = sm2(nb);
+    const void* fn = nb == 8 ? (const void*)heig_tri2_kernel<8> : (const void*)heig_tri2_kernel<4>;
+    hipLaunchKernelGGL(heig_sync_zero_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, sc, per, m, batch);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-  } else if ((stages & HEIG_TRIDIAG) && blocked && sm2(4) <= lds_total) {
-    hipLaunchKernelGGL(heig_tri2_kernel<4>, dim3(batch), dim3(T2_NT), sm2(4), s, (const cx<double>*)Gpart, nsum,
-                       part_stride, m, MP, sc, per, upper_only ? 1 : 0);
+    // several co-resident workgroups per slice for large m when the slices
+    // leave CUs idle (cooperative launch guarantees co-residency)
+    int P = 1;
+    if (m >= 256) {
+      static int coop = -1, cus = 0;
+      if (coop < 0) {
+        int dev = 0;
+        coop = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+          (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+          (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        }
+        (void)hipGetLastError();
+      }
+      if (coop > 0 && cus > 0) P = std::min(TRI_PMAX, cus / batch);
+      if (P < 2) P = 1;
+    }
+    const cx<double>* G = (const cx<double>*)Gpart;
+    int nsum_a = nsum, m_a = m, mp_a = MP, up = upper_only ? 1 : 0;
+    int64_t ps = part_stride;
+    unsigned char* sc_a = sc;
+    size_t per_a = per;
+    int* info_a = info;
+    if (P > 1) {
+      void* args[] = {(void*)&G, (void*)&nsum_a, (void*)&ps, (void*)&m_a, (void*)&mp_a, (void*)&sc_a, (void*)&per_a,
+                      (void*)&up, (void*)&P, (void*)&info_a};
+      if (hipLaunchCooperativeKernel(fn, dim3(batch * P), dim3(T2_NT), args, (unsigned)sm, s) != hipSuccess) {
+        (void)hipGetLastError();  // not co-resident at this size: one workgroup per slice
+        P = 1;
+      }
+    }
+    if (P == 1) {
+      if (nb == 8)
+        hipLaunchKernelGGL(heig_tri2_kernel<8>, dim3(batch), dim3(T2_NT), sm, s, G, nsum_a, ps, m_a, mp_a, sc_a, per_a,
+                           up, 1, info_a);
+      else
+        hipLaunchKernelGGL(heig_tri2_kernel<4>, dim3(batch), dim3(T2_NT), sm, s, G, nsum_a, ps, m_a, mp_a, sc_a, per_a,
+                           up, 1, info_a);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else if (stages & HEIG_TRIDIAG) {
     hipLaunchKernelGGL(heig_tridiag_kernel, dim3(batch), dim3(TRI_NT), sm1, s, (const cx<double>*)Gpart, nsum,

@@ -110,7 +110,9 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
 hipError_t scale_cols(const double* W, const double* lambda, void* Wout, int m, int k, int batch, int scale_mode,
                       DType t, hipStream_t s);
 // Phase canonicalisation of (U_f, V_f) column pairs and sigma = sqrt(lambda).
-hipError_t canon_phase(void* U, int64_t n1, void* V, int64_t n2, int k, int batch, DType t, hipStream_t s);
+size_t canon_scratch_bytes(int64_t n1, int k, int batch);
+hipError_t canon_phase(void* U, int64_t n1, void* V, int64_t n2, int k, int batch, DType t, void* scratch,
+                       hipStream_t s);
 // sigma = sqrt(max(lambda, 0)) (FP64) and (sigma, 0) as complex in dtype t.
 hipError_t sigma_from_lambda(const double* lambda, double* sigma, void* scx, int64_t n, DType t, hipStream_t s);
 // U * diag(sigma): Uout (batch x n1 x k) = Uin * sigma (per slice).

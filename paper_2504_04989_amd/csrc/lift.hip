@@ -1,5 +1,7 @@
 // Small element-wise kernels around the lift of Alg. 2 (U_f = Q_f W_k,
 // V_f = C_f^H W_k diag(1/sigma)) and the phase convention of the outputs.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -87,76 +89,110 @@ hipError_t sigma_from_lambda(const double* lambda, double* sigma, void* scx, int
 // Phase convention: for every slice f and column j, find the entry of U_f(:, j)
 // of largest modulus (lowest row index on ties) and multiply U_f(:, j) and
 // V_f(:, j) by the conjugate of its phase, so that entry becomes real positive.
-// One workgroup per (f, j).
+// Three coalesced passes (rows of U_f are contiguous over j):
+//  1. partial column maxima of |U_f(i, j)|^2 over chunks of rows;
+//  2. per (f, j): the chunk results combined in chunk order, and the phase;
+//  3. U_f and V_f scaled elementwise.
+constexpr int CANON_MAXCH = 64;  // row chunks per slice
+
+static int canon_chunk_rows(int64_t n1) {
+  const int64_t cr = (n1 + CANON_MAXCH - 1) / CANON_MAXCH;
+  return (int)std::max<int64_t>(64, cr);
+}
+
+size_t canon_scratch_bytes(int64_t n1, int k, int batch) {
+  const int64_t nch = (n1 + canon_chunk_rows(n1) - 1) / canon_chunk_rows(n1);
+  // partial maxima (as double) and row indices, then one complex double phase per column
+  return (size_t)batch * k * (size_t)(nch * (8 + 4) + 16) + 256;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void canon_kernel(cx<T>* U, int64_t n1, cx<T>* V, int64_t n2, int k) {
-  __shared__ T sv[4];
-  __shared__ int si[4];
-  __shared__ T s_c, s_s;
-  const int j = blockIdx.x;
+__global__ __launch_bounds__(256) void canon_colmax_kernel(const cx<T>* __restrict__ U, int64_t n1, int k, int cr,
+                                                           double* __restrict__ pv, int* __restrict__ pi) {
+  const int ch = blockIdx.x, nch = gridDim.x;
   const int64_t f = blockIdx.y;
-  cx<T>* u = U + f * n1 * k + j;
-  cx<T>* v = V + f * n2 * k + j;
-  T best = -1;
-  int bi = 0x7fffffff;
-  for (int64_t i = threadIdx.x; i < n1; i += 256) {
-    const cx<T> a = u[i * k];
-    const T m2 = a.re * a.re + a.im * a.im;
-    if (m2 > best) {
-      best = m2;
-      bi = (int)i;
-    }
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    const T ob = __shfl_xor(best, off, 64);
-    const int oi = __shfl_xor(bi, off, 64);
-    if (ob > best || (ob == best && oi < bi)) {
-      best = ob;
-      bi = oi;
-    }
-  }
-  if ((threadIdx.x & 63) == 0) {
-    sv[threadIdx.x >> 6] = best;
-    si[threadIdx.x >> 6] = bi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    T b = sv[0];
-    int i0 = si[0];
-    for (int w = 1; w < 4; ++w)
-      if (sv[w] > b || (sv[w] == b && si[w] < i0)) {
-        b = sv[w];
-        i0 = si[w];
+  const cx<T>* u = U + f * n1 * k;
+  const int64_t r0 = (int64_t)ch * cr, r1 = min(n1, r0 + cr);
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    T best = -1;
+    int bi = 0x7fffffff;
+    for (int64_t i = r0; i < r1; ++i) {
+      const cx<T> a = u[i * k + j];
+      const T m2 = a.re * a.re + a.im * a.im;
+      if (m2 > best) {
+        best = m2;
+        bi = (int)i;
       }
-    T c = 1, s = 0;
-    if (b > 0) {
-      const cx<T> a = u[(int64_t)i0 * k];
-      const T r = sqrt(a.re * a.re + a.im * a.im);
-      c = a.re / r;
-      s = -a.im / r;  // conj(phase)
     }
-    s_c = c;
-    s_s = s;
-  }
-  __syncthreads();
-  const T c = s_c, s = s_s;
-  for (int64_t i = threadIdx.x; i < n1; i += 256) {
-    const cx<T> a = u[i * k];
-    u[i * k] = cx<T>{a.re * c - a.im * s, a.re * s + a.im * c};
-  }
-  for (int64_t i = threadIdx.x; i < n2; i += 256) {
-    const cx<T> a = v[i * k];
-    v[i * k] = cx<T>{a.re * c - a.im * s, a.re * s + a.im * c};
+    pv[(f * nch + ch) * k + j] = (double)best;
+    pi[(f * nch + ch) * k + j] = bi;
   }
 }
-hipError_t canon_phase(void* U, int64_t n1, void* V, int64_t n2, int k, int batch, DType t, hipStream_t s) {
-  if (batch == 0 || k == 0) return hipSuccess;
-  const dim3 g(k, batch);
-  if (t == DT_F64)
-    hipLaunchKernelGGL(canon_kernel<double>, g, dim3(256), 0, s, (cx<double>*)U, n1, (cx<double>*)V, n2, k);
-  else
-    hipLaunchKernelGGL(canon_kernel<float>, g, dim3(256), 0, s, (cx<float>*)U, n1, (cx<float>*)V, n2, k);
+
+template <typename T>
+__global__ __launch_bounds__(256) void canon_pick_kernel(const cx<T>* __restrict__ U, int64_t n1, int k, int nch,
+                                                         const double* __restrict__ pv, const int* __restrict__ pi,
+                                                         cx<double>* __restrict__ ph) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t f = blockIdx.y;
+  if (j >= k) return;
+  double best = -1;
+  int bi = 0x7fffffff;
+  for (int ch = 0; ch < nch; ++ch) {  // chunks in row order: a tie keeps the lower row
+    const double v = pv[(f * nch + ch) * k + j];
+    if (v > best) {
+      best = v;
+      bi = pi[(f * nch + ch) * k + j];
+    }
+  }
+  T c = 1, s = 0;
+  if (best > 0) {
+    const cx<T> a = U[f * n1 * k + (int64_t)bi * k + j];
+    const T r = sqrt(a.re * a.re + a.im * a.im);
+    c = a.re / r;
+    s = -a.im / r;  // conj(phase)
+  }
+  ph[f * k + j] = cx<double>{(double)c, (double)s};
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void canon_scale_kernel(cx<T>* __restrict__ X, int64_t rows, int k, int batch,
+                                                          const cx<double>* __restrict__ ph) {
+  const int64_t per = rows * k, total = per * batch;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = e / per;
+    const int j = (int)(e % k);
+    const cx<double> p = ph[f * k + j];
+    const T c = (T)p.re, s = (T)p.im;
+    const cx<T> a = X[e];
+    X[e] = cx<T>{a.re * c - a.im * s, a.re * s + a.im * c};
+  }
+}
+
+template <typename T>
+static hipError_t canon_t(cx<T>* U, int64_t n1, cx<T>* V, int64_t n2, int k, int batch, void* scratch,
+                          hipStream_t s) {
+  const int cr = canon_chunk_rows(n1);
+  const int nch = (int)((n1 + cr - 1) / cr);
+  unsigned char* w = static_cast<unsigned char*>(scratch);
+  double* pv = reinterpret_cast<double*>(w);
+  int* pi = reinterpret_cast<int*>(w + (size_t)batch * nch * k * 8);
+  cx<double>* ph = reinterpret_cast<cx<double>*>(w + (((size_t)batch * nch * k * 12 + 255) & ~(size_t)255));
+  hipLaunchKernelGGL(canon_colmax_kernel<T>, dim3(nch, batch), dim3(256), 0, s, U, n1, k, cr, pv, pi);
+  hipLaunchKernelGGL(canon_pick_kernel<T>, dim3((k + 255) / 256, batch), dim3(256), 0, s, U, n1, k, nch, pv, pi, ph);
+  const int64_t nu = n1 * k * batch, nv = n2 * k * batch;
+  hipLaunchKernelGGL(canon_scale_kernel<T>, dim3((unsigned)std::min<int64_t>((nu + 255) / 256, 8192)), dim3(256), 0,
+                     s, U, n1, k, batch, ph);
+  hipLaunchKernelGGL(canon_scale_kernel<T>, dim3((unsigned)std::min<int64_t>((nv + 255) / 256, 8192)), dim3(256), 0,
+                     s, V, n2, k, batch, ph);
   return hipGetLastError();
+}
+
+hipError_t canon_phase(void* U, int64_t n1, void* V, int64_t n2, int k, int batch, DType t, void* scratch,
+                       hipStream_t s) {
+  if (batch == 0 || k == 0) return hipSuccess;
+  if (t == DT_F64) return canon_t<double>((cx<double>*)U, n1, (cx<double>*)V, n2, k, batch, scratch, s);
+  return canon_t<float>((cx<float>*)U, n1, (cx<float>*)V, n2, k, batch, scratch, s);
 }
 
 }  // namespace tsvd

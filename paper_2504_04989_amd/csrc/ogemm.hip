@@ -447,6 +447,27 @@ hipError_t ogemm_nn(const float* X, int64_t lx, int64_t strideX, const double* B
   a.xvec = ((lx & 1) == 0 && (strideX & 1) == 0 && ((uintptr_t)X & 15) == 0) ? 1 : 0;
   const int TT = othin_tiles(N);
   fill_grid(a, TT);
+  // Slices past the last full round of workgroup slots would run as a nearly
+  // empty extra round: they go to a second launch with narrower thin chunks
+  // (more, shorter workgroups).
+  const int64_t slots = ogemm_slots();
+  const int64_t per_slice = (int64_t)a.nbig * a.nthin;
+  const int64_t full = (int64_t)a.total / slots * slots;
+  const int fsplit = (int)(full / per_slice);
+  if (TT > 4 && fsplit >= 1 && fsplit < batch && (a.total - full) * 2 < slots) {
+    OArgs b = a;
+    b.batch = fsplit;
+    fill_grid(b, TT);
+    hipError_t e = olaunch<false>(b, TT, s);
+    if (e != hipSuccess) return e;
+    OArgs r = a;
+    r.X = X + 2 * strideX * fsplit;
+    r.B = B + 2 * strideB * fsplit;  // complex doubles
+    r.C = C + 2 * strideC * fsplit;
+    r.batch = batch - fsplit;
+    fill_grid(r, 4);
+    return olaunch<false>(r, 4, s);
+  }
   return olaunch<false>(a, TT, s);
 }
 

@@ -49,6 +49,7 @@ struct Plan {
   int ks_ax, ks_ahy;            // K splits of the Krylov products A X and A^H Y
   size_t kpart_bytes;           // their partials (K splits or tail splits)
   // workspace offsets (bytes)
+  size_t o_canon;
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
       o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, o_kpack,
       total;
@@ -144,6 +145,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_wd = take(need_svd ? (size_t)F * m * k * 16 : 0);
   p->o_wds = take(need_svd ? (size_t)F * m * k * 16 : 0);
   p->o_heig = take(need_svd ? (size_t)F * heig_scratch_bytes((int)m, (int)k) : 0);
+  p->o_canon = take(need_svd ? canon_scratch_bytes(n1, (int)k, (int)F) : 0);
   p->o_uf = take(need_svd ? (size_t)F * n1 * k * cs : 0);
   p->o_vf = take(need_svd ? (size_t)F * n2 * k * cs : 0);
   p->o_scx = take(need_svd ? (size_t)F * k * cs : 0);
@@ -622,7 +624,7 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   }
   {
     Timed tm_(K_MISC, c.s);
-    HIPCHK(canon_phase(c.at(p.o_uf), p.n1, c.at(p.o_vf), p.n2, (int)p.k, (int)p.F, dt, c.s));
+    HIPCHK(canon_phase(c.at(p.o_uf), p.n1, c.at(p.o_vf), p.n2, (int)p.k, (int)p.F, dt, c.at(p.o_canon), c.s));
   }
   {
     Timed tm_(K_MISC, c.s);
