@@ -69,7 +69,30 @@ def class_work(cls: str, c: dict, prec: str):
     return None
 
 
-def roofline_for(kernels: dict, c: dict, prec: str):
+def profiled_traffic(cls: str, prec: str, workload: str):
+    """HBM bytes per launch of a kernel class from the rocprofv3 counter
+    summaries in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a device copy
+    of known size), or None when no summary covers it or when a source file it
+    was measured on has changed since."""
+    import glob
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    for fn in sorted(glob.glob(os.path.join(root, "profiles", "*.md"))):
+        for line in open(fn):
+            if not line.startswith("traffic-record:"):
+                continue
+            rec = json.loads(line.split(":", 1)[1])
+            if (rec["class"], rec["form"], rec["workload"]) != (cls, prec, workload):
+                continue
+            for src, digest in rec["sources_sha256"].items():
+                path = os.path.join(root, src)
+                if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != digest:
+                    return None
+            return {"bytes_per_launch": rec["bytes_per_launch"], "source": os.path.relpath(fn, root)}
+    return None
+
+
+def roofline_for(kernels: dict, c: dict, prec: str, workload: str):
     """Roofline of the dominant kernel class that has a stated algorithmic work."""
     for cls, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
         w = class_work(cls, c, prec)
@@ -77,8 +100,11 @@ def roofline_for(kernels: dict, c: dict, prec: str):
             continue
         amount, unit, bound, peak, note = w
         achieved = amount / (v["ms_per_step"] * 1e-3)
+        tr = profiled_traffic(cls, prec, workload)
         return {"kernel": cls, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": None, "work": note,
+                "frac": achieved / peak, "traffic": tr["bytes_per_launch"] if tr else None,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_source": tr["source"] if tr else None, "work": note,
                 "launches_per_step": v["launches_per_step"], "avg_launch_ms": v["avg_launch_ms"]}
     return None
 
@@ -189,7 +215,7 @@ def main():
                 f"{v['avg_launch_ms'] * 1e3:.1f} us/launch")
         kry = kernels.get("gemm_krylov")
         kw = class_work("gemm_krylov", c, prec)
-        legs[prec] = {"value": 1e3 / ms, "ms_per_step": ms, "roofline": roofline_for(kernels, c, prec),
+        legs[prec] = {"value": 1e3 / ms, "ms_per_step": ms, "roofline": roofline_for(kernels, c, prec, args.workload),
                       "krylov_mfma_util": (kw[0] / (kry["ms_per_step"] * 1e-3) / kw[3]) if kry else None,
                       "kernels": kernels, "numeric_info": info}
         outs[prec] = tuple(t.cpu().numpy().astype(np.float64) for t in out)
