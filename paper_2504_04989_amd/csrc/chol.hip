@@ -31,6 +31,16 @@ __device__ unsigned long long g_phase[16];
 #define PHASE_T0()
 #define PHASE(i)
 #endif
+#ifdef TSVD_PHASE_PROF
+extern "C" int tsvd_phase_read(unsigned long long* out, int reset) {
+  if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase)) != hipSuccess) return 1;
+  if (reset) {
+    unsigned long long z[16] = {};
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z)) != hipSuccess) return 1;
+  }
+  return 0;
+}
+#endif
 
 namespace tsvd {
 
@@ -305,20 +315,25 @@ __device__ int tile_cholesky(cx<double>* T, int lane, int nvalid) {
   return bad;
 }
 
+// Waves of the blocked kernel: the panel, trailing and inverse tile work is
+// spread over them (one tile per wave at a time); 8 waves keep two per SIMD.
+constexpr int CB_W = 8, CB_NT = 64 * CB_W, CB_SLOTS = (8 + CB_W - 1) / CB_W;
+
 template <int NT>
-__global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restrict__ Gpart, int nsum,
+__global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __restrict__ Gpart, int nsum,
                                                        int64_t part_stride, cx<double>* __restrict__ Rinv, int b,
                                                        double shift_coef, int* info, int mode) {
   extern __shared__ __align__(16) unsigned char smem[];
   cx<double>* L = reinterpret_cast<cx<double>*>(smem);
-  __shared__ double red[4];
+  __shared__ double red[CB_W];
   const int f = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const cx<double>* G = Gpart + (int64_t)f * b * b;
   constexpr int BP = NT * TSZ;
+  PHASE_T0();
 
   // ---- load: lower triangle (i >= j) of the padded matrix into tiles ----
-  for (int e = tid; e < BP * BP; e += 256) {
+  for (int e = tid; e < BP * BP; e += CB_NT) {
     const int i = e / BP, j = e % BP;
     if (j > i) continue;
     cx<double> v{(i == j && i >= b) ? 1.0 : 0.0, 0.0};
@@ -341,18 +356,19 @@ __global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restr
     L[tix(i >> 4, j >> 4) + (i & 15) * TRS + (j & 15)] = v;
   }
   __syncthreads();
+  PHASE(8);
 
   int bad = 0;
   if (mode == 1) {
     // invert the diagonal tiles (one wave each)
-    for (int K = wave; K < NT; K += 4) tile_inverse(L + tix(K, K), lane);
+    for (int K = wave; K < NT; K += CB_W) tile_inverse(L + tix(K, K), lane);
     __syncthreads();
   } else {
     double tr = 0;
-    for (int i = tid; i < b; i += 256) tr += L[tix(i >> 4, i >> 4) + (i & 15) * (TRS + 1)].re;
-    tr = block_sum<256>(tr, red);
+    for (int i = tid; i < b; i += CB_NT) tr += L[tix(i >> 4, i >> 4) + (i & 15) * (TRS + 1)].re;
+    tr = block_sum<CB_NT>(tr, red);
     const double shift = shift_coef * tr;
-    for (int i = tid; i < b; i += 256) L[tix(i >> 4, i >> 4) + (i & 15) * (TRS + 1)].re += shift;
+    for (int i = tid; i < b; i += CB_NT) L[tix(i >> 4, i >> 4) + (i & 15) * (TRS + 1)].re += shift;
     __syncthreads();
     for (int K = 0; K < NT; ++K) {
       cx<double>* D = L + tix(K, K);
@@ -362,7 +378,7 @@ __global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restr
       }
       __syncthreads();
       // panel: A_IK <- A_IK X_KK^H (one tile per wave at a time)
-      for (int I = K + 1 + wave; I < NT; I += 4) {
+      for (int I = K + 1 + wave; I < NT; I += CB_W) {
         cx<double>* P = L + tix(I, K);
         cx<double> out[4];
 #pragma unroll
@@ -384,7 +400,7 @@ __global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restr
       // trailing: A_IJ -= A_IK A_JK^H, K < J <= I
       const int m = NT - K - 1;
       const int npairs = m * (m + 1) / 2;
-      for (int pidx = wave; pidx < npairs; pidx += 4) {
+      for (int pidx = wave; pidx < npairs; pidx += CB_W) {
         int I = 0, rem = pidx;
         while (rem >= I + 1) {
           rem -= I + 1;
@@ -414,13 +430,14 @@ __global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restr
   // wave 0 carries `bad`; other waves never set it
   (void)bad;
 
+  PHASE(9);
   // ---- inverse: row by row, X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ ----
   for (int I = 1; I < NT; ++I) {
     // phase A: S_IJ into registers (tiles J < I spread over the waves)
-    cx<double> sreg[2][4];
+    cx<double> sreg[CB_SLOTS][4];
 #pragma unroll
-    for (int slot = 0; slot < 2; ++slot) {
-      const int J = wave + 4 * slot;
+    for (int slot = 0; slot < CB_SLOTS; ++slot) {
+      const int J = wave + CB_W * slot;
       if (J >= I) continue;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -437,8 +454,8 @@ __global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restr
     }
     __syncthreads();
 #pragma unroll
-    for (int slot = 0; slot < 2; ++slot) {
-      const int J = wave + 4 * slot;
+    for (int slot = 0; slot < CB_SLOTS; ++slot) {
+      const int J = wave + CB_W * slot;
       if (J >= I) continue;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -450,8 +467,8 @@ __global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restr
     // phase B: X_IJ = -X_II S_IJ (X_II lower triangular)
     const cx<double>* XI = L + tix(I, I);
 #pragma unroll
-    for (int slot = 0; slot < 2; ++slot) {
-      const int J = wave + 4 * slot;
+    for (int slot = 0; slot < CB_SLOTS; ++slot) {
+      const int J = wave + CB_W * slot;
       if (J >= I) continue;
       const cx<double>* S = L + tix(I, J);
 #pragma unroll
@@ -464,8 +481,8 @@ __global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restr
     }
     __syncthreads();
 #pragma unroll
-    for (int slot = 0; slot < 2; ++slot) {
-      const int J = wave + 4 * slot;
+    for (int slot = 0; slot < CB_SLOTS; ++slot) {
+      const int J = wave + CB_W * slot;
       if (J >= I) continue;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -476,9 +493,10 @@ __global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restr
     __syncthreads();
   }
 
+  PHASE(10);
   // ---- R^{-1} = X^H (upper triangular), b x b row-major ----
   cx<double>* out = Rinv + (int64_t)f * b * b;
-  for (int e = tid; e < b * b; e += 256) {
+  for (int e = tid; e < b * b; e += CB_NT) {
     const int r = e / b, c = e % b;
     cx<double> v{0.0, 0.0};
     if (c >= r) {
@@ -487,6 +505,7 @@ __global__ __launch_bounds__(256) void chol_blk_kernel(const cx<double>* __restr
     }
     out[e] = v;
   }
+  PHASE(11);
 }
 
 }  // namespace
@@ -514,7 +533,7 @@ hipError_t chol_inv_blocked(const double* Gpart, int nsum, int64_t part_stride, 
   switch (nt) {
 #define TSVD_CHOL_CASE(n)                                                                                        \
   case n:                                                                                                        \
-    hipLaunchKernelGGL(chol_blk_kernel<n>, dim3(batch), dim3(256), lds, s, G, nsum, part_stride, R, b, shift_coef, \
+    hipLaunchKernelGGL(chol_blk_kernel<n>, dim3(batch), dim3(CB_NT), lds, s, G, nsum, part_stride, R, b, shift_coef, \
                        info, mode);                                                                              \
     break;
     TSVD_CHOL_CASE(1)
