@@ -111,6 +111,8 @@ hipError_t scale_cols(const double* W, const double* lambda, void* Wout, int m, 
                       DType t, hipStream_t s);
 // Phase canonicalisation of (U_f, V_f) column pairs and sigma = sqrt(lambda).
 size_t canon_scratch_bytes(int64_t n1, int k, int batch);
+hipError_t lift_operands_f32(const double* W, const double* lambda, void* Wf, void* Wsf, int m, int k, int batch,
+                             hipStream_t s);
 hipError_t canon_phase(void* U, int64_t n1, void* V, int64_t n2, int k, int batch, DType t, void* scratch,
                        hipStream_t s);
 // sigma = sqrt(max(lambda, 0)) (FP64) and (sigma, 0) as complex in dtype t.

@@ -40,6 +40,31 @@ hipError_t scale_cols(const double* W, const double* lambda, void* Wout, int m, 
   return hipGetLastError();
 }
 
+// W_k rounded to complex FP32, and W_k diag(1 / sigma) likewise (sigma =
+// sqrt(lambda), 0 where lambda <= 0): the thin operands of the lift products
+// U_f = Q_f W_k and V_f = T_f W_k Sigma^{-1} on the FP32 path.
+__global__ void lift_operands_kernel(const cx<double>* __restrict__ W, const double* __restrict__ lambda,
+                                     cx<float>* __restrict__ Wf, cx<float>* __restrict__ Wsf, int m, int k,
+                                     int64_t total) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int c = (int)(t % k);
+  const int64_t f = t / ((int64_t)m * k);
+  const double l = lambda[f * k + c];
+  const double g = l > 0 ? 1.0 / sqrt(l) : 0.0;
+  const cx<double> w = W[t];
+  Wf[t] = cx<float>{(float)w.re, (float)w.im};
+  Wsf[t] = cx<float>{(float)(w.re * g), (float)(w.im * g)};
+}
+hipError_t lift_operands_f32(const double* W, const double* lambda, void* Wf, void* Wsf, int m, int k, int batch,
+                             hipStream_t s) {
+  const int64_t total = (int64_t)batch * m * k;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(lift_operands_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     (const cx<double>*)W, lambda, (cx<float>*)Wf, (cx<float>*)Wsf, m, k, total);
+  return hipGetLastError();
+}
+
 // Uout[f][i][c] = Uin[f][i][c] * sigma[f][c]
 template <typename T>
 __global__ void scale_by_kernel(const cx<T>* U, const double* sigma, cx<T>* out, int64_t n1, int k, int64_t total) {

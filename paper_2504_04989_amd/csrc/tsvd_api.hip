@@ -584,43 +584,80 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
     HIPCHK(heig_topk(part, nsum_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
                      c.info(), c.s, sc[0], upper));
   }
-  // U_f = Q_f W_k
-  GemmDesc d = gd();
-  d.A = c.at(p.o_q);
-  d.lda = p.m;
-  d.strideA = p.n1 * p.m;
-  d.ta = dt;
-  d.B = Wd;
-  d.ldb = p.k;
-  d.strideB = p.m * p.k;
-  d.tb = DT_F64;
-  d.C = c.at(p.o_uf);
-  d.ldc = p.k;
-  d.strideC = p.n1 * p.k;
-  d.tc = dt;
-  d.M = (int)p.n1;
-  d.N = (int)p.k;
-  d.K = (int)p.m;
-  d.batch = (int)p.F;
-  d.compute = dt;
-  {
-    Timed tm_(K_GEMM_LIFT, c.s);
-    HIPCHK(zgemm(d, c.s));
-  }
-  // V_f = T_f W_k diag(1/sigma)
-  {
-    Timed tm_(K_MISC, c.s);
-    HIPCHK(scale_cols(Wd, lam, c.at(p.o_wds), (int)p.m, (int)p.k, (int)p.F, 1, DT_F64, c.s));
-  }
-  d.A = T;
-  d.strideA = p.n2 * p.m;
-  d.B = c.at(p.o_wds);
-  d.C = c.at(p.o_vf);
-  d.strideC = p.n2 * p.k;
-  d.M = (int)p.n2;
-  {
-    Timed tm_(K_GEMM_LIFT, c.s);
-    HIPCHK(zgemm(d, c.s));
+  if (dt == DT_F32) {
+    // FP32 lift products on the Krylov-product kernel (FP32 MFMA, FP32
+    // accumulation, as the generic product computes them): thin operands W_k
+    // and W_k Sigma^{-1} rounded to complex FP32 in the o_wds buffer
+    unsigned char* wb = c.at<unsigned char>(p.o_wds);
+    void* Wf = wb;
+    void* Wsf = wb + (size_t)p.F * p.m * p.k * 8;
+    {
+      Timed tm_(K_MISC, c.s);
+      HIPCHK(lift_operands_f32(Wd, lam, Wf, Wsf, (int)p.m, (int)p.k, (int)p.F, c.s));
+    }
+    for (int side = 0; side < 2; ++side) {
+      const int64_t nb = side == 0 ? p.n1 : p.n2;
+      KGemmDesc k{};
+      k.A = side == 0 ? c.at(p.o_q) : T;
+      k.lda = p.m;
+      k.strideA = nb * p.m;
+      k.rows = (int)nb;
+      k.cols = (int)p.m;
+      k.herm = false;
+      k.X = side == 0 ? Wf : Wsf;
+      k.ldx = p.k;
+      k.strideX = p.m * p.k;
+      k.C = c.at(side == 0 ? p.o_uf : p.o_vf);
+      k.ldc = p.k;
+      k.strideC = nb * p.k;
+      k.N = (int)p.k;
+      k.batch = (int)p.F;
+      k.mode = KM_F32;
+      k.nsplit = 1;
+      k.part = c.at(p.o_kpart);
+      k.part_bytes = p.kpart_bytes;
+      Timed tm_(K_GEMM_LIFT, c.s);
+      HIPCHK(kgemm(k, c.s));
+    }
+  } else {
+    // U_f = Q_f W_k
+    GemmDesc d = gd();
+    d.A = c.at(p.o_q);
+    d.lda = p.m;
+    d.strideA = p.n1 * p.m;
+    d.ta = dt;
+    d.B = Wd;
+    d.ldb = p.k;
+    d.strideB = p.m * p.k;
+    d.tb = DT_F64;
+    d.C = c.at(p.o_uf);
+    d.ldc = p.k;
+    d.strideC = p.n1 * p.k;
+    d.tc = dt;
+    d.M = (int)p.n1;
+    d.N = (int)p.k;
+    d.K = (int)p.m;
+    d.batch = (int)p.F;
+    d.compute = dt;
+    {
+      Timed tm_(K_GEMM_LIFT, c.s);
+      HIPCHK(zgemm(d, c.s));
+    }
+    // V_f = T_f W_k diag(1/sigma)
+    {
+      Timed tm_(K_MISC, c.s);
+      HIPCHK(scale_cols(Wd, lam, c.at(p.o_wds), (int)p.m, (int)p.k, (int)p.F, 1, DT_F64, c.s));
+    }
+    d.A = T;
+    d.strideA = p.n2 * p.m;
+    d.B = c.at(p.o_wds);
+    d.C = c.at(p.o_vf);
+    d.strideC = p.n2 * p.k;
+    d.M = (int)p.n2;
+    {
+      Timed tm_(K_GEMM_LIFT, c.s);
+      HIPCHK(zgemm(d, c.s));
+    }
   }
   {
     Timed tm_(K_MISC, c.s);
