@@ -64,7 +64,8 @@ int kgemm_bf16_split(int M, int K, int N, int batch);
 //   batch * M * N entries on return.
 // ogemm_nn: C_f (M x N, FP32, row stride ldc) = alpha X_f B_f + beta C_f with
 //   X_f (M x K, row stride lx, FP32) and B_f (K x N, FP64, row stride ldb) the
-//   sum of nsum matrices spaced bsum_stride complex elements.
+//   sum of nsum matrices spaced bsum_stride complex elements; b_triu: B_f is
+//   upper triangular with its zeros stored (their products are skipped).
 size_t ogemm_tn_part_bytes(int M, int K, int N, int batch);
 // upper = true (square products): only the entries on and above the
 // diagonal are guaranteed; whole tiles below it are skipped.
@@ -72,7 +73,8 @@ hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y,
                     double* part, int M, int N, int K, int batch, hipStream_t s, bool upper = false);
 hipError_t ogemm_nn(const float* X, int64_t lx, int64_t strideX, const double* B, int64_t ldb, int64_t strideB,
                     int nsum, int64_t bsum_stride, float* C, int64_t ldc, int64_t strideC, int M, int N, int K,
-                    int batch, double alpha, double beta, hipStream_t s);
+                    int batch, double alpha, double beta, hipStream_t s,
+                    bool b_triu = false);
 
 // Mode-3 real-to-half-spectrum DFT: X (ntubes x n3, tube-contiguous) ->
 // Xb (F x ntubes complex, F = n3/2 + 1), slice-major.

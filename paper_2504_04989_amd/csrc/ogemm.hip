@@ -45,6 +45,7 @@ struct OArgs {
   int nbig, nthin, total, per;
   int xvec;
   int upper;  // TN: skip tiles strictly below the diagonal of a square product
+  int triu;   // NN: B is upper triangular (zeros below the diagonal, stored)
 };
 
 template <bool TN, int TT, bool XVEC>
@@ -188,11 +189,14 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
 #pragma unroll
   for (int i = 0; i < TT; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  auto compute = [&](const double* buf, const float (&v)[4]) {
+  // NN with upper-triangular B: in the K step starting at complex row k0,
+  // thin tiles i < (k0 - n0) / 8 see only zeros of B and are skipped (exact)
+  auto tile0 = [&](int k0) { return (!TN && a.triu && k0 > n0) ? (k0 - n0) / 8 : 0; };
+  auto compute = [&](const double* buf, const float (&v)[4], int istart) {
     const double bv[4] = {(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
 #pragma unroll
     for (int i = 0; i < TT; ++i) {
-      if (i < tt) {
+      if (i < tt && i >= istart) {
         const double* rowp = buf + (16 * i + r16) * OSTRIDE + 4 * q4;
         const double2 w0 = *reinterpret_cast<const double2*>(rowp);
         const double2 w1 = *reinterpret_cast<const double2*>(rowp + 2);
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
     const int sn = s + 1 < nfull ? s + 1 : s;
     load_thin_full(kb + sn * OKSTEP, tx);
     load_big_full(kb + sn * OKSTEP, nxt);
-    compute(olds + (s & 1) * BUF, cur);
+    compute(olds + (s & 1) * BUF, cur, tile0(kb + s * OKSTEP));
     if (s + 1 < nfull) store_thin(olds + ((s + 1) & 1) * BUF, tx);
     __syncthreads();
 #pragma unroll
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
     store_thin(olds + (nfull & 1) * BUF, tx);
     load_big(k0, cur);
     __syncthreads();
-    compute(olds + (nfull & 1) * BUF, cur);
+    compute(olds + (nfull & 1) * BUF, cur, tile0(k0));
   }
 
   // Lanes q4 and q4 ^ 1 hold the real and the imaginary parts of the same
@@ -421,7 +425,7 @@ hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y,
 
 hipError_t ogemm_nn(const float* X, int64_t lx, int64_t strideX, const double* B, int64_t ldb, int64_t strideB,
                     int nsum, int64_t bsum_stride, float* C, int64_t ldc, int64_t strideC, int M, int N, int K,
-                    int batch, double alpha, double beta, hipStream_t s) {
+                    int batch, double alpha, double beta, hipStream_t s, bool b_triu) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   if (nsum != 1) return hipErrorInvalidValue;  // callers pass a single (summed) B
   OArgs a{};
@@ -445,6 +449,7 @@ hipError_t ogemm_nn(const float* X, int64_t lx, int64_t strideX, const double* B
   a.nsplit = 1;
   a.kchunk = (K + OKSTEP - 1) / OKSTEP * OKSTEP;
   a.xvec = ((lx & 1) == 0 && (strideX & 1) == 0 && ((uintptr_t)X & 15) == 0) ? 1 : 0;
+  a.triu = b_triu ? 1 : 0;
   const int TT = othin_tiles(N);
   fill_grid(a, TT);
   // Slices past the last full round of workgroup slots would run as a nearly

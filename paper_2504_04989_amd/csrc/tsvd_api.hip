@@ -303,7 +303,7 @@ int apply_rinv(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ld
     Timed tm_(K_GEMM_ORTH, c.s);
     HIPCHK(ogemm_nn(static_cast<const float*>(src), lds, p.n1 * lds, c.at<double>(p.o_rinv), p.b, p.b * p.b, 1, 0,
                     static_cast<float*>(dst), ldd, p.n1 * ldd, (int)p.n1, (int)p.b, (int)p.b, (int)p.F, 1.0, 0.0,
-                    c.s));
+                    c.s, true));
     return TSVD_OK;
   }
   GemmDesc d = gd();
