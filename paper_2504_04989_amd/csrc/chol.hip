@@ -341,10 +341,11 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
       v = cx<double>{0.0, 0.0};
       for (int s = 0; s < nsum; ++s) {
         const cx<double>* Gs = G + s * part_stride;
-        if (mode == 1) {
-          const cx<double> r = Gs[(int64_t)j * b + i];  // L = R^H
+        if (mode != 0) {
+          // mode 1: L = R^H; mode 2: the Hermitian extension of the upper triangle
+          const cx<double> r = Gs[(int64_t)j * b + i];
           v.re += r.re;
-          v.im -= r.im;
+          v.im -= (mode == 2 && i == j) ? 0.0 : r.im;
         } else {
           const cx<double> g = Gs[(int64_t)i * b + j];
           const cx<double> h = Gs[(int64_t)j * b + i];

@@ -90,7 +90,9 @@ hipError_t fft_c2r(const void* Xb, int64_t slice_stride, void* X, int64_t ntubes
 // complex doubles per slice, used when !chol_uses_lds(b).
 inline bool chol_uses_lds(int64_t b) { return b * (b + 1) / 2 * 16 <= 120 * 1024; }
 // mode 1: the partials sum to an upper triangular R instead; the kernel only
-// inverts it (Rinv = R^{-1}).
+// inverts it (Rinv = R^{-1}).  mode 2 (b <= 128): only the upper triangle of
+// the partials is valid; G is its Hermitian extension.
+bool chol_blocked_ok(int b);  // the blocked factorisation (and mode 2) applies
 hipError_t chol_inv_ex(const double* Gpart, int nsum, int64_t part_stride, double* Rinv, void* gscratch, int b,
                        int batch, double shift_coef, int* info, hipStream_t s, int mode = 0);
 

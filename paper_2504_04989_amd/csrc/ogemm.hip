@@ -191,7 +191,17 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
 
   // NN with upper-triangular B: in the K step starting at complex row k0,
   // thin tiles i < (k0 - n0) / 8 see only zeros of B and are skipped (exact)
-  auto tile0 = [&](int k0) { return (!TN && a.triu && k0 > n0) ? (k0 - n0) / 8 : 0; };
+  // TN with `upper`: thin tiles whose columns all lie below the wave's first
+  // output row (n0 + 8 i + 8 <= first column of this wave) give only entries
+  // below the diagonal, which the consumer does not read
+  auto tile0 = [&](int k0) {
+    if (TN) {
+      if (!a.upper) return 0;
+      const int cmin = bt * 64 + wave * 16;
+      return cmin > n0 ? (cmin - n0) / 8 : 0;
+    }
+    return (a.triu && k0 > n0) ? (k0 - n0) / 8 : 0;
+  };
   auto compute = [&](const double* buf, const float (&v)[4], int istart) {
     const double bv[4] = {(double)v[0], (double)v[1], (double)v[2], (double)v[3]};
 #pragma unroll

@@ -336,15 +336,17 @@ int cholqr_pass(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t l
   const Plan& p = c.p;
   double* part = c.at<double>(p.o_part);
   int nsum = 1;
+  // the Gram is Hermitian: on the FP32 path (b <= 128) only its upper triangle is formed
+  const bool upper = p.dt == DT_F32 && chol_blocked_ok((int)p.b);
   int r = inner_products(c, src, lds, (int)p.b, src, lds, (int)p.b, p.n1, p.n1 * lds, p.n1 * lds, p.nsplit_blk,
-                         p.kchunk_blk, part, &nsum);
+                         p.kchunk_blk, part, &nsum, K_GEMM_ORTH, upper);
   if (r) return r;
   const double u = 1.1102230246251565e-16;
   const double shift = shifted ? 11.0 * ((double)p.n1 * p.b + (double)p.b * (p.b + 1)) * u : 0.0;
   {
     Timed tm_(K_CHOL, c.s);
     HIPCHK(chol_inv_ex(part, nsum, p.F * p.b * p.b, c.at<double>(p.o_rinv), c.at(p.o_chol), (int)p.b, (int)p.F,
-                       shift, c.info(), c.s));
+                       shift, c.info(), c.s, upper ? 2 : 0));
   }
   return apply_rinv(c, src, lds, dst, ldd);
 }
