@@ -29,6 +29,13 @@ Pins (tests/test_oracle_*.py, all ``-m "not gpu"``):
                            literal == stabilised Krylov form
   proj / proj_backward     central finite differences, torch CPU autograd,
                            Euler homogeneity
+  power_tsvd (Alg. 1)      n3 = 1 is the matrix randomized subspace iteration
+                           (numpy QR / SVD); b = n1 gives the exact truncated
+                           T-SVD; exact recovery of a tubal-rank-r tensor;
+                           q = 0 equals Alg. 2 at q = 0; the last iterate
+                           computed with spatial T-products lies in range(Q_f);
+                           literal == stabilised; Alg. 2's error <= Alg. 1's
+                           for the same Omega and q (range(Y_q) in range(K))
 
 Readings (where the paper is silent / ambiguous):
   R1  Omega has n2 rows (Alg. 2 draws randn(n1, ...) but X*Omega needs n2 rows,
@@ -50,6 +57,12 @@ Readings (where the paper is silent / ambiguous):
   R9  Singular vectors carry an arbitrary phase; for comparison each column of
       U_f and V_f is multiplied by the conjugate phase of the largest-modulus
       entry of the U_f column (first such entry on ties).
+  R10 Alg. 1 orthonormalises its last power iterate Y_q (its T-QR line names
+      the Krylov tensor K, which Alg. 1 never forms); the parity reference
+      orthonormalises every iterate before the next multiplication, which
+      spans the same range as the literal powers in exact arithmetic; the
+      literal form is kept as a cross-check (power="lit").  Alg. 1 shares
+      Alg. 2's projection, small SVD, lift and rank-k truncation.
 """
 from __future__ import annotations
 
@@ -372,26 +385,18 @@ def _check_params(n1, n2, n3, k, b, q):
         raise ValueError("need m = b (q + 1) <= min(n1, n2)")
 
 
-def rbk_slices(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
-               freqs=None, krylov: str = "stab"):
-    """Alg. 2 in the Fourier domain for the requested slices (default: the
-    n3//2 + 1 slices of the half spectrum).
-
-    Per slice f: Krylov basis Q_f (Alg. 2 Krylov loop + T-QR), C_f = Q_f^H A_f
-    (Alg. 2, projection), SVD of C_f (Alg. 2, T-SVD of C), U_f = Q_f W(:, :k),
-    S_f = s[:k], V_f = Z(:, :k) (Alg. 2, lift and truncation), phases
-    canonicalised (reading R9).  Returns a dict of per-slice arrays indexed like
-    ``freqs``: Uf (n1,k,nf), Sf (k,nf), Vf (n2,k,nf), Q (n1,m,nf), C (m,n2,nf),
-    s_all (m,nf) (all singular values of C_f)."""
+def _truncated_slices(A, Omega, k, b, m, freqs, basis):
+    """Shared tail of Alg. 1 and Alg. 2 in the Fourier domain: per slice f,
+    Q_f = basis(A_f, Om_f) (n1 x m, orthonormal), C_f = Q_f^H A_f (projection),
+    SVD of C_f, U_f = Q_f W(:, :k), S_f = s[:k], V_f = Z(:, :k) (lift and
+    truncation), phases canonicalised (reading R9)."""
     n1, n2, n3 = A.shape
-    _check_params(n1, n2, n3, k, b, q)
     if Omega.shape != (n2, b, n3):
         raise ValueError("Omega must be n2 x b x n3")
     if freqs is None:
         freqs = list(range(n_half(n3)))
     Ab = dft_mode3(A, freqs)
     Ob = dft_mode3(Omega, freqs)
-    m = b * (q + 1)
     nf = len(freqs)
     out = {
         "freqs": list(freqs),
@@ -401,7 +406,7 @@ def rbk_slices(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
     }
     for idx in range(nf):
         Af, Of = Ab[:, :, idx], Ob[:, :, idx]
-        Q, _ = krylov_basis(Af, Of, q, krylov)
+        Q = basis(Af, Of)
         C = Q.conj().T @ Af
         W, s, Z, _ = jacobi_svd(C)
         Uf = Q @ W[:, :k]
@@ -416,18 +421,90 @@ def rbk_slices(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
     return out
 
 
-def rbk_tsvd(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
-             krylov: str = "stab"):
-    """Alg. 2: U (n1 x k x n3), S (k x n3: the diagonal tubes of the f-diagonal
-    S_R), V (n2 x k x n3) with A ~ U * S * V^T, plus the half-spectrum pieces.
-    The mirror and inverse transform follow Alg. TP."""
-    n1, n2, n3 = A.shape
-    sl = rbk_slices(A, Omega, k, b, q, None, krylov)
+def _spatial_factors(sl: dict, n3: int) -> dict:
+    """Mirror and inverse-transform the half-spectrum factors (Alg. TP)."""
     U = real_part_checked(idft_mode3(mirror(sl["Uf"], n3)))
     V = real_part_checked(idft_mode3(mirror(sl["Vf"], n3)))
     S = real_part_checked(idft_mode3(mirror(sl["Sf"].astype(np.complex128), n3)))
     sl.update(U=U, S=S, V=V)
     return sl
+
+
+def rbk_slices(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
+               freqs=None, krylov: str = "stab"):
+    """Alg. 2 in the Fourier domain for the requested slices (default: the
+    n3//2 + 1 slices of the half spectrum).
+
+    Per slice f: Krylov basis Q_f (Alg. 2 Krylov loop + T-QR), then the shared
+    projection / small SVD / lift / truncation.  Returns a dict of per-slice
+    arrays indexed like ``freqs``: Uf (n1,k,nf), Sf (k,nf), Vf (n2,k,nf),
+    Q (n1,m,nf), C (m,n2,nf), s_all (m,nf) (all singular values of C_f)."""
+    n1, n2, n3 = A.shape
+    _check_params(n1, n2, n3, k, b, q)
+    return _truncated_slices(A, Omega, k, b, b * (q + 1), freqs,
+                             lambda Af, Of: krylov_basis(Af, Of, q, krylov)[0])
+
+
+def rbk_tsvd(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
+             krylov: str = "stab"):
+    """Alg. 2: U (n1 x k x n3), S (k x n3: the diagonal tubes of the f-diagonal
+    S_R), V (n2 x k x n3) with A ~ U * S * V^T, plus the half-spectrum pieces.
+    The mirror and inverse transform follow Alg. TP."""
+    sl = rbk_slices(A, Omega, k, b, q, None, krylov)
+    return _spatial_factors(sl, A.shape[2])
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1: classical randomized subspace method with power iteration
+# ---------------------------------------------------------------------------
+
+def power_basis(Af: np.ndarray, Of: np.ndarray, q: int, power: str = "stab"):
+    """Orthonormal basis Q_f (n1 x b) of range((A A^H)^q A Om) for one slice:
+    only the last power iterate Y_q is used (Alg. 1).
+
+    power="lit": Y_0 = A Om, Y_i = A (A^H Y_{i-1}) exactly as written, then one
+    Householder QR of Y_q.
+    power="stab": the same range with every iterate orthonormalised before the
+    next multiplication, Q_0 = qr(A Om), Q_i = qr(A (A^H Q_{i-1})) (reading R10)."""
+    if power == "lit":
+        Y = Af @ Of
+        for _ in range(q):
+            Y = Af @ (Af.conj().T @ Y)
+        Q, _ = householder_qr(Y)
+        return Q
+    if power != "stab":
+        raise ValueError(power)
+    Qp, _ = householder_qr(Af @ Of)
+    for _ in range(q):
+        Qp, _ = householder_qr(Af @ (Af.conj().T @ Qp))
+    return Qp
+
+
+def power_slices(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
+                 freqs=None, power: str = "stab"):
+    """Alg. 1 in the Fourier domain: basis of the last power iterate (m = b
+    columns per slice), then the projection / small SVD / lift / truncation
+    shared with Alg. 2.  Same dict layout as rbk_slices with m = b."""
+    n1, n2, n3 = A.shape
+    _check_params(n1, n2, n3, k, b, 0)
+    if q < 0:
+        raise ValueError("need q >= 0")
+    return _truncated_slices(A, Omega, k, b, b, freqs,
+                             lambda Af, Of: power_basis(Af, Of, q, power))
+
+
+def power_tsvd(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int,
+               power: str = "stab"):
+    """Alg. 1: U (n1 x k x n3), S (k x n3), V (n2 x k x n3) with
+    A ~ U * S * V^T, plus the half-spectrum pieces."""
+    sl = power_slices(A, Omega, k, b, q, None, power)
+    return _spatial_factors(sl, A.shape[2])
+
+
+def power_approx(A, Omega, k, b, q, power: str = "stab") -> np.ndarray:
+    """Rank-k approximation U * S * V^T returned by Alg. 1."""
+    n1, n2, n3 = A.shape
+    return approx_from_slices(power_slices(A, Omega, k, b, q, None, power), n1, n2, n3)
 
 
 def s_tensor(S: np.ndarray) -> np.ndarray:

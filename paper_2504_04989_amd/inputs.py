@@ -15,6 +15,11 @@ Workload recipes (real tensors, C-contiguous (n1, n2, n3), tubes contiguous):
                random spectral curves, min-max scaled to [0, 1], plus noise.
   completion   T = U * V^T of tubal rank r (N(0, 1) factors) and a Bernoulli
                keep-mask; the starting point X0 = M (.) T.
+  spectrum     A = U * S * V^T with U, V orthogonal tensors (every Fourier slice
+               unitary: numpy's QR of a complex Gaussian matrix, real at the DC
+               and Nyquist slices) and S f-diagonal with tubes sigma_m e_1, so
+               every Fourier slice of A has exactly the singular values
+               sigma_1 >= sigma_2 >= ... (Sec. 5, Example 1: m^-5, m^-6, 0.5^m).
 
 Draw order inside one seed: factors U, then S tubes, then V, then noise, then
 the mask.  The Gaussian test tensor Omega (n2 x b x n3) comes from a separate
@@ -40,6 +45,18 @@ CONFIGS = {
     "c5_fp32_4096x4096x64": dict(kind="lowrank", n1=4096, n2=4096, n3=64, r=400,
                                  decay=("pow", -1.5), noise=1e-5, k=100, b=110, q=3,
                                  seed=4, prec="f32"),
+}
+
+# Sec. 5, Example 1: n x n x n tensors with prescribed slice spectra, R = 45,
+# P = 5, q = 2 (the paper does not state n; 256 here).  Compared between the
+# power-iteration method (Alg. 1) and the block Krylov method (Alg. 2).
+EX1_CONFIGS = {
+    "ex1_pow5_256": dict(kind="spectrum", n1=256, n2=256, n3=256, decay=("pow", -5.0),
+                         k=45, b=50, q=2, seed=11, prec="f64"),
+    "ex1_pow6_256": dict(kind="spectrum", n1=256, n2=256, n3=256, decay=("pow", -6.0),
+                         k=45, b=50, q=2, seed=12, prec="f64"),
+    "ex1_geom05_256": dict(kind="spectrum", n1=256, n2=256, n3=256, decay=("geom", 0.5),
+                           k=45, b=50, q=2, seed=13, prec="f64"),
 }
 
 
@@ -119,6 +136,33 @@ def hyperspectral_tensor(n1, n2, n3, r, noise, seed):
     return np.ascontiguousarray(A)
 
 
+def _orthogonal_tensor(n: int, r: int, n3: int, rng) -> np.ndarray:
+    """Real n x r x n3 tensor whose half-spectrum Fourier slices have
+    orthonormal columns (numpy's QR of complex Gaussian matrices; real
+    Gaussian at the DC slice and, for even n3, the Nyquist slice)."""
+    F = n3 // 2 + 1
+    Ub = np.empty((n, r, F), dtype=np.complex128)
+    for f in range(F):
+        G = rng.standard_normal((n, r))
+        if not (f == 0 or (n3 % 2 == 0 and f == n3 // 2)):
+            G = G + 1j * rng.standard_normal((n, r))
+        Ub[:, :, f], _ = np.linalg.qr(G)
+    return np.fft.irfft(Ub, n=n3, axis=2)
+
+
+def spectrum_tensor(n1, n2, n3, decay, seed):
+    """Recipe ``spectrum``: A = U * S * V^T, U and V orthogonal tensors, S
+    f-diagonal with tubes sigma_m e_1 (m = 1..min(n1, n2)), so that every
+    Fourier slice of A has the singular values sigma_m."""
+    rng, _ = _streams(seed)
+    r = min(n1, n2)
+    U = _orthogonal_tensor(n1, r, n3, rng)
+    V = _orthogonal_tensor(n2, r, n3, rng)
+    s = np.zeros((r, n3))
+    s[:, 0] = _decay(decay, r)
+    return np.ascontiguousarray(_tprod_usvt(U, s, V))
+
+
 def completion_problem(n1, n2, n3, r, keep, seed):
     """Recipe ``completion``: T = U * V^T (tubal rank r, N(0,1) factors),
     mask M ~ Bernoulli(keep) per entry, X0 = M (.) T.  Returns (T, M, X0)."""
@@ -139,12 +183,14 @@ def omega(n2, b, n3, seed):
 
 def make_config(name: str):
     """(A, Omega, params) for a named workload; A and Omega are float64."""
-    c = dict(CONFIGS[name])
+    c = dict(CONFIGS[name] if name in CONFIGS else EX1_CONFIGS[name])
     kind = c["kind"]
     if kind == "lowrank":
         A = lowrank_tensor(c["n1"], c["n2"], c["n3"], c["r"], c["decay"], c["noise"], c["seed"])
     elif kind == "hyperspectral":
         A = hyperspectral_tensor(c["n1"], c["n2"], c["n3"], c["r"], c["noise"], c["seed"])
+    elif kind == "spectrum":
+        A = spectrum_tensor(c["n1"], c["n2"], c["n3"], c["decay"], c["seed"])
     elif kind == "completion":
         T, M, A = completion_problem(c["n1"], c["n2"], c["n3"], c["r"], c["keep"], c["seed"])
         c["T"], c["M"] = T, M

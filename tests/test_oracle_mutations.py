@@ -67,6 +67,21 @@ def pin_krylov_spatial(O):
         assert np.linalg.norm(res) < 1e-10 * np.linalg.norm(Kb[:, :, f])
 
 
+def pin_power_spatial(O):
+    A = inputs.random_tensor((9, 8, 5), 25)
+    b, q = 3, 2
+    Om = inputs.omega(8, b, 5, 25)
+    Y = O.tprod_bcirc(A, Om)
+    for _ in range(q):
+        Y = O.tprod_bcirc(A, O.tprod_bcirc(O.ttranspose(A), Y))
+    Yb = np.fft.fft(Y, axis=2)
+    sl = O.power_slices(A, Om, 1, b, q)
+    for f in range(3):
+        Q = sl["Q"][:, :, f]
+        res = Yb[:, :, f] - Q @ (Q.conj().T @ Yb[:, :, f])
+        assert np.linalg.norm(res) < 1e-10 * np.linalg.norm(Yb[:, :, f])
+
+
 def pin_exact_tsvd(O):
     # m = n1: Alg. 2 must equal the truncated T-SVD computed with numpy's SVD.
     n1, n2, n3, k = 20, 24, 4, 5
@@ -108,6 +123,12 @@ MUTATIONS = [
     ("jacobi phase", "eph = np.conj(gamma / ag)", "eph = gamma / ag", pin_svd),
     ("krylov transpose without conj", "W = Af @ (Af.conj().T @ Qs[-1])", "W = Af @ (Af.T @ Qs[-1])", pin_krylov_spatial),
     ("reorthogonalisation sign", "W = W - Qp @ (Qp.conj().T @ W)", "W = W + Qp @ (Qp.conj().T @ W)", pin_krylov_spatial),
+    ("power iterate transpose without conj", "Qp, _ = householder_qr(Af @ (Af.conj().T @ Qp))",
+     "Qp, _ = householder_qr(Af @ (Af.T @ Qp))", pin_power_spatial),
+    ("power iteration one short", "    for _ in range(q):\n        Qp, _ =", "    for _ in range(q - 1):\n        Qp, _ =",
+     pin_power_spatial),
+    ("power basis without A^H", "Qp, _ = householder_qr(Af @ (Af.conj().T @ Qp))", "Qp, _ = householder_qr(Af @ Qp[:Af.shape[1]])",
+     pin_power_spatial),
     ("projection without conj", "C = Q.conj().T @ Af", "C = Q.T @ Af", pin_exact_tsvd),
     ("truncation off by one", "Vf = Z[:, :k]", "Vf = Z[:, 1:k + 1]", pin_exact_tsvd),
     ("lift with conj", "Uf = Q @ W[:, :k]", "Uf = Q @ W[:, :k].conj()", pin_exact_tsvd),
