@@ -354,7 +354,12 @@ def krylov_basis(Af: np.ndarray, Of: np.ndarray, q: int, krylov: str = "stab"):
     krylov="lit": the blocks exactly as written (K_i = A (A^H K_{i-1})), then one
     Householder QR of K (Alg. 2, Krylov loop and T-QR).
     krylov="stab": Q_0 = qr(A Om); for i >= 1, W = A (A^H Q_{i-1}),
-    W -= Q_<i (Q_<i^H W) twice, Q_i = qr(W); Q = [Q_0 .. Q_q] (reading R6).
+    Y = qr(W - Q_<i Q_<i^H W), Q_i = qr(Y - Q_<i Q_<i^H Y); Q = [Q_0 .. Q_q]
+    (reading R6).  The second projection acts on the normalised block: when
+    the new block lies numerically inside the earlier span (a spectrum that
+    falls below the rounding level within the first blocks), two projections
+    before normalising leave Q far from orthonormal, which the T-QR of the
+    Krylov tensor excludes.
     Returns (Q, blocks) where blocks are the R factors / literal blocks."""
     if krylov == "lit":
         blocks = [Af @ Of]
@@ -369,9 +374,10 @@ def krylov_basis(Af: np.ndarray, Of: np.ndarray, q: int, krylov: str = "stab"):
     for _ in range(q):
         W = Af @ (Af.conj().T @ Qs[-1])
         Qp = np.concatenate(Qs, axis=1)
-        for _rep in range(2):
-            W = W - Qp @ (Qp.conj().T @ W)
-        Qi, _ = householder_qr(W)
+        Y = W - Qp @ (Qp.conj().T @ W)
+        Y, _ = householder_qr(Y)
+        Y = Y - Qp @ (Qp.conj().T @ Y)
+        Qi, _ = householder_qr(Y)
         Qs.append(Qi)
     return np.concatenate(Qs, axis=1), None
 

@@ -122,7 +122,10 @@ MUTATIONS = [
     ("jacobi rotation sign", "M[:, p] = c * mp - s * eph * mq", "M[:, p] = c * mp + s * eph * mq", pin_svd),
     ("jacobi phase", "eph = np.conj(gamma / ag)", "eph = gamma / ag", pin_svd),
     ("krylov transpose without conj", "W = Af @ (Af.conj().T @ Qs[-1])", "W = Af @ (Af.T @ Qs[-1])", pin_krylov_spatial),
-    ("reorthogonalisation sign", "W = W - Qp @ (Qp.conj().T @ W)", "W = W + Qp @ (Qp.conj().T @ W)", pin_krylov_spatial),
+    ("reorthogonalisation sign",
+     "Y = W - Qp @ (Qp.conj().T @ W)\n        Y, _ = householder_qr(Y)\n        Y = Y - Qp @ (Qp.conj().T @ Y)",
+     "Y = W + Qp @ (Qp.conj().T @ W)\n        Y, _ = householder_qr(Y)\n        Y = Y + Qp @ (Qp.conj().T @ Y)",
+     pin_krylov_spatial),
     ("power iterate transpose without conj", "Qp, _ = householder_qr(Af @ (Af.conj().T @ Qp))",
      "Qp, _ = householder_qr(Af @ (Af.T @ Qp))", pin_power_spatial),
     ("power iteration one short", "    for _ in range(q):\n        Qp, _ =", "    for _ in range(q - 1):\n        Qp, _ =",
