@@ -59,10 +59,11 @@ Readings (where the paper is silent / ambiguous):
       entry of the U_f column (first such entry on ties).
   R10 Alg. 1 orthonormalises its last power iterate Y_q (its T-QR line names
       the Krylov tensor K, which Alg. 1 never forms); the parity reference
-      orthonormalises every iterate before the next multiplication, which
-      spans the same range as the literal powers in exact arithmetic; the
-      literal form is kept as a cross-check (power="lit").  Alg. 1 shares
-      Alg. 2's projection, small SVD, lift and rank-k truncation.
+      orthonormalises after every product with A^H and with A (randomized
+      subspace iteration), which spans the same range as the literal powers
+      in exact arithmetic and never forms the squared spectrum; the literal
+      form is kept as a cross-check (power="lit").  Alg. 1 shares Alg. 2's
+      projection, small SVD, lift and rank-k truncation.
 """
 from __future__ import annotations
 
@@ -470,8 +471,10 @@ def power_basis(Af: np.ndarray, Of: np.ndarray, q: int, power: str = "stab"):
 
     power="lit": Y_0 = A Om, Y_i = A (A^H Y_{i-1}) exactly as written, then one
     Householder QR of Y_q.
-    power="stab": the same range with every iterate orthonormalised before the
-    next multiplication, Q_0 = qr(A Om), Q_i = qr(A (A^H Q_{i-1})) (reading R10)."""
+    power="stab": the same range with an orthonormalisation after every
+    product (randomized subspace iteration, Halko, Martinsson and Tropp 2011,
+    Alg. 4.4): Q_0 = qr(A Om), Qt_i = qr(A^H Q_{i-1}), Q_i = qr(A Qt_i)
+    (reading R10)."""
     if power == "lit":
         Y = Af @ Of
         for _ in range(q):
@@ -482,7 +485,8 @@ def power_basis(Af: np.ndarray, Of: np.ndarray, q: int, power: str = "stab"):
         raise ValueError(power)
     Qp, _ = householder_qr(Af @ Of)
     for _ in range(q):
-        Qp, _ = householder_qr(Af @ (Af.conj().T @ Qp))
+        Qt, _ = householder_qr(Af.conj().T @ Qp)
+        Qp, _ = householder_qr(Af @ Qt)
     return Qp
 
 

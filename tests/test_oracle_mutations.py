@@ -126,11 +126,11 @@ MUTATIONS = [
      "Y = W - Qp @ (Qp.conj().T @ W)\n        Y, _ = householder_qr(Y)\n        Y = Y - Qp @ (Qp.conj().T @ Y)",
      "Y = W + Qp @ (Qp.conj().T @ W)\n        Y, _ = householder_qr(Y)\n        Y = Y + Qp @ (Qp.conj().T @ Y)",
      pin_krylov_spatial),
-    ("power iterate transpose without conj", "Qp, _ = householder_qr(Af @ (Af.conj().T @ Qp))",
-     "Qp, _ = householder_qr(Af @ (Af.T @ Qp))", pin_power_spatial),
-    ("power iteration one short", "    for _ in range(q):\n        Qp, _ =", "    for _ in range(q - 1):\n        Qp, _ =",
+    ("power iterate transpose without conj", "Qt, _ = householder_qr(Af.conj().T @ Qp)",
+     "Qt, _ = householder_qr(Af.T @ Qp)", pin_power_spatial),
+    ("power iteration one short", "    for _ in range(q):\n        Qt, _ =", "    for _ in range(q - 1):\n        Qt, _ =",
      pin_power_spatial),
-    ("power basis without A^H", "Qp, _ = householder_qr(Af @ (Af.conj().T @ Qp))", "Qp, _ = householder_qr(Af @ Qp[:Af.shape[1]])",
+    ("power basis without A^H", "Qt, _ = householder_qr(Af.conj().T @ Qp)", "Qt, _ = householder_qr(Qp[:Af.shape[1]])",
      pin_power_spatial),
     ("projection without conj", "C = Q.conj().T @ Af", "C = Q.T @ Af", pin_exact_tsvd),
     ("truncation off by one", "Vf = Z[:, :k]", "Vf = Z[:, 1:k + 1]", pin_exact_tsvd),
