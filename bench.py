@@ -137,6 +137,44 @@ def slice_relerr(U, S, V, sl, freqs):
     return float(np.sqrt(num / den)), per
 
 
+def compare_alg1_alg2(api, inputs, steps: int, warmup: int):
+    """Sec. 5, Example 1: the power-iteration method (Alg. 1) and the block
+    Krylov method (Alg. 2) on n x n x n tensors with prescribed slice spectra,
+    R = 45, P = 5, q = 2, FP64.  Per spectrum: ms per call of each method (K
+    timed calls after W warmups, input resident in HBM) and the relative
+    Frobenius error of its rank-R approximation, beside the optimum."""
+    import torch
+    res = {}
+    for name in inputs.EX1_CONFIGS:
+        A64, Om64, c = inputs.make_config(name)
+        k, b, q = c["k"], c["b"], c["q"]
+        n1, n2, n3 = A64.shape
+        A = torch.from_numpy(A64).to("cuda")
+        Om = torch.from_numpy(Om64).to("cuda")
+        sig = inputs._decay(c["decay"], min(n1, n2))
+        case = {"optimum_rel_err": float(np.sqrt(np.sum(sig[k:] ** 2) / np.sum(sig ** 2)))}
+        for alg, fn, op in (("alg1", api.tsvd_power_approx, "power_approx"), ("alg2", api.tsvd_rbk_approx, "approx")):
+            ws = api.workspace(n1, n2, n3, k, b, q, "f64", op, "cuda")
+            for _ in range(warmup):
+                out = fn(A, Om, k, b, q, "f64", ws=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                out = fn(A, Om, k, b, q, "f64", ws=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            err = float(torch.linalg.norm(out[3] - A) / torch.linalg.norm(A))
+            case[alg] = {"ms_per_call": ms, "rel_err": err, "basis_columns": b if alg == "alg1" else b * (q + 1)}
+            del ws, out
+        log(f"[bench] {name}: alg1 {case['alg1']['ms_per_call']:.2f} ms err {case['alg1']['rel_err']:.4e}; "
+            f"alg2 {case['alg2']['ms_per_call']:.2f} ms err {case['alg2']['rel_err']:.4e}; "
+            f"optimum {case['optimum_rel_err']:.4e}")
+        res[name] = case
+        del A, Om
+        torch.cuda.empty_cache()
+    return {"workload": "Example 1 spectra m^-5, m^-6, 0.5^m; n = 256; R = 45, P = 5, q = 2; f64", "cases": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +184,7 @@ def main():
     ap.add_argument("--precs", default=None, help="comma-separated forms to time (default: f32,bf16x3; f64 for FP64 workloads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=1)
+    ap.add_argument("--no-alg1", action="store_true", help="skip the Alg. 1 vs Alg. 2 comparison (Example 1)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -247,6 +286,8 @@ def main():
             log(f"[bench] {prec}: rel err vs FP64 oracle on slices {freqs}: {e:.2e}")
         log(f"[bench] cpu baseline {base['value']:.4g} T-SVD/s ({base['sample']})")
 
+    alg12 = None if args.no_alg1 else compare_alg1_alg2(api, inputs, max(args.steps // 2, 3), 1)
+
     ok = [p for p in precs if legs[p].get("rel_err_vs_oracle", 0.0) <= RELERR_GATE]
     best = max(ok or precs, key=lambda p: legs[p]["value"])
     head = legs[best]
@@ -271,6 +312,8 @@ def main():
     }
     if "f32" in legs and best != "f32":
         res["speedup_vs_fp32"] = head["value"] / legs["f32"]["value"]
+    if alg12 is not None:
+        res["alg1_vs_alg2"] = alg12
     if base is not None:
         res["cpu_baseline"] = base
     print(json.dumps(res), flush=True)

@@ -4,8 +4,9 @@
  *
  * Method: M. Nobakht Kooshkghazi, S. Ahmadi-Asl, A. L. F. de Almeida,
  * "Randomized block Krylov method for approximation of truncated tensor SVD",
- * arXiv:2504.04989, Alg. 2 (proposed method), with the T-product / T-QR /
- * T-SVD machinery of Sec. 2 (Alg. TP, Alg. TQR).
+ * arXiv:2504.04989, Alg. 2 (proposed method) and the classical randomized
+ * power-iteration method it is compared with (Alg. 1), with the T-product /
+ * T-QR / T-SVD machinery of Sec. 2 (Alg. TP, Alg. TQR).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -33,10 +34,11 @@
  *
  * Parameters: k = target tubal rank (R in the paper), b = block width
  * (R + P: rank plus oversampling), q = number of Krylov steps.
- * m = b (q + 1) is the number of basis columns per Fourier slice.
+ * m = b (q + 1) is the number of basis columns per Fourier slice (Alg. 2;
+ * for Alg. 1, q counts power iterations and m = b).
  * Requirements (else TSVD_EINVAL, nothing enqueued):
  *   n1, n2, n3 >= 1;  1 <= k <= b;  q >= 0;  m <= min(n1, n2);
- *   n1 * n2 * n3 < 2^31;  m <= 1024;  n3 <= 4096.
+ *   n1 * n2 * n3 < 2^31;  m <= 1024;  n3 <= 4096;  q <= 4096 for Alg. 1.
  *
  * Errors: every entry point returns a status.  TSVD_EINVAL (bad arguments),
  * TSVD_ENOMEM (ws_bytes below tsvd_workspace_bytes), TSVD_EHIP (a HIP launch
@@ -92,6 +94,8 @@ extern "C" {
 #define TSVD_OP_APPROX 1
 #define TSVD_OP_PROJ 2
 #define TSVD_OP_PROJ_BWD 3
+#define TSVD_OP_POWER 4
+#define TSVD_OP_POWER_APPROX 5
 
 /* diagnostic counters returned by tsvd_read_info (int32 each) */
 #define TSVD_INFO_CHOL_SHIFTED 0   /* shifted Cholesky passes that were needed */
@@ -137,6 +141,24 @@ int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2,
                     int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
                     void* U, void* S, void* V, void* Xhat, void* ws,
                     size_t ws_bytes, void* stream);
+
+/* Alg. 1: classical randomized subspace method with q power iterations.
+ * Same arguments, layouts and outputs as tsvd_rbk, but the basis Q_f
+ * (n1 x b per Fourier slice) spans only the last power iterate
+ * (A_f A_f^H)^q A_f Om_f; each iterate is orthonormalised before the next
+ * multiplication (the same range as the literal powers in exact arithmetic).
+ * Projection, small SVD, lift, truncation and phase rule as in tsvd_rbk. */
+int tsvd_power(const void* A, const void* Omega, int64_t n1, int64_t n2,
+               int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
+               void* U, void* S, void* V, void* ws, size_t ws_bytes,
+               void* stream);
+
+/* Alg. 1 followed by the rank-k approximation Xhat = U * S * V^T
+ * (n1 x n2 x n3), as tsvd_rbk_approx does for Alg. 2. */
+int tsvd_power_approx(const void* A, const void* Omega, int64_t n1,
+                      int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q,
+                      int prec, void* U, void* S, void* V, void* Xhat,
+                      void* ws, size_t ws_bytes, void* stream);
 
 /* Projection P(A) = Q * Q^T * A (n1 x n2 x n3), Q the T-orthonormal basis of
  * the block Krylov tensor of Alg. 2 (the projector of Thm. mn44 and

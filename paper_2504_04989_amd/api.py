@@ -16,12 +16,12 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 
 TSVD_OK, TSVD_EINVAL, TSVD_ENOMEM, TSVD_EHIP, TSVD_ENUMERIC = 0, 1, 2, 3, 4
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
-OP = {"rbk": 0, "approx": 1, "proj": 2, "proj_bwd": 3}
+OP = {"rbk": 0, "approx": 1, "proj": 2, "proj_bwd": 3, "power": 4, "power_approx": 5}
 INFO_NAMES = ("chol_shifted", "chol_breakdown", "eig_noconv", "nonfinite")
 INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_rbk", "tsvd_rbk_approx",
-           "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
+           "tsvd_power", "tsvd_power_approx", "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
            "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_heig",
            "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read")
 
@@ -45,6 +45,11 @@ def _load():
     lib.tsvd_rbk.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, sz, vp]
     lib.tsvd_rbk_approx.restype = ctypes.c_int
     lib.tsvd_rbk_approx.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, vp, sz, vp]
+    lib.tsvd_power.restype = ctypes.c_int
+    lib.tsvd_power.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, sz, vp]
+    lib.tsvd_power_approx.restype = ctypes.c_int
+    lib.tsvd_power_approx.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, vp, sz,
+                                      vp]
     lib.tsvd_proj.restype = ctypes.c_int
     lib.tsvd_proj.argtypes = [vp, vp, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, sz, vp]
     lib.tsvd_proj_backward.restype = ctypes.c_int
@@ -166,6 +171,47 @@ def tsvd_rbk_approx(A, Omega, k, b, q, prec=None, ws=None):
     X = torch.empty((n1, n2, n3), dtype=dt, device=dev)
     _check(lib.tsvd_rbk_approx(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S), _ptr(V),
                                _ptr(X), _ptr(ws), ws.numel(), _stream(dev)))
+    return U, S, V, X
+
+
+def tsvd_power(A: torch.Tensor, Omega: torch.Tensor, k: int, b: int, q: int, prec=None, ws=None):
+    """Alg. 1 (q power iterations): returns (U, S, V) like tsvd_rbk."""
+    prec = _prec_of(A, prec)
+    dt = _dtype_of(prec)
+    _check_in(A, dt, "A")
+    _check_in(Omega, dt, "Omega")
+    n1, n2, n3 = A.shape
+    if tuple(Omega.shape) != (n2, b, n3):
+        raise ValueError("Omega must have shape (n2, b, n3)")
+    dev = A.device
+    if ws is None:
+        ws = workspace(n1, n2, n3, k, b, q, prec, "power", dev)
+    U = torch.empty((n1, k, n3), dtype=dt, device=dev)
+    S = torch.empty((k, n3), dtype=dt, device=dev)
+    V = torch.empty((n2, k, n3), dtype=dt, device=dev)
+    _check(lib.tsvd_power(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S), _ptr(V),
+                          _ptr(ws), ws.numel(), _stream(dev)))
+    return U, S, V
+
+
+def tsvd_power_approx(A, Omega, k, b, q, prec=None, ws=None):
+    """Alg. 1 plus X_hat = U * S * V^T: returns (U, S, V, X_hat)."""
+    prec = _prec_of(A, prec)
+    dt = _dtype_of(prec)
+    _check_in(A, dt, "A")
+    _check_in(Omega, dt, "Omega")
+    n1, n2, n3 = A.shape
+    if tuple(Omega.shape) != (n2, b, n3):
+        raise ValueError("Omega must have shape (n2, b, n3)")
+    dev = A.device
+    if ws is None:
+        ws = workspace(n1, n2, n3, k, b, q, prec, "power_approx", dev)
+    U = torch.empty((n1, k, n3), dtype=dt, device=dev)
+    S = torch.empty((k, n3), dtype=dt, device=dev)
+    V = torch.empty((n2, k, n3), dtype=dt, device=dev)
+    X = torch.empty((n1, n2, n3), dtype=dt, device=dev)
+    _check(lib.tsvd_power_approx(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S),
+                                 _ptr(V), _ptr(X), _ptr(ws), ws.numel(), _stream(dev)))
     return U, S, V, X
 
 

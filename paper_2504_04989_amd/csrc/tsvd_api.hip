@@ -40,11 +40,13 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Plan {
   int64_t n1, n2, n3, k, b, q, m, F;
+  bool power;  // Alg. 1: basis of the last power iterate only (m = b)
   int prec;
   DType dt;
   size_t cs;  // bytes of one complex element in the working precision
   int nsplit_blk, kchunk_blk;   // split-K for K = n1 products (block Grams, projections)
   int nsplit_g, kchunk_g;       // split-K for G = T^H T (K = n2)
+  int nsplit_t, kchunk_t;       // split-K for the n2-row block Grams of Alg. 1
   int kmode;                    // Krylov-product arithmetic (KM_*) when dt == DT_F32
   int ks_ax, ks_ahy;            // K splits of the Krylov products A X and A^H Y
   size_t kpart_bytes;           // their partials (K splits or tail splits)
@@ -71,20 +73,28 @@ int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
 int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, int prec, int op, Plan* p) {
   if (n1 < 1 || n2 < 1 || n3 < 1) return fail(TSVD_EINVAL, "n1, n2, n3 must be >= 1");
   if (b < 1 || q < 0) return fail(TSVD_EINVAL, "need b >= 1 and q >= 0");
-  if (op == TSVD_OP_RBK || op == TSVD_OP_APPROX) {
+  const bool power = op == TSVD_OP_POWER || op == TSVD_OP_POWER_APPROX;
+  if (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || power) {
     if (k < 1 || k > b) return fail(TSVD_EINVAL, "need 1 <= k <= b");
   } else {
     k = 1;
   }
-  const int64_t m = b * (q + 1);
-  if (m > std::min(n1, n2)) return fail(TSVD_EINVAL, "need m = b (q + 1) <= min(n1, n2)");
-  if (m > 1024) return fail(TSVD_EINVAL, "m = b (q + 1) must be <= 1024");
+  if (power && q > 4096) return fail(TSVD_EINVAL, "q must be <= 4096");
+  const int64_t m = power ? b : b * (q + 1);
+  if (power) {
+    if (m > std::min(n1, n2)) return fail(TSVD_EINVAL, "need b <= min(n1, n2)");
+    if (m > 1024) return fail(TSVD_EINVAL, "b must be <= 1024");
+  } else {
+    if (m > std::min(n1, n2)) return fail(TSVD_EINVAL, "need m = b (q + 1) <= min(n1, n2)");
+    if (m > 1024) return fail(TSVD_EINVAL, "m = b (q + 1) must be <= 1024");
+  }
   if (n3 > 4096) return fail(TSVD_EINVAL, "n3 must be <= 4096");
   if (n1 * n2 * n3 >= (int64_t)1 << 31 || n1 * n2 >= (int64_t)1 << 31)
     return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
   if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32 && prec != TSVD_PREC_BF16 && prec != TSVD_PREC_BF16X3)
     return fail(TSVD_EINVAL, "unknown precision mode");
-  if (op < TSVD_OP_RBK || op > TSVD_OP_PROJ_BWD) return fail(TSVD_EINVAL, "unsupported operation");
+  if (op < TSVD_OP_RBK || op > TSVD_OP_POWER_APPROX) return fail(TSVD_EINVAL, "unsupported operation");
+  p->power = power;
   p->n1 = n1;
   p->n2 = n2;
   p->n3 = n3;
@@ -101,6 +111,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->nsplit_blk = split_for(n1, tb * ((m + 63) / 64), F, &p->kchunk_blk);
   const int64_t tm = (m + 63) / 64;
   p->nsplit_g = split_for(n2, tm * tm, F, &p->kchunk_g);
+  p->nsplit_t = split_for(n2, tb * tb, F, &p->kchunk_t);
   p->kmode = prec == TSVD_PREC_BF16 ? KM_BF16 : (prec == TSVD_PREC_BF16X3 ? KM_BF16X3 : KM_F32);
   int kc_unused;
   if (p->kmode != KM_BF16) {
@@ -123,23 +134,32 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_obar = take((size_t)F * n2 * b * cs);
   p->o_q = take((size_t)F * n1 * m * cs);
   p->o_t = take((size_t)F * n2 * m * cs);
-  p->o_s0 = take((size_t)F * n1 * b * cs);
-  p->o_s1 = take((size_t)F * n1 * b * cs);
+  // block scratch: n1-row Krylov blocks; Alg. 1 also orthonormalises the
+  // n2-row half-step iterates A_f^H Q
+  const int64_t srows = power ? std::max(n1, n2) : n1;
+  p->o_s0 = take((size_t)F * srows * b * cs);
+  p->o_s1 = take((size_t)F * srows * b * cs);
   size_t part = (size_t)p->nsplit_blk * F * m * b * 16;
   part = std::max(part, (size_t)p->nsplit_g * F * m * m * 16);
+  if (power) part = std::max(part, (size_t)p->nsplit_t * F * b * b * 16);
   if (p->dt == DT_F32) {
     // FP64-arithmetic products on FP32 blocks: block Grams (b x b), projections
     // (i b x b and b x i b), G = T^H T (m x m)
     part = ogemm_tn_part_bytes((int)m, (int)n2, (int)m, (int)F);
-    for (int64_t i = 1; i <= std::max<int64_t>(q, 1); ++i) {
+    // block Grams and projections against the i b earlier columns (Alg. 2
+    // only; Alg. 1 orthonormalises each iterate on its own)
+    for (int64_t i = 1; i <= (power ? 1 : std::max<int64_t>(q, 1)); ++i) {
       part = std::max(part, ogemm_tn_part_bytes((int)(i * b), (int)n1, (int)b, (int)F));
       part = std::max(part, ogemm_tn_part_bytes((int)b, (int)n1, (int)(i * b), (int)F));
+    }
+    if (power) {
+      part = std::max(part, ogemm_tn_part_bytes((int)b, (int)n2, (int)b, (int)F));
     }
   }
   p->o_part = take(part);
   p->o_rinv = take((size_t)F * b * b * 16);
   p->o_chol = take(chol_uses_lds(b) ? 0 : (size_t)F * b * (b + 1) / 2 * 16);
-  const bool need_svd = (op == TSVD_OP_RBK || op == TSVD_OP_APPROX);
+  const bool need_svd = (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || power);
   p->o_lam = take(need_svd ? (size_t)F * k * 8 : 0);
   p->o_sig = take(need_svd ? (size_t)F * k * 8 : 0);
   p->o_wd = take(need_svd ? (size_t)F * m * k * 16 : 0);
@@ -149,7 +169,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_uf = take(need_svd ? (size_t)F * n1 * k * cs : 0);
   p->o_vf = take(need_svd ? (size_t)F * n2 * k * cs : 0);
   p->o_scx = take(need_svd ? (size_t)F * k * cs : 0);
-  p->o_us = take(op == TSVD_OP_APPROX ? (size_t)F * n1 * k * cs : 0);
+  p->o_us = take(op == TSVD_OP_APPROX || op == TSVD_OP_POWER_APPROX ? (size_t)F * n1 * k * cs : 0);
   const bool bwd = op == TSVD_OP_PROJ_BWD;
   p->o_gbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
   p->o_dbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
@@ -296,20 +316,20 @@ int inner_products(const Ctx& c, const void* X, int64_t lx, int M, const void* Y
   return TSVD_OK;
 }
 
-// dst (n1 x b, ld ldd) = src (n1 x b, ld lds) * Rinv   (FP64 arithmetic)
-int apply_rinv(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ldd) {
+// dst (rows x b, ld ldd) = src (rows x b, ld lds) * Rinv   (FP64 arithmetic)
+int apply_rinv(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ldd, int64_t rows) {
   const Plan& p = c.p;
   if (p.dt == DT_F32) {
     Timed tm_(K_GEMM_ORTH, c.s);
-    HIPCHK(ogemm_nn(static_cast<const float*>(src), lds, p.n1 * lds, c.at<double>(p.o_rinv), p.b, p.b * p.b, 1, 0,
-                    static_cast<float*>(dst), ldd, p.n1 * ldd, (int)p.n1, (int)p.b, (int)p.b, (int)p.F, 1.0, 0.0,
+    HIPCHK(ogemm_nn(static_cast<const float*>(src), lds, rows * lds, c.at<double>(p.o_rinv), p.b, p.b * p.b, 1, 0,
+                    static_cast<float*>(dst), ldd, rows * ldd, (int)rows, (int)p.b, (int)p.b, (int)p.F, 1.0, 0.0,
                     c.s, true));
     return TSVD_OK;
   }
   GemmDesc d = gd();
   d.A = src;
   d.lda = lds;
-  d.strideA = p.n1 * lds;
+  d.strideA = rows * lds;
   d.ta = p.dt;
   d.B = c.at(p.o_rinv);
   d.ldb = p.b;
@@ -317,9 +337,9 @@ int apply_rinv(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ld
   d.tb = DT_F64;
   d.C = dst;
   d.ldc = ldd;
-  d.strideC = p.n1 * ldd;
+  d.strideC = rows * ldd;
   d.tc = p.dt;
-  d.M = (int)p.n1;
+  d.M = (int)rows;
   d.N = (int)p.b;
   d.K = (int)p.b;
   d.batch = (int)p.F;
@@ -331,24 +351,27 @@ int apply_rinv(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ld
   return TSVD_OK;
 }
 
-// One CholeskyQR pass: dst = src R^{-1}, G = src^H src (+ shift).
-int cholqr_pass(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ldd, bool shifted) {
+// One CholeskyQR pass over a rows x b block (rows = n1 for the Krylov blocks,
+// n2 for Alg. 1's half-step iterates): dst = src R^{-1}, G = src^H src (+ shift).
+int cholqr_pass(const Ctx& c, const void* src, int64_t lds, void* dst, int64_t ldd, bool shifted, int64_t rows) {
   const Plan& p = c.p;
   double* part = c.at<double>(p.o_part);
   int nsum = 1;
   // the Gram is Hermitian: on the FP32 path (b <= 128) only its upper triangle is formed
   const bool upper = p.dt == DT_F32 && chol_blocked_ok((int)p.b);
-  int r = inner_products(c, src, lds, (int)p.b, src, lds, (int)p.b, p.n1, p.n1 * lds, p.n1 * lds, p.nsplit_blk,
-                         p.kchunk_blk, part, &nsum, K_GEMM_ORTH, upper);
+  const bool long_rows = rows == p.n1;
+  int r = inner_products(c, src, lds, (int)p.b, src, lds, (int)p.b, rows, rows * lds, rows * lds,
+                         long_rows ? p.nsplit_blk : p.nsplit_t, long_rows ? p.kchunk_blk : p.kchunk_t, part, &nsum,
+                         K_GEMM_ORTH, upper);
   if (r) return r;
   const double u = 1.1102230246251565e-16;
-  const double shift = shifted ? 11.0 * ((double)p.n1 * p.b + (double)p.b * (p.b + 1)) * u : 0.0;
+  const double shift = shifted ? 11.0 * ((double)rows * p.b + (double)p.b * (p.b + 1)) * u : 0.0;
   {
     Timed tm_(K_CHOL, c.s);
     HIPCHK(chol_inv_ex(part, nsum, p.F * p.b * p.b, c.at<double>(p.o_rinv), c.at(p.o_chol), (int)p.b, (int)p.F,
                        shift, c.info(), c.s, upper ? 2 : 0));
   }
-  return apply_rinv(c, src, lds, dst, ldd);
+  return apply_rinv(c, src, lds, dst, ldd, rows);
 }
 
 // W (n1 x b, ld b) -= Q_<i (Q_<i^H W), Q_<i = first i*b columns of Q.
@@ -398,6 +421,27 @@ int project_out(const Ctx& c, void* W, int i) {
   return TSVD_OK;
 }
 
+// Shifted CholeskyQR3 of a rows x b block whose first pass has been done
+// (result in S1): dst = orthonormal basis of its range.
+int cholqr_finish(const Ctx& c, int64_t rows, void* dst, int64_t ldd) {
+  const Plan& p = c.p;
+  void* S0 = c.at(p.o_s0);
+  void* S1 = c.at(p.o_s1);
+  int r;
+  if (p.dt == DT_F64) {
+    // FP64 blocks can be far more ill-conditioned than FP32 ones, whose
+    // rounding noise bounds the condition number near 1e8: a slice spectrum
+    // that reaches the FP64 rounding level within one block gives
+    // kappa >= 1/u.  One shifted pass then leaves kappa above u^{-1/2}
+    // (rounding in W R^{-1}); two more bring it down before the unshifted
+    // CholeskyQR2.
+    if ((r = cholqr_pass(c, S1, p.b, S0, p.b, true, rows))) return r;
+    if ((r = cholqr_pass(c, S0, p.b, S1, p.b, true, rows))) return r;
+  }
+  if ((r = cholqr_pass(c, S1, p.b, S0, p.b, false, rows))) return r;
+  return cholqr_pass(c, S0, p.b, dst, ldd, false, rows);
+}
+
 // Orthonormalise the block in S0 against Q_<i and write it to Q(:, i b : (i+1) b).
 int orth_block(const Ctx& c, int i) {
   const Plan& p = c.p;
@@ -406,10 +450,17 @@ int orth_block(const Ctx& c, int i) {
   void* dst = c.at<unsigned char>(p.o_q) + (size_t)i * p.b * p.cs;
   int r;
   if ((r = project_out(c, S0, i))) return r;
-  if ((r = cholqr_pass(c, S0, p.b, S1, p.b, true))) return r;
+  if ((r = cholqr_pass(c, S0, p.b, S1, p.b, true, p.n1))) return r;
   if ((r = project_out(c, S1, i))) return r;
-  if ((r = cholqr_pass(c, S1, p.b, S0, p.b, false))) return r;
-  return cholqr_pass(c, S0, p.b, dst, p.m, false);
+  return cholqr_finish(c, p.n1, dst, p.m);
+}
+
+// Orthonormalise an n2 x b block in place (ld b): Alg. 1's half-step iterate.
+int orth_rows_n2(const Ctx& c, void* X) {
+  const Plan& p = c.p;
+  int r;
+  if ((r = cholqr_pass(c, X, p.b, c.at(p.o_s1), p.b, true, p.n2))) return r;
+  return cholqr_finish(c, p.n2, X, p.b);
 }
 
 // Out (M x N, ld ldc) = A_f (n1 x n2) * X (n2 x N, ld ldx): the big products.
@@ -552,6 +603,20 @@ int krylov(const Ctx& c, const void* A, const void* Omega, bool keep_raw = false
   unsigned char* T = c.at<unsigned char>(p.o_t);
   int r;
   if ((r = big_AX(c, c.at(p.o_obar), p.b, p.n2 * p.b, c.at(p.o_s0), p.b, p.n1 * p.b, (int)p.b))) return r;
+  if (p.power) {
+    // Alg. 1, q power iterations with an orthonormalisation after every
+    // product: T <- orth(A_f^H Q), Q <- orth(A_f T); the basis is the last
+    // iterate's (same range as (A A^H)^q A Om in exact arithmetic, without
+    // squaring the condition number at each step)
+    if ((r = orth_block(c, 0))) return r;
+    for (int i = 1; i <= p.q; ++i) {
+      if ((r = big_AhY(c, Q, p.m, p.n1 * p.m, T, p.m, p.n2 * p.m, (int)p.b))) return r;
+      if ((r = orth_rows_n2(c, T))) return r;
+      if ((r = big_AX(c, T, p.m, p.n2 * p.m, c.at(p.o_s0), p.b, p.n1 * p.b, (int)p.b))) return r;
+      if ((r = orth_block(c, 0))) return r;
+    }
+    return big_AhY(c, Q, p.m, p.n1 * p.m, T, p.m, p.n2 * p.m, (int)p.b);
+  }
   if (keep_raw && (r = save_raw(c, 0))) return r;
   if ((r = orth_block(c, 0))) return r;
   for (int i = 1; i <= p.q; ++i) {
@@ -684,6 +749,44 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   return TSVD_OK;
 }
 
+
+// X_f = (U_f diag(sigma)) V_f^H over A_f's buffer, then the inverse DFT to
+// Xhat (the rank-k approximation U * S * V^T, Alg. TP).
+int approx_tail(const Ctx& c, void* Xhat) {
+  const Plan& p = c.p;
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(scale_cols_by(c.at(p.o_uf), c.at<double>(p.o_sig), c.at(p.o_us), p.n1, (int)p.k, (int)p.F, p.dt, c.s));
+  }
+  GemmDesc d = gd();
+  d.A = c.at(p.o_us);
+  d.lda = p.k;
+  d.strideA = p.n1 * p.k;
+  d.ta = p.dt;
+  d.B = c.at(p.o_vf);
+  d.ldb = p.k;
+  d.strideB = p.n2 * p.k;
+  d.tb = p.dt;
+  d.b_conj = true;
+  d.C = c.at(p.o_abar);
+  d.ldc = p.n2;
+  d.strideC = p.n1 * p.n2;
+  d.tc = p.dt;
+  d.M = (int)p.n1;
+  d.N = (int)p.n2;
+  d.K = (int)p.k;
+  d.batch = (int)p.F;
+  d.compute = p.dt;
+  {
+    Timed tm_(K_GEMM_LIFT, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, Xhat, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  }
+  return TSVD_OK;
+}
 
 // Generic batched product C = alpha opA(A) opB(B) + beta C over the F slices
 // (element strides and leading dimensions in complex elements).
@@ -888,38 +991,35 @@ int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2, in
   Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
   if ((r = krylov(c, A, Omega))) return r;
   if ((r = svd_and_lift(c, U, S, V))) return r;
-  // X_f = (U_f diag(sigma)) V_f^H, then the inverse DFT.
-  {
-    Timed tm_(K_MISC, c.s);
-    HIPCHK(scale_cols_by(c.at(p.o_uf), c.at<double>(p.o_sig), c.at(p.o_us), p.n1, (int)p.k, (int)p.F, p.dt, c.s));
-  }
-  GemmDesc d = gd();
-  d.A = c.at(p.o_us);
-  d.lda = p.k;
-  d.strideA = p.n1 * p.k;
-  d.ta = p.dt;
-  d.B = c.at(p.o_vf);
-  d.ldb = p.k;
-  d.strideB = p.n2 * p.k;
-  d.tb = p.dt;
-  d.b_conj = true;
-  d.C = c.at(p.o_abar);
-  d.ldc = p.n2;
-  d.strideC = p.n1 * p.n2;
-  d.tc = p.dt;
-  d.M = (int)p.n1;
-  d.N = (int)p.n2;
-  d.K = (int)p.k;
-  d.batch = (int)p.F;
-  d.compute = p.dt;
-  {
-    Timed tm_(K_GEMM_LIFT, c.s);
-    HIPCHK(zgemm(d, c.s));
-  }
-  {
-    Timed tm_(K_FFT_INV, c.s);
-    HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, Xhat, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
-  }
+  if ((r = approx_tail(c, Xhat))) return r;
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_power(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+               int64_t q, int prec, void* U, void* S, void* V, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_POWER, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, Omega, U, S, V}, ws, ws_bytes, p))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = krylov(c, A, Omega))) return r;
+  if ((r = svd_and_lift(c, U, S, V))) return r;
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_power_approx(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                      int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
+                      void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_POWER_APPROX, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, Omega, U, S, V, Xhat}, ws, ws_bytes, p))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = krylov(c, A, Omega))) return r;
+  if ((r = svd_and_lift(c, U, S, V))) return r;
+  if ((r = approx_tail(c, Xhat))) return r;
   g_err.clear();
   return TSVD_OK;
 }

@@ -80,3 +80,24 @@ def test_entry_points_reject_bad_pointers_without_touching_the_gpu():
     assert r == api.TSVD_ENOMEM
     r = L.tsvd_diag_zgemm(nul, 0, nul, 0, nul, 4, 4, 4, 1, 1.0, 0.0, 1, nul)
     assert r == api.TSVD_EINVAL
+
+
+def test_power_method_sizes_and_rejections():
+    # Alg. 1 keeps m = b basis columns whatever q is: b (q + 1) > min(n1, n2)
+    # is accepted, b > min(n1, n2) is not.
+    from paper_2504_04989_amd import api
+    assert api.workspace_bytes(10, 10, 4, 2, 4, 5, "f32", "power") > 0
+    assert api.workspace_bytes(10, 10, 4, 2, 4, 5, "f32", "rbk") == 0
+    assert api.workspace_bytes(10, 10, 4, 2, 11, 1, "f32", "power") == 0
+    assert api.workspace_bytes(10, 10, 4, 5, 4, 1, "f32", "power") == 0          # k > b
+    ws = api.workspace_bytes(256, 256, 256, 45, 50, 2, "f64", "power")
+    assert 0 < ws < api.workspace_bytes(256, 256, 256, 45, 50, 2, "f64", "rbk")
+    assert api.workspace_bytes(256, 256, 256, 45, 50, 2, "f64", "power_approx") > ws
+    L = api.lib
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.tsvd_power(nul, nul, 10, 10, 4, 2, 3, 1, 1, nul, nul, nul, nul, 0, nul) == api.TSVD_EINVAL
+    r = L.tsvd_power_approx(fake, fake, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, fake, fake, 16, nul)
+    assert r == api.TSVD_ENOMEM
+    r = L.tsvd_power(fake, fake, 10, 10, 4, 2, 3, 5000, 1, fake, fake, fake, fake, 1 << 30, nul)   # q too large
+    assert r == api.TSVD_EINVAL
