@@ -55,17 +55,23 @@ def class_work(cls: str, c: dict, prec: str):
         return fl / 1e12, "TFLOP/s", "mfma", PEAK["mfma_tflops"][prec], "algorithmic flops"
     if cls == "fft_A":         # read the real tensor, write the half spectrum
         return (es * n1 * n2 * n3 + 2 * es * n1 * n2 * F) / 1e9, "GB/s", "hbm", PEAK["hbm_gbs"], "algorithmic bytes"
-    if cls == "gemm_orth":     # block CGS2 against earlier blocks + shifted CholeskyQR3, FP64 arithmetic
-        fl = sum(2 * 16.0 * n1 * (i * b) * b for i in range(1, q + 1)) + (q + 1) * 3 * 16.0 * n1 * b * b
-        return fl * F / 1e12, "TFLOP/s", "mfma", PEAK["mfma_tflops"]["f64"], "algorithmic flops (full Grams)"
-    if cls == "chol":          # b x b complex Cholesky + triangular inverse per slice, 3 (q + 1) launches
-        return 3 * (q + 1) * F * (16.0 / 3.0 * b ** 3) / 1e12, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"], \
+    # CholeskyQR passes per block: shifted + 2 (FP32 storage); FP64 adds two
+    # more shifted passes
+    passes = 5 if prec == "f64" else 3
+    if cls == "gemm_orth":     # block CGS2 against earlier blocks + shifted CholeskyQR, FP64 arithmetic
+        # projections: two passes of Q^H W and W - Q coef; each CholeskyQR pass:
+        # the Hermitian b x b Gram (upper half) and W R^{-1} (triangular)
+        fl = sum(2 * 16.0 * n1 * (i * b) * b for i in range(1, q + 1)) + (q + 1) * passes * 8.0 * n1 * b * (b + 1)
+        return fl * F / 1e12, "TFLOP/s", "mfma", PEAK["mfma_tflops"]["f64"], \
+            "algorithmic flops (Hermitian Grams and W R^-1 counted as upper halves)"
+    if cls == "chol":          # b x b complex Cholesky + triangular inverse per slice, one per CholeskyQR pass
+        return passes * (q + 1) * F * (16.0 / 3.0 * b ** 3) / 1e12, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"], \
             "algorithmic flops"
     if cls == "heig_tri":      # Householder tridiagonalisation of the m x m Hermitian G_f
         return F * (16.0 / 3.0 * m ** 3) / 1e12, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"], "algorithmic flops"
-    if cls == "gemm_lift":     # G = T^H T (full), U = Q W_k, V = T W_k
-        return F * (8.0 * n2 * m * m + 8.0 * (n1 + n2) * m * k) / 1e12, "TFLOP/s", "mfma", \
-            PEAK["mfma_tflops"]["f64"], "algorithmic flops (full Gram)"
+    if cls == "gemm_lift":     # G = T^H T (Hermitian: upper half), U = Q W_k, V = T W_k
+        return F * (4.0 * n2 * m * (m + 1) + 8.0 * (n1 + n2) * m * k) / 1e12, "TFLOP/s", "mfma", \
+            PEAK["mfma_tflops"]["f64"], "algorithmic flops (Hermitian Gram counted as its upper half)"
     return None
 
 
