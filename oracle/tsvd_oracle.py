@@ -29,6 +29,11 @@ Pins (tests/test_oracle_*.py, all ``-m "not gpu"``):
                            literal == stabilised Krylov form
   proj / proj_backward     central finite differences, torch CPU autograd,
                            Euler homogeneity
+  tqr / tpinv              X = Q * R and Q^T * Q = I with spatial T-products,
+                           triangular slices with a real non-negative
+                           diagonal, numpy QR at n3 = 1; the four Penrose
+                           conditions with spatial T-products (full rank and
+                           rank deficient), X^+ * X = I for full column rank
   power_tsvd (Alg. 1)      n3 = 1 is the matrix randomized subspace iteration
                            (numpy QR / SVD); b = n1 gives the exact truncated
                            T-SVD; exact recovery of a tubal-rank-r tensor;
@@ -64,6 +69,10 @@ Readings (where the paper is silent / ambiguous):
       in exact arithmetic and never forms the squared spectrum; the literal
       form is kept as a cross-check (power="lit").  Alg. 1 shares Alg. 2's
       projection, small SVD, lift and rank-k truncation.
+  R19 T-QR: qr(X_f, 0) fixes Q_f and R_f only up to one unit phase per column;
+      the diagonal of R_f is taken real and non-negative (unique when the
+      first r = min(n1, n2) columns of X_f are independent).  For n1 < n2 the
+      economy QR orthonormalises the first n1 columns and R_f = Q_f^H X_f.
 """
 from __future__ import annotations
 
@@ -625,6 +634,51 @@ def proj_backward(A: np.ndarray, Omega: np.ndarray, G: np.ndarray, b: int, q: in
     for f in range(F):
         Dh[:, :, f] = _proj_slice_adjoint(Ab[:, :, f], Ob[:, :, f], Gb[:, :, f], q)
     return real_part_checked(idft_mode3(mirror(Dh, n3)))
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2: T-QR (Alg. TQR) and the Moore-Penrose pseudoinverse (Alg. mp)
+# ---------------------------------------------------------------------------
+
+def tqr(X: np.ndarray):
+    """Alg. TQR: economy T-QR X = Q * R, Q (n1 x r x n3) with Q^T * Q = I,
+    R (r x n2 x n3) with upper-trapezoidal Fourier slices, r = min(n1, n2).
+
+    Per half-spectrum slice: Householder QR of the first r columns, R_f =
+    Q_f^H X_f with the strictly lower part set to zero, then each pair
+    (Q_f(:, j), R_f(j, :)) scaled by one unit phase so that R_f(j, j) is real
+    and non-negative (reading R19); mirror (Alg. TQR, second loop); inverse
+    DFT."""
+    n1, n2, n3 = X.shape
+    r = min(n1, n2)
+    F = n_half(n3)
+    Xb = dft_mode3(X, range(F))
+    Qh = np.zeros((n1, r, F), complex)
+    Rh = np.zeros((r, n2, F), complex)
+    for f in range(F):
+        Q, _ = householder_qr(Xb[:, :r, f])
+        R = np.triu(Q.conj().T @ Xb[:, :, f])
+        d = np.diag(R[:, :r])
+        ph = np.ones(r, complex)
+        nz = np.abs(d) > 0
+        ph[nz] = np.conj(d[nz]) / np.abs(d[nz])
+        Qh[:, :, f] = Q * np.conj(ph)[None, :]
+        Rh[:, :, f] = R * ph[:, None]
+    Q = real_part_checked(idft_mode3(mirror(Qh, n3)))
+    R = real_part_checked(idft_mode3(mirror(Rh, n3)))
+    return Q, R
+
+
+def tpinv(X: np.ndarray) -> np.ndarray:
+    """Alg. mp: Moore-Penrose pseudoinverse X^+ (n2 x n1 x n3): numpy's
+    SVD-based pinv of every half-spectrum slice, mirror, inverse DFT."""
+    n1, n2, n3 = X.shape
+    F = n_half(n3)
+    Xb = dft_mode3(X, range(F))
+    Ch = np.zeros((n2, n1, F), complex)
+    for f in range(F):
+        Ch[:, :, f] = np.linalg.pinv(Xb[:, :, f])
+    return real_part_checked(idft_mode3(mirror(Ch, n3)))
 
 
 def masked_loss(T: np.ndarray, M: np.ndarray, P: np.ndarray) -> float:

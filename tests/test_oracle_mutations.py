@@ -82,6 +82,20 @@ def pin_power_spatial(O):
         assert np.linalg.norm(res) < 1e-10 * np.linalg.norm(Yb[:, :, f])
 
 
+def pin_tqr(O):
+    X = inputs.random_tensor((7, 5, 4), 41)
+    Q, R = O.tqr(X)
+    assert np.allclose(O.tprod_bcirc(Q, R), X, atol=1e-12 * np.abs(X).max())
+    assert np.allclose(O.tprod_bcirc(O.ttranspose(Q), Q), O.identity_tensor(5, 4), atol=1e-12)
+
+
+def pin_tpinv(O):
+    X = inputs.random_tensor((7, 5, 4), 43)
+    P = O.tpinv(X)
+    assert np.allclose(O.tprod_bcirc(O.tprod_bcirc(X, P), X), X, atol=1e-10)
+    assert np.allclose(O.tprod_bcirc(P, X), O.identity_tensor(5, 4), atol=1e-10)
+
+
 def pin_exact_tsvd(O):
     # m = n1: Alg. 2 must equal the truncated T-SVD computed with numpy's SVD.
     n1, n2, n3, k = 20, 24, 4, 5
@@ -132,6 +146,11 @@ MUTATIONS = [
      pin_power_spatial),
     ("power basis without A^H", "Qt, _ = householder_qr(Af.conj().T @ Qp)", "Qt, _ = householder_qr(Qp[:Af.shape[1]])",
      pin_power_spatial),
+    ("tqr phase applied twice to R", "Rh[:, :, f] = R * ph[:, None]", "Rh[:, :, f] = R * np.conj(ph)[:, None]",
+     pin_tqr),
+    ("tqr R without conj", "R = np.triu(Q.conj().T @ Xb[:, :, f])", "R = np.triu(Q.T @ Xb[:, :, f])", pin_tqr),
+    ("tpinv conjugated", "Ch[:, :, f] = np.linalg.pinv(Xb[:, :, f])", "Ch[:, :, f] = np.linalg.pinv(Xb[:, :, f]).conj()",
+     pin_tpinv),
     ("projection without conj", "C = Q.conj().T @ Af", "C = Q.T @ Af", pin_exact_tsvd),
     ("truncation off by one", "Vf = Z[:, :k]", "Vf = Z[:, 1:k + 1]", pin_exact_tsvd),
     ("lift with conj", "Uf = Q @ W[:, :k]", "Uf = Q @ W[:, :k].conj()", pin_exact_tsvd),
