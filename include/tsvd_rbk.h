@@ -96,6 +96,8 @@ extern "C" {
 #define TSVD_OP_PROJ_BWD 3
 #define TSVD_OP_POWER 4
 #define TSVD_OP_POWER_APPROX 5
+#define TSVD_OP_TQR 6     /* k, b, q ignored */
+#define TSVD_OP_TPINV 7   /* k, b, q ignored */
 
 /* diagnostic counters returned by tsvd_read_info (int32 each) */
 #define TSVD_INFO_CHOL_SHIFTED 0   /* shifted Cholesky passes that were needed */
@@ -159,6 +161,32 @@ int tsvd_power_approx(const void* A, const void* Omega, int64_t n1,
                       int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q,
                       int prec, void* U, void* S, void* V, void* Xhat,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* Alg. TQR: economy T-QR A = Q * R (Sec. 2).
+ * In:  A (n1 x n2 x n3).  Out: Q (n1 x r x n3) with Q^T * Q = I, and
+ * R (r x n2 x n3) whose Fourier slices are upper trapezoidal, r = min(n1, n2).
+ * Per Fourier slice f = 0 .. n3/2: Q_f orthonormalises the first r columns of
+ * A_f (shifted CholeskyQR, FP64 Grams and factors) and R_f = Q_f^H A_f, zero
+ * below the diagonal; conjugate symmetry gives the other slices.  The
+ * diagonal of every R_f is real and positive, which makes the factorisation
+ * unique; the first r columns of each A_f must be linearly independent (a
+ * breakdown is counted in TSVD_INFO_CHOL_BREAKDOWN).
+ * prec: TSVD_PREC_F64 or TSVD_PREC_F32 (storage and the Q, R products; the
+ * Grams are FP64).  Requirements: min(n1, n2) <= 1024, n3 <= 4096,
+ * n1 * n2 * n3 < 2^31.  Workspace: tsvd_workspace_bytes(n1, n2, n3, 0, 0, 0,
+ * prec, TSVD_OP_TQR). */
+int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec,
+             void* Q, void* R, void* ws, size_t ws_bytes, void* stream);
+
+/* Alg. mp: Moore-Penrose T-pseudoinverse X = A^+ (n2 x n1 x n3, Sec. 2), for
+ * tensors whose Fourier slices have full column rank (n1 >= n2, else
+ * TSVD_EINVAL; a wide tensor follows from (A^T)^+ = (A^+)^T).  Per slice,
+ * A_f = Q_f R_f as in tsvd_tqr and A_f^+ = R_f^{-1} Q_f^H (FP64 triangular
+ * inverse and product).  Rank-deficient slices are outside its domain: their
+ * R_f^{-1} is not the pseudoinverse's.  prec: TSVD_PREC_F64 or
+ * TSVD_PREC_F32.  Workspace: tsvd_workspace_bytes(..., TSVD_OP_TPINV). */
+int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec,
+               void* X, void* ws, size_t ws_bytes, void* stream);
 
 /* Projection P(A) = Q * Q^T * A (n1 x n2 x n3), Q the T-orthonormal basis of
  * the block Krylov tensor of Alg. 2 (the projector of Thm. mn44 and

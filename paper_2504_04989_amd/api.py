@@ -16,12 +16,12 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 
 TSVD_OK, TSVD_EINVAL, TSVD_ENOMEM, TSVD_EHIP, TSVD_ENUMERIC = 0, 1, 2, 3, 4
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
-OP = {"rbk": 0, "approx": 1, "proj": 2, "proj_bwd": 3, "power": 4, "power_approx": 5}
+OP = {"rbk": 0, "approx": 1, "proj": 2, "proj_bwd": 3, "power": 4, "power_approx": 5, "tqr": 6, "tpinv": 7}
 INFO_NAMES = ("chol_shifted", "chol_breakdown", "eig_noconv", "nonfinite")
 INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_rbk", "tsvd_rbk_approx",
-           "tsvd_power", "tsvd_power_approx", "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
+           "tsvd_power", "tsvd_power_approx", "tsvd_tqr", "tsvd_tpinv", "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
            "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_heig",
            "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read")
 
@@ -50,6 +50,10 @@ def _load():
     lib.tsvd_power_approx.restype = ctypes.c_int
     lib.tsvd_power_approx.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, vp, sz,
                                       vp]
+    lib.tsvd_tqr.restype = ctypes.c_int
+    lib.tsvd_tqr.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp, vp, sz, vp]
+    lib.tsvd_tpinv.restype = ctypes.c_int
+    lib.tsvd_tpinv.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp, sz, vp]
     lib.tsvd_proj.restype = ctypes.c_int
     lib.tsvd_proj.argtypes = [vp, vp, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, sz, vp]
     lib.tsvd_proj_backward.restype = ctypes.c_int
@@ -213,6 +217,35 @@ def tsvd_power_approx(A, Omega, k, b, q, prec=None, ws=None):
     _check(lib.tsvd_power_approx(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S),
                                  _ptr(V), _ptr(X), _ptr(ws), ws.numel(), _stream(dev)))
     return U, S, V, X
+
+
+def tsvd_tqr(A: torch.Tensor, prec=None, ws=None):
+    """Alg. TQR: returns (Q, R), Q (n1, r, n3), R (r, n2, n3), r = min(n1, n2)."""
+    prec = _prec_of(A, prec)
+    dt = _dtype_of(prec)
+    _check_in(A, dt, "A")
+    n1, n2, n3 = A.shape
+    r = min(n1, n2)
+    if ws is None:
+        ws = workspace(n1, n2, n3, 0, 0, 0, prec, "tqr", A.device)
+    Q = torch.empty((n1, r, n3), dtype=dt, device=A.device)
+    R = torch.empty((r, n2, n3), dtype=dt, device=A.device)
+    _check(lib.tsvd_tqr(_ptr(A), n1, n2, n3, PREC[prec], _ptr(Q), _ptr(R), _ptr(ws), ws.numel(),
+                        _stream(A.device)))
+    return Q, R
+
+
+def tsvd_tpinv(A: torch.Tensor, prec=None, ws=None):
+    """Alg. mp for slices of full column rank: returns A^+ (n2, n1, n3)."""
+    prec = _prec_of(A, prec)
+    dt = _dtype_of(prec)
+    _check_in(A, dt, "A")
+    n1, n2, n3 = A.shape
+    if ws is None:
+        ws = workspace(n1, n2, n3, 0, 0, 0, prec, "tpinv", A.device)
+    X = torch.empty((n2, n1, n3), dtype=dt, device=A.device)
+    _check(lib.tsvd_tpinv(_ptr(A), n1, n2, n3, PREC[prec], _ptr(X), _ptr(ws), ws.numel(), _stream(A.device)))
+    return X
 
 
 def tsvd_proj(A, Omega, b, q, prec=None, ws=None):

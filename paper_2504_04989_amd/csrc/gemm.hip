@@ -225,6 +225,7 @@ hipError_t zgemm(const GemmDesc& d, hipStream_t s) {
   if (a == DT_F32 && b == DT_F32 && c == DT_F64 && t == DT_F64) return launch_conj<float, float, double, double>(d, s);
   if (a == DT_F32 && b == DT_F64 && c == DT_F32 && t == DT_F64) return launch_conj<float, double, float, double>(d, s);
   if (a == DT_F32 && b == DT_F64 && c == DT_F32 && t == DT_F32) return launch_conj<float, double, float, float>(d, s);
+  if (a == DT_F64 && b == DT_F32 && c == DT_F32 && t == DT_F64) return launch_conj<double, float, float, double>(d, s);
   return hipErrorInvalidValue;
 }
 

@@ -124,6 +124,10 @@ hipError_t sigma_from_lambda(const double* lambda, double* sigma, void* scx, int
 // U * diag(sigma): Uout (batch x n1 x k) = Uin * sigma (per slice).
 hipError_t scale_cols_by(const void* Uin, const double* sigma, void* Uout, int64_t n1, int k, int batch, DType t,
                          hipStream_t s);
+// R (batch x r x n, dtype t) = upper-trapezoidal part of the sum of nsum FP64
+// partials (spaced part_stride complex elements); zeros below the diagonal.
+hipError_t triu_store(const double* part, int nsum, int64_t part_stride, int r, int n, int batch, void* R, DType t,
+                      hipStream_t s);
 hipError_t zero_info(int* info, hipStream_t s);
 
 }  // namespace tsvd

@@ -111,6 +111,41 @@ hipError_t sigma_from_lambda(const double* lambda, double* sigma, void* scx, int
   return hipGetLastError();
 }
 
+// R_f (r x n, dtype T, row-major) = upper-trapezoidal part of the sum of
+// nsum FP64 partial products (partial s of slice f at part + s * part_stride
+// + f * r * n complex doubles); entries below the diagonal are written as 0.
+template <typename T>
+__global__ void triu_store_kernel(const cx<double>* __restrict__ part, int nsum, int64_t part_stride, int r, int n,
+                                  int batch, cx<T>* __restrict__ R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)r * n;
+  if (t >= per * batch) return;
+  const int64_t e = t % per;
+  const int i = (int)(e / n), j = (int)(e % n);
+  cx<double> v{0.0, 0.0};
+  if (j >= i) {
+    for (int s = 0; s < nsum; ++s) {
+      const cx<double> w = part[s * part_stride + t];
+      v.re += w.re;
+      v.im += w.im;
+    }
+  }
+  R[t] = cx<T>{(T)v.re, (T)v.im};
+}
+hipError_t triu_store(const double* part, int nsum, int64_t part_stride, int r, int n, int batch, void* R, DType t,
+                      hipStream_t s) {
+  const int64_t tot = (int64_t)r * n * batch;
+  if (tot == 0) return hipSuccess;
+  const dim3 g((unsigned)((tot + 255) / 256));
+  if (t == DT_F64)
+    hipLaunchKernelGGL(triu_store_kernel<double>, g, dim3(256), 0, s, (const cx<double>*)part, nsum, part_stride, r,
+                       n, batch, (cx<double>*)R);
+  else
+    hipLaunchKernelGGL(triu_store_kernel<float>, g, dim3(256), 0, s, (const cx<double>*)part, nsum, part_stride, r,
+                       n, batch, (cx<float>*)R);
+  return hipGetLastError();
+}
+
 // Phase convention: for every slice f and column j, find the entry of U_f(:, j)
 // of largest modulus (lowest row index on ties) and multiply U_f(:, j) and
 // V_f(:, j) by the conjugate of its phase, so that entry becomes real positive.

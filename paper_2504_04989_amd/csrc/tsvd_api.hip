@@ -47,11 +47,13 @@ struct Plan {
   int nsplit_blk, kchunk_blk;   // split-K for K = n1 products (block Grams, projections)
   int nsplit_g, kchunk_g;       // split-K for G = T^H T (K = n2)
   int nsplit_t, kchunk_t;       // split-K for the n2-row block Grams of Alg. 1
+  int nsplit_r, kchunk_r;       // split-K for R_f = Q_f^H A_f (T-QR, FP64 path)
+  bool tensor_op;               // T-QR / pseudoinverse: QR of A_f itself, r = b = min(n1, n2)
   int kmode;                    // Krylov-product arithmetic (KM_*) when dt == DT_F32
   int ks_ax, ks_ahy;            // K splits of the Krylov products A X and A^H Y
   size_t kpart_bytes;           // their partials (K splits or tail splits)
   // workspace offsets (bytes)
-  size_t o_canon;
+  size_t o_canon, o_rout, o_xp;
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
       o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, o_kpack,
       total;
@@ -72,6 +74,20 @@ int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
 
 int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, int prec, int op, Plan* p) {
   if (n1 < 1 || n2 < 1 || n3 < 1) return fail(TSVD_EINVAL, "n1, n2, n3 must be >= 1");
+  const bool tensor_op = op == TSVD_OP_TQR || op == TSVD_OP_TPINV;
+  if (tensor_op) {
+    // Alg. TQR / Alg. mp: the QR of every slice A_f itself (r = min(n1, n2)
+    // columns); k, b and q are not used
+    if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32)
+      return fail(TSVD_EINVAL, "T-QR and the pseudoinverse take TSVD_PREC_F64 or TSVD_PREC_F32");
+    if (op == TSVD_OP_TPINV && n1 < n2)
+      return fail(TSVD_EINVAL, "the pseudoinverse needs n1 >= n2 (slices of full column rank); for n1 < n2 use "
+                               "(X^T)^+ = (X^+)^T");
+    if (std::min(n1, n2) > 1024) return fail(TSVD_EINVAL, "min(n1, n2) must be <= 1024");
+    k = 1;
+    b = std::min(n1, n2);
+    q = 0;
+  }
   if (b < 1 || q < 0) return fail(TSVD_EINVAL, "need b >= 1 and q >= 0");
   const bool power = op == TSVD_OP_POWER || op == TSVD_OP_POWER_APPROX;
   if (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || power) {
@@ -93,8 +109,9 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
     return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
   if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32 && prec != TSVD_PREC_BF16 && prec != TSVD_PREC_BF16X3)
     return fail(TSVD_EINVAL, "unknown precision mode");
-  if (op < TSVD_OP_RBK || op > TSVD_OP_POWER_APPROX) return fail(TSVD_EINVAL, "unsupported operation");
+  if (op < TSVD_OP_RBK || op > TSVD_OP_TPINV) return fail(TSVD_EINVAL, "unsupported operation");
   p->power = power;
+  p->tensor_op = tensor_op;
   p->n1 = n1;
   p->n2 = n2;
   p->n3 = n3;
@@ -112,6 +129,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   const int64_t tm = (m + 63) / 64;
   p->nsplit_g = split_for(n2, tm * tm, F, &p->kchunk_g);
   p->nsplit_t = split_for(n2, tb * tb, F, &p->kchunk_t);
+  p->nsplit_r = split_for(n1, tb * ((n2 + 63) / 64), F, &p->kchunk_r);
   p->kmode = prec == TSVD_PREC_BF16 ? KM_BF16 : (prec == TSVD_PREC_BF16X3 ? KM_BF16X3 : KM_F32);
   int kc_unused;
   if (p->kmode != KM_BF16) {
@@ -131,9 +149,9 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   const size_t cs = p->cs;
   p->o_info = take(256);
   p->o_abar = take((size_t)F * n1 * n2 * cs);
-  p->o_obar = take((size_t)F * n2 * b * cs);
+  p->o_obar = take(tensor_op ? 0 : (size_t)F * n2 * b * cs);
   p->o_q = take((size_t)F * n1 * m * cs);
-  p->o_t = take((size_t)F * n2 * m * cs);
+  p->o_t = take(tensor_op ? 0 : (size_t)F * n2 * m * cs);
   // block scratch: n1-row Krylov blocks; Alg. 1 also orthonormalises the
   // n2-row half-step iterates A_f^H Q
   const int64_t srows = power ? std::max(n1, n2) : n1;
@@ -142,6 +160,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   size_t part = (size_t)p->nsplit_blk * F * m * b * 16;
   part = std::max(part, (size_t)p->nsplit_g * F * m * m * 16);
   if (power) part = std::max(part, (size_t)p->nsplit_t * F * b * b * 16);
+  if (tensor_op) part = std::max(part, (size_t)p->nsplit_r * F * b * n2 * 16);
   if (p->dt == DT_F32) {
     // FP64-arithmetic products on FP32 blocks: block Grams (b x b), projections
     // (i b x b and b x i b), G = T^H T (m x m)
@@ -154,6 +173,9 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
     }
     if (power) {
       part = std::max(part, ogemm_tn_part_bytes((int)b, (int)n2, (int)b, (int)F));
+    }
+    if (tensor_op) {
+      part = std::max(part, ogemm_tn_part_bytes((int)b, (int)n1, (int)n2, (int)F));
     }
   }
   p->o_part = take(part);
@@ -170,6 +192,8 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_vf = take(need_svd ? (size_t)F * n2 * k * cs : 0);
   p->o_scx = take(need_svd ? (size_t)F * k * cs : 0);
   p->o_us = take(op == TSVD_OP_APPROX || op == TSVD_OP_POWER_APPROX ? (size_t)F * n1 * k * cs : 0);
+  p->o_rout = take(tensor_op ? (size_t)F * b * n2 * cs : 0);
+  p->o_xp = take(op == TSVD_OP_TPINV ? (size_t)F * n2 * n1 * cs : 0);
   const bool bwd = op == TSVD_OP_PROJ_BWD;
   p->o_gbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
   p->o_dbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
@@ -187,6 +211,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
       if (p->ks_ax == 1) kp = std::max(kp, kgemm_part_bytes((int)n1, (int)n2, (int)b, (int)F, 1));
       if (p->ks_ahy == 1) kp = std::max(kp, kgemm_part_bytes((int)n2, (int)n1, (int)b, (int)F, 1));
     }
+    if (tensor_op) kp = 0;
     p->kpart_bytes = kp;
     p->o_kpart = take(kp);
     const bool bfm = p->dt == DT_F32 && p->kmode == KM_BF16;
@@ -788,6 +813,27 @@ int approx_tail(const Ctx& c, void* Xhat) {
   return TSVD_OK;
 }
 
+// Alg. TQR on the half spectrum: A_f -> Ā, Q_f = orthonormal basis of the
+// first r = min(n1, n2) columns of A_f (shifted CholeskyQR, the diagonal of R
+// real positive), R_f = Q_f^H A_f as FP64 partials (upper trapezoid valid).
+int tqr_core(const Ctx& c, const void* A, int* nsum) {
+  const Plan& p = c.p;
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(zero_info(c.info(), c.s));
+  }
+  {
+    Timed tm_(K_FFT_A, c.s);
+    HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  }
+  int r;
+  // first (shifted) pass straight from the leading columns of A_f (row stride n2)
+  if ((r = cholqr_pass(c, c.at(p.o_abar), p.n2, c.at(p.o_s1), p.b, true, p.n1))) return r;
+  if ((r = cholqr_finish(c, p.n1, c.at(p.o_q), p.m))) return r;
+  return inner_products(c, c.at(p.o_q), p.m, (int)p.b, c.at(p.o_abar), p.n2, (int)p.n2, p.n1, p.n1 * p.m,
+                        p.n1 * p.n2, p.nsplit_r, p.kchunk_r, c.at<double>(p.o_part), nsum);
+}
+
 // Generic batched product C = alpha opA(A) opB(B) + beta C over the F slices
 // (element strides and leading dimensions in complex elements).
 struct Op {
@@ -1020,6 +1066,78 @@ int tsvd_power_approx(const void* A, const void* Omega, int64_t n1, int64_t n2, 
   if ((r = krylov(c, A, Omega))) return r;
   if ((r = svd_and_lift(c, U, S, V))) return r;
   if ((r = approx_tail(c, Xhat))) return r;
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void* Q, void* R, void* ws,
+             size_t ws_bytes, void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, 1, 1, 0, prec, TSVD_OP_TQR, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, Q, R}, ws, ws_bytes, p))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  int nsum = 1;
+  if ((r = tqr_core(c, A, &nsum))) return r;
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(triu_store(c.at<double>(p.o_part), nsum, p.F * p.b * p.n2, (int)p.b, (int)p.n2, (int)p.F, c.at(p.o_rout),
+                      p.dt, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_q), p.n1 * p.m, Q, p.n1 * p.b, (int)p.n3, p.dt, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_rout), p.b * p.n2, R, p.b * p.n2, (int)p.n3, p.dt, c.s));
+  }
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void* X, void* ws, size_t ws_bytes,
+               void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, 1, 1, 0, prec, TSVD_OP_TPINV, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, X}, ws, ws_bytes, p))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  int nsum = 1;
+  if ((r = tqr_core(c, A, &nsum))) return r;
+  // X^+_f = R_f^{-1} Q_f^H (slices of full column rank, r = n2)
+  {
+    Timed tm_(K_CHOL, c.s);
+    HIPCHK(chol_inv_ex(c.at<double>(p.o_part), nsum, p.F * p.b * p.n2, c.at<double>(p.o_rinv), c.at(p.o_chol),
+                       (int)p.b, (int)p.F, 0.0, c.info(), c.s, 1));
+  }
+  GemmDesc d = gd();
+  d.A = c.at(p.o_rinv);
+  d.lda = p.b;
+  d.strideA = p.b * p.b;
+  d.ta = DT_F64;
+  d.B = c.at(p.o_q);
+  d.ldb = p.m;
+  d.strideB = p.n1 * p.m;
+  d.tb = p.dt;
+  d.b_conj = true;
+  d.C = c.at(p.o_xp);
+  d.ldc = p.n1;
+  d.strideC = p.n2 * p.n1;
+  d.tc = p.dt;
+  d.M = (int)p.n2;
+  d.N = (int)p.n1;
+  d.K = (int)p.b;
+  d.batch = (int)p.F;
+  d.compute = DT_F64;
+  {
+    Timed tm_(K_GEMM_LIFT, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_xp), p.n2 * p.n1, X, p.n2 * p.n1, (int)p.n3, p.dt, c.s));
+  }
   g_err.clear();
   return TSVD_OK;
 }

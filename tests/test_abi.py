@@ -101,3 +101,20 @@ def test_power_method_sizes_and_rejections():
     assert r == api.TSVD_ENOMEM
     r = L.tsvd_power(fake, fake, 10, 10, 4, 2, 3, 5000, 1, fake, fake, fake, fake, 1 << 30, nul)   # q too large
     assert r == api.TSVD_EINVAL
+
+
+def test_tensor_ops_sizes_and_rejections():
+    from paper_2504_04989_amd import api
+    assert api.workspace_bytes(30, 20, 8, 0, 0, 0, "f32", "tqr") > 0
+    assert api.workspace_bytes(20, 30, 8, 0, 0, 0, "f64", "tqr") > 0          # wide: r = n1
+    assert api.workspace_bytes(30, 20, 8, 0, 0, 0, "f64", "tpinv") > 0
+    assert api.workspace_bytes(20, 30, 8, 0, 0, 0, "f64", "tpinv") == 0        # needs n1 >= n2
+    assert "n1 >= n2" in api.lib.tsvd_last_error().decode()
+    assert api.workspace_bytes(30, 20, 8, 0, 0, 0, "bf16x3", "tqr") == 0      # FP64 / FP32 only
+    assert api.workspace_bytes(2000, 1100, 4, 0, 0, 0, "f32", "tqr") == 0     # min(n1, n2) > 1024
+    L = api.lib
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.tsvd_tqr(nul, 10, 8, 4, 1, nul, nul, nul, 0, nul) == api.TSVD_EINVAL
+    assert L.tsvd_tqr(fake, 10, 8, 4, 1, fake, fake, fake, 16, nul) == api.TSVD_ENOMEM
+    assert L.tsvd_tpinv(fake, 8, 10, 4, 1, fake, fake, 1 << 30, nul) == api.TSVD_EINVAL
