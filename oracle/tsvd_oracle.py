@@ -34,6 +34,10 @@ Pins (tests/test_oracle_*.py, all ``-m "not gpu"``):
                            diagonal, numpy QR at n3 = 1; the four Penrose
                            conditions with spatial T-products (full rank and
                            rank deficient), X^+ * X = I for full column rank
+  complete (Ex. 3)         full observation returns the data; with an exact
+                           rank-k step the objective ||X - C|| never rises;
+                           a tubal-rank-r tensor is recovered from half its
+                           entries; observed entries equal the data
   power_tsvd (Alg. 1)      n3 = 1 is the matrix randomized subspace iteration
                            (numpy QR / SVD); b = n1 gives the exact truncated
                            T-SVD; exact recovery of a tubal-rank-r tensor;
@@ -69,6 +73,9 @@ Readings (where the paper is silent / ambiguous):
       in exact arithmetic and never forms the squared spectrum; the literal
       form is kept as a cross-check (power="lit").  Alg. 1 shares Alg. 2's
       projection, small SVD, lift and rank-k truncation.
+  R20 Completion (Example 3): the iteration starts from C^(0) = T (.) M (the
+      missing entries zero), uses the same test tensor Omega in every call
+      of L, and returns C^(iters), whose observed entries equal the data.
   R19 T-QR: qr(X_f, 0) fixes Q_f and R_f only up to one unit phase per column;
       the diagonal of R_f is taken real and non-negative (unique when the
       first r = min(n1, n2) columns of X_f are independent).  For n1 < n2 the
@@ -684,6 +691,28 @@ def tpinv(X: np.ndarray) -> np.ndarray:
 def masked_loss(T: np.ndarray, M: np.ndarray, P: np.ndarray) -> float:
     """||M (.) (T - P)||_F^2, the completion data term of Ex. 3."""
     return float(np.sum((M * (T - P)) ** 2))
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5, Example 3: completion by alternating a rank-R approximation and the
+# data constraint
+# ---------------------------------------------------------------------------
+
+def complete(Mobs: np.ndarray, T: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int, iters: int,
+             alg: int = 2, history: bool = False):
+    """Completion of Example 3: C^(0) = T (.) M (reading R20); then `iters`
+    times X^(n) = L(C^(n)), the rank-k approximation of Alg. 2 (alg=2) or
+    Alg. 1 (alg=1) with test tensor Omega, and C^(n+1) = T (.) M +
+    (1 - T) (.) X^(n).  T is the 0/1 observation tensor.  Returns C^(iters)
+    (and, with history, the values ||X^(n) - C^(n)||_F)."""
+    L = rbk_approx if alg == 2 else power_approx
+    C = T * Mobs
+    hist = []
+    for _ in range(iters):
+        X = L(C, Omega, k, b, q)
+        hist.append(fro(X - C))
+        C = T * Mobs + (1.0 - T) * X
+    return (C, hist) if history else C
 
 
 # ---------------------------------------------------------------------------

@@ -15,6 +15,8 @@ Workload recipes (real tensors, C-contiguous (n1, n2, n3), tubes contiguous):
                random spectral curves, min-max scaled to [0, 1], plus noise.
   completion   T = U * V^T of tubal rank r (N(0, 1) factors) and a Bernoulli
                keep-mask; the starting point X0 = M (.) T.
+  image        power-law random fields in [0, 255] (n1 x n2 x 3), stand-ins for
+               the photographs of Example 3, with Bernoulli or line masks.
   spectrum     A = U * S * V^T with U, V orthogonal tensors (every Fourier slice
                unitary: numpy's QR of a complex Gaussian matrix, real at the DC
                and Nyquist slices) and S f-diagonal with tubes sigma_m e_1, so
@@ -172,6 +174,55 @@ def completion_problem(n1, n2, n3, r, keep, seed):
     T = _tprod_usvt(U, None, V)
     M = (rng.random((n1, n2, n3)) < keep).astype(np.float64)
     return np.ascontiguousarray(T), M, np.ascontiguousarray(M * T)
+
+
+def image_tensor(n1, n2, n3, seed, alpha=1.6):
+    """Recipe ``image``: a random image stand-in in [0, 255] with a power-law
+    spectrum.  Each channel is white Gaussian noise whose 2-D Fourier
+    amplitudes are scaled by 1 / (|f| + 1/max(n1, n2))^alpha (numpy FFT); the
+    channels are mixed by a random positive matrix so that they are
+    correlated, then the whole is min-max scaled to [0, 255].  alpha = 1.6
+    leaves about 9% relative error in the best tubal-rank-50 approximation of
+    a 512 x 768 x 3 image."""
+    rng, _ = _streams(seed)
+    fi = np.fft.fftfreq(n1)[:, None]
+    fj = np.fft.fftfreq(n2)[None, :]
+    filt = 1.0 / (np.sqrt(fi ** 2 + fj ** 2) + 1.0 / max(n1, n2)) ** alpha
+    base = np.empty((n1, n2, n3))
+    for c in range(n3):
+        z = rng.standard_normal((n1, n2))
+        base[:, :, c] = np.real(np.fft.ifft2(np.fft.fft2(z) * filt))
+    mix = 0.5 + rng.random((n3, n3))
+    img = np.einsum("ijc,dc->ijd", base, mix)
+    img = (img - img.min()) / (img.max() - img.min()) * 255.0
+    return np.ascontiguousarray(img)
+
+
+def bernoulli_mask(shape, keep, seed):
+    """0/1 observation tensor, each entry kept with probability `keep`
+    (one draw per pixel, shared by the n3 channels)."""
+    rng, _ = _streams(seed + 1000)
+    m = (rng.random(shape[:2]) < keep).astype(np.float64)
+    return np.ascontiguousarray(np.repeat(m[:, :, None], shape[2], axis=2))
+
+
+def line_mask(shape, every, seed):
+    """0/1 observation tensor with every `every`-th row and column missing,
+    starting at a random offset (structured loss, Example 3)."""
+    rng, _ = _streams(seed + 2000)
+    n1, n2, n3 = shape
+    m = np.ones((n1, n2))
+    m[int(rng.integers(0, every))::every, :] = 0.0
+    m[:, int(rng.integers(0, every))::every] = 0.0
+    return np.ascontiguousarray(np.repeat(m[:, :, None], n3, axis=2))
+
+
+# Sec. 5, Example 3: completion of 512 x 768 x 3 images with 70% of the pixels
+# missing, tubal rank 50, P = 10, q = 2 (smooth random stand-ins for the
+# missing Kodak images).
+COMPLETION_CONFIGS = {
+    "ex3_image_512x768x3": dict(n1=512, n2=768, n3=3, keep=0.3, k=50, b=60, q=2, iters=100, seed=21),
+}
 
 
 def omega(n2, b, n3, seed):

@@ -96,6 +96,14 @@ def pin_tpinv(O):
     assert np.allclose(O.tprod_bcirc(P, X), O.identity_tensor(5, 4), atol=1e-10)
 
 
+def pin_complete(O):
+    M = inputs.exact_lowrank_tensor(20, 24, 3, 2, seed=64)
+    T = inputs.bernoulli_mask(M.shape, 0.6, 64)
+    C = O.complete(M, T, inputs.omega(24, 4, 3, 64), 2, 4, 1, 60)
+    assert np.array_equal(C[T == 1], M[T == 1])
+    assert O.relative_error(M, C) < 0.1 * O.relative_error(M, T * M)
+
+
 def pin_exact_tsvd(O):
     # m = n1: Alg. 2 must equal the truncated T-SVD computed with numpy's SVD.
     n1, n2, n3, k = 20, 24, 4, 5
@@ -151,6 +159,9 @@ MUTATIONS = [
     ("tqr R without conj", "R = np.triu(Q.conj().T @ Xb[:, :, f])", "R = np.triu(Q.T @ Xb[:, :, f])", pin_tqr),
     ("tpinv conjugated", "Ch[:, :, f] = np.linalg.pinv(Xb[:, :, f])", "Ch[:, :, f] = np.linalg.pinv(Xb[:, :, f]).conj()",
      pin_tpinv),
+    ("completion merge with the mask swapped", "C = T * Mobs + (1.0 - T) * X", "C = (1.0 - T) * Mobs + T * X",
+     pin_complete),
+    ("completion never updates C", "C = T * Mobs + (1.0 - T) * X", "C = T * Mobs + 0.0 * X", pin_complete),
     ("projection without conj", "C = Q.conj().T @ Af", "C = Q.T @ Af", pin_exact_tsvd),
     ("truncation off by one", "Vf = Z[:, :k]", "Vf = Z[:, 1:k + 1]", pin_exact_tsvd),
     ("lift with conj", "Uf = Q @ W[:, :k]", "Uf = Q @ W[:, :k].conj()", pin_exact_tsvd),
