@@ -98,6 +98,8 @@ extern "C" {
 #define TSVD_OP_POWER_APPROX 5
 #define TSVD_OP_TQR 6     /* k, b, q ignored */
 #define TSVD_OP_TPINV 7   /* k, b, q ignored */
+#define TSVD_OP_COMPLETE_RBK 8    /* tsvd_complete with alg = 2 */
+#define TSVD_OP_COMPLETE_POWER 9  /* tsvd_complete with alg = 1 */
 
 /* diagnostic counters returned by tsvd_read_info (int32 each) */
 #define TSVD_INFO_CHOL_SHIFTED 0   /* shifted Cholesky passes that were needed */
@@ -187,6 +189,25 @@ int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec,
  * TSVD_PREC_F32.  Workspace: tsvd_workspace_bytes(..., TSVD_OP_TPINV). */
 int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec,
                void* X, void* ws, size_t ws_bytes, void* stream);
+
+/* Completion of Sec. 5, Example 3: alternate a rank-k approximation and the
+ * data constraint,
+ *   C^(0)   = T (.) M,
+ *   X^(n)   = Alg. 2 (alg = 2) or Alg. 1 (alg = 1) rank-k approximation of
+ *             C^(n) with test tensor Omega (the same Omega at every step),
+ *   C^(n+1) = T (.) M + (1 - T) (.) X^(n),
+ * and write C^(iters) to C (n1 x n2 x n3): observed entries equal M, missing
+ * entries come from the last approximation.
+ * M: the data (n1 x n2 x n3; entries where T is 0 are not read).  mask: T as
+ * n1 x n2 x n3 bytes in the same layout (device pointer; 0 = missing,
+ * non-zero = observed).  Omega (n2 x b x n3), k, b, q and prec as for
+ * tsvd_rbk / tsvd_power.  iters in [0, 10^6].  Workspace:
+ * tsvd_workspace_bytes(..., TSVD_OP_COMPLETE_RBK or TSVD_OP_COMPLETE_POWER).
+ * tsvd_read_info reports the counters of the last iteration. */
+int tsvd_complete(const void* M, const void* mask, const void* Omega,
+                  int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                  int64_t q, int64_t iters, int alg, int prec, void* C,
+                  void* ws, size_t ws_bytes, void* stream);
 
 /* Projection P(A) = Q * Q^T * A (n1 x n2 x n3), Q the T-orthonormal basis of
  * the block Krylov tensor of Alg. 2 (the projector of Thm. mn44 and

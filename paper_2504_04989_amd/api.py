@@ -16,12 +16,14 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 
 TSVD_OK, TSVD_EINVAL, TSVD_ENOMEM, TSVD_EHIP, TSVD_ENUMERIC = 0, 1, 2, 3, 4
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
-OP = {"rbk": 0, "approx": 1, "proj": 2, "proj_bwd": 3, "power": 4, "power_approx": 5, "tqr": 6, "tpinv": 7}
+OP = {"rbk": 0, "approx": 1, "proj": 2, "proj_bwd": 3, "power": 4, "power_approx": 5, "tqr": 6, "tpinv": 7, "complete2": 8,
+      "complete1": 9}
 INFO_NAMES = ("chol_shifted", "chol_breakdown", "eig_noconv", "nonfinite")
 INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_rbk", "tsvd_rbk_approx",
-           "tsvd_power", "tsvd_power_approx", "tsvd_tqr", "tsvd_tpinv", "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
+           "tsvd_power", "tsvd_power_approx", "tsvd_tqr", "tsvd_tpinv", "tsvd_complete",
+           "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
            "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_heig",
            "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read")
 
@@ -54,6 +56,9 @@ def _load():
     lib.tsvd_tqr.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp, vp, sz, vp]
     lib.tsvd_tpinv.restype = ctypes.c_int
     lib.tsvd_tpinv.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp, sz, vp]
+    lib.tsvd_complete.restype = ctypes.c_int
+    lib.tsvd_complete.argtypes = [vp, vp, vp, i64, i64, i64, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, vp,
+                                  sz, vp]
     lib.tsvd_proj.restype = ctypes.c_int
     lib.tsvd_proj.argtypes = [vp, vp, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, sz, vp]
     lib.tsvd_proj_backward.restype = ctypes.c_int
@@ -246,6 +251,29 @@ def tsvd_tpinv(A: torch.Tensor, prec=None, ws=None):
     X = torch.empty((n2, n1, n3), dtype=dt, device=A.device)
     _check(lib.tsvd_tpinv(_ptr(A), n1, n2, n3, PREC[prec], _ptr(X), _ptr(ws), ws.numel(), _stream(A.device)))
     return X
+
+
+def tsvd_complete(M: torch.Tensor, mask: torch.Tensor, Omega: torch.Tensor, k: int, b: int, q: int, iters: int,
+                  alg: int = 2, prec=None, ws=None):
+    """Completion of Example 3: returns C^(iters) (n1, n2, n3).  mask: bool or
+    uint8 tensor of M's shape (True / non-zero = observed)."""
+    prec = _prec_of(M, prec)
+    dt = _dtype_of(prec)
+    _check_in(M, dt, "M")
+    _check_in(Omega, dt, "Omega")
+    n1, n2, n3 = M.shape
+    if tuple(mask.shape) != tuple(M.shape) or mask.dtype not in (torch.bool, torch.uint8):
+        raise ValueError("mask must be a bool / uint8 tensor of M's shape")
+    if not mask.is_cuda or not mask.is_contiguous():
+        raise ValueError("mask must be a contiguous device tensor")
+    if tuple(Omega.shape) != (n2, b, n3):
+        raise ValueError("Omega must have shape (n2, b, n3)")
+    if ws is None:
+        ws = workspace(n1, n2, n3, k, b, q, prec, "complete2" if alg == 2 else "complete1", M.device)
+    C = torch.empty_like(M)
+    _check(lib.tsvd_complete(_ptr(M), _ptr(mask), _ptr(Omega), n1, n2, n3, k, b, q, iters, alg, PREC[prec], _ptr(C),
+                             _ptr(ws), ws.numel(), _stream(M.device)))
+    return C
 
 
 def tsvd_proj(A, Omega, b, q, prec=None, ws=None):

@@ -128,6 +128,9 @@ hipError_t scale_cols_by(const void* Uin, const double* sigma, void* Uout, int64
 // partials (spaced part_stride complex elements); zeros below the diagonal.
 hipError_t triu_store(const double* part, int nsum, int64_t part_stride, int r, int n, int batch, void* R, DType t,
                       hipStream_t s);
+// C (n elements of dtype t) = mask ? M : X (X == nullptr: 0).
+hipError_t masked_merge(const void* M, const unsigned char* mask, const void* X, void* C, int64_t n, DType t,
+                        hipStream_t s);
 hipError_t zero_info(int* info, hipStream_t s);
 
 }  // namespace tsvd

@@ -146,6 +146,31 @@ hipError_t triu_store(const double* part, int nsum, int64_t part_stride, int r, 
   return hipGetLastError();
 }
 
+// C = mask ? M : X elementwise (X == nullptr: 0), the data step of the
+// completion iteration; four elements per thread.
+template <typename T>
+__global__ void masked_merge_kernel(const T* __restrict__ M, const unsigned char* __restrict__ mask,
+                                    const T* __restrict__ X, T* __restrict__ C, int64_t n) {
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t i = i0 + u;
+    if (i < n) C[i] = mask[i] ? M[i] : (X ? X[i] : (T)0);
+  }
+}
+hipError_t masked_merge(const void* M, const unsigned char* mask, const void* X, void* C, int64_t n, DType t,
+                        hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 g((unsigned)((n + 1023) / 1024));
+  if (t == DT_F64)
+    hipLaunchKernelGGL(masked_merge_kernel<double>, g, dim3(256), 0, s, (const double*)M, mask, (const double*)X,
+                       (double*)C, n);
+  else
+    hipLaunchKernelGGL(masked_merge_kernel<float>, g, dim3(256), 0, s, (const float*)M, mask, (const float*)X,
+                       (float*)C, n);
+  return hipGetLastError();
+}
+
 // Phase convention: for every slice f and column j, find the entry of U_f(:, j)
 // of largest modulus (lowest row index on ties) and multiply U_f(:, j) and
 // V_f(:, j) by the conjugate of its phase, so that entry becomes real positive.

@@ -54,6 +54,7 @@ struct Plan {
   size_t kpart_bytes;           // their partials (K splits or tail splits)
   // workspace offsets (bytes)
   size_t o_canon, o_rout, o_xp;
+  size_t o_cbuf, o_xbuf, o_uo, o_so, o_vo;  // completion: C^(n), X^(n) and the factors of L
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
       o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, o_kpack,
       total;
@@ -74,6 +75,10 @@ int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
 
 int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, int prec, int op, Plan* p) {
   if (n1 < 1 || n2 < 1 || n3 < 1) return fail(TSVD_EINVAL, "n1, n2, n3 must be >= 1");
+  // completion (Example 3): the approximation plan of the chosen method plus
+  // the iterate buffers
+  const bool completion = op == TSVD_OP_COMPLETE_RBK || op == TSVD_OP_COMPLETE_POWER;
+  if (completion) op = op == TSVD_OP_COMPLETE_RBK ? TSVD_OP_APPROX : TSVD_OP_POWER_APPROX;
   const bool tensor_op = op == TSVD_OP_TQR || op == TSVD_OP_TPINV;
   if (tensor_op) {
     // Alg. TQR / Alg. mp: the QR of every slice A_f itself (r = min(n1, n2)
@@ -219,6 +224,12 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
                                      kgemm_bf16_pack_bytes(p->kmode, (int)n1, (int)b, (int)F))
                           : 0);
   }
+  const size_t es = p->dt == DT_F64 ? 8 : 4;
+  p->o_cbuf = take(completion ? (size_t)n1 * n2 * n3 * es : 0);
+  p->o_xbuf = take(completion ? (size_t)n1 * n2 * n3 * es : 0);
+  p->o_uo = take(completion ? (size_t)n1 * k * n3 * es : 0);
+  p->o_so = take(completion ? (size_t)k * n3 * es : 0);
+  p->o_vo = take(completion ? (size_t)n2 * k * n3 * es : 0);
   p->total = o;
   return TSVD_OK;
 }
@@ -1137,6 +1148,38 @@ int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void
   {
     Timed tm_(K_FFT_INV, c.s);
     HIPCHK(fft_c2r(c.at(p.o_xp), p.n2 * p.n1, X, p.n2 * p.n1, (int)p.n3, p.dt, c.s));
+  }
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_complete(const void* M, const void* mask, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k,
+                  int64_t b, int64_t q, int64_t iters, int alg, int prec, void* C, void* ws, size_t ws_bytes,
+                  void* stream) {
+  if (alg != 1 && alg != 2) return fail(TSVD_EINVAL, "alg must be 1 (power iteration) or 2 (block Krylov)");
+  if (iters < 0 || iters > 1000000) return fail(TSVD_EINVAL, "need 0 <= iters <= 1000000");
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, alg == 2 ? TSVD_OP_COMPLETE_RBK : TSVD_OP_COMPLETE_POWER, &p);
+  if (r) return r;
+  if ((r = check_ptrs({M, Omega, C}, ws, ws_bytes, p))) return r;
+  if (!mask) return fail(TSVD_EINVAL, "null mask");
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  const int64_t n = n1 * n2 * n3;
+  const unsigned char* T = static_cast<const unsigned char*>(mask);
+  void* Cb = c.at(p.o_cbuf);
+  {
+    // C^(0) = T (.) M
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(masked_merge(M, T, nullptr, iters == 0 ? C : Cb, n, p.dt, c.s));
+  }
+  for (int64_t it = 0; it < iters; ++it) {
+    // X^(n) = L(C^(n)): the rank-k approximation of the chosen method
+    if ((r = krylov(c, Cb, Omega))) return r;
+    if ((r = svd_and_lift(c, c.at(p.o_uo), c.at(p.o_so), c.at(p.o_vo)))) return r;
+    if ((r = approx_tail(c, c.at(p.o_xbuf)))) return r;
+    // C^(n+1) = T (.) M + (1 - T) (.) X^(n)
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(masked_merge(M, T, c.at(p.o_xbuf), it + 1 == iters ? C : Cb, n, p.dt, c.s));
   }
   g_err.clear();
   return TSVD_OK;

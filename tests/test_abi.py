@@ -118,3 +118,18 @@ def test_tensor_ops_sizes_and_rejections():
     assert L.tsvd_tqr(nul, 10, 8, 4, 1, nul, nul, nul, 0, nul) == api.TSVD_EINVAL
     assert L.tsvd_tqr(fake, 10, 8, 4, 1, fake, fake, fake, 16, nul) == api.TSVD_ENOMEM
     assert L.tsvd_tpinv(fake, 8, 10, 4, 1, fake, fake, 1 << 30, nul) == api.TSVD_EINVAL
+
+
+def test_completion_sizes_and_rejections():
+    from paper_2504_04989_amd import api
+    w2 = api.workspace_bytes(64, 96, 3, 5, 8, 2, "f32", "complete2")
+    w1 = api.workspace_bytes(64, 96, 3, 5, 8, 2, "f32", "complete1")
+    assert w2 > api.workspace_bytes(64, 96, 3, 5, 8, 2, "f32", "approx") and w1 > 0
+    L = api.lib
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    args = (fake, fake, fake, 64, 96, 3, 5, 8, 2)
+    assert L.tsvd_complete(*args, 10, 3, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL      # bad alg
+    assert L.tsvd_complete(*args, -1, 2, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL      # iters < 0
+    assert L.tsvd_complete(*args, 10, 2, 1, fake, fake, 16, nul) == api.TSVD_ENOMEM
+    assert L.tsvd_complete(fake, nul, fake, 64, 96, 3, 5, 8, 2, 10, 2, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL
