@@ -73,13 +73,13 @@ Readings (where the paper is silent / ambiguous):
       in exact arithmetic and never forms the squared spectrum; the literal
       form is kept as a cross-check (power="lit").  Alg. 1 shares Alg. 2's
       projection, small SVD, lift and rank-k truncation.
-  R20 Completion (Example 3): the iteration starts from C^(0) = T (.) M (the
-      missing entries zero), uses the same test tensor Omega in every call
-      of L, and returns C^(iters), whose observed entries equal the data.
   R19 T-QR: qr(X_f, 0) fixes Q_f and R_f only up to one unit phase per column;
       the diagonal of R_f is taken real and non-negative (unique when the
       first r = min(n1, n2) columns of X_f are independent).  For n1 < n2 the
       economy QR orthonormalises the first n1 columns and R_f = Q_f^H X_f.
+  R20 Completion (Example 3): the iteration starts from C^(0) = T (.) M (the
+      missing entries zero), uses the same test tensor Omega in every call
+      of L, and returns C^(iters), whose observed entries equal the data.
 """
 from __future__ import annotations
 
