@@ -207,13 +207,37 @@ def bernoulli_mask(shape, keep, seed):
 
 
 def line_mask(shape, every, seed):
-    """0/1 observation tensor with every `every`-th row and column missing,
-    starting at a random offset (structured loss, Example 3)."""
+    """0/1 observation tensor with line segments missing on every `every`-th
+    row and column (random offset): each segment covers a random 20-60% of
+    its row or column (structured loss, Example 3).  Whole missing rows or
+    columns would be unrecoverable by any low-rank model: a row with no
+    observed entry stays zero in every rank-k approximation."""
     rng, _ = _streams(seed + 2000)
     n1, n2, n3 = shape
     m = np.ones((n1, n2))
-    m[int(rng.integers(0, every))::every, :] = 0.0
-    m[:, int(rng.integers(0, every))::every] = 0.0
+    for i in range(int(rng.integers(0, every)), n1, every):
+        ln = int(rng.uniform(0.2, 0.6) * n2)
+        j0 = int(rng.integers(0, n2 - ln + 1))
+        m[i, j0:j0 + ln] = 0.0
+    for j in range(int(rng.integers(0, every)), n2, every):
+        ln = int(rng.uniform(0.2, 0.6) * n1)
+        i0 = int(rng.integers(0, n1 - ln + 1))
+        m[i0:i0 + ln, j] = 0.0
+    return np.ascontiguousarray(np.repeat(m[:, :, None], n3, axis=2))
+
+
+def circle_mask(shape, count, seed, rmin=10.0, rmax=60.0, width=2.0):
+    """0/1 observation tensor with `count` random circles missing: rings of
+    radius U[rmin, rmax] and the given width around uniformly placed centres
+    (structured loss, Example 3)."""
+    rng, _ = _streams(seed + 3000)
+    n1, n2, n3 = shape
+    i = np.arange(n1, dtype=np.float64)[:, None]
+    j = np.arange(n2, dtype=np.float64)[None, :]
+    m = np.ones((n1, n2))
+    for _ in range(count):
+        ci, cj, r = rng.uniform(0, n1), rng.uniform(0, n2), rng.uniform(rmin, rmax)
+        m[np.abs(np.sqrt((i - ci) ** 2 + (j - cj) ** 2) - r) < width / 2] = 0.0
     return np.ascontiguousarray(np.repeat(m[:, :, None], n3, axis=2))
 
 

@@ -51,4 +51,11 @@ def test_image_recipe_and_masks():
     m = inputs.bernoulli_mask(X.shape, 0.3, 65)
     assert abs(m.mean() - 0.3) < 0.02 and np.array_equal(m[:, :, 0], m[:, :, 2])
     L = inputs.line_mask(X.shape, 8, 65)
-    assert 0.7 < L.mean() < 0.8
+    assert 0.85 < L.mean() < 0.98 and L[:, :, 0].min(axis=1).max() == 1.0
+    assert L[:, :, 0].max(axis=1).min() == 1.0 and L[:, :, 0].max(axis=0).min() == 1.0   # no empty row / column
+
+
+def test_circle_mask():
+    m = inputs.circle_mask((128, 160, 3), 12, 66)
+    assert 0.5 < m.mean() < 0.99 and np.array_equal(m[:, :, 0], m[:, :, 1])
+    assert set(np.unique(m)) <= {0.0, 1.0}
