@@ -218,6 +218,32 @@ def completion_runs(api, inputs):
             "runs": res}
 
 
+def tqr_runs(api, inputs, steps: int, warmup: int):
+    """T-QR (Alg. TQR) and the T-pseudoinverse (Alg. mp) of a tall Gaussian
+    tensor, FP32, input resident: ms per call and the rate over the
+    algorithmic HBM traffic (read A, write Q and R, or A^+)."""
+    import torch
+    n1, n2, n3 = 4096, 256, 64
+    A = torch.from_numpy(inputs.random_tensor((n1, n2, n3), 81).astype(np.float32)).to("cuda")
+    res = {}
+    for op, fn, out_elems in (("tqr", api.tsvd_tqr, n1 * n2 * n3 + n2 * n2 * n3),
+                              ("tpinv", api.tsvd_tpinv, n2 * n1 * n3)):
+        ws = api.workspace(n1, n2, n3, 0, 0, 0, "f32", op, "cuda")
+        for _ in range(warmup):
+            fn(A, "f32", ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn(A, "f32", ws=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        gb = 4.0 * (n1 * n2 * n3 + out_elems) / 1e9
+        res[op] = {"ms_per_call": ms, "algorithmic_GB": gb, "GB_per_s": gb / (ms * 1e-3)}
+        log(f"[bench] {op} {n1}x{n2}x{n3} f32: {ms:.3f} ms per call ({gb / (ms * 1e-3):.0f} GB/s algorithmic)")
+        del ws
+    return {"workload": f"Gaussian {n1} x {n2} x {n3}, f32", "calls": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +255,7 @@ def main():
     ap.add_argument("--cpu-slices", type=int, default=1)
     ap.add_argument("--no-alg1", action="store_true", help="skip the Alg. 1 vs Alg. 2 comparison (Example 1)")
     ap.add_argument("--no-completion", action="store_true", help="skip the completion runs (Example 3)")
+    ap.add_argument("--no-tqr", action="store_true", help="skip the T-QR / T-pseudoinverse timing")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -332,6 +359,7 @@ def main():
 
     alg12 = None if args.no_alg1 else compare_alg1_alg2(api, inputs, max(args.steps // 2, 3), 1)
     compl = None if args.no_completion else completion_runs(api, inputs)
+    tqr = None if args.no_tqr else tqr_runs(api, inputs, max(args.steps // 2, 3), 1)
 
     ok = [p for p in precs if legs[p].get("rel_err_vs_oracle", 0.0) <= RELERR_GATE]
     best = max(ok or precs, key=lambda p: legs[p]["value"])
@@ -361,6 +389,8 @@ def main():
         res["alg1_vs_alg2"] = alg12
     if compl is not None:
         res["completion"] = compl
+    if tqr is not None:
+        res["tqr_tpinv"] = tqr
     if base is not None:
         res["cpu_baseline"] = base
     print(json.dumps(res), flush=True)

@@ -48,7 +48,8 @@ struct Plan {
   int nsplit_g, kchunk_g;       // split-K for G = T^H T (K = n2)
   int nsplit_t, kchunk_t;       // split-K for the n2-row block Grams of Alg. 1
   int nsplit_r, kchunk_r;       // split-K for R_f = Q_f^H A_f (T-QR, FP64 path)
-  bool tensor_op;               // T-QR / pseudoinverse: QR of A_f itself, r = b = min(n1, n2)
+  bool tensor_op;               // T-QR / pseudoinverse: QR of A_f itself, r = m = min(n1, n2) in
+                                // q + 1 column panels of width b <= 128
   int kmode;                    // Krylov-product arithmetic (KM_*) when dt == DT_F32
   int ks_ax, ks_ahy;            // K splits of the Krylov products A X and A^H Y
   size_t kpart_bytes;           // their partials (K splits or tail splits)
@@ -89,9 +90,15 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
       return fail(TSVD_EINVAL, "the pseudoinverse needs n1 >= n2 (slices of full column rank); for n1 < n2 use "
                                "(X^T)^+ = (X^+)^T");
     if (std::min(n1, n2) > 1024) return fail(TSVD_EINVAL, "min(n1, n2) must be <= 1024");
+    // the r = min(n1, n2) columns are orthonormalised in equal panels of at
+    // most 128 columns (block Gram-Schmidt twice against the earlier panels,
+    // shifted CholeskyQR per panel, as for the Krylov blocks)
+    const int64_t r = std::min(n1, n2);
+    int64_t npan = (r + 127) / 128;
+    while (r % npan) ++npan;
     k = 1;
-    b = std::min(n1, n2);
-    q = 0;
+    b = r / npan;
+    q = npan - 1;
   }
   if (b < 1 || q < 0) return fail(TSVD_EINVAL, "need b >= 1 and q >= 0");
   const bool power = op == TSVD_OP_POWER || op == TSVD_OP_POWER_APPROX;
@@ -134,7 +141,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   const int64_t tm = (m + 63) / 64;
   p->nsplit_g = split_for(n2, tm * tm, F, &p->kchunk_g);
   p->nsplit_t = split_for(n2, tb * tb, F, &p->kchunk_t);
-  p->nsplit_r = split_for(n1, tb * ((n2 + 63) / 64), F, &p->kchunk_r);
+  p->nsplit_r = split_for(n1, ((m + 63) / 64) * ((n2 + 63) / 64), F, &p->kchunk_r);
   p->kmode = prec == TSVD_PREC_BF16 ? KM_BF16 : (prec == TSVD_PREC_BF16X3 ? KM_BF16X3 : KM_F32);
   int kc_unused;
   if (p->kmode != KM_BF16) {
@@ -165,7 +172,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   size_t part = (size_t)p->nsplit_blk * F * m * b * 16;
   part = std::max(part, (size_t)p->nsplit_g * F * m * m * 16);
   if (power) part = std::max(part, (size_t)p->nsplit_t * F * b * b * 16);
-  if (tensor_op) part = std::max(part, (size_t)p->nsplit_r * F * b * n2 * 16);
+  if (tensor_op) part = std::max(part, (size_t)p->nsplit_r * F * m * n2 * 16);
   if (p->dt == DT_F32) {
     // FP64-arithmetic products on FP32 blocks: block Grams (b x b), projections
     // (i b x b and b x i b), G = T^H T (m x m)
@@ -180,12 +187,14 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
       part = std::max(part, ogemm_tn_part_bytes((int)b, (int)n2, (int)b, (int)F));
     }
     if (tensor_op) {
-      part = std::max(part, ogemm_tn_part_bytes((int)b, (int)n1, (int)n2, (int)F));
+      part = std::max(part, ogemm_tn_part_bytes((int)m, (int)n1, (int)n2, (int)F));
     }
   }
   p->o_part = take(part);
-  p->o_rinv = take((size_t)F * b * b * 16);
-  p->o_chol = take(chol_uses_lds(b) ? 0 : (size_t)F * b * (b + 1) / 2 * 16);
+  // the pseudoinverse inverts the whole r x r factor R_f (r = m)
+  const int64_t rb = op == TSVD_OP_TPINV ? m : b;
+  p->o_rinv = take((size_t)F * rb * rb * 16);
+  p->o_chol = take(chol_uses_lds(rb) ? 0 : (size_t)F * rb * (rb + 1) / 2 * 16);
   const bool need_svd = (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || power);
   p->o_lam = take(need_svd ? (size_t)F * k * 8 : 0);
   p->o_sig = take(need_svd ? (size_t)F * k * 8 : 0);
@@ -197,7 +206,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_vf = take(need_svd ? (size_t)F * n2 * k * cs : 0);
   p->o_scx = take(need_svd ? (size_t)F * k * cs : 0);
   p->o_us = take(op == TSVD_OP_APPROX || op == TSVD_OP_POWER_APPROX ? (size_t)F * n1 * k * cs : 0);
-  p->o_rout = take(tensor_op ? (size_t)F * b * n2 * cs : 0);
+  p->o_rout = take(tensor_op ? (size_t)F * m * n2 * cs : 0);
   p->o_xp = take(op == TSVD_OP_TPINV ? (size_t)F * n2 * n1 * cs : 0);
   const bool bwd = op == TSVD_OP_PROJ_BWD;
   p->o_gbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
@@ -825,8 +834,11 @@ int approx_tail(const Ctx& c, void* Xhat) {
 }
 
 // Alg. TQR on the half spectrum: A_f -> Ā, Q_f = orthonormal basis of the
-// first r = min(n1, n2) columns of A_f (shifted CholeskyQR, the diagonal of R
-// real positive), R_f = Q_f^H A_f as FP64 partials (upper trapezoid valid).
+// first r = min(n1, n2) columns of A_f, one b-column panel after the other
+// (each projected off the earlier panels and orthonormalised by shifted
+// CholeskyQR, so span Q_f(:, 1:j) = span A_f(:, 1:j) at every panel end and
+// the diagonal of R is real positive), R_f = Q_f^H A_f as FP64 partials
+// (upper trapezoid valid).
 int tqr_core(const Ctx& c, const void* A, int* nsum) {
   const Plan& p = c.p;
   {
@@ -838,10 +850,17 @@ int tqr_core(const Ctx& c, const void* A, int* nsum) {
     HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, p.dt, c.s));
   }
   int r;
-  // first (shifted) pass straight from the leading columns of A_f (row stride n2)
-  if ((r = cholqr_pass(c, c.at(p.o_abar), p.n2, c.at(p.o_s1), p.b, true, p.n1))) return r;
-  if ((r = cholqr_finish(c, p.n1, c.at(p.o_q), p.m))) return r;
-  return inner_products(c, c.at(p.o_q), p.m, (int)p.b, c.at(p.o_abar), p.n2, (int)p.n2, p.n1, p.n1 * p.m,
+  for (int i = 0; i <= p.q; ++i) {
+    // panel i of A_f (row stride n2) into the staging block, then as a Krylov block
+    {
+      Timed tm_(K_MISC, c.s);
+      HIPCHK(hipMemcpy2DAsync(c.at(p.o_s0), (size_t)p.b * p.cs,
+                              c.at<unsigned char>(p.o_abar) + (size_t)i * p.b * p.cs, (size_t)p.n2 * p.cs,
+                              (size_t)p.b * p.cs, (size_t)(p.F * p.n1), hipMemcpyDeviceToDevice, c.s));
+    }
+    if ((r = orth_block(c, i))) return r;
+  }
+  return inner_products(c, c.at(p.o_q), p.m, (int)p.m, c.at(p.o_abar), p.n2, (int)p.n2, p.n1, p.n1 * p.m,
                         p.n1 * p.n2, p.nsplit_r, p.kchunk_r, c.at<double>(p.o_part), nsum);
 }
 
@@ -1092,16 +1111,16 @@ int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void* 
   if ((r = tqr_core(c, A, &nsum))) return r;
   {
     Timed tm_(K_MISC, c.s);
-    HIPCHK(triu_store(c.at<double>(p.o_part), nsum, p.F * p.b * p.n2, (int)p.b, (int)p.n2, (int)p.F, c.at(p.o_rout),
+    HIPCHK(triu_store(c.at<double>(p.o_part), nsum, p.F * p.m * p.n2, (int)p.m, (int)p.n2, (int)p.F, c.at(p.o_rout),
                       p.dt, c.s));
   }
   {
     Timed tm_(K_FFT_INV, c.s);
-    HIPCHK(fft_c2r(c.at(p.o_q), p.n1 * p.m, Q, p.n1 * p.b, (int)p.n3, p.dt, c.s));
+    HIPCHK(fft_c2r(c.at(p.o_q), p.n1 * p.m, Q, p.n1 * p.m, (int)p.n3, p.dt, c.s));
   }
   {
     Timed tm_(K_FFT_INV, c.s);
-    HIPCHK(fft_c2r(c.at(p.o_rout), p.b * p.n2, R, p.b * p.n2, (int)p.n3, p.dt, c.s));
+    HIPCHK(fft_c2r(c.at(p.o_rout), p.m * p.n2, R, p.m * p.n2, (int)p.n3, p.dt, c.s));
   }
   g_err.clear();
   return TSVD_OK;
@@ -1119,13 +1138,13 @@ int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void
   // X^+_f = R_f^{-1} Q_f^H (slices of full column rank, r = n2)
   {
     Timed tm_(K_CHOL, c.s);
-    HIPCHK(chol_inv_ex(c.at<double>(p.o_part), nsum, p.F * p.b * p.n2, c.at<double>(p.o_rinv), c.at(p.o_chol),
-                       (int)p.b, (int)p.F, 0.0, c.info(), c.s, 1));
+    HIPCHK(chol_inv_ex(c.at<double>(p.o_part), nsum, p.F * p.m * p.n2, c.at<double>(p.o_rinv), c.at(p.o_chol),
+                       (int)p.m, (int)p.F, 0.0, c.info(), c.s, 1));
   }
   GemmDesc d = gd();
   d.A = c.at(p.o_rinv);
-  d.lda = p.b;
-  d.strideA = p.b * p.b;
+  d.lda = p.m;
+  d.strideA = p.m * p.m;
   d.ta = DT_F64;
   d.B = c.at(p.o_q);
   d.ldb = p.m;
@@ -1138,7 +1157,7 @@ int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void
   d.tc = p.dt;
   d.M = (int)p.n2;
   d.N = (int)p.n1;
-  d.K = (int)p.b;
+  d.K = (int)p.m;
   d.batch = (int)p.F;
   d.compute = DT_F64;
   {
