@@ -1090,6 +1090,16 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Value of v held by lane j (j uniform across the wave): two v_readlane_b32.
+// The dependent chains of the inverse iteration walk through a 64-entry chunk
+// that the lanes fetched from LDS in parallel, at register latency.
+__device__ __forceinline__ double lane_get(double v, int j) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double hash_uniform(uint32_t a, uint32_t b) {
   uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
   h ^= h >> 15;
@@ -1140,66 +1150,120 @@ __global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned 
   const double tinyp = eps * fmax(tnorm, 1e-300);
   for (int t = t0; t < t1; ++t) {
     const double lv = lam[t];
-    if (lane == 0) {
+    {
+      // pivoted LU of T - lambda I (the recurrence runs, uniform, in every
+      // lane; lane j keeps step base + j of the factors for the chunk store)
       double pc = d[0] - lv, qc = (m > 1) ? e[0] : 0.0, rc = 0.0;
-      for (int i = 0; i < m - 1; ++i) {
-        const double ei = e[i];
-        const double an = d[i + 1] - lv;
-        const double en = (i + 1 < m - 1) ? e[i + 1] : 0.0;
-        if (fabs(pc) >= fabs(ei)) {
-          double piv = pc;
-          if (fabs(piv) < tinyp) piv = copysign(tinyp, piv == 0.0 ? 1.0 : piv);
-          const double mu = ei / piv;
-          u0[i] = piv;
-          u1[i] = qc;
-          u2[i] = rc;
-          mult[i] = mu;
-          swp[i] = 0.0;
-          pc = an - mu * qc;
-          qc = en - mu * rc;
-          rc = 0.0;
-        } else {
-          const double mu = pc / ei;
-          u0[i] = ei;
-          u1[i] = an;
-          u2[i] = en;
-          mult[i] = mu;
-          swp[i] = 1.0;
-          const double npc = qc - mu * an;
-          const double nqc = rc - mu * en;
-          pc = npc;
-          qc = nqc;
-          rc = 0.0;
+      for (int base = 0; base < m - 1; base += 64) {
+        const int i = base + lane;
+        const int cnt = min(64, m - 1 - base);
+        const double ei_l = i < m - 1 ? e[i] : 0.0;
+        const double an_l = i < m - 1 ? d[i + 1] - lv : 0.0;
+        const double en_l = i + 1 < m - 1 ? e[i + 1] : 0.0;
+        double o0 = 1.0, o1 = 0.0, o2 = 0.0, om = 0.0, os = 0.0;
+        for (int j = 0; j < cnt; ++j) {
+          const double ei = lane_get(ei_l, j);
+          const double an = lane_get(an_l, j);
+          const double en = lane_get(en_l, j);
+          double r0, r1, r2, rm, rs;
+          if (fabs(pc) >= fabs(ei)) {
+            double piv = pc;
+            if (fabs(piv) < tinyp) piv = copysign(tinyp, piv == 0.0 ? 1.0 : piv);
+            const double mu = ei / piv;
+            r0 = piv;
+            r1 = qc;
+            r2 = rc;
+            rm = mu;
+            rs = 0.0;
+            pc = an - mu * qc;
+            qc = en - mu * rc;
+            rc = 0.0;
+          } else {
+            const double mu = pc / ei;
+            r0 = ei;
+            r1 = an;
+            r2 = en;
+            rm = mu;
+            rs = 1.0;
+            const double npc = qc - mu * an;
+            const double nqc = rc - mu * en;
+            pc = npc;
+            qc = nqc;
+            rc = 0.0;
+          }
+          if (lane == j) {
+            o0 = r0;
+            o1 = r1;
+            o2 = r2;
+            om = rm;
+            os = rs;
+          }
+        }
+        if (lane < cnt) {
+          u0[i] = 1.0 / o0;  // the solves multiply by the reciprocal pivots
+          u1[i] = o1;
+          u2[i] = o2;
+          mult[i] = om;
+          swp[i] = os;
         }
       }
       if (fabs(pc) < tinyp) pc = copysign(tinyp, pc == 0.0 ? 1.0 : pc);
-      u0[m - 1] = pc;
-      u1[m - 1] = 0.0;
-      u2[m - 1] = 0.0;
-      for (int i = 0; i < m; ++i) u0[i] = 1.0 / u0[i];  // the solves multiply by the reciprocal pivots
+      if (lane == 0) {
+        u0[m - 1] = 1.0 / pc;
+        u1[m - 1] = 0.0;
+        u2[m - 1] = 0.0;
+      }
     }
     for (int i = lane; i < m; i += 64) z[i] = hash_uniform((uint32_t)t, (uint32_t)i);
     wave_sync();
     for (int it = 0; it < 4; ++it) {
-      if (lane == 0) {
+      {
+        // forward elimination with the row swaps and multipliers, then back
+        // substitution; the chains run uniform in every lane over 64-entry
+        // chunks fetched in parallel, lane j keeping result base + j
         double zc = z[0];
-        for (int i = 0; i < m - 1; ++i) {
-          double zn = z[i + 1];
-          if (swp[i] != 0.0) {
-            const double tmp = zc;
-            zc = zn;
-            zn = tmp;
+        for (int base = 0; base < m - 1; base += 64) {
+          const int i = base + lane;
+          const int cnt = min(64, m - 1 - base);
+          const double zn_l = i < m - 1 ? z[i + 1] : 0.0;
+          const double sw_l = i < m - 1 ? swp[i] : 0.0;
+          const double mu_l = i < m - 1 ? mult[i] : 0.0;
+          double out = 0.0;
+          for (int j = 0; j < cnt; ++j) {
+            double zn = lane_get(zn_l, j);
+            if (lane_get(sw_l, j) != 0.0) {
+              const double tmp = zc;
+              zc = zn;
+              zn = tmp;
+            }
+            if (lane == j) out = zc;
+            zc = zn - lane_get(mu_l, j) * zc;
           }
-          z[i] = zc;
-          zc = zn - mult[i] * zc;
+          wave_sync();
+          if (lane < cnt) z[i] = out;
+          wave_sync();
         }
-        z[m - 1] = zc;
+        if (lane == 0) z[m - 1] = zc;
+        wave_sync();
         double z1 = 0.0, z2 = 0.0;
-        for (int i = m - 1; i >= 0; --i) {
-          const double v = (z[i] - u1[i] * z1 - u2[i] * z2) * u0[i];
-          z[i] = v;
-          z2 = z1;
-          z1 = v;
+        for (int top = m; top > 0; top -= 64) {
+          const int base = top > 64 ? top - 64 : 0;
+          const int cnt = top - base;
+          const int i = base + lane;
+          const bool ok = lane < cnt;
+          const double zi_l = ok ? z[i] : 0.0;
+          const double a0 = ok ? u0[i] : 0.0;
+          const double a1 = ok ? u1[i] : 0.0;
+          const double a2 = ok ? u2[i] : 0.0;
+          double out = 0.0;
+          for (int j = cnt - 1; j >= 0; --j) {
+            const double v = (lane_get(zi_l, j) - lane_get(a1, j) * z1 - lane_get(a2, j) * z2) * lane_get(a0, j);
+            if (lane == j) out = v;
+            z2 = z1;
+            z1 = v;
+          }
+          wave_sync();
+          if (ok) z[i] = out;
         }
       }
       wave_sync();
