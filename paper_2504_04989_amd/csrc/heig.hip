@@ -1090,6 +1090,12 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Waves (eigenvectors) per workgroup of the inverse iteration at most; each
+// holds 6 m doubles of LU factors and iterate in LDS.
+#ifndef TSVD_INVIT_NW
+#define TSVD_INVIT_NW 2
+#endif
+
 // Value of v held by lane j (j uniform across the wave): two v_readlane_b32.
 // The dependent chains of the inverse iteration walk through a 64-entry chunk
 // that the lanes fetched from LDS in parallel, at register latency.
@@ -1562,7 +1568,7 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
   }
   // 3. eigenvectors: per-wave LU workspace of 6 m doubles in LDS
   int nw = (int)((140 * 1024 - 16 * (size_t)m) / (48 * (size_t)m));
-  if (nw > 4) nw = 4;
+  if (nw > TSVD_INVIT_NW) nw = TSVD_INVIT_NW;
   if (nw < 1) nw = 1;
   const size_t sm3 = (size_t)2 * m * sizeof(double) + (size_t)nw * 6 * m * sizeof(double);
   if (stages & HEIG_INVIT) {
