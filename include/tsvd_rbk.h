@@ -100,6 +100,7 @@ extern "C" {
 #define TSVD_OP_TPINV 7   /* k, b, q ignored */
 #define TSVD_OP_COMPLETE_RBK 8    /* tsvd_complete with alg = 2 */
 #define TSVD_OP_COMPLETE_POWER 9  /* tsvd_complete with alg = 1 */
+#define TSVD_OP_RBK_LITERAL 10    /* tsvd_rbk_literal */
 
 /* diagnostic counters returned by tsvd_read_info (int32 each) */
 #define TSVD_INFO_CHOL_SHIFTED 0   /* shifted Cholesky passes that were needed */
@@ -145,6 +146,22 @@ int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2,
                     int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
                     void* U, void* S, void* V, void* Xhat, void* ws,
                     size_t ws_bytes, void* stream);
+
+/* Alg. 2 with the Krylov blocks exactly as the algorithm writes them:
+ * K_0 = A_f Om_f and K_i = A_f (A_f^H K_{i-1}), none orthonormalised before
+ * the next product, then the T-QR of K = [K_0 .. K_q] (block by block, the
+ * same span as one QR of K), C_f, small SVD, lift and phase as tsvd_rbk.  In
+ * exact arithmetic it equals tsvd_rbk; in floating point each raw block K_i
+ * carries only the directions whose sigma_j / sigma_1 exceeds about the
+ * working precision to the power 1 / (2i + 1), so the later blocks add less
+ * than tsvd_rbk's orthonormalised recursion does.  Offered for comparison.  The raw blocks grow like sigma_1^(2i): A should be
+ * scaled so that sigma_1^(2q+1) stays within the working precision's range.
+ * Xhat (n1 x n2 x n3) may be NULL; otherwise it receives U * S * V^T.
+ * Workspace: tsvd_workspace_bytes(..., TSVD_OP_RBK_LITERAL). */
+int tsvd_rbk_literal(const void* A, const void* Omega, int64_t n1, int64_t n2,
+                     int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
+                     void* U, void* S, void* V, void* Xhat, void* ws,
+                     size_t ws_bytes, void* stream);
 
 /* Alg. 1: classical randomized subspace method with q power iterations.
  * Same arguments, layouts and outputs as tsvd_rbk, but the basis Q_f

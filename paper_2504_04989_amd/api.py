@@ -17,12 +17,13 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 TSVD_OK, TSVD_EINVAL, TSVD_ENOMEM, TSVD_EHIP, TSVD_ENUMERIC = 0, 1, 2, 3, 4
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 OP = {"rbk": 0, "approx": 1, "proj": 2, "proj_bwd": 3, "power": 4, "power_approx": 5, "tqr": 6, "tpinv": 7, "complete2": 8,
-      "complete1": 9}
+      "complete1": 9, "literal": 10}
 INFO_NAMES = ("chol_shifted", "chol_breakdown", "eig_noconv", "nonfinite")
 INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_rbk", "tsvd_rbk_approx",
            "tsvd_power", "tsvd_power_approx", "tsvd_tqr", "tsvd_tpinv", "tsvd_complete",
+           "tsvd_rbk_literal",
            "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
            "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_heig",
            "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read")
@@ -56,6 +57,8 @@ def _load():
     lib.tsvd_tqr.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp, vp, sz, vp]
     lib.tsvd_tpinv.restype = ctypes.c_int
     lib.tsvd_tpinv.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp, sz, vp]
+    lib.tsvd_rbk_literal.restype = ctypes.c_int
+    lib.tsvd_rbk_literal.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, vp, sz, vp]
     lib.tsvd_complete.restype = ctypes.c_int
     lib.tsvd_complete.argtypes = [vp, vp, vp, i64, i64, i64, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, vp,
                                   sz, vp]
@@ -180,6 +183,28 @@ def tsvd_rbk_approx(A, Omega, k, b, q, prec=None, ws=None):
     X = torch.empty((n1, n2, n3), dtype=dt, device=dev)
     _check(lib.tsvd_rbk_approx(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S), _ptr(V),
                                _ptr(X), _ptr(ws), ws.numel(), _stream(dev)))
+    return U, S, V, X
+
+
+def tsvd_rbk_literal(A, Omega, k, b, q, prec=None, ws=None, approx=True):
+    """Alg. 2 with the literal Krylov powers (no orthonormalisation between
+    steps): returns (U, S, V, X_hat) (X_hat None when approx is False)."""
+    prec = _prec_of(A, prec)
+    dt = _dtype_of(prec)
+    _check_in(A, dt, "A")
+    _check_in(Omega, dt, "Omega")
+    n1, n2, n3 = A.shape
+    if tuple(Omega.shape) != (n2, b, n3):
+        raise ValueError("Omega must have shape (n2, b, n3)")
+    dev = A.device
+    if ws is None:
+        ws = workspace(n1, n2, n3, k, b, q, prec, "literal", dev)
+    U = torch.empty((n1, k, n3), dtype=dt, device=dev)
+    S = torch.empty((k, n3), dtype=dt, device=dev)
+    V = torch.empty((n2, k, n3), dtype=dt, device=dev)
+    X = torch.empty((n1, n2, n3), dtype=dt, device=dev) if approx else None
+    _check(lib.tsvd_rbk_literal(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S), _ptr(V),
+                                _ptr(X), _ptr(ws), ws.numel(), _stream(dev)))
     return U, S, V, X
 
 

@@ -80,6 +80,8 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   // the iterate buffers
   const bool completion = op == TSVD_OP_COMPLETE_RBK || op == TSVD_OP_COMPLETE_POWER;
   if (completion) op = op == TSVD_OP_COMPLETE_RBK ? TSVD_OP_APPROX : TSVD_OP_POWER_APPROX;
+  // literal Krylov powers: the buffers of the approximation
+  if (op == TSVD_OP_RBK_LITERAL) op = TSVD_OP_APPROX;
   const bool tensor_op = op == TSVD_OP_TQR || op == TSVD_OP_TPINV;
   if (tensor_op) {
     // Alg. TQR / Alg. mp: the QR of every slice A_f itself (r = min(n1, n2)
@@ -675,6 +677,49 @@ int krylov(const Ctx& c, const void* A, const void* Omega, bool keep_raw = false
   return big_AhY(c, Q + col, p.m, p.n1 * p.m, T + col, p.m, p.n2 * p.m, (int)p.b);
 }
 
+// Alg. 2 with the Krylov blocks exactly as written, K_0 = A_f Om_f,
+// K_i = A_f (A_f^H K_{i-1}), none orthonormalised before the next product;
+// then the T-QR of K = [K_0 .. K_q], block by block (each block projected off
+// the earlier ones twice and orthonormalised by shifted CholeskyQR, the same
+// span as one QR of K), and C_f^H = A_f^H Q_f.
+int krylov_literal(const Ctx& c, const void* A, const void* Omega) {
+  const Plan& p = c.p;
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(zero_info(c.info(), c.s));
+  }
+  {
+    Timed tm_(K_FFT_A, c.s);
+    HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  }
+  {
+    Timed tm_(K_FFT_OMEGA, c.s);
+    HIPCHK(fft_r2c(Omega, c.at(p.o_obar), p.n2 * p.b, (int)p.n3, p.dt, c.s));
+  }
+  unsigned char* Q = c.at<unsigned char>(p.o_q);
+  unsigned char* T = c.at<unsigned char>(p.o_t);
+  int r;
+  if ((r = big_AX(c, c.at(p.o_obar), p.b, p.n2 * p.b, Q, p.m, p.n1 * p.m, (int)p.b))) return r;
+  for (int i = 1; i <= p.q; ++i) {
+    const size_t prev = (size_t)(i - 1) * p.b * p.cs, col = (size_t)i * p.b * p.cs;
+    if ((r = big_AhY(c, Q + prev, p.m, p.n1 * p.m, T + prev, p.m, p.n2 * p.m, (int)p.b))) return r;
+    if ((r = big_AX(c, T + prev, p.m, p.n2 * p.m, Q + col, p.m, p.n1 * p.m, (int)p.b))) return r;
+  }
+  for (int i = 0; i <= p.q; ++i) {
+    {
+      Timed tm_(K_MISC, c.s);
+      HIPCHK(hipMemcpy2DAsync(c.at(p.o_s0), (size_t)p.b * p.cs, Q + (size_t)i * p.b * p.cs, (size_t)p.m * p.cs,
+                              (size_t)p.b * p.cs, (size_t)(p.F * p.n1), hipMemcpyDeviceToDevice, c.s));
+    }
+    if ((r = orth_block(c, i))) return r;
+  }
+  for (int i = 0; i <= p.q; ++i) {
+    const size_t col = (size_t)i * p.b * p.cs;
+    if ((r = big_AhY(c, Q + col, p.m, p.n1 * p.m, T + col, p.m, p.n2 * p.m, (int)p.b))) return r;
+  }
+  return TSVD_OK;
+}
+
 // Small SVD of C_f = T_f^H via G = T^H T, lift, phase, inverse DFT.
 int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   const Plan& p = c.p;
@@ -1096,6 +1141,22 @@ int tsvd_power_approx(const void* A, const void* Omega, int64_t n1, int64_t n2, 
   if ((r = krylov(c, A, Omega))) return r;
   if ((r = svd_and_lift(c, U, S, V))) return r;
   if ((r = approx_tail(c, Xhat))) return r;
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_rbk_literal(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                     int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
+                     void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_RBK_LITERAL, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, Omega, U, S, V}, ws, ws_bytes, p))) return r;
+  if (Xhat && !aligned(Xhat, 16)) return fail(TSVD_EINVAL, "misaligned (16 B) Xhat");
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = krylov_literal(c, A, Omega))) return r;
+  if ((r = svd_and_lift(c, U, S, V))) return r;
+  if (Xhat && (r = approx_tail(c, Xhat))) return r;
   g_err.clear();
   return TSVD_OK;
 }

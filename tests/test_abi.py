@@ -133,3 +133,16 @@ def test_completion_sizes_and_rejections():
     assert L.tsvd_complete(*args, -1, 2, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL      # iters < 0
     assert L.tsvd_complete(*args, 10, 2, 1, fake, fake, 16, nul) == api.TSVD_ENOMEM
     assert L.tsvd_complete(fake, nul, fake, 64, 96, 3, 5, 8, 2, 10, 2, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL
+
+
+def test_literal_sizes_and_rejections():
+    from paper_2504_04989_amd import api
+    w = api.workspace_bytes(64, 64, 16, 5, 10, 2, "f64", "literal")
+    assert w == api.workspace_bytes(64, 64, 16, 5, 10, 2, "f64", "approx") > 0
+    L = api.lib
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.tsvd_rbk_literal(fake, fake, 10, 10, 4, 2, 4, 2, 1, fake, fake, fake, nul, fake, 1 << 30, nul) \
+        == api.TSVD_EINVAL                                                   # m = 12 > 10
+    assert L.tsvd_rbk_literal(fake, fake, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, nul, fake, 16, nul) \
+        == api.TSVD_ENOMEM
