@@ -131,6 +131,14 @@ hipError_t triu_store(const double* part, int nsum, int64_t part_stride, int r, 
 // C (n elements of dtype t) = mask ? M : X (X == nullptr: 0).
 hipError_t masked_merge(const void* M, const unsigned char* mask, const void* X, void* C, int64_t n, DType t,
                         hipStream_t s);
+// Second pass of the FP64 small SVD: the number J of the first pass's top-k
+// eigenpairs (lam1, W1: m x k per slice) kept per slice, with W1m = W1 whose
+// columns from J on are cleared; and the merge of the kept pairs with the
+// second pass's (lam2, W2) into lambda and W (m x k).
+hipError_t tail_split(const double* lam1, const void* W1, void* W1m, int m, int k, int batch, double tau,
+                      double min_ratio, int* J, hipStream_t s);
+hipError_t tail_merge(const double* lam1, const void* W1, const double* lam2, const void* W2, const int* J, int m,
+                      int k, int batch, double* lam, void* W, hipStream_t s);
 hipError_t zero_info(int* info, hipStream_t s);
 
 }  // namespace tsvd

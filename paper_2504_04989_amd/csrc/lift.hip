@@ -171,6 +171,69 @@ hipError_t masked_merge(const void* M, const unsigned char* mask, const void* X,
   return hipGetLastError();
 }
 
+// Second pass of the FP64 small SVD.  tail_split: per slice, the number J of
+// leading eigenpairs of the first pass that are kept: the largest J < k with
+// lambda_{J-1} >= tau lambda_0 and lambda_{J-1} / lambda_J >= min_ratio (no
+// such J: J = k, the first pass is kept whole); W1m = W1 with the columns
+// from J on cleared.
+__global__ void tail_split_kernel(const double* __restrict__ lam1, const cx<double>* __restrict__ W1,
+                                  cx<double>* __restrict__ W1m, int m, int k, double tau, double min_ratio,
+                                  int* __restrict__ J) {
+  __shared__ int js;
+  const int f = blockIdx.x;
+  if (threadIdx.x == 0) {
+    const double* l = lam1 + (int64_t)f * k;
+    int best = 0;
+    for (int j = 1; j < k; ++j) {
+      const double a = l[j - 1], bj = l[j];
+      if (a >= tau * l[0] && (bj <= 0.0 || a >= min_ratio * bj)) best = j;
+    }
+    if (best == 0) best = k;
+    js = best;
+    J[f] = best;
+  }
+  __syncthreads();
+  const int jf = js;
+  const int64_t per = (int64_t)m * k;
+  for (int64_t e = threadIdx.x; e < per; e += blockDim.x) {
+    const int c = (int)(e % k);
+    W1m[(int64_t)f * per + e] = c < jf ? W1[(int64_t)f * per + e] : cx<double>{0.0, 0.0};
+  }
+}
+hipError_t tail_split(const double* lam1, const void* W1, void* W1m, int m, int k, int batch, double tau,
+                      double min_ratio, int* J, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tail_split_kernel, dim3(batch), dim3(256), 0, s, lam1, (const cx<double>*)W1, (cx<double>*)W1m,
+                     m, k, tau, min_ratio, J);
+  return hipGetLastError();
+}
+
+// merge: column c of the result takes the first pass's eigenpair c when
+// c < J, else the second pass's eigenpair c - J.
+__global__ void tail_merge_kernel(const double* __restrict__ lam1, const cx<double>* __restrict__ W1,
+                                  const double* __restrict__ lam2, const cx<double>* __restrict__ W2,
+                                  const int* __restrict__ J, int m, int k, int batch, double* __restrict__ lam,
+                                  cx<double>* __restrict__ W) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)m * k;
+  if (t >= per * batch) return;
+  const int f = (int)(t / per);
+  const int64_t e = t % per;
+  const int r = (int)(e / k), c = (int)(e % k);
+  const int jf = J[f];
+  const int64_t base = (int64_t)f * per + (int64_t)r * k;
+  W[t] = c < jf ? W1[base + c] : W2[base + (c - jf)];
+  if (r == 0) lam[(int64_t)f * k + c] = c < jf ? lam1[(int64_t)f * k + c] : lam2[(int64_t)f * k + (c - jf)];
+}
+hipError_t tail_merge(const double* lam1, const void* W1, const double* lam2, const void* W2, const int* J, int m,
+                      int k, int batch, double* lam, void* W, hipStream_t s) {
+  const int64_t tot = (int64_t)m * k * batch;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(tail_merge_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, lam1,
+                     (const cx<double>*)W1, lam2, (const cx<double>*)W2, J, m, k, batch, lam, (cx<double>*)W);
+  return hipGetLastError();
+}
+
 // Phase convention: for every slice f and column j, find the entry of U_f(:, j)
 // of largest modulus (lowest row index on ties) and multiply U_f(:, j) and
 // V_f(:, j) by the conjugate of its phase, so that entry becomes real positive.

@@ -56,6 +56,7 @@ struct Plan {
   // workspace offsets (bytes)
   size_t o_canon, o_rout, o_xp;
   size_t o_cbuf, o_xbuf, o_uo, o_so, o_vo;  // completion: C^(n), X^(n) and the factors of L
+  size_t o_lam1, o_w1, o_w1m, o_p, o_t1, o_lam2, o_w2, o_rk, o_split;  // FP64 small SVD, second pass
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
       o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, o_kpack,
       total;
@@ -204,6 +205,16 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_wds = take(need_svd ? (size_t)F * m * k * 16 : 0);
   p->o_heig = take(need_svd ? (size_t)F * heig_scratch_bytes((int)m, (int)k) : 0);
   p->o_canon = take(need_svd ? canon_scratch_bytes(n1, (int)k, (int)F) : 0);
+  const bool pass2 = need_svd && p->dt == DT_F64;
+  p->o_lam1 = take(pass2 ? (size_t)F * k * 8 : 0);
+  p->o_w1 = take(pass2 ? (size_t)F * m * k * 16 : 0);
+  p->o_w1m = take(pass2 ? (size_t)F * m * k * 16 : 0);
+  p->o_p = take(pass2 ? (size_t)F * n2 * k * 16 : 0);
+  p->o_t1 = take(pass2 ? (size_t)F * n2 * m * 16 : 0);
+  p->o_lam2 = take(pass2 ? (size_t)F * k * 8 : 0);
+  p->o_w2 = take(pass2 ? (size_t)F * m * k * 16 : 0);
+  p->o_rk = take(pass2 ? (size_t)F * k * k * 16 : 0);
+  p->o_split = take(pass2 ? (size_t)F * 4 : 0);
   p->o_uf = take(need_svd ? (size_t)F * n1 * k * cs : 0);
   p->o_vf = take(need_svd ? (size_t)F * n2 * k * cs : 0);
   p->o_scx = take(need_svd ? (size_t)F * k * cs : 0);
@@ -736,10 +747,91 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
   double* Wd = c.at<double>(p.o_wd);
   const int stage_cls[4][2] = {
       {HEIG_TRIDIAG, K_HEIG_TRI}, {HEIG_BISECT, K_HEIG_BISECT}, {HEIG_INVIT, K_HEIG_INVIT}, {HEIG_BACKXF, K_HEIG_BACKXF}};
-  for (const auto& sc : stage_cls) {
-    Timed tm_(sc[1], c.s);
-    HIPCHK(heig_topk(part, nsum_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
-                     c.info(), c.s, sc[0], upper));
+  if (dt == DT_F32) {
+    for (const auto& sc : stage_cls) {
+      Timed tm_(sc[1], c.s);
+      HIPCHK(heig_topk(part, nsum_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam, Wd, c.at(p.o_heig),
+                       c.info(), c.s, sc[0], upper));
+    }
+  } else {
+    // FP64: the eigenvalues of the Gram carry an absolute error of order
+    // m u lambda_0, which leaves sigma_j below about sqrt(m u) sigma_0
+    // unresolved.  The first pass keeps its J leading eigenpairs (above
+    // 1e-9 lambda_0 and a gap); the second pass projects them out of C^H,
+    // T1 = T (I - W_J W_J^H), and takes the top eigenpairs of T1^H T1, whose
+    // absolute error scales with the much smaller norm of the rest; they are
+    // projected off W_J once more and fill the columns from J on.
+    double* lam1 = c.at<double>(p.o_lam1);
+    double* W1 = c.at<double>(p.o_w1);
+    for (const auto& sc : stage_cls) {
+      Timed tm_(sc[1], c.s);
+      HIPCHK(heig_topk(part, nsum_g, p.F * p.m * p.m, (int)p.m, (int)p.k, (int)p.F, lam1, W1, c.at(p.o_heig),
+                       c.info(), c.s, sc[0], false));
+    }
+    int* J = c.at<int>(p.o_split);
+    void* W1m = c.at(p.o_w1m);
+    {
+      Timed tm_(K_MISC, c.s);
+      HIPCHK(tail_split(lam1, W1, W1m, (int)p.m, (int)p.k, (int)p.F, 1e-9, 1.5, J, c.s));
+    }
+    auto z64 = [&](const void* A, int64_t lda, int64_t sa, bool ac, const void* B, int64_t ldb, int64_t sb, bool bc,
+                   void* C, int64_t ldc, int64_t sc, int M, int N, int K, double alpha, double beta) -> int {
+      GemmDesc d = gd();
+      d.A = A;
+      d.lda = lda;
+      d.strideA = sa;
+      d.ta = DT_F64;
+      d.a_conj = ac;
+      d.B = B;
+      d.ldb = ldb;
+      d.strideB = sb;
+      d.tb = DT_F64;
+      d.b_conj = bc;
+      d.C = C;
+      d.ldc = ldc;
+      d.strideC = sc;
+      d.tc = DT_F64;
+      d.M = M;
+      d.N = N;
+      d.K = K;
+      d.batch = (int)p.F;
+      d.alpha = alpha;
+      d.beta = beta;
+      d.compute = DT_F64;
+      Timed tm_(K_GEMM_LIFT, c.s);
+      HIPCHK(zgemm(d, c.s));
+      return TSVD_OK;
+    };
+    const int im = (int)p.m, ik = (int)p.k, in2 = (int)p.n2;
+    void* P = c.at(p.o_p);
+    void* T1 = c.at(p.o_t1);
+    // P = T W1m (n2 x k); T1 = T - P W1m^H (n2 x m)
+    if ((r = z64(T, p.m, p.n2 * p.m, false, W1m, p.k, p.m * p.k, false, P, p.k, p.n2 * p.k, in2, ik, im, 1.0, 0.0)))
+      return r;
+    HIPCHK(hipMemcpyAsync(T1, T, (size_t)p.F * p.n2 * p.m * 16, hipMemcpyDeviceToDevice, c.s));
+    if ((r = z64(P, p.k, p.n2 * p.k, false, W1m, p.k, p.m * p.k, true, T1, p.m, p.n2 * p.m, in2, im, ik, -1.0, 1.0)))
+      return r;
+    int nsum2 = 1;
+    r = inner_products(c, T1, p.m, im, T1, p.m, im, p.n2, p.n2 * p.m, p.n2 * p.m, p.nsplit_g, p.kchunk_g, part,
+                       &nsum2, K_GEMM_LIFT);
+    if (r) return r;
+    double* lam2 = c.at<double>(p.o_lam2);
+    double* W2 = c.at<double>(p.o_w2);
+    for (const auto& sc : stage_cls) {
+      Timed tm_(sc[1], c.s);
+      HIPCHK(heig_topk(part, nsum2, p.F * p.m * p.m, im, ik, (int)p.F, lam2, W2, c.at(p.o_heig), c.info(), c.s,
+                       sc[0], false));
+    }
+    // W2 -= W1m (W1m^H W2)
+    void* Rk = c.at(p.o_rk);
+    if ((r = z64(W1m, p.k, p.m * p.k, true, W2, p.k, p.m * p.k, false, Rk, p.k, p.k * p.k, ik, ik, im, 1.0, 0.0)))
+      return r;
+    if ((r = z64(W1m, p.k, p.m * p.k, false, Rk, p.k, p.k * p.k, false, W2, p.k, p.m * p.k, im, ik, ik, -1.0, 1.0)))
+      return r;
+    {
+      Timed tm_(K_MISC, c.s);
+      HIPCHK(tail_merge(lam1, W1, lam2, W2, J, im, ik, (int)p.F, lam, Wd, c.s));
+    }
   }
   if (dt == DT_F32) {
     // FP32 lift products on the Krylov-product kernel (FP32 MFMA, FP32

@@ -108,15 +108,11 @@ def test_block_krylov_not_worse_than_power_iteration_gpu():
         assert abs(e1 - e1o) <= 1e-10 * e1o and abs(e2 - e2o) <= 1e-10 * e2o
 
 
-# Resolution of the FP64 small SVD on the GPU: the eigenvalues of the FP64
-# Gram G_f = C_f C_f^H carry an absolute error of order m u ||G_f||, so a
-# singular value sqrt(lambda) is resolved to about sqrt(m u) sigma_1
-# (1.3e-7 sigma_1 for m = 150).  Example 1 asks for sigma_45 / sigma_1 =
-# 5e-9 (m^-5), 1e-10 (m^-6) and 3e-14 (0.5^m), below that floor: there the
-# GPU results are checked against the floor, not to 1e-10.
-GRAM_FLOOR = 2e-7
-
-
+# Example 1 asks for sigma_45 / sigma_1 = 5e-9 (m^-5), 1e-10 (m^-6) and 3e-14
+# (0.5^m), below what one eigendecomposition of the FP64 Gram C_f C_f^H
+# resolves (about sqrt(m u) sigma_1); the second pass of the FP64 small SVD
+# (the leading eigenpairs projected out, the rest solved again) brings the GPU
+# to the oracle's accuracy, which these checks hold it to.
 @pytest.mark.parametrize("name", ["ex1_pow5_256", "ex1_pow6_256", "ex1_geom05_256"])
 def test_example1_full_size_sampled_slices(name):
     A, Om, c = inputs.make_config(name)
@@ -136,7 +132,9 @@ def test_example1_full_size_sampled_slices(name):
     e1, e2 = rel_f(X1[3], A), rel_f(X2[3], A)
     print(f"[power] {name}: alg1 {e1:.6e} alg2 {e2:.6e} optimum {opt:.6e}", flush=True)
     for e in (e1, e2):
-        assert opt * (1 - 1e-6) - 1e-14 <= e <= opt + GRAM_FLOOR
+        assert opt * (1 - 1e-6) - 1e-14 <= e <= opt * (1 + 1e-3) + 1e-12
+    # Sec. 3: Alg. 2 is not worse than Alg. 1 (up to the rounding level)
+    assert e2 <= e1 * (1 + 1e-6) + 1e-12
     freqs = [0, 1, 77, 128]
     Ab = np.fft.fft(A, axis=2)[:, :, freqs]
     for out, slices in ((X1, O.power_slices), (X2, O.rbk_slices)):
@@ -145,16 +143,13 @@ def test_example1_full_size_sampled_slices(name):
         Sb = np.fft.fft(S, axis=1)[:, freqs]
         Xb = np.fft.fft(X, axis=2)[:, :, freqs]
         for j, f in enumerate(freqs):
-            # singular values against the exact spectrum the input is built
-            # with: an eigenvalue error of GRAM_FLOOR^2 sigma_1^2 moves sigma_j
-            # by GRAM_FLOOR^2 sigma_1^2 / (2 sigma_j), at most GRAM_FLOOR sigma_1
+            # singular values against the exact spectrum the input is built with
             s = sig[:k]
-            bound = 1e-10 * s + np.minimum(GRAM_FLOOR * sig[0], GRAM_FLOOR ** 2 * sig[0] ** 2 / s)
-            ds = np.abs(Sb[:, j].real - s)
+            ds = np.max(np.abs(Sb[:, j].real - s))
             assert np.max(np.abs(sl["Sf"][:, j] - s)) <= 1e-10 * sig[0]
             Xo = (sl["Uf"][:, :, j] * sl["Sf"][:, j]) @ sl["Vf"][:, :, j].conj().T
             d = np.linalg.norm(Xb[:, :, j] - Xo) / np.linalg.norm(Ab[:, :, j])
-            print(f"[power] {name} {slices.__name__} f={f}: sigma err / bound {np.max(ds / bound):.2e}, "
+            print(f"[power] {name} {slices.__name__} f={f}: max sigma err {ds / sig[0]:.2e} sigma_1, "
                   f"X_hat slice diff {d:.3e}", flush=True)
-            assert np.all(ds <= bound)
-            assert d <= GRAM_FLOOR
+            assert ds <= 1e-10 * sig[0]
+            assert d <= 1e-10
