@@ -227,3 +227,15 @@ def test_config5_fp32_full_size_sampled_slices():
     """4096 x 4096 x 64 tensor of tubal rank 400, k = 100, b = 110, q = 3, FP32:
     DC, an interior slice and Nyquist."""
     _sampled_slices("c5_fp32_4096x4096x64", [0, 14, 32], 1e-5, "c5")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape,k,b,q", [
+    ((300, 260, 2), 20, 150, 0),     # b > 128: the Cholesky's unblocked form
+    ((320, 300, 1), 10, 140, 1),     # and with a projection against the first block, m = 280
+])
+def test_wide_blocks(shape, k, b, q, prec):
+    n1, n2, n3 = shape
+    A = inputs.lowrank_tensor(n1, n2, n3, 60, ("geom", 0.9), 1e-3, 95)
+    Om = inputs.omega(n2, b, n3, 95)
+    _compare(A, Om, k, b, q, prec, factors=False)
