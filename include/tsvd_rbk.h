@@ -64,7 +64,9 @@
  * earlier blocks, application of R^{-1}) and G_f = C_f C_f^H use FP64
  * arithmetic on the stored values in every mode; the lift (U_f = Q_f W_k,
  * V_f = C_f^H W_k / sigma) and the adjoint's other products use the storage
- * type's arithmetic.
+ * type's arithmetic.  With TSVD_PREC_F64 the small SVD takes a second pass
+ * (the leading eigenpairs of G_f projected out, the rest solved again) so
+ * that singular values far below sqrt(u) sigma_1 keep FP64 accuracy.
  */
 #ifndef TSVD_RBK_H
 #define TSVD_RBK_H
