@@ -285,6 +285,194 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
   }
 }
 
+// TN product of a square block with itself, upper triangle only, N <= 120
+// (the block Grams): with one 64-row tile per wave the upper-triangle skip
+// leaves the waves unequal (14, 12, 10, 8 thin tiles for N = 110, and a second
+// row tile of mostly padding).  Here wave w owns the row groups w and 7 - w
+// (16 rows each), 2 tt - 14 <= 16 thin tiles in all, and one workgroup per
+// slice and split covers the whole triangle.  Accumulator slot s holds thin
+// tile s of group w when 2 w <= s < tt, else the next tile of group 7 - w.
+__global__ __launch_bounds__(256, 2) void ogemm_tn_pair_kernel(const OArgs a) {
+  constexpr int TT = 16;
+  constexpr int ROWS = TT * 16;
+  constexpr int BUF = ROWS * OSTRIDE;
+  constexpr int NCH = TT * 8;
+  constexpr int TEL = OKSTEP * NCH / 256;
+  extern __shared__ __align__(16) double olds[];
+
+  const int id = blockIdx.x;
+  const int t = (id & 7) * a.per + (id >> 3);
+  if (t >= a.total) return;
+  const int sp = t % a.nsplit;
+  const int f = t / a.nsplit;
+  const int kb = sp * a.kchunk;
+  const int ke = min(a.K, kb + a.kchunk);
+  const int nc = a.N;
+  const int tt = (2 * nc + 15) / 16;
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: slot choices branch on scalars
+  const int q4 = lane >> 4, r16 = lane & 15;
+  const float* Xf = a.X + (int64_t)f * a.strideX;
+  const int ga = wave, gb = 7 - wave;
+  const int cola = 16 * ga + r16, colb = 16 * gb + r16;
+  const bool oka = cola < a.M, okb = colb < a.M;
+  const int cla = oka ? cola : a.M - 1, clb = okb ? colb : a.M - 1;
+
+  auto load_big = [&](int k0, int col, bool ok, bool full, float (&v)[4]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int i = k0 + 2 * q4 + c;
+      float2 x = make_float2(0.f, 0.f);
+      if (ok && (full || i < ke)) x = *reinterpret_cast<const float2*>(Xf + (int64_t)i * a.lx + 2 * col);
+      v[2 * c] = x.x;
+      v[2 * c + 1] = x.y;
+    }
+  };
+  auto load_big_full = [&](int k0, int col, float (&v)[4]) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const float2 x = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + 2 * q4 + c) * a.lx + 2 * col);
+      v[2 * c] = x.x;
+      v[2 * c + 1] = x.y;
+    }
+  };
+  // full steps: every load issued, unconditionally, so that the next step's
+  // loads stay in flight across this step's MFMAs.  Padding columns nn >= N
+  // read column N - 1 instead of zeros: a thin row only reaches the output
+  // rows it forms itself, and rows n >= N are never stored.
+  auto load_thin_full = [&](int k0, double2 (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % OKSTEP, nn = min(idx / OKSTEP, nc - 1);
+      const int64_t off = (int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + nn;
+      const float2 y = reinterpret_cast<const float2*>(a.B)[off];
+      x[e] = make_double2((double)y.x, (double)y.y);
+    }
+  };
+  auto load_thin = [&](int k0, double2 (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % OKSTEP, nn = idx / OKSTEP;
+      double2 v = make_double2(0.0, 0.0);
+      if (k0 + kk < ke && nn < nc) {
+        const int64_t off = (int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + nn;
+        const float2 y = reinterpret_cast<const float2*>(a.B)[off];
+        v = make_double2((double)y.x, (double)y.y);
+      }
+      x[e] = v;
+    }
+  };
+  auto store_thin = [&](double* buf, const double2 (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % OKSTEP, nn = idx / OKSTEP;
+      const double xr = x[e].x, xi = x[e].y;
+      double* row0 = buf + (2 * nn) * OSTRIDE + 2 * kk;
+      double* row1 = row0 + OSTRIDE;
+      *reinterpret_cast<double2*>(row0) = make_double2(xr, xi);
+      *reinterpret_cast<double2*>(row1) = make_double2(xi, -xr);
+    }
+  };
+  // slot s -> (group b?, thin tile); tile >= tt: unused slot
+  auto slot_tile = [&](int s, bool& useb) {
+    if (s >= 2 * ga && s < tt) {
+      useb = false;
+      return s;
+    }
+    useb = true;
+    const int idx = s < 2 * ga ? s : 2 * ga + (s - tt);
+    return 2 * gb + idx;
+  };
+
+  f64x4 acc[TT];
+#pragma unroll
+  for (int i = 0; i < TT; ++i) acc[i] = f64x4{0.0, 0.0, 0.0, 0.0};
+  auto compute = [&](const double* buf, const float (&va)[4], const float (&vb)[4]) {
+    // register vectors, selected whole (a select between two arrays would
+    // become a select between their addresses, i.e. private memory)
+    const f64x4 dav = {(double)va[0], (double)va[1], (double)va[2], (double)va[3]};
+    const f64x4 dbv = {(double)vb[0], (double)vb[1], (double)vb[2], (double)vb[3]};
+#pragma unroll
+    for (int s = 0; s < TT; ++s) {
+      bool useb;
+      const int tile = slot_tile(s, useb);
+      if (tile < tt) {
+        const double* rowp = buf + (16 * tile + r16) * OSTRIDE + 4 * q4;
+        const double2 w0 = *reinterpret_cast<const double2*>(rowp);
+        const double2 w1 = *reinterpret_cast<const double2*>(rowp + 2);
+        const double w[4] = {w0.x, w0.y, w1.x, w1.y};
+        const f64x4 bv = useb ? dbv : dav;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(w[bb], bv[bb], acc[s], 0, 0, 0);
+      }
+    }
+  };
+
+  const int nfull = (ke - kb) / OKSTEP;
+  const bool tail = kb + nfull * OKSTEP < ke;
+  float cura[4], curb[4], nxta[4], nxtb[4];
+  double2 tx[TEL];
+  if (nfull > 0) {
+    load_big_full(kb, cla, cura);
+    load_big_full(kb, clb, curb);
+    load_thin_full(kb, tx);
+    store_thin(olds, tx);
+  }
+  __syncthreads();
+  for (int s = 0; s < nfull; ++s) {
+    const int sn = s + 1 < nfull ? s + 1 : s;
+    load_thin_full(kb + sn * OKSTEP, tx);
+    load_big_full(kb + sn * OKSTEP, cla, nxta);
+    load_big_full(kb + sn * OKSTEP, clb, nxtb);
+    compute(olds + (s & 1) * BUF, cura, curb);
+    if (s + 1 < nfull) store_thin(olds + ((s + 1) & 1) * BUF, tx);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cura[j] = nxta[j];
+      curb[j] = nxtb[j];
+    }
+  }
+  if (tail) {
+    const int k0 = kb + nfull * OKSTEP;
+    load_thin(k0, tx);
+    store_thin(olds + (nfull & 1) * BUF, tx);
+    load_big(k0, cla, oka, false, cura);
+    load_big(k0, clb, okb, false, curb);
+    __syncthreads();
+    compute(olds + (nfull & 1) * BUF, cura, curb);
+  }
+
+  // lanes q4 and q4 ^ 1 hold the real and the imaginary parts of the same
+  // columns (same row pair): one exchange, then whole complex numbers
+  const bool odd = q4 & 1;
+#pragma unroll
+  for (int s = 0; s < TT; ++s) {
+    bool useb;
+    const int tile = slot_tile(s, useb);
+    if (tile >= tt) continue;
+    double other[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) other[rr] = __shfl_xor(acc[s][rr], 16, 64);
+    const int col = useb ? colb : cola;
+    if (!(useb ? okb : oka)) continue;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rr = odd ? 2 + h : h;
+      const double re = odd ? other[rr] : acc[s][rr];
+      const double im = odd ? acc[s][rr] : other[rr];
+      const int n = 8 * tile + (q4 >> 1) + 2 * rr;
+      if (n >= a.N) continue;
+      double2* out = static_cast<double2*>(a.C) + (((int64_t)sp * a.batch + f) * a.M * a.N + (int64_t)col * a.N + n);
+      *out = make_double2(re, im);
+    }
+  }
+}
+
 // part[e] = sum_s part[s * total + e] in a fixed order (slot 0 in place).
 __global__ void opart_reduce_kernel(double2* part, int nsplit, int64_t total) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -396,8 +584,34 @@ int ogemm_tn_split(int M, int K, int N, int batch, bool upper) {
   return best;
 }
 
+namespace {
+
+// Split of the paired upper-triangle kernel (one workgroup per slice and
+// split): the same makespan model.
+int ogemm_tn_pair_split(int K, int batch) {
+  const int64_t slots = ogemm_slots();
+  int best = 1;
+  double bcost = 1e300;
+  for (int ns = 1; ns <= 32; ++ns) {
+    int kc = (K + ns - 1) / ns;
+    kc = (kc + OKSTEP - 1) / OKSTEP * OKSTEP;
+    if (ns > 1 && kc < 16 * OKSTEP) break;
+    const int nsx = (K + kc - 1) / kc;
+    const int64_t rounds = ((int64_t)batch * nsx + slots - 1) / slots;
+    const double cost = (double)rounds * (kc / OKSTEP + 6) + (nsx > 1 ? 0.5 * nsx : 0.0);
+    if (cost < bcost - 1e-9) {
+      bcost = cost;
+      best = nsx;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
 size_t ogemm_tn_part_bytes(int M, int K, int N, int batch) {
-  const int ns = std::max(ogemm_tn_split(M, K, N, batch, false), ogemm_tn_split(M, K, N, batch, true));
+  int ns = std::max(ogemm_tn_split(M, K, N, batch, false), ogemm_tn_split(M, K, N, batch, true));
+  if (M == N && N > 64 && N <= 120) ns = std::max(ns, ogemm_tn_pair_split(K, batch));
   return (size_t)ns * batch * M * N * 16;
 }
 
@@ -424,8 +638,31 @@ hipError_t ogemm_tn(const float* X, int64_t lx, int64_t strideX, const float* Y,
   a.xvec = 0;
   a.upper = (upper && M == N) ? 1 : 0;
   const int TT = othin_tiles(N);
-  fill_grid(a, TT);
-  hipError_t e = olaunch<true>(a, TT, s);
+  hipError_t e;
+  if (a.upper && N > 64 && N <= 120) {
+    a.nsplit = ogemm_tn_pair_split(K, batch);
+    kc = (K + a.nsplit - 1) / a.nsplit;
+    kc = (kc + OKSTEP - 1) / OKSTEP * OKSTEP;
+    a.kchunk = kc < OKSTEP ? OKSTEP : kc;
+    a.nsplit = (K + a.kchunk - 1) / a.kchunk;
+    a.nbig = 1;
+    a.nthin = 1;
+    a.total = a.nsplit * batch;
+    a.per = (a.total + 7) / 8;
+    const size_t lds = (size_t)2 * 16 * 16 * OSTRIDE * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)ogemm_tn_pair_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+      (void)hipGetLastError();
+      attr = true;
+    }
+    hipLaunchKernelGGL(ogemm_tn_pair_kernel, dim3(8 * a.per), dim3(256), lds, s, a);
+    e = hipGetLastError();
+  } else {
+    fill_grid(a, TT);
+    e = olaunch<true>(a, TT, s);
+  }
   if (e != hipSuccess || a.nsplit <= 1) return e;
   const int64_t total = (int64_t)batch * M * N;
   const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
