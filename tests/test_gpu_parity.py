@@ -239,3 +239,18 @@ def test_wide_blocks(shape, k, b, q, prec):
     A = inputs.lowrank_tensor(n1, n2, n3, 60, ("geom", 0.9), 1e-3, 95)
     Om = inputs.omega(n2, b, n3, 95)
     _compare(A, Om, k, b, q, prec, factors=False)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+@pytest.mark.parametrize("shape,k,b,q", [
+    ((203, 150, 6), 20, 65, 1),      # 65-column blocks, n1 = 203 (a ragged K step in every block Gram)
+    ((250, 261, 3), 20, 120, 0),     # 120-column blocks, and m = 120: the Gram of C too, over n2 = 261
+])
+def test_mid_blocks(shape, k, b, q, prec):
+    # blocks of 64 < b <= 120 columns on FP32 storage: the block Grams (and,
+    # at m <= 120, the Gram of C) take the square upper-triangle product that
+    # pairs the row groups w and 7 - w of each wave
+    n1, n2, n3 = shape
+    A = inputs.lowrank_tensor(n1, n2, n3, 60, ("geom", 0.9), 1e-3, 96)
+    Om = inputs.omega(n2, b, n3, 96)
+    _compare(A, Om, k, b, q, prec, factors=False)

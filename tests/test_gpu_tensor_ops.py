@@ -38,6 +38,7 @@ CASES = [
     ((60, 1, 5), "f64"),                # r = 1
     ((300, 150, 4), "f64"),             # r > 128: unblocked Cholesky
     ((1200, 200, 2), "f32"),            # r > 128, FP32
+    ((333, 120, 3), "f32"),             # one 120-column panel over a ragged n1
 ]
 
 
