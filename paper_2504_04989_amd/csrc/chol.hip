@@ -378,7 +378,11 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
         tile_inverse(D, lane);  // D <- X_KK = L_KK^{-1}
       }
       __syncthreads();
-      // panel: A_IK <- A_IK X_KK^H (one tile per wave at a time)
+      // panel: A_IK <- A_IK X_KK^H (one tile per wave at a time).  The
+      // triangular tiles hold exact zeros above the diagonal, so every inner
+      // product below runs over all 16 terms: the extra terms add exact
+      // zeros after (or before) the nonzero ones, and the fixed trip count
+      // lets the loads of a whole row issue at once.
       for (int I = K + 1 + wave; I < NT; I += CB_W) {
         cx<double>* P = L + tix(I, K);
         cx<double> out[4];
@@ -386,7 +390,8 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
         for (int u = 0; u < 4; ++u) {
           const int e = lane + 64 * u, r = e >> 4, c = e & 15;
           cx<double> acc{0.0, 0.0};
-          for (int k = 0; k <= c; ++k) acc = cmadc(acc, P[r * TRS + k], D[c * TRS + k]);
+#pragma unroll
+          for (int k = 0; k < TSZ; ++k) acc = cmadc(acc, P[r * TRS + k], D[c * TRS + k]);
           out[u] = acc;
         }
         wsync();
@@ -447,8 +452,9 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
         for (int K = J; K < I; ++K) {
           const cx<double>* LI = L + tix(I, K);
           const cx<double>* XK = L + tix(K, J);
-          const int kmin = (K == J) ? c : 0;  // X_JJ is lower triangular
-          for (int k = kmin; k < TSZ; ++k) acc = cmad(acc, LI[r * TRS + k], XK[k * TRS + c]);
+          // X_JJ (K == J) is lower triangular, its zeros stored
+#pragma unroll
+          for (int k = 0; k < TSZ; ++k) acc = cmad(acc, LI[r * TRS + k], XK[k * TRS + c]);
         }
         sreg[slot][u] = acc;
       }
@@ -476,7 +482,8 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
       for (int u = 0; u < 4; ++u) {
         const int e = lane + 64 * u, r = e >> 4, c = e & 15;
         cx<double> acc{0.0, 0.0};
-        for (int k = 0; k <= r; ++k) acc = cmad(acc, XI[r * TRS + k], S[k * TRS + c]);
+#pragma unroll
+        for (int k = 0; k < TSZ; ++k) acc = cmad(acc, XI[r * TRS + k], S[k * TRS + c]);
         sreg[slot][u] = cx<double>{-acc.re, -acc.im};
       }
     }
