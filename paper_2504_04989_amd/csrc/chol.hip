@@ -383,16 +383,17 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
       // product below runs over all 16 terms: the extra terms add exact
       // zeros after (or before) the nonzero ones, and the fixed trip count
       // lets the loads of a whole row issue at once.
+      // Lane (q, c) forms rows r = 4 u + q of column c: the column operand is
+      // read once per k for its four rows.
+      const int q = lane >> 4, c = lane & 15;
       for (int I = K + 1 + wave; I < NT; I += CB_W) {
         cx<double>* P = L + tix(I, K);
-        cx<double> out[4];
+        cx<double> out[4] = {};
+#pragma unroll 4
+        for (int k = 0; k < TSZ; ++k) {
+          const cx<double> d = D[c * TRS + k];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = lane + 64 * u, r = e >> 4, c = e & 15;
-          cx<double> acc{0.0, 0.0};
-#pragma unroll
-          for (int k = 0; k < TSZ; ++k) acc = cmadc(acc, P[r * TRS + k], D[c * TRS + k]);
-          out[u] = acc;
+          for (int u = 0; u < 4; ++u) out[u] = cmadc(out[u], P[(4 * u + q) * TRS + k], d);
         }
         wsync();
 #pragma unroll
@@ -416,16 +417,20 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
         const cx<double>* AI = L + tix(Ig, K);
         const cx<double>* AJ = L + tix(Jg, K);
         cx<double>* T = L + tix(Ig, Jg);
+        cx<double> acc[4] = {};
+#pragma unroll 4
+        for (int k = 0; k < TSZ; ++k) {
+          const cx<double> aj = AJ[c * TRS + k];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[u] = cmadc(acc[u], AI[(4 * u + q) * TRS + k], aj);
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int e = lane + 64 * u, r = e >> 4, c = e & 15;
+          const int r = 4 * u + q;
           if (Ig == Jg && c > r) continue;
-          cx<double> acc{0.0, 0.0};
-#pragma unroll
-          for (int k = 0; k < TSZ; ++k) acc = cmadc(acc, AI[r * TRS + k], AJ[c * TRS + k]);
           cx<double> v = T[r * TRS + c];
-          v.re -= acc.re;
-          v.im -= acc.im;
+          v.re -= acc[u].re;
+          v.im -= acc[u].im;
           T[r * TRS + c] = v;
         }
       }
@@ -438,6 +443,8 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
 
   PHASE(9);
   // ---- inverse: row by row, X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ ----
+  // (lane (q, c) forms rows r = 4 u + q of column c, as in the factorisation)
+  const int q = lane >> 4, c = lane & 15;
   for (int I = 1; I < NT; ++I) {
     // phase A: S_IJ into registers (tiles J < I spread over the waves)
     cx<double> sreg[CB_SLOTS][4];
@@ -446,17 +453,17 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
       const int J = wave + CB_W * slot;
       if (J >= I) continue;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = lane + 64 * u, r = e >> 4, c = e & 15;
-        cx<double> acc{0.0, 0.0};
-        for (int K = J; K < I; ++K) {
-          const cx<double>* LI = L + tix(I, K);
-          const cx<double>* XK = L + tix(K, J);
-          // X_JJ (K == J) is lower triangular, its zeros stored
+      for (int u = 0; u < 4; ++u) sreg[slot][u] = cx<double>{0.0, 0.0};
+      for (int K = J; K < I; ++K) {
+        const cx<double>* LI = L + tix(I, K);
+        const cx<double>* XK = L + tix(K, J);
+        // X_JJ (K == J) is lower triangular, its zeros stored
+#pragma unroll 4
+        for (int k = 0; k < TSZ; ++k) {
+          const cx<double> x = XK[k * TRS + c];
 #pragma unroll
-          for (int k = 0; k < TSZ; ++k) acc = cmad(acc, LI[r * TRS + k], XK[k * TRS + c]);
+          for (int u = 0; u < 4; ++u) sreg[slot][u] = cmad(sreg[slot][u], LI[(4 * u + q) * TRS + k], x);
         }
-        sreg[slot][u] = acc;
       }
     }
     __syncthreads();
@@ -478,14 +485,15 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
       const int J = wave + CB_W * slot;
       if (J >= I) continue;
       const cx<double>* S = L + tix(I, J);
+      cx<double> acc[4] = {};
+#pragma unroll 4
+      for (int k = 0; k < TSZ; ++k) {
+        const cx<double> sv = S[k * TRS + c];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = lane + 64 * u, r = e >> 4, c = e & 15;
-        cx<double> acc{0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < TSZ; ++k) acc = cmad(acc, XI[r * TRS + k], S[k * TRS + c]);
-        sreg[slot][u] = cx<double>{-acc.re, -acc.im};
+        for (int u = 0; u < 4; ++u) acc[u] = cmad(acc[u], XI[(4 * u + q) * TRS + k], sv);
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sreg[slot][u] = cx<double>{-acc[u].re, -acc[u].im};
     }
     __syncthreads();
 #pragma unroll
