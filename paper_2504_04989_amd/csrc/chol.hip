@@ -371,13 +371,16 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
     const double shift = shift_coef * tr;
     for (int i = tid; i < b; i += CB_NT) L[tix(i >> 4, i >> 4) + (i & 15) * (TRS + 1)].re += shift;
     __syncthreads();
+    // Look-ahead: the diagonal tile of step K + 1 is factored (and inverted)
+    // by wave 0 during step K's trailing update, right after wave 0 has
+    // applied that update to it, while the other waves update the rest.
+    if (wave == 0) {
+      bad |= tile_cholesky(L, lane, b);
+      tile_inverse(L, lane);  // X_00 = L_00^{-1}
+    }
+    __syncthreads();
     for (int K = 0; K < NT; ++K) {
-      cx<double>* D = L + tix(K, K);
-      if (wave == 0) {
-        bad |= tile_cholesky(D, lane, b - K * TSZ);
-        tile_inverse(D, lane);  // D <- X_KK = L_KK^{-1}
-      }
-      __syncthreads();
+      const cx<double>* D = L + tix(K, K);  // X_KK
       // panel: A_IK <- A_IK X_KK^H (one tile per wave at a time).  The
       // triangular tiles hold exact zeros above the diagonal, so every inner
       // product below runs over all 16 terms: the extra terms add exact
@@ -404,10 +407,15 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
         wsync();
       }
       __syncthreads();
-      // trailing: A_IJ -= A_IK A_JK^H, K < J <= I
+      // trailing: A_IJ -= A_IK A_JK^H, K < J <= I.  Pair 0 is the next
+      // diagonal tile (K + 1, K + 1): wave 0 updates it alone and then
+      // factors it; waves 1 .. CB_W - 1 take the other pairs.
       const int m = NT - K - 1;
       const int npairs = m * (m + 1) / 2;
-      for (int pidx = wave; pidx < npairs; pidx += CB_W) {
+      const int pfirst = wave == 0 ? 0 : wave;
+      const int plast = wave == 0 ? min(npairs, 1) : npairs;
+      const int pstep = wave == 0 ? 1 : CB_W - 1;
+      for (int pidx = pfirst; pidx < plast; pidx += pstep) {
         int I = 0, rem = pidx;
         while (rem >= I + 1) {
           rem -= I + 1;
@@ -433,6 +441,12 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
           v.im -= acc[u].im;
           T[r * TRS + c] = v;
         }
+      }
+      if (wave == 0 && npairs > 0) {
+        cx<double>* Dn = L + tix(K + 1, K + 1);
+        wsync();  // the lanes' updates of the tile are visible to the whole wave
+        bad |= tile_cholesky(Dn, lane, b - (K + 1) * TSZ);
+        tile_inverse(Dn, lane);  // X_{K+1,K+1}
       }
       __syncthreads();
     }
