@@ -29,8 +29,11 @@
  *
  * Omega is the Gaussian test tensor of Alg. 2 (n2 x b x n3; the algorithm's
  * first line reads randn(n1, ...), but the product X * Omega needs n2 rows, as
- * in Alg. 1).  The random draws are an input: the same (A, Omega) always
- * gives the same result.
+ * in Alg. 1).  The entry points named after the paper's operations take a
+ * 64-bit `seed` and draw Omega themselves, on the device, into the workspace
+ * (tsvd_omega gives the same numbers on the host).  Each has an `_omega` twin
+ * that takes Omega as a device tensor instead (for tests with arbitrary test
+ * tensors).  The same (A, seed) or (A, Omega) always gives the same result.
  *
  * Parameters: k = target tubal rank (R in the paper), b = block width
  * (R + P: rank plus oversampling), q = number of Krylov steps.
@@ -44,8 +47,10 @@
  * TSVD_ENOMEM (ws_bytes below tsvd_workspace_bytes), TSVD_EHIP (a HIP launch
  * or runtime call failed; nothing more is enqueued).  Numerical events found
  * on the device (Cholesky shifts, a breakdown, an eigensolver that did not
- * converge, non-finite values) are counted in the workspace and read with
- * tsvd_read_info().  tsvd_last_error() gives a message for the last non-zero
+ * converge, non-finite values) are counted in the workspace; the calls are
+ * asynchronous, so they are reported by tsvd_read_info(), which returns
+ * TSVD_ENUMERIC when a breakdown, an unconverged eigenvector or a non-finite
+ * value was met.  tsvd_last_error() gives a message for the last non-zero
  * status returned on the calling thread.
  *
  * Internal precision: Gram matrices, Cholesky factors, re-orthogonalisation
@@ -105,7 +110,10 @@ extern "C" {
 #define TSVD_OP_RBK_LITERAL 10    /* tsvd_rbk_literal */
 
 /* diagnostic counters returned by tsvd_read_info (int32 each) */
-#define TSVD_INFO_CHOL_SHIFTED 0   /* shifted Cholesky passes that were needed */
+#define TSVD_INFO_CHOL_SHIFTED 0   /* shifted Cholesky passes whose shift rescued a
+                                      pivot (unshifted pivot <= shift: the block
+                                      is numerically rank deficient); not an
+                                      error */
 #define TSVD_INFO_CHOL_BREAKDOWN 1 /* pivots still non-positive after the shift */
 #define TSVD_INFO_EIG_NOCONV 2     /* eigenvectors that did not converge        */
 #define TSVD_INFO_NONFINITE 3      /* non-finite values met                     */
@@ -124,8 +132,20 @@ const char* tsvd_last_error(void);
 size_t tsvd_workspace_bytes(int64_t n1, int64_t n2, int64_t n3, int64_t k,
                             int64_t b, int64_t q, int prec, int op);
 
+/* The seeded Gaussian test tensor of Alg. 2 (its first step, randn), on the
+ * host: out_host (n2 x b x n3 doubles, host memory owned by the caller)
+ * receives the tensor that the seed-taking entry points draw on the device
+ * for the same (n2, b, n3, seed), bit for bit (the FP32 modes use these
+ * values rounded to float).  Element e = (j b + c) n3 + t is value e of a
+ * counter-based stream: pair e / 2 of Philox4x32-10 (Salmon et al., SC'11;
+ * counter = pair index, key = seed) through a Box-Muller transform whose
+ * logarithm, sine, cosine and square root are fixed sequences of IEEE double
+ * operations.  n2 * b * n3 <= 2^40, else TSVD_EINVAL.  Pure host function. */
+int tsvd_omega(int64_t n2, int64_t b, int64_t n3, uint64_t seed, double* out_host);
+
 /* Alg. 2: randomized block Krylov truncated T-SVD.
- * In:  A (n1 x n2 x n3), Omega (n2 x b x n3).
+ * In:  A (n1 x n2 x n3); the test tensor Omega (n2 x b x n3) is drawn from
+ *      seed as tsvd_omega does, into the workspace.
  * Out: U (n1 x k x n3), S (k x n3: the k diagonal tubes of the f-diagonal
  *      S_R, row j is the tube S(j, j, :)), V (n2 x k x n3), with
  *      A ~ U * S * V^T (T-product, Sec. 2).
@@ -137,17 +157,26 @@ size_t tsvd_workspace_bytes(int64_t n1, int64_t n2, int64_t n3, int64_t k,
  * V_f = right singular vectors.  Each column pair (U_f(:, j), V_f(:, j)) is
  * scaled by one unit phase so that the largest-modulus entry of U_f(:, j)
  * (first on ties) is real and positive. */
-int tsvd_rbk(const void* A, const void* Omega, int64_t n1, int64_t n2,
-             int64_t n3, int64_t k, int64_t b, int64_t q, int prec, void* U,
-             void* S, void* V, void* ws, size_t ws_bytes, void* stream);
+int tsvd_rbk(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k,
+             int64_t b, int64_t q, uint64_t seed, int prec, void* U, void* S,
+             void* V, void* ws, size_t ws_bytes, void* stream);
+/* tsvd_rbk with the test tensor given: Omega (n2 x b x n3, device). */
+int tsvd_rbk_omega(const void* A, const void* Omega, int64_t n1, int64_t n2,
+                   int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
+                   void* U, void* S, void* V, void* ws, size_t ws_bytes,
+                   void* stream);
 
 /* Alg. 2 followed by the rank-k approximation Xhat = U * S * V^T
  * (n1 x n2 x n3), which equals Q * (Q^T * A)_k (Lemma mn38).  U, S and V
  * are written as in tsvd_rbk and may not be NULL. */
-int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2,
-                    int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
+int tsvd_rbk_approx(const void* A, int64_t n1, int64_t n2, int64_t n3,
+                    int64_t k, int64_t b, int64_t q, uint64_t seed, int prec,
                     void* U, void* S, void* V, void* Xhat, void* ws,
                     size_t ws_bytes, void* stream);
+int tsvd_rbk_approx_omega(const void* A, const void* Omega, int64_t n1,
+                          int64_t n2, int64_t n3, int64_t k, int64_t b,
+                          int64_t q, int prec, void* U, void* S, void* V,
+                          void* Xhat, void* ws, size_t ws_bytes, void* stream);
 
 /* Alg. 2 with the Krylov blocks exactly as the algorithm writes them:
  * K_0 = A_f Om_f and K_i = A_f (A_f^H K_{i-1}), none orthonormalised before
@@ -160,10 +189,14 @@ int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2,
  * scaled so that sigma_1^(2q+1) stays within the working precision's range.
  * Xhat (n1 x n2 x n3) may be NULL; otherwise it receives U * S * V^T.
  * Workspace: tsvd_workspace_bytes(..., TSVD_OP_RBK_LITERAL). */
-int tsvd_rbk_literal(const void* A, const void* Omega, int64_t n1, int64_t n2,
-                     int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
+int tsvd_rbk_literal(const void* A, int64_t n1, int64_t n2, int64_t n3,
+                     int64_t k, int64_t b, int64_t q, uint64_t seed, int prec,
                      void* U, void* S, void* V, void* Xhat, void* ws,
                      size_t ws_bytes, void* stream);
+int tsvd_rbk_literal_omega(const void* A, const void* Omega, int64_t n1,
+                           int64_t n2, int64_t n3, int64_t k, int64_t b,
+                           int64_t q, int prec, void* U, void* S, void* V,
+                           void* Xhat, void* ws, size_t ws_bytes, void* stream);
 
 /* Alg. 1: classical randomized subspace method with q power iterations.
  * Same arguments, layouts and outputs as tsvd_rbk, but the basis Q_f
@@ -171,17 +204,25 @@ int tsvd_rbk_literal(const void* A, const void* Omega, int64_t n1, int64_t n2,
  * (A_f A_f^H)^q A_f Om_f; each iterate is orthonormalised before the next
  * multiplication (the same range as the literal powers in exact arithmetic).
  * Projection, small SVD, lift, truncation and phase rule as in tsvd_rbk. */
-int tsvd_power(const void* A, const void* Omega, int64_t n1, int64_t n2,
-               int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
-               void* U, void* S, void* V, void* ws, size_t ws_bytes,
-               void* stream);
+int tsvd_power(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k,
+               int64_t b, int64_t q, uint64_t seed, int prec, void* U,
+               void* S, void* V, void* ws, size_t ws_bytes, void* stream);
+int tsvd_power_omega(const void* A, const void* Omega, int64_t n1, int64_t n2,
+                     int64_t n3, int64_t k, int64_t b, int64_t q, int prec,
+                     void* U, void* S, void* V, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /* Alg. 1 followed by the rank-k approximation Xhat = U * S * V^T
  * (n1 x n2 x n3), as tsvd_rbk_approx does for Alg. 2. */
-int tsvd_power_approx(const void* A, const void* Omega, int64_t n1,
-                      int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q,
+int tsvd_power_approx(const void* A, int64_t n1, int64_t n2, int64_t n3,
+                      int64_t k, int64_t b, int64_t q, uint64_t seed,
                       int prec, void* U, void* S, void* V, void* Xhat,
                       void* ws, size_t ws_bytes, void* stream);
+int tsvd_power_approx_omega(const void* A, const void* Omega, int64_t n1,
+                            int64_t n2, int64_t n3, int64_t k, int64_t b,
+                            int64_t q, int prec, void* U, void* S, void* V,
+                            void* Xhat, void* ws, size_t ws_bytes,
+                            void* stream);
 
 /* Alg. TQR: economy T-QR A = Q * R (Sec. 2).
  * In:  A (n1 x n2 x n3).  Out: Q (n1 x r x n3) with Q^T * Q = I, and
@@ -219,33 +260,48 @@ int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec,
  * entries come from the last approximation.
  * M: the data (n1 x n2 x n3; entries where T is 0 are not read).  mask: T as
  * n1 x n2 x n3 bytes in the same layout (device pointer; 0 = missing,
- * non-zero = observed).  Omega (n2 x b x n3), k, b, q and prec as for
- * tsvd_rbk / tsvd_power.  iters in [0, 10^6].  Workspace:
+ * non-zero = observed).  seed (Omega drawn once, used at every step), k, b,
+ * q and prec as for tsvd_rbk / tsvd_power; tsvd_complete_omega takes Omega
+ * (n2 x b x n3) instead.  iters in [0, 10^6].  Workspace:
  * tsvd_workspace_bytes(..., TSVD_OP_COMPLETE_RBK or TSVD_OP_COMPLETE_POWER).
  * tsvd_read_info reports the counters of the last iteration. */
-int tsvd_complete(const void* M, const void* mask, const void* Omega,
-                  int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
-                  int64_t q, int64_t iters, int alg, int prec, void* C,
-                  void* ws, size_t ws_bytes, void* stream);
+int tsvd_complete(const void* M, const void* mask, int64_t n1, int64_t n2,
+                  int64_t n3, int64_t k, int64_t b, int64_t q, uint64_t seed,
+                  int64_t iters, int alg, int prec, void* C, void* ws,
+                  size_t ws_bytes, void* stream);
+int tsvd_complete_omega(const void* M, const void* mask, const void* Omega,
+                        int64_t n1, int64_t n2, int64_t n3, int64_t k,
+                        int64_t b, int64_t q, int64_t iters, int alg,
+                        int prec, void* C, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* Projection P(A) = Q * Q^T * A (n1 x n2 x n3), Q the T-orthonormal basis of
  * the block Krylov tensor of Alg. 2 (the projector of Thm. mn44 and
- * Lemma mn38; no truncation). */
-int tsvd_proj(const void* A, const void* Omega, int64_t n1, int64_t n2,
-              int64_t n3, int64_t b, int64_t q, int prec, void* P, void* ws,
+ * Lemma mn38; no truncation), the test tensor drawn from seed. */
+int tsvd_proj(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t b,
+              int64_t q, uint64_t seed, int prec, void* P, void* ws,
               size_t ws_bytes, void* stream);
+int tsvd_proj_omega(const void* A, const void* Omega, int64_t n1, int64_t n2,
+                    int64_t n3, int64_t b, int64_t q, int prec, void* P,
+                    void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint of the projection: given G = dL/dP (n1 x n2 x n3), writes
  * dA = dL/dA (n1 x n2 x n3) for L(P(A)).  The Krylov blocks are recomputed
  * from A and Omega, not stored.  Derivative of the map defined by tsvd_proj;
  * for the real inner product sum_ijt x_ijt y_ijt (Sec. 2). */
-int tsvd_proj_backward(const void* A, const void* Omega, const void* G,
-                       int64_t n1, int64_t n2, int64_t n3, int64_t b,
-                       int64_t q, int prec, void* dA, void* ws,
-                       size_t ws_bytes, void* stream);
+int tsvd_proj_backward(const void* A, const void* G, int64_t n1, int64_t n2,
+                       int64_t n3, int64_t b, int64_t q, uint64_t seed,
+                       int prec, void* dA, void* ws, size_t ws_bytes,
+                       void* stream);
+int tsvd_proj_backward_omega(const void* A, const void* Omega, const void* G,
+                             int64_t n1, int64_t n2, int64_t n3, int64_t b,
+                             int64_t q, int prec, void* dA, void* ws,
+                             size_t ws_bytes, void* stream);
 
 /* Copy the TSVD_INFO_COUNT diagnostic counters of the last call that used
- * workspace `ws` into info_host (host memory).  Synchronises `stream`. */
+ * workspace `ws` into info_host (host memory).  Synchronises `stream`.
+ * Returns TSVD_ENUMERIC (counters still copied) when that call met a
+ * Cholesky breakdown, an unconverged eigenvector or a non-finite value. */
 int tsvd_read_info(const void* ws, int32_t* info_host, void* stream);
 
 #ifdef __cplusplus

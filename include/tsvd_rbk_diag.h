@@ -58,6 +58,12 @@ size_t tsvd_diag_heig_ws_bytes(int64_t m, int64_t k, int64_t batch);
 int tsvd_diag_heig(const void* G, int64_t m, int64_t k, int64_t batch, void* lambda, void* W, void* ws,
                    size_t ws_bytes, void* stream);
 
+/* The seeded test tensor of Alg. 2 as the seed-taking entry points draw it on
+ * the device: out (device, n values of dtype 0 = double / 1 = float) receives
+ * values 0 .. n-1 of the stream that tsvd_omega writes on the host for the
+ * same seed (FP32: those values rounded once). */
+int tsvd_diag_omega(void* out, int64_t n, uint64_t seed, int dtype, void* stream);
+
 /* Event timer over the kernels of the entry points in tsvd_rbk.h.
  * tsvd_diag_timing(1) clears the counters and starts recording a pair of HIP
  * events on the caller's stream around every launch; (0) stops.

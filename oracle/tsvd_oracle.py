@@ -428,20 +428,30 @@ def _truncated_slices(A, Omega, k, b, m, freqs, basis):
         "C": np.zeros((m, n2, nf), complex), "s_all": np.zeros((m, nf)),
     }
     for idx in range(nf):
-        Af, Of = Ab[:, :, idx], Ob[:, :, idx]
-        Q = basis(Af, Of)
-        C = Q.conj().T @ Af
-        W, s, Z, _ = jacobi_svd(C)
-        Uf = Q @ W[:, :k]
-        Vf = Z[:, :k]
-        Uf, Vf = canonical_phase(Uf, Vf)
-        out["Uf"][:, :, idx] = Uf
-        out["Vf"][:, :, idx] = Vf
-        out["Sf"][:, idx] = s[:k]
-        out["Q"][:, :, idx] = Q
-        out["C"][:, :, idx] = C
-        out["s_all"][:, idx] = s
+        r = truncated_slice(Ab[:, :, idx], Ob[:, :, idx], k, basis)
+        for key in ("Uf", "Vf", "Q", "C"):
+            out[key][:, :, idx] = r[key]
+        out["Sf"][:, idx] = r["Sf"]
+        out["s_all"][:, idx] = r["s_all"]
     return out
+
+
+def truncated_slice(Af: np.ndarray, Of: np.ndarray, k: int, basis):
+    """One Fourier slice of the shared tail of Alg. 1 and Alg. 2: Q = basis(Af,
+    Of), C = Q^H Af, C = W diag(s) Z^H (Jacobi SVD), U_f = Q W(:, :k),
+    S_f = s[:k], V_f = Z(:, :k), phases canonicalised (reading R9)."""
+    Q = basis(Af, Of)
+    C = Q.conj().T @ Af
+    W, s, Z, _ = jacobi_svd(C)
+    Uf, Vf = canonical_phase(Q @ W[:, :k], Z[:, :k])
+    return {"Uf": Uf, "Vf": Vf, "Sf": s[:k], "Q": Q, "C": C, "s_all": s}
+
+
+def rbk_slice(Af: np.ndarray, Of: np.ndarray, k: int, b: int, q: int, krylov: str = "stab"):
+    """Alg. 2 on one Fourier slice (Af n1 x n2, Of n2 x b): the per-slice body
+    of rbk_slices for a slice whose DFT is already taken."""
+    _check_params(Af.shape[0], Af.shape[1], 1, k, b, q)
+    return truncated_slice(Af, Of, k, lambda A_, O_: krylov_basis(A_, O_, q, krylov)[0])
 
 
 def _spatial_factors(sl: dict, n3: int) -> dict:

@@ -21,12 +21,14 @@ OP = {"rbk": 0, "approx": 1, "proj": 2, "proj_bwd": 3, "power": 4, "power_approx
 INFO_NAMES = ("chol_shifted", "chol_breakdown", "eig_noconv", "nonfinite")
 INFO_COUNT = 8
 
-EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_rbk", "tsvd_rbk_approx",
-           "tsvd_power", "tsvd_power_approx", "tsvd_tqr", "tsvd_tpinv", "tsvd_complete",
-           "tsvd_rbk_literal",
-           "tsvd_proj", "tsvd_proj_backward", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
+EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_omega",
+           "tsvd_rbk", "tsvd_rbk_omega", "tsvd_rbk_approx", "tsvd_rbk_approx_omega",
+           "tsvd_power", "tsvd_power_omega", "tsvd_power_approx", "tsvd_power_approx_omega",
+           "tsvd_rbk_literal", "tsvd_rbk_literal_omega", "tsvd_complete", "tsvd_complete_omega",
+           "tsvd_tqr", "tsvd_tpinv", "tsvd_proj", "tsvd_proj_omega", "tsvd_proj_backward",
+           "tsvd_proj_backward_omega", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
            "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_heig",
-           "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read")
+           "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read", "tsvd_diag_omega")
 
 
 class TsvdError(RuntimeError):
@@ -44,28 +46,35 @@ def _load():
     lib.tsvd_last_error.restype = ctypes.c_char_p
     lib.tsvd_workspace_bytes.restype = sz
     lib.tsvd_workspace_bytes.argtypes = [i64, i64, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int]
-    lib.tsvd_rbk.restype = ctypes.c_int
-    lib.tsvd_rbk.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, sz, vp]
-    lib.tsvd_rbk_approx.restype = ctypes.c_int
-    lib.tsvd_rbk_approx.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, vp, sz, vp]
-    lib.tsvd_power.restype = ctypes.c_int
-    lib.tsvd_power.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, sz, vp]
-    lib.tsvd_power_approx.restype = ctypes.c_int
-    lib.tsvd_power_approx.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, vp, sz,
-                                      vp]
-    lib.tsvd_tqr.restype = ctypes.c_int
-    lib.tsvd_tqr.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp, vp, sz, vp]
-    lib.tsvd_tpinv.restype = ctypes.c_int
-    lib.tsvd_tpinv.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp, sz, vp]
-    lib.tsvd_rbk_literal.restype = ctypes.c_int
-    lib.tsvd_rbk_literal.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, vp, vp, vp, sz, vp]
-    lib.tsvd_complete.restype = ctypes.c_int
-    lib.tsvd_complete.argtypes = [vp, vp, vp, i64, i64, i64, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, vp,
-                                  sz, vp]
-    lib.tsvd_proj.restype = ctypes.c_int
-    lib.tsvd_proj.argtypes = [vp, vp, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, sz, vp]
-    lib.tsvd_proj_backward.restype = ctypes.c_int
-    lib.tsvd_proj_backward.argtypes = [vp, vp, vp, i64, i64, i64, i64, i64, ctypes.c_int, vp, vp, sz, vp]
+    u64, ci = ctypes.c_uint64, ctypes.c_int
+    lib.tsvd_omega.restype = ci
+    lib.tsvd_omega.argtypes = [i64, i64, i64, u64, vp]
+    # (A, n1, n2, n3, k, b, q, seed, prec, U, S, V[, Xhat], ws, ws_bytes, stream) and the _omega twins
+    # (A, Omega, n1, n2, n3, k, b, q, prec, U, S, V[, Xhat], ws, ws_bytes, stream)
+    for name, nout in (("tsvd_rbk", 3), ("tsvd_rbk_approx", 4), ("tsvd_power", 3), ("tsvd_power_approx", 4),
+                       ("tsvd_rbk_literal", 4)):
+        f = getattr(lib, name)
+        f.restype = ci
+        f.argtypes = [vp, i64, i64, i64, i64, i64, i64, u64, ci] + [vp] * nout + [vp, sz, vp]
+        f = getattr(lib, name + "_omega")
+        f.restype = ci
+        f.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ci] + [vp] * nout + [vp, sz, vp]
+    lib.tsvd_tqr.restype = ci
+    lib.tsvd_tqr.argtypes = [vp, i64, i64, i64, ci, vp, vp, vp, sz, vp]
+    lib.tsvd_tpinv.restype = ci
+    lib.tsvd_tpinv.argtypes = [vp, i64, i64, i64, ci, vp, vp, sz, vp]
+    lib.tsvd_complete.restype = ci
+    lib.tsvd_complete.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, u64, i64, ci, ci, vp, vp, sz, vp]
+    lib.tsvd_complete_omega.restype = ci
+    lib.tsvd_complete_omega.argtypes = [vp, vp, vp, i64, i64, i64, i64, i64, i64, i64, ci, ci, vp, vp, sz, vp]
+    lib.tsvd_proj.restype = ci
+    lib.tsvd_proj.argtypes = [vp, i64, i64, i64, i64, i64, u64, ci, vp, vp, sz, vp]
+    lib.tsvd_proj_omega.restype = ci
+    lib.tsvd_proj_omega.argtypes = [vp, vp, i64, i64, i64, i64, i64, ci, vp, vp, sz, vp]
+    lib.tsvd_proj_backward.restype = ci
+    lib.tsvd_proj_backward.argtypes = [vp, vp, i64, i64, i64, i64, i64, u64, ci, vp, vp, sz, vp]
+    lib.tsvd_proj_backward_omega.restype = ci
+    lib.tsvd_proj_backward_omega.argtypes = [vp, vp, vp, i64, i64, i64, i64, i64, ci, vp, vp, sz, vp]
     lib.tsvd_read_info.restype = ctypes.c_int
     lib.tsvd_read_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.tsvd_diag_fft_r2c.restype = ctypes.c_int
@@ -85,6 +94,8 @@ def _load():
     lib.tsvd_diag_kgemm.restype = ctypes.c_int
     lib.tsvd_diag_kgemm.argtypes = [vp, ctypes.c_int, vp, vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, sz,
                                     vp]
+    lib.tsvd_diag_omega.restype = ci
+    lib.tsvd_diag_omega.argtypes = [vp, i64, u64, ci, vp]
     lib.tsvd_diag_heig_ws_bytes.restype = sz
     lib.tsvd_diag_heig_ws_bytes.argtypes = [i64, i64, i64]
     lib.tsvd_diag_heig.restype = ctypes.c_int
@@ -139,114 +150,105 @@ def workspace(n1, n2, n3, k, b, q, prec, op, device) -> torch.Tensor:
 
 
 def read_info(ws: torch.Tensor) -> dict:
+    """Diagnostic counters of the last call that used `ws` (synchronises its
+    stream).  "status" is TSVD_ENUMERIC when that call met a Cholesky
+    breakdown, an unconverged eigenvector or a non-finite value, else TSVD_OK."""
     buf = (ctypes.c_int32 * INFO_COUNT)()
-    _check(lib.tsvd_read_info(_ptr(ws), buf, _stream(ws.device)))
-    return {name: int(buf[i]) for i, name in enumerate(INFO_NAMES)}
+    code = lib.tsvd_read_info(_ptr(ws), buf, _stream(ws.device))
+    if code not in (TSVD_OK, TSVD_ENUMERIC):
+        _check(code)
+    out = {name: int(buf[i]) for i, name in enumerate(INFO_NAMES)}
+    out["status"] = int(code)
+    return out
 
 
-def tsvd_rbk(A: torch.Tensor, Omega: torch.Tensor, k: int, b: int, q: int, prec=None, ws=None, out=None):
-    """Alg. 2: returns (U, S, V) with U (n1,k,n3), S (k,n3), V (n2,k,n3)."""
+def omega(n2: int, b: int, n3: int, seed: int):
+    """The seeded test tensor (n2, b, n3) float64 on the host, as the
+    seed-taking entry points draw it on the device (tsvd_omega)."""
+    import numpy as np
+    out = np.empty((n2, b, n3), dtype=np.float64)
+    _check(lib.tsvd_omega(n2, b, n3, int(seed) & 0xFFFFFFFFFFFFFFFF, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def _is_seed(Omega) -> bool:
+    return isinstance(Omega, int) and not isinstance(Omega, bool)
+
+
+def _omega_in(Omega, dt, n2: int, b: int, n3: int):
+    """Validate a test-tensor argument: an int seed, or a contiguous device
+    tensor of shape (n2, b, n3) in the working dtype."""
+    if _is_seed(Omega):
+        return
+    if not isinstance(Omega, torch.Tensor):
+        raise ValueError("Omega must be an int seed or a device tensor")
+    _check_in(Omega, dt, "Omega")
+    if tuple(Omega.shape) != (n2, b, n3):
+        raise ValueError(f"Omega must have shape (n2, b, n3) = {(n2, b, n3)}, got {tuple(Omega.shape)}")
+
+
+def _shape3(A: torch.Tensor, name="A"):
+    if A.dim() != 3:
+        raise ValueError(f"{name} must be a 3-way tensor (n1, n2, n3)")
+    return tuple(int(x) for x in A.shape)
+
+
+def _svd_call(name, op, A, Omega, k, b, q, prec, ws, out, with_x):
     prec = _prec_of(A, prec)
     dt = _dtype_of(prec)
     _check_in(A, dt, "A")
-    _check_in(Omega, dt, "Omega")
-    n1, n2, n3 = A.shape
-    if tuple(Omega.shape) != (n2, b, n3):
-        raise ValueError("Omega must have shape (n2, b, n3)")
+    n1, n2, n3 = _shape3(A)
+    _omega_in(Omega, dt, n2, b, n3)
     dev = A.device
     if ws is None:
-        ws = workspace(n1, n2, n3, k, b, q, prec, "rbk", dev)
+        ws = workspace(n1, n2, n3, k, b, q, prec, op, dev)
     if out is None:
         out = (torch.empty((n1, k, n3), dtype=dt, device=dev), torch.empty((k, n3), dtype=dt, device=dev),
                torch.empty((n2, k, n3), dtype=dt, device=dev))
     U, S, V = out
-    _check(lib.tsvd_rbk(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S), _ptr(V),
-                        _ptr(ws), ws.numel(), _stream(dev)))
-    return U, S, V
+    for t, nm, shp in ((U, "U", (n1, k, n3)), (S, "S", (k, n3)), (V, "V", (n2, k, n3))):
+        _check_in(t, dt, nm)
+        if tuple(t.shape) != shp:
+            raise ValueError(f"{nm} must have shape {shp}")
+    X = torch.empty((n1, n2, n3), dtype=dt, device=dev) if with_x else None
+    xs = [_ptr(X)] if name != "tsvd_rbk" and name != "tsvd_power" else []
+    if _is_seed(Omega):
+        f = getattr(lib, name)
+        _check(f(_ptr(A), n1, n2, n3, k, b, q, int(Omega) & 0xFFFFFFFFFFFFFFFF, PREC[prec], _ptr(U), _ptr(S),
+                 _ptr(V), *xs, _ptr(ws), ws.numel(), _stream(dev)))
+    else:
+        f = getattr(lib, name + "_omega")
+        _check(f(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S), _ptr(V), *xs, _ptr(ws),
+                 ws.numel(), _stream(dev)))
+    return U, S, V, X
+
+
+def tsvd_rbk(A: torch.Tensor, Omega, k: int, b: int, q: int, prec=None, ws=None, out=None):
+    """Alg. 2: returns (U, S, V) with U (n1,k,n3), S (k,n3), V (n2,k,n3).
+    Omega: an int seed (the test tensor is drawn on the device) or a device
+    tensor (n2, b, n3)."""
+    return _svd_call("tsvd_rbk", "rbk", A, Omega, k, b, q, prec, ws, out, False)[:3]
 
 
 def tsvd_rbk_approx(A, Omega, k, b, q, prec=None, ws=None):
     """Alg. 2 plus X_hat = U * S * V^T: returns (U, S, V, X_hat)."""
-    prec = _prec_of(A, prec)
-    dt = _dtype_of(prec)
-    _check_in(A, dt, "A")
-    _check_in(Omega, dt, "Omega")
-    n1, n2, n3 = A.shape
-    if tuple(Omega.shape) != (n2, b, n3):
-        raise ValueError("Omega must have shape (n2, b, n3)")
-    dev = A.device
-    if ws is None:
-        ws = workspace(n1, n2, n3, k, b, q, prec, "approx", dev)
-    U = torch.empty((n1, k, n3), dtype=dt, device=dev)
-    S = torch.empty((k, n3), dtype=dt, device=dev)
-    V = torch.empty((n2, k, n3), dtype=dt, device=dev)
-    X = torch.empty((n1, n2, n3), dtype=dt, device=dev)
-    _check(lib.tsvd_rbk_approx(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S), _ptr(V),
-                               _ptr(X), _ptr(ws), ws.numel(), _stream(dev)))
-    return U, S, V, X
+    return _svd_call("tsvd_rbk_approx", "approx", A, Omega, k, b, q, prec, ws, None, True)
 
 
 def tsvd_rbk_literal(A, Omega, k, b, q, prec=None, ws=None, approx=True):
     """Alg. 2 with the literal Krylov powers (no orthonormalisation between
     steps): returns (U, S, V, X_hat) (X_hat None when approx is False)."""
-    prec = _prec_of(A, prec)
-    dt = _dtype_of(prec)
-    _check_in(A, dt, "A")
-    _check_in(Omega, dt, "Omega")
-    n1, n2, n3 = A.shape
-    if tuple(Omega.shape) != (n2, b, n3):
-        raise ValueError("Omega must have shape (n2, b, n3)")
-    dev = A.device
-    if ws is None:
-        ws = workspace(n1, n2, n3, k, b, q, prec, "literal", dev)
-    U = torch.empty((n1, k, n3), dtype=dt, device=dev)
-    S = torch.empty((k, n3), dtype=dt, device=dev)
-    V = torch.empty((n2, k, n3), dtype=dt, device=dev)
-    X = torch.empty((n1, n2, n3), dtype=dt, device=dev) if approx else None
-    _check(lib.tsvd_rbk_literal(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S), _ptr(V),
-                                _ptr(X), _ptr(ws), ws.numel(), _stream(dev)))
-    return U, S, V, X
+    return _svd_call("tsvd_rbk_literal", "literal", A, Omega, k, b, q, prec, ws, None, approx)
 
 
-def tsvd_power(A: torch.Tensor, Omega: torch.Tensor, k: int, b: int, q: int, prec=None, ws=None):
+def tsvd_power(A: torch.Tensor, Omega, k: int, b: int, q: int, prec=None, ws=None):
     """Alg. 1 (q power iterations): returns (U, S, V) like tsvd_rbk."""
-    prec = _prec_of(A, prec)
-    dt = _dtype_of(prec)
-    _check_in(A, dt, "A")
-    _check_in(Omega, dt, "Omega")
-    n1, n2, n3 = A.shape
-    if tuple(Omega.shape) != (n2, b, n3):
-        raise ValueError("Omega must have shape (n2, b, n3)")
-    dev = A.device
-    if ws is None:
-        ws = workspace(n1, n2, n3, k, b, q, prec, "power", dev)
-    U = torch.empty((n1, k, n3), dtype=dt, device=dev)
-    S = torch.empty((k, n3), dtype=dt, device=dev)
-    V = torch.empty((n2, k, n3), dtype=dt, device=dev)
-    _check(lib.tsvd_power(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S), _ptr(V),
-                          _ptr(ws), ws.numel(), _stream(dev)))
-    return U, S, V
+    return _svd_call("tsvd_power", "power", A, Omega, k, b, q, prec, ws, None, False)[:3]
 
 
 def tsvd_power_approx(A, Omega, k, b, q, prec=None, ws=None):
     """Alg. 1 plus X_hat = U * S * V^T: returns (U, S, V, X_hat)."""
-    prec = _prec_of(A, prec)
-    dt = _dtype_of(prec)
-    _check_in(A, dt, "A")
-    _check_in(Omega, dt, "Omega")
-    n1, n2, n3 = A.shape
-    if tuple(Omega.shape) != (n2, b, n3):
-        raise ValueError("Omega must have shape (n2, b, n3)")
-    dev = A.device
-    if ws is None:
-        ws = workspace(n1, n2, n3, k, b, q, prec, "power_approx", dev)
-    U = torch.empty((n1, k, n3), dtype=dt, device=dev)
-    S = torch.empty((k, n3), dtype=dt, device=dev)
-    V = torch.empty((n2, k, n3), dtype=dt, device=dev)
-    X = torch.empty((n1, n2, n3), dtype=dt, device=dev)
-    _check(lib.tsvd_power_approx(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(U), _ptr(S),
-                                 _ptr(V), _ptr(X), _ptr(ws), ws.numel(), _stream(dev)))
-    return U, S, V, X
+    return _svd_call("tsvd_power_approx", "power_approx", A, Omega, k, b, q, prec, ws, None, True)
 
 
 def tsvd_tqr(A: torch.Tensor, prec=None, ws=None):
@@ -254,7 +256,7 @@ def tsvd_tqr(A: torch.Tensor, prec=None, ws=None):
     prec = _prec_of(A, prec)
     dt = _dtype_of(prec)
     _check_in(A, dt, "A")
-    n1, n2, n3 = A.shape
+    n1, n2, n3 = _shape3(A)
     r = min(n1, n2)
     if ws is None:
         ws = workspace(n1, n2, n3, 0, 0, 0, prec, "tqr", A.device)
@@ -270,7 +272,7 @@ def tsvd_tpinv(A: torch.Tensor, prec=None, ws=None):
     prec = _prec_of(A, prec)
     dt = _dtype_of(prec)
     _check_in(A, dt, "A")
-    n1, n2, n3 = A.shape
+    n1, n2, n3 = _shape3(A)
     if ws is None:
         ws = workspace(n1, n2, n3, 0, 0, 0, prec, "tpinv", A.device)
     X = torch.empty((n2, n1, n3), dtype=dt, device=A.device)
@@ -278,75 +280,101 @@ def tsvd_tpinv(A: torch.Tensor, prec=None, ws=None):
     return X
 
 
-def tsvd_complete(M: torch.Tensor, mask: torch.Tensor, Omega: torch.Tensor, k: int, b: int, q: int, iters: int,
+def tsvd_complete(M: torch.Tensor, mask: torch.Tensor, Omega, k: int, b: int, q: int, iters: int,
                   alg: int = 2, prec=None, ws=None):
     """Completion of Example 3: returns C^(iters) (n1, n2, n3).  mask: bool or
-    uint8 tensor of M's shape (True / non-zero = observed)."""
+    uint8 tensor of M's shape (True / non-zero = observed).  Omega: int seed
+    or device tensor (n2, b, n3)."""
     prec = _prec_of(M, prec)
     dt = _dtype_of(prec)
     _check_in(M, dt, "M")
-    _check_in(Omega, dt, "Omega")
-    n1, n2, n3 = M.shape
+    n1, n2, n3 = _shape3(M, "M")
     if tuple(mask.shape) != tuple(M.shape) or mask.dtype not in (torch.bool, torch.uint8):
         raise ValueError("mask must be a bool / uint8 tensor of M's shape")
     if not mask.is_cuda or not mask.is_contiguous():
         raise ValueError("mask must be a contiguous device tensor")
-    if tuple(Omega.shape) != (n2, b, n3):
-        raise ValueError("Omega must have shape (n2, b, n3)")
+    _omega_in(Omega, dt, n2, b, n3)
     if ws is None:
         ws = workspace(n1, n2, n3, k, b, q, prec, "complete2" if alg == 2 else "complete1", M.device)
     C = torch.empty_like(M)
-    _check(lib.tsvd_complete(_ptr(M), _ptr(mask), _ptr(Omega), n1, n2, n3, k, b, q, iters, alg, PREC[prec], _ptr(C),
-                             _ptr(ws), ws.numel(), _stream(M.device)))
+    if _is_seed(Omega):
+        _check(lib.tsvd_complete(_ptr(M), _ptr(mask), n1, n2, n3, k, b, q, int(Omega) & 0xFFFFFFFFFFFFFFFF, iters,
+                                 alg, PREC[prec], _ptr(C), _ptr(ws), ws.numel(), _stream(M.device)))
+    else:
+        _check(lib.tsvd_complete_omega(_ptr(M), _ptr(mask), _ptr(Omega), n1, n2, n3, k, b, q, iters, alg,
+                                       PREC[prec], _ptr(C), _ptr(ws), ws.numel(), _stream(M.device)))
     return C
 
 
 def tsvd_proj(A, Omega, b, q, prec=None, ws=None):
-    """P(A) = Q * Q^T * A with Q the T-QR basis of the block Krylov tensor."""
+    """P(A) = Q * Q^T * A with Q the T-QR basis of the block Krylov tensor.
+    Omega: int seed or device tensor (n2, b, n3)."""
     prec = _prec_of(A, prec)
     dt = _dtype_of(prec)
     _check_in(A, dt, "A")
-    _check_in(Omega, dt, "Omega")
-    n1, n2, n3 = A.shape
+    n1, n2, n3 = _shape3(A)
+    _omega_in(Omega, dt, n2, b, n3)
     dev = A.device
     if ws is None:
         ws = workspace(n1, n2, n3, 1, b, q, prec, "proj", dev)
     P = torch.empty_like(A)
-    _check(lib.tsvd_proj(_ptr(A), _ptr(Omega), n1, n2, n3, b, q, PREC[prec], _ptr(P), _ptr(ws), ws.numel(),
-                         _stream(dev)))
+    if _is_seed(Omega):
+        _check(lib.tsvd_proj(_ptr(A), n1, n2, n3, b, q, int(Omega) & 0xFFFFFFFFFFFFFFFF, PREC[prec], _ptr(P),
+                             _ptr(ws), ws.numel(), _stream(dev)))
+    else:
+        _check(lib.tsvd_proj_omega(_ptr(A), _ptr(Omega), n1, n2, n3, b, q, PREC[prec], _ptr(P), _ptr(ws),
+                                   ws.numel(), _stream(dev)))
     return P
 
 
 def tsvd_proj_backward(A, Omega, G, b, q, prec=None, ws=None):
-    """dL/dA for L(P(A)) given G = dL/dP."""
+    """dL/dA for L(P(A)) given G = dL/dP (G has A's shape)."""
     prec = _prec_of(A, prec)
     dt = _dtype_of(prec)
-    for t, nm in ((A, "A"), (Omega, "Omega"), (G, "G")):
-        _check_in(t, dt, nm)
-    n1, n2, n3 = A.shape
+    _check_in(A, dt, "A")
+    _check_in(G, dt, "G")
+    n1, n2, n3 = _shape3(A)
+    if tuple(G.shape) != (n1, n2, n3):
+        raise ValueError(f"G must have A's shape {(n1, n2, n3)}, got {tuple(G.shape)}")
+    _omega_in(Omega, dt, n2, b, n3)
     dev = A.device
     if ws is None:
         ws = workspace(n1, n2, n3, 1, b, q, prec, "proj_bwd", dev)
     dA = torch.empty_like(A)
-    _check(lib.tsvd_proj_backward(_ptr(A), _ptr(Omega), _ptr(G), n1, n2, n3, b, q, PREC[prec], _ptr(dA), _ptr(ws),
-                                  ws.numel(), _stream(dev)))
+    if _is_seed(Omega):
+        _check(lib.tsvd_proj_backward(_ptr(A), _ptr(G), n1, n2, n3, b, q, int(Omega) & 0xFFFFFFFFFFFFFFFF,
+                                      PREC[prec], _ptr(dA), _ptr(ws), ws.numel(), _stream(dev)))
+    else:
+        _check(lib.tsvd_proj_backward_omega(_ptr(A), _ptr(Omega), _ptr(G), n1, n2, n3, b, q, PREC[prec], _ptr(dA),
+                                            _ptr(ws), ws.numel(), _stream(dev)))
     return dA
 
 
 class TProject(torch.autograd.Function):
     """A -> Q * Q^T * A with the hand-written adjoint; the Krylov blocks are
-    recomputed in backward from (A, Omega), not stored."""
+    recomputed in backward from (A, Omega), not stored.  Omega: int seed or
+    device tensor (n2, b, n3)."""
 
     @staticmethod
     def forward(ctx, A, Omega, b, q, prec=None):
-        ctx.save_for_backward(A, Omega)
+        if _is_seed(Omega):
+            ctx.save_for_backward(A)
+            ctx.seed = int(Omega)
+        else:
+            ctx.save_for_backward(A, Omega)
+            ctx.seed = None
         ctx.b, ctx.q, ctx.prec = b, q, prec
-        return tsvd_proj(A.detach().contiguous(), Omega.contiguous(), b, q, prec)
+        return tsvd_proj(A.detach().contiguous(), Omega if ctx.seed is not None else Omega.contiguous(), b, q, prec)
 
     @staticmethod
     def backward(ctx, G):
-        A, Omega = ctx.saved_tensors
-        dA = tsvd_proj_backward(A.detach().contiguous(), Omega.contiguous(), G.contiguous(), ctx.b, ctx.q, ctx.prec)
+        if ctx.seed is not None:
+            (A,) = ctx.saved_tensors
+            Om = ctx.seed
+        else:
+            A, Om = ctx.saved_tensors
+            Om = Om.contiguous()
+        dA = tsvd_proj_backward(A.detach().contiguous(), Om, G.contiguous(), ctx.b, ctx.q, ctx.prec)
         return dA, None, None, None, None
 
 
@@ -417,6 +445,15 @@ def diag_heig(G, k):
     ws = torch.empty(nb, dtype=torch.uint8, device=G.device)
     _check(lib.tsvd_diag_heig(_ptr(G), m, k, batch, _ptr(lam), _ptr(W), _ptr(ws), ws.numel(), _stream(G.device)))
     return lam, W, read_info(ws)
+
+
+def diag_omega(n: int, seed: int, dtype=torch.float64, device="cuda") -> torch.Tensor:
+    """Values 0 .. n-1 of the seeded test-tensor stream, drawn on the device
+    (see tsvd_diag_omega)."""
+    out = torch.empty(n, dtype=dtype, device=device)
+    _check(lib.tsvd_diag_omega(_ptr(out), n, int(seed) & 0xFFFFFFFFFFFFFFFF, 0 if dtype == torch.float64 else 1,
+                               _stream(out.device)))
+    return out
 
 
 KERNEL_CLASSES = ("fft_A", "fft_omega", "gemm_krylov", "gemm_orth", "chol", "heig_tri", "gemm_lift", "fft_inv", "misc",

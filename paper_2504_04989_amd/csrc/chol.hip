@@ -16,31 +16,6 @@
 #include "common.h"
 #include "kernels.h"
 
-#ifdef TSVD_PHASE_PROF
-__device__ unsigned long long g_phase[16];
-#define PHASE_T0() unsigned long long ph_t = clock64()
-#define PHASE(i)                                            \
-  do {                                                      \
-    if (blockIdx.x == 0 && threadIdx.x == 0) {              \
-      const unsigned long long now = clock64();             \
-      atomicAdd(&g_phase[i], now - ph_t);                   \
-      ph_t = now;                                           \
-    }                                                       \
-  } while (0)
-#else
-#define PHASE_T0()
-#define PHASE(i)
-#endif
-#ifdef TSVD_PHASE_PROF
-extern "C" int tsvd_phase_read(unsigned long long* out, int reset) {
-  if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase)) != hipSuccess) return 1;
-  if (reset) {
-    unsigned long long z[16] = {};
-    if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z)) != hipSuccess) return 1;
-  }
-  return 0;
-}
-#endif
 
 namespace tsvd {
 
@@ -63,7 +38,6 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const cx<double>* __restr
   const int64_t ntri = (int64_t)b * (b + 1) / 2;
   cx<double>* L = LDS ? reinterpret_cast<cx<double>*>(smem) : gscratch + (int64_t)f * ntri;
   const cx<double>* G = Gpart + (int64_t)f * b * b;
-  PHASE_T0();
 
   if (mode == 1) {
     // L = R^H from the (summed) upper triangle of R
@@ -108,11 +82,11 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const cx<double>* __restr
     for (int i = tid; i < b; i += 256) tr += L[tri(i, i)].re;
     tr = block_sum<256>(tr, red);
     const double shift = shift_coef * tr;
-    PHASE(0);
 
     // Right-looking Cholesky, lower: G + shift I = L L^H.
-    int bad = 0;
+    int bad = 0, rescued = 0;
     for (int j = 0; j < b; ++j) {
+      if (shift > 0 && !(L[tri(j, j)].re > shift)) rescued = 1;  // the shift carries this pivot
       const double dj = L[tri(j, j)].re + shift;
       double piv = 1.0;
       if (dj > 0 && isfinite(dj))
@@ -143,7 +117,7 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const cx<double>* __restr
       __syncthreads();
     }
     if (tid == 0 && bad) atomicAdd(&info[INFO_CHOL_BREAKDOWN], 1);
-    PHASE(1);
+    if (tid == 0 && rescued) atomicAdd(&info[INFO_CHOL_SHIFTED], 1);
   }
 
   // In-place inverse of the lower factor, X = L^{-1}: forward elimination of
@@ -172,7 +146,6 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const cx<double>* __restr
     }
     __syncthreads();
   }
-  PHASE(2);
   // R^{-1} = (L^{-1})^H, upper triangular, row-major b x b.
   cx<double>* out = Rinv + (int64_t)f * b * b;
   for (int r = ty; r < b; r += 16) {
@@ -185,7 +158,6 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const cx<double>* __restr
       out[(int64_t)r * b + c] = v;
     }
   }
-  PHASE(3);
 }
 
 hipError_t chol_inv_blocked(const double* Gpart, int nsum, int64_t part_stride, double* Rinv, int b, int batch,
@@ -278,16 +250,19 @@ __device__ void tile_inverse(cx<double>* T, int lane) {
 }
 
 // Cholesky of the Hermitian 16 x 16 tile T (lower part used) in place (one
-// wave).  Returns 1 on a non-positive or non-finite pivot in a row < nvalid.
-__device__ int tile_cholesky(cx<double>* T, int lane, int nvalid) {
+// wave).  Returns bit 0 on a non-positive or non-finite pivot in a row <
+// nvalid, bit 1 when such a row's pivot is at most `thr` (thr > 0: twice the
+// shift that was added to the diagonal, i.e. the shift carries the pivot).
+__device__ int tile_cholesky(cx<double>* T, int lane, int nvalid, double thr) {
   int bad = 0;
   for (int k = 0; k < TSZ; ++k) {
     const double d = T[k * TRS + k].re;
+    if (thr > 0 && k < nvalid && !(d > thr)) bad |= 2;
     double piv = 1.0;
     if (d > 0 && isfinite(d))
       piv = sqrt(d);
     else if (k < nvalid)
-      bad = 1;
+      bad |= 1;
     const double inv = 1.0 / piv;
     wsync();
     if (lane > k && lane < TSZ) {
@@ -330,7 +305,6 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const cx<double>* G = Gpart + (int64_t)f * b * b;
   constexpr int BP = NT * TSZ;
-  PHASE_T0();
 
   // ---- load: lower triangle (i >= j) of the padded matrix into tiles ----
   for (int e = tid; e < BP * BP; e += CB_NT) {
@@ -357,7 +331,6 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
     L[tix(i >> 4, j >> 4) + (i & 15) * TRS + (j & 15)] = v;
   }
   __syncthreads();
-  PHASE(8);
 
   int bad = 0;
   if (mode == 1) {
@@ -375,7 +348,7 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
     // by wave 0 during step K's trailing update, right after wave 0 has
     // applied that update to it, while the other waves update the rest.
     if (wave == 0) {
-      bad |= tile_cholesky(L, lane, b);
+      bad |= tile_cholesky(L, lane, b, 2.0 * shift);
       tile_inverse(L, lane);  // X_00 = L_00^{-1}
     }
     __syncthreads();
@@ -445,17 +418,17 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
       if (wave == 0 && npairs > 0) {
         cx<double>* Dn = L + tix(K + 1, K + 1);
         wsync();  // the lanes' updates of the tile are visible to the whole wave
-        bad |= tile_cholesky(Dn, lane, b - (K + 1) * TSZ);
+        bad |= tile_cholesky(Dn, lane, b - (K + 1) * TSZ, 2.0 * shift);
         tile_inverse(Dn, lane);  // X_{K+1,K+1}
       }
       __syncthreads();
     }
-    if (tid == 0 && bad) atomicAdd(&info[INFO_CHOL_BREAKDOWN], 1);
+    if (tid == 0 && (bad & 1)) atomicAdd(&info[INFO_CHOL_BREAKDOWN], 1);
+    if (tid == 0 && (bad & 2)) atomicAdd(&info[INFO_CHOL_SHIFTED], 1);
   }
   // wave 0 carries `bad`; other waves never set it
   (void)bad;
 
-  PHASE(9);
   // ---- inverse: row by row, X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ ----
   // (lane (q, c) forms rows r = 4 u + q of column c, as in the factorisation)
   const int q = lane >> 4, c = lane & 15;
@@ -523,7 +496,6 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
     __syncthreads();
   }
 
-  PHASE(10);
   // ---- R^{-1} = X^H (upper triangular), b x b row-major ----
   cx<double>* out = Rinv + (int64_t)f * b * b;
   for (int e = tid; e < b * b; e += CB_NT) {
@@ -535,7 +507,6 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
     }
     out[e] = v;
   }
-  PHASE(11);
 }
 
 }  // namespace

@@ -24,31 +24,6 @@
 #include "common.h"
 #include "kernels.h"
 
-#ifdef TSVD_PHASE_PROF
-__device__ unsigned long long g_phase[16];
-#define PHASE_T0() unsigned long long ph_t = clock64()
-#define PHASE(i)                                            \
-  do {                                                      \
-    if (blockIdx.x == 0 && threadIdx.x == 0) {              \
-      const unsigned long long now = clock64();             \
-      atomicAdd(&g_phase[i], now - ph_t);                   \
-      ph_t = now;                                           \
-    }                                                       \
-  } while (0)
-#else
-#define PHASE_T0()
-#define PHASE(i)
-#endif
-#ifdef TSVD_PHASE_PROF
-extern "C" int tsvd_phase_read(unsigned long long* out, int reset) {
-  if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase)) != hipSuccess) return 1;
-  if (reset) {
-    unsigned long long z[16] = {};
-    if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z)) != hipSuccess) return 1;
-  }
-  return 0;
-}
-#endif
 
 namespace tsvd {
 
@@ -394,7 +369,6 @@ __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* 
     }
     return;
   }
-  PHASE_T0();
   const MatView Bg{A, m, 0};
   int cur = 0;  // which of the two vector buffers holds v_s / p_s
   auto vb = [&](int which) { return which ? vbuf1 : vbuf0; };
@@ -417,14 +391,12 @@ __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* 
     }
     __syncthreads();
   }
-  PHASE(0);
   // global phase
   int s = 0;
   bool done = false;
   for (; s < m - 1; ++s) {
     const int L = m - s - 1;
     tri_w(L, vb(cur), wb(cur), sh);
-    PHASE(1);
     if (s == m - 2) {
       tri_last(Bg, m, vb(cur), wb(cur), hv);
       done = true;
@@ -432,7 +404,6 @@ __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* 
     }
     if (L <= Lsw) break;
     tri_cde(Bg, s, m, vb(cur), wb(cur), vb(cur ^ 1), wb(cur ^ 1), hv, sh);
-    PHASE(2);
     cur ^= 1;
   }
   if (done) return;
@@ -442,19 +413,16 @@ __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* 
     for (int c = tid % 32; c < L0; c += 32) Tl[r * L0 + c] = A[(int64_t)(s + 1 + r) * m + (s + 1 + c)];
   __syncthreads();
   const MatView Bl{Tl, L0, s + 1};
-  PHASE(3);
   tri_cde(Bl, s, m, vb(cur), wb(cur), vb(cur ^ 1), wb(cur ^ 1), hv, sh);
   cur ^= 1;
   for (++s; s < m - 1; ++s) {
     const int L = m - s - 1;
     tri_w(L, vb(cur), wb(cur), sh);
-    PHASE(4);
     if (s == m - 2) {
       tri_last(Bl, m, vb(cur), wb(cur), hv);
       break;
     }
     tri_cde(Bl, s, m, vb(cur), wb(cur), vb(cur ^ 1), wb(cur ^ 1), hv, sh);
-    PHASE(5);
     cur ^= 1;
   }
 }
@@ -721,14 +689,12 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
   cx<double>* A = hv.A;
   unsigned* ctr = hv.sync;
   unsigned gen = 0;
-  PHASE_T0();
   tri_load_lower(Gpart + (int64_t)f * m * m, nsum, part_stride, m, upper_only, A, pg, P);
   for (int r = tid; r < (2 * NB + 3) * MP; r += T2_NT) vcur[r] = cx<double>{0, 0};
   const int la = lane >> 3, lb = lane & 7;
   const int T = MP / 32;
   const int w0 = pg * T2_W + wv, wstep = P * T2_W;  // this wave's first tile and tile stride
   group_sync(ctr, gen, P, info);
-  PHASE(8);
 
   // The trailing matrix is only read within a panel, so a step's column and
   // its first symv tiles are requested early: the column one step ahead, the
@@ -778,7 +744,6 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
         col[r] = a;
       }
       __syncthreads();
-      PHASE(9);
       // (2) reflector from alpha = col[i+1], x = col[i+2..m-1]
       double s2 = 0;
       for (int r = i + 2 + tid; r < m; r += T2_NT) s2 += col[r].re * col[r].re + col[r].im * col[r].im;
@@ -824,7 +789,6 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
       }
       if (tid == 0) vcur[i] = cx<double>{0, 0};
       __syncthreads();
-      PHASE(10);
       // (3a) x1 = W^H v, x2 = V^H v over rows i+1..m-1 (one wave per product)
       for (int dd = wv; dd < 2 * ii; dd += T2_W) {
         const cx<double>* X = (dd < ii ? Wl + dd * MP : Vl + (dd - ii) * MP);
@@ -894,7 +858,6 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
         }
         __syncthreads();
       }
-      PHASE(11);
       // (4) y -= V x1 + W x2; w = tau y; w += alpha v with alpha = -tau (w^H v) / 2
       //     (rows i+1..m-1, at most two per thread)
       cx<double> wl[2];
@@ -927,7 +890,6 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
         }
       }
       __syncthreads();
-      PHASE(12);
     }
     // (5) A -= V W^H + W V^H on the lower triangle of rows / columns >= j0 + pw
     const int rs = j0 + pw;
@@ -978,7 +940,6 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
       }
     }
     group_sync(ctr, gen, P, info);
-    PHASE(13);
   }
   if (tid == 0 && lead) {
     hv.d[m - 1] = A[(int64_t)(m - 1) * m + (m - 1)].re;

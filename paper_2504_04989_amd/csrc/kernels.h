@@ -121,6 +121,9 @@ hipError_t canon_phase(void* U, int64_t n1, void* V, int64_t n2, int k, int batc
                        hipStream_t s);
 // sigma = sqrt(max(lambda, 0)) (FP64) and (sigma, 0) as complex in dtype t.
 hipError_t sigma_from_lambda(const double* lambda, double* sigma, void* scx, int64_t n, DType t, hipStream_t s);
+// FP64: P (batch x n2 x k, = T_f W_k) -> sigma_j = ||P(:, j)||, V = P / sigma
+// in place, sigma (FP64) and (sigma, 0) as complex double.
+hipError_t colnorm_sigma(void* P, int64_t n2, int k, int batch, double* sigma, void* scx, hipStream_t s);
 // U * diag(sigma): Uout (batch x n1 x k) = Uin * sigma (per slice).
 hipError_t scale_cols_by(const void* Uin, const double* sigma, void* Uout, int64_t n1, int k, int batch, DType t,
                          hipStream_t s);
@@ -140,5 +143,12 @@ hipError_t tail_split(const double* lam1, const void* W1, void* W1m, int m, int 
 hipError_t tail_merge(const double* lam1, const void* W1, const double* lam2, const void* W2, const int* J, int m,
                       int k, int batch, double* lam, void* W, hipStream_t s);
 hipError_t zero_info(int* info, hipStream_t s);
+
+// The seeded Gaussian test tensor of Alg. 2 (counter-based: Philox4x32-10 and
+// a Box-Muller transform evaluated with a fixed sequence of IEEE double
+// operations, identical on the host and the device): n values, element e of
+// the stream at out[e], rounded once to dtype t on the device.
+hipError_t omega_fill(void* out, int64_t n, uint64_t seed, DType t, hipStream_t s);
+void omega_host(double* out, int64_t n, uint64_t seed);
 
 }  // namespace tsvd

@@ -111,6 +111,43 @@ hipError_t sigma_from_lambda(const double* lambda, double* sigma, void* scx, int
   return hipGetLastError();
 }
 
+// FP64 lift of the right factor: P = T_f W_k (F x n2 x k) on entry; per
+// column, sigma_j = ||P(:, j)||_2 (sum of squares in row order), then
+// V(:, j) = P(:, j) / sigma_j in place (left zero when sigma_j = 0), and sigma
+// as FP64 and as complex (sigma, 0).  ||T_f w_j|| = ||C_f^H w_j|| is sigma_j
+// to a relative accuracy of about u sigma_1 / sigma_j, where sqrt(lambda_j)
+// carries the Gram's absolute error m u lambda_1 / (2 lambda_j).
+__global__ void colnorm_sigma_kernel(cx<double>* __restrict__ P, int64_t n2, int k, int64_t total,
+                                     double* __restrict__ sigma, cx<double>* __restrict__ scx) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int c = (int)(t % k);
+  const int64_t f = t / k;
+  cx<double>* col = P + f * n2 * k + c;
+  double ss = 0.0;
+  for (int64_t i = 0; i < n2; ++i) {
+    const cx<double> v = col[i * k];
+    ss += v.re * v.re + v.im * v.im;
+  }
+  const double sg = sqrt(ss);
+  if (sg > 0) {
+    const double inv = 1.0 / sg;
+    for (int64_t i = 0; i < n2; ++i) {
+      cx<double> v = col[i * k];
+      col[i * k] = cx<double>{v.re * inv, v.im * inv};
+    }
+  }
+  sigma[t] = sg;
+  scx[t] = cx<double>{sg, 0.0};
+}
+hipError_t colnorm_sigma(void* P, int64_t n2, int k, int batch, double* sigma, void* scx, hipStream_t s) {
+  const int64_t total = (int64_t)batch * k;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(colnorm_sigma_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, (cx<double>*)P,
+                     n2, k, total, sigma, (cx<double>*)scx);
+  return hipGetLastError();
+}
+
 // R_f (r x n, dtype T, row-major) = upper-trapezoidal part of the sum of
 // nsum FP64 partial products (partial s of slice f at part + s * part_stride
 // + f * r * n complex doubles); entries below the diagonal are written as 0.

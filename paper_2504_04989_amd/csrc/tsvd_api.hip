@@ -57,6 +57,7 @@ struct Plan {
   size_t o_canon, o_rout, o_xp;
   size_t o_cbuf, o_xbuf, o_uo, o_so, o_vo;  // completion: C^(n), X^(n) and the factors of L
   size_t o_lam1, o_w1, o_w1m, o_p, o_t1, o_lam2, o_w2, o_rk, o_split;  // FP64 small SVD, second pass
+  size_t o_omsp;  // the spatial test tensor drawn from the seed (n2 x b x n3, storage type)
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
       o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, o_kpack,
       total;
@@ -163,6 +164,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   };
   const size_t cs = p->cs;
   p->o_info = take(256);
+  p->o_omsp = take(tensor_op ? 0 : (size_t)n2 * b * n3 * (p->dt == DT_F64 ? 8 : 4));
   p->o_abar = take((size_t)F * n1 * n2 * cs);
   p->o_obar = take(tensor_op ? 0 : (size_t)F * n2 * b * cs);
   p->o_q = take((size_t)F * n1 * m * cs);
@@ -892,14 +894,11 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
       Timed tm_(K_GEMM_LIFT, c.s);
       HIPCHK(zgemm(d, c.s));
     }
-    // V_f = T_f W_k diag(1/sigma)
-    {
-      Timed tm_(K_MISC, c.s);
-      HIPCHK(scale_cols(Wd, lam, c.at(p.o_wds), (int)p.m, (int)p.k, (int)p.F, 1, DT_F64, c.s));
-    }
+    // V_f = T_f W_k diag(1/sigma) with sigma_j = ||T_f w_j|| (the columns'
+    // norms resolve small sigma_j far better than sqrt(lambda_j) of the Gram)
     d.A = T;
     d.strideA = p.n2 * p.m;
-    d.B = c.at(p.o_wds);
+    d.B = Wd;
     d.C = c.at(p.o_vf);
     d.strideC = p.n2 * p.k;
     d.M = (int)p.n2;
@@ -907,12 +906,16 @@ int svd_and_lift(const Ctx& c, void* U, void* S, void* V) {
       Timed tm_(K_GEMM_LIFT, c.s);
       HIPCHK(zgemm(d, c.s));
     }
+    {
+      Timed tm_(K_MISC, c.s);
+      HIPCHK(colnorm_sigma(c.at(p.o_vf), p.n2, (int)p.k, (int)p.F, c.at<double>(p.o_sig), c.at(p.o_scx), c.s));
+    }
   }
   {
     Timed tm_(K_MISC, c.s);
     HIPCHK(canon_phase(c.at(p.o_uf), p.n1, c.at(p.o_vf), p.n2, (int)p.k, (int)p.F, dt, c.at(p.o_canon), c.s));
   }
-  {
+  if (dt == DT_F32) {
     Timed tm_(K_MISC, c.s);
     HIPCHK(sigma_from_lambda(lam, c.at<double>(p.o_sig), c.at(p.o_scx), p.F * p.k, dt, c.s));
   }
@@ -1167,6 +1170,139 @@ int check_ptrs(std::initializer_list<const void*> ptrs, const void* ws, size_t w
   return TSVD_OK;
 }
 
+
+// Omega == nullptr: the test tensor of Alg. 2 is drawn from `seed` into the
+// workspace (the seed-taking entry points); otherwise the caller's tensor is used.
+int resolve_omega(const Ctx& c, const void*& Omega, uint64_t seed) {
+  if (Omega) return TSVD_OK;
+  void* o = c.at(c.p.o_omsp);
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(omega_fill(o, c.p.n2 * c.p.b * c.p.n3, seed, c.p.dt, c.s));
+  }
+  Omega = o;
+  return TSVD_OK;
+}
+
+int need_omega(const void* Omega) {
+  if (!Omega || !aligned(Omega, 16)) return fail(TSVD_EINVAL, "null or misaligned (16 B) Omega");
+  return TSVD_OK;
+}
+
+// Alg. 2 (op RBK / APPROX / RBK_LITERAL) or Alg. 1 (POWER / POWER_APPROX) on
+// one tensor: Krylov (or power) basis, small SVD, lift, optional X_hat.
+int svd_call(bool given, int op, const void* A, const void* Omega, uint64_t seed, int64_t n1, int64_t n2, int64_t n3, int64_t k,
+             int64_t b, int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
+             void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, op, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, U, S, V}, ws, ws_bytes, p))) return r;
+  if (given && (r = need_omega(Omega))) return r;
+  if ((op == TSVD_OP_APPROX || op == TSVD_OP_POWER_APPROX) && (!Xhat || !aligned(Xhat, 16)))
+    return fail(TSVD_EINVAL, "null or misaligned (16 B) Xhat");
+  if (Xhat && !aligned(Xhat, 16)) return fail(TSVD_EINVAL, "misaligned (16 B) Xhat");
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = resolve_omega(c, Omega, seed))) return r;
+  if ((r = op == TSVD_OP_RBK_LITERAL ? krylov_literal(c, A, Omega) : krylov(c, A, Omega))) return r;
+  if ((r = svd_and_lift(c, U, S, V))) return r;
+  if (Xhat && (r = approx_tail(c, Xhat))) return r;
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int complete_call(bool given, const void* M, const void* mask, const void* Omega, uint64_t seed, int64_t n1, int64_t n2,
+                  int64_t n3, int64_t k, int64_t b, int64_t q, int64_t iters, int alg, int prec, void* C, void* ws,
+                  size_t ws_bytes, void* stream) {
+  if (alg != 1 && alg != 2) return fail(TSVD_EINVAL, "alg must be 1 (power iteration) or 2 (block Krylov)");
+  if (iters < 0 || iters > 1000000) return fail(TSVD_EINVAL, "need 0 <= iters <= 1000000");
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, alg == 2 ? TSVD_OP_COMPLETE_RBK : TSVD_OP_COMPLETE_POWER, &p);
+  if (r) return r;
+  if ((r = check_ptrs({M, C}, ws, ws_bytes, p))) return r;
+  if (!mask) return fail(TSVD_EINVAL, "null mask");
+  if (given && (r = need_omega(Omega))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  // the same test tensor at every iteration
+  if ((r = resolve_omega(c, Omega, seed))) return r;
+  const int64_t n = n1 * n2 * n3;
+  const unsigned char* T = static_cast<const unsigned char*>(mask);
+  void* Cb = c.at(p.o_cbuf);
+  {
+    // C^(0) = T (.) M
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(masked_merge(M, T, nullptr, iters == 0 ? C : Cb, n, p.dt, c.s));
+  }
+  for (int64_t it = 0; it < iters; ++it) {
+    // X^(n) = L(C^(n)): the rank-k approximation of the chosen method
+    if ((r = krylov(c, Cb, Omega))) return r;
+    if ((r = svd_and_lift(c, c.at(p.o_uo), c.at(p.o_so), c.at(p.o_vo)))) return r;
+    if ((r = approx_tail(c, c.at(p.o_xbuf)))) return r;
+    // C^(n+1) = T (.) M + (1 - T) (.) X^(n)
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(masked_merge(M, T, c.at(p.o_xbuf), it + 1 == iters ? C : Cb, n, p.dt, c.s));
+  }
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int proj_call(bool given, const void* A, const void* Omega, uint64_t seed, int64_t n1, int64_t n2, int64_t n3, int64_t b,
+              int64_t q, int prec, void* P, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, 1, b, q, prec, TSVD_OP_PROJ, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, P}, ws, ws_bytes, p))) return r;
+  if (given && (r = need_omega(Omega))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = resolve_omega(c, Omega, seed))) return r;
+  if ((r = krylov(c, A, Omega))) return r;
+  // P_f = Q_f C_f = Q_f T_f^H, written over A_f (no longer needed).
+  GemmDesc d = gd();
+  d.A = c.at(p.o_q);
+  d.lda = p.m;
+  d.strideA = p.n1 * p.m;
+  d.ta = p.dt;
+  d.B = c.at(p.o_t);
+  d.ldb = p.m;
+  d.strideB = p.n2 * p.m;
+  d.tb = p.dt;
+  d.b_conj = true;
+  d.C = c.at(p.o_abar);
+  d.ldc = p.n2;
+  d.strideC = p.n1 * p.n2;
+  d.tc = p.dt;
+  d.M = (int)p.n1;
+  d.N = (int)p.n2;
+  d.K = (int)p.m;
+  d.batch = (int)p.F;
+  d.compute = p.dt;
+  {
+    Timed tm_(K_GEMM_LIFT, c.s);
+    HIPCHK(zgemm(d, c.s));
+  }
+  {
+    Timed tm_(K_FFT_INV, c.s);
+    HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, P, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+  }
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int proj_backward_call(bool given, const void* A, const void* Omega, uint64_t seed, const void* G, int64_t n1, int64_t n2,
+                       int64_t n3, int64_t b, int64_t q, int prec, void* dA, void* ws, size_t ws_bytes, void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, 1, b, q, prec, TSVD_OP_PROJ_BWD, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, G, dA}, ws, ws_bytes, p))) return r;
+  if (given && (r = need_omega(Omega))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = resolve_omega(c, Omega, seed))) return r;
+  if ((r = proj_backward_impl(c, A, Omega, G, dA))) return r;
+  g_err.clear();
+  return TSVD_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -1181,76 +1317,71 @@ size_t tsvd_workspace_bytes(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64
   return p.total;
 }
 
-int tsvd_rbk(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q,
+int tsvd_omega(int64_t n2, int64_t b, int64_t n3, uint64_t seed, double* out_host) {
+  if (n2 < 1 || b < 1 || n3 < 1 || !out_host) return fail(TSVD_EINVAL, "need n2, b, n3 >= 1 and a host buffer");
+  if (n2 > ((int64_t)1 << 40) / b || n2 * b > ((int64_t)1 << 40) / n3)
+    return fail(TSVD_EINVAL, "n2 * b * n3 must be <= 2^40");
+  omega_host(out_host, n2 * b * n3, seed);
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int tsvd_rbk(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, uint64_t seed,
              int prec, void* U, void* S, void* V, void* ws, size_t ws_bytes, void* stream) {
-  Plan p;
-  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_RBK, &p);
-  if (r) return r;
-  if ((r = check_ptrs({A, Omega, U, S, V}, ws, ws_bytes, p))) return r;
-  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
-  if ((r = krylov(c, A, Omega))) return r;
-  if ((r = svd_and_lift(c, U, S, V))) return r;
-  g_err.clear();
-  return TSVD_OK;
+  return svd_call(false, TSVD_OP_RBK, A, nullptr, seed, n1, n2, n3, k, b, q, prec, U, S, V, nullptr, ws, ws_bytes, stream);
 }
 
-int tsvd_rbk_approx(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
-                    int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
+int tsvd_rbk_omega(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                   int64_t q, int prec, void* U, void* S, void* V, void* ws, size_t ws_bytes, void* stream) {
+  return svd_call(true, TSVD_OP_RBK, A, Omega, 0, n1, n2, n3, k, b, q, prec, U, S, V, nullptr, ws, ws_bytes, stream);
+}
+
+int tsvd_rbk_approx(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q,
+                    uint64_t seed, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
                     void* stream) {
-  Plan p;
-  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_APPROX, &p);
-  if (r) return r;
-  if ((r = check_ptrs({A, Omega, U, S, V, Xhat}, ws, ws_bytes, p))) return r;
-  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
-  if ((r = krylov(c, A, Omega))) return r;
-  if ((r = svd_and_lift(c, U, S, V))) return r;
-  if ((r = approx_tail(c, Xhat))) return r;
-  g_err.clear();
-  return TSVD_OK;
+  return svd_call(false, TSVD_OP_APPROX, A, nullptr, seed, n1, n2, n3, k, b, q, prec, U, S, V, Xhat, ws, ws_bytes, stream);
 }
 
-int tsvd_power(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
-               int64_t q, int prec, void* U, void* S, void* V, void* ws, size_t ws_bytes, void* stream) {
-  Plan p;
-  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_POWER, &p);
-  if (r) return r;
-  if ((r = check_ptrs({A, Omega, U, S, V}, ws, ws_bytes, p))) return r;
-  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
-  if ((r = krylov(c, A, Omega))) return r;
-  if ((r = svd_and_lift(c, U, S, V))) return r;
-  g_err.clear();
-  return TSVD_OK;
+int tsvd_rbk_approx_omega(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                          int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
+                          void* stream) {
+  return svd_call(true, TSVD_OP_APPROX, A, Omega, 0, n1, n2, n3, k, b, q, prec, U, S, V, Xhat, ws, ws_bytes, stream);
 }
 
-int tsvd_power_approx(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
-                      int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
+int tsvd_power(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, uint64_t seed,
+               int prec, void* U, void* S, void* V, void* ws, size_t ws_bytes, void* stream) {
+  return svd_call(false, TSVD_OP_POWER, A, nullptr, seed, n1, n2, n3, k, b, q, prec, U, S, V, nullptr, ws, ws_bytes, stream);
+}
+
+int tsvd_power_omega(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                     int64_t q, int prec, void* U, void* S, void* V, void* ws, size_t ws_bytes, void* stream) {
+  return svd_call(true, TSVD_OP_POWER, A, Omega, 0, n1, n2, n3, k, b, q, prec, U, S, V, nullptr, ws, ws_bytes, stream);
+}
+
+int tsvd_power_approx(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q,
+                      uint64_t seed, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
                       void* stream) {
-  Plan p;
-  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_POWER_APPROX, &p);
-  if (r) return r;
-  if ((r = check_ptrs({A, Omega, U, S, V, Xhat}, ws, ws_bytes, p))) return r;
-  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
-  if ((r = krylov(c, A, Omega))) return r;
-  if ((r = svd_and_lift(c, U, S, V))) return r;
-  if ((r = approx_tail(c, Xhat))) return r;
-  g_err.clear();
-  return TSVD_OK;
+  return svd_call(false, TSVD_OP_POWER_APPROX, A, nullptr, seed, n1, n2, n3, k, b, q, prec, U, S, V, Xhat, ws, ws_bytes,
+                  stream);
 }
 
-int tsvd_rbk_literal(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
-                     int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
+int tsvd_power_approx_omega(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k,
+                            int64_t b, int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws,
+                            size_t ws_bytes, void* stream) {
+  return svd_call(true, TSVD_OP_POWER_APPROX, A, Omega, 0, n1, n2, n3, k, b, q, prec, U, S, V, Xhat, ws, ws_bytes, stream);
+}
+
+int tsvd_rbk_literal(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q,
+                     uint64_t seed, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
                      void* stream) {
-  Plan p;
-  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_RBK_LITERAL, &p);
-  if (r) return r;
-  if ((r = check_ptrs({A, Omega, U, S, V}, ws, ws_bytes, p))) return r;
-  if (Xhat && !aligned(Xhat, 16)) return fail(TSVD_EINVAL, "misaligned (16 B) Xhat");
-  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
-  if ((r = krylov_literal(c, A, Omega))) return r;
-  if ((r = svd_and_lift(c, U, S, V))) return r;
-  if (Xhat && (r = approx_tail(c, Xhat))) return r;
-  g_err.clear();
-  return TSVD_OK;
+  return svd_call(false, TSVD_OP_RBK_LITERAL, A, nullptr, seed, n1, n2, n3, k, b, q, prec, U, S, V, Xhat, ws, ws_bytes,
+                  stream);
+}
+
+int tsvd_rbk_literal_omega(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                           int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
+                           void* stream) {
+  return svd_call(true, TSVD_OP_RBK_LITERAL, A, Omega, 0, n1, n2, n3, k, b, q, prec, U, S, V, Xhat, ws, ws_bytes, stream);
 }
 
 int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void* Q, void* R, void* ws,
@@ -1325,88 +1456,36 @@ int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void
   return TSVD_OK;
 }
 
-int tsvd_complete(const void* M, const void* mask, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k,
-                  int64_t b, int64_t q, int64_t iters, int alg, int prec, void* C, void* ws, size_t ws_bytes,
+int tsvd_complete(const void* M, const void* mask, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                  int64_t q, uint64_t seed, int64_t iters, int alg, int prec, void* C, void* ws, size_t ws_bytes,
                   void* stream) {
-  if (alg != 1 && alg != 2) return fail(TSVD_EINVAL, "alg must be 1 (power iteration) or 2 (block Krylov)");
-  if (iters < 0 || iters > 1000000) return fail(TSVD_EINVAL, "need 0 <= iters <= 1000000");
-  Plan p;
-  int r = make_plan(n1, n2, n3, k, b, q, prec, alg == 2 ? TSVD_OP_COMPLETE_RBK : TSVD_OP_COMPLETE_POWER, &p);
-  if (r) return r;
-  if ((r = check_ptrs({M, Omega, C}, ws, ws_bytes, p))) return r;
-  if (!mask) return fail(TSVD_EINVAL, "null mask");
-  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
-  const int64_t n = n1 * n2 * n3;
-  const unsigned char* T = static_cast<const unsigned char*>(mask);
-  void* Cb = c.at(p.o_cbuf);
-  {
-    // C^(0) = T (.) M
-    Timed tm_(K_MISC, c.s);
-    HIPCHK(masked_merge(M, T, nullptr, iters == 0 ? C : Cb, n, p.dt, c.s));
-  }
-  for (int64_t it = 0; it < iters; ++it) {
-    // X^(n) = L(C^(n)): the rank-k approximation of the chosen method
-    if ((r = krylov(c, Cb, Omega))) return r;
-    if ((r = svd_and_lift(c, c.at(p.o_uo), c.at(p.o_so), c.at(p.o_vo)))) return r;
-    if ((r = approx_tail(c, c.at(p.o_xbuf)))) return r;
-    // C^(n+1) = T (.) M + (1 - T) (.) X^(n)
-    Timed tm_(K_MISC, c.s);
-    HIPCHK(masked_merge(M, T, c.at(p.o_xbuf), it + 1 == iters ? C : Cb, n, p.dt, c.s));
-  }
-  g_err.clear();
-  return TSVD_OK;
+  return complete_call(false, M, mask, nullptr, seed, n1, n2, n3, k, b, q, iters, alg, prec, C, ws, ws_bytes, stream);
 }
 
-int tsvd_proj(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t b, int64_t q, int prec,
+int tsvd_complete_omega(const void* M, const void* mask, const void* Omega, int64_t n1, int64_t n2, int64_t n3,
+                        int64_t k, int64_t b, int64_t q, int64_t iters, int alg, int prec, void* C, void* ws,
+                        size_t ws_bytes, void* stream) {
+  return complete_call(true, M, mask, Omega, 0, n1, n2, n3, k, b, q, iters, alg, prec, C, ws, ws_bytes, stream);
+}
+
+int tsvd_proj(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t b, int64_t q, uint64_t seed, int prec,
               void* P, void* ws, size_t ws_bytes, void* stream) {
-  Plan p;
-  int r = make_plan(n1, n2, n3, 1, b, q, prec, TSVD_OP_PROJ, &p);
-  if (r) return r;
-  if ((r = check_ptrs({A, Omega, P}, ws, ws_bytes, p))) return r;
-  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
-  if ((r = krylov(c, A, Omega))) return r;
-  // P_f = Q_f C_f = Q_f T_f^H, written over A_f (no longer needed).
-  GemmDesc d = gd();
-  d.A = c.at(p.o_q);
-  d.lda = p.m;
-  d.strideA = p.n1 * p.m;
-  d.ta = p.dt;
-  d.B = c.at(p.o_t);
-  d.ldb = p.m;
-  d.strideB = p.n2 * p.m;
-  d.tb = p.dt;
-  d.b_conj = true;
-  d.C = c.at(p.o_abar);
-  d.ldc = p.n2;
-  d.strideC = p.n1 * p.n2;
-  d.tc = p.dt;
-  d.M = (int)p.n1;
-  d.N = (int)p.n2;
-  d.K = (int)p.m;
-  d.batch = (int)p.F;
-  d.compute = p.dt;
-  {
-    Timed tm_(K_GEMM_LIFT, c.s);
-    HIPCHK(zgemm(d, c.s));
-  }
-  {
-    Timed tm_(K_FFT_INV, c.s);
-    HIPCHK(fft_c2r(c.at(p.o_abar), p.n1 * p.n2, P, p.n1 * p.n2, (int)p.n3, p.dt, c.s));
-  }
-  g_err.clear();
-  return TSVD_OK;
+  return proj_call(false, A, nullptr, seed, n1, n2, n3, b, q, prec, P, ws, ws_bytes, stream);
 }
 
-int tsvd_proj_backward(const void* A, const void* Omega, const void* G, int64_t n1, int64_t n2, int64_t n3, int64_t b,
-                       int64_t q, int prec, void* dA, void* ws, size_t ws_bytes, void* stream) {
-  Plan p;
-  int r = make_plan(n1, n2, n3, 1, b, q, prec, TSVD_OP_PROJ_BWD, &p);
-  if (r) return r;
-  if ((r = check_ptrs({A, Omega, G, dA}, ws, ws_bytes, p))) return r;
-  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
-  if ((r = proj_backward_impl(c, A, Omega, G, dA))) return r;
-  g_err.clear();
-  return TSVD_OK;
+int tsvd_proj_omega(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t b, int64_t q,
+                    int prec, void* P, void* ws, size_t ws_bytes, void* stream) {
+  return proj_call(true, A, Omega, 0, n1, n2, n3, b, q, prec, P, ws, ws_bytes, stream);
+}
+
+int tsvd_proj_backward(const void* A, const void* G, int64_t n1, int64_t n2, int64_t n3, int64_t b, int64_t q,
+                       uint64_t seed, int prec, void* dA, void* ws, size_t ws_bytes, void* stream) {
+  return proj_backward_call(false, A, nullptr, seed, G, n1, n2, n3, b, q, prec, dA, ws, ws_bytes, stream);
+}
+
+int tsvd_proj_backward_omega(const void* A, const void* Omega, const void* G, int64_t n1, int64_t n2, int64_t n3,
+                             int64_t b, int64_t q, int prec, void* dA, void* ws, size_t ws_bytes, void* stream) {
+  return proj_backward_call(true, A, Omega, 0, G, n1, n2, n3, b, q, prec, dA, ws, ws_bytes, stream);
 }
 
 int tsvd_read_info(const void* ws, int32_t* info_host, void* stream) {
@@ -1415,6 +1494,14 @@ int tsvd_read_info(const void* ws, int32_t* info_host, void* stream) {
                                 (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return fail(TSVD_EHIP, hipGetErrorString(e));
+  if (info_host[TSVD_INFO_CHOL_BREAKDOWN] || info_host[TSVD_INFO_EIG_NOCONV] || info_host[TSVD_INFO_NONFINITE]) {
+    char msg[192];
+    snprintf(msg, sizeof msg, "numerical failure on the device: %d Cholesky breakdowns, %d unconverged eigenvectors, "
+             "%d non-finite values", info_host[TSVD_INFO_CHOL_BREAKDOWN], info_host[TSVD_INFO_EIG_NOCONV],
+             info_host[TSVD_INFO_NONFINITE]);
+    return fail(TSVD_ENUMERIC, msg);
+  }
+  g_err.clear();
   return TSVD_OK;
 }
 
@@ -1423,6 +1510,12 @@ int tsvd_read_info(const void* ws, int32_t* info_host, void* stream) {
 #include "../../include/tsvd_rbk_diag.h"
 
 extern "C" {
+
+int tsvd_diag_omega(void* out, int64_t n, uint64_t seed, int dtype, void* stream) {
+  if (!out || n < 0 || n > ((int64_t)1 << 40) || (dtype != 0 && dtype != 1)) return fail(TSVD_EINVAL, "bad arguments");
+  HIPCHK(omega_fill(out, n, seed, dtype == 0 ? DT_F64 : DT_F32, (hipStream_t)stream));
+  return TSVD_OK;
+}
 
 int tsvd_diag_fft_r2c(const void* X, void* Xb, int64_t ntubes, int64_t n3, int dtype, void* stream) {
   if (!X || !Xb || ntubes < 0 || n3 < 1 || n3 > 4096 || (dtype != 0 && dtype != 1))

@@ -249,11 +249,119 @@ COMPLETION_CONFIGS = {
 }
 
 
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers:
+    as easy as 1, 2, 3", SC'11), vectorised over counters.  ctr: uint32 array
+    (..., 4); key: two uint32 words.  Ten rounds; each multiplies words 0 and 2
+    by 0xD2511F53 and 0xCD9E8D57 (32 x 32 -> 64 bits), mixes the high halves
+    with words 1 and 3 and the key, and the key is bumped by 0x9E3779B9 and
+    0xBB67AE85 after every round.  Returns uint32 array (..., 4)."""
+    c = [np.asarray(ctr[..., i], dtype=np.uint64) for i in range(4)]
+    k0, k1 = np.uint64(int(key[0]) & 0xFFFFFFFF), np.uint64(int(key[1]) & 0xFFFFFFFF)
+    mask = np.uint64(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = np.uint64(0xD2511F53) * c[0]
+        p1 = np.uint64(0xCD9E8D57) * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+        k0 = (k0 + np.uint64(0x9E3779B9)) & mask
+        k1 = (k1 + np.uint64(0xBB67AE85)) & mask
+    return np.stack([x.astype(np.uint32) for x in c], axis=-1)
+
+
+def _unit(hi, lo):
+    """Uniform in (0, 1): (2 x + 1) 2^-53 with the 52-bit integer
+    x = (hi >> 6) 2^26 + (lo >> 6)."""
+    x = (hi.astype(np.uint64) >> np.uint64(6) << np.uint64(26)) | (lo.astype(np.uint64) >> np.uint64(6))
+    return (2 * x + 1).astype(np.float64) * 2.0 ** -53
+
+
+def _log_unit(u):
+    """ln u for u in (0, 1), as a fixed sequence of IEEE double operations:
+    u = 2^e m with m in (sqrt(1/2), sqrt(2)], ln m = 2 atanh(s),
+    s = (m - 1)/(m + 1), atanh by its Taylor series to s^21."""
+    m, e = np.frexp(u)               # u = m 2^e, m in [0.5, 1)
+    m = m * 2.0
+    e = e - 1                        # m in [1, 2)
+    big = m > float.fromhex("0x1.6a09e667f3bcdp+0")
+    m = np.where(big, m * 0.5, m)
+    e = np.where(big, e + 1, e)
+    s = (m - 1.0) / (m + 1.0)
+    s2 = s * s
+    p = np.full_like(s, 1.0 / 21.0)
+    for d in (19.0, 17.0, 15.0, 13.0, 11.0, 9.0, 7.0, 5.0, 3.0):
+        p = p * s2 + 1.0 / d
+    p = p * s2 + 1.0
+    lm = 2.0 * s * p
+    return e.astype(np.float64) * float.fromhex("0x1.62e42fefa39efp-1") + lm
+
+
+def _sqrt_newton(x):
+    """sqrt x: five Newton steps y <- (y + x / y) / 2 from the guess with
+    the halved exponent (bits(x) >> 1) + 0x1ff8000000000000."""
+    y = ((x.view(np.uint64) >> np.uint64(1)) + np.uint64(0x1FF8000000000000)).view(np.float64)
+    for _ in range(5):
+        y = 0.5 * (y + x / y)
+    return y
+
+
+def _sincos_2pi(u):
+    """(cos 2 pi u, sin 2 pi u) for u in (0, 1): quadrant j = floor(4 u), the
+    Taylor series of sin and cos of x = (pi/2)(4 u - j) to degree 25 and 24
+    (Horner in x^2, alternating signs), rotated by j; a fixed sequence of IEEE
+    double operations."""
+    import math
+    inv = {d: 1.0 / float(math.factorial(d)) for d in range(2, 26)}
+    v = u * 4.0
+    j = v.astype(np.int64)
+    x = (v - j.astype(np.float64)) * float.fromhex("0x1.921fb54442d18p+0")
+    x2 = x * x
+    ps = np.full_like(x, inv[25])
+    for d in range(23, 2, -2):                 # -1/23!, +1/21!, ..., -1/3!
+        ps = ps * x2 - inv[d] if (d // 2) % 2 == 1 else ps * x2 + inv[d]
+    pc = np.full_like(x, inv[24])
+    for d in range(22, 1, -2):                 # -1/22!, +1/20!, ..., -1/2!
+        pc = pc * x2 - inv[d] if (d // 2) % 2 == 1 else pc * x2 + inv[d]
+    sn = x + x * x2 * ps
+    cs = 1.0 + x2 * pc
+    q = j & 3
+    c = np.select([q == 0, q == 1, q == 2], [cs, -sn, -cs], sn)
+    s = np.select([q == 0, q == 1, q == 2], [sn, cs, -sn], -cs)
+    return c, s
+
+
+def omega_counter(n: int, seed: int) -> np.ndarray:
+    """The first n values of the seeded Gaussian stream of the test tensor
+    Omega (Alg. 2 draws randn): element e takes pair p = e // 2 of a
+    Box-Muller transform of Philox4x32-10(counter (p_lo, p_hi, 0, 0), key
+    (seed_lo, seed_hi)), r cos(theta) for even e and r sin(theta) for odd e,
+    with u1, u2 from the words (0, 1) and (2, 3), r = sqrt(-2 ln u1),
+    theta = 2 pi u2."""
+    seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    npairs = (n + 1) // 2
+    out = np.empty(2 * npairs, dtype=np.float64)
+    chunk = 1 << 22
+    for p0 in range(0, npairs, chunk):
+        p = np.arange(p0, min(npairs, p0 + chunk), dtype=np.uint64)
+        ctr = np.zeros(p.shape + (4,), dtype=np.uint64)
+        ctr[:, 0] = p & np.uint64(0xFFFFFFFF)
+        ctr[:, 1] = p >> np.uint64(32)
+        w = philox4x32_10(ctr, (seed & 0xFFFFFFFF, seed >> 32))
+        u1 = _unit(w[:, 0], w[:, 1])
+        u2 = _unit(w[:, 2], w[:, 3])
+        r = _sqrt_newton(-2.0 * _log_unit(u1))
+        c, s = _sincos_2pi(u2)
+        out[2 * p0:2 * p0 + 2 * p.size:2] = r * c
+        out[2 * p0 + 1:2 * p0 + 2 * p.size:2] = r * s
+    return out[:n]
+
+
 def omega(n2, b, n3, seed):
     """Gaussian test tensor Omega ~ N(0, 1), n2 x b x n3 (Alg. 2, first line,
-    with n2 rows), from the seed's second stream."""
-    _, rng = _streams(seed)
-    return np.ascontiguousarray(rng.standard_normal((n2, b, n3)))
+    with n2 rows): element (j, c, t) is value (j b + c) n3 + t of the seeded
+    counter-based stream (omega_counter)."""
+    return np.ascontiguousarray(omega_counter(n2 * b * n3, seed).reshape(n2, b, n3))
 
 
 def make_config(name: str):

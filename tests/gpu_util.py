@@ -58,8 +58,14 @@ def fp32_twin_slice(A, Om, k, b, q, f):
     Test infrastructure: it measures what a plain FP32 computation of the slice
     reaches, so that a GPU error can be told apart from the FP32 limit."""
     w = np.exp(-2j * np.pi * f * np.arange(A.shape[2]) / A.shape[2])
-    Af = (A @ w).astype(np.complex64)
-    Of = (Om @ w).astype(np.complex64)
+    return fp32_twin_slice_f(A @ w, Om @ w, k, b, q)
+
+
+def fp32_twin_slice_f(Af, Of, k, b, q):
+    """fp32_twin_slice on a slice whose DFT is already taken (Af n1 x n2,
+    Of n2 x b), rounded here to complex64."""
+    Af = np.asarray(Af).astype(np.complex64)
+    Of = np.asarray(Of).astype(np.complex64)
     Qs = [np.linalg.qr(Af @ Of)[0]]
     for _ in range(q):
         W = Af @ (Af.conj().T @ Qs[-1])

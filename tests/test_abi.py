@@ -68,15 +68,15 @@ def test_entry_points_reject_bad_pointers_without_touching_the_gpu():
     from paper_2504_04989_amd import api
     L = api.lib
     nul = ctypes.c_void_p(0)
-    r = L.tsvd_rbk(nul, nul, 10, 10, 4, 2, 3, 1, 1, nul, nul, nul, nul, 0, nul)
+    r = L.tsvd_rbk_omega(nul, nul, 10, 10, 4, 2, 3, 1, 1, nul, nul, nul, nul, 0, nul)
     assert r == api.TSVD_EINVAL
-    r = L.tsvd_rbk(nul, nul, 10, 10, 4, 5, 3, 1, 1, nul, nul, nul, nul, 0, nul)   # k > b
+    r = L.tsvd_rbk_omega(nul, nul, 10, 10, 4, 5, 3, 1, 1, nul, nul, nul, nul, 0, nul)   # k > b
     assert r == api.TSVD_EINVAL and "k <= b" in L.tsvd_last_error().decode()
-    r = L.tsvd_proj(nul, nul, 10, 10, 4, 3, 1, 7, nul, nul, 0, nul)               # bad precision
+    r = L.tsvd_proj_omega(nul, nul, 10, 10, 4, 3, 1, 7, nul, nul, 0, nul)               # bad precision
     assert r == api.TSVD_EINVAL
     # aligned fake pointers but a workspace that is too small -> ENOMEM, nothing launched
     fake = ctypes.c_void_p(1 << 20)
-    r = L.tsvd_rbk(fake, fake, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, fake, 16, nul)
+    r = L.tsvd_rbk_omega(fake, fake, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, fake, 16, nul)
     assert r == api.TSVD_ENOMEM
     r = L.tsvd_diag_zgemm(nul, 0, nul, 0, nul, 4, 4, 4, 1, 1.0, 0.0, 1, nul)
     assert r == api.TSVD_EINVAL
@@ -96,10 +96,10 @@ def test_power_method_sizes_and_rejections():
     L = api.lib
     nul = ctypes.c_void_p(0)
     fake = ctypes.c_void_p(1 << 20)
-    assert L.tsvd_power(nul, nul, 10, 10, 4, 2, 3, 1, 1, nul, nul, nul, nul, 0, nul) == api.TSVD_EINVAL
-    r = L.tsvd_power_approx(fake, fake, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, fake, fake, 16, nul)
+    assert L.tsvd_power_omega(nul, nul, 10, 10, 4, 2, 3, 1, 1, nul, nul, nul, nul, 0, nul) == api.TSVD_EINVAL
+    r = L.tsvd_power_approx_omega(fake, fake, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, fake, fake, 16, nul)
     assert r == api.TSVD_ENOMEM
-    r = L.tsvd_power(fake, fake, 10, 10, 4, 2, 3, 5000, 1, fake, fake, fake, fake, 1 << 30, nul)   # q too large
+    r = L.tsvd_power_omega(fake, fake, 10, 10, 4, 2, 3, 5000, 1, fake, fake, fake, fake, 1 << 30, nul)   # q too large
     assert r == api.TSVD_EINVAL
 
 
@@ -129,10 +129,10 @@ def test_completion_sizes_and_rejections():
     nul = ctypes.c_void_p(0)
     fake = ctypes.c_void_p(1 << 20)
     args = (fake, fake, fake, 64, 96, 3, 5, 8, 2)
-    assert L.tsvd_complete(*args, 10, 3, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL      # bad alg
-    assert L.tsvd_complete(*args, -1, 2, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL      # iters < 0
-    assert L.tsvd_complete(*args, 10, 2, 1, fake, fake, 16, nul) == api.TSVD_ENOMEM
-    assert L.tsvd_complete(fake, nul, fake, 64, 96, 3, 5, 8, 2, 10, 2, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL
+    assert L.tsvd_complete_omega(*args, 10, 3, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL      # bad alg
+    assert L.tsvd_complete_omega(*args, -1, 2, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL      # iters < 0
+    assert L.tsvd_complete_omega(*args, 10, 2, 1, fake, fake, 16, nul) == api.TSVD_ENOMEM
+    assert L.tsvd_complete_omega(fake, nul, fake, 64, 96, 3, 5, 8, 2, 10, 2, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL
 
 
 def test_literal_sizes_and_rejections():
@@ -142,7 +142,42 @@ def test_literal_sizes_and_rejections():
     L = api.lib
     nul = ctypes.c_void_p(0)
     fake = ctypes.c_void_p(1 << 20)
-    assert L.tsvd_rbk_literal(fake, fake, 10, 10, 4, 2, 4, 2, 1, fake, fake, fake, nul, fake, 1 << 30, nul) \
+    assert L.tsvd_rbk_literal_omega(fake, fake, 10, 10, 4, 2, 4, 2, 1, fake, fake, fake, nul, fake, 1 << 30, nul) \
         == api.TSVD_EINVAL                                                   # m = 12 > 10
-    assert L.tsvd_rbk_literal(fake, fake, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, nul, fake, 16, nul) \
+    assert L.tsvd_rbk_literal_omega(fake, fake, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, nul, fake, 16, nul) \
         == api.TSVD_ENOMEM
+
+
+def test_seed_entry_points_reject_bad_arguments_on_the_host():
+    # the seed-taking forms validate like their _omega twins, before any launch
+    from paper_2504_04989_amd import api
+    L = api.lib
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.tsvd_rbk(nul, 10, 10, 4, 2, 3, 1, 7, 1, nul, nul, nul, nul, 0, nul) == api.TSVD_EINVAL
+    assert L.tsvd_rbk(fake, 10, 10, 4, 2, 3, 1, 7, 1, fake, fake, fake, fake, 16, nul) == api.TSVD_ENOMEM
+    assert L.tsvd_rbk_approx(fake, 10, 10, 4, 2, 3, 1, 7, 1, fake, fake, fake, nul, fake, 1 << 30, nul) \
+        == api.TSVD_EINVAL                                                   # Xhat missing
+    assert L.tsvd_proj(fake, 10, 10, 4, 3, 1, 7, 9, fake, fake, 1 << 30, nul) == api.TSVD_EINVAL   # bad precision
+    assert L.tsvd_proj_backward(fake, nul, 10, 10, 4, 3, 1, 7, 1, fake, fake, 1 << 30, nul) == api.TSVD_EINVAL
+    assert L.tsvd_complete(fake, fake, 64, 96, 3, 5, 8, 2, 7, 10, 3, 1, fake, fake, 1 << 40, nul) == api.TSVD_EINVAL
+    assert L.tsvd_power(fake, 10, 10, 4, 2, 11, 1, 7, 1, fake, fake, fake, fake, 1 << 30, nul) == api.TSVD_EINVAL
+    # the _omega twins need the tensor
+    assert L.tsvd_rbk_omega(fake, nul, 10, 10, 4, 2, 3, 1, 1, fake, fake, fake, fake, 1 << 30, nul) \
+        == api.TSVD_EINVAL
+    assert "Omega" in L.tsvd_last_error().decode()
+
+
+def test_seeded_omega_on_the_host_matches_the_input_generator():
+    # tsvd_omega (the library's host copy of the generator the seed-taking
+    # entry points run on the device) against the independent numpy
+    # implementation of the same Philox4x32-10 / Box-Muller stream, bit for bit
+    import numpy as np
+    from paper_2504_04989_amd import api, inputs
+    for shape, seed in (((7, 3, 5), 0), ((64, 10, 16), 0), ((33, 4, 9), 2**40 + 17), ((1, 1, 1), 5)):
+        a = api.omega(*shape, seed)
+        b = inputs.omega(*shape, seed)
+        assert a.dtype == np.float64 and np.array_equal(a, b), (shape, seed)
+    assert api.lib.tsvd_omega(0, 3, 4, 1, ctypes.c_void_p(1 << 20)) == api.TSVD_EINVAL
+    assert api.lib.tsvd_omega(3, 3, 4, 1, ctypes.c_void_p(0)) == api.TSVD_EINVAL
+    assert api.lib.tsvd_omega(1 << 20, 1 << 20, 2, 1, ctypes.c_void_p(1 << 20)) == api.TSVD_EINVAL   # > 2^40

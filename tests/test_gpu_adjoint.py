@@ -26,18 +26,57 @@ def test_backward_fp64_vs_oracle(shape, b, q):
     G = inputs.random_tensor(shape, 12)
     dA = host(api.tsvd_proj_backward(dev(A), dev(Om), dev(G), b, q))
     ref = O.proj_backward(A, Om, G, b, q)
-    assert rel_f(dA, ref) <= 1e-9
+    e = rel_f(dA, ref)
+    print(f"[adjoint]   rel err vs oracle {e:.2e}", flush=True)
+    assert e <= 1e-10
+
+
+def _c4_crop():
+    """The 40 x 40 x 8 crop of the 2000 x 2000 x 16 completion workload
+    (T and the mask cropped, X0 = M (.) T on the crop) with b = 10, q = 2
+    (reading R11: b = 30 would give m = 90 > 40) and the workload's seed."""
+    _, _, c = inputs.make_config("c4_completion_2000x2000x16")
+    T, M = c["T"][:40, :40, :8].copy(), c["M"][:40, :40, :8].copy()
+    return T, M, M * T, 10, 2, c["seed"]
 
 
 def test_backward_fp32_crop_vs_oracle():
-    T, M, X0 = inputs.completion_problem(40, 40, 8, 5, 0.3, seed=3)
-    Om = inputs.omega(40, 10, 8, 3)
-    X0, Om = _cast(X0, "f32"), _cast(Om, "f32")
-    P = O.proj(X0, Om, 10, 2)
+    T, M, X0, b, q, seed = _c4_crop()
+    Om = _cast(inputs.omega(40, b, 8, seed), "f32")
+    X0 = _cast(X0, "f32")
+    P = O.proj(X0, Om, b, q)
     G = _cast(-2.0 * M * (T - P), "f32")
-    dA = host(api.tsvd_proj_backward(dev(X0, torch.float32), dev(Om, torch.float32), dev(G, torch.float32), 10, 2))
-    ref = O.proj_backward(X0, Om, G, 10, 2)
-    assert rel_f(dA.astype(np.float64), ref) <= 1e-3
+    dA = host(api.tsvd_proj_backward(dev(X0, torch.float32), seed, dev(G, torch.float32), b, q))
+    ref = O.proj_backward(X0, Om, G, b, q)
+    e = rel_f(dA.astype(np.float64), ref)
+    print(f"[adjoint] c4 crop FP32 gradient rel err vs oracle {e:.2e}", flush=True)
+    assert e <= 1e-4
+
+
+def test_config4_crop_finite_differences():
+    """Central finite differences of the masked loss ||M (.) (T - P(X))||^2 on
+    the crop, FP64: the gradient through the hand-written adjoint against
+    (L(X + h D) - L(X - h D)) / 2h in 8 random directions, h = 1e-6 max|X|."""
+    T, M, X0, b, q, seed = _c4_crop()
+    Td, Md = dev(T), dev(M)
+
+    def loss(X):
+        P = api.tsvd_proj(dev(X), seed, b, q, "f64")
+        return float(((Md * (Td - P)) ** 2).sum())
+
+    X = dev(X0).requires_grad_(True)
+    L = ((Md * (Td - api.TProject.apply(X, seed, b, q, "f64"))) ** 2).sum()
+    L.backward()
+    g = host(X.grad)
+    rng = np.random.default_rng(3)
+    h = 1e-6 * np.max(np.abs(X0))
+    for i in range(8):
+        D = rng.standard_normal(X0.shape)
+        fd = (loss(X0 + h * D) - loss(X0 - h * D)) / (2 * h)
+        an = float(np.sum(g * D))
+        print(f"[adjoint] c4 crop direction {i}: FD {fd:.10e} adjoint {an:.10e} rel {abs(fd - an) / abs(fd):.1e}",
+              flush=True)
+        assert abs(fd - an) <= 1e-6 * abs(fd)
 
 
 def test_backward_directional_finite_differences_fp64():
@@ -99,7 +138,7 @@ def test_config4_full_size_fp32():
     lhs, rhs = np.sum(dA * X0), np.sum(G * P)
     print(f"[adjoint] c4 Euler rel {abs(lhs - rhs) / abs(rhs):.2e}", flush=True)
     assert abs(lhs - rhs) <= 1e-4 * abs(rhs)
-    freqs = [0, 5]
+    freqs = [0, 3, 5, 8]
     Ab, Ob, Gb = (O.dft_mode3(x, freqs) for x in (X0, Om, G))
     Pb, Db = np.fft.fft(P, axis=2), np.fft.fft(dA, axis=2)
     for j, f in enumerate(freqs):
@@ -110,4 +149,4 @@ def test_config4_full_size_fp32():
         ed = rel_f(Db[:, :, f], Df)
         print(f"[adjoint] c4 slice {f}: projection rel err {ep:.2e}, gradient rel err {ed:.2e}", flush=True)
         assert ep <= 1e-5
-        assert ed <= 1e-3
+        assert ed <= 1e-4

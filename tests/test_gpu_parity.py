@@ -12,7 +12,7 @@ import torch
 
 from oracle import tsvd_oracle as O
 from paper_2504_04989_amd import inputs
-from tests.gpu_util import load_api, dev, fourier_factors, fp32_twin_slice, host, rel_f, unambiguous_phase_columns
+from tests.gpu_util import DEV, load_api, dev, fourier_factors, host, rel_f, unambiguous_phase_columns
 
 pytestmark = pytest.mark.gpu
 api = load_api()
@@ -49,6 +49,7 @@ def _compare(A, Om, k, b, q, prec, factors=True, sv_tol=None):
     Ub, Sb, Vb = fourier_factors(U, S, V, list(range(F)))
     assert np.max(np.abs(Sb.imag)) <= 1e-6 * np.max(np.abs(Sb)) + 1e-300
     s_err = np.max(np.abs(Sb.real - sl["Sf"]) / np.maximum(sl["Sf"], 1e-300))
+    print(f"[parity]   X rel {e:.2e}, sigma rel {s_err:.2e}", flush=True)
     assert s_err <= (sv_tol or tol), f"sigma rel err {s_err:.3e}"
     if factors:
         for f in range(F):
@@ -81,7 +82,7 @@ def test_small_shapes(shape, k, b, q, prec):
     n1, n2, n3 = shape
     A = inputs.lowrank_tensor(n1, n2, n3, min(n1, n2) // 2, ("geom", 0.9), 1e-3, seed=sum(shape))
     Om = inputs.omega(n2, b, n3, seed=sum(shape))
-    _compare(A, Om, k, b, q, prec, sv_tol=TOL[prec] * (10 if prec == "f32" else 1))
+    _compare(A, Om, k, b, q, prec)
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
@@ -154,36 +155,56 @@ def test_config2_fp32_full_size_sampled_slices():
         assert s_err <= 1e-5
 
 
-def _slice_xhat(sl, j):
-    return (sl["Uf"][:, :, j] * sl["Sf"][:, j]) @ sl["Vf"][:, :, j].conj().T
+C5_FREQS = [0, 5, 9, 14, 18, 23, 27, 32]      # the 8 sampled Fourier slices of the 4096 x 4096 x 64 workload
+C3_FREQS = [0, 1, 7, 50, 100]
+_HOST = {}       # workload -> FP32-rounded (A, params), generated once per process
+_ORACLE = {}     # workload -> tests.oracle_slices.Pending
+
+
+def _workload(name, freqs):
+    """FP32 input of a full-size workload (cached) and the oracle slices,
+    started in a child process the first time and shared by every form."""
+    from tests.oracle_slices import Pending
+    if name not in _ORACLE:
+        _ORACLE[name] = Pending(name, freqs)
+    if name not in _HOST:
+        A, _, c = inputs.make_config(name)
+        _HOST.clear()
+        _HOST[name] = (A.astype(np.float32), c)
+    return _HOST[name], _ORACLE[name]
 
 
 def _sampled_slices(name, freqs, tol, label, prec="f32"):
-    """A full-size workload through tsvd_rbk in the launch configuration the
-    benchmark times; the oracle recomputes the sampled Fourier slices from the
-    same FP32 input.
+    """A full-size workload through the seed-taking tsvd_rbk (the call the
+    benchmark times, in its launch configuration); the FP64 oracle recomputes
+    the sampled Fourier slices from the same FP32 input and the same seeded
+    test tensor (independently generated), in a child process.
 
     Gate: the Parseval-weighted relative error of X_hat over the sampled
     slices (weight 1 for DC / Nyquist, 2 otherwise) and the largest relative
     singular-value error of each slice, each within max(tol, 4 * floor), where
     the floor is the error of the same slices computed entirely in FP32
-    (fp32_twin_slice) against the FP64 oracle.  When sigma_k / sigma_1 or the gap sigma_k - sigma_{k+1} is
-    tiny, no FP32 computation reaches tol; both figures are printed."""
-    A, Om, c = inputs.make_config(name)
-    A, Om = _cast(A, "f32"), _cast(Om, "f32")
+    (fp32_twin_slice) against the FP64 oracle (reading R15: when
+    sigma_k / sigma_1 or the gap sigma_k - sigma_{k+1} is tiny, no FP32
+    computation reaches tol).  BF16 bulk holds sigma norm-wise (reading R16).
+    Every per-slice figure is printed."""
+    (A, c), pend = _workload(name, freqs)
     n1, n2, n3 = A.shape
     k, b, q = c["k"], c["b"], c["q"]
-    print(f"[parity] {label} full size {n1}x{n2}x{n3}", flush=True)
-    U, S, V = api.tsvd_rbk(dev(A, torch.float32), dev(Om, torch.float32), k, b, q, prec)
+    print(f"[parity] {label} full size {n1}x{n2}x{n3} k={k} b={b} q={q} seed={c['seed']} prec={prec}", flush=True)
+    U, S, V = api.tsvd_rbk(torch.from_numpy(A).to(DEV), c["seed"], k, b, q, prec)
     torch.cuda.synchronize()
     U, S, V = (host(t).astype(np.float64) for t in (U, S, V))
     Ub, Sb, Vb = fourier_factors(U, S, V, freqs)
+    sl = pend.get()
+    assert list(sl["freqs"]) == list(freqs)
     num = den = fnum = 0.0
     s_ok = True
+    worst = 0.0
     for i, f in enumerate(freqs):
-        sl = O.rbk_slices(A, Om, k, b, q, freqs=[f])
-        Xo, so = _slice_xhat(sl, 0), sl["Sf"][:, 0]
-        Xt, st = fp32_twin_slice(A, Om, k, b, q, f)
+        Xo = (sl["Uf"][:, :, i] * sl["Sf"][:, i]) @ sl["Vf"][:, :, i].conj().T
+        so = sl["Sf"][:, i]
+        Xt, st = sl["Xt"][:, :, i], sl["st"][:, i]
         Xg = (Ub[:, :, i] * Sb[:, i].real) @ Vb[:, :, i].conj().T
         w = 1.0 if f == 0 or 2 * f == n3 else 2.0
         d2, o2, t2 = (np.linalg.norm(Xg - Xo) ** 2, np.linalg.norm(Xo) ** 2, np.linalg.norm(Xt - Xo) ** 2)
@@ -193,40 +214,46 @@ def _sampled_slices(name, freqs, tol, label, prec="f32"):
         s_err = np.abs(Sb[:, i].real - so) / so
         s_floor = np.abs(st - so) / so
         if prec == "bf16":
-            # bulk BF16 products carry an absolute error of order 2^-9 sigma_1:
-            # singular values are held norm-wise, |d sigma_j| <= tol * sigma_1
             s_ok &= bool(np.max(np.abs(Sb[:, i].real - so)) <= tol * so[0])
         else:
             s_ok &= bool(s_err.max() <= max(tol, 4 * s_floor.max()))
-        s_all = sl["s_all"][:, 0]
+        worst = max(worst, float(s_err.max()))
+        s_all = sl["s_all"][:, i]
         gap = (s_all[k - 1] - s_all[k]) / s_all[0] if s_all.size > k else 1.0
         print(f"[parity] {label} slice {f}: X rel {np.sqrt(d2 / o2):.2e} (FP32 floor {np.sqrt(t2 / o2):.2e}); "
               f"sigma rel max {s_err.max():.2e} (floor {s_floor.max():.2e}); sigma_k/sigma_1 {so[-1] / so[0]:.1e}, "
               f"gap(k)/sigma_1 {gap:.1e}", flush=True)
     e, fl = float(np.sqrt(num / den)), float(np.sqrt(fnum / den))
-    print(f"[parity] {label} weighted X rel {e:.2e}, FP32 floor {fl:.2e}, gate {max(tol, 4 * fl):.2e}", flush=True)
+    print(f"[parity] {label} weighted X rel {e:.2e}, FP32 floor {fl:.2e}, gate {max(tol, 4 * fl):.2e}; "
+          f"worst sigma rel {worst:.2e}", flush=True)
     assert e <= max(tol, 4 * fl)
     assert s_ok
 
 
+@pytest.mark.timeout(1500)
 def test_config3_fp32_full_size_sampled_slices():
     """512 x 512 x 200 hyperspectral-like tensor, k = 30, b = 40, q = 3, FP32:
     DC, two low frequencies, a middle one and Nyquist."""
-    _sampled_slices("c3_hyper_512x512x200", [0, 1, 7, 50, 100], 1e-5, "c3")
+    _sampled_slices("c3_hyper_512x512x200", C3_FREQS, 1e-5, "c3")
 
 
+@pytest.mark.timeout(1500)
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
 def test_config3_mixed_precision_sampled_slices(prec):
     """The precision form on the hyperspectral workload: BF16x3 (split) and
     BF16 (bulk) Krylov products, FP64 Gram / Cholesky / eigensolver, against
     the FP64 oracle on the same FP32 input (tolerances 1e-4 and 3e-3)."""
-    _sampled_slices("c3_hyper_512x512x200", [0, 1, 7, 50, 100], TOL[prec], f"c3 {prec}", prec)
+    _sampled_slices("c3_hyper_512x512x200", C3_FREQS, TOL[prec], f"c3 {prec}", prec)
 
 
-def test_config5_fp32_full_size_sampled_slices():
-    """4096 x 4096 x 64 tensor of tubal rank 400, k = 100, b = 110, q = 3, FP32:
-    DC, an interior slice and Nyquist."""
-    _sampled_slices("c5_fp32_4096x4096x64", [0, 14, 32], 1e-5, "c5")
+@pytest.mark.timeout(1500)
+@pytest.mark.parametrize("prec", ["f32", "bf16x3", "bf16"])
+def test_config5_full_size_sampled_slices(prec):
+    """4096 x 4096 x 64 tensor of tubal rank 400, k = 100, b = 110, q = 3,
+    seed 4, in the plain FP32 form and both mixed-precision forms, on the 8
+    sampled Fourier slices f = 0, 5, 9, 14, 18, 23, 27, 32 (DC and Nyquist
+    included): X_hat within 1e-5 (FP32), 1e-4 (BF16x3), 3e-3 (BF16)."""
+    _sampled_slices("c5_fp32_4096x4096x64", C5_FREQS, TOL[prec], f"c5 {prec}", prec)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -254,3 +281,25 @@ def test_mid_blocks(shape, k, b, q, prec):
     A = inputs.lowrank_tensor(n1, n2, n3, 60, ("geom", 0.9), 1e-3, 96)
     Om = inputs.omega(n2, b, n3, 96)
     _compare(A, Om, k, b, q, prec, factors=False)
+
+
+def test_fp64_small_singular_values_relative():
+    """FP64 with sigma_k / sigma_1 of order 1e-4 (geometric decay 0.65^i): every
+    singular value within 1e-10 of the oracle's Jacobi value, relatively.
+    sqrt of the Gram's eigenvalue would carry m u lambda_1 / (2 lambda_k),
+    about 1e-8 here; the lift takes sigma_j = ||T_f w_j|| instead."""
+    n1, n2, n3, k, b, q = 90, 70, 6, 20, 22, 2
+    A = inputs.lowrank_tensor(n1, n2, n3, 30, ("geom", 0.65), 1e-9, seed=77)
+    Om = inputs.omega(n2, b, n3, 77)
+    U, S, V, X = _run_gpu(A, Om, k, b, q, "f64")
+    sl = O.rbk_slices(A, Om, k, b, q)
+    F = n3 // 2 + 1
+    _, Sb, _ = fourier_factors(U, S, V, list(range(F)))
+    ratio = np.min(sl["Sf"][-1] / sl["Sf"][0])
+    s_err = np.max(np.abs(Sb.real - sl["Sf"]) / sl["Sf"])
+    Xo = O.approx_from_slices(sl, n1, n2, n3)
+    print(f"[parity] small sigma FP64: min sigma_k/sigma_1 {ratio:.1e}, max rel sigma err {s_err:.2e}, "
+          f"X rel {rel_f(X, Xo):.2e}", flush=True)
+    assert ratio < 1e-3
+    assert s_err <= 1e-10
+    assert rel_f(X, Xo) <= 1e-10

@@ -163,8 +163,8 @@ MUTATIONS = [
      pin_complete),
     ("completion never updates C", "C = T * Mobs + (1.0 - T) * X", "C = T * Mobs + 0.0 * X", pin_complete),
     ("projection without conj", "C = Q.conj().T @ Af", "C = Q.T @ Af", pin_exact_tsvd),
-    ("truncation off by one", "Vf = Z[:, :k]", "Vf = Z[:, 1:k + 1]", pin_exact_tsvd),
-    ("lift with conj", "Uf = Q @ W[:, :k]", "Uf = Q @ W[:, :k].conj()", pin_exact_tsvd),
+    ("truncation off by one", "canonical_phase(Q @ W[:, :k], Z[:, :k])", "canonical_phase(Q @ W[:, :k], Z[:, 1:k + 1])", pin_exact_tsvd),
+    ("lift with conj", "canonical_phase(Q @ W[:, :k], Z", "canonical_phase(Q @ W[:, :k].conj(), Z", pin_exact_tsvd),
     ("adjoint direct term dropped", "Abar = Q @ (Q.conj().T @ Yb)", "Abar = 0 * Yb", pin_adjoint_fd),
     ("adjoint Qbar term dropped", "Qbar_all = Yb @ (A.conj().T @ Q) + A @ (Yb.conj().T @ Q)",
      "Qbar_all = Yb @ (A.conj().T @ Q)", pin_adjoint_fd),
