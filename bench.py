@@ -1,19 +1,24 @@
 #!/usr/bin/env python
 """Throughput of the randomized block Krylov truncated T-SVD (Alg. 2) on one
 MI355X: truncated T-SVDs per second with the input resident in HBM, for the
-plain FP32 form and the mixed-precision form (BF16x3 Krylov products, FP64
-Gram / Cholesky / eigensolver), each checked against the FP64 oracle.
+plain FP32 form and the mixed-precision forms (BF16x3 and BF16 Krylov
+products, FP64 Gram / Cholesky / eigensolver), each checked against the FP64
+oracle.
 
-One step = one call of tsvd_rbk on the whole tensor (mode-3 DFT, Krylov
-products, orthonormalisation, small SVD, lift, inverse DFT) on seeded
-synthetic input of the stated shape.  Each precision is timed over K steps
-after W warmup steps; `value` is the fastest form whose relative error
-against the oracle (sampled Fourier slices) is at most 1e-4.  Inside the
-timed region, HIP events on the library's stream time every kernel class
-(roofline).  Prints one JSON line.
+One step = one call of the seed-taking tsvd_rbk on the whole tensor (the
+test tensor drawn on the device, mode-3 DFT, Krylov products,
+orthonormalisation, small SVD, lift, inverse DFT) on seeded synthetic input
+of the stated shape.  Each form is timed over K steps after W warmup steps.
+`value` is the fastest form whose relative error against the FP64 oracle on
+the 8 sampled Fourier slices is at most 1e-4; a form with no measured error
+never qualifies.  Inside the timed region, HIP events on the library's stream
+time every kernel class (roofline).  Side legs: the other workloads (1000^2 x
+32 FP32, 512^2 x 200 in three precisions, the 2000^2 x 16 projection forward
+and backward), Alg. 1 vs Alg. 2 on Example 1, the completion of Example 3 and
+the T-QR / T-pseudoinverse.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--precs f32,bf16x3]
-                    [--no-cpu-baseline] [--cpu-slices N]
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--precs f32,bf16x3,bf16]
+                    [--no-cpu-baseline] [--no-legs] [--no-alg1] [--no-completion] [--no-tqr]
 """
 from __future__ import annotations
 
@@ -32,6 +37,7 @@ PEAK = {  # MI355X published peaks
 }
 RELERR_GATE = 1e-4
 METRIC = "truncated T-SVDs/s + MFMA util at rel-err<=1e-4: mixed-prec vs plain FP32"
+C5_FREQS = [0, 5, 9, 14, 18, 23, 27, 32]   # the 8 sampled Fourier slices of the 4096 x 4096 x 64 workload
 
 
 def log(*a):
@@ -40,8 +46,8 @@ def log(*a):
 
 def class_work(cls: str, c: dict, prec: str):
     """Algorithmic work of one step in a kernel class:
-    (amount, unit, bound, peak, note).  Complex products count 8 real flops
-    per multiply-add."""
+    (amount, executed/algorithmic factor, unit, bound, peak, note).  Complex
+    products count 8 real flops per multiply-add."""
     n1, n2, n3, k, b, q = c["n1"], c["n2"], c["n3"], c["k"], c["b"], c["q"]
     F = n3 // 2 + 1
     m = b * (q + 1)
@@ -49,28 +55,28 @@ def class_work(cls: str, c: dict, prec: str):
     if cls == "gemm_krylov":   # (2q + 2) passes over A_f, b columns each
         fl = (2 * q + 2) * 8.0 * n1 * n2 * b * F
         if prec in ("bf16", "bf16x3"):
-            ex = fl * (3 if prec == "bf16x3" else 1)
-            return ex / 1e12, "TFLOP/s", "mfma", PEAK["mfma_tflops"]["bf16"], \
-                f"executed BF16 MFMA flops ({'3x ' if prec == 'bf16x3' else ''}algorithmic {fl:.3g})"
-        return fl / 1e12, "TFLOP/s", "mfma", PEAK["mfma_tflops"][prec], "algorithmic flops"
+            return fl / 1e12, (3.0 if prec == "bf16x3" else 1.0), "TFLOP/s", "mfma", PEAK["mfma_tflops"]["bf16"], \
+                "algorithmic flops against the BF16 MFMA peak" + \
+                (" (BF16x3 executes 3 BF16 products per algorithmic one)" if prec == "bf16x3" else "")
+        return fl / 1e12, 1.0, "TFLOP/s", "mfma", PEAK["mfma_tflops"][prec], "algorithmic flops"
     if cls == "fft_A":         # read the real tensor, write the half spectrum
-        return (es * n1 * n2 * n3 + 2 * es * n1 * n2 * F) / 1e9, "GB/s", "hbm", PEAK["hbm_gbs"], "algorithmic bytes"
+        return (es * n1 * n2 * n3 + 2 * es * n1 * n2 * F) / 1e9, 1.0, "GB/s", "hbm", PEAK["hbm_gbs"], \
+            "algorithmic bytes"
     # CholeskyQR passes per block: shifted + 2 (FP32 storage); FP64 adds two
     # more shifted passes
     passes = 5 if prec == "f64" else 3
     if cls == "gemm_orth":     # block CGS2 against earlier blocks + shifted CholeskyQR, FP64 arithmetic
-        # projections: two passes of Q^H W and W - Q coef; each CholeskyQR pass:
-        # the Hermitian b x b Gram (upper half) and W R^{-1} (triangular)
         fl = sum(2 * 16.0 * n1 * (i * b) * b for i in range(1, q + 1)) + (q + 1) * passes * 8.0 * n1 * b * (b + 1)
-        return fl * F / 1e12, "TFLOP/s", "mfma", PEAK["mfma_tflops"]["f64"], \
+        return fl * F / 1e12, 1.0, "TFLOP/s", "mfma", PEAK["mfma_tflops"]["f64"], \
             "algorithmic flops (Hermitian Grams and W R^-1 counted as upper halves)"
     if cls == "chol":          # b x b complex Cholesky + triangular inverse per slice, one per CholeskyQR pass
-        return passes * (q + 1) * F * (16.0 / 3.0 * b ** 3) / 1e12, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"], \
-            "algorithmic flops"
+        return passes * (q + 1) * F * (16.0 / 3.0 * b ** 3) / 1e12, 1.0, "TFLOP/s", "alu", \
+            PEAK["valu_tflops"]["f64"], "algorithmic flops"
     if cls == "heig_tri":      # Householder tridiagonalisation of the m x m Hermitian G_f
-        return F * (16.0 / 3.0 * m ** 3) / 1e12, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"], "algorithmic flops"
+        return F * (16.0 / 3.0 * m ** 3) / 1e12, 1.0, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"], \
+            "algorithmic flops"
     if cls == "gemm_lift":     # G = T^H T (Hermitian: upper half), U = Q W_k, V = T W_k
-        return F * (4.0 * n2 * m * (m + 1) + 8.0 * (n1 + n2) * m * k) / 1e12, "TFLOP/s", "mfma", \
+        return F * (4.0 * n2 * m * (m + 1) + 8.0 * (n1 + n2) * m * k) / 1e12, 1.0, "TFLOP/s", "mfma", \
             PEAK["mfma_tflops"]["f64"], "algorithmic flops (Hermitian Gram counted as its upper half)"
     return None
 
@@ -99,48 +105,190 @@ def profiled_traffic(cls: str, prec: str, workload: str):
 
 
 def roofline_for(kernels: dict, c: dict, prec: str, workload: str):
-    """Roofline of the dominant kernel class that has a stated algorithmic work."""
+    """Roofline of the dominant kernel class that has a stated algorithmic
+    work: achieved = algorithmic work per step / that class's time per step;
+    frac = achieved / peak; frac_executed counts the MFMA work the form
+    actually issues (3x the algorithmic flops for BF16x3)."""
     for cls, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
         w = class_work(cls, c, prec)
         if w is None:
             continue
-        amount, unit, bound, peak, note = w
+        amount, xf, unit, bound, peak, note = w
         achieved = amount / (v["ms_per_step"] * 1e-3)
         tr = profiled_traffic(cls, prec, workload)
         return {"kernel": cls, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": tr["bytes_per_launch"] if tr else None,
+                "frac": achieved / peak, "frac_executed": achieved * xf / peak,
+                "traffic": tr["bytes_per_launch"] if tr else None,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "traffic_source": tr["source"] if tr else None, "work": note,
                 "launches_per_step": v["launches_per_step"], "avg_launch_ms": v["avg_launch_ms"]}
     return None
 
 
-def oracle_sample(A, Om, c, freqs):
-    """The FP64 oracle on a bounded sample: the mode-3 DFT at the sampled
-    frequencies plus those Fourier slices of Alg. 2."""
-    from oracle import tsvd_oracle as O
+def kernel_figures(kernels: dict, c: dict, prec: str):
+    """Krylov-product MFMA utilisation (algorithmic and executed) and the
+    mode-3 DFT's HBM rate, from the timed kernel classes."""
+    out = {}
+    kry = kernels.get("gemm_krylov")
+    if kry:
+        amount, xf, _, _, peak, _ = class_work("gemm_krylov", c, prec)
+        rate = amount / (kry["ms_per_step"] * 1e-3)
+        out["krylov_mfma_util"] = rate / peak
+        out["krylov_mfma_util_executed"] = rate * xf / peak
+        out["krylov_tflops_algorithmic"] = rate
+    fft = kernels.get("fft_A")
+    if fft:
+        gb, _, _, _, peak, _ = class_work("fft_A", c, prec)
+        out["fft_hbm"] = {"achieved_GBs": gb / (fft["ms_per_step"] * 1e-3), "peak_GBs": peak,
+                          "frac": gb / (fft["ms_per_step"] * 1e-3) / peak, "bytes_per_launch": gb * 1e9,
+                          "ms_per_launch": fft["avg_launch_ms"]}
+    return out
+
+
+def time_calls(api, fn, steps: int, warmup: int):
+    """Warmup, then exactly `steps` timed calls bracketed by synchronisations,
+    with the per-class HIP-event timer on; returns (ms per call, kernels)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    api.diag_timing(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sl = O.rbk_slices(A, Om, c["k"], c["b"], c["q"], freqs=freqs)
-    return sl, time.perf_counter() - t0
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    timing = api.diag_timing_read()
+    api.diag_timing(False)
+    kernels = {}
+    for cls, (tms, cnt) in timing.items():
+        if cnt:
+            kernels[cls] = {"ms_per_step": tms / steps, "launches_per_step": cnt / steps, "avg_launch_ms": tms / cnt}
+    return ms, kernels
 
 
-def slice_relerr(U, S, V, sl, freqs):
+def slice_relerr(U, S, V, sl, freqs, idx=None):
     """Parseval-weighted relative error of X_hat = U * S * V^T on the sampled
-    Fourier slices against the oracle's slices."""
+    Fourier slices against the oracle's slices (idx: positions of freqs in
+    the oracle's arrays).  Returns (weighted error, per-slice errors, per-slice
+    largest relative singular-value errors)."""
     n3 = U.shape[2]
+    idx = list(range(len(freqs))) if idx is None else idx
     w = np.exp(-2j * np.pi * np.outer(np.arange(n3), freqs) / n3)      # (n3, nf)
     Ub, Vb, Sb = U @ w, V @ w, (S @ w).real
     num = den = 0.0
-    per = []
-    for i, f in enumerate(freqs):
+    per, sig = [], []
+    for i, (f, j) in enumerate(zip(freqs, idx)):
         Xg = (Ub[:, :, i] * Sb[:, i]) @ Vb[:, :, i].conj().T
-        Xo = (sl["Uf"][:, :, i] * sl["Sf"][:, i]) @ sl["Vf"][:, :, i].conj().T
+        Xo = (sl["Uf"][:, :, j] * sl["Sf"][:, j]) @ sl["Vf"][:, :, j].conj().T
         d2, o2 = np.linalg.norm(Xg - Xo) ** 2, np.linalg.norm(Xo) ** 2
         wt = 1.0 if f == 0 or 2 * f == n3 else 2.0
         num += wt * d2
         den += wt * o2
         per.append(float(np.sqrt(d2 / o2)))
-    return float(np.sqrt(num / den)), per
+        sig.append(float(np.max(np.abs(Sb[:, i] - sl["Sf"][:, j]) / sl["Sf"][:, j])))
+    return float(np.sqrt(num / den)), per, sig
+
+
+def run_rbk_form(api, A64, c, prec, steps, warmup, workload):
+    """Time tsvd_rbk (seed-taking) in one precision; returns (leg, outputs)."""
+    import torch
+    n1, n2, n3 = A64.shape
+    k, b, q, seed = c["k"], c["b"], c["q"], c["seed"]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    A = torch.from_numpy(A64.astype(np.float64 if prec == "f64" else np.float32)).to("cuda")
+    ws = api.workspace(n1, n2, n3, k, b, q, prec, "rbk", "cuda")
+    out = (torch.empty((n1, k, n3), dtype=dt, device="cuda"), torch.empty((k, n3), dtype=dt, device="cuda"),
+           torch.empty((n2, k, n3), dtype=dt, device="cuda"))
+    log(f"[bench] {workload} {prec}: {n1}x{n2}x{n3} k={k} b={b} q={q} seed={seed} workspace "
+        f"{ws.numel() / 2**20:.1f} MiB")
+    ms, kernels = time_calls(api, lambda: api.tsvd_rbk(A, seed, k, b, q, prec, ws=ws, out=out), steps, warmup)
+    info = api.read_info(ws)
+    log(f"[bench] {workload} {prec}: {ms:.3f} ms/step ({1e3 / ms:.2f} T-SVD/s); info {info}")
+    for cls, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        log(f"[bench]   {cls:12s} {v['ms_per_step']:.3f} ms/step  {v['launches_per_step']:.0f} launches  "
+            f"{v['avg_launch_ms'] * 1e3:.1f} us/launch")
+    leg = {"value": 1e3 / ms, "ms_per_step": ms, "roofline": roofline_for(kernels, c, prec, workload),
+           "kernels": kernels, "numeric_info": info}
+    leg.update(kernel_figures(kernels, c, prec))
+    outs = tuple(t.cpu().numpy().astype(np.float64) for t in out)
+    del A, ws, out
+    torch.cuda.empty_cache()
+    return leg, outs
+
+
+def other_workloads(api, inputs, steps: int, warmup: int):
+    """The other workloads: 1000 x 1000 x 32 (FP32), the 512 x 512 x 200
+    hyperspectral tensor (FP32, BF16x3, BF16) and the 2000 x 2000 x 16
+    projection forward + backward (FP32): per form the time per call, the
+    roofline of its dominant class, the Krylov MFMA utilisation, the DFT's HBM
+    rate and the error against the FP64 oracle on sampled slices (the oracle's
+    time per slice beside it)."""
+    import torch
+    from oracle import tsvd_oracle as O
+    res = {}
+    for name, precs, freqs in (("c2_fp32_1000x1000x32", ["f32"], [0, 8, 16]),
+                               ("c3_hyper_512x512x200", ["f32", "bf16x3", "bf16"], [0, 1, 7, 50, 100])):
+        A64, Om64, c = inputs.make_config(name)
+        A32 = A64.astype(np.float32).astype(np.float64)
+        Om32 = Om64.astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        sl = O.rbk_slices(A32, Om32, c["k"], c["b"], c["q"], freqs=freqs)
+        t_or = (time.perf_counter() - t0) / len(freqs)
+        legs = {}
+        for prec in precs:
+            leg, outs = run_rbk_form(api, A64, c, prec, steps, warmup, name)
+            e, per, sig = slice_relerr(*outs, sl, freqs)
+            leg.update(rel_err_vs_oracle=e, rel_err_slices=dict(zip(map(str, freqs), per)),
+                       sigma_rel_err_slices=dict(zip(map(str, freqs), sig)))
+            log(f"[bench] {name} {prec}: rel err vs FP64 oracle on slices {freqs}: {e:.2e}")
+            legs[prec] = leg
+        F = c["n3"] // 2 + 1
+        res[name] = {"forms": legs, "oracle_seconds_per_slice": t_or, "oracle_seconds_extrapolated": t_or * F,
+                     "sampled_slices": freqs}
+    # the differentiation form: P(A) = Q * Q^T * A and its adjoint
+    name = "c4_completion_2000x2000x16"
+    A64, Om64, c = inputs.make_config(name)
+    T, M = c["T"], c["M"]
+    b, q, seed = c["b"], c["q"], c["seed"]
+    n1, n2, n3 = A64.shape
+    X = torch.from_numpy(A64.astype(np.float32)).to("cuda")
+    Td, Md = torch.from_numpy(T.astype(np.float32)).to("cuda"), torch.from_numpy(M.astype(np.float32)).to("cuda")
+    wf = api.workspace(n1, n2, n3, 1, b, q, "f32", "proj", "cuda")
+    wb = api.workspace(n1, n2, n3, 1, b, q, "f32", "proj_bwd", "cuda")
+    state = {}
+
+    def fwd_bwd():
+        P = api.tsvd_proj(X, seed, b, q, "f32", ws=wf)
+        G = -2.0 * Md * (Td - P)
+        state["P"], state["G"] = P, G
+        state["dA"] = api.tsvd_proj_backward(X, seed, G, b, q, "f32", ws=wb)
+
+    ms, kernels = time_calls(api, fwd_bwd, max(steps // 2, 3), 1)
+    P, G, dA = (state[k].cpu().numpy().astype(np.float64) for k in ("P", "G", "dA"))
+    lhs, rhs = float(np.sum(dA * A64.astype(np.float32))), float(np.sum(G * P))
+    freqs = [0, 5]
+    X32 = A64.astype(np.float32).astype(np.float64)
+    Om32 = Om64.astype(np.float32).astype(np.float64)
+    Ab, Ob, Gb = (O.dft_mode3(x, freqs) for x in (X32, Om32, G))
+    Db = np.fft.fft(dA, axis=2)
+    t0 = time.perf_counter()
+    gerr = {}
+    for j, f in enumerate(freqs):
+        Df = O._proj_slice_adjoint(Ab[:, :, j], Ob[:, :, j], Gb[:, :, j], q)
+        gerr[str(f)] = float(np.linalg.norm(Db[:, :, f] - Df) / np.linalg.norm(Df))
+    t_or = (time.perf_counter() - t0) / len(freqs)
+    log(f"[bench] {name} f32 forward + backward: {ms:.3f} ms; Euler rel {abs(lhs - rhs) / abs(rhs):.1e}; "
+        f"gradient rel err vs oracle {gerr}")
+    cfw = dict(c, k=1)
+    kf = kernel_figures(kernels, cfw, "f32")
+    res[name] = {"ms_per_fwd_bwd": ms, "fwd_bwd_per_s": 1e3 / ms, "kernels": kernels,
+                 "fft_hbm": kf.get("fft_hbm"), "euler_rel": abs(lhs - rhs) / abs(rhs),
+                 "gradient_rel_err_slices": gerr, "oracle_adjoint_seconds_per_slice": t_or}
+    del X, Td, Md, wf, wb, state
+    torch.cuda.empty_cache()
+    return res
 
 
 def compare_alg1_alg2(api, inputs, steps: int, warmup: int):
@@ -152,21 +300,20 @@ def compare_alg1_alg2(api, inputs, steps: int, warmup: int):
     import torch
     res = {}
     for name in inputs.EX1_CONFIGS:
-        A64, Om64, c = inputs.make_config(name)
-        k, b, q = c["k"], c["b"], c["q"]
+        A64, _, c = inputs.make_config(name)
+        k, b, q, seed = c["k"], c["b"], c["q"], c["seed"]
         n1, n2, n3 = A64.shape
         A = torch.from_numpy(A64).to("cuda")
-        Om = torch.from_numpy(Om64).to("cuda")
         sig = inputs._decay(c["decay"], min(n1, n2))
         case = {"optimum_rel_err": float(np.sqrt(np.sum(sig[k:] ** 2) / np.sum(sig ** 2)))}
         for alg, fn, op in (("alg1", api.tsvd_power_approx, "power_approx"), ("alg2", api.tsvd_rbk_approx, "approx")):
             ws = api.workspace(n1, n2, n3, k, b, q, "f64", op, "cuda")
             for _ in range(warmup):
-                out = fn(A, Om, k, b, q, "f64", ws=ws)
+                out = fn(A, seed, k, b, q, "f64", ws=ws)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(steps):
-                out = fn(A, Om, k, b, q, "f64", ws=ws)
+                out = fn(A, seed, k, b, q, "f64", ws=ws)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3 / steps
             err = float(torch.linalg.norm(out[3] - A) / torch.linalg.norm(A))
@@ -176,7 +323,7 @@ def compare_alg1_alg2(api, inputs, steps: int, warmup: int):
             f"alg2 {case['alg2']['ms_per_call']:.2f} ms err {case['alg2']['rel_err']:.4e}; "
             f"optimum {case['optimum_rel_err']:.4e}")
         res[name] = case
-        del A, Om
+        del A
         torch.cuda.empty_cache()
     return {"workload": "Example 1 spectra m^-5, m^-6, 0.5^m; n = 256; R = 45, P = 5, q = 2; f64", "cases": res}
 
@@ -192,18 +339,16 @@ def completion_runs(api, inputs):
     c = inputs.COMPLETION_CONFIGS[name]
     M64 = inputs.image_tensor(c["n1"], c["n2"], c["n3"], c["seed"])
     T = inputs.bernoulli_mask(M64.shape, c["keep"], c["seed"])
-    Om64 = inputs.omega(c["n2"], c["b"], c["n3"], c["seed"])
     M = torch.from_numpy(M64.astype(np.float32)).to("cuda")
     mask = torch.from_numpy(T != 0).to("cuda")
-    Om = torch.from_numpy(Om64.astype(np.float32)).to("cuda")
-    k, b, q, iters = c["k"], c["b"], c["q"], c["iters"]
+    k, b, q, iters, seed = c["k"], c["b"], c["q"], c["iters"], c["seed"]
     res = {}
     for alg in (2, 1):
         ws = api.workspace(c["n1"], c["n2"], c["n3"], k, b, q, "f32", f"complete{alg}", "cuda")
-        api.tsvd_complete(M, mask, Om, k, b, q, 2, alg, "f32", ws=ws)   # warmup
+        api.tsvd_complete(M, mask, seed, k, b, q, 2, alg, "f32", ws=ws)   # warmup
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        C = api.tsvd_complete(M, mask, Om, k, b, q, iters, alg, "f32", ws=ws)
+        C = api.tsvd_complete(M, mask, seed, k, b, q, iters, alg, "f32", ws=ws)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         mse = float(torch.mean((C.double() - M.double()) ** 2))
@@ -250,15 +395,23 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c5_fp32_4096x4096x64")
-    ap.add_argument("--precs", default=None, help="comma-separated forms to time (default: f32,bf16x3; f64 for FP64 workloads)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slices", type=int, default=1)
+    ap.add_argument("--precs", default=None,
+                    help="comma-separated forms to time (default: f32,bf16x3,bf16; f64 for FP64 workloads)")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the FP64 oracle (then no form is gated and the headline is the plain FP32 form)")
+    ap.add_argument("--no-legs", action="store_true", help="skip the other workloads (1000^2x32, 512^2x200, 2000^2x16)")
     ap.add_argument("--no-alg1", action="store_true", help="skip the Alg. 1 vs Alg. 2 comparison (Example 1)")
     ap.add_argument("--no-completion", action="store_true", help="skip the completion runs (Example 3)")
     ap.add_argument("--no-tqr", action="store_true", help="skip the T-QR / T-pseudoinverse timing")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the Fourier slices of one tensor are processed by one device, and "
+              "the frequency-sharded multi-GPU path is not built (see the design notes)", file=sys.stderr)
+        print(json.dumps({"error": "only --gpus 1 is supported", "n_gpus": args.gpus}))
+        sys.exit(2)
     if args.calibrate_copy_mib:
         import torch
         n = args.calibrate_copy_mib * 2**20 // 4
@@ -269,100 +422,69 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}), flush=True)
         return
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU (one Fourier-slice batch per device); "
-                                   "multi-GPU frequency sharding is not built", "n_gpus": args.gpus}))
-        sys.exit(2)
 
-    import torch
-    from paper_2504_04989_amd import api, inputs
+    from paper_2504_04989_amd import inputs
 
     t0 = time.perf_counter()
     A64, Om64, c = inputs.make_config(args.workload)
     log(f"[bench] generated {args.workload} in {time.perf_counter() - t0:.1f} s")
-    if args.precs:
-        precs = args.precs.split(",")
-    else:
-        precs = ["f64"] if c["prec"] == "f64" else ["f32", "bf16x3"]
+    precs = args.precs.split(",") if args.precs else (["f64"] if c["prec"] == "f64" else ["f32", "bf16x3", "bf16"])
     n1, n2, n3 = A64.shape
     k, b, q = c["k"], c["b"], c["q"]
     F = n3 // 2 + 1
-    legs = {}
-    outs = {}
-    for prec in precs:
-        npdt = np.float64 if prec == "f64" else np.float32
-        dt = torch.float64 if prec == "f64" else torch.float32
-        A = torch.from_numpy(A64.astype(npdt)).to("cuda")
-        Om = torch.from_numpy(Om64.astype(npdt)).to("cuda")
-        ws = api.workspace(n1, n2, n3, k, b, q, prec, "rbk", "cuda")
-        out = (torch.empty((n1, k, n3), dtype=dt, device="cuda"), torch.empty((k, n3), dtype=dt, device="cuda"),
-               torch.empty((n2, k, n3), dtype=dt, device="cuda"))
-        log(f"[bench] {prec}: {n1}x{n2}x{n3} k={k} b={b} q={q} workspace {ws.numel() / 2**20:.1f} MiB")
-        for _ in range(args.warmup):
-            api.tsvd_rbk(A, Om, k, b, q, prec, ws=ws, out=out)
-        torch.cuda.synchronize()
-        # timed region: exactly K steps; HIP events recorded on the library's
-        # stream around every launch class give the per-kernel times
-        api.diag_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            api.tsvd_rbk(A, Om, k, b, q, prec, ws=ws, out=out)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        timing = api.diag_timing_read()
-        api.diag_timing(False)
-        info = api.read_info(ws)
-        kernels = {}
-        for cls, (tms, cnt) in timing.items():
-            if cnt:
-                kernels[cls] = {"ms_per_step": tms / args.steps, "launches_per_step": cnt / args.steps,
-                                "avg_launch_ms": tms / cnt}
-        log(f"[bench] {prec}: {ms:.3f} ms/step ({1e3 / ms:.2f} T-SVD/s); info {info}")
-        for cls, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
-            log(f"[bench]   {cls:12s} {v['ms_per_step']:.3f} ms/step  {v['launches_per_step']:.0f} launches  "
-                f"{v['avg_launch_ms'] * 1e3:.1f} us/launch")
-        kry = kernels.get("gemm_krylov")
-        kw = class_work("gemm_krylov", c, prec)
-        legs[prec] = {"value": 1e3 / ms, "ms_per_step": ms, "roofline": roofline_for(kernels, c, prec, args.workload),
-                      "krylov_mfma_util": (kw[0] / (kry["ms_per_step"] * 1e-3) / kw[3]) if kry else None,
-                      "kernels": kernels, "numeric_info": info}
-        outs[prec] = tuple(t.cpu().numpy().astype(np.float64) for t in out)
-        del A, Om, ws, out
-        torch.cuda.empty_cache()
+    freqs = [f for f in C5_FREQS if f < F] if args.workload.startswith("c5") else sorted({0, F // 2, F - 1})
 
-    # accuracy of every form against the FP64 oracle on sampled Fourier slices
-    base = None
+    # The FP64 oracle on the sampled slices runs in worker processes forked
+    # now, before this process initialises the GPU, and overlaps the GPU legs.
+    pool = None
     if not args.no_cpu_baseline:
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-        except Exception:  # pragma: no cover
-            cores = os.cpu_count() or 1
-        freqs = [int(x) for x in np.linspace(0, F - 1, args.cpu_slices + 2)[1:-1]] if args.cpu_slices > 0 else []
-        freqs = freqs or [F // 2]
-        Ain = A64 if precs == ["f64"] else A64.astype(np.float32).astype(np.float64)
-        Oin = Om64 if precs == ["f64"] else Om64.astype(np.float32).astype(np.float64)
-        log(f"[bench] cpu baseline: FP64 oracle on Fourier slices {freqs}")
-        sl, t_sl = oracle_sample(Ain, Oin, c, freqs)
-        t_job = t_sl / len(freqs) * F
-        base = {"value": 1.0 / t_job, "unit": "T-SVD/s", "cores": int(cores), "kind": "oracle",
-                "sample": f"mode-3 DFT at {len(freqs)} frequency + {len(freqs)} of {F} Fourier slices of Alg. 2 "
-                          f"in {t_sl:.1f} s, extrapolated to {F} slices: {t_job:.0f} s per T-SVD"}
-        for prec in precs:
-            e, per = slice_relerr(*outs[prec], sl, freqs)
-            legs[prec]["rel_err_vs_oracle"] = e
-            legs[prec]["rel_err_slices"] = dict(zip([str(f) for f in freqs], per))
-            log(f"[bench] {prec}: rel err vs FP64 oracle on slices {freqs}: {e:.2e}")
-        log(f"[bench] cpu baseline {base['value']:.4g} T-SVD/s ({base['sample']})")
+        from oracle.pool import SlicePool
+        cast = (lambda x: x) if precs == ["f64"] else (lambda x: x.astype(np.float32).astype(np.float64))
+        pool = SlicePool(cast(A64), cast(Om64), k, b, q, freqs)
+        log(f"[bench] FP64 oracle started on Fourier slices {freqs}: {pool.workers} workers x {pool.threads} "
+            f"BLAS threads (DFT {pool.dft_seconds:.1f} s)")
+    del Om64
 
+    from paper_2504_04989_amd import api
+
+    legs, outs = {}, {}
+    for prec in precs:
+        legs[prec], outs[prec] = run_rbk_form(api, A64, c, prec, args.steps, args.warmup, args.workload)
+    del A64
+
+    others = None if args.no_legs else other_workloads(api, inputs, max(args.steps // 2, 3), 1)
     alg12 = None if args.no_alg1 else compare_alg1_alg2(api, inputs, max(args.steps // 2, 3), 1)
     compl = None if args.no_completion else completion_runs(api, inputs)
     tqr = None if args.no_tqr else tqr_runs(api, inputs, max(args.steps // 2, 3), 1)
 
-    ok = [p for p in precs if legs[p].get("rel_err_vs_oracle", 0.0) <= RELERR_GATE]
-    best = max(ok or precs, key=lambda p: legs[p]["value"])
+    base = None
+    if pool is not None:
+        sl = pool.get(progress=lambda msg: log(f"[bench] {msg}"))
+        t_slice = sl["wall"] / len(freqs)
+        base = {"value": 1.0 / (t_slice * F), "unit": "T-SVD/s", "cores": int(sl["threads"]), "kind": "oracle",
+                "sample": f"FP64 oracle (plain numpy DFT, Householder QR, Jacobi SVD): mode-3 DFT at {len(freqs)} "
+                          f"frequencies + Alg. 2 on Fourier slices {freqs} of {F} in {sl['wall']:.1f} s wall "
+                          f"({sl['workers']} worker processes, {sl['threads']} threads in all; "
+                          f"{np.mean(sl['seconds']):.1f} s per slice in a worker), extrapolated to all {F} slices: "
+                          f"{t_slice * F:.0f} s per T-SVD"}
+        for prec in precs:
+            e, per, sig = slice_relerr(*outs[prec], sl, freqs)
+            legs[prec]["rel_err_vs_oracle"] = e
+            legs[prec]["rel_err_slices"] = dict(zip(map(str, freqs), per))
+            legs[prec]["sigma_rel_err_slices"] = dict(zip(map(str, freqs), sig))
+            log(f"[bench] {prec}: rel err vs FP64 oracle on slices {freqs}: {e:.2e} "
+                f"(per slice {', '.join(f'{x:.1e}' for x in per)})")
+        log(f"[bench] cpu baseline {base['value']:.4g} T-SVD/s ({base['sample']})")
+
+    # headline: the fastest form whose measured error meets the gate; with no
+    # measured error no form qualifies and the plain FP32 form is reported,
+    # marked ungated
+    gated = [p for p in precs if legs[p].get("rel_err_vs_oracle") is not None
+             and legs[p]["rel_err_vs_oracle"] <= RELERR_GATE]
+    if gated:
+        best = max(gated, key=lambda p: legs[p]["value"])
+    else:
+        best = "f32" if "f32" in precs else precs[0]
     head = legs[best]
     res = {
         "metric": METRIC,
@@ -378,13 +500,19 @@ def main():
         "dtype": best,
         "data": "synthetic",
         "config": {"workload": args.workload, "n1": n1, "n2": n2, "n3": n3, "k": k, "b": b, "q": q,
-                   "form": best, "forms_timed": precs},
+                   "seed": c["seed"], "form": best, "forms_timed": precs},
+        "gate": {"rel_err_max": RELERR_GATE, "passed": bool(gated), "forms_passing": gated,
+                 "rel_err_vs_oracle": head.get("rel_err_vs_oracle"), "sampled_slices": freqs},
         "roofline": head["roofline"],
-        "krylov_mfma_util": head["krylov_mfma_util"],
+        "krylov_mfma_util": head.get("krylov_mfma_util"),
+        "krylov_mfma_util_executed": head.get("krylov_mfma_util_executed"),
+        "fft_hbm": head.get("fft_hbm"),
         "forms": legs,
     }
     if "f32" in legs and best != "f32":
         res["speedup_vs_fp32"] = head["value"] / legs["f32"]["value"]
+    if others is not None:
+        res["other_workloads"] = others
     if alg12 is not None:
         res["alg1_vs_alg2"] = alg12
     if compl is not None:
