@@ -160,6 +160,23 @@ int tsvd_omega(int64_t n2, int64_t b, int64_t n3, uint64_t seed, double* out_hos
 int tsvd_rbk(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k,
              int64_t b, int64_t q, uint64_t seed, int prec, void* U, void* S,
              void* V, void* ws, size_t ws_bytes, void* stream);
+/* tsvd_rbk for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and outputs as tsvd_rbk (same kernels, bit-identical results)
+ * with no workspace argument and no allocation of any kind.  Its scratch is
+ * a static device array of TSVD_NOALLOC_SCRATCH_BYTES (64 MiB) that
+ * every device the library runs on holds until the process ends; sizes whose
+ * tsvd_workspace_bytes(..., TSVD_OP_RBK) exceeds it return TSVD_ENOMEM with
+ * nothing enqueued.  All calls on one device share that device's array and
+ * it keeps the last call's contents (each call clears what it needs
+ * cleared): calls that overlap on one device, on different streams or from
+ * different threads, race and must be serialised by the caller.
+ * tsvd_read_info does not apply (the scratch has no caller-visible handle). */
+int tsvd_rbk_noalloc(const void* A, int64_t n1, int64_t n2, int64_t n3,
+                     int64_t k, int64_t b, int64_t q, uint64_t seed, int prec,
+                     void* U, void* S, void* V, void* stream);
+#define TSVD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
 /* tsvd_rbk with the test tensor given: Omega (n2 x b x n3, device). */
 int tsvd_rbk_omega(const void* A, const void* Omega, int64_t n1, int64_t n2,
                    int64_t n3, int64_t k, int64_t b, int64_t q, int prec,

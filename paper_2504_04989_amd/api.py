@@ -22,7 +22,7 @@ INFO_NAMES = ("chol_shifted", "chol_breakdown", "eig_noconv", "nonfinite")
 INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_omega",
-           "tsvd_rbk", "tsvd_rbk_omega", "tsvd_rbk_approx", "tsvd_rbk_approx_omega",
+           "tsvd_rbk", "tsvd_rbk_omega", "tsvd_rbk_noalloc", "tsvd_rbk_approx", "tsvd_rbk_approx_omega",
            "tsvd_power", "tsvd_power_omega", "tsvd_power_approx", "tsvd_power_approx_omega",
            "tsvd_rbk_literal", "tsvd_rbk_literal_omega", "tsvd_complete", "tsvd_complete_omega",
            "tsvd_tqr", "tsvd_tpinv", "tsvd_proj", "tsvd_proj_omega", "tsvd_proj_backward",
@@ -59,6 +59,8 @@ def _load():
         f = getattr(lib, name + "_omega")
         f.restype = ci
         f.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ci] + [vp] * nout + [vp, sz, vp]
+    lib.tsvd_rbk_noalloc.restype = ci
+    lib.tsvd_rbk_noalloc.argtypes = [vp, i64, i64, i64, i64, i64, i64, u64, ci, vp, vp, vp, vp]
     lib.tsvd_tqr.restype = ci
     lib.tsvd_tqr.argtypes = [vp, i64, i64, i64, ci, vp, vp, vp, sz, vp]
     lib.tsvd_tpinv.restype = ci
@@ -228,6 +230,33 @@ def tsvd_rbk(A: torch.Tensor, Omega, k: int, b: int, q: int, prec=None, ws=None,
     Omega: an int seed (the test tensor is drawn on the device) or a device
     tensor (n2, b, n3)."""
     return _svd_call("tsvd_rbk", "rbk", A, Omega, k, b, q, prec, ws, out, False)[:3]
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def tsvd_rbk_noalloc(A: torch.Tensor, seed: int, k: int, b: int, q: int, prec=None, out=None):
+    """tsvd_rbk through the entry point that allocates nothing (its scratch is
+    the library's static device array of NOALLOC_SCRATCH_BYTES): returns
+    (U, S, V).  Outputs are allocated here unless `out` is given."""
+    prec = _prec_of(A, prec)
+    dt = _dtype_of(prec)
+    _check_in(A, dt, "A")
+    n1, n2, n3 = _shape3(A)
+    if not _is_seed(seed):
+        raise ValueError("seed must be an int")
+    dev = A.device
+    if out is None:
+        out = (torch.empty((n1, k, n3), dtype=dt, device=dev), torch.empty((k, n3), dtype=dt, device=dev),
+               torch.empty((n2, k, n3), dtype=dt, device=dev))
+    U, S, V = out
+    for t, nm, shp in ((U, "U", (n1, k, n3)), (S, "S", (k, n3)), (V, "V", (n2, k, n3))):
+        _check_in(t, dt, nm)
+        if tuple(t.shape) != shp:
+            raise ValueError(f"{nm} must have shape {shp}")
+    _check(lib.tsvd_rbk_noalloc(_ptr(A), n1, n2, n3, k, b, q, int(seed) & 0xFFFFFFFFFFFFFFFF, PREC[prec], _ptr(U),
+                                _ptr(S), _ptr(V), _stream(dev)))
+    return U, S, V
 
 
 def tsvd_rbk_approx(A, Omega, k, b, q, prec=None, ws=None):

@@ -1303,6 +1303,35 @@ int proj_backward_call(bool given, const void* A, const void* Omega, uint64_t se
 }
 
 
+// ---- scratch for the entry point that allocates nothing ----
+// A file-scope device array: each device the library runs on holds its own
+// copy until the process ends.  In host code its name stands for a host-side
+// symbol, not a device address: the device address comes from
+// hipGetSymbolAddress, once per device, and is the only handle used.
+constexpr size_t kStaticScratchBytes = TSVD_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on its first use
+// on that device, with that device current).
+int static_scratch(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(TSVD_EHIP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> l(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(TSVD_EHIP, "hipGetSymbolAddress returned no address for the static scratch");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TSVD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1329,6 +1358,23 @@ int tsvd_omega(int64_t n2, int64_t b, int64_t n3, uint64_t seed, double* out_hos
 int tsvd_rbk(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, uint64_t seed,
              int prec, void* U, void* S, void* V, void* ws, size_t ws_bytes, void* stream) {
   return svd_call(false, TSVD_OP_RBK, A, nullptr, seed, n1, n2, n3, k, b, q, prec, U, S, V, nullptr, ws, ws_bytes, stream);
+}
+
+int tsvd_rbk_noalloc(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q,
+                     uint64_t seed, int prec, void* U, void* S, void* V, void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_RBK, &p);
+  if (r) return r;
+  if (p.total > kStaticScratchBytes) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "tsvd_rbk_noalloc: these sizes need %zu bytes of scratch, beyond its %zu bytes; use "
+             "tsvd_rbk with a workspace", p.total, kStaticScratchBytes);
+    return fail(TSVD_ENOMEM, msg);
+  }
+  void* ws = nullptr;
+  if ((r = static_scratch(&ws))) return r;
+  return svd_call(false, TSVD_OP_RBK, A, nullptr, seed, n1, n2, n3, k, b, q, prec, U, S, V, nullptr, ws,
+                  kStaticScratchBytes, stream);
 }
 
 int tsvd_rbk_omega(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
