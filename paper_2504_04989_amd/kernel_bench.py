@@ -4,6 +4,7 @@ data drawn on the device (no host generation, so a profiler pass is short).
 
     python -m paper_2504_04989_amd.kernel_bench krylov [--prec f32|bf16|bf16x3] [--n 4096] [--f 33] [--N 110]
     python -m paper_2504_04989_amd.kernel_bench fft [--n 4096] [--n3 64]
+    python -m paper_2504_04989_amd.kernel_bench orth [--n 4096] [--m 440] [--n3 64]
 
 krylov: the Krylov products of Alg. 2, C_f = A_f X_f and C_f = A_f^H Y_f,
 over f slices of an n x n complex FP32 A_f and N thin columns (the
@@ -12,6 +13,11 @@ timed over --reps launches after one warmup, with HIP events; prints the
 time per launch and the rate in algorithmic flops (8 n^2 N f per launch).
 fft: the mode-3 real-to-half-spectrum DFT of n^2 real tubes of length n3
 (FP32), timed likewise, with its algorithmic bytes (4 n^2 n3 + 8 n^2 F).
+orth: the T-QR (Alg. TQR) of an n x m x n3 FP32 tensor, m = 440 orthonormalised
+in four 110-column panels: the same orthonormalisation launches (block
+Gram-Schmidt projections, shifted CholeskyQR, FP64 Grams and factors) as the
+Krylov basis of the 4096 x 4096 x 64 workload (b = 110, q = 3), without the
+small eigensolver.
 Prints one JSON line per measurement.
 """
 from __future__ import annotations
@@ -60,18 +66,28 @@ def fft(n: int, n3: int, reps: int):
                       "frac_hbm": gb / ms * 1e3 / 8000.0}), flush=True)
 
 
+def orth(n: int, m: int, n3: int, reps: int):
+    A = torch.randn((n, m, n3), dtype=torch.float32, device="cuda")
+    ws = api.workspace(n, m, n3, 0, 0, 0, "f32", "tqr", "cuda")
+    ms = _time(lambda: api.tsvd_tqr(A, "f32", ws=ws), reps)
+    print(json.dumps({"kernel": "tqr", "n1": n, "n2": m, "n3": n3, "ms_per_call": ms}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["krylov", "fft"])
+    ap.add_argument("what", choices=["krylov", "fft", "orth"])
     ap.add_argument("--prec", default="bf16x3")
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--f", type=int, default=33)
     ap.add_argument("--N", type=int, default=110)
     ap.add_argument("--n3", type=int, default=64)
+    ap.add_argument("--m", type=int, default=440)
     ap.add_argument("--reps", type=int, default=5)
     a = ap.parse_args()
     if a.what == "krylov":
         krylov(a.n, a.f, a.N, a.prec, a.reps)
+    elif a.what == "orth":
+        orth(a.n, a.m, a.n3, a.reps)
     else:
         fft(a.n, a.n3, a.reps)
 
