@@ -32,8 +32,11 @@ Pins (tests/test_oracle_*.py, all ``-m "not gpu"``):
   tqr / tpinv              X = Q * R and Q^T * Q = I with spatial T-products,
                            triangular slices with a real non-negative
                            diagonal, numpy QR at n3 = 1; the four Penrose
-                           conditions with spatial T-products (full rank and
-                           rank deficient), X^+ * X = I for full column rank
+                           conditions with spatial T-products (full rank,
+                           rank deficient, wide), X^+ * X = I for full column
+                           rank; at n3 = 1 a matrix with known singular values
+                           gives V_r diag(1/s_r) U_r^H on either side of the
+                           cut-off
   complete (Ex. 3)         full observation returns the data; with an exact
                            rank-k step the objective ||X - C|| never rises;
                            a tubal-rank-r tensor is recovered from half its
@@ -80,6 +83,10 @@ Readings (where the paper is silent / ambiguous):
   R20 Completion (Example 3): the iteration starts from C^(0) = T (.) M (the
       missing entries zero), uses the same test tensor Omega in every call
       of L, and returns C^(iters), whose observed entries equal the data.
+  R21 Alg. mp applies pinv to each Fourier slice without a tolerance; a
+      singular value s_j of X_f counts as nonzero when s_j > rtol * s_1(X_f)
+      (the usual relative rank cut-off of a matrix pinv), with
+      rtol = max(n1, n2) * 2^-52 unless given.
 """
 from __future__ import annotations
 
@@ -686,15 +693,33 @@ def tqr(X: np.ndarray):
     return Q, R
 
 
-def tpinv(X: np.ndarray) -> np.ndarray:
-    """Alg. mp: Moore-Penrose pseudoinverse X^+ (n2 x n1 x n3): numpy's
-    SVD-based pinv of every half-spectrum slice, mirror, inverse DFT."""
+def pinv_default_rtol(n1: int, n2: int) -> float:
+    """Default relative cut-off of tpinv for FP64 data: max(n1, n2) times the
+    FP64 machine epsilon 2^-52 (reading R21)."""
+    return max(n1, n2) * 2.0 ** -52
+
+
+def tpinv(X: np.ndarray, rtol: float | None = None) -> np.ndarray:
+    """Alg. mp: Moore-Penrose pseudoinverse X^+ (n2 x n1 x n3).
+
+    Every half-spectrum slice X_f = U diag(s) V^H (numpy's SVD, s descending)
+    is inverted on its nonzero singular values, X_f^+ = V diag(s^+) U^H, the
+    matrix form of A^+ = V * S^+ * U^T (Sec. 2: S^+ transposes S and inverts
+    its nonzero tubes); s_j counts as nonzero when s_j > rtol * s_1 (reading
+    R21; default pinv_default_rtol).  Mirror (Alg. mp, second loop), inverse
+    DFT."""
     n1, n2, n3 = X.shape
+    if rtol is None:
+        rtol = pinv_default_rtol(n1, n2)
     F = n_half(n3)
     Xb = dft_mode3(X, range(F))
     Ch = np.zeros((n2, n1, F), complex)
     for f in range(F):
-        Ch[:, :, f] = np.linalg.pinv(Xb[:, :, f])
+        U, s, Vh = np.linalg.svd(Xb[:, :, f], full_matrices=False)
+        keep = s > rtol * s[0]
+        sp = np.zeros_like(s)
+        sp[keep] = 1.0 / s[keep]
+        Ch[:, :, f] = (Vh.conj().T * sp[None, :]) @ U.conj().T
     return real_part_checked(idft_mode3(mirror(Ch, n3)))
 
 

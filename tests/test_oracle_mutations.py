@@ -96,6 +96,16 @@ def pin_tpinv(O):
     assert np.allclose(O.tprod_bcirc(P, X), O.identity_tensor(5, 4), atol=1e-10)
 
 
+def pin_tpinv_cutoff(O):
+    g = np.random.default_rng(51)
+    U, _ = np.linalg.qr(g.standard_normal((6, 3)))
+    V, _ = np.linalg.qr(g.standard_normal((4, 3)))
+    s = np.array([4.0, 2.0, 1e-3])
+    X = ((U * s) @ V.T)[:, :, None]
+    want = (V[:, :2] / s[:2]) @ U[:, :2].T
+    assert np.allclose(O.tpinv(X, rtol=1e-2)[:, :, 0], want, atol=1e-9)
+
+
 def pin_complete(O):
     M = inputs.exact_lowrank_tensor(20, 24, 3, 2, seed=64)
     T = inputs.bernoulli_mask(M.shape, 0.6, 64)
@@ -157,8 +167,11 @@ MUTATIONS = [
     ("tqr phase applied twice to R", "Rh[:, :, f] = R * ph[:, None]", "Rh[:, :, f] = R * np.conj(ph)[:, None]",
      pin_tqr),
     ("tqr R without conj", "R = np.triu(Q.conj().T @ Xb[:, :, f])", "R = np.triu(Q.T @ Xb[:, :, f])", pin_tqr),
-    ("tpinv conjugated", "Ch[:, :, f] = np.linalg.pinv(Xb[:, :, f])", "Ch[:, :, f] = np.linalg.pinv(Xb[:, :, f]).conj()",
-     pin_tpinv),
+    ("tpinv conjugated", "Ch[:, :, f] = (Vh.conj().T * sp[None, :]) @ U.conj().T",
+     "Ch[:, :, f] = ((Vh.conj().T * sp[None, :]) @ U.conj().T).conj()", pin_tpinv),
+    ("tpinv cut-off against the smallest value", "keep = s > rtol * s[0]", "keep = s > rtol * s[-1]",
+     pin_tpinv_cutoff),
+    ("tpinv keeps every value", "keep = s > rtol * s[0]", "keep = s >= 0.0", pin_tpinv_cutoff),
     ("completion merge with the mask swapped", "C = T * Mobs + (1.0 - T) * X", "C = (1.0 - T) * Mobs + T * X",
      pin_complete),
     ("completion never updates C", "C = T * Mobs + (1.0 - T) * X", "C = T * Mobs + 0.0 * X", pin_complete),

@@ -68,3 +68,44 @@ def test_tpinv_rank_deficient():
 def test_tpinv_full_column_rank_is_left_inverse():
     X = inputs.random_tensor((9, 4, 5), 45)
     assert np.allclose(O.tprod_bcirc(O.tpinv(X), X), O.identity_tensor(4, 5), atol=1e-11)
+
+
+def _known_spectrum(n1, n2, s, seed):
+    # n1 x n2 matrix U diag(s) V^T with Haar-orthonormal U, V (numpy QR of
+    # Gaussian matrices)
+    g = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(g.standard_normal((n1, len(s))))
+    V, _ = np.linalg.qr(g.standard_normal((n2, len(s))))
+    return U, np.asarray(s, float), V
+
+
+@pytest.mark.parametrize("n1,n2", [(6, 4), (4, 6), (5, 5)])
+def test_tpinv_cutoff_known_spectrum(n1, n2):
+    # n3 = 1: X^+ = V_r diag(1/s_r) U_r^T over the singular values above
+    # rtol * s_1, written out from the constructed factors (reading R21)
+    U, s, V = _known_spectrum(n1, n2, [4.0, 2.0, 1e-3, 1e-9][: min(n1, n2)], 50 + n1)
+    X = (U * s) @ V.T
+    for rtol, r in ((1e-2, 2), (1e-5, 3), (1e-12, 4)):
+        r = min(r, len(s))
+        want = (V[:, :r] / s[:r]) @ U[:, :r].T
+        got = O.tpinv(X[:, :, None], rtol=rtol)[:, :, 0]
+        assert np.allclose(got, want, atol=1e-9 * np.abs(want).max()), (rtol, r)
+
+
+def test_tpinv_default_cutoff_drops_rounding_level_values():
+    # a rank-2 slice whose third singular value sits at rounding level: the
+    # default cut-off max(n1, n2) 2^-52 s_1 treats it as zero
+    U, s, V = _known_spectrum(7, 5, [3.0, 1.0, 1e-17], 60)
+    X = (U * s) @ V.T
+    want = (V[:, :2] / s[:2]) @ U[:, :2].T
+    assert O.pinv_default_rtol(7, 5) == 7 * 2.0 ** -52
+    assert np.allclose(O.tpinv(X[:, :, None])[:, :, 0], want, atol=1e-12)
+
+
+def test_tpinv_wide_is_transpose_of_tall():
+    # (X^T)^+ = (X^+)^T for the T-transpose, and the Penrose conditions
+    X = inputs.random_tensor((4, 9, 5), 46)
+    P = O.tpinv(X)
+    assert np.allclose(O.ttranspose(O.tpinv(O.ttranspose(X))), P, atol=1e-11)
+    tp = O.tprod_bcirc
+    assert np.allclose(tp(X, P), O.identity_tensor(4, 5), atol=1e-11)
