@@ -375,11 +375,11 @@ def tqr_runs(api, inputs, steps: int, warmup: int):
                               ("tpinv", api.tsvd_tpinv, n2 * n1 * n3)):
         ws = api.workspace(n1, n2, n3, 0, 0, 0, "f32", op, "cuda")
         for _ in range(warmup):
-            fn(A, "f32", ws=ws)
+            fn(A, prec="f32", ws=ws)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            fn(A, "f32", ws=ws)
+            fn(A, prec="f32", ws=ws)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
         gb = 4.0 * (n1 * n2 * n3 + out_elems) / 1e9

@@ -257,15 +257,36 @@ int tsvd_power_approx_omega(const void* A, const void* Omega, int64_t n1,
 int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec,
              void* Q, void* R, void* ws, size_t ws_bytes, void* stream);
 
-/* Alg. mp: Moore-Penrose T-pseudoinverse X = A^+ (n2 x n1 x n3, Sec. 2), for
- * tensors whose Fourier slices have full column rank (n1 >= n2, else
- * TSVD_EINVAL; a wide tensor follows from (A^T)^+ = (A^+)^T).  Per slice,
- * A_f = Q_f R_f as in tsvd_tqr and A_f^+ = R_f^{-1} Q_f^H (FP64 triangular
- * inverse and product).  Rank-deficient slices are outside its domain: their
- * R_f^{-1} is not the pseudoinverse's.  prec: TSVD_PREC_F64 or
- * TSVD_PREC_F32.  Workspace: tsvd_workspace_bytes(..., TSVD_OP_TPINV). */
-int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec,
-               void* X, void* ws, size_t ws_bytes, void* stream);
+/* Alg. mp: Moore-Penrose T-pseudoinverse X = A^+ (n2 x n1 x n3, Sec. 2), the
+ * tensor with A*X*A = A, X*A*X = X and A*X, X*A symmetric, for any shape and
+ * rank.  Per Fourier slice f = 0 .. n3/2 the Gram on the short side,
+ * G_f = A_f^H A_f (n1 >= n2) or A_f A_f^H (n1 < n2), r = min(n1, n2), gives
+ * all r eigenpairs (FP64 Hermitian eigensolver); a singular value
+ * s_j = sqrt(lambda_j) counts as nonzero when s_j > rtol * s_1(A_f), and
+ * X_f = W diag(s^-2 over those) W^H A_f^H (tall) or A_f^H W diag(...) W^H
+ * (wide), which is V S^+ U^H, the matrix form of A^+ = V * S^+ * U^T
+ * (S^+ inverts the nonzero tubes of S, Sec. 2); conjugate symmetry gives the
+ * other slices (Alg. mp, second loop).
+ * rtol: relative cut-off; rtol <= 0 takes tsvd_tpinv_default_rtol(n1, n2,
+ * prec).  The Gram squares the spectrum, so singular values below about
+ * sqrt((n1 + n2) 2^-53) s_1 are not resolved: an rtol below
+ * 4 sqrt((n1 + n2) 2^-53) returns TSVD_EINVAL, and a kept singular value
+ * s_j carries a relative error of about (n1 + n2) 2^-53 (s_1 / s_j)^2.
+ * prec: TSVD_PREC_F64 or TSVD_PREC_F32 (storage and the final product; the
+ * Gram, eigensolver and weights are FP64).  Requirements:
+ * min(n1, n2) <= 1024, n3 <= 4096, n1 * n2 * n3 < 2^31.  A slice whose
+ * eigenvector iteration did not converge is counted in
+ * TSVD_INFO_EIG_NOCONV.  Workspace: tsvd_workspace_bytes(n1, n2, n3, 0, 0,
+ * 0, prec, TSVD_OP_TPINV). */
+int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, double rtol,
+               int prec, void* X, void* ws, size_t ws_bytes, void* stream);
+
+/* Default relative cut-off of tsvd_tpinv: max(max(n1, n2) eps,
+ * 4 sqrt((n1 + n2) 2^-53)) with eps the machine epsilon of the data
+ * (2^-52 for TSVD_PREC_F64, 2^-23 for TSVD_PREC_F32), the usual matrix pinv
+ * tolerance raised to what the FP64 Gram resolves.  Returns -1 for invalid
+ * arguments.  Host only. */
+double tsvd_tpinv_default_rtol(int64_t n1, int64_t n2, int prec);
 
 /* Completion of Sec. 5, Example 3: alternate a rank-k approximation and the
  * data constraint,

@@ -25,7 +25,7 @@ EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_omeg
            "tsvd_rbk", "tsvd_rbk_omega", "tsvd_rbk_noalloc", "tsvd_rbk_approx", "tsvd_rbk_approx_omega",
            "tsvd_power", "tsvd_power_omega", "tsvd_power_approx", "tsvd_power_approx_omega",
            "tsvd_rbk_literal", "tsvd_rbk_literal_omega", "tsvd_complete", "tsvd_complete_omega",
-           "tsvd_tqr", "tsvd_tpinv", "tsvd_proj", "tsvd_proj_omega", "tsvd_proj_backward",
+           "tsvd_tqr", "tsvd_tpinv", "tsvd_tpinv_default_rtol", "tsvd_proj", "tsvd_proj_omega", "tsvd_proj_backward",
            "tsvd_proj_backward_omega", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
            "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_heig",
            "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read", "tsvd_diag_omega")
@@ -64,7 +64,9 @@ def _load():
     lib.tsvd_tqr.restype = ci
     lib.tsvd_tqr.argtypes = [vp, i64, i64, i64, ci, vp, vp, vp, sz, vp]
     lib.tsvd_tpinv.restype = ci
-    lib.tsvd_tpinv.argtypes = [vp, i64, i64, i64, ci, vp, vp, sz, vp]
+    lib.tsvd_tpinv.argtypes = [vp, i64, i64, i64, ctypes.c_double, ci, vp, vp, sz, vp]
+    lib.tsvd_tpinv_default_rtol.restype = ctypes.c_double
+    lib.tsvd_tpinv_default_rtol.argtypes = [i64, i64, ci]
     lib.tsvd_complete.restype = ci
     lib.tsvd_complete.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, u64, i64, ci, ci, vp, vp, sz, vp]
     lib.tsvd_complete_omega.restype = ci
@@ -296,8 +298,10 @@ def tsvd_tqr(A: torch.Tensor, prec=None, ws=None):
     return Q, R
 
 
-def tsvd_tpinv(A: torch.Tensor, prec=None, ws=None):
-    """Alg. mp for slices of full column rank: returns A^+ (n2, n1, n3)."""
+def tsvd_tpinv(A: torch.Tensor, rtol: float = 0.0, prec=None, ws=None):
+    """Alg. mp: returns A^+ (n2, n1, n3) for any shape and rank; singular
+    values s_j <= rtol * s_1 of a Fourier slice count as zero (rtol <= 0:
+    tpinv_default_rtol)."""
     prec = _prec_of(A, prec)
     dt = _dtype_of(prec)
     _check_in(A, dt, "A")
@@ -305,8 +309,14 @@ def tsvd_tpinv(A: torch.Tensor, prec=None, ws=None):
     if ws is None:
         ws = workspace(n1, n2, n3, 0, 0, 0, prec, "tpinv", A.device)
     X = torch.empty((n2, n1, n3), dtype=dt, device=A.device)
-    _check(lib.tsvd_tpinv(_ptr(A), n1, n2, n3, PREC[prec], _ptr(X), _ptr(ws), ws.numel(), _stream(A.device)))
+    _check(lib.tsvd_tpinv(_ptr(A), n1, n2, n3, float(rtol), PREC[prec], _ptr(X), _ptr(ws), ws.numel(),
+                          _stream(A.device)))
     return X
+
+
+def tpinv_default_rtol(n1: int, n2: int, prec: str) -> float:
+    """The cut-off tsvd_tpinv takes for rtol <= 0."""
+    return float(lib.tsvd_tpinv_default_rtol(n1, n2, PREC[prec]))
 
 
 def tsvd_complete(M: torch.Tensor, mask: torch.Tensor, Omega, k: int, b: int, q: int, iters: int,

@@ -1079,7 +1079,8 @@ __device__ __forceinline__ double hash_uniform(uint32_t a, uint32_t b) {
 
 __global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned char* scratch, size_t per_slice,
                                                          const double* __restrict__ lambda,
-                                                         cx<double>* __restrict__ Wout, int* info) {
+                                                         cx<double>* __restrict__ Wout, int* info,
+                                                         double vfloor_rel) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* d = reinterpret_cast<double*>(smem);
   double* e = d + m;
@@ -1111,9 +1112,18 @@ __global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned 
   // eigenvalues further apart are computed independently (in parallel), with
   // a contamination of about eps * ||T|| / gap <= 2e-7 by their neighbours.
   const double ortol = 1e-9 * tnorm;
+  // eigenvalues at or below vfloor_rel * lambda_0 (when vfloor_rel > 0) get a
+  // zero vector and are not computed: a caller that discards them saves the
+  // inverse iterations of a large cluster near zero
+  const bool use_floor = vfloor_rel > 0.0;
+  const double vfloor = vfloor_rel * lam[0];
+  if (use_floor && !(lam[t0] > vfloor)) {
+    for (int i = lane; i < m; i += 64) W[(int64_t)i * k + t0] = cx<double>{0.0, 0.0};
+    return;
+  }
   if (t0 > 0 && lam[t0 - 1] - lam[t0] < ortol) return;  // not the head of its cluster
   int t1 = t0 + 1;
-  while (t1 < k && lam[t1 - 1] - lam[t1] < ortol) ++t1;
+  while (t1 < k && lam[t1 - 1] - lam[t1] < ortol && !(use_floor && !(lam[t1] > vfloor))) ++t1;
   const double tinyp = eps * fmax(tnorm, 1e-300);
   for (int t = t0; t < t1; ++t) {
     const double lv = lam[t];
@@ -1435,7 +1445,8 @@ __global__ __launch_bounds__(256) void heig_backxf2_kernel(int m, int k, unsigne
 }
 
 hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, int k, int batch, double* lambda,
-                     double* W, void* scratch, int* info, hipStream_t s, int stages, bool upper_only) {
+                     double* W, void* scratch, int* info, hipStream_t s, int stages, bool upper_only,
+                     double vfloor_rel) {
   if (batch <= 0) return hipSuccess;
   if (m > 1024 || k > m || k < 1) return hipErrorInvalidValue;
   static bool attr_set = false;
@@ -1534,7 +1545,7 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
   const size_t sm3 = (size_t)2 * m * sizeof(double) + (size_t)nw * 6 * m * sizeof(double);
   if (stages & HEIG_INVIT) {
     hipLaunchKernelGGL(heig_invit_kernel, dim3(batch, (k + nw - 1) / nw), dim3(64 * nw), sm3, s, m, k, sc, per,
-                       lambda, (cx<double>*)W, info);
+                       lambda, (cx<double>*)W, info, vfloor_rel);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // 4. back-transformation

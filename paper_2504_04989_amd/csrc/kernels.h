@@ -104,15 +104,21 @@ enum HeigStage { HEIG_TRIDIAG = 1, HEIG_BISECT = 2, HEIG_INVIT = 4, HEIG_BACKXF 
 size_t heig_scratch_bytes(int m, int k);
 // upper_only: only the entries on and above the diagonal of the summed
 // partials are valid (the matrix is taken as their Hermitian extension).
+// vfloor_rel > 0: eigenvalues lambda_j <= vfloor_rel * lambda_0 get a zero
+// vector instead of an inverse iteration.
 hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, int k, int batch, double* lambda,
                      double* W, void* scratch, int* info, hipStream_t s, int stages = HEIG_ALL,
-                     bool upper_only = false);
+                     bool upper_only = false, double vfloor_rel = 0.0);
 
 // Lift helpers.
 // Wout (batch x m x k, dtype t) = W * diag(scale) where scale = sqrt(lambda)
 // (scale_mode 0), 1/sqrt(lambda) (mode 1, 0 where lambda <= 0) or 1 (mode 2).
 hipError_t scale_cols(const double* W, const double* lambda, void* Wout, int m, int k, int batch, int scale_mode,
                       DType t, hipStream_t s);
+// Ws = W diag(g), g_c = 1 / lambda_c where lambda_c > thr * lambda_0 and
+// lambda_c > 0, else 0 (FP64, batch x m x k, lambda descending per slice).
+hipError_t pinv_weights(const double* W, const double* lambda, void* Ws, int m, int k, int batch, double thr,
+                        hipStream_t s);
 // Phase canonicalisation of (U_f, V_f) column pairs and sigma = sqrt(lambda).
 size_t canon_scratch_bytes(int64_t n1, int k, int batch);
 hipError_t lift_operands_f32(const double* W, const double* lambda, void* Wf, void* Wsf, int m, int k, int batch,

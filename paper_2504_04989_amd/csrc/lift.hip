@@ -40,6 +40,30 @@ hipError_t scale_cols(const double* W, const double* lambda, void* Wout, int m, 
   return hipGetLastError();
 }
 
+// Ws[f][r][c] = W[f][r][c] / lambda[f][c] where lambda[f][c] > thr * lambda[f][0]
+// and lambda[f][c] > 0, else 0: the eigenvectors of a Gram X^H X (or X X^H)
+// weighted by sigma^-2 over the singular values kept by a relative cut-off
+// sigma_c > sqrt(thr) sigma_0.
+__global__ void pinv_weights_kernel(const cx<double>* W, const double* lambda, cx<double>* out, int m, int k,
+                                    int64_t total, double thr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int c = (int)(t % k);
+  const int64_t f = t / ((int64_t)m * k);
+  const double l = lambda[f * k + c], l0 = lambda[f * k];
+  const double g = (l > 0.0 && l > thr * l0) ? 1.0 / l : 0.0;
+  const cx<double> w = W[t];
+  out[t] = cx<double>{w.re * g, w.im * g};
+}
+hipError_t pinv_weights(const double* W, const double* lambda, void* Ws, int m, int k, int batch, double thr,
+                        hipStream_t s) {
+  const int64_t total = (int64_t)batch * m * k;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(pinv_weights_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     (const cx<double>*)W, lambda, (cx<double>*)Ws, m, k, total, thr);
+  return hipGetLastError();
+}
+
 // W_k rounded to complex FP32, and W_k diag(1 / sigma) likewise (sigma =
 // sqrt(lambda), 0 where lambda <= 0): the thin operands of the lift products
 // U_f = Q_f W_k and V_f = T_f W_k Sigma^{-1} on the FP32 path.

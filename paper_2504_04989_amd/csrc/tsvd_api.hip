@@ -17,6 +17,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -76,23 +77,70 @@ int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
   return (int)ns;
 }
 
+// Alg. mp: per Fourier slice the Gram on the short side (A_f^H A_f when
+// n1 >= n2, else A_f A_f^H; r = min(n1, n2)), all its eigenpairs, the
+// sigma^-2-weighted projector Wg and the product with A_f^H.
+int make_plan_tpinv(int64_t n1, int64_t n2, int64_t n3, int prec, Plan* p) {
+  if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32)
+    return fail(TSVD_EINVAL, "the pseudoinverse takes TSVD_PREC_F64 or TSVD_PREC_F32");
+  const int64_t r = std::min(n1, n2), K = std::max(n1, n2);
+  if (r > 1024) return fail(TSVD_EINVAL, "min(n1, n2) must be <= 1024");
+  if (n3 > 4096) return fail(TSVD_EINVAL, "n3 must be <= 4096");
+  if (n1 * n2 * n3 >= (int64_t)1 << 31 || n1 * n2 >= (int64_t)1 << 31)
+    return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
+  *p = Plan{};
+  p->n1 = n1;
+  p->n2 = n2;
+  p->n3 = n3;
+  p->k = r;
+  p->b = r;
+  p->q = 0;
+  p->m = r;
+  p->F = n3 / 2 + 1;
+  p->prec = prec;
+  p->dt = prec == TSVD_PREC_F64 ? DT_F64 : DT_F32;
+  p->cs = prec == TSVD_PREC_F64 ? 16 : 8;
+  p->tensor_op = true;
+  p->kmode = KM_F32;
+  const int64_t F = p->F, tm = (r + 63) / 64;
+  p->nsplit_g = split_for(K, tm * tm, F, &p->kchunk_g);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  const size_t cs = p->cs, rr = (size_t)r * r;
+  p->o_info = take(256);
+  p->o_abar = take((size_t)F * n1 * n2 * cs);
+  size_t part = (size_t)p->nsplit_g * F * rr * 16;
+  if (p->dt == DT_F32 && n1 >= n2) part = ogemm_tn_part_bytes((int)r, (int)n1, (int)r, (int)F);
+  p->o_part = take(part);
+  p->o_lam = take((size_t)F * r * 8);
+  p->o_wd = take((size_t)F * rr * 16);
+  p->o_wds = take((size_t)F * rr * 16);
+  p->o_rinv = take((size_t)F * rr * 16);
+  p->o_heig = take((size_t)F * heig_scratch_bytes((int)r, (int)r));
+  p->o_xp = take((size_t)F * n2 * n1 * cs);
+  p->total = o;
+  return TSVD_OK;
+}
+
 int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, int prec, int op, Plan* p) {
   if (n1 < 1 || n2 < 1 || n3 < 1) return fail(TSVD_EINVAL, "n1, n2, n3 must be >= 1");
+  if (op == TSVD_OP_TPINV) return make_plan_tpinv(n1, n2, n3, prec, p);
   // completion (Example 3): the approximation plan of the chosen method plus
   // the iterate buffers
   const bool completion = op == TSVD_OP_COMPLETE_RBK || op == TSVD_OP_COMPLETE_POWER;
   if (completion) op = op == TSVD_OP_COMPLETE_RBK ? TSVD_OP_APPROX : TSVD_OP_POWER_APPROX;
   // literal Krylov powers: the buffers of the approximation
   if (op == TSVD_OP_RBK_LITERAL) op = TSVD_OP_APPROX;
-  const bool tensor_op = op == TSVD_OP_TQR || op == TSVD_OP_TPINV;
+  const bool tensor_op = op == TSVD_OP_TQR;
   if (tensor_op) {
-    // Alg. TQR / Alg. mp: the QR of every slice A_f itself (r = min(n1, n2)
-    // columns); k, b and q are not used
+    // Alg. TQR: the QR of every slice A_f itself (r = min(n1, n2) columns);
+    // k, b and q are not used
     if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32)
-      return fail(TSVD_EINVAL, "T-QR and the pseudoinverse take TSVD_PREC_F64 or TSVD_PREC_F32");
-    if (op == TSVD_OP_TPINV && n1 < n2)
-      return fail(TSVD_EINVAL, "the pseudoinverse needs n1 >= n2 (slices of full column rank); for n1 < n2 use "
-                               "(X^T)^+ = (X^+)^T");
+      return fail(TSVD_EINVAL, "T-QR takes TSVD_PREC_F64 or TSVD_PREC_F32");
     if (std::min(n1, n2) > 1024) return fail(TSVD_EINVAL, "min(n1, n2) must be <= 1024");
     // the r = min(n1, n2) columns are orthonormalised in equal panels of at
     // most 128 columns (block Gram-Schmidt twice against the earlier panels,
@@ -196,10 +244,8 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
     }
   }
   p->o_part = take(part);
-  // the pseudoinverse inverts the whole r x r factor R_f (r = m)
-  const int64_t rb = op == TSVD_OP_TPINV ? m : b;
-  p->o_rinv = take((size_t)F * rb * rb * 16);
-  p->o_chol = take(chol_uses_lds(rb) ? 0 : (size_t)F * rb * (rb + 1) / 2 * 16);
+  p->o_rinv = take((size_t)F * b * b * 16);
+  p->o_chol = take(chol_uses_lds(b) ? 0 : (size_t)F * b * (b + 1) / 2 * 16);
   const bool need_svd = (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || power);
   p->o_lam = take(need_svd ? (size_t)F * k * 8 : 0);
   p->o_sig = take(need_svd ? (size_t)F * k * 8 : 0);
@@ -222,7 +268,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->o_scx = take(need_svd ? (size_t)F * k * cs : 0);
   p->o_us = take(op == TSVD_OP_APPROX || op == TSVD_OP_POWER_APPROX ? (size_t)F * n1 * k * cs : 0);
   p->o_rout = take(tensor_op ? (size_t)F * m * n2 * cs : 0);
-  p->o_xp = take(op == TSVD_OP_TPINV ? (size_t)F * n2 * n1 * cs : 0);
+  p->o_xp = take(0);
   const bool bwd = op == TSVD_OP_PROJ_BWD;
   p->o_gbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
   p->o_dbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
@@ -1456,47 +1502,112 @@ int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void* 
   return TSVD_OK;
 }
 
-int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void* X, void* ws, size_t ws_bytes,
-               void* stream) {
+// Smallest relative cut-off the FP64 Gram resolves: its eigenvalues carry an
+// absolute error of about (n1 + n2) u lambda_0 (u = 2^-53), so singular values
+// below sqrt((n1 + n2) u) sigma_0 cannot be told from zero; the factor 4 keeps
+// the kept values 16x above that level.
+double tpinv_floor(int64_t n1, int64_t n2) { return 4.0 * std::sqrt((double)(n1 + n2) * 0x1p-53); }
+
+double tsvd_tpinv_default_rtol(int64_t n1, int64_t n2, int prec) {
+  if (n1 < 1 || n2 < 1 || (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32)) return -1.0;
+  const double eps = prec == TSVD_PREC_F64 ? 0x1p-52 : 0x1p-23;
+  return std::max((double)std::max(n1, n2) * eps, tpinv_floor(n1, n2));
+}
+
+int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, double rtol, int prec, void* X, void* ws,
+               size_t ws_bytes, void* stream) {
   Plan p;
   int r = make_plan(n1, n2, n3, 1, 1, 0, prec, TSVD_OP_TPINV, &p);
   if (r) return r;
+  if (std::isnan(rtol)) return fail(TSVD_EINVAL, "rtol is NaN");
+  if (rtol <= 0.0)
+    rtol = tsvd_tpinv_default_rtol(n1, n2, prec);
+  else if (rtol < tpinv_floor(n1, n2))
+    return fail(TSVD_EINVAL, "rtol is below 4 sqrt((n1 + n2) 2^-53), the resolution of the FP64 Gram eigensolver");
   if ((r = check_ptrs({A, X}, ws, ws_bytes, p))) return r;
   Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  const DType dt = p.dt;
+  const int64_t rr = p.m, F = p.F, s12 = n1 * n2;
+  const bool tall = n1 >= n2;
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(zero_info(c.info(), c.s));
+  }
+  void* Ab = c.at(p.o_abar);
+  {
+    Timed tm_(K_FFT_A, c.s);
+    HIPCHK(fft_r2c(A, Ab, s12, (int)n3, dt, c.s));
+  }
+  // G_f on the short side: A_f^H A_f = V S^2 V^H (tall) or A_f A_f^H = U S^2 U^H
+  double* part = c.at<double>(p.o_part);
   int nsum = 1;
-  if ((r = tqr_core(c, A, &nsum))) return r;
-  // X^+_f = R_f^{-1} Q_f^H (slices of full column rank, r = n2)
-  {
-    Timed tm_(K_CHOL, c.s);
-    HIPCHK(chol_inv_ex(c.at<double>(p.o_part), nsum, p.F * p.m * p.n2, c.at<double>(p.o_rinv), c.at(p.o_chol),
-                       (int)p.m, (int)p.F, 0.0, c.info(), c.s, 1));
+  const bool upper = tall && dt == DT_F32;
+  if (tall) {
+    if ((r = inner_products(c, Ab, n2, (int)n2, Ab, n2, (int)n2, n1, s12, s12, p.nsplit_g, p.kchunk_g, part, &nsum,
+                            K_GEMM_LIFT, upper)))
+      return r;
+  } else {
+    GemmDesc d = gd();
+    d.A = Ab;
+    d.lda = n2;
+    d.strideA = s12;
+    d.ta = dt;
+    d.B = Ab;
+    d.ldb = n2;
+    d.strideB = s12;
+    d.tb = dt;
+    d.b_conj = true;
+    d.C = part;
+    d.ldc = n1;
+    d.strideC = n1 * n1;
+    d.tc = DT_F64;
+    d.M = (int)n1;
+    d.N = (int)n1;
+    d.K = (int)n2;
+    d.batch = (int)F;
+    d.nsplit = p.nsplit_g;
+    d.kchunk = p.kchunk_g;
+    d.c_split_stride = F * n1 * n1;
+    d.compute = DT_F64;
+    {
+      Timed tm_(K_GEMM_LIFT, c.s);
+      HIPCHK(zgemm(d, c.s));
+    }
+    nsum = p.nsplit_g;
   }
-  GemmDesc d = gd();
-  d.A = c.at(p.o_rinv);
-  d.lda = p.m;
-  d.strideA = p.m * p.m;
-  d.ta = DT_F64;
-  d.B = c.at(p.o_q);
-  d.ldb = p.m;
-  d.strideB = p.n1 * p.m;
-  d.tb = p.dt;
-  d.b_conj = true;
-  d.C = c.at(p.o_xp);
-  d.ldc = p.n1;
-  d.strideC = p.n2 * p.n1;
-  d.tc = p.dt;
-  d.M = (int)p.n2;
-  d.N = (int)p.n1;
-  d.K = (int)p.m;
-  d.batch = (int)p.F;
-  d.compute = DT_F64;
-  {
-    Timed tm_(K_GEMM_LIFT, c.s);
-    HIPCHK(zgemm(d, c.s));
+  // all r eigenpairs; those below a quarter of the cut-off get zero vectors
+  double* lam = c.at<double>(p.o_lam);
+  double* W = c.at<double>(p.o_wd);
+  const double thr = rtol * rtol;
+  const int stage_cls[4][2] = {
+      {HEIG_TRIDIAG, K_HEIG_TRI}, {HEIG_BISECT, K_HEIG_BISECT}, {HEIG_INVIT, K_HEIG_INVIT}, {HEIG_BACKXF, K_HEIG_BACKXF}};
+  for (const auto& sc : stage_cls) {
+    Timed tm_(sc[1], c.s);
+    HIPCHK(heig_topk(part, nsum, F * rr * rr, (int)rr, (int)rr, (int)F, lam, W, c.at(p.o_heig), c.info(), c.s, sc[0],
+                     upper, 0.25 * thr));
   }
+  // Wg = W diag(s^-2 over the kept values) W^H
+  void* Ws = c.at(p.o_wds);
+  void* Wg = c.at(p.o_rinv);
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(pinv_weights(W, lam, Ws, (int)rr, (int)rr, (int)F, thr, c.s));
+  }
+  if ((r = gemm(c, K_GEMM_LIFT, Op{Ws, rr, rr * rr, DT_F64, false}, Op{W, rr, rr * rr, DT_F64, true}, Wg, rr, rr * rr,
+                DT_F64, (int)rr, (int)rr, (int)rr, 1.0, 0.0, DT_F64)))
+    return r;
+  // X_f^+ = V S^-2 V^H A_f^H = V S^+ U^H (tall), A_f^H U S^-2 U^H (wide)
+  void* Xp = c.at(p.o_xp);
+  if (tall)
+    r = gemm(c, K_GEMM_LIFT, Op{Wg, rr, rr * rr, DT_F64, false}, Op{Ab, n2, s12, dt, true}, Xp, n1, s12, dt, (int)n2,
+             (int)n1, (int)n2, 1.0, 0.0, DT_F64);
+  else
+    r = gemm(c, K_GEMM_LIFT, Op{Ab, n2, s12, dt, true}, Op{Wg, rr, rr * rr, DT_F64, false}, Xp, n1, s12, dt, (int)n2,
+             (int)n1, (int)n1, 1.0, 0.0, DT_F64);
+  if (r) return r;
   {
     Timed tm_(K_FFT_INV, c.s);
-    HIPCHK(fft_c2r(c.at(p.o_xp), p.n2 * p.n1, X, p.n2 * p.n1, (int)p.n3, p.dt, c.s));
+    HIPCHK(fft_c2r(Xp, s12, X, s12, (int)n3, dt, c.s));
   }
   g_err.clear();
   return TSVD_OK;

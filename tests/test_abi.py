@@ -2,6 +2,7 @@
 declared in include/*.h, sizes workspaces and rejects bad arguments on the
 host before anything is enqueued."""
 import ctypes
+import math
 import glob
 import os
 import re
@@ -108,8 +109,9 @@ def test_tensor_ops_sizes_and_rejections():
     assert api.workspace_bytes(30, 20, 8, 0, 0, 0, "f32", "tqr") > 0
     assert api.workspace_bytes(20, 30, 8, 0, 0, 0, "f64", "tqr") > 0          # wide: r = n1
     assert api.workspace_bytes(30, 20, 8, 0, 0, 0, "f64", "tpinv") > 0
-    assert api.workspace_bytes(20, 30, 8, 0, 0, 0, "f64", "tpinv") == 0        # needs n1 >= n2
-    assert "n1 >= n2" in api.lib.tsvd_last_error().decode()
+    assert api.workspace_bytes(20, 30, 8, 0, 0, 0, "f64", "tpinv") > 0         # wide: Gram A A^H
+    assert api.workspace_bytes(2000, 1100, 4, 0, 0, 0, "f32", "tpinv") == 0   # min(n1, n2) > 1024
+    assert api.workspace_bytes(30, 20, 8, 0, 0, 0, "bf16", "tpinv") == 0
     assert api.workspace_bytes(30, 20, 8, 0, 0, 0, "bf16x3", "tqr") == 0      # FP64 / FP32 only
     assert api.workspace_bytes(2000, 1100, 4, 0, 0, 0, "f32", "tqr") == 0     # min(n1, n2) > 1024
     L = api.lib
@@ -117,7 +119,23 @@ def test_tensor_ops_sizes_and_rejections():
     fake = ctypes.c_void_p(1 << 20)
     assert L.tsvd_tqr(nul, 10, 8, 4, 1, nul, nul, nul, 0, nul) == api.TSVD_EINVAL
     assert L.tsvd_tqr(fake, 10, 8, 4, 1, fake, fake, fake, 16, nul) == api.TSVD_ENOMEM
-    assert L.tsvd_tpinv(fake, 8, 10, 4, 1, fake, fake, 1 << 30, nul) == api.TSVD_EINVAL
+    # rtol below 4 sqrt((n1 + n2) 2^-53), NaN rtol, null pointers
+    assert L.tsvd_tpinv(fake, 8, 10, 4, 1e-12, 1, fake, fake, 1 << 30, nul) == api.TSVD_EINVAL
+    assert "resolution" in api.lib.tsvd_last_error().decode()
+    assert L.tsvd_tpinv(fake, 8, 10, 4, float("nan"), 1, fake, fake, 1 << 30, nul) == api.TSVD_EINVAL
+    assert L.tsvd_tpinv(nul, 8, 10, 4, 0.0, 1, fake, fake, 1 << 30, nul) == api.TSVD_EINVAL
+    assert L.tsvd_tpinv(fake, 8, 10, 4, 0.0, 1, fake, fake, 16, nul) == api.TSVD_ENOMEM
+
+
+def test_tpinv_default_rtol():
+    # max(max(n1, n2) eps, 4 sqrt((n1 + n2) 2^-53)), eps of the data type
+    from paper_2504_04989_amd import api
+    floor = lambda n1, n2: 4.0 * math.sqrt((n1 + n2) * 2.0 ** -53)
+    assert api.tpinv_default_rtol(4096, 256, "f32") == 4096 * 2.0 ** -23
+    assert api.tpinv_default_rtol(90, 60, "f64") == floor(90, 60)
+    assert api.tpinv_default_rtol(3, 2, "f32") == max(3 * 2.0 ** -23, floor(3, 2))
+    assert api.tpinv_default_rtol(0, 2, "f32") == -1.0
+    assert api.tpinv_default_rtol(5, 2, "bf16") == -1.0
 
 
 def test_completion_sizes_and_rejections():
