@@ -37,7 +37,9 @@ int tsvd_diag_zgemm(const void* A, int a_conj, const void* B, int b_conj, void* 
  * slices.  A_f: rows x cols (contiguous slices); herm = 0: op = identity,
  * X_f is cols x N, C_f rows x N; herm = 1: op = ^H, X_f is rows x N, C_f
  * cols x N.  mode: 0 FP32 MFMA, 1 BF16 (one product), 2 BF16x3 (split
- * operands, three products); FP32 accumulation.  nsplit > 1 splits the
+ * operands, three products), 3 BF16x3 with A already in (hi, lo) bf16 pair
+ * form (tsvd_diag_split_bf16x3; X is complex FP32 as for the other modes),
+ * bitwise equal to mode 2 on the unsplit A; FP32 accumulation.  nsplit > 1 splits the
  * contraction (partials reduced in a fixed order).  ws: device workspace of
  * tsvd_diag_kgemm_ws_bytes() bytes (256-byte aligned; may be NULL when that
  * is 0). */
@@ -45,6 +47,13 @@ size_t tsvd_diag_kgemm_ws_bytes(int herm, int64_t rows, int64_t cols, int64_t N,
                                 int nsplit);
 int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t rows, int64_t cols, int64_t N,
                     int64_t batch, int mode, int nsplit, void* ws, size_t ws_bytes, void* stream);
+
+/* n complex FP32 values (interleaved re, im) -> n (hi, lo) bf16 pairs, the
+ * operand form of mode 3 above: hi = bf16(z) and lo = bf16(z - hi) per part
+ * (round to nearest even), stored as two 32-bit words re | im << 16 (8 bytes
+ * per value, like the input).  in, out: device pointers, 8-byte aligned, may
+ * not overlap partially (in == out is allowed).  Asynchronous on stream. */
+int tsvd_diag_split_bf16x3(const void* in, void* out, int64_t n, void* stream);
 
 /* The small Hermitian eigensolver alone (the per-slice SVD of C_f in Alg. 2
  * taken through C_f C_f^H, FP64): the k largest eigenvalues (descending) and

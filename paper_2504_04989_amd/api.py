@@ -27,7 +27,7 @@ EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_omeg
            "tsvd_rbk_literal", "tsvd_rbk_literal_omega", "tsvd_complete", "tsvd_complete_omega",
            "tsvd_tqr", "tsvd_tpinv", "tsvd_tpinv_default_rtol", "tsvd_proj", "tsvd_proj_omega", "tsvd_proj_backward",
            "tsvd_proj_backward_omega", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
-           "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_heig",
+           "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_split_bf16x3", "tsvd_diag_heig",
            "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read", "tsvd_diag_omega")
 
 
@@ -95,6 +95,8 @@ def _load():
                                     ctypes.c_double, ctypes.c_int, vp]
     lib.tsvd_diag_kgemm_ws_bytes.restype = sz
     lib.tsvd_diag_kgemm_ws_bytes.argtypes = [ctypes.c_int, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int]
+    lib.tsvd_diag_split_bf16x3.restype = ctypes.c_int
+    lib.tsvd_diag_split_bf16x3.argtypes = [vp, vp, i64, vp]
     lib.tsvd_diag_kgemm.restype = ctypes.c_int
     lib.tsvd_diag_kgemm.argtypes = [vp, ctypes.c_int, vp, vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, sz,
                                     vp]
@@ -454,7 +456,7 @@ def diag_zgemm(A, B, a_conj=False, b_conj=False, C=None, alpha=1.0, beta=0.0):
     return C
 
 
-KGEMM_MODE = {"f32": 0, "bf16": 1, "bf16x3": 2}
+KGEMM_MODE = {"f32": 0, "bf16": 1, "bf16x3": 2, "bf16x3s": 3}
 
 
 def diag_kgemm(A, X, herm=False, mode="f32", nsplit=1):
@@ -469,6 +471,16 @@ def diag_kgemm(A, X, herm=False, mode="f32", nsplit=1):
     _check(lib.tsvd_diag_kgemm(_ptr(A), int(herm), _ptr(X), _ptr(C), rows, cols, N, batch, KGEMM_MODE[mode], nsplit,
                                _ptr(ws), ws.numel(), _stream(A.device)))
     return C
+
+
+def diag_split_bf16x3(Z):
+    """Complex64 tensor -> the same number of (hi, lo) bf16 pairs (see
+    tsvd_diag_split_bf16x3), held in a complex64 tensor of the same shape as
+    opaque bits: the A operand of diag_kgemm(..., mode="bf16x3s")."""
+    Z = Z.contiguous()
+    out = torch.empty_like(Z)
+    _check(lib.tsvd_diag_split_bf16x3(_ptr(Z), _ptr(out), Z.numel(), _stream(Z.device)))
+    return out
 
 
 def diag_heig(G, k):

@@ -38,9 +38,18 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *CXXFLAGS, "-c", src, "-o", obj]
+# host code only: AddressSanitizer and UndefinedBehaviorSanitizer on the CPU
+# side of every source (argument checks, workspace planning, the host
+# generator); device code is built as usual
+SAN_FLAGS = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+SAN_BUILD = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN_BUILD, "libtsvd_rbk_san.so")
+
+
+def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [_hipcc(), *CXXFLAGS, *extra, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
                      if "packed-fp32-ops" not in l)
@@ -55,19 +64,24 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build_library(jobs: int = 8) -> str:
-    """Compile every source and link the shared library; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
-    os.makedirs(LIBDIR, exist_ok=True)
+def build_library(jobs: int = 8, sanitize: bool = False) -> str:
+    """Compile every source and link the shared library; returns its path.
+    sanitize: a separate build with host-side ASan / UBSan (SAN_LIB), for
+    a sanitizer-linked host program on the CPU."""
+    out_dir = SAN_BUILD if sanitize else BUILD
+    lib = SAN_LIB if sanitize else LIB
+    os.makedirs(out_dir, exist_ok=True)
+    os.makedirs(os.path.dirname(lib), exist_ok=True)
+    extra = SAN_FLAGS if sanitize else ()
     with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, 16))) as ex:
-        objs = list(ex.map(_compile, sources()))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, out_dir, extra), sources()))
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

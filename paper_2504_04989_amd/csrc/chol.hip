@@ -307,7 +307,30 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
   constexpr int BP = NT * TSZ;
 
   // ---- load: lower triangle (i >= j) of the padded matrix into tiles ----
-  for (int e = tid; e < BP * BP; e += CB_NT) {
+  if (mode != 0) {
+    // modes 1 and 2 need the upper triangle of the summed partials: read it
+    // row by row (coalesced) and store its conjugate transpose, L(i, j) =
+    // conj(G(j, i)) for i >= j (mode 2 keeps the diagonal real); padding rows
+    // b .. BP - 1 take the identity
+#pragma unroll 2
+    for (int e = tid; e < b * b; e += CB_NT) {
+      const int r = e / b, cc = e - r * b;
+      if (cc >= r) {
+        cx<double> g{0.0, 0.0};
+        for (int s = 0; s < nsum; ++s) {
+          const cx<double> x = G[s * part_stride + e];
+          g.re += x.re;
+          g.im += x.im;
+        }
+        L[tix(cc >> 4, r >> 4) + (cc & 15) * TRS + (r & 15)] = cx<double>{g.re, (mode == 2 && cc == r) ? 0.0 : -g.im};
+      }
+    }
+    for (int e = tid; e < (BP - b) * BP; e += CB_NT) {
+      const int i = b + e / BP, j = e % BP;
+      if (j <= i) L[tix(i >> 4, j >> 4) + (i & 15) * TRS + (j & 15)] = cx<double>{i == j ? 1.0 : 0.0, 0.0};
+    }
+  }
+  for (int e = tid; mode == 0 && e < BP * BP; e += CB_NT) {
     const int i = e / BP, j = e % BP;
     if (j > i) continue;
     cx<double> v{(i == j && i >= b) ? 1.0 : 0.0, 0.0};
@@ -315,17 +338,10 @@ __global__ __launch_bounds__(CB_NT) void chol_blk_kernel(const cx<double>* __res
       v = cx<double>{0.0, 0.0};
       for (int s = 0; s < nsum; ++s) {
         const cx<double>* Gs = G + s * part_stride;
-        if (mode != 0) {
-          // mode 1: L = R^H; mode 2: the Hermitian extension of the upper triangle
-          const cx<double> r = Gs[(int64_t)j * b + i];
-          v.re += r.re;
-          v.im -= (mode == 2 && i == j) ? 0.0 : r.im;
-        } else {
-          const cx<double> g = Gs[(int64_t)i * b + j];
-          const cx<double> h = Gs[(int64_t)j * b + i];
-          v.re += 0.5 * (g.re + h.re);
-          v.im += 0.5 * (g.im - h.im);
-        }
+        const cx<double> g = Gs[(int64_t)i * b + j];
+        const cx<double> h = Gs[(int64_t)j * b + i];
+        v.re += 0.5 * (g.re + h.re);
+        v.im += 0.5 * (g.im - h.im);
       }
     }
     L[tix(i >> 4, j >> 4) + (i & 15) * TRS + (j & 15)] = v;

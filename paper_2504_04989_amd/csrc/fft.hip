@@ -770,7 +770,23 @@ __device__ __forceinline__ void st_stream4(float4* p, float4 x) {
 #endif
 }
 
-template <int N>
+// One complex FP32 value z as the pair (hi, lo) of complex bf16 values with
+// hi = bf16(z) and lo = bf16(z - hi) (round to nearest even), packed as
+// (re_hi | im_hi << 16, re_lo | im_lo << 16): the operand form of the
+// three-product BF16 Krylov products, 8 bytes like the FP32 value.
+__device__ __forceinline__ void st_split2(float2* p, float a, float b) {
+  const __bf16 ha = (__bf16)a, hb = (__bf16)b;
+  const __bf16 la = (__bf16)(a - (float)ha), lb = (__bf16)(b - (float)hb);
+  const uint32_t h = (uint32_t)__builtin_bit_cast(unsigned short, ha) |
+                     ((uint32_t)__builtin_bit_cast(unsigned short, hb) << 16);
+  const uint32_t l = (uint32_t)__builtin_bit_cast(unsigned short, la) |
+                     ((uint32_t)__builtin_bit_cast(unsigned short, lb) << 16);
+  st_stream2(p, __uint_as_float(h), __uint_as_float(l));
+}
+
+// SPLIT: the half spectrum is written as (hi, lo) bf16 pairs (st_split2)
+// instead of complex FP32.
+template <int N, bool SPLIT>
 __global__ __launch_bounds__(REG_TUBES) void fft_r2c_reg_kernel(const float* __restrict__ X,
                                                                  float2* __restrict__ Xb, int64_t ntubes) {
   constexpr int M = N / 2, LB = ct_log2(M), SPF = N + 4;
@@ -819,8 +835,13 @@ __global__ __launch_bounds__(REG_TUBES) void fft_r2c_reg_kernel(const float* __r
     const double orr = 0.5 * (zfi + zgi), oi = -0.5 * (zfr - zgr);
     const double wr = tw.c[f], wi = -tw.s[f];
     const double tr = fma(wr, orr, -wi * oi), ti = fma(wr, oi, wi * orr);
-    st_stream2(out + (int64_t)f * ntubes, (float)(er + tr), (float)(ei + ti));
-    if (g != f) st_stream2(out + (int64_t)g * ntubes, (float)(er - tr), (float)(ti - ei));
+    if (SPLIT) {
+      st_split2(out + (int64_t)f * ntubes, (float)(er + tr), (float)(ei + ti));
+      if (g != f) st_split2(out + (int64_t)g * ntubes, (float)(er - tr), (float)(ti - ei));
+    } else {
+      st_stream2(out + (int64_t)f * ntubes, (float)(er + tr), (float)(ei + ti));
+      if (g != f) st_stream2(out + (int64_t)g * ntubes, (float)(er - tr), (float)(ti - ei));
+    }
   }
 }
 
@@ -878,10 +899,10 @@ __global__ __launch_bounds__(REG_TUBES) void fft_c2r_reg_kernel(const float2* __
   }
 }
 
-template <int N>
+template <int N, bool SPLIT = false>
 hipError_t reg_r2c(const void* X, void* Xb, int64_t ntubes, hipStream_t s) {
   const int64_t nblk = (ntubes + REG_TUBES - 1) / REG_TUBES;
-  hipLaunchKernelGGL((fft_r2c_reg_kernel<N>), dim3((unsigned)nblk), dim3(REG_TUBES), 0, s, (const float*)X,
+  hipLaunchKernelGGL((fft_r2c_reg_kernel<N, SPLIT>), dim3((unsigned)nblk), dim3(REG_TUBES), 0, s, (const float*)X,
                      (float2*)Xb, ntubes);
   return hipGetLastError();
 }
@@ -904,6 +925,16 @@ hipError_t fft_r2c_reg(const void* X, void* Xb, int64_t ntubes, int n3, hipStrea
     case 16: return reg_r2c<16>(X, Xb, ntubes, s);
     case 32: return reg_r2c<32>(X, Xb, ntubes, s);
     case 64: return reg_r2c<64>(X, Xb, ntubes, s);
+    default: return hipErrorNotSupported;
+  }
+}
+hipError_t fft_r2c_split(const void* X, void* Xb, int64_t ntubes, int n3, hipStream_t s) {
+  if (ntubes <= 0) return hipSuccess;
+  switch (n3) {
+    case 8: return reg_r2c<8, true>(X, Xb, ntubes, s);
+    case 16: return reg_r2c<16, true>(X, Xb, ntubes, s);
+    case 32: return reg_r2c<32, true>(X, Xb, ntubes, s);
+    case 64: return reg_r2c<64, true>(X, Xb, ntubes, s);
     default: return hipErrorNotSupported;
   }
 }

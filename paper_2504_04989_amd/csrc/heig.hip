@@ -56,6 +56,7 @@ struct HeigView {
   double* e;
   cx<double>* ypg;  // 2 x TRI_PMAX x mp partial products of the slice's workgroups
   unsigned* sync;   // barrier counter and abort flag of the slice's workgroups
+  double* fscale;   // partial sums of ||G||_F^2 (PREP_WG of them): the fixed-point scale of the symv sums
 };
 __device__ __forceinline__ HeigView heig_view(unsigned char* scratch, size_t per_slice, int f, int m) {
   HeigView v;
@@ -68,6 +69,7 @@ __device__ __forceinline__ HeigView heig_view(unsigned char* scratch, size_t per
   v.ypg = reinterpret_cast<cx<double>*>(base + off);
   const size_t mp = (size_t)(m + 31) / 32 * 32;
   v.sync = reinterpret_cast<unsigned*>(base + off + (size_t)2 * TRI_PMAX * mp * 16);
+  v.fscale = reinterpret_cast<double*>(v.sync + 2);
   return v;
 }
 
@@ -441,9 +443,13 @@ __global__ __launch_bounds__(TRI_NT) void heig_tridiag_kernel(const cx<double>* 
 // finished with three lane exchanges each and added into y in LDS.  The
 // panel's V and W stay in LDS.  The trailing matrix is read about once per
 // step at half size, against a read and a write of the full matrix per step in
-// the unblocked form.  The LDS additions into y from different waves land in
-// an order that depends on timing, so results can differ between runs in the
-// last bits.
+// the unblocked form.  The waves' additions into y land in an order that
+// depends on timing, so they are made in 64-bit fixed point (integer addition
+// is associative): a contribution x is added as rint(x 2^62 / S) with S a power
+// of two >= m ||G||_F.  Every partial sum of a row of the trailing matrix times
+// v is below S in modulus (|a_rc| <= ||G||_2 <= ||G||_F, |v_c| <= 1), and
+// the rounding, below 2^-61 m ||G||_F per contribution, stays under the FP64
+// error of the product; the results are bitwise reproducible.
 // ---------------------------------------------------------------------------
 constexpr int T2_NT = 512;
 constexpr int T2_W = T2_NT / 64;
@@ -630,12 +636,59 @@ __device__ __forceinline__ void group_sync(unsigned* ctr, unsigned& gen, int P, 
   }
 }
 
-__global__ void heig_sync_zero_kernel(unsigned char* scratch, size_t per_slice, int m, int batch) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= batch) return;
-  unsigned* c = heig_view(scratch, per_slice, f, m).sync;
-  c[0] = 0;
-  c[1] = 0;
+// Per slice, PREP_WG workgroups (blockIdx.y): the barrier counters cleared and
+// the partial sums of ||G||_F^2 over the rows r = y mod PREP_WG of the summed
+// partials (their upper triangle counted twice when only it is valid); the
+// tridiagonalisation adds the PREP_WG partials in order and takes the power of
+// two S >= m ||G||_F as the fixed-point scale of its symv sums.
+constexpr int PREP_WG = 8;
+__global__ __launch_bounds__(256) void heig_prep_kernel(const cx<double>* __restrict__ Gpart, int nsum,
+                                                        int64_t part_stride, int m, int upper_only,
+                                                        unsigned char* scratch, size_t per_slice) {
+  __shared__ double red[4];
+  const int f = blockIdx.x, y = blockIdx.y;
+  const HeigView hv = heig_view(scratch, per_slice, f, m);
+  const cx<double>* G = Gpart + (int64_t)f * m * m;
+  double acc = 0.0;
+  // four rows per pass keep several loads of each thread in flight
+  for (int r0 = y; r0 < m; r0 += 4 * PREP_WG) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u * PREP_WG;
+      if (r >= m) continue;
+      for (int c = (upper_only ? r : 0) + (int)threadIdx.x; c < m; c += 256) {
+        const int64_t t = (int64_t)r * m + c;
+        cx<double> g{0, 0};
+        for (int s = 0; s < nsum; ++s) {
+          const cx<double> x = G[s * part_stride + t];
+          g.re += x.re;
+          g.im += x.im;
+        }
+        acc += (upper_only && c != r ? 2.0 : 1.0) * (g.re * g.re + g.im * g.im);
+      }
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    hv.fscale[y] = red[0] + red[1] + red[2] + red[3];
+    if (y == 0) {
+      hv.sync[0] = 0;
+      hv.sync[1] = 0;
+    }
+  }
+}
+
+// S = 2^e >= m ||G||_F from the prep kernel's partial sums (fixed order).
+__device__ __forceinline__ double tri_fix_scale(const HeigView& hv, int m) {
+  double fro2 = 0.0;
+  for (int y = 0; y < PREP_WG; ++y) fro2 += hv.fscale[y];
+  const double bound = (double)m * sqrt(fro2);
+  if (!(bound > 0.0) || !isfinite(bound)) return 1.0;
+  int e = 0;
+  (void)frexp(bound, &e);  // bound < 2^e
+  return ldexp(1.0, e);
 }
 
 // Lighter barrier for data exchanged only through device-coherent accesses
@@ -689,6 +742,10 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
   cx<double>* A = hv.A;
   unsigned* ctr = hv.sync;
   unsigned gen = 0;
+  // fixed-point scale factors of the symv sums (powers of two: exact)
+  const double fsc = tri_fix_scale(hv, m);
+  const double to_fix = ldexp(1.0, 62) / fsc, from_fix = fsc * ldexp(1.0, -62);
+  unsigned long long* yq = reinterpret_cast<unsigned long long*>(y);
   tri_load_lower(Gpart + (int64_t)f * m * m, nsum, part_stride, m, upper_only, A, pg, P);
   for (int r = tid; r < (2 * NB + 3) * MP; r += T2_NT) vcur[r] = cx<double>{0, 0};
   const int la = lane >> 3, lb = lane & 7;
@@ -812,15 +869,16 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
             symv_block<true>(a, vcur, r0, c0, m, i + 1, yR, yC);
           const cx<double> sr = reduce4<4, 2, 1>(yR, lane);
           const cx<double> sc = reduce4<32, 16, 8>(yC, lane);
+          auto fix = [&](double x) { return (unsigned long long)(long long)rint(x * to_fix); };
           if (!(lane & 1)) {
             const int q = ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
-            atomicAdd(&y[r0 + q].re, sr.re);
-            atomicAdd(&y[r0 + q].im, sr.im);
+            atomicAdd(&yq[2 * (r0 + q)], fix(sr.re));
+            atomicAdd(&yq[2 * (r0 + q) + 1], fix(sr.im));
           }
           if (!(la & 1)) {
             const int p = ((la >> 2) & 1) * 2 + ((la >> 1) & 1);
-            atomicAdd(&y[c0 + 8 * p].re, sc.re);
-            atomicAdd(&y[c0 + 8 * p].im, sc.im);
+            atomicAdd(&yq[2 * (c0 + 8 * p)], fix(sc.re));
+            atomicAdd(&yq[2 * (c0 + 8 * p) + 1], fix(sc.im));
           }
         };
         // two tile buffers (the first requested at the start of the step);
@@ -835,6 +893,12 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
           load_block(A, m, r0, c0, a0);
           process(a1, t + wstep);
         }
+      }
+      __syncthreads();
+      // the fixed-point sums back to FP64 (each thread converts its own rows)
+      for (int r = i + 1 + tid; r < m; r += T2_NT) {
+        const long long qr = (long long)yq[2 * r], qi = (long long)yq[2 * r + 1];
+        y[r] = cx<double>{(double)qr * from_fix, (double)qi * from_fix};
       }
       __syncthreads();
       if (P > 1) {
@@ -1485,7 +1549,8 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
     const int nb = sm2(8) <= lds_total ? 8 : 4;
     const size_t sm = sm2(nb);
     const void* fn = nb == 8 ? (const void*)heig_tri2_kernel<8> : (const void*)heig_tri2_kernel<4>;
-    hipLaunchKernelGGL(heig_sync_zero_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, sc, per, m, batch);
+    hipLaunchKernelGGL(heig_prep_kernel, dim3(batch, PREP_WG), dim3(256), 0, s, (const cx<double>*)Gpart, nsum,
+                       part_stride, m, upper_only ? 1 : 0, sc, per);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // several co-resident workgroups per slice for large m when the slices
     // leave CUs idle (cooperative launch guarantees co-residency)

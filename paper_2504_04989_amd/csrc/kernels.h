@@ -35,7 +35,12 @@ hipError_t zgemm(const GemmDesc& d, hipStream_t s);
 // FP32 MFMA, BF16 (one product), BF16x3 (hi/lo split, three products), FP32
 // accumulation.  nsplit > 1 splits K; part must then hold
 // nsplit * batch * M * N complex FP32 values (reduced in a fixed order).
-enum KMode { KM_F32 = 0, KM_BF16 = 1, KM_BF16X3 = 2 };
+// KM_BF16X3_SPLIT: BF16x3 with the big operand already stored as (hi, lo)
+// bf16 pairs (fft_r2c_split's output form, 8 bytes per complex element); the
+// thin operand is split once per call into xsplit (batch x K x N pairs)
+// instead of in every workgroup.  Same products in the same order as
+// KM_BF16X3: the results are bitwise equal.
+enum KMode { KM_F32 = 0, KM_BF16 = 1, KM_BF16X3 = 2, KM_BF16X3_SPLIT = 3 };
 struct KGemmDesc {
   const void* A; int64_t lda, strideA; int rows, cols; bool herm;
   const void* X; int64_t ldx, strideX;
@@ -43,8 +48,11 @@ struct KGemmDesc {
   int N, batch, mode, nsplit;
   void* part;
   size_t part_bytes;  // size of part; a tail split is used only when it fits
+  void* xsplit;       // KM_BF16X3_SPLIT: batch * K * N * 8 bytes for the split thin operand
 };
 hipError_t kgemm(const KGemmDesc& d, hipStream_t s);
+// n complex FP32 values -> n (hi, lo) bf16 pairs (the KM_BF16X3_SPLIT form).
+hipError_t split_bf16x3(const void* in, void* out, int64_t n, hipStream_t s);
 // Bytes of d.part that kgemm uses: nsplit > 1 partials, or (nsplit == 1) the
 // partials of the split remainder tiles (0 when there is no tail split).
 size_t kgemm_part_bytes(int M, int K, int N, int batch, int nsplit);
@@ -82,6 +90,12 @@ hipError_t fft_r2c(const void* X, void* Xb, int64_t ntubes, int n3, DType t, hip
 // Inverse: Xb (F x ntubes, slice stride `slice_stride` elements) -> X
 // (ntubes x n3 real).  Imaginary parts of DC / Nyquist are ignored.
 hipError_t fft_c2r(const void* Xb, int64_t slice_stride, void* X, int64_t ntubes, int n3, DType t, hipStream_t s);
+// fft_r2c for FP32 data written as (hi, lo) bf16 pairs per complex value
+// (hi = bf16(z), lo = bf16(z - hi), packed re | im << 16 each): the big
+// operand of KM_BF16X3_SPLIT.  Only for the register-resident lengths
+// (fft_reg_supported); hipErrorNotSupported otherwise.
+bool fft_reg_supported(int n3, DType t);
+hipError_t fft_r2c_split(const void* X, void* Xb, int64_t ntubes, int n3, hipStream_t s);
 
 // Per-slice b x b Hermitian Gram (sum of nsum FP64 partials, partial s at
 // Gpart + s * part_stride complex elements, slice f at + f * b * b) -> inverse

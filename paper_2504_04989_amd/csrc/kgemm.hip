@@ -70,12 +70,18 @@ template <int MODE>
 struct Lds {
   static constexpr int WORDS = MODE == KM_F32 ? 2 * KSTEP : KSTEP;  // 32-bit words per row
   static constexpr int STRIDE = WORDS + 4;
-  static constexpr int PLANES = MODE == KM_BF16X3 ? 2 : 1;
+  static constexpr int PLANES = (MODE == KM_BF16X3 || MODE == KM_BF16X3_SPLIT) ? 2 : 1;
 };
+
+// Pack of two bf16 bit patterns: lo in bits 0..15, hi in 16..31.
+__device__ __forceinline__ uint32_t swap16(uint32_t x) { return (x >> 16) | (x << 16); }
 
 template <int MODE, bool HN, int TT, int TB, bool AVEC, bool FULL>
 __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   typedef Lds<MODE> L;
+  // three-product BF16; PRE: both operands arrive as (hi, lo) bf16 pairs
+  constexpr bool X3 = MODE == KM_BF16X3 || MODE == KM_BF16X3_SPLIT;
+  constexpr bool PRE = MODE == KM_BF16X3_SPLIT;
   constexpr int ROWS = TT * 16;
   constexpr int PLANE = ROWS * L::STRIDE;
   constexpr int BUF = PLANE * L::PLANES;
@@ -241,6 +247,14 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
       if (MODE == KM_F32) {
         *reinterpret_cast<float2*>(row0 + 2 * kk) = make_float2(xr, HN ? xi : -xi);
         *reinterpret_cast<float2*>(row1 + 2 * kk) = make_float2(xi, HN ? -xr : xr);
+      } else if (PRE) {
+        // x.x = (re_hi | im_hi << 16), x.y = (re_lo | im_lo << 16): the rows
+        // are these words with the halves swapped and / or a sign flipped
+        const uint32_t h = __float_as_uint(xr), l = __float_as_uint(xi);
+        row0[kk] = HN ? h : (h ^ 0x80000000u);
+        row1[kk] = HN ? (swap16(h) ^ 0x80000000u) : swap16(h);
+        row0[PLANE + kk] = HN ? l : (l ^ 0x80000000u);
+        row1[PLANE + kk] = HN ? (swap16(l) ^ 0x80000000u) : swap16(l);
       } else {
         // each value is rounded once; negation flips the bf16 sign bit
         const __bf16 hr = (__bf16)xr, hi = (__bf16)xi;
@@ -282,11 +296,21 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
       bf16x8 bh[TB], bl[TB];
 #pragma unroll
       for (int u = 0; u < TB; ++u) {
+        if (PRE) {
+          // complex c of the lane's four: word 2c = hi pair, word 2c + 1 = lo pair
+          const uint4 wh = make_uint4(__float_as_uint(v[u][0]), __float_as_uint(v[u][2]), __float_as_uint(v[u][4]),
+                                      __float_as_uint(v[u][6]));
+          const uint4 wl = make_uint4(__float_as_uint(v[u][1]), __float_as_uint(v[u][3]), __float_as_uint(v[u][5]),
+                                      __float_as_uint(v[u][7]));
+          bh[u] = __builtin_bit_cast(bf16x8, wh);
+          bl[u] = __builtin_bit_cast(bf16x8, wl);
+        } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const __bf16 h = (__bf16)v[u][j];
-          bh[u][j] = h;
-          if (MODE == KM_BF16X3) bl[u][j] = (__bf16)(v[u][j] - (float)h);
+          for (int j = 0; j < 8; ++j) {
+            const __bf16 h = (__bf16)v[u][j];
+            bh[u][j] = h;
+            if (X3) bl[u][j] = (__bf16)(v[u][j] - (float)h);
+          }
         }
       }
 #pragma unroll
@@ -294,7 +318,7 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
         if (i < tt) {
           const uint32_t* rowp = buf + (16 * i + r16) * L::STRIDE + 4 * q4;
           const bf16x8 th = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(rowp));
-          if (MODE == KM_BF16X3) {
+          if (X3) {
             const bf16x8 tl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(rowp + PLANE));
 #pragma unroll
             for (int u = 0; u < TB; ++u) {
@@ -382,6 +406,25 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
         if (n + 1 < a.N) *reinterpret_cast<float2*>(p + 2) = make_float2(acc[i][u][2], acc[i][u][3]);
       }
     }
+  }
+}
+
+// Thin operand of KM_BF16X3_SPLIT: Xs[f][k][n] = (hi, lo) bf16 pairs of
+// X[f][k][n] (complex FP32, row stride ldx, slice stride strideX, in floats),
+// dense K x N per slice.
+__global__ void kgemm_split_thin_kernel(const float* __restrict__ X, int64_t ldx, int64_t strideX, int K, int N,
+                                        int batch, uint2* __restrict__ Xs) {
+  const int64_t per = (int64_t)K * N, total = per * batch;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t f = e / per, rem = e - f * per;
+    const int k = (int)(rem / N), n = (int)(rem - (int64_t)k * N);
+    const float2 x = *reinterpret_cast<const float2*>(X + f * strideX + (int64_t)k * ldx + 2 * n);
+    const __bf16 hr = (__bf16)x.x, hi = (__bf16)x.y;
+    const __bf16 lr = (__bf16)(x.x - (float)hr), li = (__bf16)(x.y - (float)hi);
+    uint2 o;
+    o.x = (uint32_t)__builtin_bit_cast(unsigned short, hr) | ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+    o.y = (uint32_t)__builtin_bit_cast(unsigned short, lr) | ((uint32_t)__builtin_bit_cast(unsigned short, li) << 16);
+    Xs[e] = o;
   }
 }
 
@@ -530,6 +573,15 @@ TailPlan kgemm_tail_plan(int M, int K, int N, int batch) {
 
 }  // namespace
 
+hipError_t split_bf16x3(const void* in, void* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(kgemm_split_thin_kernel, dim3(blocks), dim3(256), 0, s, static_cast<const float*>(in), (int64_t)2,
+                     2 * n, (int)n, 1, 1, static_cast<uint2*>(out));
+  return hipGetLastError();
+}
+
 size_t kgemm_part_bytes(int M, int K, int N, int batch, int nsplit) {
   if (nsplit > 1) return (size_t)nsplit * batch * M * N * 8;
   return kgemm_tail_plan(M, K, N, batch).bytes;
@@ -606,6 +658,19 @@ hipError_t kgemm(const KGemmDesc& d, hipStream_t s) {
     case KM_BF16X3:
       e = d.herm ? launch_mode<KM_BF16X3, true>(a, TT, s) : launch_mode<KM_BF16X3, false>(a, TT, s);
       break;
+    case KM_BF16X3_SPLIT: {
+      if (!d.xsplit) return hipErrorInvalidValue;
+      const int64_t n = (int64_t)K * d.N * d.batch;
+      const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+      hipLaunchKernelGGL(kgemm_split_thin_kernel, dim3(blocks), dim3(256), 0, s, a.X, a.ldx, a.strideX, K, d.N,
+                         d.batch, static_cast<uint2*>(d.xsplit));
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      a.X = static_cast<const float*>(d.xsplit);
+      a.ldx = 2 * (int64_t)d.N;
+      a.strideX = 2 * (int64_t)K * d.N;
+      e = d.herm ? launch_mode<KM_BF16X3_SPLIT, true>(a, TT, s) : launch_mode<KM_BF16X3_SPLIT, false>(a, TT, s);
+      break;
+    }
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;

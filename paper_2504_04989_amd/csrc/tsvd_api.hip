@@ -52,6 +52,8 @@ struct Plan {
   bool tensor_op;               // T-QR / pseudoinverse: QR of A_f itself, r = m = min(n1, n2) in
                                 // q + 1 column panels of width b <= 128
   int kmode;                    // Krylov-product arithmetic (KM_*) when dt == DT_F32
+  bool asplit;                  // BF16x3 with A_f transformed straight into (hi, lo) bf16 pairs
+                                // (KM_BF16X3_SPLIT; A_f is read only by the Krylov products)
   int ks_ax, ks_ahy;            // K splits of the Krylov products A X and A^H Y
   size_t kpart_bytes;           // their partials (K splits or tail splits)
   // workspace offsets (bytes)
@@ -59,6 +61,7 @@ struct Plan {
   size_t o_cbuf, o_xbuf, o_uo, o_so, o_vo;  // completion: C^(n), X^(n) and the factors of L
   size_t o_lam1, o_w1, o_w1m, o_p, o_t1, o_lam2, o_w2, o_rk, o_split;  // FP64 small SVD, second pass
   size_t o_omsp;  // the spatial test tensor drawn from the seed (n2 x b x n3, storage type)
+  size_t o_xsplit;  // KM_BF16X3_SPLIT: the thin operand as (hi, lo) bf16 pairs
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
       o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, o_kpack,
       total;
@@ -77,6 +80,14 @@ int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
   return (int)ns;
 }
 
+// n1 * n2 * n3 < 2^31 for 1 <= n3 <= 4096, without overflowing on the way.
+bool small_volume(int64_t n1, int64_t n2, int64_t n3) {
+  const int64_t lim = (int64_t)1 << 31;
+  if (n1 >= lim || n2 >= lim) return false;
+  const int64_t a = n1 * n2;  // < 2^62
+  return a < lim && a * n3 < lim;
+}
+
 // Alg. mp: per Fourier slice the Gram on the short side (A_f^H A_f when
 // n1 >= n2, else A_f A_f^H; r = min(n1, n2)), all its eigenpairs, the
 // sigma^-2-weighted projector Wg and the product with A_f^H.
@@ -86,8 +97,7 @@ int make_plan_tpinv(int64_t n1, int64_t n2, int64_t n3, int prec, Plan* p) {
   const int64_t r = std::min(n1, n2), K = std::max(n1, n2);
   if (r > 1024) return fail(TSVD_EINVAL, "min(n1, n2) must be <= 1024");
   if (n3 > 4096) return fail(TSVD_EINVAL, "n3 must be <= 4096");
-  if (n1 * n2 * n3 >= (int64_t)1 << 31 || n1 * n2 >= (int64_t)1 << 31)
-    return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
+  if (!small_volume(n1, n2, n3)) return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
   *p = Plan{};
   p->n1 = n1;
   p->n2 = n2;
@@ -160,7 +170,8 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
     k = 1;
   }
   if (power && q > 4096) return fail(TSVD_EINVAL, "q must be <= 4096");
-  const int64_t m = power ? b : b * (q + 1);
+  // (b and q bounded before the product: m only matters up to 1024)
+  const int64_t m = power ? b : ((b > 1024 || q > 1023) ? (int64_t)1025 : b * (q + 1));
   if (power) {
     if (m > std::min(n1, n2)) return fail(TSVD_EINVAL, "need b <= min(n1, n2)");
     if (m > 1024) return fail(TSVD_EINVAL, "b must be <= 1024");
@@ -169,8 +180,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
     if (m > 1024) return fail(TSVD_EINVAL, "m = b (q + 1) must be <= 1024");
   }
   if (n3 > 4096) return fail(TSVD_EINVAL, "n3 must be <= 4096");
-  if (n1 * n2 * n3 >= (int64_t)1 << 31 || n1 * n2 >= (int64_t)1 << 31)
-    return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
+  if (!small_volume(n1, n2, n3)) return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
   if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32 && prec != TSVD_PREC_BF16 && prec != TSVD_PREC_BF16X3)
     return fail(TSVD_EINVAL, "unknown precision mode");
   if (op < TSVD_OP_RBK || op > TSVD_OP_TPINV) return fail(TSVD_EINVAL, "unsupported operation");
@@ -195,6 +205,10 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   p->nsplit_t = split_for(n2, tb * tb, F, &p->kchunk_t);
   p->nsplit_r = split_for(n1, ((m + 63) / 64) * ((n2 + 63) / 64), F, &p->kchunk_r);
   p->kmode = prec == TSVD_PREC_BF16 ? KM_BF16 : (prec == TSVD_PREC_BF16X3 ? KM_BF16X3 : KM_F32);
+  // the split form of A_f where nothing but the Krylov products reads it (not
+  // the projection and its adjoint) and the transform has the split epilogue
+  p->asplit = p->kmode == KM_BF16X3 && p->dt == DT_F32 && fft_reg_supported((int)n3, DT_F32) &&
+              (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || op == TSVD_OP_POWER || op == TSVD_OP_POWER_APPROX);
   int kc_unused;
   if (p->kmode != KM_BF16) {
     p->ks_ax = p->dt == DT_F32 ? kgemm_split((int)n1, (int)n2, (int)b, (int)F, &kc_unused) : 1;
@@ -213,6 +227,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   const size_t cs = p->cs;
   p->o_info = take(256);
   p->o_omsp = take(tensor_op ? 0 : (size_t)n2 * b * n3 * (p->dt == DT_F64 ? 8 : 4));
+  p->o_xsplit = take(p->asplit ? (size_t)F * std::max(n1, n2) * b * 8 : 0);
   p->o_abar = take((size_t)F * n1 * n2 * cs);
   p->o_obar = take(tensor_op ? 0 : (size_t)F * n2 * b * cs);
   p->o_q = take((size_t)F * n1 * m * cs);
@@ -543,7 +558,20 @@ int cholqr_finish(const Ctx& c, int64_t rows, void* dst, int64_t ldd) {
     // CholeskyQR2.
     if ((r = cholqr_pass(c, S1, p.b, S0, p.b, true, rows))) return r;
     if ((r = cholqr_pass(c, S0, p.b, S1, p.b, true, rows))) return r;
+    if ((r = cholqr_pass(c, S1, p.b, S0, p.b, false, rows))) return r;
+    return cholqr_pass(c, S0, p.b, dst, ldd, false, rows);
   }
+  // FP32 storage with FP64 Grams.  The shifted pass maps sigma_j(W) to
+  // sigma_j / sqrt(sigma_j^2 + s), so kappa(X1) <= sqrt(alpha) kappa(W) with
+  // alpha = s / ||W||^2 <= 11 (rows b + b (b + 1)) 2^-53 b, and an FP32 block
+  // has kappa(W) below about 1e8 (its rounding noise).  One unshifted pass
+  // then leaves an FP64 orthogonality error of about 2^-53 kappa(X1)^2; when
+  // that bound stays within 16 FP32 roundings (2^-20), below the FP32 rounding
+  // of the block itself in the 2-norm, a second unshifted pass cannot improve
+  // the stored result and is left out (rows * b up to about 6e6 at b = 110).
+  const double u64 = 0x1p-53;
+  const double alpha_max = 11.0 * ((double)rows * p.b + (double)p.b * (p.b + 1)) * u64 * (double)p.b;
+  if (alpha_max * u64 * 1e16 <= 0x1p-20) return cholqr_pass(c, S1, p.b, dst, ldd, false, rows);
   if ((r = cholqr_pass(c, S1, p.b, S0, p.b, false, rows))) return r;
   return cholqr_pass(c, S0, p.b, dst, ldd, false, rows);
 }
@@ -588,7 +616,8 @@ int big_AX(const Ctx& c, const void* X, int64_t ldx, int64_t strideX, void* Out,
     k.strideC = strideO;
     k.N = N;
     k.batch = (int)p.F;
-    k.mode = p.kmode;
+    k.mode = p.asplit ? KM_BF16X3_SPLIT : p.kmode;
+    k.xsplit = p.asplit ? c.at(p.o_xsplit) : nullptr;
     k.nsplit = N == p.b ? p.ks_ax : 1;
     k.part = c.at(p.o_kpart);
     k.part_bytes = p.kpart_bytes;
@@ -644,7 +673,8 @@ int big_AhY(const Ctx& c, const void* Y, int64_t ldy, int64_t strideY, void* Out
     k.strideC = strideO;
     k.N = N;
     k.batch = (int)p.F;
-    k.mode = p.kmode;
+    k.mode = p.asplit ? KM_BF16X3_SPLIT : p.kmode;
+    k.xsplit = p.asplit ? c.at(p.o_xsplit) : nullptr;
     k.nsplit = N == p.b ? p.ks_ahy : 1;
     k.part = c.at(p.o_kpart);
     k.part_bytes = p.kpart_bytes;
@@ -699,7 +729,10 @@ int krylov(const Ctx& c, const void* A, const void* Omega, bool keep_raw = false
   }
   {
     Timed tm_(K_FFT_A, c.s);
-    HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, dt, c.s));
+    if (p.asplit)
+      HIPCHK(fft_r2c_split(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, c.s));
+    else
+      HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, dt, c.s));
   }
   {
     Timed tm_(K_FFT_OMEGA, c.s);
@@ -749,7 +782,10 @@ int krylov_literal(const Ctx& c, const void* A, const void* Omega) {
   }
   {
     Timed tm_(K_FFT_A, c.s);
-    HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, p.dt, c.s));
+    if (p.asplit)
+      HIPCHK(fft_r2c_split(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, c.s));
+    else
+      HIPCHK(fft_r2c(A, c.at(p.o_abar), p.n1 * p.n2, (int)p.n3, p.dt, c.s));
   }
   {
     Timed tm_(K_FFT_OMEGA, c.s);
@@ -1417,6 +1453,9 @@ int tsvd_rbk_noalloc(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t 
              "tsvd_rbk with a workspace", p.total, kStaticScratchBytes);
     return fail(TSVD_ENOMEM, msg);
   }
+  // pointer checks before the device is touched
+  for (const void* ptr : {A, (const void*)U, (const void*)S, (const void*)V})
+    if (!ptr || !aligned(ptr, 16)) return fail(TSVD_EINVAL, "null or misaligned (16 B) tensor pointer");
   void* ws = nullptr;
   if ((r = static_scratch(&ws))) return r;
   return svd_call(false, TSVD_OP_RBK, A, nullptr, seed, n1, n2, n3, k, b, q, prec, U, S, V, nullptr, ws,
@@ -1506,7 +1545,7 @@ int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void* 
 // absolute error of about (n1 + n2) u lambda_0 (u = 2^-53), so singular values
 // below sqrt((n1 + n2) u) sigma_0 cannot be told from zero; the factor 4 keeps
 // the kept values 16x above that level.
-double tpinv_floor(int64_t n1, int64_t n2) { return 4.0 * std::sqrt((double)(n1 + n2) * 0x1p-53); }
+double tpinv_floor(int64_t n1, int64_t n2) { return 4.0 * std::sqrt(((double)n1 + (double)n2) * 0x1p-53); }
 
 double tsvd_tpinv_default_rtol(int64_t n1, int64_t n2, int prec) {
   if (n1 < 1 || n2 < 1 || (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32)) return -1.0;
@@ -1690,21 +1729,22 @@ int tsvd_diag_fft_c2r(const void* Xb, void* X, int64_t ntubes, int64_t n3, int d
 
 size_t tsvd_diag_kgemm_ws_bytes(int herm, int64_t rows, int64_t cols, int64_t N, int64_t batch, int mode,
                                 int nsplit) {
-  if (rows < 1 || cols < 1 || N < 1 || batch < 1 || mode < KM_F32 || mode > KM_BF16X3 || nsplit < 1 ||
-      rows * cols >= ((int64_t)1 << 31) || N >= (1 << 20) || batch > 65535)
+  if (rows < 1 || cols < 1 || N < 1 || batch < 1 || mode < KM_F32 || mode > KM_BF16X3_SPLIT || nsplit < 1 ||
+      !small_volume(rows, cols, 1) || N >= (1 << 20) || batch > 65535)
     return 0;
   const int64_t M = herm ? cols : rows, K = herm ? rows : cols;
   size_t bytes = nsplit > 1 ? align256((size_t)nsplit * batch * M * N * 8) : 0;
   if (mode == KM_BF16) bytes += align256(kgemm_bf16_pack_bytes(mode, (int)K, (int)N, (int)batch));
   else if (nsplit == 1) bytes += align256(kgemm_part_bytes((int)M, (int)K, (int)N, (int)batch, 1));
+  if (mode == KM_BF16X3_SPLIT) bytes += align256((size_t)batch * K * N * 8);
   return bytes;
 }
 
 int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t rows, int64_t cols, int64_t N,
                     int64_t batch, int mode, int nsplit, void* ws, size_t ws_bytes, void* stream) {
   const size_t need = tsvd_diag_kgemm_ws_bytes(herm, rows, cols, N, batch, mode, nsplit);
-  if (!A || !X || !C || rows < 1 || cols < 1 || N < 1 || batch < 1 || mode < KM_F32 || mode > KM_BF16X3 ||
-      nsplit < 1 || nsplit > 64 || rows * cols >= ((int64_t)1 << 31) || N >= (1 << 20) || batch > 65535)
+  if (!A || !X || !C || rows < 1 || cols < 1 || N < 1 || batch < 1 || mode < KM_F32 || mode > KM_BF16X3_SPLIT ||
+      nsplit < 1 || nsplit > 64 || !small_volume(rows, cols, 1) || N >= (1 << 20) || batch > 65535)
     return fail(TSVD_EINVAL, "bad arguments");
   if (need > 0 && (!ws || ws_bytes < need || !aligned(ws, 256))) return fail(TSVD_ENOMEM, "workspace too small");
   const int64_t M = herm ? cols : rows, K = herm ? rows : cols;
@@ -1728,15 +1768,28 @@ int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t row
   unsigned char* w = static_cast<unsigned char*>(ws);
   d.part = nsplit > 1 ? w : nullptr;
   d.part_bytes = nsplit > 1 ? (size_t)nsplit * batch * M * N * 8 : 0;
-  if (nsplit == 1 && mode != KM_BF16 && need > 0) {
+  size_t xs_bytes = 0;
+  if (mode == KM_BF16X3_SPLIT) {
+    // the split thin operand at the end of the workspace
+    xs_bytes = align256((size_t)batch * K * N * 8);
+    d.xsplit = w + need - xs_bytes;
+  }
+  if (nsplit == 1 && mode != KM_BF16 && need - xs_bytes > 0) {
     d.part = w;
-    d.part_bytes = need;
+    d.part_bytes = need - xs_bytes;
   }
   void* pack = w + (nsplit > 1 ? align256((size_t)nsplit * batch * M * N * 8) : 0);
   if (mode == KM_BF16)
     HIPCHK(kgemm_bf16(d, pack, (hipStream_t)stream));
   else
     HIPCHK(kgemm(d, (hipStream_t)stream));
+  return TSVD_OK;
+}
+
+int tsvd_diag_split_bf16x3(const void* in, void* out, int64_t n, void* stream) {
+  if (!in || !out || n < 1 || n >= ((int64_t)1 << 31) || !aligned(in, 8) || !aligned(out, 8))
+    return fail(TSVD_EINVAL, "bad arguments");
+  HIPCHK(split_bf16x3(in, out, n, (hipStream_t)stream));
   return TSVD_OK;
 }
 

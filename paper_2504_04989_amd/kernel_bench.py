@@ -2,7 +2,7 @@
 through the kernel entry points of the C ABI (include/tsvd_rbk_diag.h), on
 data drawn on the device (no host generation, so a profiler pass is short).
 
-    python -m paper_2504_04989_amd.kernel_bench krylov [--prec f32|bf16|bf16x3] [--n 4096] [--f 33] [--N 110]
+    python -m paper_2504_04989_amd.kernel_bench krylov [--prec f32|bf16|bf16x3|bf16x3s] [--n 4096] [--f 33] [--N 110]
     python -m paper_2504_04989_amd.kernel_bench fft [--n 4096] [--n3 64]
     python -m paper_2504_04989_amd.kernel_bench orth [--n 4096] [--m 440] [--n3 64]
 
@@ -11,6 +11,9 @@ over f slices of an n x n complex FP32 A_f and N thin columns (the
 4096 x 4096 x 64 workload: n = 4096, 33 slices, N = b = 110), each direction
 timed over --reps launches after one warmup, with HIP events; prints the
 time per launch and the rate in algorithmic flops (8 n^2 N f per launch).
+bf16x3s: the BF16x3 form on A already split into (hi, lo) bf16 pairs, as
+the split transform writes it for the Krylov basis (the thin operand is split
+once per launch inside the timed call).
 fft: the mode-3 real-to-half-spectrum DFT of n^2 real tubes of length n3
 (FP32), timed likewise, with its algorithmic bytes (4 n^2 n3 + 8 n^2 F).
 orth: the T-QR (Alg. TQR) of an n x m x n3 FP32 tensor, m = 440 orthonormalised
@@ -46,11 +49,14 @@ def krylov(n: int, F: int, N: int, prec: str, reps: int):
     g = torch.Generator(device="cuda").manual_seed(1)
     A = torch.randn((F, n, n), dtype=torch.complex64, device="cuda", generator=g)
     X = torch.randn((F, n, N), dtype=torch.complex64, device="cuda", generator=g)
+    if prec == "bf16x3s":
+        # the big operand as written by the split transform: (hi, lo) bf16 pairs
+        A = api.diag_split_bf16x3(A)
     for herm in (False, True):
         ms = _time(lambda: api.diag_kgemm(A, X, herm=herm, mode=prec), reps)
         fl = 8.0 * n * n * N * F
-        peak = {"f32": 157.3e12, "bf16": 2500e12, "bf16x3": 2500e12}[prec]
-        ex = 3.0 if prec == "bf16x3" else 1.0
+        peak = {"f32": 157.3e12, "bf16": 2500e12, "bf16x3": 2500e12, "bf16x3s": 2500e12}[prec]
+        ex = 3.0 if prec in ("bf16x3", "bf16x3s") else 1.0
         print(json.dumps({"kernel": "krylov", "op": "A^H Y" if herm else "A X", "prec": prec, "n": n, "slices": F,
                           "N": N, "ms_per_launch": ms, "tflops_algorithmic": fl / ms / 1e9,
                           "frac_algorithmic": fl / ms / 1e-3 / peak, "frac_executed": ex * fl / ms / 1e-3 / peak,

@@ -61,6 +61,48 @@ def fp32_twin_slice(A, Om, k, b, q, f):
     return fp32_twin_slice_f(A @ w, Om @ w, k, b, q)
 
 
+def _bf16(x):
+    """Round float32 values to bfloat16 (nearest even), returned as float32."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(torch.bfloat16).to(torch.float32).numpy()
+
+
+def _split16(z):
+    """Complex64 z -> (hi, lo): hi = bf16(z), lo = bf16(z - hi) per real part."""
+    z = np.asarray(z, dtype=np.complex64)
+    hr, hi = _bf16(z.real), _bf16(z.imag)
+    lr, li = _bf16(z.real - hr), _bf16(z.imag - hi)
+    return (hr + 1j * hi).astype(np.complex64), (lr + 1j * li).astype(np.complex64)
+
+
+def _x3(X, Y):
+    """The three-product BF16 form of X @ Y: hi hi + hi lo + lo hi with
+    float32 accumulation (complex64 products of bf16-valued operands)."""
+    Xh, Xl = _split16(X)
+    Yh, Yl = _split16(Y)
+    return (Xh @ Yh) + (Xh @ Yl) + (Xl @ Yh)
+
+
+def bf16x3_twin_slice_f(Af, Of, k, b, q):
+    """fp32_twin_slice_f with every Krylov product (A Omega, A^H Q, A T and
+    Q^H A) in the three-product BF16 form of the GPU's BF16x3 mode: the floor
+    of that arithmetic (both operands held to 16 significant bits)."""
+    Af = np.asarray(Af).astype(np.complex64)
+    Of = np.asarray(Of).astype(np.complex64)
+    Ah = np.ascontiguousarray(Af.conj().T)
+    Qs = [np.linalg.qr(_x3(Af, Of))[0]]
+    for _ in range(q):
+        W = _x3(Af, _x3(Ah, Qs[-1]))
+        Qp = np.concatenate(Qs, axis=1)
+        W = W - Qp @ (Qp.conj().T @ W)
+        W = W - Qp @ (Qp.conj().T @ W)
+        Qs.append(np.linalg.qr(W)[0])
+    Q = np.concatenate(Qs, axis=1)
+    C = _x3(Ah, Q).conj().T
+    W, s, Zh = np.linalg.svd(C, full_matrices=False)
+    return ((Q @ W[:, :k]) * s[:k]) @ Zh[:k], s[:k].astype(np.float64)
+
+
 def fp32_twin_slice_f(Af, Of, k, b, q):
     """fp32_twin_slice on a slice whose DFT is already taken (Af n1 x n2,
     Of n2 x b), rounded here to complex64."""

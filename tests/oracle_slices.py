@@ -6,7 +6,9 @@ and cached on disk for the GPU tests that sample it.
 The child generates the workload (FP32-rounded, widened back to FP64, as the
 GPU paths read it), runs the FP64 oracle on the listed Fourier slices in
 parallel workers (oracle.pool) and, per slice, the plain FP32 computation of
-the same slice (tests.gpu_util.fp32_twin_slice) that measures the FP32 floor.
+the same slice (tests.gpu_util.fp32_twin_slice_f) that measures the FP32 floor,
+and the same with the Krylov products in the three-product BF16 form
+(tests.gpu_util.bf16x3_twin_slice_f), the floor of the BF16x3 mode.
 It runs in its own process because the pool forks workers, which a test
 process that has already initialised the GPU must not do."""
 import hashlib
@@ -22,9 +24,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _twin(Af, Of, k, b, q):
-    from tests.gpu_util import fp32_twin_slice_f
+    from tests.gpu_util import bf16x3_twin_slice_f, fp32_twin_slice_f
     Xt, st = fp32_twin_slice_f(Af, Of, k, b, q)
-    return {"Xt": Xt, "st": st}
+    Xt3, st3 = bf16x3_twin_slice_f(Af, Of, k, b, q)
+    return {"Xt": Xt, "st": st, "Xt3": Xt3, "st3": st3}
 
 
 def main(argv):
@@ -44,7 +47,8 @@ def main(argv):
           flush=True)
     ex = r.pop("extra")
     np.savez(out + ".tmp.npz", Uf=r["Uf"], Sf=r["Sf"], Vf=r["Vf"], s_all=r["s_all"], freqs=np.array(freqs),
-             Xt=np.stack([e["Xt"] for e in ex], axis=2), st=np.stack([e["st"] for e in ex], axis=1))
+             Xt=np.stack([e["Xt"] for e in ex], axis=2), st=np.stack([e["st"] for e in ex], axis=1),
+             Xt3=np.stack([e["Xt3"] for e in ex], axis=2), st3=np.stack([e["st3"] for e in ex], axis=1))
     os.replace(out + ".tmp.npz", out)
 
 

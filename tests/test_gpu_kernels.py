@@ -109,6 +109,42 @@ def test_kgemm_vs_float64(case, herm, mode):
     assert err <= tol, f"rel err {err:.2e}"
 
 
+@pytest.mark.parametrize("case", KG_CASES + [(33, 512, 520, 110, 1)])
+@pytest.mark.parametrize("herm", [False, True])
+def test_kgemm_presplit_bitwise_equals_bf16x3(case, herm):
+    """BF16x3 with A given as (hi, lo) bf16 pairs and the thin operand split
+    once per call gives the same products in the same order as the on-the-fly
+    split: the results agree bit for bit (ragged tiles, K splits and the tail
+    split of a 33-slice product included)."""
+    batch, rows, cols, N, ns = case
+    K = rows if herm else cols
+    _, Ad = _cplx((batch, rows, cols), 11, torch.complex64)
+    _, Xd = _cplx((batch, K, N), 12, torch.complex64)
+    As = api.diag_split_bf16x3(Ad)
+    c2 = api.diag_kgemm(Ad, Xd, herm=herm, mode="bf16x3", nsplit=ns)
+    c3 = api.diag_kgemm(As, Xd, herm=herm, mode="bf16x3s", nsplit=ns)
+    assert torch.equal(c2, c3)
+
+
+def test_split_bf16x3_pairs():
+    """The (hi, lo) pair form against its definition: hi = bf16(z), lo =
+    bf16(z - hi) per part, round to nearest even (torch's bfloat16 cast)."""
+    g = torch.Generator().manual_seed(13)
+    Z = torch.complex(torch.randn(4097, generator=g), torch.randn(4097, generator=g))
+    Z[0] = complex(0.0, -0.0)
+    Z[1] = complex(3.0e38, -1.0e-30)
+    P = api.diag_split_bf16x3(Z.cuda()).cpu()
+    w = torch.view_as_real(P).contiguous().view(torch.int32).view(-1, 2)
+    zr = torch.view_as_real(Z)
+    hi = zr.to(torch.bfloat16)
+    lo = (zr - hi.to(torch.float32)).to(torch.bfloat16)
+    hb = hi.view(torch.int16).to(torch.int32) & 0xFFFF
+    lb = lo.view(torch.int16).to(torch.int32) & 0xFFFF
+    want_h = hb[:, 0] | (hb[:, 1] << 16)
+    want_l = lb[:, 0] | (lb[:, 1] << 16)
+    assert torch.equal(w[:, 0], want_h) and torch.equal(w[:, 1], want_l)
+
+
 def test_kgemm_split_is_deterministic_and_matches_unsplit():
     A, Ad = _cplx((2, 200, 700), 3, torch.complex64)
     X, Xd = _cplx((2, 700, 40), 4, torch.complex64)

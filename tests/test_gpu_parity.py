@@ -126,6 +126,24 @@ def test_deterministic_bitwise():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec,n3", [("f32", 16), ("bf16x3", 16), ("f64", 8)])
+def test_deterministic_bitwise_m440(prec, n3):
+    """m = b (q + 1) = 440, the basis width of the 4096 x 4096 x 64 workload:
+    the blocked tridiagonalisation runs several workgroups per slice and sums
+    its symv contributions in fixed point, so two calls (separate workspaces)
+    agree bit for bit."""
+    print(f"[bitwise] m=440 prec={prec} n3={n3}", flush=True)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    A = dev(inputs.random_tensor((512, 512, n3), 71), dt)
+    outs = []
+    for _ in range(2):
+        U, S, V = api.tsvd_rbk(A, 7, 100, 110, 3, prec)
+        torch.cuda.synchronize()
+        outs.append((host(U), host(S), host(V)))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 def test_info_counters_clean_on_config1():
     A, Om, c = inputs.make_config("c1_fp64_64x64x16")
     ws = api.workspace(64, 64, 16, c["k"], c["b"], c["q"], "f64", "rbk", "cuda")
@@ -184,9 +202,12 @@ def _sampled_slices(name, freqs, tol, label, prec="f32"):
     slices (weight 1 for DC / Nyquist, 2 otherwise) and the largest relative
     singular-value error of each slice, each within max(tol, 4 * floor), where
     the floor is the error of the same slices computed entirely in FP32
-    (fp32_twin_slice) against the FP64 oracle (reading R15: when
+    (fp32_twin_slice_f) against the FP64 oracle (reading R15: when
     sigma_k / sigma_1 or the gap sigma_k - sigma_{k+1} is tiny, no FP32
-    computation reaches tol).  BF16 bulk holds sigma norm-wise (reading R16).
+    computation reaches tol); for BF16x3 the twin also takes its Krylov
+    products in the three-product BF16 form (bf16x3_twin_slice_f), whose
+    operands carry 16 significant bits.  BF16 bulk holds sigma norm-wise
+    (reading R16).
     Every per-slice figure is printed."""
     (A, c), pend = _workload(name, freqs)
     n1, n2, n3 = A.shape
@@ -204,7 +225,10 @@ def _sampled_slices(name, freqs, tol, label, prec="f32"):
     for i, f in enumerate(freqs):
         Xo = (sl["Uf"][:, :, i] * sl["Sf"][:, i]) @ sl["Vf"][:, :, i].conj().T
         so = sl["Sf"][:, i]
-        Xt, st = sl["Xt"][:, :, i], sl["st"][:, i]
+        # the floor of the form's own arithmetic: FP32, or for BF16x3 the
+        # three-product BF16 Krylov products (16-bit operands)
+        tw = "3" if prec == "bf16x3" else ""
+        Xt, st = sl["Xt" + tw][:, :, i], sl["st" + tw][:, i]
         Xg = (Ub[:, :, i] * Sb[:, i].real) @ Vb[:, :, i].conj().T
         w = 1.0 if f == 0 or 2 * f == n3 else 2.0
         d2, o2, t2 = (np.linalg.norm(Xg - Xo) ** 2, np.linalg.norm(Xo) ** 2, np.linalg.norm(Xt - Xo) ** 2)
@@ -220,7 +244,7 @@ def _sampled_slices(name, freqs, tol, label, prec="f32"):
         worst = max(worst, float(s_err.max()))
         s_all = sl["s_all"][:, i]
         gap = (s_all[k - 1] - s_all[k]) / s_all[0] if s_all.size > k else 1.0
-        print(f"[parity] {label} slice {f}: X rel {np.sqrt(d2 / o2):.2e} (FP32 floor {np.sqrt(t2 / o2):.2e}); "
+        print(f"[parity] {label} slice {f}: X rel {np.sqrt(d2 / o2):.2e} ({'BF16x3' if tw else 'FP32'} floor {np.sqrt(t2 / o2):.2e}); "
               f"sigma rel max {s_err.max():.2e} (floor {s_floor.max():.2e}); sigma_k/sigma_1 {so[-1] / so[0]:.1e}, "
               f"gap(k)/sigma_1 {gap:.1e}", flush=True)
     e, fl = float(np.sqrt(num / den)), float(np.sqrt(fnum / den))
