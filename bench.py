@@ -45,40 +45,125 @@ def log(*a):
 
 
 def class_work(cls: str, c: dict, prec: str):
-    """Algorithmic work of one step in a kernel class:
-    (amount, executed/algorithmic factor, unit, bound, peak, note).  Complex
-    products count 8 real flops per multiply-add."""
+    """Algorithmic work of one step in a kernel class, as a dict:
+    flops (algorithmic, complex products at 8 real flops per multiply-add),
+    xf (MFMA flops the form executes per algorithmic flop: 3 for BF16x3),
+    bytes (algorithmic HBM bytes, where stated), mfma / hbm peaks, and the
+    bound of the algorithmic roofline: the resource whose time at its
+    published peak is the larger (algorithmic flops / MFMA peak of the
+    product's type against algorithmic bytes / HBM peak).  None for classes
+    without a stated work."""
     n1, n2, n3, k, b, q = c["n1"], c["n2"], c["n3"], c["k"], c["b"], c["q"]
     F = n3 // 2 + 1
     m = b * (q + 1)
     es = 8 if prec == "f64" else 4
+    hbm = PEAK["hbm_gbs"] * 1e9
     if cls == "gemm_krylov":   # (2q + 2) passes over A_f, b columns each
-        fl = (2 * q + 2) * 8.0 * n1 * n2 * b * F
-        if prec in ("bf16", "bf16x3"):
-            return fl / 1e12, (3.0 if prec == "bf16x3" else 1.0), "TFLOP/s", "mfma", PEAK["mfma_tflops"]["bf16"], \
-                "algorithmic flops against the BF16 MFMA peak" + \
-                (" (BF16x3 executes 3 BF16 products per algorithmic one)" if prec == "bf16x3" else "")
-        return fl / 1e12, 1.0, "TFLOP/s", "mfma", PEAK["mfma_tflops"][prec], "algorithmic flops"
-    if cls == "fft_A":         # read the real tensor, write the half spectrum
-        return (es * n1 * n2 * n3 + 2 * es * n1 * n2 * F) / 1e9, 1.0, "GB/s", "hbm", PEAK["hbm_gbs"], \
-            "algorithmic bytes"
-    # CholeskyQR passes per block: shifted + 2 (FP32 storage); FP64 adds two
-    # more shifted passes
-    passes = 5 if prec == "f64" else 3
-    if cls == "gemm_orth":     # block CGS2 against earlier blocks + shifted CholeskyQR, FP64 arithmetic
+        launches = 2 * q + 2
+        fl = launches * 8.0 * n1 * n2 * b * F
+        # per launch: A_f read once (complex, 2 es bytes; BF16x3 keeps it as
+        # (hi, lo) bf16 pairs of the same size, BF16 bulk needs one bf16 pair),
+        # the thin block read and the result written (complex, 2 es bytes)
+        ea = 4 if prec == "bf16" else 2 * es
+        by = launches * (ea * n1 * n2 + 2 * es * (n1 + n2) * b) * F
+        dt = "bf16" if prec in ("bf16", "bf16x3") else prec
+        w = {"flops": fl, "xf": 3.0 if prec == "bf16x3" else 1.0, "bytes": by,
+             "mfma_peak": PEAK["mfma_tflops"][dt] * 1e12, "hbm_peak": hbm,
+             "note": "algorithmic flops 8 n1 n2 b F and bytes (A_f once, thin block, result) per launch" +
+                     (" (BF16x3 executes 3 BF16 products per algorithmic one)" if prec == "bf16x3" else "")}
+    elif cls == "fft_A":       # read the real tensor, write the half spectrum
+        return {"flops": None, "xf": 1.0, "bytes": float(es * n1 * n2 * n3 + 2 * es * n1 * n2 * F),
+                "mfma_peak": None, "hbm_peak": hbm, "bound": "hbm", "note": "algorithmic bytes"}
+    elif cls == "gemm_orth":   # block CGS2 against earlier blocks + shifted CholeskyQR, FP64 arithmetic
+        # CholeskyQR passes per block: shifted + 1 (FP32 storage, when the
+        # FP64 orthogonality bound allows it, else + 2); FP64 adds two more
+        # shifted passes
+        passes = 5 if prec == "f64" else cholqr_passes(n1, b)
         fl = sum(2 * 16.0 * n1 * (i * b) * b for i in range(1, q + 1)) + (q + 1) * passes * 8.0 * n1 * b * (b + 1)
-        return fl * F / 1e12, 1.0, "TFLOP/s", "mfma", PEAK["mfma_tflops"]["f64"], \
-            "algorithmic flops (Hermitian Grams and W R^-1 counted as upper halves)"
-    if cls == "chol":          # b x b complex Cholesky + triangular inverse per slice, one per CholeskyQR pass
-        return passes * (q + 1) * F * (16.0 / 3.0 * b ** 3) / 1e12, 1.0, "TFLOP/s", "alu", \
-            PEAK["valu_tflops"]["f64"], "algorithmic flops"
-    if cls == "heig_tri":      # Householder tridiagonalisation of the m x m Hermitian G_f
-        return F * (16.0 / 3.0 * m ** 3) / 1e12, 1.0, "TFLOP/s", "alu", PEAK["valu_tflops"]["f64"], \
-            "algorithmic flops"
-    if cls == "gemm_lift":     # G = T^H T (Hermitian: upper half), U = Q W_k, V = T W_k
-        return F * (4.0 * n2 * m * (m + 1) + 8.0 * (n1 + n2) * m * k) / 1e12, 1.0, "TFLOP/s", "mfma", \
-            PEAK["mfma_tflops"]["f64"], "algorithmic flops (Hermitian Gram counted as its upper half)"
+        w = {"flops": fl * F, "xf": 1.0, "bytes": None, "mfma_peak": PEAK["mfma_tflops"]["f64"] * 1e12,
+             "hbm_peak": hbm, "note": "algorithmic FP64 flops (Hermitian Grams and W R^-1 counted as upper halves)"}
+    elif cls == "chol":        # b x b complex Cholesky + triangular inverse per slice, one per CholeskyQR pass
+        passes = 5 if prec == "f64" else cholqr_passes(n1, b)
+        return {"flops": passes * (q + 1) * F * (16.0 / 3.0 * b ** 3), "xf": 1.0, "bytes": None,
+                "mfma_peak": PEAK["valu_tflops"]["f64"] * 1e12, "hbm_peak": hbm, "bound": "alu",
+                "note": "algorithmic FP64 flops against the FP64 vector peak"}
+    elif cls == "heig_tri":    # Householder tridiagonalisation of the m x m Hermitian G_f
+        return {"flops": F * (16.0 / 3.0 * m ** 3), "xf": 1.0, "bytes": None,
+                "mfma_peak": PEAK["valu_tflops"]["f64"] * 1e12, "hbm_peak": hbm, "bound": "alu",
+                "note": "algorithmic FP64 flops against the FP64 vector peak"}
+    elif cls == "gemm_lift":   # G = T^H T (Hermitian: upper half), U = Q W_k, V = T W_k
+        w = {"flops": F * (4.0 * n2 * m * (m + 1) + 8.0 * (n1 + n2) * m * k), "xf": 1.0, "bytes": None,
+             "mfma_peak": PEAK["mfma_tflops"]["f64"] * 1e12, "hbm_peak": hbm,
+             "note": "algorithmic flops (Hermitian Gram counted as its upper half)"}
+    else:
+        return None
+    t_mfma = w["flops"] / w["mfma_peak"]
+    t_hbm = w["bytes"] / w["hbm_peak"] if w["bytes"] else 0.0
+    w["bound"] = "hbm" if t_hbm > t_mfma else "mfma"
+    return w
+
+
+def cholqr_passes(rows: int, b: int) -> int:
+    """CholeskyQR passes per FP32-stored block: the shifted pass plus one
+    unshifted pass when the FP64 orthogonality bound of that pass stays within
+    2^-20, else plus two (the library's rule for FP32 storage)."""
+    u64 = 2.0 ** -53
+    alpha = 11.0 * (rows * b + b * (b + 1)) * u64 * b
+    return 2 if alpha * u64 * 1e16 <= 2.0 ** -20 else 3
+
+
+def roofline_for(kernels: dict, c: dict, prec: str, workload: str):
+    """Roofline of the dominant kernel class that has a stated algorithmic
+    work.  bound = hbm: achieved = algorithmic bytes per step / that class's
+    time per step against the HBM peak; bound = mfma or alu: algorithmic flops
+    against the MFMA (or vector) peak of the class's arithmetic type.
+    frac_mfma_executed gives the MFMA flops the form actually issues (3x the
+    algorithmic flops for BF16x3) against the MFMA peak."""
+    for cls, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        w = class_work(cls, c, prec)
+        if w is None:
+            continue
+        sec = v["ms_per_step"] * 1e-3
+        if w["bound"] == "hbm":
+            achieved, peak, unit = w["bytes"] / sec / 1e9, w["hbm_peak"] / 1e9, "GB/s"
+        else:
+            achieved, peak, unit = w["flops"] / sec / 1e12, w["mfma_peak"] / 1e12, "TFLOP/s"
+        tr = profiled_traffic(cls, prec, workload)
+        out = {"kernel": cls, "bound": w["bound"], "achieved": achieved, "peak": peak, "unit": unit,
+               "frac": achieved / peak,
+               "traffic": tr["bytes_per_launch"] if tr else None,
+               "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+               "traffic_source": tr["source"] if tr else None, "work": w["note"],
+               "launches_per_step": v["launches_per_step"], "avg_launch_ms": v["avg_launch_ms"]}
+        if w["flops"] and w["mfma_peak"]:
+            out["frac_mfma_executed"] = w["flops"] * w["xf"] / sec / w["mfma_peak"]
+        if w["bytes"]:
+            out["algorithmic_bytes_per_launch"] = w["bytes"] / v["launches_per_step"]
+        return out
     return None
+
+
+def kernel_figures(kernels: dict, c: dict, prec: str):
+    """Krylov-product MFMA utilisation (algorithmic and executed flops against
+    the MFMA peak of the form's type), their HBM rate over the algorithmic
+    bytes, and the mode-3 DFT's HBM rate, from the timed kernel classes."""
+    out = {}
+    kry = kernels.get("gemm_krylov")
+    if kry:
+        w = class_work("gemm_krylov", c, prec)
+        sec = kry["ms_per_step"] * 1e-3
+        out["krylov_mfma_util"] = w["flops"] / sec / w["mfma_peak"]
+        out["krylov_mfma_util_executed"] = w["flops"] * w["xf"] / sec / w["mfma_peak"]
+        out["krylov_tflops_algorithmic"] = w["flops"] / sec / 1e12
+        out["krylov_hbm_frac"] = w["bytes"] / sec / w["hbm_peak"]
+        out["krylov_bound"] = w["bound"]
+    fft = kernels.get("fft_A")
+    if fft:
+        w = class_work("fft_A", c, prec)
+        gbs = w["bytes"] / (fft["ms_per_step"] * 1e-3) / 1e9
+        out["fft_hbm"] = {"achieved_GBs": gbs, "peak_GBs": w["hbm_peak"] / 1e9, "frac": gbs * 1e9 / w["hbm_peak"],
+                          "bytes_per_launch": w["bytes"], "ms_per_launch": fft["avg_launch_ms"]}
+    return out
 
 
 def profiled_traffic(cls: str, prec: str, workload: str):
@@ -102,47 +187,6 @@ def profiled_traffic(cls: str, prec: str, workload: str):
                     return None
             return {"bytes_per_launch": rec["bytes_per_launch"], "source": os.path.relpath(fn, root)}
     return None
-
-
-def roofline_for(kernels: dict, c: dict, prec: str, workload: str):
-    """Roofline of the dominant kernel class that has a stated algorithmic
-    work: achieved = algorithmic work per step / that class's time per step;
-    frac = achieved / peak; frac_executed counts the MFMA work the form
-    actually issues (3x the algorithmic flops for BF16x3)."""
-    for cls, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_step"]):
-        w = class_work(cls, c, prec)
-        if w is None:
-            continue
-        amount, xf, unit, bound, peak, note = w
-        achieved = amount / (v["ms_per_step"] * 1e-3)
-        tr = profiled_traffic(cls, prec, workload)
-        return {"kernel": cls, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "frac_executed": achieved * xf / peak,
-                "traffic": tr["bytes_per_launch"] if tr else None,
-                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "traffic_source": tr["source"] if tr else None, "work": note,
-                "launches_per_step": v["launches_per_step"], "avg_launch_ms": v["avg_launch_ms"]}
-    return None
-
-
-def kernel_figures(kernels: dict, c: dict, prec: str):
-    """Krylov-product MFMA utilisation (algorithmic and executed) and the
-    mode-3 DFT's HBM rate, from the timed kernel classes."""
-    out = {}
-    kry = kernels.get("gemm_krylov")
-    if kry:
-        amount, xf, _, _, peak, _ = class_work("gemm_krylov", c, prec)
-        rate = amount / (kry["ms_per_step"] * 1e-3)
-        out["krylov_mfma_util"] = rate / peak
-        out["krylov_mfma_util_executed"] = rate * xf / peak
-        out["krylov_tflops_algorithmic"] = rate
-    fft = kernels.get("fft_A")
-    if fft:
-        gb, _, _, _, peak, _ = class_work("fft_A", c, prec)
-        out["fft_hbm"] = {"achieved_GBs": gb / (fft["ms_per_step"] * 1e-3), "peak_GBs": peak,
-                          "frac": gb / (fft["ms_per_step"] * 1e-3) / peak, "bytes_per_launch": gb * 1e9,
-                          "ms_per_launch": fft["avg_launch_ms"]}
-    return out
 
 
 def time_calls(api, fn, steps: int, warmup: int):
