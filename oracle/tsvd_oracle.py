@@ -29,6 +29,13 @@ Pins (tests/test_oracle_*.py, all ``-m "not gpu"``):
                            literal == stabilised Krylov form
   proj / proj_backward     central finite differences, torch CPU autograd,
                            Euler homogeneity
+  approx_backward          central finite differences, torch CPU autograd
+                           through QR and a Hermitian eigendecomposition,
+                           Euler homogeneity, k = m equals proj_backward
+  ritz_tsvd                the singular values of Q_r^T * A are the top r of
+                           Q^T * A (Rayleigh-Ritz), the rank-k result equals
+                           Alg. 2's, Q_r^T * Q_r = I and Q * Q^T * Q_r = Q_r
+                           with spatial T-products, r = m spans Q
   tqr / tpinv              X = Q * R and Q^T * Q = I with spatial T-products,
                            triangular slices with a real non-negative
                            diagonal, numpy QR at n3 = 1; the four Penrose
@@ -87,6 +94,15 @@ Readings (where the paper is silent / ambiguous):
       singular value s_j of X_f counts as nonzero when s_j > rtol * s_1(X_f)
       (the usual relative rank cut-off of a matrix pinv), with
       rtol = max(n1, n2) * 2^-52 unless given.
+  R23 "Q truncated to k + p terms" (the timing remark of Ex. 1): with the
+      block order of Alg. 2 the first k + p columns of Q span only A*Omega, so
+      the truncation is read as a Rayleigh-Ritz reduction: Q_r = Q W(:, 1:r),
+      W the left singular vectors of C = Q^T * A per slice, r = k + p.  The
+      rank-k result equals the full basis's in exact arithmetic.
+  R24 Differentiating through the rank-k truncation: L = <G, X_hat(A)> with
+      X_hat = Q * (Q^T * A)_k (Lemma mn38); the truncation enters through the
+      projector onto the top-k eigenvectors of C C^H per slice, defined when
+      lambda_k > lambda_{k+1} there.
 """
 from __future__ import annotations
 
@@ -595,20 +611,11 @@ def proj(A: np.ndarray, Omega: np.ndarray, b: int, q: int, krylov: str = "stab")
     return real_part_checked(idft_mode3(mirror(Ph, n3)))
 
 
-def _proj_slice_adjoint(Af, Of, Yb, q):
-    """Adjoint of the per-slice map A_f -> Q Q^H A_f at A_f, applied to the
-    cotangent Yb, for the real inner product <X, Y> = Re tr(X^H Y).
-
-    Forward (stabilised form, reading R6): Q_0 R_0 = A Om; for i >= 1,
-    T_i = A^H Q_{i-1}, W_i = A T_i, Z_i = (I - Q_<i Q_<i^H) W_i, Q_i R_i = Z_i.
-    Reverse: direct term Q Q^H Yb; Qbar = (Yb A^H + A Yb^H) Q; for i = q..1:
-    Zbar_i = (I - Q_i Q_i^H) Qbar_i R_i^{-H} (the loss depends on Q_i only
-    through its range); Wbar_i = (I - Q_<i Q_<i^H) Zbar_i;
-    Qbar_l -= (Zbar_i W_i^H + W_i Zbar_i^H) Q_l for l < i;
-    Abar += Wbar_i T_i^H; Tbar_i = A^H Wbar_i; Abar += Q_{i-1} Tbar_i^H;
-    Qbar_{i-1} += A Tbar_i.  Finally Zbar_0 = (I - Q_0 Q_0^H) Qbar_0 R_0^{-H}
-    and Abar += Zbar_0 Om^H."""
-    A = Af
+def _krylov_factors(A, Of, q):
+    """The stabilised recursion (reading R6) with the factors its reverse pass
+    needs: Q_0 R_0 = A Om; for i >= 1, T_i = A^H Q_{i-1}, W_i = A T_i,
+    Z_i = (I - Q_<i Q_<i^H) W_i (twice), Q_i R_i = Z_i.  Returns the lists
+    (Qs, Rs, Ts, Ws) with None in the unused i = 0 entries of Ts and Ws."""
     Q0, R0 = householder_qr(A @ Of)
     Qs, Rs, Ts, Ws = [Q0], [R0], [None], [None]
     for i in range(1, q + 1):
@@ -622,10 +629,20 @@ def _proj_slice_adjoint(Af, Of, Yb, q):
         Rs.append(Ri)
         Ts.append(T)
         Ws.append(W)
-    Q = np.concatenate(Qs, axis=1)
-    b = Q0.shape[1]
-    Abar = Q @ (Q.conj().T @ Yb)
-    Qbar_all = Yb @ (A.conj().T @ Q) + A @ (Yb.conj().T @ Q)   # (Yb A^H + A Yb^H) Q
+    return Qs, Rs, Ts, Ws
+
+
+def _krylov_reverse(A, Of, Qs, Rs, Ts, Ws, Abar, Qbar_all):
+    """Reverse pass of the stabilised recursion for a loss that depends on
+    every block Q_i only through its range: given Abar (the direct part of
+    dL/dA_f) and Qbar_all (dL/dQ, n1 x m), for i = q..1:
+    Zbar_i = (I - Q_i Q_i^H) Qbar_i R_i^{-H}; Wbar_i = (I - Q_<i Q_<i^H) Zbar_i;
+    Qbar_l -= (Zbar_i W_i^H + W_i Zbar_i^H) Q_l for l < i;
+    Abar += Wbar_i T_i^H; Tbar_i = A^H Wbar_i; Abar += Q_{i-1} Tbar_i^H;
+    Qbar_{i-1} += A Tbar_i.  Finally Zbar_0 = (I - Q_0 Q_0^H) Qbar_0 R_0^{-H}
+    and Abar += Zbar_0 Om^H."""
+    q = len(Qs) - 1
+    b = Qs[0].shape[1]
     Qbar = [Qbar_all[:, i * b:(i + 1) * b].copy() for i in range(q + 1)]
     for i in range(q, 0, -1):
         Qi, Ri = Qs[i], Rs[i]
@@ -639,10 +656,27 @@ def _proj_slice_adjoint(Af, Of, Yb, q):
         Tbar = A.conj().T @ Wbar
         Abar += Qs[i - 1] @ Tbar.conj().T
         Qbar[i - 1] += A @ Tbar
+    Q0, R0 = Qs[0], Rs[0]
     X = Qbar[0] - Q0 @ (Q0.conj().T @ Qbar[0])
     Zbar0 = np.linalg.solve(R0, X.conj().T).conj().T
     Abar += Zbar0 @ Of.conj().T
     return Abar
+
+
+def _proj_slice_adjoint(Af, Of, Yb, q):
+    """Adjoint of the per-slice map A_f -> Q Q^H A_f at A_f, applied to the
+    cotangent Yb, for the real inner product <X, Y> = Re tr(X^H Y).
+
+    Forward: the stabilised recursion (_krylov_factors).  Reverse: direct term
+    Q Q^H Yb; Qbar = (Yb A^H + A Yb^H) Q; then the reverse recursion
+    (_krylov_reverse), in which the loss depends on each Q_i only through its
+    range (the gauge term of the QR adjoint vanishes)."""
+    A = Af
+    Qs, Rs, Ts, Ws = _krylov_factors(A, Of, q)
+    Q = np.concatenate(Qs, axis=1)
+    Abar = Q @ (Q.conj().T @ Yb)
+    Qbar_all = Yb @ (A.conj().T @ Q) + A @ (Yb.conj().T @ Q)   # (Yb A^H + A Yb^H) Q
+    return _krylov_reverse(A, Of, Qs, Rs, Ts, Ws, Abar, Qbar_all)
 
 
 def proj_backward(A: np.ndarray, Omega: np.ndarray, G: np.ndarray, b: int, q: int):
@@ -658,6 +692,107 @@ def proj_backward(A: np.ndarray, Omega: np.ndarray, G: np.ndarray, b: int, q: in
     for f in range(F):
         Dh[:, :, f] = _proj_slice_adjoint(Ab[:, :, f], Ob[:, :, f], Gb[:, :, f], q)
     return real_part_checked(idft_mode3(mirror(Dh, n3)))
+
+
+def _approx_slice_adjoint(Af, Of, Yb, k, q):
+    """Adjoint of the per-slice rank-k approximation of Alg. 2,
+    A_f -> X_f = Q Pi C with C = Q^H A_f and Pi = W_k W_k^H the projector onto
+    the top-k eigenvectors of G = C C^H (Lemma mn38: X_f = U_k U_k^H A_f with
+    U_k = Q W_k), applied to the cotangent Yb, real inner product Re tr(X^H Y)
+    (reading R24).
+
+    With Y = Q^H Yb: the direct terms give Cbar = Pi Y and Qbar = Yb C^H Pi.
+    Pi depends on G through the eigenvectors on either side of the cut: for
+    a in the top k and c outside it, first-order perturbation theory gives
+    dPi = sum w_c w_c^H dG w_a w_a^H / (lambda_a - lambda_c) + its conjugate
+    transpose, so with M = W^H (Y C^H) W (Y C^H is the cotangent of Pi) the
+    cotangent of G is W N W^H, N_ac = M_ac / (lambda_a - lambda_c) and
+    N_ca = M_ca / (lambda_a - lambda_c) (zero inside either group), and
+    G = C C^H adds (W (N + N^H) W^H) C to Cbar.  C = Q^H A_f then gives
+    Abar = Q Cbar and Qbar += A_f Cbar^H.  X_f depends on Q only through its
+    range, so the reverse recursion of the projection applies unchanged.
+    Needs lambda_k - lambda_{k+1} above the eigenvalues' rounding level
+    m 2^-53 lambda_1 (else ValueError)."""
+    A = Af
+    Qs, Rs, Ts, Ws = _krylov_factors(A, Of, q)
+    Q = np.concatenate(Qs, axis=1)
+    m = Q.shape[1]
+    C = Q.conj().T @ A
+    W, s, _, _ = jacobi_svd(C)
+    lam = s * s
+    if k < m and not lam[k - 1] - lam[k] > m * EPS64 * lam[0]:
+        # a gap at the rounding level of the eigenvalues: the top-k subspace,
+        # and with it the derivative, is not determined
+        raise ValueError("the rank-k truncation needs lambda_k > lambda_{k+1}")
+    Y = Q.conj().T @ Yb
+    Wk = W[:, :k]
+    Pi = Wk @ Wk.conj().T
+    M = W.conj().T @ (Y @ C.conj().T) @ W
+    N = np.zeros((m, m), dtype=np.complex128)
+    for a in range(k):
+        for c in range(k, m):
+            N[a, c] = M[a, c] / (lam[a] - lam[c])
+            N[c, a] = M[c, a] / (lam[a] - lam[c])
+    H = W @ (N + N.conj().T) @ W.conj().T
+    Cbar = Pi @ Y + H @ C
+    Abar = Q @ Cbar
+    Qbar_all = Yb @ (C.conj().T @ Pi) + A @ Cbar.conj().T
+    return _krylov_reverse(A, Of, Qs, Rs, Ts, Ws, Abar, Qbar_all)
+
+
+def approx_backward(A: np.ndarray, Omega: np.ndarray, G: np.ndarray, k: int, b: int, q: int):
+    """dL/dA for L = <G, X_hat(A)>, X_hat = U * S * V^T the rank-k result of
+    Alg. 2 (= Q * (Q^T * A)_k, Lemma mn38): per-slice adjoint of the Fourier
+    domain map applied to fft(G), mirrored, inverse transformed (as for
+    proj_backward)."""
+    n1, n2, n3 = A.shape
+    _check_params(n1, n2, n3, k, b, q)
+    F = n_half(n3)
+    Ab, Ob, Gb = dft_mode3(A, range(F)), dft_mode3(Omega, range(F)), dft_mode3(G, range(F))
+    Dh = np.zeros((n1, n2, F), complex)
+    for f in range(F):
+        Dh[:, :, f] = _approx_slice_adjoint(Ab[:, :, f], Ob[:, :, f], Gb[:, :, f], k, q)
+    return real_part_checked(idft_mode3(mirror(Dh, n3)))
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5 (Ex. 1, timing remark): the basis truncated to k + p columns, read as
+# a Rayleigh-Ritz reduction (reading R23)
+# ---------------------------------------------------------------------------
+
+def ritz_basis(Af: np.ndarray, Of: np.ndarray, q: int, r: int):
+    """The block Krylov basis Q_f (n1 x m) of Alg. 2 reduced to its top r
+    Ritz directions for A_f A_f^H: C = Q_f^H A_f = W diag(s) Z^H (Jacobi SVD),
+    Q_r = Q_f W(:, :r), columns in the phase convention of reading R9.
+    span Q_r is the r-dimensional subspace of span Q_f that captures the
+    most of A_f (Rayleigh-Ritz)."""
+    Q, _ = krylov_basis(Af, Of, q)
+    W, _, _, _ = jacobi_svd(Q.conj().T @ Af)
+    Qr, _ = canonical_phase(Q @ W[:, :r], np.zeros((1, r), dtype=np.complex128))
+    return Qr
+
+
+def ritz_slices(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int, r: int | None = None, freqs=None):
+    """Alg. 2 with Q truncated to r = k + p (default b) columns before the
+    projection (reading R23): per slice Q_r = ritz_basis, then C_r = Q_r^H A_f,
+    its SVD, lift and truncation exactly as for the full basis.  Same dict
+    layout as rbk_slices, with Q the n1 x r truncated basis."""
+    n1, n2, n3 = A.shape
+    _check_params(n1, n2, n3, k, b, q)
+    r = b if r is None else r
+    if not k <= r <= b * (q + 1):
+        raise ValueError("need k <= r <= m")
+    return _truncated_slices(A, Omega, k, b, r, freqs, lambda Af, Of: ritz_basis(Af, Of, q, r))
+
+
+def ritz_tsvd(A: np.ndarray, Omega: np.ndarray, k: int, b: int, q: int, r: int | None = None):
+    """Spatial U, S, V of the truncated-basis variant, plus Qr: the truncated
+    basis as an orthonormal n1 x r x n3 tensor (Qr^T * Qr = I)."""
+    sl = ritz_slices(A, Omega, k, b, q, r)
+    n3 = A.shape[2]
+    sl = _spatial_factors(sl, n3)
+    sl["Qr"] = real_part_checked(idft_mode3(mirror(sl["Q"], n3)))
+    return sl
 
 
 # ---------------------------------------------------------------------------

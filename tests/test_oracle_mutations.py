@@ -144,6 +144,30 @@ def pin_adjoint_fd(O):
         assert abs(fd - np.sum(g * D)) <= 1e-6 * abs(fd) + 1e-9
 
 
+def pin_approx_adjoint_fd(O):
+    n1, n2, n3, k, b, q = 7, 6, 3, 2, 3, 1
+    A = inputs.random_tensor((n1, n2, n3), 12)
+    Om = inputs.omega(n2, b, n3, 12)
+    G = inputs.random_tensor((n1, n2, n3), 13)
+    g = O.approx_backward(A, Om, G, k, b, q)
+    h = 1e-6
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        D = rng.standard_normal(A.shape)
+        fd = (np.sum(G * O.rbk_approx(A + h * D, Om, k, b, q)) - np.sum(G * O.rbk_approx(A - h * D, Om, k, b, q))) / (2 * h)
+        assert abs(fd - np.sum(g * D)) <= 1e-6 * abs(fd) + 1e-9
+
+
+def pin_ritz(O):
+    n1, n2, n3, k, b, q = 12, 10, 4, 3, 4, 1
+    A = inputs.random_tensor((n1, n2, n3), 14)
+    Om = inputs.omega(n2, b, n3, 14)
+    sr = O.ritz_slices(A, Om, k, b, q)
+    sf = O.rbk_slices(A, Om, k, b, q)
+    assert np.allclose(sr["s_all"], sf["s_all"][:b], atol=1e-12 * sf["s_all"].max())
+    assert np.allclose(O.approx_from_slices(sr, n1, n2, n3), O.approx_from_slices(sf, n1, n2, n3), atol=1e-12)
+
+
 MUTATIONS = [
     ("dft sign", "- 1j * np.sin(2.0 * np.pi * r / n)", "+ 1j * np.sin(2.0 * np.pi * r / n)", pin_dft),
     ("mirror without conj", "full[..., f] = np.conj(Xh[..., n3 - f])", "full[..., f] = Xh[..., n3 - f]", pin_tprod),
@@ -183,6 +207,16 @@ MUTATIONS = [
      "Qbar_all = Yb @ (A.conj().T @ Q)", pin_adjoint_fd),
     ("adjoint reverse Krylov term dropped", "Abar += Qs[i - 1] @ Tbar.conj().T", "pass", pin_adjoint_fd),
     ("adjoint R^-H dropped", "Zbar0 = np.linalg.solve(R0, X.conj().T).conj().T", "Zbar0 = X", pin_adjoint_fd),
+    ("truncation adjoint without the eigenvector term", "Cbar = Pi @ Y + H @ C", "Cbar = Pi @ Y",
+     pin_approx_adjoint_fd),
+    ("truncation adjoint gap sign", "N[c, a] = M[c, a] / (lam[a] - lam[c])", "N[c, a] = M[c, a] / (lam[c] - lam[a])",
+     pin_approx_adjoint_fd),
+    ("truncation adjoint Qbar without the projector", "Qbar_all = Yb @ (C.conj().T @ Pi) + A @ Cbar.conj().T",
+     "Qbar_all = Yb @ C.conj().T + A @ Cbar.conj().T", pin_approx_adjoint_fd),
+    ("truncated basis as the first r columns", "canonical_phase(Q @ W[:, :r], np.zeros",
+     "canonical_phase(Q[:, :r] + 0 * W[:1, :r], np.zeros", pin_ritz),
+    ("truncated basis from the smallest Ritz values", "canonical_phase(Q @ W[:, :r], np.zeros",
+     "canonical_phase(Q @ W[:, -r:], np.zeros", pin_ritz),
 ]
 
 
