@@ -14,7 +14,7 @@
  * (i * n2 + j) * n3 + t, so every tube X(i, j, :) is contiguous.  A tensor
  * written "p x r x n3" uses the same rule with (p, r, n3).
  *
- * Pointers named A, Omega, G, U, S, V, Xhat, P, dA and ws are DEVICE pointers
+ * Pointers named A, Omega, G, U, S, V, Xhat, P, Qr, dA and ws are DEVICE pointers
  * on the current HIP device.  The caller owns all of them; the library never
  * allocates or frees device memory and never keeps a pointer after return.
  * Inputs are read only.  Outputs may not alias inputs or each other.
@@ -108,6 +108,8 @@ extern "C" {
 #define TSVD_OP_COMPLETE_RBK 8    /* tsvd_complete with alg = 2 */
 #define TSVD_OP_COMPLETE_POWER 9  /* tsvd_complete with alg = 1 */
 #define TSVD_OP_RBK_LITERAL 10    /* tsvd_rbk_literal */
+#define TSVD_OP_RBK_RITZ 11       /* tsvd_rbk_ritz */
+#define TSVD_OP_APPROX_BWD 12     /* tsvd_rbk_approx_backward */
 
 /* diagnostic counters returned by tsvd_read_info (int32 each) */
 #define TSVD_INFO_CHOL_SHIFTED 0   /* shifted Cholesky passes whose shift rescued a
@@ -117,6 +119,9 @@ extern "C" {
 #define TSVD_INFO_CHOL_BREAKDOWN 1 /* pivots still non-positive after the shift */
 #define TSVD_INFO_EIG_NOCONV 2     /* eigenvectors that did not converge        */
 #define TSVD_INFO_NONFINITE 3      /* non-finite values met                     */
+#define TSVD_INFO_TRUNCATION_TIE 4 /* tsvd_rbk_approx_backward: pairs of eigenvalues
+                                      across the rank-k cut closer than their
+                                      rounding level (derivative undefined) */
 #define TSVD_INFO_COUNT 8
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -214,6 +219,28 @@ int tsvd_rbk_literal_omega(const void* A, const void* Omega, int64_t n1,
                            int64_t n2, int64_t n3, int64_t k, int64_t b,
                            int64_t q, int prec, void* U, void* S, void* V,
                            void* Xhat, void* ws, size_t ws_bytes, void* stream);
+
+/* Alg. 2 with the basis truncated to k + p columns before the projection
+ * (the timing remark of Sec. 5, Ex. 1: "Q truncated to k + p terms"), read as
+ * a Rayleigh-Ritz reduction: per Fourier slice, the block Krylov basis Q_f
+ * (n1 x m) of tsvd_rbk and C_f = Q_f^H A_f give the top b = k + p left
+ * singular vectors W_b of C_f, and Q_r = Q_f W_b (n1 x b, columns in the
+ * phase rule of tsvd_rbk); then Alg. 2's projection C_r = Q_r^H A_f (one more
+ * b-column product over A_f), small SVD, lift and truncation to k run on Q_r.
+ * The rank-k result equals tsvd_rbk's in exact arithmetic (the singular values
+ * of C_r are the b largest of C_f).
+ * Out: Qr (n1 x b x n3, the truncated basis as an orthonormal tensor,
+ *      Qr^T * Qr = I), U, S, V as for tsvd_rbk.  Arguments, errors and
+ * workspace (tsvd_workspace_bytes(..., TSVD_OP_RBK_RITZ)) otherwise as
+ * tsvd_rbk; 1 <= k <= b. */
+int tsvd_rbk_ritz(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k,
+                  int64_t b, int64_t q, uint64_t seed, int prec, void* Qr,
+                  void* U, void* S, void* V, void* ws, size_t ws_bytes,
+                  void* stream);
+int tsvd_rbk_ritz_omega(const void* A, const void* Omega, int64_t n1,
+                        int64_t n2, int64_t n3, int64_t k, int64_t b,
+                        int64_t q, int prec, void* Qr, void* U, void* S,
+                        void* V, void* ws, size_t ws_bytes, void* stream);
 
 /* Alg. 1: classical randomized subspace method with q power iterations.
  * Same arguments, layouts and outputs as tsvd_rbk, but the basis Q_f
@@ -335,6 +362,28 @@ int tsvd_proj_backward_omega(const void* A, const void* Omega, const void* G,
                              int64_t n1, int64_t n2, int64_t n3, int64_t b,
                              int64_t q, int prec, void* dA, void* ws,
                              size_t ws_bytes, void* stream);
+
+/* Adjoint through the rank-k truncation: given G = dL/dXhat (n1 x n2 x n3),
+ * writes dA = dL/dA (n1 x n2 x n3) for L(Xhat(A)), Xhat = U * S * V^T the
+ * rank-k result of Alg. 2 with the test tensor of seed (= Q * (Q^T * A)_k,
+ * Lemma mn38), real inner product sum_ijt x_ijt y_ijt.  Per Fourier slice
+ * the truncation enters through the projector onto the top-k eigenvectors
+ * of C_f C_f^H (all m eigenpairs are formed, FP64); the Krylov blocks are
+ * recomputed from A and Omega.  The derivative exists where lambda_k >
+ * lambda_{k+1} in every slice: eigenvalue pairs across the cut closer than
+ * 8 m 2^-53 lambda_1 contribute nothing and are counted in
+ * TSVD_INFO_TRUNCATION_TIE (tsvd_read_info then returns TSVD_ENUMERIC).
+ * Arguments as tsvd_rbk (1 <= k <= b) plus G and dA (device, A's layout and
+ * type); workspace tsvd_workspace_bytes(..., TSVD_OP_APPROX_BWD). */
+int tsvd_rbk_approx_backward(const void* A, const void* G, int64_t n1,
+                             int64_t n2, int64_t n3, int64_t k, int64_t b,
+                             int64_t q, uint64_t seed, int prec, void* dA,
+                             void* ws, size_t ws_bytes, void* stream);
+int tsvd_rbk_approx_backward_omega(const void* A, const void* Omega,
+                                   const void* G, int64_t n1, int64_t n2,
+                                   int64_t n3, int64_t k, int64_t b, int64_t q,
+                                   int prec, void* dA, void* ws,
+                                   size_t ws_bytes, void* stream);
 
 /* Copy the TSVD_INFO_COUNT diagnostic counters of the last call that used
  * workspace `ws` into info_host (host memory).  Synchronises `stream`.

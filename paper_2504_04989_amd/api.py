@@ -17,14 +17,15 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lib", "lib
 TSVD_OK, TSVD_EINVAL, TSVD_ENOMEM, TSVD_EHIP, TSVD_ENUMERIC = 0, 1, 2, 3, 4
 PREC = {"f64": 0, "f32": 1, "bf16": 2, "bf16x3": 3}
 OP = {"rbk": 0, "approx": 1, "proj": 2, "proj_bwd": 3, "power": 4, "power_approx": 5, "tqr": 6, "tpinv": 7, "complete2": 8,
-      "complete1": 9, "literal": 10}
-INFO_NAMES = ("chol_shifted", "chol_breakdown", "eig_noconv", "nonfinite")
+      "complete1": 9, "literal": 10, "ritz": 11, "approx_bwd": 12}
+INFO_NAMES = ("chol_shifted", "chol_breakdown", "eig_noconv", "nonfinite", "truncation_tie")
 INFO_COUNT = 8
 
 EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_omega",
            "tsvd_rbk", "tsvd_rbk_omega", "tsvd_rbk_noalloc", "tsvd_rbk_approx", "tsvd_rbk_approx_omega",
            "tsvd_power", "tsvd_power_omega", "tsvd_power_approx", "tsvd_power_approx_omega",
-           "tsvd_rbk_literal", "tsvd_rbk_literal_omega", "tsvd_complete", "tsvd_complete_omega",
+           "tsvd_rbk_literal", "tsvd_rbk_literal_omega", "tsvd_rbk_ritz", "tsvd_rbk_ritz_omega",
+           "tsvd_rbk_approx_backward", "tsvd_rbk_approx_backward_omega", "tsvd_complete", "tsvd_complete_omega",
            "tsvd_tqr", "tsvd_tpinv", "tsvd_tpinv_default_rtol", "tsvd_proj", "tsvd_proj_omega", "tsvd_proj_backward",
            "tsvd_proj_backward_omega", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
            "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_split_bf16x3", "tsvd_diag_heig",
@@ -59,6 +60,14 @@ def _load():
         f = getattr(lib, name + "_omega")
         f.restype = ci
         f.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ci] + [vp] * nout + [vp, sz, vp]
+    lib.tsvd_rbk_ritz.restype = ci
+    lib.tsvd_rbk_ritz.argtypes = [vp, i64, i64, i64, i64, i64, i64, u64, ci] + [vp] * 4 + [vp, sz, vp]
+    lib.tsvd_rbk_ritz_omega.restype = ci
+    lib.tsvd_rbk_ritz_omega.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, ci] + [vp] * 4 + [vp, sz, vp]
+    lib.tsvd_rbk_approx_backward.restype = ci
+    lib.tsvd_rbk_approx_backward.argtypes = [vp, vp, i64, i64, i64, i64, i64, i64, u64, ci, vp, vp, sz, vp]
+    lib.tsvd_rbk_approx_backward_omega.restype = ci
+    lib.tsvd_rbk_approx_backward_omega.argtypes = [vp, vp, vp, i64, i64, i64, i64, i64, i64, ci, vp, vp, sz, vp]
     lib.tsvd_rbk_noalloc.restype = ci
     lib.tsvd_rbk_noalloc.argtypes = [vp, i64, i64, i64, i64, i64, i64, u64, ci, vp, vp, vp, vp]
     lib.tsvd_tqr.restype = ci
@@ -158,7 +167,8 @@ def workspace(n1, n2, n3, k, b, q, prec, op, device) -> torch.Tensor:
 def read_info(ws: torch.Tensor) -> dict:
     """Diagnostic counters of the last call that used `ws` (synchronises its
     stream).  "status" is TSVD_ENUMERIC when that call met a Cholesky
-    breakdown, an unconverged eigenvector or a non-finite value, else TSVD_OK."""
+    breakdown, an unconverged eigenvector, a non-finite value or (adjoint of
+    the truncation) a tie at the rank-k cut, else TSVD_OK."""
     buf = (ctypes.c_int32 * INFO_COUNT)()
     code = lib.tsvd_read_info(_ptr(ws), buf, _stream(ws.device))
     if code not in (TSVD_OK, TSVD_ENUMERIC):
@@ -272,6 +282,55 @@ def tsvd_rbk_literal(A, Omega, k, b, q, prec=None, ws=None, approx=True):
     """Alg. 2 with the literal Krylov powers (no orthonormalisation between
     steps): returns (U, S, V, X_hat) (X_hat None when approx is False)."""
     return _svd_call("tsvd_rbk_literal", "literal", A, Omega, k, b, q, prec, ws, None, approx)
+
+
+def tsvd_rbk_ritz(A: torch.Tensor, Omega, k: int, b: int, q: int, prec=None, ws=None):
+    """Alg. 2 with the basis truncated to its top b Ritz directions before the
+    projection: returns (Qr, U, S, V), Qr (n1, b, n3) the truncated basis, U,
+    S, V as tsvd_rbk (see tsvd_rbk_ritz in the C header)."""
+    prec = _prec_of(A, prec)
+    dt = _dtype_of(prec)
+    _check_in(A, dt, "A")
+    n1, n2, n3 = _shape3(A)
+    _omega_in(Omega, dt, n2, b, n3)
+    dev = A.device
+    if ws is None:
+        ws = workspace(n1, n2, n3, k, b, q, prec, "ritz", dev)
+    Qr = torch.empty((n1, b, n3), dtype=dt, device=dev)
+    U = torch.empty((n1, k, n3), dtype=dt, device=dev)
+    S = torch.empty((k, n3), dtype=dt, device=dev)
+    V = torch.empty((n2, k, n3), dtype=dt, device=dev)
+    if _is_seed(Omega):
+        _check(lib.tsvd_rbk_ritz(_ptr(A), n1, n2, n3, k, b, q, int(Omega) & 0xFFFFFFFFFFFFFFFF, PREC[prec], _ptr(Qr),
+                                 _ptr(U), _ptr(S), _ptr(V), _ptr(ws), ws.numel(), _stream(dev)))
+    else:
+        _check(lib.tsvd_rbk_ritz_omega(_ptr(A), _ptr(Omega), n1, n2, n3, k, b, q, PREC[prec], _ptr(Qr), _ptr(U),
+                                       _ptr(S), _ptr(V), _ptr(ws), ws.numel(), _stream(dev)))
+    return Qr, U, S, V
+
+
+def tsvd_rbk_approx_backward(A, Omega, G, k, b, q, prec=None, ws=None):
+    """dL/dA for L(X_hat(A)) given G = dL/dX_hat (A's shape), X_hat the
+    rank-k result of tsvd_rbk_approx (the derivative through the truncation)."""
+    prec = _prec_of(A, prec)
+    dt = _dtype_of(prec)
+    _check_in(A, dt, "A")
+    _check_in(G, dt, "G")
+    n1, n2, n3 = _shape3(A)
+    if tuple(G.shape) != (n1, n2, n3):
+        raise ValueError(f"G must have A's shape {(n1, n2, n3)}, got {tuple(G.shape)}")
+    _omega_in(Omega, dt, n2, b, n3)
+    dev = A.device
+    if ws is None:
+        ws = workspace(n1, n2, n3, k, b, q, prec, "approx_bwd", dev)
+    dA = torch.empty_like(A)
+    if _is_seed(Omega):
+        _check(lib.tsvd_rbk_approx_backward(_ptr(A), _ptr(G), n1, n2, n3, k, b, q, int(Omega) & 0xFFFFFFFFFFFFFFFF,
+                                            PREC[prec], _ptr(dA), _ptr(ws), ws.numel(), _stream(dev)))
+    else:
+        _check(lib.tsvd_rbk_approx_backward_omega(_ptr(A), _ptr(Omega), _ptr(G), n1, n2, n3, k, b, q, PREC[prec],
+                                                  _ptr(dA), _ptr(ws), ws.numel(), _stream(dev)))
+    return dA
 
 
 def tsvd_power(A: torch.Tensor, Omega, k: int, b: int, q: int, prec=None, ws=None):
@@ -417,6 +476,36 @@ class TProject(torch.autograd.Function):
             Om = Om.contiguous()
         dA = tsvd_proj_backward(A.detach().contiguous(), Om, G.contiguous(), ctx.b, ctx.q, ctx.prec)
         return dA, None, None, None, None
+
+
+class TApprox(torch.autograd.Function):
+    """A -> X_hat(A), the rank-k result of Alg. 2, with the hand-written
+    adjoint through the truncation; the Krylov blocks and the small SVD are
+    recomputed in backward from (A, Omega).  Omega: int seed or device tensor
+    (n2, b, n3)."""
+
+    @staticmethod
+    def forward(ctx, A, Omega, k, b, q, prec=None):
+        if _is_seed(Omega):
+            ctx.save_for_backward(A)
+            ctx.seed = int(Omega)
+        else:
+            ctx.save_for_backward(A, Omega)
+            ctx.seed = None
+        ctx.k, ctx.b, ctx.q, ctx.prec = k, b, q, prec
+        Om = Omega if ctx.seed is not None else Omega.contiguous()
+        return tsvd_rbk_approx(A.detach().contiguous(), Om, k, b, q, prec)[3]
+
+    @staticmethod
+    def backward(ctx, G):
+        if ctx.seed is not None:
+            (A,) = ctx.saved_tensors
+            Om = ctx.seed
+        else:
+            A, Om = ctx.saved_tensors
+            Om = Om.contiguous()
+        dA = tsvd_rbk_approx_backward(A.detach().contiguous(), Om, G.contiguous(), ctx.k, ctx.b, ctx.q, ctx.prec)
+        return dA, None, None, None, None, None
 
 
 # ---- kernel-level entry points (include/tsvd_rbk_diag.h) --------------------

@@ -60,6 +60,7 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
 }
 
 // Diagnostic counters kept at the start of the workspace.
-enum { INFO_CHOL_SHIFTED = 0, INFO_CHOL_BREAKDOWN = 1, INFO_EIG_NOCONV = 2, INFO_NONFINITE = 3, INFO_COUNT = 8 };
+enum { INFO_CHOL_SHIFTED = 0, INFO_CHOL_BREAKDOWN = 1, INFO_EIG_NOCONV = 2, INFO_NONFINITE = 3, INFO_TIE = 4,
+       INFO_COUNT = 8 };
 
 }  // namespace tsvd

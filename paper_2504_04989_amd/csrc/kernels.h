@@ -158,6 +158,13 @@ hipError_t masked_merge(const void* M, const unsigned char* mask, const void* X,
 // eigenpairs (lam1, W1: m x k per slice) kept per slice, with W1m = W1 whose
 // columns from J on are cleared; and the merge of the kept pairs with the
 // second pass's (lam2, W2) into lambda and W (m x k).
+// Adjoint through the rank-k truncation: per slice, S = N + N^H from
+// M (m x m, FP64 complex) and the descending eigenvalues lambda (m):
+// S_xy = (M_xy + conj(M_yx)) / (lambda_min(x,y) - lambda_max(x,y)) when
+// exactly one of x, y is below k, else 0.  A gap at or below
+// rel_tol * lambda_0 gives 0 there and counts in info[INFO_TIE].
+hipError_t gap_weights(const void* M, const double* lambda, int m, int k, int batch, double rel_tol, void* S,
+                       int* info, hipStream_t s);
 hipError_t tail_split(const double* lam1, const void* W1, void* W1m, int m, int k, int batch, double tau,
                       double min_ratio, int* J, hipStream_t s);
 hipError_t tail_merge(const double* lam1, const void* W1, const double* lam2, const void* W2, const int* J, int m,

@@ -232,6 +232,38 @@ hipError_t masked_merge(const void* M, const unsigned char* mask, const void* X,
   return hipGetLastError();
 }
 
+// Adjoint through the rank-k truncation: the eigenvector coupling across the
+// cut.  One thread per entry (x, y) of slice f.
+__global__ void gap_weights_kernel(const cx<double>* __restrict__ M, const double* __restrict__ lam, int m, int k,
+                                   int64_t total, double rel_tol, cx<double>* __restrict__ S, int* __restrict__ info) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int64_t per = (int64_t)m * m;
+  const int64_t f = t / per;
+  const int x = (int)((t - f * per) / m), y = (int)((t - f * per) % m);
+  cx<double> out{0.0, 0.0};
+  if ((x < k) != (y < k)) {
+    const double* l = lam + f * m;
+    const int a = x < y ? x : y, c = x < y ? y : x;  // a in the top k, c outside it
+    const double gap = l[a] - l[c];
+    if (gap > rel_tol * l[0]) {
+      const cx<double> mxy = M[t], myx = M[f * per + (int64_t)y * m + x];
+      out = cx<double>{(mxy.re + myx.re) / gap, (mxy.im - myx.im) / gap};
+    } else if (x < y) {
+      atomicAdd(&info[INFO_TIE], 1);
+    }
+  }
+  S[t] = out;
+}
+hipError_t gap_weights(const void* M, const double* lambda, int m, int k, int batch, double rel_tol, void* S,
+                       int* info, hipStream_t s) {
+  const int64_t total = (int64_t)batch * m * m;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(gap_weights_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     (const cx<double>*)M, lambda, m, k, total, rel_tol, (cx<double>*)S, info);
+  return hipGetLastError();
+}
+
 // Second pass of the FP64 small SVD.  tail_split: per slice, the number J of
 // leading eigenpairs of the first pass that are kept: the largest J < k with
 // lambda_{J-1} >= tau lambda_0 and lambda_{J-1} / lambda_J >= min_ratio (no

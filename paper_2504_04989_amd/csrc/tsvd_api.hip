@@ -62,6 +62,10 @@ struct Plan {
   size_t o_lam1, o_w1, o_w1m, o_p, o_t1, o_lam2, o_w2, o_rk, o_split;  // FP64 small SVD, second pass
   size_t o_omsp;  // the spatial test tensor drawn from the seed (n2 x b x n3, storage type)
   size_t o_xsplit;  // KM_BF16X3_SPLIT: the thin operand as (hi, lo) bf16 pairs
+  size_t o_vr, o_sr;  // truncated basis: spatial V and S of its Ritz step (scratch outputs)
+  // adjoint through the rank-k truncation: all eigenpairs of C C^H, four
+  // m x m FP64 matrices, the modified cotangents U2 Pi + T H and T Pi
+  size_t o_wall, o_lall, o_mm0, o_mm1, o_mm2, o_mm3, o_u2b, o_tp;
   size_t o_info, o_abar, o_obar, o_q, o_t, o_s0, o_s1, o_part, o_rinv, o_chol, o_lam, o_sig, o_wd, o_wds, o_heig,
       o_uf, o_vf, o_scx, o_us, o_gbar, o_dbar, o_wraw, o_qbar, o_u2, o_zbar, o_wbar, o_tbar, o_kpart, o_kpack,
       total;
@@ -164,7 +168,9 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   }
   if (b < 1 || q < 0) return fail(TSVD_EINVAL, "need b >= 1 and q >= 0");
   const bool power = op == TSVD_OP_POWER || op == TSVD_OP_POWER_APPROX;
-  if (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || power) {
+  const bool ritz = op == TSVD_OP_RBK_RITZ;
+  const bool abwd = op == TSVD_OP_APPROX_BWD;
+  if (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || power || ritz || abwd) {
     if (k < 1 || k > b) return fail(TSVD_EINVAL, "need 1 <= k <= b");
   } else {
     k = 1;
@@ -183,7 +189,9 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   if (!small_volume(n1, n2, n3)) return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
   if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32 && prec != TSVD_PREC_BF16 && prec != TSVD_PREC_BF16X3)
     return fail(TSVD_EINVAL, "unknown precision mode");
-  if (op < TSVD_OP_RBK || op > TSVD_OP_TPINV) return fail(TSVD_EINVAL, "unsupported operation");
+  if (op < TSVD_OP_RBK || op > TSVD_OP_APPROX_BWD || op == TSVD_OP_COMPLETE_RBK || op == TSVD_OP_COMPLETE_POWER ||
+      op == TSVD_OP_RBK_LITERAL)
+    return fail(TSVD_EINVAL, "unsupported operation");
   p->power = power;
   p->tensor_op = tensor_op;
   p->n1 = n1;
@@ -208,7 +216,8 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   // the split form of A_f where nothing but the Krylov products reads it (not
   // the projection and its adjoint) and the transform has the split epilogue
   p->asplit = p->kmode == KM_BF16X3 && p->dt == DT_F32 && fft_reg_supported((int)n3, DT_F32) &&
-              (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || op == TSVD_OP_POWER || op == TSVD_OP_POWER_APPROX);
+              (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || op == TSVD_OP_POWER || op == TSVD_OP_POWER_APPROX ||
+               ritz);
   int kc_unused;
   if (p->kmode != KM_BF16) {
     p->ks_ax = p->dt == DT_F32 ? kgemm_split((int)n1, (int)n2, (int)b, (int)F, &kc_unused) : 1;
@@ -257,34 +266,48 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
     if (tensor_op) {
       part = std::max(part, ogemm_tn_part_bytes((int)m, (int)n1, (int)n2, (int)F));
     }
+    if (ritz) part = std::max(part, ogemm_tn_part_bytes((int)b, (int)n2, (int)b, (int)F));
   }
+  if (ritz) part = std::max(part, (size_t)p->nsplit_t * F * b * b * 16);
   p->o_part = take(part);
   p->o_rinv = take((size_t)F * b * b * 16);
   p->o_chol = take(chol_uses_lds(b) ? 0 : (size_t)F * b * (b + 1) / 2 * 16);
-  const bool need_svd = (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || power);
-  p->o_lam = take(need_svd ? (size_t)F * k * 8 : 0);
-  p->o_sig = take(need_svd ? (size_t)F * k * 8 : 0);
-  p->o_wd = take(need_svd ? (size_t)F * m * k * 16 : 0);
-  p->o_wds = take(need_svd ? (size_t)F * m * k * 16 : 0);
-  p->o_heig = take(need_svd ? (size_t)F * heig_scratch_bytes((int)m, (int)k) : 0);
-  p->o_canon = take(need_svd ? canon_scratch_bytes(n1, (int)k, (int)F) : 0);
+  const bool need_svd = (op == TSVD_OP_RBK || op == TSVD_OP_APPROX || power || ritz);
+  const int64_t ks = ritz ? b : k;  // columns of the small SVD's buffers
+  p->o_lam = take(need_svd ? (size_t)F * ks * 8 : 0);
+  p->o_sig = take(need_svd ? (size_t)F * ks * 8 : 0);
+  p->o_wd = take(need_svd ? (size_t)F * m * ks * 16 : 0);
+  p->o_wds = take(need_svd ? (size_t)F * m * ks * 16 : 0);
+  p->o_heig = take(need_svd || abwd ? (size_t)F * heig_scratch_bytes((int)m, (int)(abwd ? m : ks)) : 0);
+  p->o_canon = take(need_svd ? canon_scratch_bytes(n1, (int)ks, (int)F) : 0);
   const bool pass2 = need_svd && p->dt == DT_F64;
-  p->o_lam1 = take(pass2 ? (size_t)F * k * 8 : 0);
-  p->o_w1 = take(pass2 ? (size_t)F * m * k * 16 : 0);
-  p->o_w1m = take(pass2 ? (size_t)F * m * k * 16 : 0);
-  p->o_p = take(pass2 ? (size_t)F * n2 * k * 16 : 0);
+  p->o_lam1 = take(pass2 ? (size_t)F * ks * 8 : 0);
+  p->o_w1 = take(pass2 ? (size_t)F * m * ks * 16 : 0);
+  p->o_w1m = take(pass2 ? (size_t)F * m * ks * 16 : 0);
+  p->o_p = take(pass2 ? (size_t)F * n2 * ks * 16 : 0);
   p->o_t1 = take(pass2 ? (size_t)F * n2 * m * 16 : 0);
-  p->o_lam2 = take(pass2 ? (size_t)F * k * 8 : 0);
-  p->o_w2 = take(pass2 ? (size_t)F * m * k * 16 : 0);
-  p->o_rk = take(pass2 ? (size_t)F * k * k * 16 : 0);
+  p->o_lam2 = take(pass2 ? (size_t)F * ks * 8 : 0);
+  p->o_w2 = take(pass2 ? (size_t)F * m * ks * 16 : 0);
+  p->o_rk = take(pass2 ? (size_t)F * ks * ks * 16 : 0);
   p->o_split = take(pass2 ? (size_t)F * 4 : 0);
-  p->o_uf = take(need_svd ? (size_t)F * n1 * k * cs : 0);
-  p->o_vf = take(need_svd ? (size_t)F * n2 * k * cs : 0);
-  p->o_scx = take(need_svd ? (size_t)F * k * cs : 0);
+  p->o_uf = take(need_svd ? (size_t)F * n1 * ks * cs : 0);
+  p->o_vf = take(need_svd ? (size_t)F * n2 * ks * cs : 0);
+  p->o_scx = take(need_svd ? (size_t)F * ks * cs : 0);
+  const size_t es0 = p->dt == DT_F64 ? 8 : 4;
+  p->o_vr = take(ritz ? (size_t)n2 * b * n3 * es0 : 0);
+  p->o_sr = take(ritz ? (size_t)b * n3 * es0 : 0);
+  p->o_wall = take(abwd ? (size_t)F * m * m * 16 : 0);
+  p->o_lall = take(abwd ? (size_t)F * m * 8 : 0);
+  p->o_mm0 = take(abwd ? (size_t)F * m * m * 16 : 0);
+  p->o_mm1 = take(abwd ? (size_t)F * m * m * 16 : 0);
+  p->o_mm2 = take(abwd ? (size_t)F * m * m * 16 : 0);
+  p->o_mm3 = take(abwd ? (size_t)F * m * m * 16 : 0);
+  p->o_u2b = take(abwd ? (size_t)F * n2 * m * cs : 0);
+  p->o_tp = take(abwd ? (size_t)F * n2 * m * cs : 0);
   p->o_us = take(op == TSVD_OP_APPROX || op == TSVD_OP_POWER_APPROX ? (size_t)F * n1 * k * cs : 0);
   p->o_rout = take(tensor_op ? (size_t)F * m * n2 * cs : 0);
   p->o_xp = take(0);
-  const bool bwd = op == TSVD_OP_PROJ_BWD;
+  const bool bwd = op == TSVD_OP_PROJ_BWD || abwd;
   p->o_gbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
   p->o_dbar = take(bwd ? (size_t)F * n1 * n2 * cs : 0);
   p->o_wraw = take(bwd ? (size_t)F * n1 * m * cs : 0);
@@ -1132,7 +1155,10 @@ int gemm(const Ctx& c, int cls, Op A, Op B, void* C, int64_t ldc, int64_t stride
 //   Wbar_i = (I - Q_<i Q_<i^H) Zbar_i, Qbar_<i -= (Zbar_i W_i^H + W_i Zbar_i^H) Q_<i,
 //   Abar += Wbar_i T_i^H, Tbar_i = A^H Wbar_i, Abar += Q_{i-1} Tbar_i^H,
 //   Qbar_{i-1} += A Tbar_i; for i = 0: Abar += Zbar_0 Om^H.
-int proj_backward_impl(const Ctx& c, const void* A, const void* Omega, const void* G, void* dA) {
+int truncation_head(const Ctx& c, void* U2, void* Ub2, void* Tp);
+
+int proj_backward_impl(const Ctx& c, const void* A, const void* Omega, const void* G, void* dA,
+                       bool truncated = false) {
   const Plan& p = c.p;
   const DType dt = p.dt;
   int r = krylov(c, A, Omega, true);
@@ -1156,18 +1182,27 @@ int proj_backward_impl(const Ctx& c, const void* A, const void* Omega, const voi
   void* Tb = c.at(p.o_tbar);
   double* part = c.at<double>(p.o_part);
   const size_t cs = p.cs;
-  // U2 = Gbar^H Q; Dbar = Q U2^H (= Q Q^H Gbar)
+  // U2 = Gbar^H Q (= Y^H, Y = Q^H Gbar); Dbar = Q U2^H (= Q Q^H Gbar)
   if ((r = gemm(c, K_GEMM_KRYLOV, Op{Gb, n2, s12, dt, true}, Op{Q, m, s1m, dt, false}, U2, m, s2m, dt, n2, m, n1, 1.0,
                 0.0, dt)))
     return r;
-  if ((r = gemm(c, K_GEMM_LIFT, Op{Q, m, s1m, dt, false}, Op{U2, m, s2m, dt, true}, Db, n2, s12, dt, n1, n2, m, 1.0,
+  // the rank-k truncation replaces U2 by Cbar^H = U2 Pi + T H and T by T Pi
+  // (truncation_head); the projection keeps them
+  void* Ub2 = U2;
+  void* Tq = T;
+  if (truncated) {
+    Ub2 = c.at(p.o_u2b);
+    Tq = c.at(p.o_tp);
+    if ((r = truncation_head(c, U2, Ub2, Tq))) return r;
+  }
+  if ((r = gemm(c, K_GEMM_LIFT, Op{Q, m, s1m, dt, false}, Op{Ub2, m, s2m, dt, true}, Db, n2, s12, dt, n1, n2, m, 1.0,
                 0.0, dt)))
     return r;
   // Qbar = Gbar T + Abar U2   (T = Abar^H Q)
-  if ((r = gemm(c, K_GEMM_KRYLOV, Op{Gb, n2, s12, dt, false}, Op{T, m, s2m, dt, false}, Qb, m, s1m, dt, n1, m, n2,
+  if ((r = gemm(c, K_GEMM_KRYLOV, Op{Gb, n2, s12, dt, false}, Op{Tq, m, s2m, dt, false}, Qb, m, s1m, dt, n1, m, n2,
                 1.0, 0.0, dt)))
     return r;
-  if ((r = gemm(c, K_GEMM_KRYLOV, Op{Ab, n2, s12, dt, false}, Op{U2, m, s2m, dt, false}, Qb, m, s1m, dt, n1, m, n2,
+  if ((r = gemm(c, K_GEMM_KRYLOV, Op{Ab, n2, s12, dt, false}, Op{Ub2, m, s2m, dt, false}, Qb, m, s1m, dt, n1, m, n2,
                 1.0, 1.0, dt)))
     return r;
   const int ns = p.nsplit_blk, kc = p.kchunk_blk;
@@ -1240,6 +1275,105 @@ int proj_backward_impl(const Ctx& c, const void* A, const void* Omega, const voi
     HIPCHK(fft_c2r(Db, s12, dA, s12, (int)p.n3, dt, c.s));
   }
   return TSVD_OK;
+}
+
+// Head of the adjoint through the rank-k truncation, X_f = Q Pi C with
+// C = Q^H A_f = T^H and Pi = W_k W_k^H the projector onto the top-k
+// eigenvectors of C C^H (Lemma mn38).  With Y = Q^H Gbar (U2 = Y^H):
+// Cbar = Pi Y + H C and Qbar = Gbar C^H Pi + A_f Cbar^H, where H = W S W^H,
+// S = N + N^H and N couples each eigenvector a of the top k with each c
+// outside it: N_ac = M_ac / (lambda_a - lambda_c), N_ca = M_ca / (lambda_a -
+// lambda_c), M = W^H (Y C^H) W.  Writes Ub2 = Cbar^H = U2 Pi + T H and
+// Tp = T Pi (n2 x m each, working type); every m x m matrix is FP64.
+int truncation_head(const Ctx& c, void* U2, void* Ub2, void* Tp) {
+  const Plan& p = c.p;
+  const DType dt = p.dt;
+  const int n2 = (int)p.n2, m = (int)p.m, k = (int)p.k;
+  const int64_t s2m = p.n2 * p.m, mm = p.m * p.m;
+  void* T = c.at(p.o_t);
+  double* part = c.at<double>(p.o_part);
+  double* lam = c.at<double>(p.o_lall);
+  void* W = c.at(p.o_wall);
+  void* M0 = c.at(p.o_mm0);
+  void* M1 = c.at(p.o_mm1);
+  void* M2 = c.at(p.o_mm2);
+  void* M3 = c.at(p.o_mm3);
+  // all m eigenpairs of C C^H = T^H T (descending)
+  const bool upper = dt == DT_F32;
+  int nsum = 1;
+  int r = inner_products(c, T, p.m, m, T, p.m, m, p.n2, s2m, s2m, p.nsplit_g, p.kchunk_g, part, &nsum, K_GEMM_LIFT,
+                         upper);
+  if (r) return r;
+  const int stage_cls[4][2] = {
+      {HEIG_TRIDIAG, K_HEIG_TRI}, {HEIG_BISECT, K_HEIG_BISECT}, {HEIG_INVIT, K_HEIG_INVIT}, {HEIG_BACKXF, K_HEIG_BACKXF}};
+  for (const auto& sc : stage_cls) {
+    Timed tm_(sc[1], c.s);
+    HIPCHK(heig_topk(part, nsum, p.F * mm, m, m, (int)p.F, lam, (double*)W, c.at(p.o_heig), c.info(), c.s, sc[0],
+                     upper));
+  }
+  // M = W^H (U2^H T) W
+  if ((r = gemm(c, K_GEMM_LIFT, Op{U2, p.m, s2m, dt, true}, Op{T, p.m, s2m, dt, false}, M0, p.m, mm, DT_F64, m, m, n2,
+                1.0, 0.0, DT_F64)))
+    return r;
+  if ((r = gemm(c, K_GEMM_LIFT, Op{M0, p.m, mm, DT_F64, false}, Op{W, p.m, mm, DT_F64, false}, M1, p.m, mm, DT_F64, m,
+                m, m, 1.0, 0.0, DT_F64)))
+    return r;
+  if ((r = gemm(c, K_GEMM_LIFT, Op{W, p.m, mm, DT_F64, true}, Op{M1, p.m, mm, DT_F64, false}, M2, p.m, mm, DT_F64, m,
+                m, m, 1.0, 0.0, DT_F64)))
+    return r;
+  // S = N + N^H (zero inside either group; a gap at the eigenvalues' rounding
+  // level counts as a tie), H = W S W^H
+  {
+    Timed tm_(K_MISC, c.s);
+    HIPCHK(gap_weights(M2, lam, m, k, (int)p.F, 8.0 * m * 0x1p-53, M0, c.info(), c.s));
+  }
+  if ((r = gemm(c, K_GEMM_LIFT, Op{W, p.m, mm, DT_F64, false}, Op{M0, p.m, mm, DT_F64, false}, M1, p.m, mm, DT_F64, m,
+                m, m, 1.0, 0.0, DT_F64)))
+    return r;
+  if ((r = gemm(c, K_GEMM_LIFT, Op{M1, p.m, mm, DT_F64, false}, Op{W, p.m, mm, DT_F64, true}, M3, p.m, mm, DT_F64, m,
+                m, m, 1.0, 0.0, DT_F64)))
+    return r;
+  // Pi = W_k W_k^H
+  if ((r = gemm(c, K_GEMM_LIFT, Op{W, p.m, mm, DT_F64, false}, Op{W, p.m, mm, DT_F64, true}, M2, p.m, mm, DT_F64, m,
+                m, k, 1.0, 0.0, DT_F64)))
+    return r;
+  // Ub2 = U2 Pi + T H; Tp = T Pi
+  if ((r = gemm(c, K_GEMM_LIFT, Op{U2, p.m, s2m, dt, false}, Op{M2, p.m, mm, DT_F64, false}, Ub2, p.m, s2m, dt, n2, m,
+                m, 1.0, 0.0, DT_F64)))
+    return r;
+  if ((r = gemm(c, K_GEMM_LIFT, Op{T, p.m, s2m, dt, false}, Op{M3, p.m, mm, DT_F64, false}, Ub2, p.m, s2m, dt, n2, m,
+                m, 1.0, 1.0, DT_F64)))
+    return r;
+  return gemm(c, K_GEMM_LIFT, Op{T, p.m, s2m, dt, false}, Op{M2, p.m, mm, DT_F64, false}, Tp, p.m, s2m, dt, n2, m, m,
+              1.0, 0.0, DT_F64);
+}
+
+// Alg. 2 with the basis truncated to its top b Ritz directions before the
+// projection (the timing remark of Sec. 5, Ex. 1, read as Rayleigh-Ritz):
+// Q_r = Q W_b (the lift of the first small SVD with b columns, phases as for
+// U), Qr = its inverse transform; then the projection with the truncated
+// basis, T_r = A_f^H Q_r (one b-column Krylov product), and the small SVD,
+// lift, truncation to k and inverse transforms of Alg. 2 on (Q_r, T_r).
+int ritz_body(const Ctx& c, const void* A, const void* Omega, void* Qr, void* U, void* S, void* V) {
+  const Plan& p = c.p;
+  int r = krylov(c, A, Omega);
+  if (r) return r;
+  // Ritz step: top-b eigenpairs of C C^H, Q_r = Q W_b into S0
+  Plan p1 = p;
+  p1.k = p.b;
+  p1.o_uf = p.o_s0;
+  Ctx c1{p1, c.ws, c.s};
+  if ((r = svd_and_lift(c1, Qr, c.at(p.o_sr), c.at(p.o_vr)))) return r;
+  // T_r = A_f^H Q_r (n2 x b, ld b) over T, which is no longer needed
+  if ((r = big_AhY(c, c.at(p.o_s0), p.b, p.n1 * p.b, c.at(p.o_t), p.b, p.n2 * p.b, (int)p.b))) return r;
+  // the small SVD of C_r = T_r^H with m = b
+  Plan p2 = p;
+  p2.m = p.b;
+  p2.o_q = p.o_s0;
+  p2.nsplit_g = p.nsplit_t;
+  p2.kchunk_g = p.kchunk_t;
+  Ctx c2{p2, c.ws, c.s};
+  return svd_and_lift(c2, U, S, V);
 }
 
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
@@ -1384,6 +1518,35 @@ int proj_backward_call(bool given, const void* A, const void* Omega, uint64_t se
   return TSVD_OK;
 }
 
+int approx_backward_call(bool given, const void* A, const void* Omega, uint64_t seed, const void* G, int64_t n1,
+                         int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, int prec, void* dA, void* ws,
+                         size_t ws_bytes, void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_APPROX_BWD, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, G, dA}, ws, ws_bytes, p))) return r;
+  if (given && (r = need_omega(Omega))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = resolve_omega(c, Omega, seed))) return r;
+  if ((r = proj_backward_impl(c, A, Omega, G, dA, true))) return r;
+  g_err.clear();
+  return TSVD_OK;
+}
+
+int ritz_call(bool given, const void* A, const void* Omega, uint64_t seed, int64_t n1, int64_t n2, int64_t n3,
+              int64_t k, int64_t b, int64_t q, int prec, void* Qr, void* U, void* S, void* V, void* ws, size_t ws_bytes,
+              void* stream) {
+  Plan p;
+  int r = make_plan(n1, n2, n3, k, b, q, prec, TSVD_OP_RBK_RITZ, &p);
+  if (r) return r;
+  if ((r = check_ptrs({A, Qr, U, S, V}, ws, ws_bytes, p))) return r;
+  if (given && (r = need_omega(Omega))) return r;
+  Ctx c{p, (unsigned char*)ws, (hipStream_t)stream};
+  if ((r = resolve_omega(c, Omega, seed))) return r;
+  if ((r = ritz_body(c, A, Omega, Qr, U, S, V))) return r;
+  g_err.clear();
+  return TSVD_OK;
+}
 
 // ---- scratch for the entry point that allocates nothing ----
 // A file-scope device array: each device the library runs on holds its own
@@ -1513,6 +1676,28 @@ int tsvd_rbk_literal_omega(const void* A, const void* Omega, int64_t n1, int64_t
                            int64_t q, int prec, void* U, void* S, void* V, void* Xhat, void* ws, size_t ws_bytes,
                            void* stream) {
   return svd_call(true, TSVD_OP_RBK_LITERAL, A, Omega, 0, n1, n2, n3, k, b, q, prec, U, S, V, Xhat, ws, ws_bytes, stream);
+}
+
+int tsvd_rbk_ritz(const void* A, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t q, uint64_t seed,
+                  int prec, void* Qr, void* U, void* S, void* V, void* ws, size_t ws_bytes, void* stream) {
+  return ritz_call(false, A, nullptr, seed, n1, n2, n3, k, b, q, prec, Qr, U, S, V, ws, ws_bytes, stream);
+}
+
+int tsvd_rbk_ritz_omega(const void* A, const void* Omega, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                        int64_t q, int prec, void* Qr, void* U, void* S, void* V, void* ws, size_t ws_bytes,
+                        void* stream) {
+  return ritz_call(true, A, Omega, 0, n1, n2, n3, k, b, q, prec, Qr, U, S, V, ws, ws_bytes, stream);
+}
+
+int tsvd_rbk_approx_backward(const void* A, const void* G, int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b,
+                             int64_t q, uint64_t seed, int prec, void* dA, void* ws, size_t ws_bytes, void* stream) {
+  return approx_backward_call(false, A, nullptr, seed, G, n1, n2, n3, k, b, q, prec, dA, ws, ws_bytes, stream);
+}
+
+int tsvd_rbk_approx_backward_omega(const void* A, const void* Omega, const void* G, int64_t n1, int64_t n2,
+                                   int64_t n3, int64_t k, int64_t b, int64_t q, int prec, void* dA, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  return approx_backward_call(true, A, Omega, 0, G, n1, n2, n3, k, b, q, prec, dA, ws, ws_bytes, stream);
 }
 
 int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec, void* Q, void* R, void* ws,
@@ -1690,11 +1875,13 @@ int tsvd_read_info(const void* ws, int32_t* info_host, void* stream) {
                                 (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return fail(TSVD_EHIP, hipGetErrorString(e));
-  if (info_host[TSVD_INFO_CHOL_BREAKDOWN] || info_host[TSVD_INFO_EIG_NOCONV] || info_host[TSVD_INFO_NONFINITE]) {
-    char msg[192];
+  if (info_host[TSVD_INFO_CHOL_BREAKDOWN] || info_host[TSVD_INFO_EIG_NOCONV] || info_host[TSVD_INFO_NONFINITE] ||
+      info_host[TSVD_INFO_TRUNCATION_TIE]) {
+    char msg[256];
     snprintf(msg, sizeof msg, "numerical failure on the device: %d Cholesky breakdowns, %d unconverged eigenvectors, "
-             "%d non-finite values", info_host[TSVD_INFO_CHOL_BREAKDOWN], info_host[TSVD_INFO_EIG_NOCONV],
-             info_host[TSVD_INFO_NONFINITE]);
+             "%d non-finite values, %d ties at the rank-k cut (derivative undefined)",
+             info_host[TSVD_INFO_CHOL_BREAKDOWN], info_host[TSVD_INFO_EIG_NOCONV], info_host[TSVD_INFO_NONFINITE],
+             info_host[TSVD_INFO_TRUNCATION_TIE]);
     return fail(TSVD_ENUMERIC, msg);
   }
   g_err.clear();

@@ -33,7 +33,7 @@ int main() {
   const int64_t small[] = {-1, 0, 1, 5, 110, 1024, 5000, (int64_t)1 << 40, INT64_MAX};
   const int precs[] = {-1, TSVD_PREC_F64, TSVD_PREC_F32, TSVD_PREC_BF16, TSVD_PREC_BF16X3, 99};
   size_t nonzero = 0, calls = 0;
-  for (int op = -1; op <= 12; ++op)
+  for (int op = -1; op <= 14; ++op)
     for (int prec : precs)
       for (int64_t n1 : dims)
         for (int64_t n2 : dims)
@@ -48,7 +48,7 @@ int main() {
   for (int64_t k : small)
     for (int64_t b : small)
       for (int64_t q : small)
-        for (int op = 0; op <= 10; ++op) {
+        for (int op = 0; op <= 12; ++op) {
           (void)tsvd_workspace_bytes(512, 300, 16, k, b, q, TSVD_PREC_F32, op);
           ++calls;
         }
@@ -103,6 +103,23 @@ int main() {
          TSVD_EINVAL);
   EXPECT(tsvd_proj(fake, 64, 64, 8, 0, 2, 1, TSVD_PREC_F32, fake, fake, 1 << 30, nul) == TSVD_EINVAL);
   EXPECT(tsvd_proj_backward(fake, nul, 64, 64, 8, 8, 2, 1, TSVD_PREC_F32, fake, fake, 1 << 30, nul) == TSVD_EINVAL);
+  EXPECT(tsvd_rbk_ritz(fake, 64, 64, 8, 9, 8, 2, 1, TSVD_PREC_F32, fake, fake, fake, fake, fake, 1 << 30, nul) ==
+         TSVD_EINVAL);
+  EXPECT(tsvd_rbk_ritz(fake, 64, 64, 8, 5, 8, 2, 1, TSVD_PREC_F32, nul, fake, fake, fake, fake, 1 << 30, nul) ==
+         TSVD_EINVAL);
+  EXPECT(tsvd_rbk_ritz_omega(fake, nul, 64, 64, 8, 5, 8, 2, TSVD_PREC_F32, fake, fake, fake, fake, fake, 1 << 30,
+                             nul) == TSVD_EINVAL);
+  EXPECT(tsvd_rbk_approx_backward(fake, nul, 64, 64, 8, 5, 8, 2, 1, TSVD_PREC_F32, fake, fake, 1 << 30, nul) ==
+         TSVD_EINVAL);
+  EXPECT(tsvd_rbk_approx_backward(fake, fake, 64, 64, 8, 0, 8, 2, 1, TSVD_PREC_F32, fake, fake, 1 << 30, nul) ==
+         TSVD_EINVAL);
+  EXPECT(tsvd_rbk_approx_backward(fake, fake, 64, 64, 8, 5, 8, 2, 1, TSVD_PREC_F32, fake, fake, 16, nul) ==
+         TSVD_ENOMEM);
+  EXPECT(tsvd_rbk_approx_backward_omega(fake, nul, fake, 64, 64, 8, 5, 8, 2, TSVD_PREC_F32, fake, fake, 1 << 30,
+                                        nul) == TSVD_EINVAL);
+  EXPECT(tsvd_workspace_bytes(4096, 4096, 64, 100, 110, 3, TSVD_PREC_F32, TSVD_OP_APPROX_BWD) >
+         tsvd_workspace_bytes(4096, 4096, 64, 100, 110, 3, TSVD_PREC_F32, TSVD_OP_PROJ_BWD));
+  EXPECT(tsvd_workspace_bytes(64, 64, 8, 5, 8, 2, TSVD_PREC_F32, 13) == 0);
   EXPECT(tsvd_read_info(nul, nullptr, nul) == TSVD_EINVAL);
   EXPECT(strlen(tsvd_last_error()) > 0);
 
