@@ -1011,6 +1011,282 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
   }
 }
 
+// Register-resident form for several co-resident workgroups per slice.  The
+// 32 x 32 tiles of the lower triangle are dealt out once: tile t (row-major
+// over the triangle) belongs to workgroup t mod P, and within it to wave
+// (t / P) mod 8, slot (t / P) / 8 (at most RES_SLOTS per wave).  A wave keeps
+// its tiles in registers for the whole reduction, in the 4 x 4 lane blocks of
+// symv_block, so the trailing matrix is never read from or written to memory:
+// every step applies the rank-2 update of the previous reflector in place.
+// Per step i, one exchange between the workgroups of the slice:
+//   - every workgroup adds its share of y = A_tr v (fixed point, as above) into
+//     one slice-wide sum with agent-scope integer atomics, which are exact and
+//     order-free, so y is the same in every workgroup and bit for bit the same
+//     from run to run;
+//   - the owners of column i + 1 publish it as it stands before this step's
+//     update; after the exchange every workgroup applies the update to that one
+//     column itself, so the next reflector needs no second exchange.
+// The reflectors, w and the column update are repeated identically in every
+// workgroup (same operands, same operations).  Sums and columns rotate through
+// three buffers, so a buffer is cleared or rewritten only after every
+// workgroup has passed the exchange that last read it.
+constexpr int RES_SLOTS = 2;
+
+__global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __restrict__ Gpart, int nsum,
+                                                            int64_t part_stride, int m, int MP,
+                                                            unsigned char* scratch, size_t per_slice, int upper_only,
+                                                            int P, int* __restrict__ info) {
+  __shared__ cx<double> col[1024];    // column i (rows >= i), replicated
+  __shared__ cx<double> vcur[1024];   // v of the step (0 outside rows i + 1 .. m - 1)
+  __shared__ cx<double> wv_[1024];    // w of the step (0 outside)
+  __shared__ unsigned long long yq[2 * 1024];  // this workgroup's share of y, fixed point
+  __shared__ double red[2 * T2_W];
+  __shared__ cx<double> s_tau, s_scale;
+  __shared__ int s_skip;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int f = blockIdx.x / P, pg = blockIdx.x - f * P;
+  const bool lead = pg == 0;
+  const HeigView hv = heig_view(scratch, per_slice, f, m);
+  cx<double>* Vout = hv.A;  // row i receives v_i (read by the back-transformation)
+  unsigned* ctr = hv.sync;
+  unsigned gen = 0;
+  const double fsc = tri_fix_scale(hv, m);
+  const double to_fix = ldexp(1.0, 62) / fsc, from_fix = fsc * ldexp(1.0, -62);
+  // exchange buffers: three fixed-point sums (2 u64 per row) and three columns
+  unsigned long long* ysum = reinterpret_cast<unsigned long long*>(hv.ypg);
+  cx<double>* colx = hv.ypg + 3 * MP;
+  const int T = MP / 32, NT = T * (T + 1) / 2;
+  const int la = lane >> 3, lb = lane & 7;
+  const cx<double>* G = Gpart + (int64_t)f * m * m;
+  auto gram = [&](int r, int c) {  // A(r, c), r >= c, from the partials
+    cx<double> g{0, 0}, h{0, 0};
+    for (int s = 0; s < nsum; ++s) {
+      const cx<double>* Gs = G + s * part_stride;
+      const cx<double> x = Gs[(int64_t)r * m + c], y = Gs[(int64_t)c * m + r];
+      g.re += x.re;
+      g.im += x.im;
+      h.re += y.re;
+      h.im += y.im;
+    }
+    return upper_only ? cx<double>{h.re, r == c ? 0.0 : -h.im}
+                      : cx<double>{0.5 * (g.re + h.re), r == c ? 0.0 : 0.5 * (g.im - h.im)};
+  };
+  // this wave's tiles
+  int tI[RES_SLOTS], tJ[RES_SLOTS];
+  bool tok[RES_SLOTS];
+  cx<double> a[RES_SLOTS][4][4];
+#pragma unroll
+  for (int sl = 0; sl < RES_SLOTS; ++sl) {
+    const int t = (sl * T2_W + wv) * P + pg;
+    tok[sl] = t < NT;
+    tri_tile(tok[sl] ? t : 0, 0, tI[sl], tJ[sl]);
+    const int r0 = 32 * tI[sl] + 4 * la, c0 = 32 * tJ[sl] + lb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int r = r0 + q, c = c0 + 8 * p;
+        a[sl][q][p] = (tok[sl] && r < m && c <= r) ? gram(r, c) : cx<double>{0, 0};
+      }
+  }
+  for (int r = tid; r < MP; r += T2_NT) {
+    col[r] = r < m ? gram(r, 0) : cx<double>{0, 0};
+    vcur[r] = wv_[r] = cx<double>{0, 0};
+    yq[2 * r] = yq[2 * r + 1] = 0ull;
+    if (lead) {
+      __hip_atomic_store(&ysum[2 * r], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ysum[2 * r + 1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  group_sync_coherent(ctr, gen, P, info);
+
+  for (int i = 0; i < m - 1; ++i) {
+    const int buf = i % 3;
+    unsigned long long* ys = ysum + (int64_t)buf * 2 * MP;
+    cx<double>* cxb = colx + (int64_t)buf * MP;
+    // (1) reflector from alpha = col[i + 1], x = col[i + 2 .. m - 1] (every workgroup)
+    double s2 = 0;
+    for (int r = i + 2 + tid; r < m; r += T2_NT) s2 += col[r].re * col[r].re + col[r].im * col[r].im;
+    s2 = block_sum2(cx<double>{s2, 0.0}, red).re;
+    if (tid == 0) {
+      const double ar = col[i + 1].re, ai = col[i + 1].im;
+      double ei;
+      if (s2 == 0.0 && ai == 0.0) {
+        s_skip = 1;
+        ei = ar;
+        s_tau = cx<double>{0, 0};
+      } else {
+        s_skip = 0;
+        const double beta = -copysign(sqrt(ar * ar + ai * ai + s2), ar);
+        s_tau = cx<double>{(beta - ar) / beta, -ai / beta};
+        const double dr = ar - beta, di = ai;
+        const double den = dr * dr + di * di;
+        s_scale = cx<double>{dr / den, -di / den};
+        ei = beta;
+      }
+      if (lead) {
+        hv.d[i] = col[i].re;
+        hv.e[i] = ei;
+        hv.tau[i] = s_tau;
+      }
+    }
+    __syncthreads();
+    const bool skip = s_skip != 0;
+    const cx<double> tau = s_tau, scale = s_scale;
+    for (int r = tid; r < MP; r += T2_NT) {
+      cx<double> v{0, 0};
+      if (r == i + 1)
+        v = cx<double>{1.0, 0.0};
+      else if (r > i + 1 && r < m && !skip)
+        v = cmulc(col[r], scale);
+      vcur[r] = v;
+      if (lead && r > i && r < m) Vout[(int64_t)i * m + r] = v;
+      yq[2 * r] = yq[2 * r + 1] = 0ull;
+    }
+    __syncthreads();
+    // (2) this workgroup's share of y = A_tr v over its resident tiles
+    const int J0 = (i + 1) >> 5;
+#pragma unroll
+    for (int sl = 0; sl < RES_SLOTS; ++sl) {
+      if (tok[sl] && tJ[sl] >= J0) {
+        const int r0 = 32 * tI[sl] + 4 * la, c0 = 32 * tJ[sl] + lb;
+        cx<double> yR[4], yC[4];
+        if (tI[sl] > tJ[sl] && 32 * tJ[sl] >= i + 1 && 32 * tI[sl] + 32 <= m)
+          symv_block<false>(a[sl], vcur, r0, c0, m, i + 1, yR, yC);
+        else
+          symv_block<true>(a[sl], vcur, r0, c0, m, i + 1, yR, yC);
+        const cx<double> sr = reduce4<4, 2, 1>(yR, lane);
+        const cx<double> sc = reduce4<32, 16, 8>(yC, lane);
+        auto fix = [&](double x) { return (unsigned long long)(long long)rint(x * to_fix); };
+        if (!(lane & 1)) {
+          const int q = ((lane >> 2) & 1) * 2 + ((lane >> 1) & 1);
+          atomicAdd(&yq[2 * (r0 + q)], fix(sr.re));
+          atomicAdd(&yq[2 * (r0 + q) + 1], fix(sr.im));
+        }
+        if (!(la & 1)) {
+          const int p = ((la >> 2) & 1) * 2 + ((la >> 1) & 1);
+          atomicAdd(&yq[2 * (c0 + 8 * p)], fix(sc.re));
+          atomicAdd(&yq[2 * (c0 + 8 * p) + 1], fix(sc.im));
+        }
+      }
+    }
+    // column i + 1 as it stands before this step's update, from its owners
+    const int Jn = (i + 1) >> 5;
+#pragma unroll
+    for (int sl = 0; sl < RES_SLOTS; ++sl) {
+      if (tok[sl] && tJ[sl] == Jn) {
+        const int r0 = 32 * tI[sl] + 4 * la, c0 = 32 * tJ[sl] + lb;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          if (c0 + 8 * p != i + 1) continue;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = r0 + q;
+            if (r >= i + 1 && r < m) {
+              double* d = reinterpret_cast<double*>(cxb + r);
+              __hip_atomic_store(d, a[sl][q][p].re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(d + 1, a[sl][q][p].im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // (3) add the share into the slice-wide sum; clear the sum of step i + 1
+    unsigned long long* ysn = ysum + (int64_t)((i + 1) % 3) * 2 * MP;
+    for (int r = i + 1 + tid; r < m; r += T2_NT) {
+      const unsigned long long qr = yq[2 * r], qi = yq[2 * r + 1];
+      if (qr) __hip_atomic_fetch_add(&ys[2 * r], qr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (qi) __hip_atomic_fetch_add(&ys[2 * r + 1], qi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lead)
+      for (int r = i + 2 + tid; r < m; r += T2_NT) {
+        __hip_atomic_store(&ysn[2 * r], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ysn[2 * r + 1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    group_sync_coherent(ctr, gen, P, info);
+    // (4) y, then w = tau y + alpha v with alpha = -tau (w^H v) / 2 (rows i+1..m-1)
+    cx<double> wl[2], cn[2];
+    cx<double> dot{0, 0};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = i + 1 + tid + u * T2_NT;
+      wl[u] = cn[u] = cx<double>{0, 0};
+      if (r < m) {
+        const long long qr = (long long)__hip_atomic_load(&ys[2 * r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const long long qi = (long long)__hip_atomic_load(&ys[2 * r + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double* d = reinterpret_cast<const double*>(cxb + r);
+        cn[u] = cx<double>{__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                           __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+        const cx<double> yy{(double)qr * from_fix, (double)qi * from_fix};
+        wl[u] = cmulc(tau, yy);
+        cfmac(dot, wl[u], vcur[r]);
+      }
+    }
+    dot = block_sum2(dot, red);
+    const cx<double> alpha = cmulc(cx<double>{-0.5 * tau.re, -0.5 * tau.im}, dot);
+    const bool zero = tau.re == 0.0 && tau.im == 0.0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = i + 1 + tid + u * T2_NT;
+      if (r < m) {
+        cx<double> w = wl[u];
+        cfma(w, alpha, vcur[r]);
+        wv_[r] = zero ? cx<double>{0, 0} : w;
+      }
+    }
+    __syncthreads();
+    // (5) A -= v w^H + w v^H on the resident tiles (v and w vanish outside the
+    // trailing rows, so the finished rows and columns are left as they are)
+#pragma unroll
+    for (int sl = 0; sl < RES_SLOTS; ++sl) {
+      if (tok[sl] && tJ[sl] >= J0) {
+        const int r0 = 32 * tI[sl] + 4 * la, c0 = 32 * tJ[sl] + lb;
+        cx<double> vc[4], wc[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          vc[p] = vcur[c0 + 8 * p];
+          wc[p] = wv_[c0 + 8 * p];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const cx<double> vr = vcur[r0 + q], wr = wv_[r0 + q];
+          const cx<double> nv{-vr.re, -vr.im}, nw{-wr.re, -wr.im};
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            cfmac(a[sl][q][p], wc[p], nv);
+            cfmac(a[sl][q][p], vc[p], nw);
+          }
+        }
+      }
+    }
+    // (6) column i + 1 after this step's update, in every workgroup
+    const cx<double> vi = vcur[i + 1], wi = wv_[i + 1];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = i + 1 + tid + u * T2_NT;
+      if (r < m) {
+        cx<double> x = cn[u];
+        const cx<double> nv{-vcur[r].re, -vcur[r].im}, nw{-wv_[r].re, -wv_[r].im};
+        cfmac(x, wi, nv);
+        cfmac(x, vi, nw);
+        if (r == i + 1) x.im = 0.0;
+        col[r] = x;
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < MP; r += T2_NT) {
+      vcur[r] = cx<double>{0, 0};
+      wv_[r] = cx<double>{0, 0};
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && lead) {
+    hv.d[m - 1] = col[m - 1].re;
+    hv.e[m - 1] = 0.0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 2. eigenvalues by multisection (one wave per eigenvalue)
 // ---------------------------------------------------------------------------
@@ -1575,7 +1851,19 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
     unsigned char* sc_a = sc;
     size_t per_a = per;
     int* info_a = info;
-    if (P > 1) {
+    // the register-resident form when the slice's tiles fit RES_SLOTS per wave
+    const int NTt = (MP / 32) * (MP / 32 + 1) / 2;
+    bool done = false;
+    if (P > 1 && MP <= 1024 && NTt <= RES_SLOTS * T2_W * P) {
+      void* args[] = {(void*)&G, (void*)&nsum_a, (void*)&ps, (void*)&m_a, (void*)&mp_a, (void*)&sc_a, (void*)&per_a,
+                      (void*)&up, (void*)&P, (void*)&info_a};
+      if (hipLaunchCooperativeKernel((const void*)heig_trires_kernel, dim3(batch * P), dim3(T2_NT), args, 0, s) ==
+          hipSuccess)
+        done = true;
+      else
+        (void)hipGetLastError();  // not co-resident: the streaming form below
+    }
+    if (!done && P > 1) {
       void* args[] = {(void*)&G, (void*)&nsum_a, (void*)&ps, (void*)&m_a, (void*)&mp_a, (void*)&sc_a, (void*)&per_a,
                       (void*)&up, (void*)&P, (void*)&info_a};
       if (hipLaunchCooperativeKernel(fn, dim3(batch * P), dim3(T2_NT), args, (unsigned)sm, s) != hipSuccess) {

@@ -23,8 +23,14 @@ def _gram(batch, m, seed, decay):
     return out
 
 
-@pytest.mark.parametrize("m,k,batch", [(1, 1, 2), (2, 1, 3), (37, 10, 3), (120, 30, 5), (440, 100, 3)])
+# m >= 256 with several workgroups per slice: the register-resident
+# tridiagonalisation while the slice's tiles fit (440 / 448 over 33 slices is
+# the 4096 x 4096 x 64 workload's shape; 256 and 300 exact and ragged tile
+# counts), the streaming form beyond it (600 over 33 slices)
+@pytest.mark.parametrize("m,k,batch", [(1, 1, 2), (2, 1, 3), (37, 10, 3), (120, 30, 5), (440, 100, 3),
+                                       (256, 60, 33), (300, 64, 7), (440, 100, 33), (448, 90, 33), (600, 50, 33)])
 def test_heig_vs_lapack(m, k, batch):
+    print(f"[heig] m={m} k={k} batch={batch}", flush=True)
     G = _gram(batch, m, seed=m, decay=1.5)
     lam, W, info = api.diag_heig(torch.tensor(G, device="cuda"), k)
     lam, W = host(lam), host(W)
@@ -58,3 +64,13 @@ def test_heig_clustered_and_degenerate():
         R = G[f] @ W[f] - W[f] * lam[f]
         assert np.max(np.linalg.norm(R, axis=0)) <= 1e-11
         assert np.max(np.abs(W[f].conj().T @ W[f] - np.eye(k))) <= 1e-10
+
+
+def test_heig_repeats_bit_for_bit():
+    """Two calls on the same matrices give the same eigenpairs bit for bit
+    (the tridiagonalisation's sums are exact integer sums), at the 4096 x 4096
+    x 64 workload's shape (m = 440 over 33 slices)."""
+    G = torch.tensor(_gram(33, 440, seed=5, decay=1.5), device="cuda")
+    l1, W1, _ = api.diag_heig(G, 100)
+    l2, W2, _ = api.diag_heig(G, 100)
+    assert torch.equal(l1, l2) and torch.equal(W1, W2)
