@@ -469,6 +469,7 @@ __device__ __forceinline__ void cfmac(cx<double>& a, cx<double> x, cx<double> y)
   a.im = fma(x.re, y.im, fma(-x.im, y.re, a.im));
 }
 
+template <int NW = T2_W>
 __device__ __forceinline__ cx<double> block_sum2(cx<double> v, double* red) {
   v.re = wave_sum(v.re);
   v.im = wave_sum(v.im);
@@ -481,7 +482,7 @@ __device__ __forceinline__ cx<double> block_sum2(cx<double> v, double* red) {
   __syncthreads();
   cx<double> r{0, 0};
 #pragma unroll
-  for (int i = 0; i < T2_W; ++i) {
+  for (int i = 0; i < NW; ++i) {
     r.re += red[2 * i];
     r.im += red[2 * i + 1];
   }
@@ -1014,7 +1015,7 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
 // Register-resident form for several co-resident workgroups per slice.  The
 // 32 x 32 tiles of the lower triangle are dealt out once: tile t (row-major
 // over the triangle) belongs to workgroup t mod P, and within it to wave
-// (t / P) mod 8, slot (t / P) / 8 (at most RES_SLOTS per wave).  A wave keeps
+// (t / P) mod RES_W, slot (t / P) / RES_W (at most RES_SLOTS per wave).  A wave keeps
 // its tiles in registers for the whole reduction, in the 4 x 4 lane blocks of
 // symv_block, so the trailing matrix is never read from or written to memory:
 // every step applies the rank-2 update of the previous reflector in place.
@@ -1030,9 +1031,48 @@ __global__ __launch_bounds__(T2_NT) void heig_tri2_kernel(const cx<double>* __re
 // workgroup (same operands, same operations).  Sums and columns rotate through
 // three buffers, so a buffer is cleared or rewritten only after every
 // workgroup has passed the exchange that last read it.
-constexpr int RES_SLOTS = 2;
+// Four waves per workgroup, one per SIMD, so that each may hold up to 512
+// registers (the tiles that do not fit the 256 vector registers sit in the
+// accumulation registers); four tile slots per wave.
+constexpr int RES_NT = 256;
+constexpr int RES_W = RES_NT / 64;
+constexpr int RES_SLOTS = 4;
 
-__global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __restrict__ Gpart, int nsum,
+// symv_block for the resident tiles with fewer live registers: the column
+// operand is read once, the row operand one row of the lane block at a time.
+template <bool MASK>
+__device__ __forceinline__ void symv_res(const cx<double> (&a)[4][4], const cx<double>* vcur, int r0, int c0, int m,
+                                         int cmin, cx<double> (&yR)[4], cx<double> (&yC)[4]) {
+  cx<double> vc[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    vc[p] = vcur[c0 + 8 * p];
+    yC[p] = cx<double>{0, 0};
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const cx<double> vr = vcur[r0 + q];
+    yR[q] = cx<double>{0, 0};
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      cx<double> x = a[q][p];
+      if (MASK) {
+        const int r = r0 + q, c = c0 + 8 * p;
+        const bool ok = r < m && c >= cmin && r >= c;
+        if (!ok) x = cx<double>{0, 0};
+        if (r == c) x.im = 0.0;
+        cfma(yR[q], x, vc[p]);
+        if (r == c) x = cx<double>{0, 0};
+        cfmac(yC[p], x, vr);
+      } else {
+        cfma(yR[q], x, vc[p]);
+        cfmac(yC[p], x, vr);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(RES_NT, 1) void heig_trires_kernel(const cx<double>* __restrict__ Gpart, int nsum,
                                                             int64_t part_stride, int m, int MP,
                                                             unsigned char* scratch, size_t per_slice, int upper_only,
                                                             int P, int* __restrict__ info) {
@@ -1040,9 +1080,7 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
   __shared__ cx<double> vcur[1024];   // v of the step (0 outside rows i + 1 .. m - 1)
   __shared__ cx<double> wv_[1024];    // w of the step (0 outside)
   __shared__ unsigned long long yq[2 * 1024];  // this workgroup's share of y, fixed point
-  __shared__ double red[2 * T2_W];
-  __shared__ cx<double> s_tau, s_scale;
-  __shared__ int s_skip;
+  __shared__ double red[2 * RES_W];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int f = blockIdx.x / P, pg = blockIdx.x - f * P;
   const bool lead = pg == 0;
@@ -1077,7 +1115,7 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
   cx<double> a[RES_SLOTS][4][4];
 #pragma unroll
   for (int sl = 0; sl < RES_SLOTS; ++sl) {
-    const int t = (sl * T2_W + wv) * P + pg;
+    const int t = (sl * RES_W + wv) * P + pg;
     tok[sl] = t < NT;
     tri_tile(tok[sl] ? t : 0, 0, tI[sl], tJ[sl]);
     const int r0 = 32 * tI[sl] + 4 * la, c0 = 32 * tJ[sl] + lb;
@@ -1089,7 +1127,7 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
         a[sl][q][p] = (tok[sl] && r < m && c <= r) ? gram(r, c) : cx<double>{0, 0};
       }
   }
-  for (int r = tid; r < MP; r += T2_NT) {
+  for (int r = tid; r < MP; r += RES_NT) {
     col[r] = r < m ? gram(r, 0) : cx<double>{0, 0};
     vcur[r] = wv_[r] = cx<double>{0, 0};
     yq[2 * r] = yq[2 * r + 1] = 0ull;
@@ -1106,40 +1144,34 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
     cx<double>* cxb = colx + (int64_t)buf * MP;
     // (1) reflector from alpha = col[i + 1], x = col[i + 2 .. m - 1] (every workgroup)
     double s2 = 0;
-    for (int r = i + 2 + tid; r < m; r += T2_NT) s2 += col[r].re * col[r].re + col[r].im * col[r].im;
-    s2 = block_sum2(cx<double>{s2, 0.0}, red).re;
-    if (tid == 0) {
-      const double ar = col[i + 1].re, ai = col[i + 1].im;
-      double ei;
-      if (s2 == 0.0 && ai == 0.0) {
-        s_skip = 1;
-        ei = ar;
-        s_tau = cx<double>{0, 0};
-      } else {
-        s_skip = 0;
-        const double beta = -copysign(sqrt(ar * ar + ai * ai + s2), ar);
-        s_tau = cx<double>{(beta - ar) / beta, -ai / beta};
-        const double dr = ar - beta, di = ai;
-        const double den = dr * dr + di * di;
-        s_scale = cx<double>{dr / den, -di / den};
-        ei = beta;
-      }
-      if (lead) {
-        hv.d[i] = col[i].re;
-        hv.e[i] = ei;
-        hv.tau[i] = s_tau;
-      }
+    for (int r = i + 2 + tid; r < m; r += RES_NT) s2 += col[r].re * col[r].re + col[r].im * col[r].im;
+    s2 = block_sum2<RES_W>(cx<double>{s2, 0.0}, red).re;
+    // every thread forms the same reflector from the same operands
+    const double ar = col[i + 1].re, ai = col[i + 1].im;
+    const bool skip = s2 == 0.0 && ai == 0.0;
+    cx<double> tau{0, 0}, scale{0, 0};
+    double ei = ar;
+    if (!skip) {
+      const double beta = -copysign(sqrt(ar * ar + ai * ai + s2), ar);
+      tau = cx<double>{(beta - ar) / beta, -ai / beta};
+      const double dr = ar - beta, di = ai;
+      const double den = dr * dr + di * di;
+      scale = cx<double>{dr / den, -di / den};
+      ei = beta;
     }
-    __syncthreads();
-    const bool skip = s_skip != 0;
-    const cx<double> tau = s_tau, scale = s_scale;
-    for (int r = tid; r < MP; r += T2_NT) {
+    if (lead && tid == 0) {
+      hv.d[i] = col[i].re;
+      hv.e[i] = ei;
+      hv.tau[i] = tau;
+    }
+    for (int r = tid; r < MP; r += RES_NT) {
       cx<double> v{0, 0};
       if (r == i + 1)
         v = cx<double>{1.0, 0.0};
       else if (r > i + 1 && r < m && !skip)
         v = cmulc(col[r], scale);
       vcur[r] = v;
+      wv_[r] = cx<double>{0, 0};
       if (lead && r > i && r < m) Vout[(int64_t)i * m + r] = v;
       yq[2 * r] = yq[2 * r + 1] = 0ull;
     }
@@ -1152,9 +1184,9 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
         const int r0 = 32 * tI[sl] + 4 * la, c0 = 32 * tJ[sl] + lb;
         cx<double> yR[4], yC[4];
         if (tI[sl] > tJ[sl] && 32 * tJ[sl] >= i + 1 && 32 * tI[sl] + 32 <= m)
-          symv_block<false>(a[sl], vcur, r0, c0, m, i + 1, yR, yC);
+          symv_res<false>(a[sl], vcur, r0, c0, m, i + 1, yR, yC);
         else
-          symv_block<true>(a[sl], vcur, r0, c0, m, i + 1, yR, yC);
+          symv_res<true>(a[sl], vcur, r0, c0, m, i + 1, yR, yC);
         const cx<double> sr = reduce4<4, 2, 1>(yR, lane);
         const cx<double> sc = reduce4<32, 16, 8>(yC, lane);
         auto fix = [&](double x) { return (unsigned long long)(long long)rint(x * to_fix); };
@@ -1194,13 +1226,13 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
     __syncthreads();
     // (3) add the share into the slice-wide sum; clear the sum of step i + 1
     unsigned long long* ysn = ysum + (int64_t)((i + 1) % 3) * 2 * MP;
-    for (int r = i + 1 + tid; r < m; r += T2_NT) {
+    for (int r = i + 1 + tid; r < m; r += RES_NT) {
       const unsigned long long qr = yq[2 * r], qi = yq[2 * r + 1];
       if (qr) __hip_atomic_fetch_add(&ys[2 * r], qr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (qi) __hip_atomic_fetch_add(&ys[2 * r + 1], qi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (lead)
-      for (int r = i + 2 + tid; r < m; r += T2_NT) {
+      for (int r = i + 2 + tid; r < m; r += RES_NT) {
         __hip_atomic_store(&ysn[2 * r], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&ysn[2 * r + 1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -1210,7 +1242,7 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
     cx<double> dot{0, 0};
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int r = i + 1 + tid + u * T2_NT;
+      const int r = i + 1 + tid + u * RES_NT;
       wl[u] = cn[u] = cx<double>{0, 0};
       if (r < m) {
         const long long qr = (long long)__hip_atomic_load(&ys[2 * r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1223,12 +1255,12 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
         cfmac(dot, wl[u], vcur[r]);
       }
     }
-    dot = block_sum2(dot, red);
+    dot = block_sum2<RES_W>(dot, red);
     const cx<double> alpha = cmulc(cx<double>{-0.5 * tau.re, -0.5 * tau.im}, dot);
     const bool zero = tau.re == 0.0 && tau.im == 0.0;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int r = i + 1 + tid + u * T2_NT;
+      const int r = i + 1 + tid + u * RES_NT;
       if (r < m) {
         cx<double> w = wl[u];
         cfma(w, alpha, vcur[r]);
@@ -1264,7 +1296,7 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
     const cx<double> vi = vcur[i + 1], wi = wv_[i + 1];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int r = i + 1 + tid + u * T2_NT;
+      const int r = i + 1 + tid + u * RES_NT;
       if (r < m) {
         cx<double> x = cn[u];
         const cx<double> nv{-vcur[r].re, -vcur[r].im}, nw{-wv_[r].re, -wv_[r].im};
@@ -1273,11 +1305,6 @@ __global__ __launch_bounds__(T2_NT) void heig_trires_kernel(const cx<double>* __
         if (r == i + 1) x.im = 0.0;
         col[r] = x;
       }
-    }
-    __syncthreads();
-    for (int r = tid; r < MP; r += T2_NT) {
-      vcur[r] = cx<double>{0, 0};
-      wv_[r] = cx<double>{0, 0};
     }
     __syncthreads();
   }
@@ -1854,10 +1881,10 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
     // the register-resident form when the slice's tiles fit RES_SLOTS per wave
     const int NTt = (MP / 32) * (MP / 32 + 1) / 2;
     bool done = false;
-    if (P > 1 && MP <= 1024 && NTt <= RES_SLOTS * T2_W * P) {
+    if (P > 1 && MP <= 2 * RES_NT && NTt <= RES_SLOTS * RES_W * P) {
       void* args[] = {(void*)&G, (void*)&nsum_a, (void*)&ps, (void*)&m_a, (void*)&mp_a, (void*)&sc_a, (void*)&per_a,
                       (void*)&up, (void*)&P, (void*)&info_a};
-      if (hipLaunchCooperativeKernel((const void*)heig_trires_kernel, dim3(batch * P), dim3(T2_NT), args, 0, s) ==
+      if (hipLaunchCooperativeKernel((const void*)heig_trires_kernel, dim3(batch * P), dim3(RES_NT), args, 0, s) ==
           hipSuccess)
         done = true;
       else
