@@ -64,13 +64,15 @@ def test_seed_call_matches_oracle_and_omega_call(prec, tol):
 
 def test_read_info_reports_numerical_failures():
     # counters written into a real workspace by the host, then read back:
-    # TSVD_ENUMERIC for a breakdown, an unconverged eigenvector or a
-    # non-finite value, TSVD_OK for a shift that carried a pivot
+    # TSVD_ENUMERIC for a breakdown, an unconverged eigenvector, a
+    # non-finite value or a tie at the rank-k cut, TSVD_OK for a shift that
+    # carried a pivot
     ws = api.workspace(64, 64, 16, 5, 10, 2, "f64", "rbk", "cuda")
-    for counters, want in (([0, 0, 0, 0], api.TSVD_OK), ([5, 0, 0, 0], api.TSVD_OK),
-                           ([0, 1, 0, 0], api.TSVD_ENUMERIC), ([0, 0, 2, 0], api.TSVD_ENUMERIC),
-                           ([0, 0, 0, 3], api.TSVD_ENUMERIC)):
-        ws[:32].view(torch.int32).copy_(torch.tensor(counters + [0] * 4, dtype=torch.int32))
+    for counters, want in (([0, 0, 0, 0, 0], api.TSVD_OK), ([5, 0, 0, 0, 0], api.TSVD_OK),
+                           ([0, 1, 0, 0, 0], api.TSVD_ENUMERIC), ([0, 0, 2, 0, 0], api.TSVD_ENUMERIC),
+                           ([0, 0, 0, 3, 0], api.TSVD_ENUMERIC), ([0, 0, 0, 0, 1], api.TSVD_ENUMERIC)):
+        pad = [0] * (api.INFO_COUNT - len(counters))
+        ws[:32].view(torch.int32).copy_(torch.tensor(counters + pad, dtype=torch.int32))
         info = api.read_info(ws)
         assert info["status"] == want, (counters, info)
         assert [info[n] for n in api.INFO_NAMES] == counters
