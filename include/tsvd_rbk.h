@@ -41,7 +41,8 @@
  * for Alg. 1, q counts power iterations and m = b).
  * Requirements (else TSVD_EINVAL, nothing enqueued):
  *   n1, n2, n3 >= 1;  1 <= k <= b;  q >= 0;  m <= min(n1, n2);
- *   n1 * n2 * n3 < 2^31;  m <= 1024;  n3 <= 4096;  q <= 4096 for Alg. 1.
+ *   n1 * n2 < 2^31;  n1 * n2 * n3 < 2^36;  m <= 1024;  n3 <= 4096;
+ *   q <= 4096 for Alg. 1.
  *
  * Errors: every entry point returns a status.  TSVD_EINVAL (bad arguments),
  * TSVD_ENOMEM (ws_bytes below tsvd_workspace_bytes), TSVD_EHIP (a HIP launch
@@ -279,8 +280,8 @@ int tsvd_power_approx_omega(const void* A, const void* Omega, int64_t n1,
  * breakdown is counted in TSVD_INFO_CHOL_BREAKDOWN).
  * prec: TSVD_PREC_F64 or TSVD_PREC_F32 (storage and the Q, R products; the
  * Grams are FP64).  Requirements: min(n1, n2) <= 1024, n3 <= 4096,
- * n1 * n2 * n3 < 2^31.  Workspace: tsvd_workspace_bytes(n1, n2, n3, 0, 0, 0,
- * prec, TSVD_OP_TQR). */
+ * n1 * n2 < 2^31, n1 * n2 * n3 < 2^36.  Workspace:
+ * tsvd_workspace_bytes(n1, n2, n3, 0, 0, 0, prec, TSVD_OP_TQR). */
 int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec,
              void* Q, void* R, void* ws, size_t ws_bytes, void* stream);
 
@@ -301,8 +302,8 @@ int tsvd_tqr(const void* A, int64_t n1, int64_t n2, int64_t n3, int prec,
  * s_j carries a relative error of about (n1 + n2) 2^-53 (s_1 / s_j)^2.
  * prec: TSVD_PREC_F64 or TSVD_PREC_F32 (storage and the final product; the
  * Gram, eigensolver and weights are FP64).  Requirements:
- * min(n1, n2) <= 1024, n3 <= 4096, n1 * n2 * n3 < 2^31.  A slice whose
- * eigenvector iteration did not converge is counted in
+ * min(n1, n2) <= 1024, n3 <= 4096, n1 * n2 < 2^31, n1 * n2 * n3 < 2^36.  A
+ * slice whose eigenvector iteration did not converge is counted in
  * TSVD_INFO_EIG_NOCONV.  Workspace: tsvd_workspace_bytes(n1, n2, n3, 0, 0,
  * 0, prec, TSVD_OP_TPINV). */
 int tsvd_tpinv(const void* A, int64_t n1, int64_t n2, int64_t n3, double rtol,

@@ -84,12 +84,16 @@ int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
   return (int)ns;
 }
 
-// n1 * n2 * n3 < 2^31 for 1 <= n3 <= 4096, without overflowing on the way.
+// Sizes the kernels address: one Fourier slice below 2^31 entries (per-slice
+// row, column and tile indices are 32-bit; every offset across slices or
+// into the whole tensor is 64-bit), the tensor below 2^36 entries (256 GiB
+// in FP32, more than one device holds with its spectrum), for
+// 1 <= n3 <= 4096, without overflowing on the way.
 bool small_volume(int64_t n1, int64_t n2, int64_t n3) {
   const int64_t lim = (int64_t)1 << 31;
   if (n1 >= lim || n2 >= lim) return false;
   const int64_t a = n1 * n2;  // < 2^62
-  return a < lim && a * n3 < lim;
+  return a < lim && a * n3 < ((int64_t)1 << 36);
 }
 
 // Alg. mp: per Fourier slice the Gram on the short side (A_f^H A_f when
@@ -101,7 +105,7 @@ int make_plan_tpinv(int64_t n1, int64_t n2, int64_t n3, int prec, Plan* p) {
   const int64_t r = std::min(n1, n2), K = std::max(n1, n2);
   if (r > 1024) return fail(TSVD_EINVAL, "min(n1, n2) must be <= 1024");
   if (n3 > 4096) return fail(TSVD_EINVAL, "n3 must be <= 4096");
-  if (!small_volume(n1, n2, n3)) return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
+  if (!small_volume(n1, n2, n3)) return fail(TSVD_EINVAL, "n1 * n2 must be < 2^31 and n1 * n2 * n3 < 2^36");
   *p = Plan{};
   p->n1 = n1;
   p->n2 = n2;
@@ -186,7 +190,7 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
     if (m > 1024) return fail(TSVD_EINVAL, "m = b (q + 1) must be <= 1024");
   }
   if (n3 > 4096) return fail(TSVD_EINVAL, "n3 must be <= 4096");
-  if (!small_volume(n1, n2, n3)) return fail(TSVD_EINVAL, "n1 * n2 * n3 must be < 2^31");
+  if (!small_volume(n1, n2, n3)) return fail(TSVD_EINVAL, "n1 * n2 must be < 2^31 and n1 * n2 * n3 < 2^36");
   if (prec != TSVD_PREC_F64 && prec != TSVD_PREC_F32 && prec != TSVD_PREC_BF16 && prec != TSVD_PREC_BF16X3)
     return fail(TSVD_EINVAL, "unknown precision mode");
   if (op < TSVD_OP_RBK || op > TSVD_OP_APPROX_BWD || op == TSVD_OP_COMPLETE_RBK || op == TSVD_OP_COMPLETE_POWER ||

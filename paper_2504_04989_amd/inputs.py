@@ -17,6 +17,10 @@ Workload recipes (real tensors, C-contiguous (n1, n2, n3), tubes contiguous):
                keep-mask; the starting point X0 = M (.) T.
   image        power-law random fields in [0, 255] (n1 x n2 x 3), stand-ins for
                the photographs of Example 3, with Bernoulli or line masks.
+  separable    A(i, j, t) = sum_c g_c(i) h_c(j) s_c(t) + noise N(i, j) w(t), all
+               factors i.i.d. N(0, 1), s_c scaled by decay^c: drawn as factors
+               only, for tensors of more than 2^31 entries that a test
+               assembles on the device (separable_factors).
   spectrum     A = U * S * V^T with U, V orthogonal tensors (every Fourier slice
                unitary: numpy's QR of a complex Gaussian matrix, real at the DC
                and Nyquist slices) and S f-diagonal with tubes sigma_m e_1, so
@@ -135,6 +139,30 @@ def hyperspectral_tensor(n1, n2, n3, r, noise, seed):
     A = (A - A.min()) / (A.max() - A.min())
     if noise:
         A += noise * rng.standard_normal((n1, n2, n3))
+    return np.ascontiguousarray(A)
+
+
+def separable_factors(n1, n2, n3, r, decay, noise, seed):
+    """Recipe ``separable``: the factors of
+    A(i, j, t) = sum_c G[i, c] H[j, c] Sp[t, c] + noise Nz[i, j] w[t]
+    with G, H, Sp, Nz, w i.i.d. N(0, 1) (drawn in that order) and column c of
+    Sp scaled by decay^c.  Every Fourier slice is a rank-r matrix plus a
+    multiple of the one dense matrix Nz.  Returns (G, H, Sp, Nz, w, noise);
+    the tensor itself is formed by the caller (separable_tensor for small
+    shapes)."""
+    rng, _ = _streams(seed)
+    G = rng.standard_normal((n1, r))
+    H = rng.standard_normal((n2, r))
+    Sp = rng.standard_normal((n3, r)) * decay ** np.arange(r, dtype=np.float64)
+    Nz = rng.standard_normal((n1, n2))
+    w = rng.standard_normal(n3)
+    return G, H, Sp, Nz, w, float(noise)
+
+
+def separable_tensor(factors) -> np.ndarray:
+    """The n1 x n2 x n3 tensor of separable_factors, on the host."""
+    G, H, Sp, Nz, w, noise = factors
+    A = np.einsum("ic,jc,tc->ijt", G, H, Sp, optimize=True) + noise * Nz[:, :, None] * w[None, None, :]
     return np.ascontiguousarray(A)
 
 
