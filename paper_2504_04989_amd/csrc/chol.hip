@@ -237,8 +237,8 @@ __device__ void tile_inverse(cx<double>* T, int lane) {
       s.im -= l.re * x[k].im + l.im * x[k].re;
     }
     const cx<double> d = T[i * TRS + i];
-    const double den = d.re * d.re + d.im * d.im;
-    const cx<double> inv{d.re / den, -d.im / den};
+    const double rden = 1.0 / (d.re * d.re + d.im * d.im);
+    const cx<double> inv{d.re * rden, -d.im * rden};
     x[i] = (i < c) ? cx<double>{0.0, 0.0} : cx<double>{s.re * inv.re - s.im * inv.im, s.re * inv.im + s.im * inv.re};
   }
   wsync();
@@ -249,14 +249,33 @@ __device__ void tile_inverse(cx<double>* T, int lane) {
   wsync();
 }
 
+// Value of x in lane l (l uniform), through the scalar unit.
+__device__ __forceinline__ double lane_bcast(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Cholesky of the Hermitian 16 x 16 tile T (lower part used) in place (one
 // wave).  Returns bit 0 on a non-positive or non-finite pivot in a row <
 // nvalid, bit 1 when such a row's pivot is at most `thr` (thr > 0: twice the
 // shift that was added to the diagonal, i.e. the shift carries the pivot).
+// Lane i (mod 16) holds row i in registers for the whole factorisation; the
+// pivot and the entries L_jk of column k reach the other rows by lane
+// broadcast, so a column costs no LDS round trip or wave barrier.  Every
+// entry sees the same operations in the same order as the column-by-column
+// right-looking form: scale column k by 1 / sqrt(pivot), then
+// A_ij -= L_ik conj(L_jk) for k < j <= i.
 __device__ int tile_cholesky(cx<double>* T, int lane, int nvalid, double thr) {
+  const int i = lane & 15;
+  cx<double> r[TSZ];
+#pragma unroll
+  for (int j = 0; j < TSZ; ++j) r[j] = T[i * TRS + j];
   int bad = 0;
+#pragma unroll
   for (int k = 0; k < TSZ; ++k) {
-    const double d = T[k * TRS + k].re;
+    const double d = lane_bcast(r[k].re, k);
     if (thr > 0 && k < nvalid && !(d > thr)) bad |= 2;
     double piv = 1.0;
     if (d > 0 && isfinite(d))
@@ -264,29 +283,27 @@ __device__ int tile_cholesky(cx<double>* T, int lane, int nvalid, double thr) {
     else if (k < nvalid)
       bad |= 1;
     const double inv = 1.0 / piv;
-    wsync();
-    if (lane > k && lane < TSZ) {
-      cx<double> v = T[lane * TRS + k];
-      v.re *= inv;
-      v.im *= inv;
-      T[lane * TRS + k] = v;
+    if (i > k) {
+      r[k].re *= inv;
+      r[k].im *= inv;
+    } else if (i == k) {
+      r[k] = cx<double>{piv, 0.0};
     }
-    if (lane == 0) T[k * TRS + k] = cx<double>{piv, 0.0};
-    wsync();
-    // T[i][j] -= T[i][k] conj(T[j][k]) for k < j <= i
-    for (int e = lane; e < TSZ * TSZ; e += 64) {
-      const int i = e >> 4, j = e & 15;
-      if (j > k && j <= i) {
-        const cx<double> a = T[i * TRS + k];
-        const cx<double> b = T[j * TRS + k];
-        cx<double> v = T[i * TRS + j];
-        v.re -= a.re * b.re + a.im * b.im;
-        v.im -= a.im * b.re - a.re * b.im;
-        T[i * TRS + j] = v;
+#pragma unroll
+    for (int j = k + 1; j < TSZ; ++j) {
+      const double lr = lane_bcast(r[k].re, j), li = lane_bcast(r[k].im, j);
+      if (j <= i) {
+        r[j].re -= r[k].re * lr + r[k].im * li;
+        r[j].im -= r[k].im * lr - r[k].re * li;
       }
     }
-    wsync();
   }
+  wsync();
+  if (lane < TSZ) {
+#pragma unroll
+    for (int j = 0; j < TSZ; ++j) T[i * TRS + j] = r[j];
+  }
+  wsync();
   return bad;
 }
 

@@ -20,6 +20,7 @@
 // (q4, r16) holds real output row 16 i + q4 + 4 r, i.e. the real (q4 even)
 // or imaginary (q4 odd) part of complex column n = 8 i + q4 / 2 + 2 r.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -131,48 +132,37 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
       }
     }
   };
-  auto load_thin_full = [&](int k0, double2 (&x)[TEL]) {
+  // the thin block is held as loaded (FP32 pairs for TN, FP64 for NN) and
+  // widened, and its padding columns cleared, only when it is stored to LDS:
+  // nothing waits for the loads before the next step's MFMAs have been issued
+  typedef typename std::conditional<TN, float2, double2>::type Raw;
+  auto load_thin_full = [&](int k0, Raw (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % OKSTEP, nn = idx / OKSTEP;
+      const int64_t off = (int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + (n0 + (nn < nc ? nn : 0));
+      x[e] = reinterpret_cast<const Raw*>(a.B)[off];
+    }
+  };
+
+  auto load_thin = [&](int k0, Raw (&x)[TEL]) {
+#pragma unroll
+    for (int e = 0; e < TEL; ++e) {
+      const int idx = tid + e * 256;
+      const int kk = idx % OKSTEP, nn = idx / OKSTEP;
+      Raw v{};
+      if (k0 + kk < ke && nn < nc) v = reinterpret_cast<const Raw*>(a.B)[(int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + (n0 + nn)];
+      x[e] = v;
+    }
+  };
+  auto store_thin = [&](double* buf, const Raw (&x)[TEL]) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
       const int idx = tid + e * 256;
       const int kk = idx % OKSTEP, nn = idx / OKSTEP;
       const bool ok = nn < nc;
-      const int64_t off = (int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + (n0 + (ok ? nn : 0));
-      double2 v;
-      if (TN) {
-        const float2 y = reinterpret_cast<const float2*>(a.B)[off];
-        v = make_double2((double)y.x, (double)y.y);
-      } else {
-        v = reinterpret_cast<const double2*>(a.B)[off];
-      }
-      x[e] = ok ? v : make_double2(0.0, 0.0);
-    }
-  };
-
-  auto load_thin = [&](int k0, double2 (&x)[TEL]) {
-#pragma unroll
-    for (int e = 0; e < TEL; ++e) {
-      const int idx = tid + e * 256;
-      const int kk = idx % OKSTEP, nn = idx / OKSTEP;
-      double2 v = make_double2(0.0, 0.0);
-      if (k0 + kk < ke && nn < nc) {
-        const int64_t off = (int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + (n0 + nn);
-        if (TN) {
-          const float2 y = reinterpret_cast<const float2*>(a.B)[off];
-          v = make_double2((double)y.x, (double)y.y);
-        } else {
-          v = reinterpret_cast<const double2*>(a.B)[off];
-        }
-      }
-      x[e] = v;
-    }
-  };
-  auto store_thin = [&](double* buf, const double2 (&x)[TEL]) {
-#pragma unroll
-    for (int e = 0; e < TEL; ++e) {
-      const int idx = tid + e * 256;
-      const int kk = idx % OKSTEP, nn = idx / OKSTEP;
-      const double xr = x[e].x, xi = x[e].y;
+      const double xr = ok ? (double)x[e].x : 0.0, xi = ok ? (double)x[e].y : 0.0;
       double* row0 = buf + (2 * nn) * OSTRIDE + 2 * kk;
       double* row1 = row0 + OSTRIDE;
       if (TN) {
@@ -219,34 +209,39 @@ __global__ __launch_bounds__(256, 2) void ogemm_kernel(const OArgs a) {
 
   // main loop over the full K steps (LDS double buffer, next step's tall
   // operand in registers; the thin block is requested first because loads
-  // complete in issue order), then a guarded ragged step
+  // complete in issue order), unrolled by two so that the two register sets
+  // of the tall operand swap roles instead of being copied (a copy would wait
+  // for the loads in flight); then a guarded ragged step
   const int nfull = (ke - kb) / OKSTEP;
   const bool tail = kb + nfull * OKSTEP < ke;
-  float cur[4], nxt[4];
-  double2 tx[TEL];
+  float bA[4], bB[4];
+  Raw tx[TEL];
   if (nfull > 0) {
-    load_big_full(kb, cur);
+    load_big_full(kb, bA);
     load_thin_full(kb, tx);
     store_thin(olds, tx);
   }
   __syncthreads();
-  for (int s = 0; s < nfull; ++s) {
+  auto step = [&](int s, const float (&cur)[4], float (&nxt)[4]) {
     const int sn = s + 1 < nfull ? s + 1 : s;
     load_thin_full(kb + sn * OKSTEP, tx);
     load_big_full(kb + sn * OKSTEP, nxt);
     compute(olds + (s & 1) * BUF, cur, tile0(kb + s * OKSTEP));
     if (s + 1 < nfull) store_thin(olds + ((s + 1) & 1) * BUF, tx);
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
+  };
+  for (int s = 0; s < nfull; s += 2) {
+    step(s, bA, bB);
+    if (s + 1 >= nfull) break;
+    step(s + 1, bB, bA);
   }
   if (tail) {
     const int k0 = kb + nfull * OKSTEP;
     load_thin(k0, tx);
     store_thin(olds + (nfull & 1) * BUF, tx);
-    load_big(k0, cur);
+    load_big(k0, bA);
     __syncthreads();
-    compute(olds + (nfull & 1) * BUF, cur, tile0(k0));
+    compute(olds + (nfull & 1) * BUF, bA, tile0(k0));
   }
 
   // Lanes q4 and q4 ^ 1 hold the real and the imaginary parts of the same
@@ -341,36 +336,31 @@ __global__ __launch_bounds__(256, 2) void ogemm_tn_pair_kernel(const OArgs a) {
   // loads stay in flight across this step's MFMAs.  Padding columns nn >= N
   // read column N - 1 instead of zeros: a thin row only reaches the output
   // rows it forms itself, and rows n >= N are never stored.
-  auto load_thin_full = [&](int k0, double2 (&x)[TEL]) {
+  // held as loaded (FP32 pairs), widened when stored to LDS
+  auto load_thin_full = [&](int k0, float2 (&x)[TEL]) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
       const int idx = tid + e * 256;
       const int kk = idx % OKSTEP, nn = min(idx / OKSTEP, nc - 1);
-      const int64_t off = (int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + nn;
-      const float2 y = reinterpret_cast<const float2*>(a.B)[off];
-      x[e] = make_double2((double)y.x, (double)y.y);
+      x[e] = reinterpret_cast<const float2*>(a.B)[(int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + nn];
     }
   };
-  auto load_thin = [&](int k0, double2 (&x)[TEL]) {
+  auto load_thin = [&](int k0, float2 (&x)[TEL]) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
       const int idx = tid + e * 256;
       const int kk = idx % OKSTEP, nn = idx / OKSTEP;
-      double2 v = make_double2(0.0, 0.0);
-      if (k0 + kk < ke && nn < nc) {
-        const int64_t off = (int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + nn;
-        const float2 y = reinterpret_cast<const float2*>(a.B)[off];
-        v = make_double2((double)y.x, (double)y.y);
-      }
+      float2 v = make_float2(0.f, 0.f);
+      if (k0 + kk < ke && nn < nc) v = reinterpret_cast<const float2*>(a.B)[(int64_t)f * a.strideB + (int64_t)(k0 + kk) * a.ldb + nn];
       x[e] = v;
     }
   };
-  auto store_thin = [&](double* buf, const double2 (&x)[TEL]) {
+  auto store_thin = [&](double* buf, const float2 (&x)[TEL]) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
       const int idx = tid + e * 256;
       const int kk = idx % OKSTEP, nn = idx / OKSTEP;
-      const double xr = x[e].x, xi = x[e].y;
+      const double xr = (double)x[e].x, xi = (double)x[e].y;
       double* row0 = buf + (2 * nn) * OSTRIDE + 2 * kk;
       double* row1 = row0 + OSTRIDE;
       *reinterpret_cast<double2*>(row0) = make_double2(xr, xi);
@@ -414,37 +404,38 @@ __global__ __launch_bounds__(256, 2) void ogemm_tn_pair_kernel(const OArgs a) {
 
   const int nfull = (ke - kb) / OKSTEP;
   const bool tail = kb + nfull * OKSTEP < ke;
-  float cura[4], curb[4], nxta[4], nxtb[4];
-  double2 tx[TEL];
+  // unrolled by two: the register sets swap roles rather than being copied
+  float aA[4], bA[4], aB[4], bB[4];
+  float2 tx[TEL];
   if (nfull > 0) {
-    load_big_full(kb, cla, cura);
-    load_big_full(kb, clb, curb);
+    load_big_full(kb, cla, aA);
+    load_big_full(kb, clb, bA);
     load_thin_full(kb, tx);
     store_thin(olds, tx);
   }
   __syncthreads();
-  for (int s = 0; s < nfull; ++s) {
+  auto step = [&](int s, const float (&ca)[4], const float (&cb)[4], float (&na)[4], float (&nb)[4]) {
     const int sn = s + 1 < nfull ? s + 1 : s;
     load_thin_full(kb + sn * OKSTEP, tx);
-    load_big_full(kb + sn * OKSTEP, cla, nxta);
-    load_big_full(kb + sn * OKSTEP, clb, nxtb);
-    compute(olds + (s & 1) * BUF, cura, curb);
+    load_big_full(kb + sn * OKSTEP, cla, na);
+    load_big_full(kb + sn * OKSTEP, clb, nb);
+    compute(olds + (s & 1) * BUF, ca, cb);
     if (s + 1 < nfull) store_thin(olds + ((s + 1) & 1) * BUF, tx);
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      cura[j] = nxta[j];
-      curb[j] = nxtb[j];
-    }
+  };
+  for (int s = 0; s < nfull; s += 2) {
+    step(s, aA, bA, aB, bB);
+    if (s + 1 >= nfull) break;
+    step(s + 1, aB, bB, aA, bA);
   }
   if (tail) {
     const int k0 = kb + nfull * OKSTEP;
     load_thin(k0, tx);
     store_thin(olds + (nfull & 1) * BUF, tx);
-    load_big(k0, cla, oka, false, cura);
-    load_big(k0, clb, okb, false, curb);
+    load_big(k0, cla, oka, false, aA);
+    load_big(k0, clb, okb, false, bA);
     __syncthreads();
-    compute(olds + (nfull & 1) * BUF, cura, curb);
+    compute(olds + (nfull & 1) * BUF, aA, bA);
   }
 
   // lanes q4 and q4 ^ 1 hold the real and the imaginary parts of the same
