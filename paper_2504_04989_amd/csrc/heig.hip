@@ -1418,11 +1418,10 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Waves (eigenvectors) per workgroup of the inverse iteration at most; each
-// holds 6 m doubles of LU factors and iterate in LDS.
-#ifndef TSVD_INVIT_NW
-#define TSVD_INVIT_NW 2
-#endif
+// Waves (eigenvectors) per workgroup of the inverse iteration.  The LU
+// factors and the iterate live in registers (NCH 64-entry chunks per lane);
+// LDS holds T (2 m doubles) and one m-vector per wave for the residual.
+constexpr int INVIT_NW = 4;
 
 // Value of v held by lane j (j uniform across the wave): two v_readlane_b32.
 // The dependent chains of the inverse iteration walk through a 64-entry chunk
@@ -1444,6 +1443,7 @@ __device__ __forceinline__ double hash_uniform(uint32_t a, uint32_t b) {
   return (double)h * (2.0 / 4294967296.0) - 1.0;
 }
 
+template <int NCH>
 __global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned char* scratch, size_t per_slice,
                                                          const double* __restrict__ lambda,
                                                          cx<double>* __restrict__ Wout, int* info,
@@ -1454,13 +1454,7 @@ __global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned 
   const int f = blockIdx.x;
   const int nw = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* wsp = e + m + (size_t)wave * 6 * m;
-  double* mult = wsp;
-  double* swp = mult + m;
-  double* u0 = swp + m;
-  double* u1 = u0 + m;
-  double* u2 = u1 + m;
-  double* z = u2 + m;
+  double* zs = e + m + (size_t)wave * m;  // this wave's iterate, for the residual
   HeigView hv = heig_view(scratch, per_slice, f, m);
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
     d[i] = hv.d[i];
@@ -1494,11 +1488,17 @@ __global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned 
   const double tinyp = eps * fmax(tnorm, 1e-300);
   for (int t = t0; t < t1; ++t) {
     const double lv = lam[t];
-    {
-      // pivoted LU of T - lambda I (the recurrence runs, uniform, in every
-      // lane; lane j keeps step base + j of the factors for the chunk store)
-      double pc = d[0] - lv, qc = (m > 1) ? e[0] : 0.0, rc = 0.0;
-      for (int base = 0; base < m - 1; base += 64) {
+    // pivoted LU of T - lambda I; entry 64 c + lane of the factors (reciprocal
+    // pivot, the two entries right of it, multiplier, row swap) stays in this
+    // lane's registers, chunk c.  The recurrence runs, uniform, in every lane.
+    double r0[NCH], r1[NCH], r2[NCH], rmu[NCH], rsw[NCH], Z[NCH];
+    double pc = d[0] - lv, qc = (m > 1) ? e[0] : 0.0, rc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      r0[c] = 1.0;
+      r1[c] = r2[c] = rmu[c] = rsw[c] = 0.0;
+      const int base = 64 * c;
+      if (base < m - 1) {
         const int i = base + lane;
         const int cnt = min(64, m - 1 - base);
         const double ei_l = i < m - 1 ? e[i] : 0.0;
@@ -1509,26 +1509,26 @@ __global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned 
           const double ei = lane_get(ei_l, j);
           const double an = lane_get(an_l, j);
           const double en = lane_get(en_l, j);
-          double r0, r1, r2, rm, rs;
+          double s0, s1, s2, sm, ss;
           if (fabs(pc) >= fabs(ei)) {
             double piv = pc;
             if (fabs(piv) < tinyp) piv = copysign(tinyp, piv == 0.0 ? 1.0 : piv);
             const double mu = ei / piv;
-            r0 = piv;
-            r1 = qc;
-            r2 = rc;
-            rm = mu;
-            rs = 0.0;
+            s0 = piv;
+            s1 = qc;
+            s2 = rc;
+            sm = mu;
+            ss = 0.0;
             pc = an - mu * qc;
             qc = en - mu * rc;
             rc = 0.0;
           } else {
             const double mu = pc / ei;
-            r0 = ei;
-            r1 = an;
-            r2 = en;
-            rm = mu;
-            rs = 1.0;
+            s0 = ei;
+            s1 = an;
+            s2 = en;
+            sm = mu;
+            ss = 1.0;
             const double npc = qc - mu * an;
             const double nqc = rc - mu * en;
             pc = npc;
@@ -1536,105 +1536,117 @@ __global__ __launch_bounds__(256) void heig_invit_kernel(int m, int k, unsigned 
             rc = 0.0;
           }
           if (lane == j) {
-            o0 = r0;
-            o1 = r1;
-            o2 = r2;
-            om = rm;
-            os = rs;
+            o0 = s0;
+            o1 = s1;
+            o2 = s2;
+            om = sm;
+            os = ss;
           }
         }
         if (lane < cnt) {
-          u0[i] = 1.0 / o0;  // the solves multiply by the reciprocal pivots
-          u1[i] = o1;
-          u2[i] = o2;
-          mult[i] = om;
-          swp[i] = os;
+          r0[c] = 1.0 / o0;  // the solves multiply by the reciprocal pivots
+          r1[c] = o1;
+          r2[c] = o2;
+          rmu[c] = om;
+          rsw[c] = os;
         }
       }
-      if (fabs(pc) < tinyp) pc = copysign(tinyp, pc == 0.0 ? 1.0 : pc);
-      if (lane == 0) {
-        u0[m - 1] = 1.0 / pc;
-        u1[m - 1] = 0.0;
-        u2[m - 1] = 0.0;
-      }
     }
-    for (int i = lane; i < m; i += 64) z[i] = hash_uniform((uint32_t)t, (uint32_t)i);
-    wave_sync();
+    if (fabs(pc) < tinyp) pc = copysign(tinyp, pc == 0.0 ? 1.0 : pc);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      if (64 * c + lane == m - 1) {
+        r0[c] = 1.0 / pc;
+        r1[c] = r2[c] = 0.0;
+      }
+      const int i = 64 * c + lane;
+      Z[c] = i < m ? hash_uniform((uint32_t)t, (uint32_t)i) : 0.0;
+    }
     for (int it = 0; it < 4; ++it) {
-      {
-        // forward elimination with the row swaps and multipliers, then back
-        // substitution; the chains run uniform in every lane over 64-entry
-        // chunks fetched in parallel, lane j keeping result base + j
-        double zc = z[0];
-        for (int base = 0; base < m - 1; base += 64) {
-          const int i = base + lane;
+      // forward elimination with the row swaps and multipliers, then back
+      // substitution, uniform in every lane over the chunks; z[i + 1] of
+      // step i is the next lane's entry (or lane 0 of the next chunk)
+      double zc = lane_get(Z[0], 0);
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int base = 64 * c;
+        if (base < m - 1) {
           const int cnt = min(64, m - 1 - base);
-          const double zn_l = i < m - 1 ? z[i + 1] : 0.0;
-          const double sw_l = i < m - 1 ? swp[i] : 0.0;
-          const double mu_l = i < m - 1 ? mult[i] : 0.0;
+          const double znext = c + 1 < NCH ? lane_get(Z[c + 1 < NCH ? c + 1 : c], 0) : 0.0;
           double out = 0.0;
           for (int j = 0; j < cnt; ++j) {
-            double zn = lane_get(zn_l, j);
-            if (lane_get(sw_l, j) != 0.0) {
+            double zn = j < 63 ? lane_get(Z[c], j + 1) : znext;
+            if (lane_get(rsw[c], j) != 0.0) {
               const double tmp = zc;
               zc = zn;
               zn = tmp;
             }
             if (lane == j) out = zc;
-            zc = zn - lane_get(mu_l, j) * zc;
+            zc = zn - lane_get(rmu[c], j) * zc;
           }
-          wave_sync();
-          if (lane < cnt) z[i] = out;
-          wave_sync();
+          if (lane < cnt) Z[c] = out;
         }
-        if (lane == 0) z[m - 1] = zc;
-        wave_sync();
-        double z1 = 0.0, z2 = 0.0;
-        for (int top = m; top > 0; top -= 64) {
-          const int base = top > 64 ? top - 64 : 0;
-          const int cnt = top - base;
-          const int i = base + lane;
-          const bool ok = lane < cnt;
-          const double zi_l = ok ? z[i] : 0.0;
-          const double a0 = ok ? u0[i] : 0.0;
-          const double a1 = ok ? u1[i] : 0.0;
-          const double a2 = ok ? u2[i] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+        if (64 * c + lane == m - 1) Z[c] = zc;
+      double z1 = 0.0, z2 = 0.0;
+#pragma unroll
+      for (int c = NCH - 1; c >= 0; --c) {
+        const int base = 64 * c;
+        if (base < m) {
+          const int cnt = min(64, m - base);
           double out = 0.0;
           for (int j = cnt - 1; j >= 0; --j) {
-            const double v = (lane_get(zi_l, j) - lane_get(a1, j) * z1 - lane_get(a2, j) * z2) * lane_get(a0, j);
+            const double v = (lane_get(Z[c], j) - lane_get(r1[c], j) * z1 - lane_get(r2[c], j) * z2) *
+                             lane_get(r0[c], j);
             if (lane == j) out = v;
             z2 = z1;
             z1 = v;
           }
-          wave_sync();
-          if (ok) z[i] = out;
+          if (lane < cnt) Z[c] = out;
         }
       }
-      wave_sync();
       // re-orthogonalise against the earlier members of the cluster
       for (int t2 = t0; t2 < t; ++t2) {
-        double c = 0;
-        for (int i = lane; i < m; i += 64) c += z[i] * W[(int64_t)i * k + t2].re;
-        c = wave_sum(c);
-        for (int i = lane; i < m; i += 64) z[i] -= c * W[(int64_t)i * k + t2].re;
+        double cc = 0;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const int i = 64 * c + lane;
+          if (i < m) cc += Z[c] * W[(int64_t)i * k + t2].re;
+        }
+        cc = wave_sum(cc);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          const int i = 64 * c + lane;
+          if (i < m) Z[c] -= cc * W[(int64_t)i * k + t2].re;
+        }
       }
       double nrm = 0;
-      for (int i = lane; i < m; i += 64) nrm += z[i] * z[i];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) nrm += Z[c] * Z[c];
       nrm = wave_sum(nrm);
       nrm = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
-      for (int i = lane; i < m; i += 64) z[i] *= nrm;
-      wave_sync();
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) Z[c] *= nrm;
     }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int i = 64 * c + lane;
+      if (i < m) zs[i] = Z[c];
+    }
+    wave_sync();
     double res = 0;
     for (int i = lane; i < m; i += 64) {
-      double y = (d[i] - lv) * z[i];
-      if (i > 0) y += e[i - 1] * z[i - 1];
-      if (i + 1 < m) y += e[i] * z[i + 1];
+      double y = (d[i] - lv) * zs[i];
+      if (i > 0) y += e[i - 1] * zs[i - 1];
+      if (i + 1 < m) y += e[i] * zs[i + 1];
       res = fmax(res, fabs(y));
     }
     res = wave_max(res);
     if (lane == 0 && !(res <= 1e3 * m * eps * fmax(tnorm, 1e-300))) atomicAdd(&info[INFO_EIG_NOCONV], 1);
-    for (int i = lane; i < m; i += 64) W[(int64_t)i * k + t] = cx<double>{z[i], 0.0};
+    for (int i = lane; i < m; i += 64) W[(int64_t)i * k + t] = cx<double>{zs[i], 0.0};
+    wave_sync();
     __threadfence();
   }
 }
@@ -1825,8 +1837,6 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
                               152 * 1024);
     (void)hipFuncSetAttribute((const void*)heig_tri2_kernel<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               152 * 1024);
-    (void)hipFuncSetAttribute((const void*)heig_invit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              152 * 1024);
     (void)hipFuncSetAttribute((const void*)heig_backxf_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               152 * 1024);
     (void)hipGetLastError();
@@ -1918,14 +1928,21 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
                        m, k, sc, per, lambda, info);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  // 3. eigenvectors: per-wave LU workspace of 6 m doubles in LDS
-  int nw = (int)((140 * 1024 - 16 * (size_t)m) / (48 * (size_t)m));
-  if (nw > TSVD_INVIT_NW) nw = TSVD_INVIT_NW;
-  if (nw < 1) nw = 1;
-  const size_t sm3 = (size_t)2 * m * sizeof(double) + (size_t)nw * 6 * m * sizeof(double);
+  // 3. eigenvectors: LU factors and iterates in registers (NCH chunks of 64
+  // entries per lane), T and one m-vector per wave in LDS
   if (stages & HEIG_INVIT) {
-    hipLaunchKernelGGL(heig_invit_kernel, dim3(batch, (k + nw - 1) / nw), dim3(64 * nw), sm3, s, m, k, sc, per,
-                       lambda, (cx<double>*)W, info, vfloor_rel);
+    const int nw = INVIT_NW;
+    const size_t sm3 = (size_t)(2 + nw) * m * sizeof(double);
+    const dim3 g3(batch, (k + nw - 1) / nw), b3(64 * nw);
+    if (m <= 128)
+      hipLaunchKernelGGL(heig_invit_kernel<2>, g3, b3, sm3, s, m, k, sc, per, lambda, (cx<double>*)W, info, vfloor_rel);
+    else if (m <= 256)
+      hipLaunchKernelGGL(heig_invit_kernel<4>, g3, b3, sm3, s, m, k, sc, per, lambda, (cx<double>*)W, info, vfloor_rel);
+    else if (m <= 512)
+      hipLaunchKernelGGL(heig_invit_kernel<8>, g3, b3, sm3, s, m, k, sc, per, lambda, (cx<double>*)W, info, vfloor_rel);
+    else
+      hipLaunchKernelGGL(heig_invit_kernel<16>, g3, b3, sm3, s, m, k, sc, per, lambda, (cx<double>*)W, info,
+                         vfloor_rel);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // 4. back-transformation

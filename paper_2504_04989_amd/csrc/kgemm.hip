@@ -146,6 +146,16 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
     colc[u] = colok[u] ? col[u] : a.M - 1;  // clamped: loads stay in bounds, results unused
   }
 
+  // Thin column of element e of this thread (k = idx mod KSTEP is the
+  // thread's K index).  In the BF16 forms the four 16-lane groups of a wave
+  // take columns 2 apart, so the LDS rows they store start 4 STRIDE = 80
+  // words (16 banks modulo 64) apart and a wave's stores do not collide.
+  auto thin_col = [&](int t, int e) {
+    if (MODE == KM_F32) return (t + e * 256) / KSTEP;
+    const int w = t >> 6, g = (t >> 4) & 3;
+    return 16 * e + 8 * (w & 1) + (w >> 1) + 2 * g;
+  };
+
   // ---- full K steps: every load is issued unconditionally (clamped
   // addresses, zero by select) so that the compiler's wait counts can leave
   // the prefetches of later steps in flight ----
@@ -181,7 +191,7 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
       const int idx = tid + e * 256;
-      const int kk = idx % KSTEP, nn = idx / KSTEP;
+      const int kk = idx % KSTEP, nn = thin_col(tid, e);
       const bool ok = nn < nc;
       const float2 v = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + kk) * a.ldx + 2 * (n0 + (ok ? nn : 0)));
       x[e] = ok ? v : make_float2(0.f, 0.f);
@@ -228,7 +238,7 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
       const int idx = tid + e * 256;
-      const int kk = idx % KSTEP, nn = idx / KSTEP;
+      const int kk = idx % KSTEP, nn = thin_col(tid, e);
       float2 v = make_float2(0.f, 0.f);
       if (k0 + kk < ke && nn < nc) v = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + kk) * a.ldx + 2 * (n0 + nn));
       x[e] = v;
@@ -238,7 +248,7 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
       const int idx = tid + e * 256;
-      const int kk = idx % KSTEP, nn = idx / KSTEP;
+      const int kk = idx % KSTEP, nn = thin_col(tid, e);
       const float xr = x[e].x, xi = x[e].y;
       // rows 2nn (real part of the output) and 2nn + 1 (imaginary part):
       //   A X  : (xr, -xi), (xi, xr);   A^H Y : (xr, xi), (xi, -xr)
