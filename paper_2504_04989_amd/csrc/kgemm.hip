@@ -369,7 +369,11 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
     load_thin_full(kb + sn * KSTEP, tx);
     load_big_full(kb + sp2 * KSTEP, pre);
     if (s < nfull) {
+      // the MFMA phase at raised wave priority: the other workgroup's waves on
+      // the SIMD, between their loads and LDS stores, issue around it
+      __builtin_amdgcn_s_setprio(1);
       compute(lds + (s & 1) * BUF, cur);
+      __builtin_amdgcn_s_setprio(0);
       if (s + 1 < nfull) store_thin(lds + ((s + 1) & 1) * BUF, tx);
       __syncthreads();
     }
