@@ -1724,14 +1724,16 @@ __global__ __launch_bounds__(256) void heig_backxf_kernel(int m, int k, unsigned
 
 // Back-transformation with the columns in registers: each half-wave owns one
 // of the workgroup's 8 columns of W (rows l32 + 32 s), so the product with a
-// reflector and the update need only lane exchanges; the reflectors pass
-// through a double-buffered LDS slot (the next one is fetched and stored
-// while the current one is applied), one workgroup barrier per reflector.
-template <int S>
+// reflector and the update need only lane exchanges.  The reflectors pass
+// through LDS in groups of NB (double-buffered by group; the next group is
+// fetched into registers while the current one is applied), one workgroup
+// barrier per group: the NB reflectors of a group are applied in order
+// with no barrier between them, since no half-wave reads another's column.
+template <int S, int NB>
 __global__ __launch_bounds__(256) void heig_backxf2_kernel(int m, int k, unsigned char* scratch, size_t per_slice,
                                                            cx<double>* __restrict__ Wout) {
   extern __shared__ __align__(16) unsigned char smem[];
-  cx<double>* vbuf = reinterpret_cast<cx<double>*>(smem);  // 2 x m
+  cx<double>* vbuf = reinterpret_cast<cx<double>*>(smem);  // 2 groups x NB x m
   const int f = blockIdx.x;
   const int tid = threadIdx.x, g = tid >> 5, l32 = tid & 31;
   const int col = blockIdx.y * 8 + g;
@@ -1744,41 +1746,52 @@ __global__ __launch_bounds__(256) void heig_backxf2_kernel(int m, int k, unsigne
     const int r = l32 + 32 * s;
     w[s] = (colok && r < m) ? W[(int64_t)r * k + col] : cx<double>{0, 0};
   }
-  constexpr int PF = 4;  // reflector entries per thread (m <= 1024)
-  constexpr int D = 3;   // reflectors in flight: v_{j-1}, v_{j-2}, v_{j-3} while v_j is applied
-  cx<double> ring[D][PF];
-  auto fetch = [&](int j, cx<double>(&dst)[PF]) {
-    const int L = m - j - 1;
-    const cx<double>* vg = hv.A + (int64_t)j * m + (j + 1);
+  constexpr int PF = 4;  // reflector entries per thread and reflector (m <= 1024)
+  // reflectors j0 .. 0 in descending order; group q holds j = j0 - q NB - u, u < NB
+  const int j0 = m - 2;
+  const int ng = (j0 + NB) / NB;
+  cx<double> pre[NB][PF];
+  auto fetch = [&](int q) {
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int i = tid + u * 256;
-      dst[u] = i < L ? vg[i] : cx<double>{0, 0};
+    for (int u = 0; u < NB; ++u) {
+      const int j = j0 - q * NB - u;
+      const int L = m - j - 1;
+      const cx<double>* vg = hv.A + (int64_t)(j >= 0 ? j : 0) * m + (j + 1);
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int i = tid + p * 256;
+        pre[u][p] = (j >= 0 && i < L) ? vg[i] : cx<double>{0, 0};
+      }
     }
   };
-  auto stage = [&](int j, const cx<double>(&src)[PF]) {
-    const int L = m - j - 1;
-    cx<double>* vb = vbuf + (j & 1) * m;
+  auto stage = [&](int q) {
+    cx<double>* vb = vbuf + (size_t)(q & 1) * NB * m;
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int i = tid + u * 256;
-      if (i < L) vb[i] = src[u];
+    for (int u = 0; u < NB; ++u) {
+      const int j = j0 - q * NB - u;
+      const int L = m - j - 1;
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int i = tid + p * 256;
+        if (j >= 0 && i < L) vb[(size_t)u * m + i] = pre[u][p];
+      }
     }
   };
-  auto apply = [&](int j) {
+  auto apply = [&](int j, const cx<double>* vb) {
     const cx<double> tau = hv.tau[j];
     if (tau.re == 0.0 && tau.im == 0.0) return;
-    const cx<double>* vb = vbuf + (j & 1) * m;
-    // rows r = j + 1 + i of the reflector; row r of W sits in w[(r - l32) / 32]
+    // rows r = j + 1 + i of the reflector; row r of W sits in w[(r - l32) / 32].
+    // The lane's entries of the reflector are read from LDS once, for both
+    // the product and the update.
+    cx<double> vv[S];
     double sr = 0, si = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int i = l32 + 32 * s - j - 1;
-      if (i >= 0 && i < m - j - 1) {
-        const cx<double> t = cjmul(vb[i], w[s]);
-        sr += t.re;
-        si += t.im;
-      }
+      vv[s] = (i >= 0 && i < m - j - 1) ? vb[i] : cx<double>{0, 0};
+      const cx<double> t = cjmul(vv[s], w[s]);
+      sr += t.re;
+      si += t.im;
     }
 #pragma unroll
     for (int o = 16; o > 0; o >>= 1) {
@@ -1788,33 +1801,29 @@ __global__ __launch_bounds__(256) void heig_backxf2_kernel(int m, int k, unsigne
     const cx<double> sc = cmulc(tau, cx<double>{sr, si});
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      const int i = l32 + 32 * s - j - 1;
-      if (i >= 0 && i < m - j - 1) {
-        const cx<double> t = cmulc(vb[i], sc);
-        w[s].re -= t.re;
-        w[s].im -= t.im;
-      }
+      const cx<double> t = cmulc(vv[s], sc);
+      w[s].re -= t.re;
+      w[s].im -= t.im;
     }
   };
-  // reflector j lives in ring slot (m - 2 - j) mod D until it is staged
-  const int j0 = m - 2;
-#pragma unroll
-  for (int q = 0; q < D; ++q)
-    if (j0 - q >= 0) fetch(j0 - q, ring[q]);
-  if (j0 >= 0) stage(j0, ring[0]);
+  if (ng > 0) {
+    fetch(0);
+    stage(0);
+    if (ng > 1) fetch(1);
+  }
   __syncthreads();
-  auto step = [&](int j, cx<double>(&mine)[PF], cx<double>(&next)[PF]) {
-    if (j - D >= 0) fetch(j - D, mine);  // slot of v_j (already staged) takes v_{j-D}
-    apply(j);
-    if (j > 0) stage(j - 1, next);
+  for (int q = 0; q < ng; ++q) {
+    const cx<double>* vb = vbuf + (size_t)(q & 1) * NB * m;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int j = j0 - q * NB - u;
+      if (j >= 0) apply(j, vb + (size_t)u * m);
+    }
+    if (q + 1 < ng) {
+      stage(q + 1);
+      if (q + 2 < ng) fetch(q + 2);
+    }
     __syncthreads();
-  };
-  for (int j = j0; j >= 0; j -= D) {
-    step(j, ring[0], ring[1]);
-    if (j - 1 < 0) break;
-    step(j - 1, ring[1], ring[2]);
-    if (j - 2 < 0) break;
-    step(j - 2, ring[2], ring[0]);
   }
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -1948,14 +1957,15 @@ hipError_t heig_topk(const double* Gpart, int nsum, int64_t part_stride, int m, 
   // 4. back-transformation
   const size_t sm4 = ((size_t)m * 8 + m) * sizeof(cx<double>);
   if (stages & HEIG_BACKXF) {
-    const size_t sm5 = (size_t)2 * m * sizeof(cx<double>);
+    // two LDS groups of NB reflectors: 4 up to m = 448 (56 KB), 2 above
+    const size_t sm5a = (size_t)2 * 4 * m * sizeof(cx<double>), sm5b = (size_t)2 * 2 * m * sizeof(cx<double>);
     const dim3 g5(batch, (k + 7) / 8);
     if (m <= 8 * 32)
-      hipLaunchKernelGGL(heig_backxf2_kernel<8>, g5, dim3(256), sm5, s, m, k, sc, per, (cx<double>*)W);
+      hipLaunchKernelGGL((heig_backxf2_kernel<8, 4>), g5, dim3(256), sm5a, s, m, k, sc, per, (cx<double>*)W);
     else if (m <= 14 * 32)
-      hipLaunchKernelGGL(heig_backxf2_kernel<14>, g5, dim3(256), sm5, s, m, k, sc, per, (cx<double>*)W);
+      hipLaunchKernelGGL((heig_backxf2_kernel<14, 4>), g5, dim3(256), sm5a, s, m, k, sc, per, (cx<double>*)W);
     else if (m <= 20 * 32)
-      hipLaunchKernelGGL(heig_backxf2_kernel<20>, g5, dim3(256), sm5, s, m, k, sc, per, (cx<double>*)W);
+      hipLaunchKernelGGL((heig_backxf2_kernel<20, 2>), g5, dim3(256), sm5b, s, m, k, sc, per, (cx<double>*)W);
     else
       hipLaunchKernelGGL(heig_backxf_kernel, dim3(batch, (k + 7) / 8), dim3(256), sm4, s, m, k, sc, per,
                          (cx<double>*)W);
