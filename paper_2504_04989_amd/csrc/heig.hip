@@ -469,12 +469,12 @@ __device__ __forceinline__ void cfmac(cx<double>& a, cx<double> x, cx<double> y)
   a.im = fma(x.re, y.im, fma(-x.im, y.re, a.im));
 }
 
-template <int NW = T2_W>
+template <int NW = T2_W, bool LEAD_SYNC = true>
 __device__ __forceinline__ cx<double> block_sum2(cx<double> v, double* red) {
   v.re = wave_sum(v.re);
   v.im = wave_sum(v.im);
   const int w = threadIdx.x >> 6;
-  __syncthreads();
+  if (LEAD_SYNC) __syncthreads();  // (skipped when red has not been read since the last barrier)
   if ((threadIdx.x & 63) == 0) {
     red[2 * w] = v.re;
     red[2 * w + 1] = v.im;
@@ -1081,6 +1081,7 @@ __global__ __launch_bounds__(RES_NT, 1) void heig_trires_kernel(const cx<double>
   __shared__ cx<double> wv_[1024];    // w of the step (0 outside)
   __shared__ unsigned long long yq[2 * 1024];  // this workgroup's share of y, fixed point
   __shared__ double red[2 * RES_W];
+  __shared__ double red2[2][RES_W];  // per-wave partials of the next step's ||x||^2, by step parity
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int f = blockIdx.x / P, pg = blockIdx.x - f * P;
   const bool lead = pg == 0;
@@ -1144,8 +1145,14 @@ __global__ __launch_bounds__(RES_NT, 1) void heig_trires_kernel(const cx<double>
     cx<double>* cxb = colx + (int64_t)buf * MP;
     // (1) reflector from alpha = col[i + 1], x = col[i + 2 .. m - 1] (every workgroup)
     double s2 = 0;
-    for (int r = i + 2 + tid; r < m; r += RES_NT) s2 += col[r].re * col[r].re + col[r].im * col[r].im;
-    s2 = block_sum2<RES_W>(cx<double>{s2, 0.0}, red).re;
+    if (i == 0) {
+      for (int r = i + 2 + tid; r < m; r += RES_NT) s2 += col[r].re * col[r].re + col[r].im * col[r].im;
+      s2 = block_sum2<RES_W>(cx<double>{s2, 0.0}, red).re;
+    } else {
+      // formed with the column update of the previous step
+#pragma unroll
+      for (int w = 0; w < RES_W; ++w) s2 += red2[i & 1][w];
+    }
     // every thread forms the same reflector from the same operands
     const double ar = col[i + 1].re, ai = col[i + 1].im;
     const bool skip = s2 == 0.0 && ai == 0.0;
@@ -1255,7 +1262,7 @@ __global__ __launch_bounds__(RES_NT, 1) void heig_trires_kernel(const cx<double>
         cfmac(dot, wl[u], vcur[r]);
       }
     }
-    dot = block_sum2<RES_W>(dot, red);
+    dot = block_sum2<RES_W, false>(dot, red);
     const cx<double> alpha = cmulc(cx<double>{-0.5 * tau.re, -0.5 * tau.im}, dot);
     const bool zero = tau.re == 0.0 && tau.im == 0.0;
 #pragma unroll
@@ -1292,8 +1299,10 @@ __global__ __launch_bounds__(RES_NT, 1) void heig_trires_kernel(const cx<double>
         }
       }
     }
-    // (6) column i + 1 after this step's update, in every workgroup
+    // (6) column i + 1 after this step's update, in every workgroup, and the
+    // per-wave partial sums of ||col[i + 3 ..]||^2 for the next reflector
     const cx<double> vi = vcur[i + 1], wi = wv_[i + 1];
+    double s2n = 0;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int r = i + 1 + tid + u * RES_NT;
@@ -1304,8 +1313,11 @@ __global__ __launch_bounds__(RES_NT, 1) void heig_trires_kernel(const cx<double>
         cfmac(x, vi, nw);
         if (r == i + 1) x.im = 0.0;
         col[r] = x;
+        if (r >= i + 3) s2n += x.re * x.re + x.im * x.im;
       }
     }
+    s2n = wave_sum(s2n);
+    if (lane == 0) red2[(i + 1) & 1][wv] = s2n;
     __syncthreads();
   }
   if (tid == 0 && lead) {
