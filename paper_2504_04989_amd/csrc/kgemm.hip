@@ -2,19 +2,19 @@
 // Fourier slice f, with A_f the large n1 x n2 slice of the transformed data
 // (FP32 interleaved complex) and X_f a thin block of N columns.
 //
-// Complex arithmetic as one real GEMM over the interleaved storage.  A row of
-// A_f read as reals is a vector of length 2 n2, so
-//   C = A X   :  C[m][2n+t] = sum_{k,s} A_int[m][2k+s] Xe[2n+t][2k+s]
-//                Xe[2n][2k] = xr, Xe[2n][2k+1] = -xi, Xe[2n+1][2k] = xi, Xe[2n+1][2k+1] = xr
-//   C = A^H Y :  C[j][2n+t] = sum_{i,s} A_int[i][2j+s] Ye[2n+t][2i+s]
-//                Ye[2n][2i] = yr, Ye[2n][2i+1] = yi, Ye[2n+1][2i] = yi, Ye[2n+1][2i+1] = -yr
-// with x = X[k][n], y = Y[i][n].  In both cases the thin, expanded operand
-// (Xe or Ye, 2N rows) is the MFMA A operand and is staged through LDS; the big
-// operand A_f is the MFMA B operand and goes from HBM straight into the
-// registers of one wave, which uses it for all 2N output rows: every element
-// of A_f is read from HBM once per product.  The output tile of a wave is
-// (2N real rows) x (16 TB big-dimension columns), i.e. C rows of the complex
-// result, written as contiguous (re, im) pairs.
+// Complex arithmetic as real MFMA over the interleaved storage.  Along K the
+// operands are read as (re, im) pairs, and each part of a complex result is
+// one real dot product over 2K terms:
+//   C = A X   :  Re C[m][n] = sum_k <(ar, ai), (xr, -xi)>,  Im C[m][n] = sum_k <(ai, -ar), (xr, -xi)>
+//   C = A^H Y :  Re C[j][n] = sum_i <(ar, ai), (yr, yi)>,   Im C[j][n] = sum_i <(-ai, ar), (yr, yi)>
+// with a = A[m][k] (A[i][j]), x = X[k][n], y = Y[i][n].  The thin operand,
+// conjugated for A X, is the MFMA A operand: one row per complex column,
+// staged through LDS.  The big operand A_f is the MFMA B operand in two forms
+// (as loaded for the real parts; each pair swapped and one sign flipped for
+// the imaginary parts) and goes from HBM straight into the registers of one
+// wave, which uses it for all N columns: every element of A_f is read from
+// HBM once per product.  The output tile of a wave is (N complex columns) x
+// (16 TB big-dimension rows), written as contiguous (re, im) pairs.
 //
 // Precision modes: FP32 (v_mfma_f32_16x16x4_f32), BF16 (one bf16 product,
 // v_mfma_f32_16x16x32_bf16) and BF16x3 (x = hi + lo with hi = bf16(x),
@@ -82,12 +82,12 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   // three-product BF16; PRE: both operands arrive as (hi, lo) bf16 pairs
   constexpr bool X3 = MODE == KM_BF16X3 || MODE == KM_BF16X3_SPLIT;
   constexpr bool PRE = MODE == KM_BF16X3_SPLIT;
-  constexpr int ROWS = TT * 16;
-  constexpr int PLANE = ROWS * L::STRIDE;
-  constexpr int BUF = PLANE * L::PLANES;
   constexpr int NCH = TT * 8;                 // complex thin columns per tile
+  constexpr int TC = NCH / 16;                // MFMA tiles of 16 complex columns
+  constexpr int PLANE = NCH * L::STRIDE;      // one LDS row per complex column
+  constexpr int BUF = PLANE * L::PLANES;
   constexpr int TEL = KSTEP * NCH / 256;      // thin elements per thread per step
-  static_assert(TEL * 256 == KSTEP * NCH, "thin split");
+  static_assert(TEL * 256 == KSTEP * NCH && TC * 16 == NCH && TEL == TC && KSTEP == 4 * NWAVE, "thin split");
   extern __shared__ __align__(16) uint32_t lds[];
 
   // ---- tile of this workgroup (XCD-aware order) ----
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   }
   const int n0 = tc * NCH;
   const int nc = min(NCH, a.N - n0);
-  const int tt = FULL ? TT : (2 * nc + 15) / 16;  // active thin tiles (all of them when FULL)
+  const int tt = FULL ? TC : (nc + 15) / 16;  // active thin tiles (all of them when FULL)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int q4 = lane >> 4, r16 = lane & 15;
@@ -146,19 +146,16 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
     colc[u] = colok[u] ? col[u] : a.M - 1;  // clamped: loads stay in bounds, results unused
   }
 
-  // Thin column of element e of this thread (k = idx mod KSTEP is the
-  // thread's K index).  In the BF16 forms the four 16-lane groups of a wave
-  // take columns 2 apart, so the LDS rows they store start 4 STRIDE = 80
-  // words (16 banks modulo 64) apart and a wave's stores do not collide.
-  auto thin_col = [&](int t, int e) {
-    if (MODE == KM_F32) return (t + e * 256) / KSTEP;
-    const int w = t >> 6, g = (t >> 4) & 3;
-    return 16 * e + 8 * (w & 1) + (w >> 1) + 2 * g;
-  };
-
+  // Thin element e of this thread: K index 4 wave + q4 of the step, complex
+  // column 16 e + r16.  A wave's global loads read 16 consecutive columns of
+  // 4 rows, and its LDS stores (row = column, word = K index) fall in 64
+  // distinct banks: the rows of a 16-lane group start 20 (36) words apart,
+  // i.e. at distinct multiples of 4 modulo 64.
+  const int tk = 4 * wave + q4;
   // ---- full K steps: every load is issued unconditionally (clamped
-  // addresses, zero by select) so that the compiler's wait counts can leave
-  // the prefetches of later steps in flight ----
+  // addresses; a clamped row or column feeds only results that are never
+  // stored) so that the compiler's wait counts can leave the prefetches of
+  // later steps in flight ----
   auto load_big_full = [&](int k0, float (&v)[TB][8]) {
 #pragma unroll
     for (int u = 0; u < TB; ++u) {
@@ -190,11 +187,12 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   auto load_thin_full = [&](int k0, float2 (&x)[TEL]) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
-      const int idx = tid + e * 256;
-      const int kk = idx % KSTEP, nn = thin_col(tid, e);
-      const bool ok = nn < nc;
-      const float2 v = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + kk) * a.ldx + 2 * (n0 + (ok ? nn : 0)));
-      x[e] = ok ? v : make_float2(0.f, 0.f);
+      // a column past nc reads column n0 instead: it feeds only its own
+      // result column, which is never stored, so it need not be zeroed (a
+      // select here would let the compiler turn the load into a branch that
+      // waits for it)
+      const int nn = 16 * e + r16;
+      x[e] = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + tk) * a.ldx + 2 * (n0 + (nn < nc ? nn : 0)));
     }
   };
 
@@ -237,60 +235,59 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   auto load_thin = [&](int k0, float2 (&x)[TEL]) {
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
-      const int idx = tid + e * 256;
-      const int kk = idx % KSTEP, nn = thin_col(tid, e);
+      const int nn = 16 * e + r16;
       float2 v = make_float2(0.f, 0.f);
-      if (k0 + kk < ke && nn < nc) v = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + kk) * a.ldx + 2 * (n0 + nn));
+      if (k0 + tk < ke && nn < nc) v = *reinterpret_cast<const float2*>(Xf + (int64_t)(k0 + tk) * a.ldx + 2 * (n0 + nn));
       x[e] = v;
     }
   };
+  // the thin operand in LDS: row nn holds column nn of X (conjugated for
+  // A X) as (re, im) pairs, FP32 or bf16 (hi and lo planes for BF16x3)
   auto store_thin = [&](uint32_t* buf, const float2 (&x)[TEL]) {
+    constexpr uint32_t CJ = HN ? 0u : 0x80000000u;  // sign of the imaginary half
 #pragma unroll
     for (int e = 0; e < TEL; ++e) {
-      const int idx = tid + e * 256;
-      const int kk = idx % KSTEP, nn = thin_col(tid, e);
+      uint32_t* row = buf + (16 * e + r16) * L::STRIDE;
       const float xr = x[e].x, xi = x[e].y;
-      // rows 2nn (real part of the output) and 2nn + 1 (imaginary part):
-      //   A X  : (xr, -xi), (xi, xr);   A^H Y : (xr, xi), (xi, -xr)
-      uint32_t* row0 = buf + (2 * nn) * L::STRIDE;
-      uint32_t* row1 = row0 + L::STRIDE;
       if (MODE == KM_F32) {
-        *reinterpret_cast<float2*>(row0 + 2 * kk) = make_float2(xr, HN ? xi : -xi);
-        *reinterpret_cast<float2*>(row1 + 2 * kk) = make_float2(xi, HN ? -xr : xr);
+        *reinterpret_cast<float2*>(row + 2 * tk) = make_float2(xr, HN ? xi : -xi);
       } else if (PRE) {
-        // x.x = (re_hi | im_hi << 16), x.y = (re_lo | im_lo << 16): the rows
-        // are these words with the halves swapped and / or a sign flipped
-        const uint32_t h = __float_as_uint(xr), l = __float_as_uint(xi);
-        row0[kk] = HN ? h : (h ^ 0x80000000u);
-        row1[kk] = HN ? (swap16(h) ^ 0x80000000u) : swap16(h);
-        row0[PLANE + kk] = HN ? l : (l ^ 0x80000000u);
-        row1[PLANE + kk] = HN ? (swap16(l) ^ 0x80000000u) : swap16(l);
+        // x.x = (re_hi | im_hi << 16), x.y = (re_lo | im_lo << 16)
+        row[tk] = __float_as_uint(xr) ^ CJ;
+        row[PLANE + tk] = __float_as_uint(xi) ^ CJ;
       } else {
-        // each value is rounded once; negation flips the bf16 sign bit
+        // each value is rounded once; conjugation flips the bf16 sign bit
         const __bf16 hr = (__bf16)xr, hi = (__bf16)xi;
-        const uint32_t br = (uint32_t)__builtin_bit_cast(unsigned short, hr);
-        const uint32_t bi = (uint32_t)__builtin_bit_cast(unsigned short, hi);
-        row0[kk] = HN ? (br | (bi << 16)) : (br | ((bi ^ 0x8000u) << 16));
-        row1[kk] = HN ? (bi | ((br ^ 0x8000u) << 16)) : (bi | (br << 16));
-        if (MODE == KM_BF16X3) {
-          const uint32_t lr = bf16_bits(xr - (float)hr), li = bf16_bits(xi - (float)hi);
-          row0[PLANE + kk] = HN ? (lr | (li << 16)) : (lr | ((li ^ 0x8000u) << 16));
-          row1[PLANE + kk] = HN ? (li | ((lr ^ 0x8000u) << 16)) : (li | (lr << 16));
-        }
+        row[tk] = ((uint32_t)__builtin_bit_cast(unsigned short, hr) |
+                   ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16)) ^ CJ;
+        if (MODE == KM_BF16X3)
+          row[PLANE + tk] = (bf16_bits(xr - (float)hr) | (bf16_bits(xi - (float)hi) << 16)) ^ CJ;
       }
     }
   };
 
-  f32x4 acc[TT][TB];
+  f32x4 accr[TC][TB], acci[TC][TB];  // real and imaginary parts
 #pragma unroll
-  for (int i = 0; i < TT; ++i)
+  for (int i = 0; i < TC; ++i)
 #pragma unroll
-    for (int u = 0; u < TB; ++u) acc[i][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < TB; ++u) {
+      accr[i][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+      acci[i][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
 
   auto compute = [&](const uint32_t* buf, const float (&v)[TB][8]) {
     if (MODE == KM_F32) {
+      // B operand of the imaginary parts: (ai, -ar) for A X, (-ai, ar) for A^H Y
+      float sv[TB][8];
 #pragma unroll
-      for (int i = 0; i < TT; ++i) {
+      for (int u = 0; u < TB; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          sv[u][2 * c] = HN ? -v[u][2 * c + 1] : v[u][2 * c + 1];
+          sv[u][2 * c + 1] = HN ? v[u][2 * c] : -v[u][2 * c];
+        }
+#pragma unroll
+      for (int i = 0; i < TC; ++i) {
         if (i < tt) {
           const float* rowp = reinterpret_cast<const float*>(buf + (16 * i + r16) * L::STRIDE + 8 * q4);
           const float4 w0 = *reinterpret_cast<const float4*>(rowp);
@@ -299,32 +296,44 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
 #pragma unroll
           for (int b = 0; b < 8; ++b)
 #pragma unroll
-            for (int u = 0; u < TB; ++u) acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[b], v[u][b], acc[i][u], 0, 0, 0);
+            for (int u = 0; u < TB; ++u) {
+              accr[i][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[b], v[u][b], accr[i][u], 0, 0, 0);
+              acci[i][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[b], sv[u][b], acci[i][u], 0, 0, 0);
+            }
         }
       }
     } else {
-      bf16x8 bh[TB], bl[TB];
+      // words (re | im << 16) of the lane's four complex values; the
+      // imaginary parts' operand swaps the halves and flips one sign
+      constexpr uint32_t SF = HN ? 0x00008000u : 0x80000000u;
+      bf16x8 bh[TB], bl[TB], sh[TB], sl[TB];
 #pragma unroll
       for (int u = 0; u < TB; ++u) {
-        if (PRE) {
-          // complex c of the lane's four: word 2c = hi pair, word 2c + 1 = lo pair
-          const uint4 wh = make_uint4(__float_as_uint(v[u][0]), __float_as_uint(v[u][2]), __float_as_uint(v[u][4]),
-                                      __float_as_uint(v[u][6]));
-          const uint4 wl = make_uint4(__float_as_uint(v[u][1]), __float_as_uint(v[u][3]), __float_as_uint(v[u][5]),
-                                      __float_as_uint(v[u][7]));
-          bh[u] = __builtin_bit_cast(bf16x8, wh);
-          bl[u] = __builtin_bit_cast(bf16x8, wl);
-        } else {
+        uint32_t wh[4], wl[4];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const __bf16 h = (__bf16)v[u][j];
-            bh[u][j] = h;
-            if (X3) bl[u][j] = (__bf16)(v[u][j] - (float)h);
+        for (int c = 0; c < 4; ++c) {
+          if (PRE) {
+            // complex c of the lane's four: word 2c = hi pair, word 2c + 1 = lo pair
+            wh[c] = __float_as_uint(v[u][2 * c]);
+            wl[c] = __float_as_uint(v[u][2 * c + 1]);
+          } else {
+            const __bf16 hr = (__bf16)v[u][2 * c], hi = (__bf16)v[u][2 * c + 1];
+            wh[c] = (uint32_t)__builtin_bit_cast(unsigned short, hr) |
+                    ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+            wl[c] = X3 ? (bf16_bits(v[u][2 * c] - (float)hr) | (bf16_bits(v[u][2 * c + 1] - (float)hi) << 16)) : 0u;
           }
+        }
+        bh[u] = __builtin_bit_cast(bf16x8, make_uint4(wh[0], wh[1], wh[2], wh[3]));
+        sh[u] = __builtin_bit_cast(bf16x8, make_uint4(swap16(wh[0]) ^ SF, swap16(wh[1]) ^ SF, swap16(wh[2]) ^ SF,
+                                                      swap16(wh[3]) ^ SF));
+        if (X3) {
+          bl[u] = __builtin_bit_cast(bf16x8, make_uint4(wl[0], wl[1], wl[2], wl[3]));
+          sl[u] = __builtin_bit_cast(bf16x8, make_uint4(swap16(wl[0]) ^ SF, swap16(wl[1]) ^ SF, swap16(wl[2]) ^ SF,
+                                                        swap16(wl[3]) ^ SF));
         }
       }
 #pragma unroll
-      for (int i = 0; i < TT; ++i) {
+      for (int i = 0; i < TC; ++i) {
         if (i < tt) {
           const uint32_t* rowp = buf + (16 * i + r16) * L::STRIDE + 4 * q4;
           const bf16x8 th = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(rowp));
@@ -332,14 +341,19 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
             const bf16x8 tl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(rowp + PLANE));
 #pragma unroll
             for (int u = 0; u < TB; ++u) {
-              acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tl, bh[u], acc[i][u], 0, 0, 0);
-              acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bl[u], acc[i][u], 0, 0, 0);
-              acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bh[u], acc[i][u], 0, 0, 0);
+              accr[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tl, bh[u], accr[i][u], 0, 0, 0);
+              accr[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bl[u], accr[i][u], 0, 0, 0);
+              accr[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bh[u], accr[i][u], 0, 0, 0);
+              acci[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tl, sh[u], acci[i][u], 0, 0, 0);
+              acci[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, sl[u], acci[i][u], 0, 0, 0);
+              acci[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, sh[u], acci[i][u], 0, 0, 0);
             }
           } else {
 #pragma unroll
-            for (int u = 0; u < TB; ++u)
-              acc[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bh[u], acc[i][u], 0, 0, 0);
+            for (int u = 0; u < TB; ++u) {
+              accr[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, bh[u], accr[i][u], 0, 0, 0);
+              acci[i][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, sh[u], acci[i][u], 0, 0, 0);
+            }
           }
         }
       }
@@ -363,6 +377,13 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
     store_thin(lds, tx);
   }
   __syncthreads();
+  // Step s of the ring (steps past the last full one only load and store
+  // clamped data).  The LDS store and the barrier are unconditional, so that
+  // the thin loads have a use outside the guarded MFMA phase and stay ahead of
+  // the A_f prefetch (sunk into that phase they would follow it, and the wait
+  // before the store would also wait for the prefetch).  A store past the
+  // last full step rewrites, with the same thread's words, a buffer that no
+  // later full step reads, after the barrier of the step that last read it.
   auto step = [&](int s, const float (&cur)[TB][8], float (&pre)[TB][8]) {
     const int sn = s + 1 < nfull ? s + 1 : nfull - 1;
     const int sp2 = s + 2 < nfull ? s + 2 : nfull - 1;
@@ -374,9 +395,9 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
       __builtin_amdgcn_s_setprio(1);
       compute(lds + (s & 1) * BUF, cur);
       __builtin_amdgcn_s_setprio(0);
-      if (s + 1 < nfull) store_thin(lds + ((s + 1) & 1) * BUF, tx);
-      __syncthreads();
     }
+    store_thin(lds + ((s + 1) & 1) * BUF, tx);
+    __syncthreads();
   };
   for (int s = 0; s < nfull; s += 3) {
     step(s, bq0, bq2);
@@ -392,7 +413,7 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
     compute(lds + (nfull & 1) * BUF, bq0);
   }
 
-  // ---- epilogue: acc[i][u][r] = C_int[col][16 i + 4 q4 + r] -> complex n = n0 + 8 i + 2 q4 + {0, 1} ----
+  // ---- epilogue: accr / acci[i][u][r] = parts of C[col][n0 + 16 i + 4 q4 + r] ----
   float* out;
   int64_t ldo;
   if (rt >= 0) {
@@ -409,15 +430,16 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
     ldo = a.ldc;
   }
 #pragma unroll
-  for (int i = 0; i < TT; ++i) {
+  for (int i = 0; i < TC; ++i) {
     if (i < tt) {
-      const int n = n0 + 8 * i + 2 * q4;
+      const int n = n0 + 16 * i + 4 * q4;
 #pragma unroll
       for (int u = 0; u < TB; ++u) {
         if (!colok[u]) continue;
         float* p = out + (int64_t)col[u] * ldo + 2 * n;
-        if (n < a.N) *reinterpret_cast<float2*>(p) = make_float2(acc[i][u][0], acc[i][u][1]);
-        if (n + 1 < a.N) *reinterpret_cast<float2*>(p + 2) = make_float2(acc[i][u][2], acc[i][u][3]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (n + r < a.N) *reinterpret_cast<float2*>(p + 2 * r) = make_float2(accr[i][u][r], acci[i][u][r]);
       }
     }
   }
@@ -491,7 +513,7 @@ __global__ void kgemm_tail_reduce_kernel(const float2* __restrict__ part, int nf
 template <int MODE, bool HN, int TT, bool AVEC, bool FULL>
 hipError_t launch_ttaf(const KArgs& a, hipStream_t s) {
   constexpr int TB = 2;
-  const size_t lds = (size_t)2 * TT * 16 * Lds<MODE>::STRIDE * Lds<MODE>::PLANES * 4;
+  const size_t lds = (size_t)2 * TT * 8 * Lds<MODE>::STRIDE * Lds<MODE>::PLANES * 4;
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void*)kgemm_kernel<MODE, HN, TT, TB, AVEC, FULL>,
@@ -509,7 +531,7 @@ template <int MODE, bool HN, int TT, bool AVEC>
 hipError_t launch_tta(const KArgs& a, hipStream_t s) {
   constexpr int NCH = TT * 8;
   const int nlast = a.N - (a.nthin - 1) * NCH;
-  if ((2 * nlast + 15) / 16 == TT) return launch_ttaf<MODE, HN, TT, AVEC, true>(a, s);
+  if ((nlast + 15) / 16 == TT / 2) return launch_ttaf<MODE, HN, TT, AVEC, true>(a, s);
   return launch_ttaf<MODE, HN, TT, AVEC, false>(a, s);
 }
 
