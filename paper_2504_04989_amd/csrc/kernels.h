@@ -37,9 +37,8 @@ hipError_t zgemm(const GemmDesc& d, hipStream_t s);
 // nsplit * batch * M * N complex FP32 values (reduced in a fixed order).
 // KM_BF16X3_SPLIT: BF16x3 with the big operand already stored as (hi, lo)
 // bf16 pairs (fft_r2c_split's output form, 8 bytes per complex element); the
-// thin operand is split once per call into xsplit (batch x K x N pairs)
-// instead of in every workgroup.  Same products in the same order as
-// KM_BF16X3: the results are bitwise equal.
+// thin operand is complex FP32 and split as it is staged, as in KM_BF16X3.
+// Same products in the same order as KM_BF16X3: the results are bitwise equal.
 enum KMode { KM_F32 = 0, KM_BF16 = 1, KM_BF16X3 = 2, KM_BF16X3_SPLIT = 3 };
 struct KGemmDesc {
   const void* A; int64_t lda, strideA; int rows, cols; bool herm;
@@ -48,7 +47,6 @@ struct KGemmDesc {
   int N, batch, mode, nsplit;
   void* part;
   size_t part_bytes;  // size of part; a tail split is used only when it fits
-  void* xsplit;       // KM_BF16X3_SPLIT: batch * K * N * 8 bytes for the split thin operand
 };
 hipError_t kgemm(const KGemmDesc& d, hipStream_t s);
 // n complex FP32 values -> n (hi, lo) bf16 pairs (the KM_BF16X3_SPLIT form).

@@ -79,7 +79,7 @@ __device__ __forceinline__ uint32_t swap16(uint32_t x) { return (x >> 16) | (x <
 template <int MODE, bool HN, int TT, int TB, bool AVEC, bool FULL>
 __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   typedef Lds<MODE> L;
-  // three-product BF16; PRE: both operands arrive as (hi, lo) bf16 pairs
+  // three-product BF16; PRE: the big operand arrives as (hi, lo) bf16 pairs
   constexpr bool X3 = MODE == KM_BF16X3 || MODE == KM_BF16X3_SPLIT;
   constexpr bool PRE = MODE == KM_BF16X3_SPLIT;
   constexpr int NCH = TT * 8;                 // complex thin columns per tile
@@ -251,17 +251,12 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
       const float xr = x[e].x, xi = x[e].y;
       if (MODE == KM_F32) {
         *reinterpret_cast<float2*>(row + 2 * tk) = make_float2(xr, HN ? xi : -xi);
-      } else if (PRE) {
-        // x.x = (re_hi | im_hi << 16), x.y = (re_lo | im_lo << 16)
-        row[tk] = __float_as_uint(xr) ^ CJ;
-        row[PLANE + tk] = __float_as_uint(xi) ^ CJ;
       } else {
         // each value is rounded once; conjugation flips the bf16 sign bit
         const __bf16 hr = (__bf16)xr, hi = (__bf16)xi;
         row[tk] = ((uint32_t)__builtin_bit_cast(unsigned short, hr) |
                    ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16)) ^ CJ;
-        if (MODE == KM_BF16X3)
-          row[PLANE + tk] = (bf16_bits(xr - (float)hr) | (bf16_bits(xi - (float)hi) << 16)) ^ CJ;
+        if (X3) row[PLANE + tk] = (bf16_bits(xr - (float)hr) | (bf16_bits(xi - (float)hi) << 16)) ^ CJ;
       }
     }
   };
@@ -445,9 +440,9 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
   }
 }
 
-// Thin operand of KM_BF16X3_SPLIT: Xs[f][k][n] = (hi, lo) bf16 pairs of
-// X[f][k][n] (complex FP32, row stride ldx, slice stride strideX, in floats),
-// dense K x N per slice.
+// (hi, lo) bf16 pairs, the big-operand form of KM_BF16X3_SPLIT:
+// Xs[f][k][n] = pairs of X[f][k][n] (complex FP32, row stride ldx, slice
+// stride strideX, in floats), dense K x N per slice.
 __global__ void kgemm_split_thin_kernel(const float* __restrict__ X, int64_t ldx, int64_t strideX, int K, int N,
                                         int batch, uint2* __restrict__ Xs) {
   const int64_t per = (int64_t)K * N, total = per * batch;
@@ -694,19 +689,9 @@ hipError_t kgemm(const KGemmDesc& d, hipStream_t s) {
     case KM_BF16X3:
       e = d.herm ? launch_mode<KM_BF16X3, true>(a, TT, s) : launch_mode<KM_BF16X3, false>(a, TT, s);
       break;
-    case KM_BF16X3_SPLIT: {
-      if (!d.xsplit) return hipErrorInvalidValue;
-      const int64_t n = (int64_t)K * d.N * d.batch;
-      const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
-      hipLaunchKernelGGL(kgemm_split_thin_kernel, dim3(blocks), dim3(256), 0, s, a.X, a.ldx, a.strideX, K, d.N,
-                         d.batch, static_cast<uint2*>(d.xsplit));
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      a.X = static_cast<const float*>(d.xsplit);
-      a.ldx = 2 * (int64_t)d.N;
-      a.strideX = 2 * (int64_t)K * d.N;
+    case KM_BF16X3_SPLIT:
       e = d.herm ? launch_mode<KM_BF16X3_SPLIT, true>(a, TT, s) : launch_mode<KM_BF16X3_SPLIT, false>(a, TT, s);
       break;
-    }
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;

@@ -61,7 +61,6 @@ struct Plan {
   size_t o_cbuf, o_xbuf, o_uo, o_so, o_vo;  // completion: C^(n), X^(n) and the factors of L
   size_t o_lam1, o_w1, o_w1m, o_p, o_t1, o_lam2, o_w2, o_rk, o_split;  // FP64 small SVD, second pass
   size_t o_omsp;  // the spatial test tensor drawn from the seed (n2 x b x n3, storage type)
-  size_t o_xsplit;  // KM_BF16X3_SPLIT: the thin operand as (hi, lo) bf16 pairs
   size_t o_vr, o_sr;  // truncated basis: spatial V and S of its Ritz step (scratch outputs)
   // adjoint through the rank-k truncation: all eigenpairs of C C^H, four
   // m x m FP64 matrices, the modified cotangents U2 Pi + T H and T Pi
@@ -240,7 +239,6 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
   const size_t cs = p->cs;
   p->o_info = take(256);
   p->o_omsp = take(tensor_op ? 0 : (size_t)n2 * b * n3 * (p->dt == DT_F64 ? 8 : 4));
-  p->o_xsplit = take(p->asplit ? (size_t)F * std::max(n1, n2) * b * 8 : 0);
   p->o_abar = take((size_t)F * n1 * n2 * cs);
   p->o_obar = take(tensor_op ? 0 : (size_t)F * n2 * b * cs);
   p->o_q = take((size_t)F * n1 * m * cs);
@@ -644,7 +642,6 @@ int big_AX(const Ctx& c, const void* X, int64_t ldx, int64_t strideX, void* Out,
     k.N = N;
     k.batch = (int)p.F;
     k.mode = p.asplit ? KM_BF16X3_SPLIT : p.kmode;
-    k.xsplit = p.asplit ? c.at(p.o_xsplit) : nullptr;
     k.nsplit = N == p.b ? p.ks_ax : 1;
     k.part = c.at(p.o_kpart);
     k.part_bytes = p.kpart_bytes;
@@ -701,7 +698,6 @@ int big_AhY(const Ctx& c, const void* Y, int64_t ldy, int64_t strideY, void* Out
     k.N = N;
     k.batch = (int)p.F;
     k.mode = p.asplit ? KM_BF16X3_SPLIT : p.kmode;
-    k.xsplit = p.asplit ? c.at(p.o_xsplit) : nullptr;
     k.nsplit = N == p.b ? p.ks_ahy : 1;
     k.part = c.at(p.o_kpart);
     k.part_bytes = p.kpart_bytes;
@@ -1927,7 +1923,6 @@ size_t tsvd_diag_kgemm_ws_bytes(int herm, int64_t rows, int64_t cols, int64_t N,
   size_t bytes = nsplit > 1 ? align256((size_t)nsplit * batch * M * N * 8) : 0;
   if (mode == KM_BF16) bytes += align256(kgemm_bf16_pack_bytes(mode, (int)K, (int)N, (int)batch));
   else if (nsplit == 1) bytes += align256(kgemm_part_bytes((int)M, (int)K, (int)N, (int)batch, 1));
-  if (mode == KM_BF16X3_SPLIT) bytes += align256((size_t)batch * K * N * 8);
   return bytes;
 }
 
@@ -1959,15 +1954,9 @@ int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t row
   unsigned char* w = static_cast<unsigned char*>(ws);
   d.part = nsplit > 1 ? w : nullptr;
   d.part_bytes = nsplit > 1 ? (size_t)nsplit * batch * M * N * 8 : 0;
-  size_t xs_bytes = 0;
-  if (mode == KM_BF16X3_SPLIT) {
-    // the split thin operand at the end of the workspace
-    xs_bytes = align256((size_t)batch * K * N * 8);
-    d.xsplit = w + need - xs_bytes;
-  }
-  if (nsplit == 1 && mode != KM_BF16 && need - xs_bytes > 0) {
+  if (nsplit == 1 && mode != KM_BF16 && need > 0) {
     d.part = w;
-    d.part_bytes = need - xs_bytes;
+    d.part_bytes = need;
   }
   void* pack = w + (nsplit > 1 ? align256((size_t)nsplit * batch * M * N * 8) : 0);
   if (mode == KM_BF16)
