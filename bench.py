@@ -78,10 +78,21 @@ def class_work(cls: str, c: dict, prec: str):
         # CholeskyQR passes per block: shifted + 1 (FP32 storage, when the
         # FP64 orthogonality bound allows it, else + 2); FP64 adds two more
         # shifted passes
+        # On FP32 storage the first projection pass (coefficients and update,
+        # 16 n1 (i b) b flops against block i) runs in FP32 arithmetic on the
+        # FP32 MFMA, the rest in FP64: the peak is the rate at which the mix
+        # would run with every part at its own published peak.
         passes = 5 if prec == "f64" else cholqr_passes(n1, b)
-        fl = sum(2 * 16.0 * n1 * (i * b) * b for i in range(1, q + 1)) + (q + 1) * passes * 8.0 * n1 * b * (b + 1)
-        w = {"flops": fl * F, "xf": 1.0, "bytes": None, "mfma_peak": PEAK["mfma_tflops"]["f64"] * 1e12,
-             "hbm_peak": hbm, "note": "algorithmic FP64 flops (Hermitian Grams and W R^-1 counted as upper halves)"}
+        proj = sum(16.0 * n1 * (i * b) * b for i in range(1, q + 1))
+        fl = 2 * proj + (q + 1) * passes * 8.0 * n1 * b * (b + 1)
+        fl32 = 0.0 if prec == "f64" else proj
+        p64, p32 = PEAK["mfma_tflops"]["f64"] * 1e12, PEAK["mfma_tflops"]["f32"] * 1e12
+        peak = fl / ((fl - fl32) / p64 + fl32 / p32)
+        w = {"flops": fl * F, "xf": 1.0, "bytes": None, "mfma_peak": peak,
+             "hbm_peak": hbm, "note": "algorithmic flops (Hermitian Grams and W R^-1 counted as upper halves); "
+                                      + ("FP64 arithmetic" if prec == "f64" else
+                                         "first projection pass in FP32 arithmetic, the rest in FP64; peak = "
+                                         "the mix's rate with each part at its published peak")}
     elif cls == "chol":        # b x b complex Cholesky + triangular inverse per slice, one per CholeskyQR pass
         passes = 5 if prec == "f64" else cholqr_passes(n1, b)
         return {"flops": passes * (q + 1) * F * (16.0 / 3.0 * b ** 3), "xf": 1.0, "bytes": None,

@@ -48,6 +48,15 @@ size_t tsvd_diag_kgemm_ws_bytes(int herm, int64_t rows, int64_t cols, int64_t N,
 int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t rows, int64_t cols, int64_t N,
                     int64_t batch, int mode, int nsplit, void* ws, size_t ws_bytes, void* stream);
 
+/* The Krylov-product kernel in its update form, C_f -= A_f X_f (the first
+ * Gram-Schmidt pass of the stabilised recursion on FP32 blocks, Alg. 2, with
+ * A_f the earlier basis columns and X_f their coefficients): A_f rows x cols,
+ * X_f cols x N, C_f rows x N, FP32 complex, contiguous slices; FP32 MFMA with
+ * FP32 accumulation, no split of the contraction.  Device pointers; C is
+ * read and written; asynchronous on stream.  TSVD_EINVAL on bad sizes. */
+int tsvd_diag_kgemm_sub(const void* A, const void* X, void* C, int64_t rows, int64_t cols, int64_t N,
+                        int64_t batch, void* stream);
+
 /* n complex FP32 values (interleaved re, im) -> n (hi, lo) bf16 pairs, the
  * operand form of mode 3 above: hi = bf16(z) and lo = bf16(z - hi) per part
  * (round to nearest even), stored as two 32-bit words re | im << 16 (8 bytes

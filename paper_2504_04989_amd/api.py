@@ -28,7 +28,7 @@ EXPORTS = ("tsvd_version", "tsvd_last_error", "tsvd_workspace_bytes", "tsvd_omeg
            "tsvd_rbk_approx_backward", "tsvd_rbk_approx_backward_omega", "tsvd_complete", "tsvd_complete_omega",
            "tsvd_tqr", "tsvd_tpinv", "tsvd_tpinv_default_rtol", "tsvd_proj", "tsvd_proj_omega", "tsvd_proj_backward",
            "tsvd_proj_backward_omega", "tsvd_read_info", "tsvd_diag_fft_r2c", "tsvd_diag_fft_c2r",
-           "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_split_bf16x3", "tsvd_diag_heig",
+           "tsvd_diag_zgemm", "tsvd_diag_kgemm", "tsvd_diag_kgemm_ws_bytes", "tsvd_diag_kgemm_sub", "tsvd_diag_split_bf16x3", "tsvd_diag_heig",
            "tsvd_diag_heig_ws_bytes", "tsvd_diag_timing", "tsvd_diag_timing_read", "tsvd_diag_omega")
 
 
@@ -109,6 +109,8 @@ def _load():
     lib.tsvd_diag_kgemm.restype = ctypes.c_int
     lib.tsvd_diag_kgemm.argtypes = [vp, ctypes.c_int, vp, vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_int, vp, sz,
                                     vp]
+    lib.tsvd_diag_kgemm_sub.restype = ci
+    lib.tsvd_diag_kgemm_sub.argtypes = [vp, vp, vp, i64, i64, i64, i64, vp]
     lib.tsvd_diag_omega.restype = ci
     lib.tsvd_diag_omega.argtypes = [vp, i64, u64, ci, vp]
     lib.tsvd_diag_heig_ws_bytes.restype = sz
@@ -559,6 +561,20 @@ def diag_kgemm(A, X, herm=False, mode="f32", nsplit=1):
     ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=A.device)
     _check(lib.tsvd_diag_kgemm(_ptr(A), int(herm), _ptr(X), _ptr(C), rows, cols, N, batch, KGEMM_MODE[mode], nsplit,
                                _ptr(ws), ws.numel(), _stream(A.device)))
+    return C
+
+
+def diag_kgemm_sub(A, X, C):
+    """The Krylov-product kernel's update form (see tsvd_diag_kgemm_sub):
+    C_f -= A_f X_f in place, complex64 tensors A (batch, rows, cols),
+    X (batch, cols, N) and C (batch, rows, N)."""
+    for name, t in (("A", A), ("X", X), ("C", C)):
+        _check_in(t, torch.complex64, name)
+    batch, rows, cols = A.shape
+    N = X.shape[2]
+    if tuple(X.shape) != (batch, cols, N) or tuple(C.shape) != (batch, rows, N):
+        raise ValueError("A (batch, rows, cols), X (batch, cols, N) and C (batch, rows, N) do not match")
+    _check(lib.tsvd_diag_kgemm_sub(_ptr(A), _ptr(X), _ptr(C), rows, cols, N, batch, _stream(A.device)))
     return C
 
 

@@ -47,6 +47,7 @@ struct KGemmDesc {
   int N, batch, mode, nsplit;
   void* part;
   size_t part_bytes;  // size of part; a tail split is used only when it fits
+  int sub;            // C -= op(A) X instead of C = op(A) X (no K split, no tail split)
 };
 hipError_t kgemm(const KGemmDesc& d, hipStream_t s);
 // n complex FP32 values -> n (hi, lo) bf16 pairs (the KM_BF16X3_SPLIT form).

@@ -59,6 +59,7 @@ struct KArgs {
   // rkchunk) and write their partials to part, one 128 x NCH block per
   // (tile, split).  rsplit == 0: no tail split.
   int nfull, nrem, rsplit, rkchunk;
+  int sub;  // C -= result (whole-K tiles written straight to C only)
 };
 
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
@@ -433,8 +434,16 @@ __global__ __launch_bounds__(256, 2) void kgemm_kernel(const KArgs a) {
         if (!colok[u]) continue;
         float* p = out + (int64_t)col[u] * ldo + 2 * n;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (n + r < a.N) *reinterpret_cast<float2*>(p + 2 * r) = make_float2(accr[i][u][r], acci[i][u][r]);
+        for (int r = 0; r < 4; ++r) {
+          if (n + r >= a.N) continue;
+          float2* o = reinterpret_cast<float2*>(p + 2 * r);
+          if (a.sub) {
+            const float2 c0 = *o;
+            *o = make_float2(c0.x - accr[i][u][r], c0.y - acci[i][u][r]);
+          } else {
+            *o = make_float2(accr[i][u][r], acci[i][u][r]);
+          }
+        }
       }
     }
   }
@@ -669,8 +678,10 @@ hipError_t kgemm(const KGemmDesc& d, hipStream_t s) {
   a.per = (a.total + 7) / 8;
   a.avec = ((d.lda & 1) == 0 && (d.strideA & 1) == 0 && ((uintptr_t)d.A & 15) == 0) ? 1 : 0;
   a.nfull = a.nrem = a.rsplit = a.rkchunk = 0;
+  a.sub = d.sub ? 1 : 0;
+  if (a.sub && a.nsplit > 1) return hipErrorInvalidValue;
   TailPlan tp{0, 0, 0, 0, 0};
-  if (a.nsplit == 1 && d.part) {
+  if (a.nsplit == 1 && d.part && !a.sub) {
     tp = kgemm_tail_plan(M, K, d.N, d.batch);
     if (tp.rsplit > 1 && d.part_bytes >= tp.bytes) {
       a.nfull = tp.nfull;

@@ -473,6 +473,7 @@ int kgemm_bf16_split(int M, int K, int N, int batch) {
 hipError_t kgemm_bf16(const KGemmDesc& d, void* pack, hipStream_t s) {
   const int M = d.herm ? d.cols : d.rows;
   const int K = d.herm ? d.rows : d.cols;
+  if (d.sub) return hipErrorInvalidValue;  // the update form is the FP32 kernel's only
   if (M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   // BF16x3 runs on the real-embedded kernel (kgemm), which measured faster
   // for three products per term at these register budgets.

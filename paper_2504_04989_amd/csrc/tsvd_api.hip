@@ -70,6 +70,8 @@ struct Plan {
       total;
 };
 
+size_t proj32_layout(int64_t ib, int64_t n1, int64_t b, int64_t F, int* nsplit, size_t* coef_off);
+
 int split_for(int64_t K, int64_t tiles, int64_t batch, int* kchunk) {
   int64_t ns = (K + 127) / 128;
   int64_t cap = std::max<int64_t>(1, 1024 / std::max<int64_t>(1, tiles * batch));
@@ -269,6 +271,9 @@ int make_plan(int64_t n1, int64_t n2, int64_t n3, int64_t k, int64_t b, int64_t 
       part = std::max(part, ogemm_tn_part_bytes((int)m, (int)n1, (int)n2, (int)F));
     }
     if (ritz) part = std::max(part, ogemm_tn_part_bytes((int)b, (int)n2, (int)b, (int)F));
+    // the FP32 first projection pass of the stabilised recursion
+    if (!power && !tensor_op)
+      for (int64_t i = 1; i <= q; ++i) part = std::max(part, proj32_layout(i * b, n1, b, F, nullptr, nullptr));
   }
   if (ritz) part = std::max(part, (size_t)p->nsplit_t * F * b * b * 16);
   p->o_part = take(part);
@@ -567,6 +572,77 @@ int project_out(const Ctx& c, void* W, int i) {
   return TSVD_OK;
 }
 
+// Bytes of o_part that project_out_f32 uses against ib earlier columns: the
+// K-split partials of the coefficient product, then the coefficients.
+size_t proj32_layout(int64_t ib, int64_t n1, int64_t b, int64_t F, int* nsplit, size_t* coef_off) {
+  int kc;
+  const int ns = kgemm_split((int)ib, (int)n1, (int)b, (int)F, &kc);
+  const size_t off = align256(kgemm_part_bytes((int)ib, (int)n1, (int)b, (int)F, ns));
+  if (nsplit) *nsplit = ns;
+  if (coef_off) *coef_off = off;
+  return off + (size_t)F * ib * b * 8;
+}
+
+// First of the two Gram-Schmidt passes of the Krylov recursion on FP32
+// blocks, in FP32 arithmetic on the Krylov-product kernel:
+// W -= Q_<i (Q_<i^H W), coefficients rounded to FP32.  Its rounding error,
+// of the order of the rounding of the block's own FP32 Krylov product, is an
+// FP32-level perturbation of the block; the second pass (FP64 arithmetic)
+// removes whatever of it lies in the span of Q_<i, so the orthogonality of
+// the basis is that of the FP64 pass.
+int project_out_f32(const Ctx& c, void* W, int i) {
+  const Plan& p = c.p;
+  if (i == 0) return TSVD_OK;
+  const int64_t ib = (int64_t)i * p.b;
+  int ns = 1;
+  size_t coef_off = 0;
+  proj32_layout(ib, p.n1, p.b, p.F, &ns, &coef_off);
+  unsigned char* base = c.at<unsigned char>(p.o_part);
+  void* coef = base + coef_off;
+  void* Q = c.at(p.o_q);
+  Timed tm_(K_GEMM_ORTH, c.s);
+  KGemmDesc k{};
+  k.A = Q;
+  k.lda = p.m;
+  k.strideA = p.n1 * p.m;
+  k.rows = (int)p.n1;
+  k.cols = (int)ib;
+  k.herm = true;
+  k.X = W;
+  k.ldx = p.b;
+  k.strideX = p.n1 * p.b;
+  k.C = coef;
+  k.ldc = p.b;
+  k.strideC = ib * p.b;
+  k.N = (int)p.b;
+  k.batch = (int)p.F;
+  k.mode = KM_F32;
+  k.nsplit = ns;
+  k.part = base;
+  k.part_bytes = coef_off;
+  HIPCHK(kgemm(k, c.s));
+  KGemmDesc u{};
+  u.A = Q;
+  u.lda = p.m;
+  u.strideA = p.n1 * p.m;
+  u.rows = (int)p.n1;
+  u.cols = (int)ib;
+  u.herm = false;
+  u.X = coef;
+  u.ldx = p.b;
+  u.strideX = ib * p.b;
+  u.C = W;
+  u.ldc = p.b;
+  u.strideC = p.n1 * p.b;
+  u.N = (int)p.b;
+  u.batch = (int)p.F;
+  u.mode = KM_F32;
+  u.nsplit = 1;
+  u.sub = 1;
+  HIPCHK(kgemm(u, c.s));
+  return TSVD_OK;
+}
+
 // Shifted CholeskyQR3 of a rows x b block whose first pass has been done
 // (result in S1): dst = orthonormal basis of its range.
 int cholqr_finish(const Ctx& c, int64_t rows, void* dst, int64_t ldd) {
@@ -602,13 +678,15 @@ int cholqr_finish(const Ctx& c, int64_t rows, void* dst, int64_t ldd) {
 }
 
 // Orthonormalise the block in S0 against Q_<i and write it to Q(:, i b : (i+1) b).
-int orth_block(const Ctx& c, int i) {
+// first32: the first projection pass in FP32 arithmetic (FP32 blocks of the
+// stabilised recursion, whose blocks are orthonormalised one by one).
+int orth_block(const Ctx& c, int i, bool first32 = false) {
   const Plan& p = c.p;
   void* S0 = c.at(p.o_s0);
   void* S1 = c.at(p.o_s1);
   void* dst = c.at<unsigned char>(p.o_q) + (size_t)i * p.b * p.cs;
   int r;
-  if ((r = project_out(c, S0, i))) return r;
+  if ((r = (first32 && p.dt == DT_F32) ? project_out_f32(c, S0, i) : project_out(c, S0, i))) return r;
   if ((r = cholqr_pass(c, S0, p.b, S1, p.b, true, p.n1))) return r;
   if ((r = project_out(c, S1, i))) return r;
   return cholqr_finish(c, p.n1, dst, p.m);
@@ -786,7 +864,7 @@ int krylov(const Ctx& c, const void* A, const void* Omega, bool keep_raw = false
     if ((r = big_AhY(c, Q + col, p.m, p.n1 * p.m, T + col, p.m, p.n2 * p.m, (int)p.b))) return r;
     if ((r = big_AX(c, T + col, p.m, p.n2 * p.m, c.at(p.o_s0), p.b, p.n1 * p.b, (int)p.b))) return r;
     if (keep_raw && (r = save_raw(c, i))) return r;
-    if ((r = orth_block(c, i))) return r;
+    if ((r = orth_block(c, i, true))) return r;
   }
   const size_t col = (size_t)p.q * p.b * p.cs;
   return big_AhY(c, Q + col, p.m, p.n1 * p.m, T + col, p.m, p.n2 * p.m, (int)p.b);
@@ -1963,6 +2041,33 @@ int tsvd_diag_kgemm(const void* A, int herm, const void* X, void* C, int64_t row
     HIPCHK(kgemm_bf16(d, pack, (hipStream_t)stream));
   else
     HIPCHK(kgemm(d, (hipStream_t)stream));
+  return TSVD_OK;
+}
+
+int tsvd_diag_kgemm_sub(const void* A, const void* X, void* C, int64_t rows, int64_t cols, int64_t N,
+                        int64_t batch, void* stream) {
+  if (!A || !X || !C || rows < 1 || cols < 1 || N < 1 || batch < 1 || !small_volume(rows, cols, 1) ||
+      !small_volume(rows, N, 1) || !small_volume(cols, N, 1) || N >= (1 << 20) || batch > 65535)
+    return fail(TSVD_EINVAL, "bad arguments");
+  KGemmDesc d{};
+  d.A = A;
+  d.lda = cols;
+  d.strideA = rows * cols;
+  d.rows = (int)rows;
+  d.cols = (int)cols;
+  d.herm = false;
+  d.X = X;
+  d.ldx = N;
+  d.strideX = cols * N;
+  d.C = C;
+  d.ldc = N;
+  d.strideC = rows * N;
+  d.N = (int)N;
+  d.batch = (int)batch;
+  d.mode = KM_F32;
+  d.nsplit = 1;
+  d.sub = 1;
+  HIPCHK(kgemm(d, (hipStream_t)stream));
   return TSVD_OK;
 }
 

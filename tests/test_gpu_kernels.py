@@ -109,6 +109,27 @@ def test_kgemm_vs_float64(case, herm, mode):
     assert err <= tol, f"rel err {err:.2e}"
 
 
+@pytest.mark.parametrize("case", [(2, 70, 90, 5), (3, 200, 330, 110), (2, 4096, 110, 110), (1, 16, 1, 1),
+                                  (33, 130, 220, 110)])
+def test_kgemm_update_form_vs_float64(case):
+    """The update form C_f -= A_f X_f (the first Gram-Schmidt pass of the
+    recursion on FP32 blocks: A_f the earlier basis columns, ragged K = i b)
+    against a float64 update of the same complex64 inputs; the inputs A, X
+    are left as they were."""
+    batch, rows, cols, N = case
+    A, Ad = _cplx((batch, rows, cols), 1, torch.complex64)
+    X, Xd = _cplx((batch, cols, N), 2, torch.complex64)
+    C0, Cd = _cplx((batch, rows, N), 3, torch.complex64)
+    A, X, C0 = (t.astype(np.complex64).astype(np.complex128) for t in (A, X, C0))
+    api.diag_kgemm_sub(Ad, Xd, Cd)
+    C = host(Cd)
+    ref = C0 - A @ X
+    scale = np.linalg.norm(C0.ravel()) + np.linalg.norm((A @ X).ravel())
+    err = np.linalg.norm((C - ref).ravel()) / scale
+    assert err <= 1e-6, f"rel err {err:.2e}"
+    assert np.array_equal(host(Ad), A.astype(np.complex64)) and np.array_equal(host(Xd), X.astype(np.complex64))
+
+
 @pytest.mark.parametrize("case", KG_CASES + [(33, 512, 520, 110, 1)])
 @pytest.mark.parametrize("herm", [False, True])
 def test_kgemm_presplit_bitwise_equals_bf16x3(case, herm):
