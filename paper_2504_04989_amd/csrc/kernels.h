@@ -57,6 +57,10 @@ hipError_t split_bf16x3(const void* in, void* out, int64_t n, hipStream_t s);
 size_t kgemm_part_bytes(int M, int K, int N, int batch, int nsplit);
 // K split (and chunk) that gives the product enough workgroups to fill the chip.
 int kgemm_split(int M, int K, int N, int batch, int* kchunk);
+// K split (at most 16) of a product with few output tiles: the count that
+// minimises rounds x (K steps per split + 6) over the device's workgroup
+// slots (two per CU), a workgroup's fixed cost taken as 6 K steps.
+int kgemm_split_balanced(int M, int K, int N, int batch);
 // BF16 / BF16x3 modes on planar data: the thin operand is first packed into
 // `pack` (kgemm_bf16_pack_bytes), partials (nsplit > 1) go to d.part.
 hipError_t kgemm_bf16(const KGemmDesc& d, void* pack, hipStream_t s);

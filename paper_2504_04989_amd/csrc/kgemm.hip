@@ -642,6 +642,33 @@ int kgemm_split(int M, int K, int N, int batch, int* kchunk) {
   return ns;
 }
 
+int kgemm_split_balanced(int M, int K, int N, int batch) {
+  static int slots = 0;
+  if (!slots) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cus <= 0)
+      cus = 256;
+    slots = 2 * cus;  // two workgroups per CU (launch bounds)
+  }
+  const int TT = kgemm_thin_tiles(N);
+  const int64_t tiles = (int64_t)((N + 8 * TT - 1) / (8 * TT)) * ((M + NWAVE * 16 * 2 - 1) / (NWAVE * 16 * 2)) * batch;
+  int best = 1;
+  double best_cost = 1e300;
+  for (int ns = 1; ns <= 16; ++ns) {
+    int kc = (K + ns - 1) / ns;
+    kc = (kc + KSTEP - 1) / KSTEP * KSTEP;
+    if ((K + kc - 1) / kc != ns) continue;  // the chunking gives fewer splits
+    const int64_t rounds = (tiles * ns + slots - 1) / slots;
+    const double cost = (double)rounds * (kc / KSTEP + 6);
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = ns;
+    }
+  }
+  return best;
+}
+
 hipError_t kgemm(const KGemmDesc& d, hipStream_t s) {
   const int M = d.herm ? d.cols : d.rows;
   const int K = d.herm ? d.rows : d.cols;

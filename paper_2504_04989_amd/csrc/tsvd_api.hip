@@ -575,8 +575,7 @@ int project_out(const Ctx& c, void* W, int i) {
 // Bytes of o_part that project_out_f32 uses against ib earlier columns: the
 // K-split partials of the coefficient product, then the coefficients.
 size_t proj32_layout(int64_t ib, int64_t n1, int64_t b, int64_t F, int* nsplit, size_t* coef_off) {
-  int kc;
-  const int ns = kgemm_split((int)ib, (int)n1, (int)b, (int)F, &kc);
+  const int ns = kgemm_split_balanced((int)ib, (int)n1, (int)b, (int)F);
   const size_t off = align256(kgemm_part_bytes((int)ib, (int)n1, (int)b, (int)F, ns));
   if (nsplit) *nsplit = ns;
   if (coef_off) *coef_off = off;
